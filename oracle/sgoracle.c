@@ -1,0 +1,770 @@
+/*
+ * sgoracle.c -- FP64 CPU reference ("oracle") of the scattering-graph hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * loads this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header or table with the GPU
+ * path.  It is deliberately plain and slow: straightforward loops in double
+ * precision that follow the method's definitions in the paper's order.
+ * OpenMP only splits independent items (edges, nodes, rows, pixels) across
+ * threads; no sum is reordered by it.
+ *
+ * Method (Mikkonen et al., "Scattering graph method for 3D radiative
+ * transfer"):
+ *   - Sec. 2, Eq. 3 (Beer-Lambert-Bouguer): transmittance exp(-int mu_e) of
+ *     every graph edge, integrated by an exact voxel traversal (O2 below);
+ *   - Sec. 2, Eq. 6 / Eq. 7: flux-matrix element = edge transmittance x the
+ *     node's scattering weight x the phase function integrated over the
+ *     spherical cell Sigma of the outgoing edge (discretised on a Fibonacci
+ *     lattice, Sec. 3);
+ *   - Sec. 2, Eq. 9: the direct-solar source; Eq. 8 / Eq. 5: (I - F) phi = S
+ *     solved by the Neumann series; Eq. 11: the observed radiance gather.
+ * The readings taken where the paper is silent or garbled are listed in the
+ * repository's design notes; the ones that change arithmetic are restated at
+ * the function that takes them.
+ *
+ * Notation: a directed edge id is its position in the adjacency CSR (edges
+ * sorted by (tail, head)); K is the transpose of the paper's F (row = the
+ * destination edge b, column = the source edge a), so that phi = S + K phi.
+ *
+ * Operation-order contract: the lattice, the unit edge directions, the
+ * rotation and the dot products that decide lattice ownership are written
+ * with the exact sequence of IEEE operations stated at each function (fma()
+ * where named, no contraction elsewhere; compile with -ffp-contract=off).
+ * Ownership is an argmax, so both implementations must take it with the same
+ * double-precision operations to agree bit for bit.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define FXS 65536LL /* fixed-point units per voxel edge */
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ==================================================================== */
+/* O2: exact voxel traversal of a segment or ray (Sec. 2, Eq. 3 / Eq. 6) */
+/* ==================================================================== */
+
+typedef struct {
+    int64_t n, d; /* non-negative rational n / d, d > 0 */
+} rat;
+
+static int rat_lt(rat a, rat b) { return a.n * b.d < b.n * a.d; }
+static int rat_eq(rat a, rat b) { return a.n * b.d == b.n * a.d; }
+
+static int64_t floor_div(int64_t a, int64_t b) {
+    int64_t q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) q -= 1;
+    return q;
+}
+
+/*
+ * Walk the voxels that P + t D crosses with positive length, for t in
+ * (0, 1] (a node-to-node segment, is_ray = 0) or until the ray leaves the
+ * grid (is_ray = 1).  P is fixed point, D integer.  A start point lying on a
+ * voxel plane belongs to the voxel the path moves into.  Crossing times
+ * (B - P_k) / D_k are compared exactly by cross multiplication; when several
+ * axes cross at the same time all of them step together, so no voxel of zero
+ * length is reported.  For each voxel the callback receives its linear id
+ * (ix + nx (iy + ny iz)) and dt, the parameter length inside it, computed as
+ * one correctly rounded division of exact integers.
+ * Returns the number of voxels, or -1 when a segment leaves the grid.
+ */
+typedef void (*visit_fn)(void *ctx, int64_t vox, double dt);
+
+static int dda_walk(int nx, int ny, int nz, const int64_t P[3], const int64_t D[3], int is_ray,
+                    visit_fn visit, void *ctx) {
+    int64_t n[3] = {nx, ny, nz};
+    int64_t idx[3], step[3];
+    rat tn[3];
+    int active[3];
+    for (int k = 0; k < 3; ++k) {
+        if (D[k] > 0) {
+            idx[k] = floor_div(P[k], FXS);
+            step[k] = 1;
+            tn[k].n = (idx[k] + 1) * FXS - P[k];
+            tn[k].d = D[k];
+            active[k] = 1;
+        } else if (D[k] < 0) {
+            idx[k] = floor_div(P[k] + FXS - 1, FXS) - 1; /* ceil(P / FXS) - 1 */
+            step[k] = -1;
+            tn[k].n = P[k] - idx[k] * FXS;
+            tn[k].d = -D[k];
+            active[k] = 1;
+        } else {
+            idx[k] = floor_div(P[k], FXS);
+            step[k] = 0;
+            tn[k].n = 0;
+            tn[k].d = 1;
+            active[k] = 0;
+        }
+    }
+    if (!active[0] && !active[1] && !active[2]) return -1;
+    rat tcur = {0, 1};
+    const rat tend = {1, 1};
+    int count = 0;
+    for (;;) {
+        int inside = idx[0] >= 0 && idx[0] < n[0] && idx[1] >= 0 && idx[1] < n[1] && idx[2] >= 0 &&
+                     idx[2] < n[2];
+        if (!inside) {
+            if (is_ray) break;
+            return -1;
+        }
+        rat tmin = {1, 0}; /* +infinity */
+        int have = 0;
+        for (int k = 0; k < 3; ++k) {
+            if (!active[k]) continue;
+            if (!have || rat_lt(tn[k], tmin)) {
+                tmin = tn[k];
+                have = 1;
+            }
+        }
+        int last = 0;
+        if (!is_ray && !rat_lt(tmin, tend)) {
+            tmin = tend;
+            last = 1;
+        }
+        int64_t num = tmin.n * tcur.d - tcur.n * tmin.d;
+        int64_t den = tmin.d * tcur.d;
+        double dt = (double)num / (double)den;
+        visit(ctx, idx[0] + (int64_t)nx * (idx[1] + (int64_t)ny * idx[2]), dt);
+        ++count;
+        if (last) break;
+        for (int k = 0; k < 3; ++k) {
+            if (active[k] && rat_eq(tn[k], tmin)) {
+                idx[k] += step[k];
+                tn[k].n += FXS;
+            }
+        }
+        tcur = tmin;
+    }
+    return count;
+}
+
+typedef struct {
+    int64_t *vox;
+    double *dt;
+    int cap, n;
+} trace_buf;
+
+static void trace_visit(void *c, int64_t vox, double dt) {
+    trace_buf *b = (trace_buf *)c;
+    if (b->n < b->cap) {
+        b->vox[b->n] = vox;
+        b->dt[b->n] = dt;
+    }
+    b->n++;
+}
+
+/* Exported for the traversal pins: voxel ids and parameter lengths of one walk. */
+int or_trace(int nx, int ny, int nz, const int64_t *P, const int64_t *D, int is_ray, int64_t *vox,
+             double *dt, int cap) {
+    trace_buf b = {vox, dt, cap, 0};
+    int r = dda_walk(nx, ny, nz, P, D, is_ray, trace_visit, &b);
+    return r < 0 ? r : b.n;
+}
+
+typedef struct {
+    const double *mu_e;
+    double tau; /* accumulated sum of mu_e * dt (dt in parameter units) */
+} tau_acc;
+
+static void tau_visit(void *c, int64_t vox, double dt) {
+    tau_acc *a = (tau_acc *)c;
+    a->tau += a->mu_e[vox] * dt;
+}
+
+/* Length in metres of the whole parameter interval t in [0, 1] of direction D. */
+static double param_length_m(const int64_t D[3], double voxel_m) {
+    int64_t s = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
+    return sqrt((double)s) * (voxel_m / (double)FXS);
+}
+
+/* Optical depth along a segment (is_ray = 0) or a ray to the grid exit. */
+static double optical_depth(int nx, int ny, int nz, const double *mu_e, double voxel_m,
+                            const int64_t P[3], const int64_t D[3], int is_ray) {
+    tau_acc a = {mu_e, 0.0};
+    dda_walk(nx, ny, nz, P, D, is_ray, tau_visit, &a);
+    return a.tau * param_length_m(D, voxel_m);
+}
+
+/* ==================================================================== */
+/* O3-O5: directions, phase function, Fibonacci lattice, ownership       */
+/* ==================================================================== */
+
+/* Henyey-Greenstein phase function, normalised to 1 over the sphere. */
+static double hg(double g, double mu) {
+    double den = 1.0 + g * g - 2.0 * g * mu;
+    return (1.0 - g * g) / (4.0 * M_PI * den * sqrt(den));
+}
+
+/*
+ * Fibonacci lattice (Sec. 3, phase integration; spherical Fibonacci point set
+ * with the golden angle): z_i = 1 - (2i + 1) / N, phi_i = (i * ga) mod 2 pi
+ * with ga = pi (3 - sqrt 5), p_i = (r cos phi_i, r sin phi_i, z_i),
+ * r = sqrt(1 - z_i * z_i).  Written as that exact operation sequence.
+ */
+void or_lattice(int N, double *p /* [N][3] */) {
+    const double ga = M_PI * (3.0 - sqrt(5.0));
+    const double two_pi = 2.0 * M_PI;
+    for (int i = 0; i < N; ++i) {
+        double z = 1.0 - (2.0 * (double)i + 1.0) / (double)N;
+        double phi = fmod((double)i * ga, two_pi);
+        double r = sqrt(1.0 - z * z);
+        p[3 * i + 0] = r * cos(phi);
+        p[3 * i + 1] = r * sin(phi);
+        p[3 * i + 2] = z;
+    }
+}
+
+/* Normalised lattice table of one HG component: Theta(z_i) / sum_j Theta(z_j). */
+void or_hg_table(double g, int N, const double *p, double *t) {
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) {
+        t[i] = hg(g, p[3 * i + 2]);
+        s += t[i];
+    }
+    for (int i = 0; i < N; ++i) t[i] = t[i] / s;
+}
+
+/* Unit vector of an integer direction: D / sqrt(Dx^2 + Dy^2 + Dz^2). */
+static void unit_of(const int64_t D[3], double u[3]) {
+    double nrm = sqrt((double)(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]));
+    u[0] = (double)D[0] / nrm;
+    u[1] = (double)D[1] / nrm;
+    u[2] = (double)D[2] / nrm;
+}
+
+/*
+ * Rotation taking the unit vector u to +z (the forward direction onto the
+ * table's theta = 0 axis, Sec. 3): the minimal rotation about u x z,
+ *   R = c I + [w]x + w w^T / (1 + c),  c = u_z,  w = (u_y, -u_x, 0),
+ * entry by entry with h = 1 / (1 + c); for 1 + c < 1e-12, R = diag(1, -1, -1).
+ */
+void or_rotation(const double u[3], double R[9]) {
+    double c = u[2];
+    if (1.0 + c < 1e-12) {
+        R[0] = 1.0; R[1] = 0.0;  R[2] = 0.0;
+        R[3] = 0.0; R[4] = -1.0; R[5] = 0.0;
+        R[6] = 0.0; R[7] = 0.0;  R[8] = -1.0;
+        return;
+    }
+    double h = 1.0 / (1.0 + c);
+    double ux = u[0], uy = u[1];
+    double xy = (ux * uy) * h;
+    R[0] = c + (uy * uy) * h; R[1] = -xy;               R[2] = -ux;
+    R[3] = -xy;               R[4] = c + (ux * ux) * h; R[5] = -uy;
+    R[6] = ux;                R[7] = uy;                R[8] = c;
+}
+
+/* r = R s, each row as fma(R2, s2, fma(R1, s1, R0 * s0)). */
+static void rot_apply(const double R[9], const double s[3], double r[3]) {
+    for (int k = 0; k < 3; ++k) r[k] = fma(R[3 * k + 2], s[2], fma(R[3 * k + 1], s[1], R[3 * k] * s[0]));
+}
+
+/* p . r as fma(p2, r2, fma(p1, r1, p0 * r0)). */
+static double dot3(const double p[3], const double r[3]) {
+    return fma(p[2], r[2], fma(p[1], r[1], p[0] * r[0]));
+}
+
+/*
+ * Lattice ownership (Eq. 7 and the definition of Sigma after it): lattice
+ * point i belongs to the outgoing direction m with the largest p_i . r_m,
+ * where r_m = R(u) s_m for an incoming propagation direction u (u == NULL:
+ * no rotation, the Lambertian surface case).  Ties go to the smallest m,
+ * which also drops a second coupling in exactly the same direction.
+ */
+void or_ownership(const double *u, int d, const double *s /* [d][3] */, int N, const double *p,
+                  int32_t *own) {
+    double R[9];
+    double *r = (double *)malloc(sizeof(double) * 3 * (d > 0 ? d : 1));
+    if (u) {
+        or_rotation(u, R);
+        for (int m = 0; m < d; ++m) rot_apply(R, s + 3 * m, r + 3 * m);
+    } else {
+        memcpy(r, s, sizeof(double) * 3 * d);
+    }
+    for (int i = 0; i < N; ++i) {
+        int best = -1;
+        double bv = 0.0;
+        for (int m = 0; m < d; ++m) {
+            double v = dot3(p + 3 * i, r + 3 * m);
+            if (best < 0 || v > bv) {
+                best = m;
+                bv = v;
+            }
+        }
+        own[i] = best;
+    }
+    free(r);
+}
+
+/* ==================================================================== */
+/* The scene and the full pipeline                                       */
+/* ==================================================================== */
+
+typedef struct {
+    int nx, ny, nz;
+    double voxel_m;
+    const double *mu_s, *mu_a; /* [nvox] in 1/m (mu_a already multiplied by the wavelength scale) */
+    int n_phase;
+    const double *hg_g;       /* [n_phase] */
+    const double *phase_frac; /* [n_phase][nvox] or NULL */
+    const int64_t *pos;       /* [N][3] every node, volume then surface */
+    int surface;
+    const int64_t *adj_ptr; /* [N+1] */
+    const int32_t *adj_idx; /* [E] */
+    const double *albedo;   /* [ny][nx] */
+    const int64_t *sun_dir; /* [3] toward the sun */
+    const int64_t *view_dir;/* [3] toward the sensor */
+    int n_fib;
+    int node_weight_mode;
+    int scatter_order; /* 0 = multiple scattering, 1 = single scattering only */
+    double tol;        /* relative 1-norm residual target of the solve */
+} or_scene;
+
+typedef struct {
+    double *tau;      /* [E]   optical depth of the edge's pair (lower id -> higher id) */
+    double *tau_sun;  /* [N]   node -> sun, to the grid exit */
+    double *rho;      /* [N]   node weight */
+    int64_t *row_ptr; /* [E+1] */
+    int32_t *col;     /* [nnz] */
+    double *val;      /* [nnz] */
+    double *S;        /* [E] */
+    double *phi;      /* [E] */
+    double *pix;      /* [ny*nx] radiance / F0 */
+    double *stats;    /* [4]: sweeps, relative residual, used GMRES, GMRES iterations */
+} or_out;
+
+static int64_t edge_rev(const or_scene *sc, int64_t e, int64_t tail) {
+    int64_t head = sc->adj_idx[e];
+    int64_t lo = sc->adj_ptr[head], hi = sc->adj_ptr[head + 1];
+    while (lo < hi) { /* first position with adj_idx >= tail */
+        int64_t mid = (lo + hi) / 2;
+        if (sc->adj_idx[mid] < tail) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+static int64_t tail_of(const int64_t *adj_ptr, int64_t N, int64_t e) {
+    int64_t lo = 0, hi = N; /* last node with adj_ptr[node] <= e */
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) / 2;
+        if (adj_ptr[mid] <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+/* ---- O8 solve helpers ---- */
+
+/* y = S + K x (one Jacobi / Neumann sweep, Eq. 5). */
+static void sweep(int64_t E, const int64_t *rp, const int32_t *col, const double *val, const double *S,
+                  const double *x, double *y) {
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < E; ++b) {
+        double acc = 0.0;
+        for (int64_t q = rp[b]; q < rp[b + 1]; ++q) acc += val[q] * x[col[q]];
+        y[b] = S[b] + acc;
+    }
+}
+
+static double norm1(int64_t n, const double *v) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += fabs(v[i]);
+    return s;
+}
+
+static double norm2(int64_t n, const double *v) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += v[i] * v[i];
+    return sqrt(s);
+}
+
+/* r = S - (I - K) x */
+static void residual(int64_t E, const int64_t *rp, const int32_t *col, const double *val, const double *S,
+                     const double *x, double *r) {
+    sweep(E, rp, col, val, S, x, r);
+    for (int64_t b = 0; b < E; ++b) r[b] -= x[b];
+}
+
+/* Restarted GMRES(m) with modified Gram-Schmidt and Givens rotations on (I - K) x = S. */
+static int gmres(int64_t E, const int64_t *rp, const int32_t *col, const double *val, const double *S,
+                 double *x, int m, double tol, int max_iter, double *relres) {
+    double *V = (double *)malloc(sizeof(double) * (size_t)E * (m + 1));
+    double *H = (double *)calloc((size_t)(m + 1) * m, sizeof(double));
+    double *cs = (double *)malloc(sizeof(double) * m), *sn = (double *)malloc(sizeof(double) * m);
+    double *g = (double *)malloc(sizeof(double) * (m + 1)), *yv = (double *)malloc(sizeof(double) * m);
+    double *w = (double *)malloc(sizeof(double) * E), *zero = (double *)calloc(E, sizeof(double));
+    double nS1 = norm1(E, S);
+    int it = 0;
+    for (;;) {
+        residual(E, rp, col, val, S, x, w);
+        double r1 = norm1(E, w);
+        *relres = nS1 > 0 ? r1 / nS1 : 0.0;
+        if (*relres <= tol || it >= max_iter) break;
+        double beta = norm2(E, w);
+        for (int64_t i = 0; i < E; ++i) V[i] = w[i] / beta;
+        memset(g, 0, sizeof(double) * (m + 1));
+        g[0] = beta;
+        int k;
+        for (k = 0; k < m && it < max_iter; ++k, ++it) {
+            double *vk = V + (size_t)k * E, *vn = V + (size_t)(k + 1) * E;
+            /* vn = (I - K) vk = vk - K vk */
+            sweep(E, rp, col, val, zero, vk, vn);
+            for (int64_t i = 0; i < E; ++i) vn[i] = vk[i] - vn[i];
+            for (int j = 0; j <= k; ++j) {
+                double *vj = V + (size_t)j * E;
+                double h = 0.0;
+                for (int64_t i = 0; i < E; ++i) h += vn[i] * vj[i];
+                H[j * m + k] = h;
+                for (int64_t i = 0; i < E; ++i) vn[i] -= h * vj[i];
+            }
+            double hn = norm2(E, vn);
+            H[(k + 1) * m + k] = hn;
+            if (hn > 0) for (int64_t i = 0; i < E; ++i) vn[i] /= hn;
+            for (int j = 0; j < k; ++j) {
+                double a = H[j * m + k], b = H[(j + 1) * m + k];
+                H[j * m + k] = cs[j] * a + sn[j] * b;
+                H[(j + 1) * m + k] = -sn[j] * a + cs[j] * b;
+            }
+            double a = H[k * m + k], b = H[(k + 1) * m + k];
+            double den = sqrt(a * a + b * b);
+            cs[k] = den > 0 ? a / den : 1.0;
+            sn[k] = den > 0 ? b / den : 0.0;
+            H[k * m + k] = den;
+            H[(k + 1) * m + k] = 0.0;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            if (fabs(g[k + 1]) <= 1e-3 * tol * beta) { ++k; ++it; break; }
+        }
+        for (int j = k - 1; j >= 0; --j) {
+            double s = g[j];
+            for (int q = j + 1; q < k; ++q) s -= H[j * m + q] * yv[q];
+            yv[j] = s / H[j * m + j];
+        }
+        for (int j = 0; j < k; ++j) {
+            double *vj = V + (size_t)j * E;
+            for (int64_t i = 0; i < E; ++i) x[i] += yv[j] * vj[i];
+        }
+    }
+    free(V); free(H); free(cs); free(sn); free(g); free(yv); free(w); free(zero);
+    return it;
+}
+
+/*
+ * O8: phi = (I - K)^-1 S (Eq. 8), by the Neumann series x <- S + K x (Eq. 5);
+ * y - x is the residual S - (I - K) x of the previous iterate.  Falls back to
+ * GMRES(50) when the sweep ratio reaches 0.99, the residual grows, or 5000
+ * sweeps pass.  stats: sweeps, final relative 1-norm residual, GMRES used,
+ * GMRES iterations.
+ */
+int or_solve(int64_t E, const int64_t *rp, const int32_t *col, const double *val, const double *S,
+             double tol, double *phi, double *stats) {
+    double *x = (double *)calloc(E > 0 ? E : 1, sizeof(double));
+    double *y = (double *)malloc(sizeof(double) * (E > 0 ? E : 1));
+    double nS = norm1(E, S);
+    int sweeps = 0, use_gmres = 0;
+    double prev = -1.0, rel = 0.0;
+    if (nS == 0.0) {
+        memset(phi, 0, sizeof(double) * E);
+        stats[0] = 0; stats[1] = 0; stats[2] = 0; stats[3] = 0;
+        free(x); free(y);
+        return 0;
+    }
+    for (;;) {
+        sweep(E, rp, col, val, S, x, y);
+        ++sweeps;
+        double r = 0.0;
+        for (int64_t i = 0; i < E; ++i) r += fabs(y[i] - x[i]);
+        rel = r / nS;
+        memcpy(x, y, sizeof(double) * E);
+        if (rel <= tol) break;
+        if (prev > 0 && (rel / prev >= 0.99 || rel > prev)) { use_gmres = 1; break; }
+        if (sweeps >= 5000) { use_gmres = 1; break; }
+        prev = rel;
+    }
+    int git = 0;
+    if (use_gmres) git = gmres(E, rp, col, val, S, x, 50, tol, 20000, &rel);
+    else {
+        /* rel above is the residual of the iterate before the last sweep; report the final one */
+        residual(E, rp, col, val, S, x, y);
+        rel = norm1(E, y) / nS;
+    }
+    memcpy(phi, x, sizeof(double) * E);
+    stats[0] = sweeps; stats[1] = rel; stats[2] = use_gmres; stats[3] = git;
+    free(x); free(y);
+    return 0;
+}
+
+/* Number of structural nonzeros sum_l d_l^2 of K. */
+int64_t or_nnz(int64_t N, const int64_t *adj_ptr) {
+    int64_t s = 0;
+    for (int64_t l = 0; l < N; ++l) {
+        int64_t d = adj_ptr[l + 1] - adj_ptr[l];
+        s += d * d;
+    }
+    return s;
+}
+
+/*
+ * Phase-cell weights of one node for one incoming direction (Eq. 7):
+ * Q[m] = sum_k f_k sum_{i : own(i) = m} Theta~_k(i)   (volume node, rotation by u)
+ * Q[m] = sum_{i : own(i) = m} max(0, z_i) / sum_j max(0, z_j)   (surface node, u ignored)
+ */
+static void node_q(int is_surface, const double *u, int d, const double *s, int N, const double *lat,
+                   const double *w /* [N] mixed table, volume only */, double *Q, int32_t *own) {
+    or_ownership(is_surface ? NULL : u, d, s, N, lat, own);
+    for (int m = 0; m < d; ++m) Q[m] = 0.0;
+    if (is_surface) {
+        double tot = 0.0;
+        for (int i = 0; i < N; ++i) tot += fmax(0.0, lat[3 * i + 2]);
+        for (int i = 0; i < N; ++i) Q[own[i]] += fmax(0.0, lat[3 * i + 2]) / tot;
+    } else {
+        for (int i = 0; i < N; ++i) Q[own[i]] += w[i];
+    }
+}
+
+/* Exported for the phase-cell pins. */
+void or_node_q(int is_surface, const double *u, int d, const double *s, int N, const double *w, double *Q) {
+    double *lat = (double *)malloc(sizeof(double) * 3 * N);
+    int32_t *own = (int32_t *)malloc(sizeof(int32_t) * N);
+    or_lattice(N, lat);
+    node_q(is_surface, u, d, s, N, lat, w, Q, own);
+    free(lat);
+    free(own);
+}
+
+/*
+ * The whole pipeline: O2 transmittances, O5 cells, O6 weights, O7 matrix and
+ * source, O8 solve, O9 gather.  Returns 0, or a negative value on an invalid
+ * scene (a segment leaving the grid).
+ */
+int or_run(const or_scene *sc, or_out *out) {
+    const int nx = sc->nx, ny = sc->ny, nz = sc->nz;
+    const int64_t nvox = (int64_t)nx * ny * nz;
+    const int64_t N = nvox + (sc->surface ? (int64_t)nx * ny : 0);
+    const int64_t E = sc->adj_ptr[N];
+    const double dx = sc->voxel_m;
+    const int NF = sc->n_fib;
+
+    /* O0: extinction and single-scattering albedo of each voxel */
+    double *mu_e = (double *)malloc(sizeof(double) * nvox);
+    double *omega = (double *)malloc(sizeof(double) * nvox);
+    for (int64_t v = 0; v < nvox; ++v) {
+        mu_e[v] = sc->mu_s[v] + sc->mu_a[v];
+        omega[v] = mu_e[v] > 0.0 ? sc->mu_s[v] / mu_e[v] : 0.0;
+    }
+
+    /* O2: edge optical depth, from the lower to the higher node id (shared by both directions) */
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t l = 0; l < N; ++l) {
+        for (int64_t e = sc->adj_ptr[l]; e < sc->adj_ptr[l + 1]; ++e) {
+            int64_t j = sc->adj_idx[e];
+            int64_t a = l < j ? l : j, b = l < j ? j : l;
+            int64_t P[3], D[3];
+            for (int k = 0; k < 3; ++k) {
+                P[k] = sc->pos[3 * a + k];
+                D[k] = sc->pos[3 * b + k] - sc->pos[3 * a + k];
+            }
+            tau_acc acc = {mu_e, 0.0};
+            if (dda_walk(nx, ny, nz, P, D, 0, tau_visit, &acc) < 0) bad = 1;
+            out->tau[e] = acc.tau * param_length_m(D, dx);
+        }
+    }
+    if (bad) { free(mu_e); free(omega); return -2; }
+
+    /* O2: node -> sun optical depth to the grid exit */
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t l = 0; l < N; ++l) {
+        out->tau_sun[l] = optical_depth(nx, ny, nz, mu_e, dx, sc->pos + 3 * l, sc->sun_dir, 1);
+    }
+
+    /* O6: node weights (bounded scattering probability over one voxel edge; mode 1: mu_s * edge) */
+    for (int64_t l = 0; l < N; ++l) {
+        if (l < nvox) {
+            if (sc->node_weight_mode == 1) out->rho[l] = sc->mu_s[l] * dx;
+            else out->rho[l] = omega[l] * (-expm1(-mu_e[l] * dx));
+        } else {
+            out->rho[l] = sc->albedo[l - nvox];
+        }
+    }
+
+    /* O5: lattice and per-component tables */
+    double *lat = (double *)malloc(sizeof(double) * 3 * NF);
+    or_lattice(NF, lat);
+    double *tab = (double *)malloc(sizeof(double) * NF * sc->n_phase);
+    for (int k = 0; k < sc->n_phase; ++k) or_hg_table(sc->hg_g[k], NF, lat, tab + (size_t)k * NF);
+
+    double sun_u[3], sun_in[3];
+    unit_of(sc->sun_dir, sun_u);
+    {
+        int64_t nsd[3] = {-sc->sun_dir[0], -sc->sun_dir[1], -sc->sun_dir[2]};
+        unit_of(nsd, sun_in); /* propagation direction of sunlight */
+    }
+    const double mu0 = sun_u[2];
+
+    /* O7: K (CSR, rows = destination edges, columns = in(tail) ascending) and S */
+    out->row_ptr[0] = 0;
+    for (int64_t l = 0; l < N; ++l) {
+        int64_t d = sc->adj_ptr[l + 1] - sc->adj_ptr[l];
+        for (int64_t e = sc->adj_ptr[l]; e < sc->adj_ptr[l + 1]; ++e) out->row_ptr[e + 1] = out->row_ptr[e] + d;
+    }
+#pragma omp parallel
+    {
+        int dmax = 1;
+        for (int64_t l = 0; l < N; ++l) {
+            int d = (int)(sc->adj_ptr[l + 1] - sc->adj_ptr[l]);
+            if (d > dmax) dmax = d;
+        }
+        double *s = (double *)malloc(sizeof(double) * 3 * dmax);
+        int64_t *rev = (int64_t *)malloc(sizeof(int64_t) * dmax);
+        double *Q = (double *)malloc(sizeof(double) * dmax);
+        double *w = (double *)malloc(sizeof(double) * NF);
+        int32_t *own = (int32_t *)malloc(sizeof(int32_t) * NF);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t l = 0; l < N; ++l) {
+            int64_t off = sc->adj_ptr[l];
+            int d = (int)(sc->adj_ptr[l + 1] - off);
+            if (d == 0) continue;
+            int is_surf = l >= nvox;
+            for (int m = 0; m < d; ++m) {
+                int64_t e = off + m, j = sc->adj_idx[e];
+                int64_t D[3];
+                for (int k = 0; k < 3; ++k) D[k] = sc->pos[3 * j + k] - sc->pos[3 * l + k];
+                unit_of(D, s + 3 * m); /* out-direction of edge (l -> j) */
+                rev[m] = edge_rev(sc, e, l); /* in-edge (j -> l) */
+            }
+            if (!is_surf) {
+                for (int i = 0; i < NF; ++i) {
+                    double acc = 0.0;
+                    for (int k = 0; k < sc->n_phase; ++k) {
+                        double f = sc->phase_frac ? sc->phase_frac[(size_t)k * nvox + l] : 1.0;
+                        acc += f * tab[(size_t)k * NF + i];
+                    }
+                    w[i] = acc;
+                }
+            }
+            /* columns: in-edges a_m = rev[m] (ascending, since heads are ascending) */
+            for (int m = 0; m < d; ++m) {
+                double u[3] = {-s[3 * m], -s[3 * m + 1], -s[3 * m + 2]}; /* propagation of (j -> l) */
+                node_q(is_surf, u, d, s, NF, lat, w, Q, own);
+                double Ta = exp(-out->tau[off + m]); /* same pair as rev[m] */
+                for (int n = 0; n < d; ++n) {
+                    int64_t b = off + n;
+                    int64_t q = out->row_ptr[b] + m;
+                    out->col[q] = (int32_t)rev[m];
+                    out->val[q] = Ta * out->rho[l] * Q[n];
+                }
+            }
+            /* source (Eq. 9): sunlight arriving at l along sun_in */
+            node_q(is_surf, sun_in, d, s, NF, lat, w, Q, own);
+            double Ts = exp(-out->tau_sun[l]);
+            for (int n = 0; n < d; ++n) {
+                if (is_surf) out->S[off + n] = out->rho[l] * mu0 * Ts * Q[n];
+                else out->S[off + n] = Ts * out->rho[l] * Q[n];
+            }
+        }
+        free(s); free(rev); free(Q); free(w); free(own);
+    }
+
+    /* O8 */
+    if (sc->scatter_order == 1) {
+        memset(out->phi, 0, sizeof(double) * E);
+        out->stats[0] = out->stats[1] = out->stats[2] = out->stats[3] = 0.0;
+    } else {
+        or_solve(E, out->row_ptr, out->col, out->val, out->S, sc->tol, out->phi, out->stats);
+    }
+
+    /* O9: gather (Eq. 11) along the line of sight of every pixel */
+    double vu[3];
+    unit_of(sc->view_dir, vu);
+    const double Lview = param_length_m(sc->view_dir, dx);
+#pragma omp parallel
+    {
+        int cap = 4 * (nx + ny + nz) + 8;
+        int64_t *vox = (int64_t *)malloc(sizeof(int64_t) * cap);
+        double *dtv = (double *)malloc(sizeof(double) * cap);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t p = 0; p < (int64_t)nx * ny; ++p) {
+            int64_t ix = p % nx, iy = p / nx;
+            int64_t P[3] = {ix * FXS + FXS / 2, iy * FXS + FXS / 2, 0};
+            trace_buf tb = {vox, dtv, cap, 0};
+            dda_walk(nx, ny, nz, P, sc->view_dir, 1, trace_visit, &tb);
+            int nseg = tb.n;
+            double Iv = 0.0;
+            double tau_after = 0.0; /* optical depth between the segment's far end and the sensor */
+            for (int k = nseg - 1; k >= 0; --k) {
+                int64_t v = vox[k];
+                double sk = dtv[k] * Lview;
+                double Tent = exp(-tau_after);
+                double wch = omega[v] * (-expm1(-mu_e[v] * sk));
+                /* the volume node of voxel v has id v */
+                double th_sun = 0.0;
+                for (int c = 0; c < sc->n_phase; ++c) {
+                    double f = sc->phase_frac ? sc->phase_frac[(size_t)c * nvox + v] : 1.0;
+                    th_sun += f * hg(sc->hg_g[c], sun_in[0] * vu[0] + sun_in[1] * vu[1] + sun_in[2] * vu[2]);
+                }
+                double J = th_sun * exp(-out->tau_sun[v]);
+                if (sc->scatter_order != 1) {
+                    for (int64_t e = sc->adj_ptr[v]; e < sc->adj_ptr[v + 1]; ++e) {
+                        int64_t j = sc->adj_idx[e];
+                        int64_t D[3];
+                        for (int k2 = 0; k2 < 3; ++k2) D[k2] = sc->pos[3 * v + k2] - sc->pos[3 * j + k2];
+                        double sa[3];
+                        unit_of(D, sa); /* propagation direction of in-edge (j -> v) */
+                        double mu = sa[0] * vu[0] + sa[1] * vu[1] + sa[2] * vu[2];
+                        double th = 0.0;
+                        for (int c = 0; c < sc->n_phase; ++c) {
+                            double f = sc->phase_frac ? sc->phase_frac[(size_t)c * nvox + v] : 1.0;
+                            th += f * hg(sc->hg_g[c], mu);
+                        }
+                        int64_t a = edge_rev(sc, e, v);
+                        J += th * exp(-out->tau[e]) * out->phi[a];
+                    }
+                }
+                Iv += Tent * wch * J;
+                tau_after += mu_e[v] * sk;
+            }
+            double Tsurf = exp(-tau_after);
+            if (sc->surface) {
+                int64_t s = nvox + p;
+                double Js = mu0 * exp(-out->tau_sun[s]);
+                if (sc->scatter_order != 1) {
+                    for (int64_t e = sc->adj_ptr[s]; e < sc->adj_ptr[s + 1]; ++e) {
+                        int64_t a = edge_rev(sc, e, s);
+                        Js += exp(-out->tau[e]) * out->phi[a];
+                    }
+                }
+                Iv += Tsurf * (sc->albedo[p] / M_PI) * Js;
+            } else {
+                Iv += Tsurf * (sc->albedo[p] / M_PI) * mu0 * exp(-optical_depth(nx, ny, nz, mu_e, dx, P, sc->sun_dir, 1));
+            }
+            out->pix[p] = Iv;
+        }
+        free(vox);
+        free(dtv);
+    }
+    free(lat); free(tab); free(mu_e); free(omega);
+    return 0;
+}
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* tail of every edge, exported for tests */
+void or_tails(int64_t N, const int64_t *adj_ptr, int64_t E, int64_t *tail) {
+    for (int64_t e = 0; e < E; ++e) tail[e] = tail_of(adj_ptr, N, e);
+}
