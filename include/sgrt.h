@@ -1,0 +1,268 @@
+/*
+ * sgrt.h -- C ABI of the scattering-graph radiative-transfer hot path on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library implements, on one GPU, the hot path of the scattering graph
+ * method (Mikkonen et al., "Scattering graph method for 3D radiative
+ * transfer"): Beer-Lambert-Bouguer transmittance of every graph edge by an
+ * exact voxel march (Sec. 2, Eq. 3 and Eq. 6), the phase-cell weights of
+ * Eq. 7 on a Fibonacci lattice (Sec. 3), assembly of the flux matrix and
+ * the direct-solar source (Eq. 6, Eq. 9), the solve of (I - F) phi = S
+ * (Eq. 8, by the series of Eq. 5 with FP64 iterative refinement and a
+ * GMRES fallback) and the gather of the observed pixel radiances (Eq. 11).
+ *
+ * Conventions used throughout:
+ *  - fixed-point positions, 65536 units per voxel edge, absolute in the box
+ *    [0, nx] x [0, ny] x [0, nz] voxels; the surface is the plane z = 0 and
+ *    the medium outside the box is vacuum;
+ *  - node ids: volume node of voxel (ix, iy, iz) = ix + nx*(iy + ny*iz),
+ *    exactly one per voxel; surface node of column (ix, iy) =
+ *    nx*ny*nz + ix + nx*iy at the column centre on z = 0;
+ *  - directed edge id = its position in the adjacency CSR, so edges are
+ *    sorted by (tail, head); the matrix K that the library builds is the
+ *    transpose of the paper's F: row = destination edge b, column = source
+ *    edge a, K[b][a] = T_a * rho_l * Q_l(a -> b) with l = head(a) = tail(b);
+ *  - radiances are in units of the solar flux F0 per steradian (F0 = 1 on a
+ *    plane normal to the beam).
+ *
+ * Every entry point returns an sg_status and never throws or aborts across
+ * the ABI.  On a non-OK status, sg_last_error() returns a message for the
+ * calling thread.  A device failure (SG_E_DEVICE) is sticky for the context:
+ * every later call on that context returns it.
+ *
+ * Thread safety: distinct scenes may be solved concurrently from different
+ * threads; one scene must not be used by two threads at once.  The server
+ * owns its worker threads.
+ */
+#ifndef SGRT_H
+#define SGRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SG_ABI_VERSION 1u
+
+typedef int32_t sg_status;
+enum {
+    SG_OK = 0,
+    SG_E_INVALID = -1, /* malformed argument or scene */
+    SG_E_NOMEM = -2,   /* device allocation failed or the context's HBM budget is exceeded */
+    SG_E_DEVICE = -3,  /* a HIP call or kernel failed; sticky for the context */
+    SG_E_NOCONV = -4,  /* the solve stopped above its tolerance; outputs hold the best iterate */
+    SG_E_BUSY = -5,    /* server queue full, try again */
+    SG_E_ABI = -6,     /* abi_version mismatch */
+    SG_E_STATE = -7    /* operation needs a prior solve (exports) or a finished ticket */
+};
+
+/* Thread-local text of the last non-OK status on the calling thread ("" if none). */
+const char *sg_last_error(void);
+
+/* SG_ABI_VERSION of the loaded library. */
+uint32_t sg_abi_version(void);
+
+typedef struct sg_ctx sg_ctx;
+typedef struct sg_scene sg_scene;
+typedef struct sg_server sg_server;
+
+/*
+ * Create a context on HIP device `hip_device`.  hbm_budget_bytes caps the
+ * device memory the context's scenes may hold (0 = 90% of the device's
+ * free memory at creation).  The context owns one default-priority HIP
+ * stream, used when a call passes hip_stream = NULL.
+ * Errors: SG_E_INVALID (bad device), SG_E_DEVICE.
+ */
+sg_status sg_ctx_create(int32_t hip_device, uint64_t hbm_budget_bytes, sg_ctx **out);
+
+/* Destroy a context.  All its scenes must have been destroyed first (else SG_E_STATE). */
+sg_status sg_ctx_destroy(sg_ctx *ctx);
+
+/*
+ * A scene: voxel medium, scattering graph G(R, L) (Sec. 2, after Eq. 4),
+ * surface, illumination and view.  All pointers are host memory, borrowed
+ * for the duration of sg_scene_create only (the library copies them).
+ */
+typedef struct sg_scene_desc {
+    uint32_t abi_version;      /* SG_ABI_VERSION */
+    int32_t nx, ny, nz;        /* grid, 1..1024 each */
+    double voxel_m;            /* voxel edge in metres, > 0 */
+    const float *mu_s;         /* [nz][ny][nx] scattering coefficient, 1/m, finite, >= 0 */
+    const float *mu_a;         /* [nz][ny][nx] absorption coefficient, 1/m, finite, >= 0 */
+    int32_t n_phase;           /* 1..4 Henyey-Greenstein components */
+    const double *hg_g;        /* [n_phase] asymmetry parameters, |g| < 1 */
+    const float *phase_frac;   /* [n_phase][nz][ny][nx] mixing fractions (by scattering
+                                  coefficient); NULL iff n_phase == 1 */
+    const int32_t *vol_pos_fx; /* [nz*ny*nx][3] node positions (x, y, z), fixed point,
+                                  strictly inside the node's own voxel */
+    int32_t surface_nodes;     /* 1: one Lambertian node per column at z = 0; 0: none */
+    const int64_t *adj_ptr;    /* [N + 1] symmetric adjacency CSR over node ids */
+    const int32_t *adj_idx;    /* [E] heads, ascending within a row, no self loops,
+                                  no surface-surface pairs, node degree <= 64 */
+    const float *surf_albedo;  /* [ny][nx] Lambertian albedo in [0, 1] */
+    int32_t sun_dir[3];        /* integer vector toward the sun (z > 0), |components| <= 2^22 */
+    int32_t view_dir[3];       /* integer vector toward the sensor (z > 0), |components| <= 2^22 */
+    int32_t n_fib;             /* Fibonacci lattice size, 1..128 (the paper uses 100) */
+    int32_t node_weight_mode;  /* 0: rho = w (1 - exp(-mu_e * voxel_m)) (bounded scattering
+                                  probability); 1: rho = mu_s * voxel_m (literal) */
+    int32_t n_lambda;          /* wavelengths solved together, 1..256 */
+    const float *abs_scale;    /* [n_lambda] multipliers of mu_a per wavelength (> 0);
+                                  NULL means one wavelength with multiplier 1 */
+} sg_scene_desc;
+
+/*
+ * Validate a scene on the host, copy it to the device and reserve all the
+ * device memory its solves need (nothing is allocated by sg_solve).  The
+ * copies are enqueued on hip_stream (NULL: the context stream) and are
+ * complete when the call returns.
+ * Errors: SG_E_ABI, SG_E_INVALID (with the reason), SG_E_NOMEM (budget or
+ * allocation), SG_E_DEVICE.
+ */
+sg_status sg_scene_create(sg_ctx *ctx, const sg_scene_desc *desc, void *hip_stream, sg_scene **out);
+
+/* Release a scene's device memory (waits for its work to finish). */
+sg_status sg_scene_destroy(sg_scene *scene);
+
+/*
+ * Sizes of a scene: nodes N, directed edges E (= couplings, rows of K),
+ * structural nonzeros of K (sum over nodes of degree^2), the largest
+ * degree, wavelengths, and the device bytes reserved.  Any pointer may be NULL.
+ */
+sg_status sg_scene_sizes(const sg_scene *scene, int64_t *n_nodes, int64_t *n_edges, int64_t *nnz,
+                         int32_t *max_degree, int32_t *n_lambda, uint64_t *device_bytes);
+
+enum { SG_FP32 = 0, SG_FP64 = 1 };
+enum { SG_SOLVER_AUTO = 0, SG_SOLVER_NEUMANN = 1, SG_SOLVER_GMRES = 2 };
+
+typedef struct sg_solve_opts {
+    uint32_t abi_version;  /* SG_ABI_VERSION */
+    int32_t precision;     /* SG_FP32: march, matrix and sweeps in FP32, residual and pixel
+                              accumulation in FP64; SG_FP64: everything in FP64 */
+    int32_t solver;        /* SG_SOLVER_AUTO: Neumann sweeps, GMRES if they stall */
+    double rtol;           /* target of ||S - (I - K) phi||_1 / ||S||_1 (<= 0: 1e-6 FP32, 1e-12 FP64) */
+    int32_t max_sweeps;    /* cap on matrix sweeps of all kinds (<= 0: 2000) */
+    int32_t gmres_restart; /* GMRES(m) restart length, 2..64 (<= 0: 32) */
+    int32_t scatter_order; /* 0: multiple scattering; 1: single scattering only (no solve) */
+    int32_t build_col_idx; /* 1: also materialise the CSR column index array */
+    int32_t timing;        /* 1: per-stage HIP-event timings into sg_solve_info */
+} sg_solve_opts;
+
+typedef struct sg_solve_info {
+    int32_t converged;      /* 1 if every wavelength reached rtol */
+    int32_t sweeps;         /* matrix sweeps (FP32 + FP64 residual + GMRES products) */
+    int32_t gmres_used;     /* 1 if GMRES ran for any wavelength */
+    int32_t refinements;    /* FP64 residual evaluations */
+    double rel_residual;    /* max over wavelengths of the final FP64 relative residual */
+    double ms_structure;    /* timings (timing = 1): CSR structure from the adjacency */
+    double ms_march;        /* edge and sun transmittances */
+    double ms_qbuild;       /* phase cells, matrix values and source */
+    double ms_solve;        /* all sweeps and residuals */
+    double ms_gather;       /* pixel radiances */
+    double ms_total;
+    double ms_spmv_sum;     /* summed duration of the FP32/FP64 sweep kernel launches */
+    int32_t spmv_launches;  /* their number */
+    int32_t reserved;
+    int64_t n_nodes, n_edges, nnz;
+} sg_solve_info;
+
+/*
+ * Solve the scene for all its wavelengths: transmittances (Eq. 3, Eq. 6),
+ * phase cells (Eq. 7), K and S (Eq. 6, Eq. 9), phi = (I - K)^-1 S (Eq. 5,
+ * Eq. 8) and the pixel radiances (Eq. 11).  radiance: [n_lambda][ny][nx]
+ * doubles, caller-allocated, host memory (radiance_on_device = 0) or device
+ * memory on the context's device (1).  Kernels run on hip_stream (NULL: the
+ * context stream); the call returns when the radiances are written.
+ * opts may be NULL (defaults); info may be NULL.
+ * Errors: SG_E_INVALID, SG_E_NOCONV (radiances of the best iterate are
+ * still written), SG_E_DEVICE.
+ */
+sg_status sg_solve(sg_scene *scene, const sg_solve_opts *opts, void *hip_stream, double *radiance,
+                   int32_t radiance_on_device, sg_solve_info *info);
+
+/*
+ * Verification exports of the last sg_solve (host buffers, NULL to skip).
+ * sg_export_csr: K of wavelength `lambda` as CSR: row_ptr [E + 1], col_idx
+ * [nnz] (ascending in-edges of the row's tail node, Sec. 2 line-graph
+ * structure), val [nnz] as double; the column index is built on the device
+ * if the solve did not build it.
+ */
+sg_status sg_export_csr(sg_scene *scene, int32_t lambda, int64_t *row_ptr, int32_t *col_idx, double *val);
+
+enum {
+    SG_VEC_TAU_S = 0,   /* [E] optical depth of mu_s along each edge's pair (Eq. 3 path integral) */
+    SG_VEC_TAU_A = 1,   /* [E] same for mu_a */
+    SG_VEC_TAU_SUN_S = 2, /* [N] node -> sun, mu_s channel (marched until it alone exceeds the cutoff) */
+    SG_VEC_TAU_SUN_A = 3, /* [N] node -> sun, mu_a channel */
+    SG_VEC_RHO = 4,     /* [n_lambda][N] node weights */
+    SG_VEC_SOURCE = 5,  /* [n_lambda][E] source S (Eq. 9) */
+    SG_VEC_PHI = 6,     /* [n_lambda][E] solution phi (Eq. 10) */
+    SG_VEC_QSUN = 7     /* [E] phase-cell weight of the sun direction per out-edge (Eq. 7) */
+};
+/* Copy one vector of the last solve, as double, into out (host). */
+sg_status sg_export_vector(sg_scene *scene, int32_t which, double *out);
+
+enum { SG_TRACE_EDGE = 0, SG_TRACE_SUN = 1, SG_TRACE_VIEW = 2 };
+/*
+ * Voxel traversal used by the march kernels (the exact integer walk of the
+ * Beer-Lambert-Bouguer path integral), for n_ids paths in one launch:
+ * SG_TRACE_EDGE id = directed edge (walked from the lower to the higher node
+ * id), SG_TRACE_SUN id = node (to the grid exit along sun_dir),
+ * SG_TRACE_VIEW id = pixel ix + nx*iy (from its surface point along
+ * view_dir).  Host buffers: voxels [n_ids][cap] (int32 voxel ids), dt
+ * [n_ids][cap] (parameter length inside the voxel, as double), count
+ * [n_ids] (voxels of the path; a value > cap means truncated output).
+ */
+sg_status sg_trace(sg_scene *scene, int32_t kind, const int64_t *ids, int32_t n_ids, int32_t cap,
+                   int32_t *voxels, double *dt, int32_t *count);
+
+/* ------------------------------------------------------------------------------------ */
+/* Serving: continuous batching of many scenes on one device                             */
+/* ------------------------------------------------------------------------------------ */
+
+typedef struct sg_server_opts {
+    uint32_t abi_version;     /* SG_ABI_VERSION */
+    int32_t max_resident;     /* scenes held on the device at once (>= 1) */
+    int32_t queue_cap;        /* pending requests before sg_submit returns SG_E_BUSY (>= 1) */
+    int32_t n_streams;        /* concurrent device streams used by the scheduler (1..8) */
+    sg_solve_opts solve;      /* options applied to every request */
+} sg_server_opts;
+
+/*
+ * Start a server on a context.  It admits queued scenes when a resident
+ * slot is free and their reserved bytes fit the context's HBM budget,
+ * overlaps the resident scenes' work on n_streams device streams, and
+ * completes each ticket independently.
+ */
+sg_status sg_server_create(sg_ctx *ctx, const sg_server_opts *opts, sg_server **out);
+
+/*
+ * Queue a scene (copied on the host before return; desc arrays are
+ * borrowed for the call only).  Non-blocking.  Errors: SG_E_BUSY (queue
+ * full), SG_E_INVALID (scene rejected), SG_E_NOMEM (the scene alone exceeds
+ * the budget).
+ */
+sg_status sg_submit(sg_server *srv, const sg_scene_desc *desc, uint64_t *ticket);
+
+/*
+ * Poll a ticket: *done = 1 when finished, then radiance ([n_lambda][ny][nx],
+ * host, may be NULL) and info are written and the ticket is released;
+ * returns the request's own status (e.g. SG_E_NOCONV).  *done = 0: still
+ * queued or running.
+ */
+sg_status sg_poll(sg_server *srv, uint64_t ticket, double *radiance, sg_solve_info *info, int32_t *done);
+
+/* Block until the ticket finishes; same outputs as sg_poll. */
+sg_status sg_wait(sg_server *srv, uint64_t ticket, double *radiance, sg_solve_info *info);
+
+/* Per-request wall times: arrival (sg_submit) to completion, in ms; writes up to cap values. */
+sg_status sg_server_latencies(sg_server *srv, double *ms, int32_t cap, int32_t *n);
+
+/* Drain in-flight work and stop the server. */
+sg_status sg_server_destroy(sg_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGRT_H */

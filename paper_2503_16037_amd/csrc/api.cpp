@@ -1,0 +1,904 @@
+// Host runtime of the library: the C ABI of sgrt.h, scene validation and
+// device memory, and the solve orchestration (sweeps, FP64 residuals and
+// iterative refinement, GMRES fallback, timing).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+namespace sg {
+
+namespace {
+thread_local std::string t_err;
+}
+
+void set_error(const std::string &msg) { t_err = msg; }
+
+namespace {
+
+sg_status fail(sg_status st, const std::string &msg) {
+    set_error(msg);
+    return st;
+}
+
+sg_status device_fail(Ctx *ctx, const char *what, hipError_t e) {
+    if (ctx) ctx->sticky.store(1);
+    return fail(SG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define SG_HIP(call)                                                   \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) return device_fail(ctx, #call, e_);      \
+    } while (0)
+
+bool reserve(Ctx *ctx, uint64_t bytes) {
+    uint64_t cur = ctx->used.load();
+    while (true) {
+        if (cur + bytes > ctx->budget) return false;
+        if (ctx->used.compare_exchange_weak(cur, cur + bytes)) return true;
+    }
+}
+
+void release(Ctx *ctx, uint64_t bytes) { ctx->used.fetch_sub(bytes); }
+
+// Device allocation tracked against the context budget.
+template <class T>
+sg_status dalloc(Scene &s, T **p, size_t count) {
+    Ctx *ctx = s.ctx;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (!reserve(ctx, bytes)) return fail(SG_E_NOMEM, "HBM budget exceeded");
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e != hipSuccess) {
+        release(ctx, bytes);
+        (void)hipGetLastError();
+        return fail(SG_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    s.bytes += bytes;
+    return SG_OK;
+}
+
+#define SG_TRY(x)                          \
+    do {                                   \
+        sg_status st_ = (x);               \
+        if (st_ != SG_OK) return st_;      \
+    } while (0)
+
+// Fibonacci lattice, as the exact operation sequence z_i = 1 - (2i + 1) / N,
+// phi_i = (i * pi (3 - sqrt 5)) mod 2 pi, p_i = (r cos phi_i, r sin phi_i, z_i),
+// r = sqrt(1 - z_i z_i) (this file is compiled without FP contraction).
+void host_lattice(int N, std::vector<double> &p) {
+    p.resize(3 * (size_t)N);
+    const double ga = M_PI * (3.0 - std::sqrt(5.0));
+    const double two_pi = 2.0 * M_PI;
+    for (int i = 0; i < N; ++i) {
+        const double z = 1.0 - (2.0 * (double)i + 1.0) / (double)N;
+        const double ph = std::fmod((double)i * ga, two_pi);
+        const double r = std::sqrt(1.0 - z * z);
+        p[3 * i] = r * std::cos(ph);
+        p[3 * i + 1] = r * std::sin(ph);
+        p[3 * i + 2] = z;
+    }
+}
+
+// Per-component Henyey-Greenstein table normalised over the lattice, then the
+// Lambertian cosine weights max(0, z_i) / sum_j max(0, z_j).
+void host_tables(int N, const std::vector<double> &p, int n_phase, const double *g, std::vector<double> &t) {
+    t.assign((size_t)(n_phase + 1) * N, 0.0);
+    for (int k = 0; k < n_phase; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < N; ++i) {
+            const double mu = p[3 * i + 2];
+            const double den = 1.0 + g[k] * g[k] - 2.0 * g[k] * mu;
+            const double v = (1.0 - g[k] * g[k]) / (4.0 * M_PI * den * std::sqrt(den));
+            t[(size_t)k * N + i] = v;
+            s += v;
+        }
+        for (int i = 0; i < N; ++i) t[(size_t)k * N + i] = t[(size_t)k * N + i] / s;
+    }
+    double tot = 0.0;
+    for (int i = 0; i < N; ++i) tot += std::max(0.0, p[3 * i + 2]);
+    for (int i = 0; i < N; ++i) t[(size_t)n_phase * N + i] = std::max(0.0, p[3 * i + 2]) / tot;
+}
+
+void unit3(const int v[3], double u[3], double sign) {
+    const long long x = v[0], y = v[1], z = v[2];
+    const double n = std::sqrt((double)(x * x + y * y + z * z));
+    u[0] = (double)(long long)(sign * x) / n;
+    u[1] = (double)(long long)(sign * y) / n;
+    u[2] = (double)(long long)(sign * z) / n;
+}
+
+sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz, int &dmax) {
+    if (!d) return fail(SG_E_INVALID, "desc is NULL");
+    if (d->abi_version != SG_ABI_VERSION) return fail(SG_E_ABI, "scene desc abi_version mismatch");
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nx > 1024 || d->ny > 1024 || d->nz > 1024)
+        return fail(SG_E_INVALID, "grid dimensions must be in 1..1024");
+    if (!(d->voxel_m > 0.0) || !std::isfinite(d->voxel_m)) return fail(SG_E_INVALID, "voxel_m must be > 0");
+    if (!d->mu_s || !d->mu_a || !d->vol_pos_fx || !d->adj_ptr || !d->surf_albedo || !d->hg_g)
+        return fail(SG_E_INVALID, "a required array is NULL");
+    if (d->n_phase < 1 || d->n_phase > 4) return fail(SG_E_INVALID, "n_phase must be 1..4");
+    if ((d->n_phase > 1) != (d->phase_frac != nullptr))
+        return fail(SG_E_INVALID, "phase_frac must be given iff n_phase > 1");
+    for (int k = 0; k < d->n_phase; ++k)
+        if (!(std::fabs(d->hg_g[k]) < 1.0)) return fail(SG_E_INVALID, "|g| must be < 1");
+    if (d->n_fib < 1 || d->n_fib > 128) return fail(SG_E_INVALID, "n_fib must be 1..128");
+    if (d->node_weight_mode != 0 && d->node_weight_mode != 1) return fail(SG_E_INVALID, "node_weight_mode must be 0 or 1");
+    if (d->n_lambda < 1 || d->n_lambda > 256) return fail(SG_E_INVALID, "n_lambda must be 1..256");
+    if (d->n_lambda > 1 && !d->abs_scale) return fail(SG_E_INVALID, "abs_scale required when n_lambda > 1");
+    if (d->abs_scale)
+        for (int k = 0; k < d->n_lambda; ++k)
+            if (!(d->abs_scale[k] > 0.0f) || !std::isfinite(d->abs_scale[k]))
+                return fail(SG_E_INVALID, "abs_scale must be finite and > 0");
+    for (const int32_t *v : {d->sun_dir, d->view_dir}) {
+        if (v[2] <= 0) return fail(SG_E_INVALID, "sun_dir and view_dir need a positive z component");
+        for (int k = 0; k < 3; ++k)
+            if (std::abs((long long)v[k]) > (1LL << 22)) return fail(SG_E_INVALID, "direction components must be <= 2^22");
+    }
+    const int64_t nvox = (int64_t)d->nx * d->ny * d->nz;
+    N = nvox + (d->surface_nodes ? (int64_t)d->nx * d->ny : 0);
+    for (int64_t v = 0; v < nvox; ++v) {
+        const float a = d->mu_s[v], b = d->mu_a[v];
+        if (!(a >= 0.0f) || !(b >= 0.0f) || !std::isfinite(a) || !std::isfinite(b))
+            return fail(SG_E_INVALID, "mu_s and mu_a must be finite and >= 0");
+    }
+    if (d->phase_frac)
+        for (int64_t v = 0; v < nvox * d->n_phase; ++v)
+            if (!(d->phase_frac[v] >= 0.0f) || !(d->phase_frac[v] <= 1.0f))
+                return fail(SG_E_INVALID, "phase_frac must be in [0, 1]");
+    for (int64_t v = 0; v < (int64_t)d->nx * d->ny; ++v)
+        if (!(d->surf_albedo[v] >= 0.0f) || !(d->surf_albedo[v] <= 1.0f))
+            return fail(SG_E_INVALID, "surf_albedo must be in [0, 1]");
+    for (int64_t v = 0; v < nvox; ++v) {
+        const int64_t ix = v % d->nx, iy = (v / d->nx) % d->ny, iz = v / ((int64_t)d->nx * d->ny);
+        const int64_t p[3] = {d->vol_pos_fx[3 * v], d->vol_pos_fx[3 * v + 1], d->vol_pos_fx[3 * v + 2]};
+        const int64_t c[3] = {ix, iy, iz};
+        for (int k = 0; k < 3; ++k)
+            if (!(p[k] > c[k] * 65536 && p[k] < (c[k] + 1) * 65536))
+                return fail(SG_E_INVALID, "node position not strictly inside its voxel (node " + std::to_string(v) + ")");
+    }
+    const int64_t *ap = d->adj_ptr;
+    if (ap[0] != 0) return fail(SG_E_INVALID, "adj_ptr[0] must be 0");
+    for (int64_t l = 0; l < N; ++l)
+        if (ap[l + 1] < ap[l]) return fail(SG_E_INVALID, "adj_ptr must be non-decreasing");
+    E = ap[N];
+    if (E >= (1LL << 31) - 1) return fail(SG_E_INVALID, "too many edges");
+    if (E > 0 && !d->adj_idx) return fail(SG_E_INVALID, "adj_idx is NULL");
+    nnz = 0;
+    dmax = 0;
+    for (int64_t l = 0; l < N; ++l) {
+        const int64_t deg = ap[l + 1] - ap[l];
+        if (deg > 64) return fail(SG_E_INVALID, "node degree above 64 (node " + std::to_string(l) + ")");
+        dmax = std::max<int>(dmax, (int)deg);
+        nnz += deg * deg;
+        for (int64_t e = ap[l]; e < ap[l + 1]; ++e) {
+            const int64_t j = d->adj_idx[e];
+            if (j < 0 || j >= N) return fail(SG_E_INVALID, "adjacency head out of range");
+            if (j == l) return fail(SG_E_INVALID, "self loop");
+            if (e > ap[l] && d->adj_idx[e - 1] >= j) return fail(SG_E_INVALID, "adjacency rows must be strictly ascending");
+            if (l >= nvox && j >= nvox) return fail(SG_E_INVALID, "surface-surface pair");
+            const int32_t *b = d->adj_idx + ap[j], *en = d->adj_idx + ap[j + 1];
+            const int32_t *it = std::lower_bound(b, en, (int32_t)l);
+            if (it == en || *it != l) return fail(SG_E_INVALID, "adjacency is not symmetric");
+        }
+    }
+    return SG_OK;
+}
+
+void fill_default_opts(sg_solve_opts &o) {
+    std::memset(&o, 0, sizeof(o));
+    o.abi_version = SG_ABI_VERSION;
+}
+
+// HIP-event timing of the stages of one solve.
+struct Timing {
+    bool on = false;
+    hipStream_t st = nullptr;
+    std::vector<hipEvent_t> ev;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spmv;
+    hipEvent_t mark() {
+        hipEvent_t e = nullptr;
+        if (!on) return e;
+        (void)hipEventCreate(&e);
+        (void)hipEventRecord(e, st);
+        ev.push_back(e);
+        return e;
+    }
+    ~Timing() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    double between(hipEvent_t a, hipEvent_t b) {
+        if (!a || !b) return 0.0;
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        return (double)ms;
+    }
+};
+
+template <class Real>
+sg_status ensure_real(Scene &s) {
+    const int rb = (int)sizeof(Real);
+    if (s.real_bytes == rb) return SG_OK;
+    Ctx *ctx = s.ctx;
+    auto drop = [&](void *&p, size_t n) {
+        if (p) {
+            (void)hipFree(p);
+            release(ctx, n);
+            s.bytes -= n;
+            p = nullptr;
+        }
+    };
+    if (s.real_bytes) {
+        const size_t ob = (size_t)s.real_bytes;
+        drop(s.tau_s, s.E * ob); drop(s.tau_a, s.E * ob); drop(s.T, s.E * ob);
+        drop(s.tsun_s, s.N * ob); drop(s.tsun_a, s.N * ob); drop(s.Tsun, s.N * ob); drop(s.rho, s.N * ob);
+        drop(s.val, s.nnz * ob); drop(s.S, s.E * ob); drop(s.x, s.E * ob); drop(s.y, s.E * ob);
+        drop(s.c_rhs, s.E * ob); drop(s.c_a, s.E * ob); drop(s.c_b, s.E * ob);
+        s.real_bytes = 0;
+    }
+    Real *p;
+    SG_TRY(dalloc(s, &p, s.E)); s.tau_s = p;
+    SG_TRY(dalloc(s, &p, s.E)); s.tau_a = p;
+    SG_TRY(dalloc(s, &p, s.E)); s.T = p;
+    SG_TRY(dalloc(s, &p, s.N)); s.tsun_s = p;
+    SG_TRY(dalloc(s, &p, s.N)); s.tsun_a = p;
+    SG_TRY(dalloc(s, &p, s.N)); s.Tsun = p;
+    SG_TRY(dalloc(s, &p, s.N)); s.rho = p;
+    SG_TRY(dalloc(s, &p, (size_t)s.nnz)); s.val = p;
+    SG_TRY(dalloc(s, &p, s.E)); s.S = p;
+    SG_TRY(dalloc(s, &p, s.E)); s.x = p;
+    SG_TRY(dalloc(s, &p, s.E)); s.y = p;
+    SG_TRY(dalloc(s, &p, s.E)); s.c_rhs = p;
+    SG_TRY(dalloc(s, &p, s.E)); s.c_a = p;
+    SG_TRY(dalloc(s, &p, s.E)); s.c_b = p;
+    s.real_bytes = rb;
+    return SG_OK;
+}
+
+// Read n doubles of device scalars after the stream drains.
+sg_status read_scalars(Scene &s, hipStream_t st, const double *dev, double *host, int n) {
+    Ctx *ctx = s.ctx;
+    SG_HIP(hipMemcpyAsync(host, dev, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    SG_HIP(hipStreamSynchronize(st));
+    return SG_OK;
+}
+
+struct SolveStats {
+    int sweeps = 0, refinements = 0, gmres_used = 0, converged = 0;
+    double rel = 0.0;
+};
+
+// FP32/FP64 Neumann sweeps x <- rhs + K x from x = 0 until the monitored
+// update ||x_new - x||_1 <= stop, or the sweep ratio shows a stall (>= 0.95 or
+// growth).  Returns 1 on a stall.  The solution ends in *xfinal.
+template <class Real>
+sg_status neumann(Scene &s, hipStream_t st, Timing &tm, const Real *rhs, Real *&xa, Real *&xb, double stop,
+                  int max_sweeps, SolveStats &ss, int &stalled) {
+    Ctx *ctx = s.ctx;
+    const int nb = spmv_blocks(s);
+    launch_fill<Real>(xa, (Real)0, s.E, st);
+    std::vector<double> hist;
+    int chunk = 2;
+    stalled = 0;
+    double host[64];
+    while (true) {
+        chunk = std::max(1, std::min(chunk, 32));
+        for (int c = 0; c < chunk; ++c) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (tm.on) e0 = tm.mark();
+            launch_spmv<Real>(s, st, rhs, xa, xb, s.partial);
+            if (tm.on) { e1 = tm.mark(); tm.spmv.push_back({e0, e1}); }
+            launch_reduce(s.partial, nb, s.scal + 16 + c, st);
+            std::swap(xa, xb);
+            ++ss.sweeps;
+        }
+        SG_HIP(hipGetLastError());
+        SG_TRY(read_scalars(s, st, s.scal + 16, host, chunk));
+        for (int c = 0; c < chunk; ++c) hist.push_back(host[c]);
+        const double r = hist.back();
+        if (!std::isfinite(r)) { stalled = 1; break; }
+        if (r <= stop) break;
+        if (ss.sweeps >= max_sweeps) break;
+        double q = 0.5;
+        if (hist.size() >= 2) q = r / hist[hist.size() - 2];
+        if (hist.size() >= 3 && (q >= 0.95 || q > 1.0)) { stalled = 1; break; }
+        q = std::min(std::max(q, 1e-12), 0.95);
+        const double need = std::log(stop / r) / std::log(q);
+        chunk = (int)std::ceil(std::max(1.0, need));
+    }
+    return SG_OK;
+}
+
+template <class Real>
+sg_status gmres64(Scene &s, hipStream_t st, Timing &tm, const Real *S, double nS1, double rtol, int m,
+                  int max_sweeps, SolveStats &ss) {
+    Ctx *ctx = s.ctx;
+    const int64_t E = s.E;
+    if (!s.gm_V || s.gm_m < m) {
+        if (s.gm_V) {
+            (void)hipFree(s.gm_V);
+            release(ctx, (size_t)(s.gm_m + 1) * E * sizeof(double));
+            s.bytes -= (size_t)(s.gm_m + 1) * E * sizeof(double);
+            s.gm_V = nullptr;
+        }
+        SG_TRY(dalloc(s, &s.gm_V, (size_t)(m + 1) * E));
+        s.gm_m = m;
+    }
+    ss.gmres_used = 1;
+    const int nbv = 1024;
+    const int nb = spmv_blocks(s);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), yv(m), h(m + 1), h2(m + 1);
+    double *V = s.gm_V;
+    while (true) {
+        launch_residual64<Real>(s, st, S, s.x64, s.r64, s.partial);
+        launch_reduce(s.partial, nb, s.scal, st);
+        ++ss.sweeps;
+        ++ss.refinements;
+        double r1;
+        SG_TRY(read_scalars(s, st, s.scal, &r1, 1));
+        ss.rel = r1 / nS1;
+        if (ss.rel <= rtol || ss.sweeps >= max_sweeps) break;
+        launch_dot_multi(s.r64, E, 1, s.r64, E, s.partial, nbv, s.scal, st);
+        double beta2;
+        SG_TRY(read_scalars(s, st, s.scal, &beta2, 1));
+        const double beta = std::sqrt(beta2);
+        SG_HIP(hipMemcpyAsync(V, s.r64, sizeof(double) * E, hipMemcpyDeviceToDevice, st));
+        launch_scale64(V, 1.0 / beta, E, st);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        for (; k < m && ss.sweeps < max_sweeps; ++k) {
+            double *vk = V + (size_t)k * E, *w = V + (size_t)(k + 1) * E;
+            launch_apply_imk64<Real>(s, st, vk, w);
+            ++ss.sweeps;
+            // classical Gram-Schmidt, twice
+            launch_dot_multi(V, E, k + 1, w, E, s.partial, nbv, s.scal, st);
+            SG_TRY(read_scalars(s, st, s.scal, h.data(), k + 1));
+            SG_HIP(hipMemcpyAsync(s.scal + 64, h.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, st));
+            launch_axpy_multi(w, V, E, k + 1, s.scal + 64, E, st);
+            launch_dot_multi(V, E, k + 1, w, E, s.partial, nbv, s.scal, st);
+            SG_TRY(read_scalars(s, st, s.scal, h2.data(), k + 1));
+            SG_HIP(hipMemcpyAsync(s.scal + 64, h2.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, st));
+            launch_axpy_multi(w, V, E, k + 1, s.scal + 64, E, st);
+            for (int j = 0; j <= k; ++j) h[j] += h2[j];
+            launch_dot_multi(w, E, 1, w, E, s.partial, nbv, s.scal, st);
+            double hn2;
+            SG_TRY(read_scalars(s, st, s.scal, &hn2, 1));
+            const double hn = std::sqrt(std::max(hn2, 0.0));
+            if (hn > 0) launch_scale64(w, 1.0 / hn, E, st);
+            for (int j = 0; j <= k; ++j) H[(size_t)j * m + k] = h[j];
+            H[(size_t)(k + 1) * m + k] = hn;
+            for (int j = 0; j < k; ++j) {
+                const double a = H[(size_t)j * m + k], b = H[(size_t)(j + 1) * m + k];
+                H[(size_t)j * m + k] = cs[j] * a + sn[j] * b;
+                H[(size_t)(j + 1) * m + k] = -sn[j] * a + cs[j] * b;
+            }
+            const double a = H[(size_t)k * m + k], b = H[(size_t)(k + 1) * m + k];
+            const double den = std::sqrt(a * a + b * b);
+            cs[k] = den > 0 ? a / den : 1.0;
+            sn[k] = den > 0 ? b / den : 0.0;
+            H[(size_t)k * m + k] = den;
+            H[(size_t)(k + 1) * m + k] = 0.0;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            if (std::fabs(g[k + 1]) <= 1e-3 * rtol * beta || hn == 0.0) { ++k; break; }
+        }
+        for (int j = k - 1; j >= 0; --j) {
+            double acc = g[j];
+            for (int q = j + 1; q < k; ++q) acc -= H[(size_t)j * m + q] * yv[q];
+            yv[j] = acc / H[(size_t)j * m + j];
+        }
+        // x64 += V y  (axpy_multi subtracts, so pass -y)
+        std::vector<double> ny(k);
+        for (int j = 0; j < k; ++j) ny[j] = -yv[j];
+        SG_HIP(hipMemcpyAsync(s.scal + 64, ny.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+        launch_axpy_multi(s.x64, V, E, k, s.scal + 64, E, st);
+        SG_HIP(hipStreamSynchronize(st));
+    }
+    ss.converged = ss.rel <= rtol;
+    return SG_OK;
+}
+
+template <class Real>
+sg_status solve_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Timing &tm, SolveStats &ss) {
+    Ctx *ctx = s.ctx;
+    const int64_t E = s.E;
+    const double rtol = o.rtol > 0 ? o.rtol : (sizeof(Real) == 4 ? 1e-6 : 1e-12);
+    const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 2000;
+    const int m = o.gmres_restart > 0 ? std::min(std::max(o.gmres_restart, 2), 64) : 32;
+    Real *S = (Real *)s.S;
+    launch_norm1_real<Real>(S, E, s.partial, 1024, s.scal, st);
+    double nS1;
+    SG_TRY(read_scalars(s, st, s.scal, &nS1, 1));
+    launch_fill<double>(s.x64, 0.0, E, st);
+    if (nS1 == 0.0) {
+        ss.converged = 1;
+        ss.rel = 0.0;
+        return SG_OK;
+    }
+    const int nb = spmv_blocks(s);
+    int use_gmres = o.solver == SG_SOLVER_GMRES;
+    if (!use_gmres) {
+        Real *xa = (Real *)s.x, *xb = (Real *)s.y;
+        int stalled = 0;
+        const double floor_rel = sizeof(Real) == 4 ? 2e-7 : 1e-15;
+        SG_TRY(neumann<Real>(s, st, tm, S, xa, xb, std::max(0.3 * rtol, floor_rel) * nS1, max_sweeps, ss, stalled));
+        launch_to64<Real>(xa, s.x64, E, st);
+        if (stalled && o.solver == SG_SOLVER_AUTO) use_gmres = 1;
+        // FP64 residual and iterative refinement
+        for (int it = 0; !use_gmres && it < 12; ++it) {
+            launch_residual64<Real>(s, st, S, s.x64, s.r64, s.partial);
+            launch_reduce(s.partial, nb, s.scal, st);
+            ++ss.sweeps;
+            ++ss.refinements;
+            double r1;
+            SG_TRY(read_scalars(s, st, s.scal, &r1, 1));
+            ss.rel = r1 / nS1;
+            if (ss.rel <= rtol) { ss.converged = 1; break; }
+            if (ss.sweeps >= max_sweeps) break;
+            // correction (I - K) d = r by sweeps in the working precision, with r scaled to
+            // the magnitude of S so that it stays well inside the FP32 range
+            const double sc = nS1 / r1;
+            Real *crhs = (Real *)s.c_rhs, *c0 = (Real *)s.c_a, *c1 = (Real *)s.c_b;
+            launch_scaled_to_real<Real>(s.r64, sc, crhs, E, st);
+            int stalled2 = 0;
+            SG_TRY(neumann<Real>(s, st, tm, crhs, c0, c1, std::max(1e-5, floor_rel) * nS1, max_sweeps, ss, stalled2));
+            launch_axpy_real_to64<Real>(s.x64, c0, 1.0 / sc, E, st);
+            if (stalled2 && o.solver == SG_SOLVER_AUTO) use_gmres = 1;
+        }
+    }
+    if (use_gmres) SG_TRY(gmres64<Real>(s, st, tm, S, nS1, rtol, m, max_sweeps, ss));
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+template <class Real>
+sg_status solve_single(Scene &s, const sg_solve_opts &o, hipStream_t st, double *radiance, int on_dev,
+                       sg_solve_info *info) {
+    Ctx *ctx = s.ctx;
+    SG_TRY(ensure_real<Real>(s));
+    Timing tm;
+    tm.on = o.timing != 0;
+    tm.st = st;
+    const float scale = s.abs_scale.empty() ? 1.0f : s.abs_scale[0];
+    hipEvent_t e0 = tm.mark();
+    launch_structure(s, st);
+    if (o.build_col_idx) {
+        if (!s.col_idx) SG_TRY(dalloc(s, &s.col_idx, (size_t)s.nnz));
+        launch_col_idx(s, st);
+        s.col_built = true;
+    } else {
+        s.col_built = false;
+    }
+    hipEvent_t e1 = tm.mark();
+    launch_march<Real>(s, st, scale, 1);
+    launch_node_weights<Real>(s, st, scale);
+    hipEvent_t e2 = tm.mark();
+    launch_qbuild<Real>(s, st, 0);
+    hipEvent_t e3 = tm.mark();
+    SG_HIP(hipGetLastError());
+    SolveStats ss;
+    if (o.scatter_order == 1) {
+        launch_fill<double>(s.x64, 0.0, s.E, st);
+        ss.converged = 1;
+    } else {
+        SG_TRY(solve_linear<Real>(s, o, st, tm, ss));
+    }
+    hipEvent_t e4 = tm.mark();
+    double *dst = on_dev ? radiance : s.pix;
+    launch_gather<Real>(s, st, s.x64, o.scatter_order, dst);
+    hipEvent_t e5 = tm.mark();
+    SG_HIP(hipGetLastError());
+    if (!on_dev) {
+        SG_HIP(hipMemcpyAsync(radiance, dst, sizeof(double) * s.npx, hipMemcpyDeviceToHost, st));
+    }
+    SG_HIP(hipStreamSynchronize(st));
+    s.solved = true;
+    s.last_precision = sizeof(Real) == 4 ? SG_FP32 : SG_FP64;
+    s.last_scatter_order = o.scatter_order;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->converged = ss.converged;
+        info->sweeps = ss.sweeps;
+        info->gmres_used = ss.gmres_used;
+        info->refinements = ss.refinements;
+        info->rel_residual = ss.rel;
+        info->n_nodes = s.N;
+        info->n_edges = s.E;
+        info->nnz = s.nnz;
+        if (tm.on) {
+            info->ms_structure = tm.between(e0, e1);
+            info->ms_march = tm.between(e1, e2);
+            info->ms_qbuild = tm.between(e2, e3);
+            info->ms_solve = tm.between(e3, e4);
+            info->ms_gather = tm.between(e4, e5);
+            info->ms_total = tm.between(e0, e5);
+            double sum = 0.0;
+            for (auto &p : tm.spmv) sum += tm.between(p.first, p.second);
+            info->ms_spmv_sum = sum;
+            info->spmv_launches = (int)tm.spmv.size();
+        }
+    }
+    if (!ss.converged) return fail(SG_E_NOCONV, "solve stopped at relative residual " + std::to_string(ss.rel));
+    return SG_OK;
+}
+
+}  // namespace
+}  // namespace sg
+
+using namespace sg;
+
+struct sg_ctx : public sg::Ctx {};
+struct sg_scene : public sg::Scene {};
+
+extern "C" {
+
+const char *sg_last_error(void) { return t_err.c_str(); }
+
+uint32_t sg_abi_version(void) { return SG_ABI_VERSION; }
+
+sg_status sg_ctx_create(int32_t hip_device, uint64_t hbm_budget_bytes, sg_ctx **out) {
+    if (!out) return fail(SG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(SG_E_DEVICE, "no HIP device");
+    if (hip_device < 0 || hip_device >= n) return fail(SG_E_INVALID, "bad device index");
+    Ctx *ctx = nullptr;
+    SG_HIP(hipSetDevice(hip_device));
+    size_t fr = 0, tot = 0;
+    SG_HIP(hipMemGetInfo(&fr, &tot));
+    std::unique_ptr<sg_ctx> c(new sg_ctx());
+    c->device = hip_device;
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)fr);
+    ctx = c.get();
+    SG_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    *out = c.release();
+    return SG_OK;
+}
+
+sg_status sg_ctx_destroy(sg_ctx *ctx) {
+    if (!ctx) return fail(SG_E_INVALID, "ctx is NULL");
+    if (ctx->n_scenes.load() != 0) return fail(SG_E_STATE, "context still has scenes");
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return SG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+void free_scene(Scene *s) {
+    void *ptrs[] = {s->mu_s, s->mu_a, s->frac, s->albedo, s->abs_scale_d, s->pos, s->adj_ptr, s->adj_idx, s->lat,
+                    s->tab, s->rev, s->nodeoff, s->row_ptr, s->col_idx, s->scan_tmp, s->tau_s, s->tau_a, s->tsun_s,
+                    s->tsun_a, s->T, s->Tsun, s->rho, s->val, s->S, s->x, s->y, s->c_rhs, s->c_a, s->c_b, s->qsun,
+                    s->q, s->bS, s->bx, s->by, s->brho, s->x64, s->r64, s->gm_V, s->partial, s->scal, s->J, s->pix};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (s->ctx) release(s->ctx, s->bytes);
+    s->bytes = 0;
+}
+
+sg_status upload(Scene &s, void *dst, const void *src, size_t bytes, hipStream_t st) {
+    Ctx *ctx = s.ctx;
+    SG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    return SG_OK;
+}
+
+sg_status create_scene(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Scene &s) {
+    int64_t N, E, nnz;
+    int dmax;
+    SG_TRY(validate(d, N, E, nnz, dmax));
+    s.ctx = ctx;
+    s.nx = d->nx; s.ny = d->ny; s.nz = d->nz;
+    s.voxel_m = d->voxel_m;
+    s.nvox = d->nx * d->ny * d->nz;
+    s.N = (int)N;
+    s.npx = d->nx * d->ny;
+    s.E = E;
+    s.nnz = nnz;
+    s.dmax = std::max(dmax, 1);
+    s.n_phase = d->n_phase;
+    for (int k = 0; k < d->n_phase; ++k) s.hg_g[k] = d->hg_g[k];
+    s.n_fib = d->n_fib;
+    s.surface = d->surface_nodes ? 1 : 0;
+    s.weight_mode = d->node_weight_mode;
+    s.n_lambda = d->n_lambda;
+    s.abs_scale.assign(d->n_lambda, 1.0f);
+    if (d->abs_scale) for (int k = 0; k < d->n_lambda; ++k) s.abs_scale[k] = d->abs_scale[k];
+    for (int k = 0; k < 3; ++k) { s.sun[k] = d->sun_dir[k]; s.view[k] = d->view_dir[k]; }
+    double su[3];
+    unit3(s.sun, su, 1.0);
+    unit3(s.sun, s.sun_in, -1.0);
+    unit3(s.view, s.view_u, 1.0);
+    s.mu0 = su[2];
+
+    const int nl = s.n_lambda;
+    // inputs
+    SG_TRY(dalloc(s, &s.mu_s, s.nvox));
+    SG_TRY(dalloc(s, &s.mu_a, s.nvox));
+    if (s.n_phase > 1) SG_TRY(dalloc(s, &s.frac, (size_t)s.n_phase * s.nvox));
+    SG_TRY(dalloc(s, &s.albedo, s.npx));
+    SG_TRY(dalloc(s, &s.pos, (size_t)3 * s.N));
+    SG_TRY(dalloc(s, &s.adj_ptr, (size_t)s.N + 1));
+    SG_TRY(dalloc(s, &s.adj_idx, (size_t)s.E));
+    SG_TRY(dalloc(s, &s.lat, (size_t)3 * s.n_fib));
+    SG_TRY(dalloc(s, &s.tab, (size_t)(s.n_phase + 1) * s.n_fib));
+    // structure
+    SG_TRY(dalloc(s, &s.rev, (size_t)s.E));
+    SG_TRY(dalloc(s, &s.nodeoff, (size_t)s.N + 1));
+    SG_TRY(dalloc(s, &s.row_ptr, (size_t)s.E + 1));
+    SG_TRY(dalloc(s, &s.scan_tmp, (size_t)s.N / 2048 + 2));
+    SG_TRY(dalloc(s, &s.qsun, (size_t)s.E));
+    // solve state
+    SG_TRY(dalloc(s, &s.x64, (size_t)s.E * nl));
+    SG_TRY(dalloc(s, &s.r64, (size_t)s.E * nl));
+    s.n_partial = std::max(spmv_blocks(s), 65 * 1024);
+    SG_TRY(dalloc(s, &s.partial, (size_t)s.n_partial));
+    SG_TRY(dalloc(s, &s.scal, 256));
+    SG_TRY(dalloc(s, &s.J, (size_t)s.N * nl));
+    SG_TRY(dalloc(s, &s.pix, (size_t)s.npx * nl));
+    if (nl == 1) {
+        SG_TRY(ensure_real<float>(s));
+    } else {
+        float *p;
+        SG_TRY(dalloc(s, &p, s.E)); s.tau_s = p;
+        SG_TRY(dalloc(s, &p, s.E)); s.tau_a = p;
+        SG_TRY(dalloc(s, &p, s.N)); s.tsun_s = p;
+        SG_TRY(dalloc(s, &p, s.N)); s.tsun_a = p;
+        SG_TRY(dalloc(s, &s.q, (size_t)s.nnz));
+        SG_TRY(dalloc(s, &s.bS, (size_t)s.E * nl));
+        SG_TRY(dalloc(s, &s.bx, (size_t)s.E * nl));
+        SG_TRY(dalloc(s, &s.by, (size_t)s.E * nl));
+        SG_TRY(dalloc(s, &s.brho, (size_t)s.N * nl));
+        SG_TRY(dalloc(s, &s.abs_scale_d, (size_t)nl));
+        SG_TRY(upload(s, s.abs_scale_d, s.abs_scale.data(), sizeof(float) * nl, st));
+    }
+
+    // host-side staging of the inputs
+    std::vector<int32_t> pos((size_t)3 * s.N);
+    std::memcpy(pos.data(), d->vol_pos_fx, sizeof(int32_t) * 3 * (size_t)s.nvox);
+    if (s.surface) {
+        for (int iy = 0; iy < s.ny; ++iy)
+            for (int ix = 0; ix < s.nx; ++ix) {
+                const size_t l = (size_t)s.nvox + ix + (size_t)s.nx * iy;
+                pos[3 * l] = ix * 65536 + 32768;
+                pos[3 * l + 1] = iy * 65536 + 32768;
+                pos[3 * l + 2] = 0;
+            }
+    }
+    std::vector<double> lat, tab;
+    host_lattice(s.n_fib, lat);
+    host_tables(s.n_fib, lat, s.n_phase, s.hg_g, tab);
+    SG_TRY(upload(s, s.mu_s, d->mu_s, sizeof(float) * s.nvox, st));
+    SG_TRY(upload(s, s.mu_a, d->mu_a, sizeof(float) * s.nvox, st));
+    if (s.frac) SG_TRY(upload(s, s.frac, d->phase_frac, sizeof(float) * s.n_phase * (size_t)s.nvox, st));
+    SG_TRY(upload(s, s.albedo, d->surf_albedo, sizeof(float) * s.npx, st));
+    SG_TRY(upload(s, s.pos, pos.data(), sizeof(int32_t) * pos.size(), st));
+    SG_TRY(upload(s, s.adj_ptr, d->adj_ptr, sizeof(int64_t) * ((size_t)s.N + 1), st));
+    if (s.E) SG_TRY(upload(s, s.adj_idx, d->adj_idx, sizeof(int32_t) * (size_t)s.E, st));
+    SG_TRY(upload(s, s.lat, lat.data(), sizeof(double) * lat.size(), st));
+    SG_TRY(upload(s, s.tab, tab.data(), sizeof(double) * tab.size(), st));
+    SG_HIP(hipStreamSynchronize(st));
+    return SG_OK;
+}
+
+hipStream_t pick_stream(Ctx *ctx, void *st) { return st ? (hipStream_t)st : ctx->stream; }
+
+}  // namespace
+
+extern "C" {
+
+sg_status sg_scene_create(sg_ctx *ctx, const sg_scene_desc *desc, void *hip_stream, sg_scene **out) {
+    if (!ctx || !out) return fail(SG_E_INVALID, "ctx or out is NULL");
+    *out = nullptr;
+    if (ctx->sticky.load()) return fail(SG_E_DEVICE, "context is in a failed state");
+    SG_HIP(hipSetDevice(ctx->device));
+    std::unique_ptr<sg_scene> s(new sg_scene());
+    sg_status st = create_scene(ctx, desc, pick_stream(ctx, hip_stream), *s);
+    if (st != SG_OK) {
+        std::string msg = sg_last_error();
+        free_scene(s.get());
+        set_error(msg);
+        return st;
+    }
+    ctx->n_scenes.fetch_add(1);
+    *out = s.release();
+    return SG_OK;
+}
+
+sg_status sg_scene_destroy(sg_scene *scene) {
+    if (!scene) return fail(SG_E_INVALID, "scene is NULL");
+    Ctx *ctx = scene->ctx;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    free_scene(scene);
+    ctx->n_scenes.fetch_sub(1);
+    delete scene;
+    return SG_OK;
+}
+
+sg_status sg_scene_sizes(const sg_scene *scene, int64_t *n_nodes, int64_t *n_edges, int64_t *nnz, int32_t *max_degree,
+                         int32_t *n_lambda, uint64_t *device_bytes) {
+    if (!scene) return fail(SG_E_INVALID, "scene is NULL");
+    if (n_nodes) *n_nodes = scene->N;
+    if (n_edges) *n_edges = scene->E;
+    if (nnz) *nnz = scene->nnz;
+    if (max_degree) *max_degree = scene->dmax;
+    if (n_lambda) *n_lambda = scene->n_lambda;
+    if (device_bytes) *device_bytes = scene->bytes;
+    return SG_OK;
+}
+
+sg_status sg_solve_batched_impl(Scene &s, const sg_solve_opts &o, hipStream_t st, double *radiance, int on_dev,
+                                sg_solve_info *info);
+
+sg_status sg_solve(sg_scene *scene, const sg_solve_opts *opts, void *hip_stream, double *radiance,
+                   int32_t radiance_on_device, sg_solve_info *info) {
+    if (!scene || !radiance) return fail(SG_E_INVALID, "scene or radiance is NULL");
+    Ctx *ctx = scene->ctx;
+    if (ctx->sticky.load()) return fail(SG_E_DEVICE, "context is in a failed state");
+    sg_solve_opts o;
+    if (opts) {
+        if (opts->abi_version != SG_ABI_VERSION) return fail(SG_E_ABI, "solve opts abi_version mismatch");
+        o = *opts;
+    } else {
+        fill_default_opts(o);
+    }
+    if (o.precision != SG_FP32 && o.precision != SG_FP64) return fail(SG_E_INVALID, "precision must be SG_FP32 or SG_FP64");
+    if (o.solver < 0 || o.solver > 2) return fail(SG_E_INVALID, "bad solver");
+    if (o.scatter_order != 0 && o.scatter_order != 1) return fail(SG_E_INVALID, "scatter_order must be 0 or 1");
+    std::lock_guard<std::mutex> lk(scene->mu);
+    SG_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = pick_stream(ctx, hip_stream);
+    if (scene->n_lambda > 1) {
+        if (o.precision != SG_FP32) return fail(SG_E_INVALID, "several wavelengths are solved in FP32 only");
+        return sg_solve_batched_impl(*scene, o, st, radiance, radiance_on_device, info);
+    }
+    if (o.precision == SG_FP64) return solve_single<double>(*scene, o, st, radiance, radiance_on_device, info);
+    return solve_single<float>(*scene, o, st, radiance, radiance_on_device, info);
+}
+
+sg_status sg_export_csr(sg_scene *scene, int32_t lambda, int64_t *row_ptr, int32_t *col_idx, double *val) {
+    if (!scene) return fail(SG_E_INVALID, "scene is NULL");
+    Scene &s = *scene;
+    Ctx *ctx = s.ctx;
+    if (!s.solved) return fail(SG_E_STATE, "no solve yet");
+    if (lambda < 0 || lambda >= s.n_lambda) return fail(SG_E_INVALID, "bad wavelength index");
+    std::lock_guard<std::mutex> lk(s.mu);
+    SG_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    if (row_ptr) SG_HIP(hipMemcpyAsync(row_ptr, s.row_ptr, sizeof(int64_t) * (s.E + 1), hipMemcpyDeviceToHost, st));
+    if (col_idx) {
+        if (!s.col_built) {
+            if (!s.col_idx) SG_TRY(dalloc(s, &s.col_idx, (size_t)s.nnz));
+            launch_col_idx(s, st);
+            s.col_built = true;
+        }
+        SG_HIP(hipMemcpyAsync(col_idx, s.col_idx, sizeof(int32_t) * s.nnz, hipMemcpyDeviceToHost, st));
+    }
+    if (val) {
+        if (s.n_lambda > 1) {
+            // K(lambda)[b][a] = T_a(lambda) rho_l(lambda) Q_l(a -> b), rebuilt on the host from device arrays
+            std::vector<float> q(s.nnz), ts(s.E), ta(s.E), rho((size_t)s.N * s.n_lambda);
+            std::vector<int64_t> ap(s.N + 1), no(s.N + 1);
+            SG_HIP(hipMemcpyAsync(q.data(), s.q, sizeof(float) * s.nnz, hipMemcpyDeviceToHost, st));
+            SG_HIP(hipMemcpyAsync(ts.data(), s.tau_s, sizeof(float) * s.E, hipMemcpyDeviceToHost, st));
+            SG_HIP(hipMemcpyAsync(ta.data(), s.tau_a, sizeof(float) * s.E, hipMemcpyDeviceToHost, st));
+            SG_HIP(hipMemcpyAsync(rho.data(), s.brho, sizeof(float) * rho.size(), hipMemcpyDeviceToHost, st));
+            SG_HIP(hipMemcpyAsync(ap.data(), s.adj_ptr, sizeof(int64_t) * (s.N + 1), hipMemcpyDeviceToHost, st));
+            SG_HIP(hipMemcpyAsync(no.data(), s.nodeoff, sizeof(int64_t) * (s.N + 1), hipMemcpyDeviceToHost, st));
+            SG_HIP(hipStreamSynchronize(st));
+            const float sl = s.abs_scale[lambda];
+            for (int64_t l = 0; l < s.N; ++l) {
+                const int64_t d = ap[l + 1] - ap[l];
+                const float r = rho[(size_t)l * s.n_lambda + lambda];
+                for (int64_t n = 0; n < d; ++n)
+                    for (int64_t m = 0; m < d; ++m) {
+                        const int64_t e = ap[l] + m;
+                        const float T = expf(-(ts[e] + sl * ta[e]));
+                        val[no[l] + n * d + m] = (double)(T * r * q[no[l] + n * d + m]);
+                    }
+            }
+        } else if (s.real_bytes == 4) {
+            std::vector<float> tmp(s.nnz);
+            SG_HIP(hipMemcpyAsync(tmp.data(), s.val, sizeof(float) * s.nnz, hipMemcpyDeviceToHost, st));
+            SG_HIP(hipStreamSynchronize(st));
+            for (int64_t i = 0; i < s.nnz; ++i) val[i] = tmp[i];
+        } else {
+            SG_HIP(hipMemcpyAsync(val, s.val, sizeof(double) * s.nnz, hipMemcpyDeviceToHost, st));
+        }
+    }
+    SG_HIP(hipStreamSynchronize(st));
+    return SG_OK;
+}
+
+sg_status sg_export_vector(sg_scene *scene, int32_t which, double *out) {
+    if (!scene || !out) return fail(SG_E_INVALID, "scene or out is NULL");
+    Scene &s = *scene;
+    Ctx *ctx = s.ctx;
+    if (!s.solved) return fail(SG_E_STATE, "no solve yet");
+    std::lock_guard<std::mutex> lk(s.mu);
+    SG_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const bool batched = s.n_lambda > 1;
+    const int rb = batched ? 4 : s.real_bytes;
+    const void *src = nullptr;
+    size_t n = 0;
+    int esz = rb;
+    switch (which) {
+        case SG_VEC_TAU_S: src = s.tau_s; n = s.E; break;
+        case SG_VEC_TAU_A: src = s.tau_a; n = s.E; break;
+        case SG_VEC_TAU_SUN_S: src = s.tsun_s; n = s.N; break;
+        case SG_VEC_TAU_SUN_A: src = s.tsun_a; n = s.N; break;
+        case SG_VEC_RHO: src = batched ? (const void *)s.brho : s.rho; n = (size_t)s.N * s.n_lambda; break;
+        case SG_VEC_SOURCE: src = batched ? (const void *)s.bS : s.S; n = (size_t)s.E * s.n_lambda; break;
+        case SG_VEC_PHI: src = s.x64; n = (size_t)s.E * s.n_lambda; esz = 8; break;
+        case SG_VEC_QSUN: src = s.qsun; n = s.E; esz = 4; break;
+        default: return fail(SG_E_INVALID, "unknown vector");
+    }
+    if (esz == 8) {
+        SG_HIP(hipMemcpyAsync(out, src, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        SG_HIP(hipStreamSynchronize(st));
+    } else {
+        std::vector<float> tmp(n);
+        SG_HIP(hipMemcpyAsync(tmp.data(), src, sizeof(float) * n, hipMemcpyDeviceToHost, st));
+        SG_HIP(hipStreamSynchronize(st));
+        for (size_t i = 0; i < n; ++i) out[i] = tmp[i];
+    }
+    // batched layouts are [E][n_lambda] on the device; the export is [n_lambda][E]
+    if (batched && (which == SG_VEC_RHO || which == SG_VEC_SOURCE || which == SG_VEC_PHI)) {
+        const size_t rows = which == SG_VEC_RHO ? (size_t)s.N : (size_t)s.E;
+        std::vector<double> t(out, out + n);
+        for (size_t r = 0; r < rows; ++r)
+            for (int k = 0; k < s.n_lambda; ++k) out[(size_t)k * rows + r] = t[r * s.n_lambda + k];
+    }
+    return SG_OK;
+}
+
+sg_status sg_trace(sg_scene *scene, int32_t kind, const int64_t *ids, int32_t n_ids, int32_t cap, int32_t *voxels,
+                   double *dt, int32_t *count) {
+    if (!scene || !ids || !voxels || !dt || !count) return fail(SG_E_INVALID, "NULL argument");
+    if (kind < 0 || kind > 2) return fail(SG_E_INVALID, "bad trace kind");
+    if (n_ids <= 0 || cap <= 0) return fail(SG_E_INVALID, "n_ids and cap must be > 0");
+    Scene &s = *scene;
+    Ctx *ctx = s.ctx;
+    const int64_t lim = kind == SG_TRACE_EDGE ? s.E : (kind == SG_TRACE_SUN ? s.N : s.npx);
+    for (int i = 0; i < n_ids; ++i)
+        if (ids[i] < 0 || ids[i] >= lim) return fail(SG_E_INVALID, "trace id out of range");
+    std::lock_guard<std::mutex> lk(s.mu);
+    SG_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    long long *d_ids = nullptr;
+    int *d_vox = nullptr, *d_cnt = nullptr;
+    double *d_dt = nullptr;
+    SG_HIP(hipMalloc((void **)&d_ids, sizeof(long long) * n_ids));
+    SG_HIP(hipMalloc((void **)&d_vox, sizeof(int) * (size_t)n_ids * cap));
+    SG_HIP(hipMalloc((void **)&d_dt, sizeof(double) * (size_t)n_ids * cap));
+    SG_HIP(hipMalloc((void **)&d_cnt, sizeof(int) * n_ids));
+    SG_HIP(hipMemcpyAsync(d_ids, ids, sizeof(long long) * n_ids, hipMemcpyHostToDevice, st));
+    launch_trace(s, st, kind, d_ids, n_ids, cap, d_vox, d_dt, d_cnt);
+    SG_HIP(hipGetLastError());
+    SG_HIP(hipMemcpyAsync(voxels, d_vox, sizeof(int) * (size_t)n_ids * cap, hipMemcpyDeviceToHost, st));
+    SG_HIP(hipMemcpyAsync(dt, d_dt, sizeof(double) * (size_t)n_ids * cap, hipMemcpyDeviceToHost, st));
+    SG_HIP(hipMemcpyAsync(count, d_cnt, sizeof(int) * n_ids, hipMemcpyDeviceToHost, st));
+    SG_HIP(hipStreamSynchronize(st));
+    (void)hipFree(d_ids);
+    (void)hipFree(d_vox);
+    (void)hipFree(d_dt);
+    (void)hipFree(d_cnt);
+    return SG_OK;
+}
+
+}  // extern "C"

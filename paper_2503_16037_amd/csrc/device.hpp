@@ -1,0 +1,110 @@
+// Device-side building blocks shared by the HIP kernels of the library.
+//
+// Contents: the exact integer voxel walk used by every march (edge, sun,
+// view), the Henyey-Greenstein phase function, and deterministic wave /
+// block reductions.  gfx950 only: 64-lane wavefronts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sg {
+
+constexpr long long kFx = 65536;  // fixed-point units per voxel edge
+constexpr int kWave = 64;
+
+__device__ __forceinline__ long long floor_div_fx(long long a) {
+    // floor(a / kFx) for any sign (kFx is a power of two: arithmetic shift)
+    return a >> 16;
+}
+
+// Exact walk of the voxels crossed with positive length by P + t D.
+//
+// Segment mode (ray = false): t in (0, 1]; ray mode: until the walk leaves
+// the grid.  Crossing times (B - P_k) / D_k are kept as integer fractions
+// n_k / d_k and compared by cross multiplication; an idle axis (D_k = 0)
+// carries the fraction 1/0, which compares greater than every finite time
+// and never equals one.  All axes whose crossing equals the minimum step
+// together, so no zero-length voxel is produced.  A start on a voxel plane
+// belongs to the voxel the path moves into (floor for D >= 0, ceil - 1 for
+// D < 0).  For each voxel the visitor gets (ix, iy, iz, num, den) with the
+// parameter length inside the voxel exactly num / den, and returns false to
+// stop the walk early.  Each lane leaves the loop on its own; the wavefront
+// retires the loop when the ballot of its live lanes is empty.  Magnitudes: grid
+// <= 1024 voxels per axis and |D| <= 2^26 keep every product below 2^63.
+template <class Visit>
+__device__ __forceinline__ int voxel_walk(int nx, int ny, int nz, long long px, long long py, long long pz,
+                                          long long dx, long long dy, long long dz, bool ray, Visit &&visit) {
+    long long ix, iy, iz;
+    int sx, sy, sz;
+    long long nxn, nyn, nzn, dxd, dyd, dzd;
+    if (dx > 0) { ix = floor_div_fx(px); sx = 1; nxn = (ix + 1) * kFx - px; dxd = dx; }
+    else if (dx < 0) { ix = floor_div_fx(px + kFx - 1) - 1; sx = -1; nxn = px - ix * kFx; dxd = -dx; }
+    else { ix = floor_div_fx(px); sx = 0; nxn = 1; dxd = 0; }
+    if (dy > 0) { iy = floor_div_fx(py); sy = 1; nyn = (iy + 1) * kFx - py; dyd = dy; }
+    else if (dy < 0) { iy = floor_div_fx(py + kFx - 1) - 1; sy = -1; nyn = py - iy * kFx; dyd = -dy; }
+    else { iy = floor_div_fx(py); sy = 0; nyn = 1; dyd = 0; }
+    if (dz > 0) { iz = floor_div_fx(pz); sz = 1; nzn = (iz + 1) * kFx - pz; dzd = dz; }
+    else if (dz < 0) { iz = floor_div_fx(pz + kFx - 1) - 1; sz = -1; nzn = pz - iz * kFx; dzd = -dz; }
+    else { iz = floor_div_fx(pz); sz = 0; nzn = 1; dzd = 0; }
+
+    long long cn = 0, cd = 1;  // current time
+    int count = 0;
+    const int max_steps = nx + ny + nz + 2;
+    for (int it = 0; it < max_steps; ++it) {
+        if (ix < 0 || ix >= nx || iy < 0 || iy >= ny || iz < 0 || iz >= nz) break;
+        long long mn = nxn, md = dxd;
+        if (nyn * md < mn * dyd) { mn = nyn; md = dyd; }
+        if (nzn * md < mn * dzd) { mn = nzn; md = dzd; }
+        bool last = false;
+        if (!ray && mn >= md) { mn = 1; md = 1; last = true; }
+        ++count;
+        if (!visit((int)ix, (int)iy, (int)iz, mn * cd - cn * md, md * cd)) break;
+        if (last) break;
+        const bool ex = nxn * md == mn * dxd;
+        const bool ey = nyn * md == mn * dyd;
+        const bool ez = nzn * md == mn * dzd;
+        if (ex) { ix += sx; nxn += kFx; }
+        if (ey) { iy += sy; nyn += kFx; }
+        if (ez) { iz += sz; nzn += kFx; }
+        cn = mn;
+        cd = md;
+    }
+    return count;
+}
+
+template <class Real>
+__device__ __forceinline__ Real ratio(long long num, long long den) {
+    return (Real)num / (Real)den;
+}
+
+// Henyey-Greenstein phase function, normalised over the sphere.
+__device__ __forceinline__ double hg_phase(double g, double mu) {
+    const double den = 1.0 + g * g - 2.0 * g * mu;
+    return (1.0 - g * g) / (4.0 * 3.14159265358979323846 * den * sqrt(den));
+}
+
+// Deterministic sum over a 64-lane wavefront (fixed butterfly order).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Deterministic block sum; every thread must call it; returns the total in thread 0.
+template <int kThreads>
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double part[kThreads / kWave];
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) part[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < kThreads / kWave; ++i) t += part[i];
+    }
+    __syncthreads();
+    return t;
+}
+
+}  // namespace sg

@@ -1,0 +1,137 @@
+// Observed radiance (Sec. 2, Eq. 11; step 5 of the TURSCA algorithm): the
+// light scattered toward the sensor at every node crossed by a pixel's line of
+// sight, attenuated on its way out.
+//
+//   J_l (volume)  = Theta_l(s_sun . v) T_sun(l) + sum_{a in in(l)} Theta_l(s_a . v) T_a phi_a
+//   J_s (surface) = mu0 T_sun(s) + sum_{a in in(s)} T_a phi_a
+//   I_p = sum_k T_entry(k) w_k (1 - exp(-mu_e,k s_k)) J_{v_k} + T_view (A_p / pi) J_{s_p}
+// with s_a the propagation direction of in-edge a, v the unit vector toward the
+// sensor, s_k the chord of the line of sight in voxel v_k and T_entry(k) the
+// transmittance from the chord's far end to the sensor.  Everything here is
+// accumulated in FP64 (one thread per node, then one thread per pixel).
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace sg {
+
+namespace {
+
+struct PhaseMix {
+    double g[4];
+    int n;
+};
+
+__device__ __forceinline__ double theta_mix(const PhaseMix &pm, const float *__restrict__ frac, int nvox, int v,
+                                            double mu) {
+    double th = 0.0;
+    for (int c = 0; c < pm.n; ++c) {
+        const double f = frac ? (double)frac[(long long)c * nvox + v] : 1.0;
+        th += f * hg_phase(pm.g[c], mu);
+    }
+    return th;
+}
+
+template <class Real>
+__global__ __launch_bounds__(256) void k_node_J(int N, int nvox, const long long *__restrict__ adj_ptr,
+                                               const int *__restrict__ adj_idx, const int *__restrict__ rev,
+                                               const int *__restrict__ pos, const Real *__restrict__ T,
+                                               const Real *__restrict__ Tsun, const double *__restrict__ phi,
+                                               PhaseMix pm, const float *__restrict__ frac, double sx, double sy,
+                                               double sz, double vx, double vy, double vz, double mu0,
+                                               int multiple, double *__restrict__ J) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= N) return;
+    const long long off = adj_ptr[l], end = adj_ptr[l + 1];
+    double acc;
+    if (l < nvox) {
+        acc = theta_mix(pm, frac, nvox, l, sx * vx + sy * vy + sz * vz) * (double)Tsun[l];
+        if (multiple) {
+            const long long Px = pos[3 * l], Py = pos[3 * l + 1], Pz = pos[3 * l + 2];
+            for (long long e = off; e < end; ++e) {
+                const int j = adj_idx[e];
+                const long long Dx = Px - pos[3 * j], Dy = Py - pos[3 * j + 1], Dz = Pz - pos[3 * j + 2];
+                const double nrm = sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
+                const double mu = ((double)Dx / nrm) * vx + ((double)Dy / nrm) * vy + ((double)Dz / nrm) * vz;
+                acc += theta_mix(pm, frac, nvox, l, mu) * (double)T[e] * phi[rev[e]];
+            }
+        }
+    } else {
+        acc = mu0 * (double)Tsun[l];
+        if (multiple)
+            for (long long e = off; e < end; ++e) acc += (double)T[e] * phi[rev[e]];
+    }
+    J[l] = acc;
+}
+
+__global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, const float *__restrict__ mu_s,
+                                              const float *__restrict__ mu_a, double scale, double len_view,
+                                              long long vdx, long long vdy, long long vdz, long long sdx,
+                                              long long sdy, long long sdz, double len_sun,
+                                              const float *__restrict__ albedo, const double *__restrict__ J,
+                                              int surface, double mu0, double *__restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nx * ny) return;
+    const long long ix = p % nx, iy = p / nx;
+    const long long px = ix * kFx + kFx / 2, py = iy * kFx + kFx / 2;
+    const long long nvox = (long long)nx * ny * nz;
+    // pass 1: optical depth of the whole line of sight
+    double tau_tot = 0.0;
+    voxel_walk(nx, ny, nz, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
+        const long long v = x + (long long)nx * (y + (long long)ny * z);
+        const double me = (double)mu_s[v] + scale * (double)mu_a[v];
+        tau_tot += me * ((double)num / (double)den * len_view);
+        return true;
+    });
+    // pass 2: chords, each attenuated from its far end to the sensor
+    double I = 0.0, cum = 0.0;
+    voxel_walk(nx, ny, nz, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
+        const long long v = x + (long long)nx * (y + (long long)ny * z);
+        const double ms = (double)mu_s[v];
+        const double me = ms + scale * (double)mu_a[v];
+        const double sk = (double)num / (double)den * len_view;
+        const double tk = me * sk;
+        const double t_entry = exp(-(tau_tot - (cum + tk)));
+        const double om = me > 0.0 ? ms / me : 0.0;
+        I += t_entry * (om * (-expm1(-tk))) * J[v];
+        cum += tk;
+        return true;
+    });
+    const double a_pi = (double)albedo[p] / 3.14159265358979323846;
+    if (surface) {
+        I += exp(-tau_tot) * a_pi * J[nvox + p];
+    } else {
+        double ts = 0.0;
+        voxel_walk(nx, ny, nz, px, py, 0, sdx, sdy, sdz, true, [&](int x, int y, int z, long long num, long long den) {
+            const long long v = x + (long long)nx * (y + (long long)ny * z);
+            ts += ((double)mu_s[v] + scale * (double)mu_a[v]) * ((double)num / (double)den * len_sun);
+            return true;
+        });
+        I += exp(-tau_tot) * a_pi * mu0 * exp(-ts);
+    }
+    out[p] = I;
+}
+
+}  // namespace
+
+template <class Real>
+void launch_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance) {
+    PhaseMix pm;
+    pm.n = s.n_phase;
+    for (int i = 0; i < 4; ++i) pm.g[i] = s.hg_g[i];
+    hipLaunchKernelGGL((k_node_J<Real>), dim3((s.N + 255) / 256), dim3(256), 0, st, s.N, s.nvox, s.adj_ptr, s.adj_idx,
+                       s.rev, s.pos, (const Real *)s.T, (const Real *)s.Tsun, phi, pm, s.frac, s.sun_in[0],
+                       s.sun_in[1], s.sun_in[2], s.view_u[0], s.view_u[1], s.view_u[2], s.mu0,
+                       scatter_order == 1 ? 0 : 1, s.J);
+    const double fx = s.voxel_m / 65536.0;
+    const double lv = sqrt((double)s.view[0] * s.view[0] + (double)s.view[1] * s.view[1] + (double)s.view[2] * s.view[2]) * fx;
+    const double ls = sqrt((double)s.sun[0] * s.sun[0] + (double)s.sun[1] * s.sun[1] + (double)s.sun[2] * s.sun[2]) * fx;
+    const double scale = s.abs_scale.empty() ? 1.0 : (double)s.abs_scale[0];
+    hipLaunchKernelGGL(k_pixels, dim3((s.npx + 63) / 64), dim3(64), 0, st, s.nx, s.ny, s.nz, s.mu_s, s.mu_a, scale, lv,
+                       (long long)s.view[0], (long long)s.view[1], (long long)s.view[2], (long long)s.sun[0],
+                       (long long)s.sun[1], (long long)s.sun[2], ls, s.albedo, s.J, s.surface, s.mu0, radiance);
+}
+
+template void launch_gather<float>(Scene &, hipStream_t, const double *, int, double *);
+template void launch_gather<double>(Scene &, hipStream_t, const double *, int, double *);
+
+}  // namespace sg

@@ -1,0 +1,147 @@
+// Internal host-side definitions of the library: context, scene state and the
+// launchers of the HIP kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sgrt.h"
+
+namespace sg {
+
+void set_error(const std::string &msg);
+
+struct Ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    std::atomic<uint64_t> used{0};
+    std::atomic<int> sticky{0};
+    std::atomic<int> n_scenes{0};
+    hipStream_t stream = nullptr;
+};
+
+// Device arrays of one scene.  "Real" arrays hold float in FP32 solves and
+// double in FP64 solves; they are allocated for the precision of the first
+// solve that needs them.
+struct Scene {
+    Ctx *ctx = nullptr;
+    // sizes
+    int nx = 0, ny = 0, nz = 0;
+    double voxel_m = 0.0;
+    int nvox = 0, N = 0, npx = 0;
+    int64_t E = 0, nnz = 0;
+    int dmax = 0;
+    int n_phase = 1;
+    double hg_g[4] = {0, 0, 0, 0};
+    int n_fib = 100;
+    int surface = 1;
+    int weight_mode = 0;
+    int n_lambda = 1;
+    std::vector<float> abs_scale;
+    int sun[3] = {0, 0, 0}, view[3] = {0, 0, 0};
+    double sun_in[3] = {0, 0, 0};  // propagation direction of sunlight (unit)
+    double view_u[3] = {0, 0, 0};  // unit vector toward the sensor
+    double mu0 = 0.0;
+    uint64_t bytes = 0;
+
+    // inputs
+    float *mu_s = nullptr, *mu_a = nullptr, *frac = nullptr, *albedo = nullptr, *abs_scale_d = nullptr;
+    int *pos = nullptr;  // [N][3]
+    long long *adj_ptr = nullptr;
+    int *adj_idx = nullptr;
+    double *lat = nullptr;  // [n_fib][3]
+    double *tab = nullptr;  // [n_phase + 1][n_fib]: HG tables, then the Lambertian cosine weights
+
+    // structure
+    int *rev = nullptr;
+    long long *nodeoff = nullptr;  // [N + 1] exclusive scan of degree^2
+    long long *row_ptr = nullptr;  // [E + 1]
+    int *col_idx = nullptr;        // [nnz], on demand
+    long long *scan_tmp = nullptr;
+    bool col_built = false;
+
+    // single-wavelength arrays (Real)
+    int real_bytes = 0;  // 4 or 8, 0 = not allocated
+    void *tau_s = nullptr, *tau_a = nullptr, *tsun_s = nullptr, *tsun_a = nullptr;
+    void *T = nullptr, *Tsun = nullptr, *rho = nullptr, *val = nullptr, *S = nullptr, *x = nullptr, *y = nullptr;
+    void *c_rhs = nullptr, *c_a = nullptr, *c_b = nullptr;  // refinement correction: RHS and two iterates
+    float *qsun = nullptr;  // [E]
+
+    // batched arrays (n_lambda > 1, FP32)
+    float *q = nullptr;                   // [nnz] phase-cell weights in K layout
+    float *bS = nullptr, *bx = nullptr, *by = nullptr;  // [E][n_lambda]
+    float *brho = nullptr;                // [N][n_lambda] (export)
+
+    // FP64 solve state
+    double *x64 = nullptr, *r64 = nullptr;  // [E * n_lambda]
+    double *gm_V = nullptr;                 // GMRES basis [(m+1) * E]
+    int gm_m = 0;
+    double *partial = nullptr;  // block partial sums
+    int n_partial = 0;
+    double *scal = nullptr;  // device scalars
+    double *J = nullptr;     // [N * n_lambda] node radiance toward the sensor
+    double *pix = nullptr;   // [n_lambda * npx] radiance staging for host outputs
+
+    bool solved = false;
+    int last_precision = 0;
+    int last_scatter_order = 0;
+    std::mutex mu;
+};
+
+// ---- launchers (defined in the .hip files) ----
+void launch_structure(Scene &s, hipStream_t st);
+void launch_col_idx(Scene &s, hipStream_t st);
+
+template <class Real>
+void launch_march(Scene &s, hipStream_t st, float scale, int use_lds);
+template <class Real>
+void launch_node_weights(Scene &s, hipStream_t st, float scale);
+template <class Real>
+void launch_qbuild(Scene &s, hipStream_t st, int write_q);
+
+template <class Real>
+void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *partial_out);
+template <class Real>
+void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x64, double *r64, double *partial_out);
+template <class Real>
+void launch_apply_imk64(Scene &s, hipStream_t st, const double *v, double *w);
+int spmv_blocks(const Scene &s);
+void launch_reduce(const double *partial, int n, double *out, hipStream_t st);
+void launch_dot_multi(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial, int nblk,
+                      double *out, hipStream_t st);
+void launch_axpy_multi(double *w, const double *V, int64_t ld, int k, const double *h, int64_t n, hipStream_t st);
+void launch_norm1_64(const double *v, int64_t n, double *partial, int nblk, double *out, hipStream_t st);
+
+template <class Real>
+void launch_to64(const Real *a, double *b, int64_t n, hipStream_t st);
+template <class Real>
+void launch_scaled_to_real(const double *a, double scale, Real *b, int64_t n, hipStream_t st);
+template <class Real>
+void launch_axpy_real_to64(double *x64, const Real *d, double alpha, int64_t n, hipStream_t st);
+void launch_axpy64(double *y, const double *x, double alpha, int64_t n, hipStream_t st);
+void launch_scale64(double *x, double alpha, int64_t n, hipStream_t st);
+template <class Real>
+void launch_fill(Real *a, Real v, int64_t n, hipStream_t st);
+template <class Real>
+void launch_norm1_real(const Real *v, int64_t n, double *partial, int nblk, double *out, hipStream_t st);
+
+template <class Real>
+void launch_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance);
+
+void launch_trace(Scene &s, hipStream_t st, int kind, const long long *ids, int n, int cap, int *vox, double *dt,
+                  int *count);
+
+// batched
+void launch_batched_march_and_weights(Scene &s, hipStream_t st);
+void launch_batched_source(Scene &s, hipStream_t st);
+void launch_spmm(Scene &s, hipStream_t st, const float *S, const float *x, float *y, double *partial, int use_source);
+void launch_batched_residual64(Scene &s, hipStream_t st, const double *x64, double *r64, double *partial);
+void launch_batched_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance);
+int spmm_blocks(const Scene &s);
+
+}  // namespace sg

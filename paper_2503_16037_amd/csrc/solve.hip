@@ -1,0 +1,323 @@
+// Solve of (I - K) phi = S (Sec. 2, Eq. 8) by the Neumann series phi = S + K S
+// + K^2 S + ... (Eq. 5), i.e. Jacobi sweeps x <- S + K x (diag K = 0), with
+// FP64 residuals for iterative refinement and the pieces of a GMRES fallback.
+//
+// The sweep is node-blocked: node l owns a dense d_l x d_l block of K (rows
+// = its out-edges, columns = its in-edges), so a wavefront stages the block
+// in LDS with coalesced loads, gathers the d_l inputs x[rev(out(l))] once and
+// never reads a column index.  Every reduction has a fixed order (wave
+// butterfly, then block, then one final block), so results are bit-identical
+// from run to run.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace sg {
+
+namespace {
+
+constexpr int kSpmvThreads = 256;
+constexpr int kNodesPerSpmvBlock = kSpmvThreads / 64;
+constexpr int kVecThreads = 256;
+
+// y = S + K x for one wavefront per node; partial[block] = sum |y - x| (FP64).
+template <class Real>
+__global__ __launch_bounds__(kSpmvThreads) void k_spmv(int N, const long long *__restrict__ adj_ptr,
+                                                      const long long *__restrict__ nodeoff,
+                                                      const int *__restrict__ rev, const Real *__restrict__ val,
+                                                      const Real *__restrict__ S, const Real *__restrict__ x,
+                                                      Real *__restrict__ y, double *__restrict__ partial, int dmax,
+                                                      int stage) {
+    extern __shared__ unsigned char smem_raw[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int per_wave = stage ? dmax * dmax + dmax : dmax;
+    Real *xg = reinterpret_cast<Real *>(smem_raw) + (size_t)w * per_wave;
+    Real *blk = xg + dmax;
+    const int l = blockIdx.x * kNodesPerSpmvBlock + w;
+    long long off = 0, base = 0;
+    int d = 0;
+    if (l < N) {
+        off = adj_ptr[l];
+        d = (int)(adj_ptr[l + 1] - off);
+        base = nodeoff[l];
+        if (stage)
+            for (int t = lane; t < d * d; t += 64) blk[t] = val[base + t];
+        if (lane < d) xg[lane] = x[rev[off + lane]];
+    }
+    __syncthreads();
+    double r = 0.0;
+    if (lane < d) {
+        Real acc = 0;
+        const Real *row = stage ? blk + lane * d : val + base + (long long)lane * d;
+        for (int m = 0; m < d; ++m) acc += row[m] * xg[m];
+        const long long b = off + lane;
+        const Real yn = S[b] + acc;
+        y[b] = yn;
+        r = fabs((double)yn - (double)x[b]);
+    }
+    const double t = block_sum<kSpmvThreads>(r);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// r = S - x + K x in FP64 (K values promoted); partial[block] = sum |r|.
+template <class Real>
+__global__ __launch_bounds__(kSpmvThreads) void k_residual64(int N, const long long *__restrict__ adj_ptr,
+                                                            const long long *__restrict__ nodeoff,
+                                                            const int *__restrict__ rev, const Real *__restrict__ val,
+                                                            const Real *__restrict__ S, const double *__restrict__ x,
+                                                            double *__restrict__ r, double *__restrict__ partial,
+                                                            int dmax) {
+    extern __shared__ unsigned char smem_raw[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double *xg = reinterpret_cast<double *>(smem_raw) + (size_t)w * dmax;
+    const int l = blockIdx.x * kNodesPerSpmvBlock + w;
+    long long off = 0, base = 0;
+    int d = 0;
+    if (l < N) {
+        off = adj_ptr[l];
+        d = (int)(adj_ptr[l + 1] - off);
+        base = nodeoff[l];
+        if (lane < d) xg[lane] = x[rev[off + lane]];
+    }
+    __syncthreads();
+    double a = 0.0;
+    if (lane < d) {
+        double acc = 0.0;
+        const Real *row = val + base + (long long)lane * d;
+        for (int m = 0; m < d; ++m) acc += (double)row[m] * xg[m];
+        const long long b = off + lane;
+        const double rb = ((double)S[b] - x[b]) + acc;
+        r[b] = rb;
+        a = fabs(rb);
+    }
+    const double t = block_sum<kSpmvThreads>(a);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// w = v - K v in FP64.
+template <class Real>
+__global__ __launch_bounds__(kSpmvThreads) void k_apply_imk64(int N, const long long *__restrict__ adj_ptr,
+                                                             const long long *__restrict__ nodeoff,
+                                                             const int *__restrict__ rev, const Real *__restrict__ val,
+                                                             const double *__restrict__ v, double *__restrict__ wv,
+                                                             int dmax) {
+    extern __shared__ unsigned char smem_raw[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double *xg = reinterpret_cast<double *>(smem_raw) + (size_t)w * dmax;
+    const int l = blockIdx.x * kNodesPerSpmvBlock + w;
+    long long off = 0, base = 0;
+    int d = 0;
+    if (l < N) {
+        off = adj_ptr[l];
+        d = (int)(adj_ptr[l + 1] - off);
+        base = nodeoff[l];
+        if (lane < d) xg[lane] = v[rev[off + lane]];
+    }
+    __syncthreads();
+    if (lane < d) {
+        double acc = 0.0;
+        const Real *row = val + base + (long long)lane * d;
+        for (int m = 0; m < d; ++m) acc += (double)row[m] * xg[m];
+        const long long b = off + lane;
+        wv[b] = v[b] - acc;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ partial, int n, double *__restrict__ out) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) s += partial[i];
+    const double t = block_sum<1024>(s);
+    if (threadIdx.x == 0) *out = t;
+}
+
+template <class Real>
+__global__ __launch_bounds__(kVecThreads) void k_norm1(const Real *__restrict__ v, long long n,
+                                                      double *__restrict__ partial) {
+    double s = 0.0;
+    for (long long i = blockIdx.x * (long long)kVecThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kVecThreads)
+        s += fabs((double)v[i]);
+    const double t = block_sum<kVecThreads>(s);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// partial[j * nblk + block] = sum_i V[j][i] w[i], j < k (one pass over w).
+__global__ __launch_bounds__(kVecThreads) void k_dot_multi(const double *__restrict__ V, long long ld, int k,
+                                                          const double *__restrict__ w, long long n,
+                                                          double *__restrict__ partial) {
+    double acc[8];
+    for (int j0 = 0; j0 < k; j0 += 8) {
+        const int kk = min(8, k - j0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+        for (long long i = blockIdx.x * (long long)kVecThreads + threadIdx.x; i < n;
+             i += (long long)gridDim.x * kVecThreads) {
+            const double wi = w[i];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (j < kk) acc[j] += V[(long long)(j0 + j) * ld + i] * wi;
+        }
+        for (int j = 0; j < kk; ++j) {
+            const double t = block_sum<kVecThreads>(acc[j]);
+            if (threadIdx.x == 0) partial[(long long)(j0 + j) * gridDim.x + blockIdx.x] = t;
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_reduce_multi(const double *__restrict__ partial, int nblk, int k,
+                                                      double *__restrict__ out) {
+    for (int j = 0; j < k; ++j) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nblk; i += 1024) s += partial[(long long)j * nblk + i];
+        const double t = block_sum<1024>(s);
+        if (threadIdx.x == 0) out[j] = t;
+    }
+}
+
+// w -= sum_j h[j] V[j]
+__global__ __launch_bounds__(kVecThreads) void k_axpy_multi(double *__restrict__ w, const double *__restrict__ V,
+                                                           long long ld, int k, const double *__restrict__ h,
+                                                           long long n) {
+    for (long long i = blockIdx.x * (long long)kVecThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kVecThreads) {
+        double s = w[i];
+        for (int j = 0; j < k; ++j) s -= h[j] * V[(long long)j * ld + i];
+        w[i] = s;
+    }
+}
+
+template <class Real>
+__global__ void k_to64(const Real *__restrict__ a, double *__restrict__ b, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        b[i] = (double)a[i];
+}
+
+template <class Real>
+__global__ void k_scaled_to_real(const double *__restrict__ a, double scale, Real *__restrict__ b, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        b[i] = (Real)(a[i] * scale);
+}
+
+template <class Real>
+__global__ void k_axpy_real_to64(double *__restrict__ x, const Real *__restrict__ d, double alpha, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        x[i] += alpha * (double)d[i];
+}
+
+__global__ void k_axpy64(double *__restrict__ y, const double *__restrict__ x, double alpha, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        y[i] += alpha * x[i];
+}
+
+__global__ void k_scale64(double *__restrict__ x, double alpha, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        x[i] *= alpha;
+}
+
+template <class Real>
+__global__ void k_fill(Real *__restrict__ a, Real v, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+inline int grid_for(long long n) {
+    long long g = (n + kVecThreads - 1) / kVecThreads;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+}  // namespace
+
+int spmv_blocks(const Scene &s) { return (s.N + kNodesPerSpmvBlock - 1) / kNodesPerSpmvBlock; }
+
+template <class Real>
+void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *partial_out) {
+    size_t shm = (size_t)kNodesPerSpmvBlock * (s.dmax * s.dmax + s.dmax) * sizeof(Real);
+    int stage = 1;
+    if (shm > 64 * 1024) {  // block does not fit: read rows straight from memory
+        stage = 0;
+        shm = (size_t)kNodesPerSpmvBlock * s.dmax * sizeof(Real);
+    }
+    hipLaunchKernelGGL((k_spmv<Real>), dim3(spmv_blocks(s)), dim3(kSpmvThreads), shm, st, s.N, s.adj_ptr, s.nodeoff,
+                       s.rev, (const Real *)s.val, S, x, y, partial_out, s.dmax, stage);
+}
+
+template <class Real>
+void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x64, double *r64, double *partial_out) {
+    const size_t shm = (size_t)kNodesPerSpmvBlock * s.dmax * sizeof(double);
+    hipLaunchKernelGGL((k_residual64<Real>), dim3(spmv_blocks(s)), dim3(kSpmvThreads), shm, st, s.N, s.adj_ptr,
+                       s.nodeoff, s.rev, (const Real *)s.val, S, x64, r64, partial_out, s.dmax);
+}
+
+template <class Real>
+void launch_apply_imk64(Scene &s, hipStream_t st, const double *v, double *w) {
+    const size_t shm = (size_t)kNodesPerSpmvBlock * s.dmax * sizeof(double);
+    hipLaunchKernelGGL((k_apply_imk64<Real>), dim3(spmv_blocks(s)), dim3(kSpmvThreads), shm, st, s.N, s.adj_ptr,
+                       s.nodeoff, s.rev, (const Real *)s.val, v, w, s.dmax);
+}
+
+void launch_reduce(const double *partial, int n, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, n, out);
+}
+
+void launch_dot_multi(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial, int nblk,
+                      double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot_multi, dim3(nblk), dim3(kVecThreads), 0, st, V, (long long)ld, k, w, (long long)n, partial);
+    hipLaunchKernelGGL(k_reduce_multi, dim3(1), dim3(1024), 0, st, partial, nblk, k, out);
+}
+
+void launch_axpy_multi(double *w, const double *V, int64_t ld, int k, const double *h, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy_multi, dim3(grid_for(n)), dim3(kVecThreads), 0, st, w, V, (long long)ld, k, h, (long long)n);
+}
+
+void launch_norm1_64(const double *v, int64_t n, double *partial, int nblk, double *out, hipStream_t st) {
+    hipLaunchKernelGGL((k_norm1<double>), dim3(nblk), dim3(kVecThreads), 0, st, v, (long long)n, partial);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, nblk, out);
+}
+
+template <class Real>
+void launch_norm1_real(const Real *v, int64_t n, double *partial, int nblk, double *out, hipStream_t st) {
+    hipLaunchKernelGGL((k_norm1<Real>), dim3(nblk), dim3(kVecThreads), 0, st, v, (long long)n, partial);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, nblk, out);
+}
+
+template <class Real>
+void launch_to64(const Real *a, double *b, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_to64<Real>), dim3(grid_for(n)), dim3(kVecThreads), 0, st, a, b, (long long)n);
+}
+
+template <class Real>
+void launch_scaled_to_real(const double *a, double scale, Real *b, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_scaled_to_real<Real>), dim3(grid_for(n)), dim3(kVecThreads), 0, st, a, scale, b, (long long)n);
+}
+
+template <class Real>
+void launch_axpy_real_to64(double *x64, const Real *d, double alpha, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_axpy_real_to64<Real>), dim3(grid_for(n)), dim3(kVecThreads), 0, st, x64, d, alpha, (long long)n);
+}
+
+void launch_axpy64(double *y, const double *x, double alpha, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy64, dim3(grid_for(n)), dim3(kVecThreads), 0, st, y, x, alpha, (long long)n);
+}
+
+void launch_scale64(double *x, double alpha, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale64, dim3(grid_for(n)), dim3(kVecThreads), 0, st, x, alpha, (long long)n);
+}
+
+template <class Real>
+void launch_fill(Real *a, Real v, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_fill<Real>), dim3(grid_for(n)), dim3(kVecThreads), 0, st, a, v, (long long)n);
+}
+
+#define SG_INST(R)                                                                                           \
+    template void launch_spmv<R>(Scene &, hipStream_t, const R *, const R *, R *, double *);               \
+    template void launch_residual64<R>(Scene &, hipStream_t, const R *, const double *, double *, double *); \
+    template void launch_apply_imk64<R>(Scene &, hipStream_t, const double *, double *);                  \
+    template void launch_to64<R>(const R *, double *, int64_t, hipStream_t);                               \
+    template void launch_scaled_to_real<R>(const double *, double, R *, int64_t, hipStream_t);             \
+    template void launch_axpy_real_to64<R>(double *, const R *, double, int64_t, hipStream_t);             \
+    template void launch_fill<R>(R *, R, int64_t, hipStream_t);                                            \
+    template void launch_norm1_real<R>(const R *, int64_t, double *, int, double *, hipStream_t);
+SG_INST(float)
+SG_INST(double)
+#undef SG_INST
+
+}  // namespace sg

@@ -178,8 +178,8 @@ def clustered_scene(mu_s_dx=2.5, seed=0):
     for iz in range(2):
         for iy in range(2):
             for ix in range(2):
-                c = np.array([ix, iy, iz]) * 2 - 1           # toward the shared corner
-                p = np.array([S, S, S]) - c * rng.integers(200, 1300, 3)
+                c = np.array([ix, iy, iz]) * 2 - 1           # which side of the shared corner
+                p = np.array([S, S, S]) + c * rng.integers(200, 1300, 3)
                 pos.append(p)
     pos = np.array(pos, np.int32)
     a, b = np.triu_indices(8, 1)
