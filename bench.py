@@ -36,14 +36,20 @@ def make_workload(name: str):
         return scenes.make_cloud(), "cloud-128x128x48 (seed 3), 1 wavelength"
     if name == "plain":
         return scenes.make_plain(), "plain-8x8x8 (seed 1), 1 wavelength"
+    if name == "batched":
+        return scenes.make_batched(), "batched plume-96x96x32 (seed 4), 64 wavelengths"
     raise SystemExit(f"unknown workload {name}")
 
 
-def spmv_bytes(n_nodes: int, n_edges: int, nnz: int, real_bytes: int = 4) -> int:
-    """Algorithmic HBM bytes of one sweep y = S + K x (node-blocked, no column index):
-    values nnz, and per edge S, y, x (own), x (gathered once), rev; per node adj_ptr and
-    the block offset."""
-    return real_bytes * nnz + n_edges * (4 * real_bytes + 4) + n_nodes * 16
+def spmv_bytes(n_nodes: int, n_edges: int, nnz: int, real_bytes: int = 4, n_lambda: int = 1) -> int:
+    """Algorithmic HBM bytes of one sweep y = S + K x (node-blocked, no column index).
+    One wavelength: values nnz, per edge S, y, x (own), x (gathered once), rev; per node
+    adj_ptr and the block offset.  n wavelengths: phase cells nnz (shared), per edge
+    tau_s, tau_a, rev, Qsun and per (edge, wavelength) y, x (own), x (gathered); per
+    (node, wavelength) rho and the solar factor."""
+    if n_lambda == 1:
+        return real_bytes * nnz + n_edges * (4 * real_bytes + 4) + n_nodes * 16
+    return 4 * nnz + n_edges * 16 + n_edges * n_lambda * 12 + n_nodes * (16 + 8 * n_lambda)
 
 
 def qbuild_flops(scene) -> float:
@@ -56,6 +62,91 @@ def qbuild_flops(scene) -> float:
     return 5.0 * float((n_in * d).sum()) * scene.n_fib
 
 
+def _gen_served(i):
+    from paper_2503_16037_amd import scenes
+    return scenes.make_served(i)
+
+
+def bench_served(args):
+    """Served stream: serial plain one-scene solves versus the continuous-batching server
+    (Poisson arrivals at 0.8 x the serial throughput, and all requests at t = 0)."""
+    import multiprocessing as mp
+    import threading
+
+    import torch
+
+    from paper_2503_16037_amd import sgrt
+
+    n = args.served
+    t = time.perf_counter()
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        stream = pool.map(_gen_served, range(n))
+    gen_s = time.perf_counter() - t
+    ctx = sgrt.Context(0)
+    # warm the kernels once
+    with sgrt.Scene(ctx, stream[0]) as g:
+        g.solve()
+    torch.cuda.synchronize()
+    serial, lat_serial = [], []
+    t0 = time.perf_counter()
+    for sc in stream:
+        ts = time.perf_counter()
+        with sgrt.Scene(ctx, sc) as g:
+            r, _ = g.solve()
+        lat_serial.append((time.perf_counter() - ts) * 1e3)
+        serial.append(np.asarray(r).reshape(sc.n_lambda, sc.ny, sc.nx))
+    serial_s = time.perf_counter() - t0
+    serial_rate = n / serial_s
+
+    def run_server(arrivals):
+        srv = sgrt.Server(ctx, max_resident=args.resident, queue_cap=4 * n, n_streams=min(args.resident, 8))
+        tickets = [None] * n
+        t_start = time.perf_counter()
+
+        def submitter():
+            for i, sc in enumerate(stream):
+                delay = arrivals[i] - (time.perf_counter() - t_start)
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[i] = srv.submit(sc)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        res = [srv.wait(tk) for tk in tickets]
+        makespan = time.perf_counter() - t_start
+        lat = srv.latencies()
+        srv.close()
+        same = all(np.array_equal(r[0], ref) for r, ref in zip(res, serial))
+        return n / makespan, lat, same
+
+    rng = np.random.default_rng(5)
+    gaps = rng.exponential(1.0 / (0.8 * serial_rate), size=n)
+    arrivals = np.concatenate([[0.0], np.cumsum(gaps)[:-1]])
+    rate_p, lat_p, same_p = run_server(arrivals)
+    rate_s, lat_s, same_s = run_server(np.zeros(n))
+    ctx.close()
+    edges = sum(sc.n_edges for sc in stream)
+    out = {"metric": METRIC, "value": round(rate_s, 3), "unit": "scenes/s", "n_gpus": 1, "steps": n, "warmup": 1,
+           "ms_per_step": round(1e3 / rate_s, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"served stream, requests 0..{n - 1} (seeds 5000+i, 16^3..128x128x48 voxels, "
+                                  f"1..32 wavelengths, plume/cloud)", "resident_slots": args.resident},
+           "saturation_scenes_per_s": round(rate_s, 3),
+           "poisson_0.8x": {"scenes_per_s": round(rate_p, 3),
+                            "latency_ms": {"p50": round(float(np.percentile(lat_p, 50)), 2),
+                                           "p99": round(float(np.percentile(lat_p, 99)), 2)}},
+           "saturation_latency_ms": {"p50": round(float(np.percentile(lat_s, 50)), 2),
+                                     "p99": round(float(np.percentile(lat_s, 99)), 2)},
+           "serial_plain": {"scenes_per_s": round(serial_rate, 3),
+                            "latency_ms": {"p50": round(float(np.percentile(lat_serial, 50)), 2),
+                                           "p99": round(float(np.percentile(lat_serial, 99)), 2)}},
+           "speedup_vs_serial": round(rate_s / serial_rate, 3),
+           "edge_couplings_per_s": round(edges / n * rate_s, 1),
+           "served_equal_to_serial_bitwise": bool(same_p and same_s), "generation_s": round(gen_s, 1)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,10 +155,16 @@ def main():
     ap.add_argument("--workload", default="plume")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--served", type=int, default=40, help="requests of the served stream (workload served)")
+    ap.add_argument("--resident", type=int, default=4, help="resident scenes of the server (workload served)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
+
+    if args.workload == "served":
+        bench_served(args)
+        return
 
     import torch
 
@@ -99,9 +196,9 @@ def main():
     spmv_launches = sum(i["spmv_launches"] for i in infos)
     spmv_avg_ms = sum(i["ms_spmv_sum"] for i in infos) / max(spmv_launches, 1)
     spmv_per_step_ms = sum(i["ms_spmv_sum"] for i in infos) / len(infos)
-    sbytes = spmv_bytes(sz["n_nodes"], sz["n_edges"], sz["nnz"])
+    sbytes = spmv_bytes(sz["n_nodes"], sz["n_edges"], sz["nnz"], n_lambda=g.n_lambda)
     qflops = qbuild_flops(scene)
-    if stages["ms_qbuild"] >= spmv_per_step_ms:
+    if stages["ms_qbuild"] >= spmv_per_step_ms and g.n_lambda == 1:
         achieved = qflops / (stages["ms_qbuild"] * 1e-3) / 1e12
         roof = {"kernel": "k_qbuild (phase cells + K values + source)", "bound": "alu",
                 "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -109,7 +206,8 @@ def main():
                 "algorithmic_per_launch": qflops, "avg_launch_ms": round(stages["ms_qbuild"], 4)}
     else:
         achieved = sbytes / (spmv_avg_ms * 1e-3) / 1e9
-        roof = {"kernel": "k_spmv (FP32 sweep)", "bound": "hbm", "achieved": round(achieved, 1),
+        roof = {"kernel": "k_spmv (FP32 sweep)" if g.n_lambda == 1 else "k_spmm (FP32, all wavelengths)",
+                "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "algorithmic_per_launch": sbytes, "avg_launch_ms": round(spmv_avg_ms, 5)}
     sweep_roof = {"kernel": "k_spmv", "avg_launch_ms": round(spmv_avg_ms, 5), "bytes_per_launch": sbytes,
@@ -120,7 +218,7 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
-           "config": {"workload": wl_name, "n_lambda": 1, "couplings": sz["n_edges"], "nnz": sz["nnz"],
+           "config": {"workload": wl_name, "n_lambda": g.n_lambda, "couplings": sz["n_edges"], "nnz": sz["nnz"],
                       "nodes": sz["n_nodes"], "parallelism": "single GPU"},
            "edge_couplings_per_s": round(scenes_per_s * sz["n_edges"], 1),
            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
@@ -129,19 +227,26 @@ def main():
            "sweeps_per_step": avg("sweeps"), "rel_residual": max(i["rel_residual"] for i in infos),
            "roofline": roof, "sweep_kernel": sweep_roof}
 
+    if g.n_lambda > 1:
+        out["wavelength_solves_per_s"] = round(scenes_per_s * g.n_lambda, 2)
     if not args.no_check or not args.no_cpu_baseline:
         import oracle  # test infrastructure: the accuracy check and the CPU baseline only
         t = time.perf_counter()
-        ref = oracle.run(scene, want_matrix=False)
+        k = 0
+        ref = oracle.run(scene, want_matrix=False) if g.n_lambda == 1 else \
+            oracle.run(scene, abs_scale=float(scene.abs_scale[k]), want_matrix=False)
         t_cpu = time.perf_counter() - t
-        err = np.abs(rad - ref["radiance"]) / np.abs(ref["radiance"])
+        got = rad if g.n_lambda == 1 else rad[k]
+        err = np.abs(got - ref["radiance"]) / np.abs(ref["radiance"])
         out["max_rel_err_vs_oracle"] = float(err.max())
         out["p99_rel_err_vs_oracle"] = float(np.percentile(err, 99))
         if not args.no_cpu_baseline:
-            out["cpu_baseline"] = {"value": round(1.0 / t_cpu, 5), "unit": "scenes/s",
+            # the oracle solves one wavelength per run: a whole n-wavelength scene costs n runs
+            out["cpu_baseline"] = {"value": round(1.0 / (t_cpu * g.n_lambda), 6), "unit": "scenes/s",
                                    "cores": oracle.num_threads(), "kind": "oracle",
-                                   "sample": f"one whole {wl_name} scene ({sz['n_edges']} couplings), "
-                                             f"FP64, all stages, {t_cpu:.2f} s"}
+                                   "sample": f"one wavelength of {wl_name} ({sz['n_edges']} couplings), "
+                                             f"FP64, all stages, {t_cpu:.2f} s"
+                                             + (f", x {g.n_lambda} wavelengths" if g.n_lambda > 1 else "")}
     g.close()
     ctx.close()
     print(json.dumps(out), flush=True)

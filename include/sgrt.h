@@ -112,10 +112,12 @@ typedef struct sg_scene_desc {
 } sg_scene_desc;
 
 /*
- * Validate a scene on the host, copy it to the device and reserve all the
- * device memory its solves need (nothing is allocated by sg_solve).  The
- * copies are enqueued on hip_stream (NULL: the context stream) and are
- * complete when the call returns.
+ * Validate a scene on the host, copy it to the device and reserve the device
+ * memory of its FP32 solves (sg_solve allocates nothing for them).  FP64
+ * solves, the optional CSR column index and the GMRES basis allocate their
+ * arrays on first use and keep them until sg_scene_destroy.  The copies are
+ * enqueued on hip_stream (NULL: the context stream) and are complete when the
+ * call returns.
  * Errors: SG_E_ABI, SG_E_INVALID (with the reason), SG_E_NOMEM (budget or
  * allocation), SG_E_DEVICE.
  */
@@ -131,6 +133,13 @@ sg_status sg_scene_destroy(sg_scene *scene);
  */
 sg_status sg_scene_sizes(const sg_scene *scene, int64_t *n_nodes, int64_t *n_edges, int64_t *nnz,
                          int32_t *max_degree, int32_t *n_lambda, uint64_t *device_bytes);
+
+/*
+ * Device bytes sg_scene_create would reserve for this description (validated
+ * on the host; no device work).  Used for admission against an HBM budget.
+ * Errors: those of validation (SG_E_ABI, SG_E_INVALID).
+ */
+sg_status sg_scene_reservation(const sg_scene_desc *desc, uint64_t *bytes);
 
 enum { SG_FP32 = 0, SG_FP64 = 1 };
 enum { SG_SOLVER_AUTO = 0, SG_SOLVER_NEUMANN = 1, SG_SOLVER_GMRES = 2 };

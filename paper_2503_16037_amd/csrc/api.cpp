@@ -23,6 +23,7 @@ thread_local std::string t_err;
 }
 
 void set_error(const std::string &msg) { t_err = msg; }
+std::string t_last_error() { return t_err; }
 
 namespace {
 
@@ -285,7 +286,6 @@ template <class Real>
 sg_status neumann(Scene &s, hipStream_t st, Timing &tm, const Real *rhs, Real *&xa, Real *&xb, double stop,
                   int max_sweeps, SolveStats &ss, int &stalled) {
     Ctx *ctx = s.ctx;
-    const int nb = spmv_blocks(s);
     launch_fill<Real>(xa, (Real)0, s.E, st);
     std::vector<double> hist;
     int chunk = 2;
@@ -296,9 +296,8 @@ sg_status neumann(Scene &s, hipStream_t st, Timing &tm, const Real *rhs, Real *&
         for (int c = 0; c < chunk; ++c) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (tm.on) e0 = tm.mark();
-            launch_spmv<Real>(s, st, rhs, xa, xb, s.partial);
+            launch_spmv<Real>(s, st, rhs, xa, xb, s.scal + 16 + c);
             if (tm.on) { e1 = tm.mark(); tm.spmv.push_back({e0, e1}); }
-            launch_reduce(s.partial, nb, s.scal + 16 + c, st);
             std::swap(xa, xb);
             ++ss.sweeps;
         }
@@ -307,10 +306,11 @@ sg_status neumann(Scene &s, hipStream_t st, Timing &tm, const Real *rhs, Real *&
         for (int c = 0; c < chunk; ++c) hist.push_back(host[c]);
         const double r = hist.back();
         if (!std::isfinite(r)) { stalled = 1; break; }
-        if (r <= stop) break;
-        if (ss.sweeps >= max_sweeps) break;
         double q = 0.5;
         if (hist.size() >= 2) q = r / hist[hist.size() - 2];
+        // r is the residual of the previous iterate; the current one's is about q r
+        if (r <= stop || (hist.size() >= 2 && q < 0.9 && q * r <= 0.5 * stop)) break;
+        if (ss.sweeps >= max_sweeps) break;
         if (hist.size() >= 3 && (q >= 0.95 || q > 1.0)) { stalled = 1; break; }
         q = std::min(std::max(q, 1e-12), 0.95);
         const double need = std::log(stop / r) / std::log(q);
@@ -336,12 +336,10 @@ sg_status gmres64(Scene &s, hipStream_t st, Timing &tm, const Real *S, double nS
     }
     ss.gmres_used = 1;
     const int nbv = 1024;
-    const int nb = spmv_blocks(s);
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), yv(m), h(m + 1), h2(m + 1);
     double *V = s.gm_V;
     while (true) {
-        launch_residual64<Real>(s, st, S, s.x64, s.r64, s.partial);
-        launch_reduce(s.partial, nb, s.scal, st);
+        launch_residual64<Real>(s, st, S, s.x64, s.r64, s.scal);
         ++ss.sweeps;
         ++ss.refinements;
         double r1;
@@ -426,7 +424,6 @@ sg_status solve_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Timing 
         ss.rel = 0.0;
         return SG_OK;
     }
-    const int nb = spmv_blocks(s);
     int use_gmres = o.solver == SG_SOLVER_GMRES;
     if (!use_gmres) {
         Real *xa = (Real *)s.x, *xb = (Real *)s.y;
@@ -437,8 +434,7 @@ sg_status solve_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Timing 
         if (stalled && o.solver == SG_SOLVER_AUTO) use_gmres = 1;
         // FP64 residual and iterative refinement
         for (int it = 0; !use_gmres && it < 12; ++it) {
-            launch_residual64<Real>(s, st, S, s.x64, s.r64, s.partial);
-            launch_reduce(s.partial, nb, s.scal, st);
+            launch_residual64<Real>(s, st, S, s.x64, s.r64, s.scal);
             ++ss.sweeps;
             ++ss.refinements;
             double r1;
@@ -533,6 +529,177 @@ sg_status solve_single(Scene &s, const sg_solve_opts &o, hipStream_t st, double 
     return SG_OK;
 }
 
+
+// Neumann sweeps for all wavelengths at once: x <- rhs + K x (rhs = NULL: the solar
+// source built on the fly).  Each wavelength stops being monitored once its update
+// falls below stop_rel * norm[lambda]; stall = a monitored wavelength whose sweep
+// ratio reaches 0.95.  The first sweep from x = 0 yields sum |rhs| per wavelength.
+sg_status neumann_batched(Scene &s, hipStream_t st, Timing &tm, const float *rhs, float *&xa, float *&xb,
+                          double stop_rel, int max_sweeps, SolveStats &ss, std::vector<double> &norm0,
+                          int &stalled) {
+    Ctx *ctx = s.ctx;
+    const int nl = s.n_lambda;
+    const long long n = (long long)s.E * nl;
+    const int grid = std::max(1, std::min({batched_groups(s), 2048, s.n_partial / nl}));
+    launch_fill_f32(xa, n, st);
+    std::vector<double> host((size_t)32 * nl), prev(nl, -1.0), last(nl, 0.0);
+    std::vector<int> done(nl, 0);
+    norm0.assign(nl, 0.0);
+    int chunk = 1, first = 1;
+    stalled = 0;
+    double *hist = s.lam_buf + 4 * nl;  // [32][nl]
+    while (true) {
+        chunk = std::max(1, std::min(chunk, 32));
+        for (int c = 0; c < chunk; ++c) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (tm.on) e0 = tm.mark();
+            launch_spmm(s, st, grid, rhs, xa, xb, s.partial);
+            if (tm.on) { e1 = tm.mark(); tm.spmv.push_back({e0, e1}); }
+            launch_reduce_lam(s.partial, grid, nl, hist + (size_t)c * nl, st);
+            std::swap(xa, xb);
+            ++ss.sweeps;
+        }
+        SG_HIP(hipGetLastError());
+        SG_TRY(read_scalars(s, st, hist, host.data(), chunk * nl));
+        int c0 = 0;
+        if (first) {
+            for (int k = 0; k < nl; ++k) norm0[k] = host[k];
+            c0 = 1;
+            first = 0;
+        }
+        bool all = true;
+        double need = 1.0;
+        for (int k = 0; k < nl; ++k) {
+            if (done[k]) continue;
+            for (int c = c0; c < chunk; ++c) {
+                prev[k] = last[k];
+                last[k] = host[(size_t)c * nl + k];
+            }
+            if (chunk == c0) { all = false; continue; }
+            const double stop = stop_rel * norm0[k];
+            if (!std::isfinite(last[k])) { stalled = 1; continue; }
+            if (last[k] <= stop) { done[k] = 1; continue; }
+            all = false;
+            double q = prev[k] > 0 ? last[k] / prev[k] : 0.5;
+            if (prev[k] > 0 && ss.sweeps >= 4 && q >= 0.95) stalled = 1;
+            q = std::min(std::max(q, 1e-12), 0.95);
+            need = std::max(need, std::log(stop / last[k]) / std::log(q));
+        }
+        if (all || stalled || ss.sweeps >= max_sweeps) break;
+        chunk = (int)std::ceil(need);
+    }
+    return SG_OK;
+}
+
+sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Timing &tm, SolveStats &ss) {
+    Ctx *ctx = s.ctx;
+    const int nl = s.n_lambda;
+    const long long n = (long long)s.E * nl;
+    const double rtol = o.rtol > 0 ? o.rtol : 1e-6;
+    const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 2000;
+    if (o.solver == SG_SOLVER_GMRES) return fail(SG_E_INVALID, "GMRES is available for single-wavelength scenes");
+    const int rgrid = std::max(1, std::min({batched_groups(s), 2048, s.n_partial / nl}));
+    float *xa = s.bx, *xb = s.by;
+    std::vector<double> nS, tmp;
+    int stalled = 0;
+    SG_TRY(neumann_batched(s, st, tm, nullptr, xa, xb, 0.3 * rtol, max_sweeps, ss, nS, stalled));
+    launch_f32_to_64(xa, s.x64, n, st);
+    std::vector<double> nr(nl), sc(nl);
+    double *d_sc = s.lam_buf;  // [nl]
+    for (int it = 0; it < 10; ++it) {
+        launch_bresidual64(s, st, rgrid, s.x64, s.r64, s.partial);
+        launch_reduce_lam(s.partial, rgrid, nl, s.lam_buf + nl, st);
+        ++ss.sweeps;
+        ++ss.refinements;
+        SG_TRY(read_scalars(s, st, s.lam_buf + nl, nr.data(), nl));
+        double worst = 0.0;
+        for (int k = 0; k < nl; ++k) {
+            const double rel = nS[k] > 0 ? nr[k] / nS[k] : 0.0;
+            worst = std::max(worst, rel);
+            sc[k] = nr[k] > 0 ? nS[k] / nr[k] : 1.0;
+        }
+        ss.rel = worst;
+        if (worst <= rtol) { ss.converged = 1; break; }
+        if (stalled || ss.sweeps >= max_sweeps) break;
+        SG_HIP(hipMemcpyAsync(d_sc, sc.data(), sizeof(double) * nl, hipMemcpyHostToDevice, st));
+        launch_lam_scale_to_f32(s.r64, d_sc, nl, s.bS, n, st);
+        float *ca = s.bx, *cb = s.by;
+        int st2 = 0;
+        SG_TRY(neumann_batched(s, st, tm, s.bS, ca, cb, 1e-5, max_sweeps, ss, tmp, st2));
+        launch_lam_axpy(s.x64, ca, d_sc, nl, n, st);
+        if (st2) stalled = 1;
+    }
+    SG_HIP(hipGetLastError());
+    return SG_OK;
+}
+
+sg_status solve_batched(Scene &s, const sg_solve_opts &o, hipStream_t st, double *radiance, int on_dev,
+                        sg_solve_info *info) {
+    Ctx *ctx = s.ctx;
+    Timing tm;
+    tm.on = o.timing != 0;
+    tm.st = st;
+    hipEvent_t e0 = tm.mark();
+    launch_structure(s, st);
+    if (o.build_col_idx) {
+        if (!s.col_idx) SG_TRY(dalloc(s, &s.col_idx, (size_t)s.nnz));
+        launch_col_idx(s, st);
+        s.col_built = true;
+    } else {
+        s.col_built = false;
+    }
+    hipEvent_t e1 = tm.mark();
+    launch_march<float>(s, st, 1.0f, 1);
+    launch_bnode_coef(s, st);
+    hipEvent_t e2 = tm.mark();
+    launch_qbuild<float>(s, st, 1);
+    hipEvent_t e3 = tm.mark();
+    SG_HIP(hipGetLastError());
+    SolveStats ss;
+    const long long n = (long long)s.E * s.n_lambda;
+    if (o.scatter_order == 1) {
+        launch_fill<double>(s.x64, 0.0, n, st);
+        ss.converged = 1;
+    } else {
+        SG_TRY(solve_batched_linear(s, o, st, tm, ss));
+    }
+    hipEvent_t e4 = tm.mark();
+    double *dst = on_dev ? radiance : s.pix;
+    launch_batched_gather(s, st, s.x64, o.scatter_order, dst);
+    hipEvent_t e5 = tm.mark();
+    SG_HIP(hipGetLastError());
+    if (!on_dev)
+        SG_HIP(hipMemcpyAsync(radiance, dst, sizeof(double) * s.npx * s.n_lambda, hipMemcpyDeviceToHost, st));
+    SG_HIP(hipStreamSynchronize(st));
+    s.solved = true;
+    s.last_precision = SG_FP32;
+    s.last_scatter_order = o.scatter_order;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->converged = ss.converged;
+        info->sweeps = ss.sweeps;
+        info->refinements = ss.refinements;
+        info->rel_residual = ss.rel;
+        info->n_nodes = s.N;
+        info->n_edges = s.E;
+        info->nnz = s.nnz;
+        if (tm.on) {
+            info->ms_structure = tm.between(e0, e1);
+            info->ms_march = tm.between(e1, e2);
+            info->ms_qbuild = tm.between(e2, e3);
+            info->ms_solve = tm.between(e3, e4);
+            info->ms_gather = tm.between(e4, e5);
+            info->ms_total = tm.between(e0, e5);
+            double sum = 0.0;
+            for (auto &p : tm.spmv) sum += tm.between(p.first, p.second);
+            info->ms_spmv_sum = sum;
+            info->spmv_launches = (int)tm.spmv.size();
+        }
+    }
+    if (!ss.converged) return fail(SG_E_NOCONV, "solve stopped at relative residual " + std::to_string(ss.rel));
+    return SG_OK;
+}
+
 }  // namespace
 }  // namespace sg
 
@@ -577,13 +744,24 @@ sg_status sg_ctx_destroy(sg_ctx *ctx) {
 
 }  // extern "C"
 
+namespace sg {
+namespace {
+sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Scene &s);
+void free_scene_impl(Scene *s);
+}  // namespace
+
+void free_scene(Scene *s) { free_scene_impl(s); }
+sg_status create_scene(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Scene &s) {
+    return create_scene_impl(ctx, d, st, s);
+}
+
 namespace {
 
-void free_scene(Scene *s) {
+void free_scene_impl(Scene *s) {
     void *ptrs[] = {s->mu_s, s->mu_a, s->frac, s->albedo, s->abs_scale_d, s->pos, s->adj_ptr, s->adj_idx, s->lat,
                     s->tab, s->rev, s->nodeoff, s->row_ptr, s->col_idx, s->scan_tmp, s->tau_s, s->tau_a, s->tsun_s,
                     s->tsun_a, s->T, s->Tsun, s->rho, s->val, s->S, s->x, s->y, s->c_rhs, s->c_a, s->c_b, s->qsun,
-                    s->q, s->bS, s->bx, s->by, s->brho, s->x64, s->r64, s->gm_V, s->partial, s->scal, s->J, s->pix};
+                    s->q, s->bS, s->bx, s->by, s->brho, s->bsrc, s->lam_buf, s->x64, s->r64, s->gm_V, s->partial, s->counter, s->scal, s->J, s->pix};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->ctx) release(s->ctx, s->bytes);
@@ -596,7 +774,7 @@ sg_status upload(Scene &s, void *dst, const void *src, size_t bytes, hipStream_t
     return SG_OK;
 }
 
-sg_status create_scene(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Scene &s) {
+sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Scene &s) {
     int64_t N, E, nnz;
     int dmax;
     SG_TRY(validate(d, N, E, nnz, dmax));
@@ -647,6 +825,8 @@ sg_status create_scene(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Scene &
     s.n_partial = std::max(spmv_blocks(s), 65 * 1024);
     SG_TRY(dalloc(s, &s.partial, (size_t)s.n_partial));
     SG_TRY(dalloc(s, &s.scal, 256));
+    SG_TRY(dalloc(s, &s.counter, 64));
+    SG_HIP(hipMemsetAsync(s.counter, 0, 64 * sizeof(unsigned), st));
     SG_TRY(dalloc(s, &s.J, (size_t)s.N * nl));
     SG_TRY(dalloc(s, &s.pix, (size_t)s.npx * nl));
     if (nl == 1) {
@@ -657,11 +837,13 @@ sg_status create_scene(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Scene &
         SG_TRY(dalloc(s, &p, s.E)); s.tau_a = p;
         SG_TRY(dalloc(s, &p, s.N)); s.tsun_s = p;
         SG_TRY(dalloc(s, &p, s.N)); s.tsun_a = p;
-        SG_TRY(dalloc(s, &s.q, (size_t)s.nnz));
+        SG_TRY(dalloc(s, &s.q, (size_t)s.nnz + 64));  // padded: whole-column reads past the last block
         SG_TRY(dalloc(s, &s.bS, (size_t)s.E * nl));
         SG_TRY(dalloc(s, &s.bx, (size_t)s.E * nl));
         SG_TRY(dalloc(s, &s.by, (size_t)s.E * nl));
         SG_TRY(dalloc(s, &s.brho, (size_t)s.N * nl));
+        SG_TRY(dalloc(s, &s.bsrc, (size_t)s.N * nl));
+        SG_TRY(dalloc(s, &s.lam_buf, (size_t)36 * nl));
         SG_TRY(dalloc(s, &s.abs_scale_d, (size_t)nl));
         SG_TRY(upload(s, s.abs_scale_d, s.abs_scale.data(), sizeof(float) * nl, st));
     }
@@ -697,6 +879,7 @@ sg_status create_scene(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Scene &
 hipStream_t pick_stream(Ctx *ctx, void *st) { return st ? (hipStream_t)st : ctx->stream; }
 
 }  // namespace
+}  // namespace sg
 
 extern "C" {
 
@@ -708,7 +891,7 @@ sg_status sg_scene_create(sg_ctx *ctx, const sg_scene_desc *desc, void *hip_stre
     std::unique_ptr<sg_scene> s(new sg_scene());
     sg_status st = create_scene(ctx, desc, pick_stream(ctx, hip_stream), *s);
     if (st != SG_OK) {
-        std::string msg = sg_last_error();
+        std::string msg = t_err;
         free_scene(s.get());
         set_error(msg);
         return st;
@@ -741,15 +924,23 @@ sg_status sg_scene_sizes(const sg_scene *scene, int64_t *n_nodes, int64_t *n_edg
     return SG_OK;
 }
 
-sg_status sg_solve_batched_impl(Scene &s, const sg_solve_opts &o, hipStream_t st, double *radiance, int on_dev,
-                                sg_solve_info *info);
+}  // extern "C"
 
-sg_status sg_solve(sg_scene *scene, const sg_solve_opts *opts, void *hip_stream, double *radiance,
-                   int32_t radiance_on_device, sg_solve_info *info) {
-    if (!scene || !radiance) return fail(SG_E_INVALID, "scene or radiance is NULL");
-    Ctx *ctx = scene->ctx;
-    if (ctx->sticky.load()) return fail(SG_E_DEVICE, "context is in a failed state");
-    sg_solve_opts o;
+namespace sg {
+sg_status solve_scene(Scene &s, const sg_solve_opts &o, hipStream_t st, double *radiance, int on_dev,
+                      sg_solve_info *info) {
+    Ctx *ctx = s.ctx;
+    std::lock_guard<std::mutex> lk(s.mu);
+    SG_HIP(hipSetDevice(ctx->device));
+    if (s.n_lambda > 1) {
+        if (o.precision != SG_FP32) return fail(SG_E_INVALID, "several wavelengths are solved in FP32 only");
+        return solve_batched(s, o, st, radiance, on_dev, info);
+    }
+    if (o.precision == SG_FP64) return solve_single<double>(s, o, st, radiance, on_dev, info);
+    return solve_single<float>(s, o, st, radiance, on_dev, info);
+}
+
+sg_status check_opts(const sg_solve_opts *opts, sg_solve_opts &o) {
     if (opts) {
         if (opts->abi_version != SG_ABI_VERSION) return fail(SG_E_ABI, "solve opts abi_version mismatch");
         o = *opts;
@@ -759,15 +950,51 @@ sg_status sg_solve(sg_scene *scene, const sg_solve_opts *opts, void *hip_stream,
     if (o.precision != SG_FP32 && o.precision != SG_FP64) return fail(SG_E_INVALID, "precision must be SG_FP32 or SG_FP64");
     if (o.solver < 0 || o.solver > 2) return fail(SG_E_INVALID, "bad solver");
     if (o.scatter_order != 0 && o.scatter_order != 1) return fail(SG_E_INVALID, "scatter_order must be 0 or 1");
-    std::lock_guard<std::mutex> lk(scene->mu);
-    SG_HIP(hipSetDevice(ctx->device));
-    hipStream_t st = pick_stream(ctx, hip_stream);
-    if (scene->n_lambda > 1) {
-        if (o.precision != SG_FP32) return fail(SG_E_INVALID, "several wavelengths are solved in FP32 only");
-        return sg_solve_batched_impl(*scene, o, st, radiance, radiance_on_device, info);
+    return SG_OK;
+}
+
+uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st) {
+    int64_t N, E, nnz;
+    int dmax;
+    *st = validate(d, N, E, nnz, dmax);
+    if (*st != SG_OK) return 0;
+    // mirrors the allocations of create_scene (each at least one element)
+    auto a = [](uint64_t count, uint64_t size) { return std::max<uint64_t>(count, 1) * size; };
+    const uint64_t nvox = (uint64_t)d->nx * d->ny * d->nz, npx = (uint64_t)d->nx * d->ny;
+    const uint64_t nl = (uint64_t)d->n_lambda, nf = (uint64_t)d->n_fib, np = (uint64_t)d->n_phase;
+    const uint64_t n = (uint64_t)N, e = (uint64_t)E, z = (uint64_t)nnz;
+    uint64_t b = a(nvox, 4) * 2 + (np > 1 ? a(np * nvox, 4) : 0) + a(npx, 4) + a(3 * n, 4) + a(n + 1, 8) +
+                 a(e, 4) + a(3 * nf, 8) + a((np + 1) * nf, 8);
+    b += a(e, 4) + a(n + 1, 8) + a(e + 1, 8) + a(n / 2048 + 2, 8) + a(e, 4);
+    b += a(e * nl, 8) * 2 + a(std::max<uint64_t>((n + 3) / 4, 65 * 1024), 8) + a(256, 8) + a(64, 4) +
+         a(n * nl, 8) + a(npx * nl, 8);
+    if (nl == 1) {
+        b += a(e, 4) * 9 + a(n, 4) * 4 + a(z, 4);
+    } else {
+        b += a(e, 4) * 2 + a(n, 4) * 2 + a(z + 64, 4) + a(e * nl, 4) * 3 + a(n * nl, 4) * 2 + a(36 * nl, 8) +
+             a(nl, 4);
     }
-    if (o.precision == SG_FP64) return solve_single<double>(*scene, o, st, radiance, radiance_on_device, info);
-    return solve_single<float>(*scene, o, st, radiance, radiance_on_device, info);
+    return b;
+}
+}  // namespace sg
+
+extern "C" {
+
+sg_status sg_solve(sg_scene *scene, const sg_solve_opts *opts, void *hip_stream, double *radiance,
+                   int32_t radiance_on_device, sg_solve_info *info) {
+    if (!scene || !radiance) return fail(SG_E_INVALID, "scene or radiance is NULL");
+    Ctx *ctx = scene->ctx;
+    if (ctx->sticky.load()) return fail(SG_E_DEVICE, "context is in a failed state");
+    sg_solve_opts o;
+    SG_TRY(check_opts(opts, o));
+    return solve_scene(*scene, o, pick_stream(ctx, hip_stream), radiance, radiance_on_device, info);
+}
+
+sg_status sg_scene_reservation(const sg_scene_desc *desc, uint64_t *bytes) {
+    if (!bytes) return fail(SG_E_INVALID, "bytes is NULL");
+    sg_status st;
+    *bytes = scene_reservation(desc, &st);
+    return st;
 }
 
 sg_status sg_export_csr(sg_scene *scene, int32_t lambda, int64_t *row_ptr, int32_t *col_idx, double *val) {
@@ -808,7 +1035,7 @@ sg_status sg_export_csr(sg_scene *scene, int32_t lambda, int64_t *row_ptr, int32
                     for (int64_t m = 0; m < d; ++m) {
                         const int64_t e = ap[l] + m;
                         const float T = expf(-(ts[e] + sl * ta[e]));
-                        val[no[l] + n * d + m] = (double)(T * r * q[no[l] + n * d + m]);
+                        val[no[l] + n * d + m] = (double)(T * r * q[no[l] + m * d + n]);
                     }
             }
         } else if (s.real_bytes == 4) {
@@ -843,7 +1070,23 @@ sg_status sg_export_vector(sg_scene *scene, int32_t which, double *out) {
         case SG_VEC_TAU_SUN_S: src = s.tsun_s; n = s.N; break;
         case SG_VEC_TAU_SUN_A: src = s.tsun_a; n = s.N; break;
         case SG_VEC_RHO: src = batched ? (const void *)s.brho : s.rho; n = (size_t)s.N * s.n_lambda; break;
-        case SG_VEC_SOURCE: src = batched ? (const void *)s.bS : s.S; n = (size_t)s.E * s.n_lambda; break;
+        case SG_VEC_SOURCE:
+            if (batched) {
+                const int nl = s.n_lambda;
+                std::vector<float> br((size_t)s.N * nl), bs((size_t)s.N * nl), qs(s.E);
+                std::vector<int64_t> ap(s.N + 1);
+                SG_HIP(hipMemcpyAsync(br.data(), s.brho, sizeof(float) * br.size(), hipMemcpyDeviceToHost, st));
+                SG_HIP(hipMemcpyAsync(bs.data(), s.bsrc, sizeof(float) * bs.size(), hipMemcpyDeviceToHost, st));
+                SG_HIP(hipMemcpyAsync(qs.data(), s.qsun, sizeof(float) * s.E, hipMemcpyDeviceToHost, st));
+                SG_HIP(hipMemcpyAsync(ap.data(), s.adj_ptr, sizeof(int64_t) * (s.N + 1), hipMemcpyDeviceToHost, st));
+                SG_HIP(hipStreamSynchronize(st));
+                for (int64_t l = 0; l < s.N; ++l)
+                    for (int64_t e = ap[l]; e < ap[l + 1]; ++e)
+                        for (int k = 0; k < nl; ++k)
+                            out[(size_t)k * s.E + e] = (double)(br[l * nl + k] * bs[l * nl + k] * qs[e]);
+                return SG_OK;
+            }
+            src = s.S; n = (size_t)s.E; break;
         case SG_VEC_PHI: src = s.x64; n = (size_t)s.E * s.n_lambda; esz = 8; break;
         case SG_VEC_QSUN: src = s.qsun; n = s.E; esz = 4; break;
         default: return fail(SG_E_INVALID, "unknown vector");

@@ -1,0 +1,384 @@
+// Many wavelengths over one scattering graph (Sec. 3: when only absorption
+// changes between wavelengths, the geometry, the graph and the phase cells are
+// computed once and reused; path integrals are kept per medium component).
+//
+// Per wavelength lambda with absorption multiplier s:
+//   tau_e(s) = tau_s,e + s tau_a,e            (exact by linearity of the path integral)
+//   T_e      = exp(-tau_e(s)),  rho_l(s) = w(s) (1 - exp(-mu_e(s) dx))  (albedo on the surface)
+//   S_b      = rho_l T_sun,l (mu0 on the surface) Qsun_b
+//   y_b      = S_b + rho_l sum_m Q_l[n][m] T_{a_m} x_{a_m}
+// The SpMM keeps the wavelengths in the lanes of a wavefront (lambda fastest in
+// every [E][n_lambda] array), so each node's phase-cell block Q (shared by all
+// wavelengths, column-major within the block) is read once per sweep for all
+// of them, through scalar loads when a wavefront holds a single node.  The
+// grid is persistent: a fixed set of workgroups strides over node groups.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace sg {
+
+namespace {
+
+// rho_l(lambda) and the solar factor T_sun,l(lambda) (x mu0 on the surface).
+__global__ __launch_bounds__(256) void k_bnode_coef(int N, int nvox, int nl, const float *__restrict__ mu_s,
+                                                   const float *__restrict__ mu_a, const float *__restrict__ albedo,
+                                                   const float *__restrict__ tsun_s, const float *__restrict__ tsun_a,
+                                                   const float *__restrict__ abs_scale, float dx, float mu0,
+                                                   int mode, float *__restrict__ brho, float *__restrict__ bsrc) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= (long long)N * nl) return;
+    const int l = (int)(i / nl), lam = (int)(i % nl);
+    const float s = abs_scale[lam];
+    float r;
+    if (l < nvox) {
+        const float ms = mu_s[l];
+        const float me = ms + s * mu_a[l];
+        if (mode == 1) r = ms * dx;
+        else r = me > 0.f ? (ms / me) * (-expm1f(-me * dx)) : 0.f;
+    } else {
+        r = albedo[l - nvox];
+    }
+    const float ts = expf(-(tsun_s[l] + s * tsun_a[l]));
+    brho[i] = r;
+    bsrc[i] = l < nvox ? ts : mu0 * ts;
+}
+
+// One node per wavefront, lanes = wavelengths (tiles of 64).  The node index is
+// wave-uniform, so the phase-cell block Q comes through scalar loads; the node's
+// in-edge list and optical depths are loaded once, coalesced, and broadcast with
+// readlane; eight input gathers are in flight at a time; the node's rows are
+// accumulated in registers, the row count rounded up to a multiple of 8 (DB) so the
+// column loads are unguarded (the Q array is padded past its end by 64 floats).
+// kResidual: FP64 residual r = S - x + K x of an FP64 iterate instead of a sweep.
+template <int DB, class XT, class AccT, bool kResidual>
+__device__ __forceinline__ double wide_node(int l, int lane, int lam, bool lv, float s, int nl,
+                                            const long long *__restrict__ adj_ptr,
+                                            const long long *__restrict__ nodeoff, const int *__restrict__ rev,
+                                            const float *__restrict__ q, const float *__restrict__ qsun,
+                                            const float *__restrict__ tau_s, const float *__restrict__ tau_a,
+                                            const float *__restrict__ brho, const float *__restrict__ bsrc,
+                                            const float *__restrict__ rhs, const XT *__restrict__ x,
+                                            XT *__restrict__ y) {
+    constexpr int kU = 8;
+    const long long off = adj_ptr[l];
+    const int d = (int)(adj_ptr[l + 1] - off);
+    const long long base = nodeoff[l];
+    int rv = 0;
+    float ts = 0.f, ta = 0.f;
+    if (lane < d) {
+        rv = rev[off + lane];
+        ts = tau_s[off + lane];
+        ta = tau_a[off + lane];
+    }
+    AccT acc[DB];
+#pragma unroll
+    for (int n = 0; n < DB; ++n) acc[n] = (AccT)0;
+    for (int m0 = 0; m0 < d; m0 += kU) {
+        XT xv[kU];
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+            const int m = min(m0 + j, 63);
+            const int r = __builtin_amdgcn_readlane(rv, m);
+            xv[j] = (m0 + j < d && lv) ? x[(long long)r * nl + lam] : (XT)0;
+        }
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+            const int m = m0 + j;
+            if (m < d) {
+                const float tsm = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ts), m));
+                const float tam = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ta), m));
+                const AccT xm = (AccT)expf(-(tsm + s * tam)) * (AccT)xv[j];
+                const float *qm = q + base + (long long)m * d;  // column m: Q[n][m], n contiguous
+#pragma unroll
+                for (int n = 0; n < DB; ++n) acc[n] += (AccT)qm[n] * xm;
+            }
+        }
+    }
+    double part = 0.0;
+    if (lv) {
+        const float rl = brho[(long long)l * nl + lam];
+        const float sl = bsrc[(long long)l * nl + lam];
+#pragma unroll
+        for (int n = 0; n < DB; ++n) {
+            if (n < d) {
+                const long long b = off + n;
+                const long long bi = b * nl + lam;
+                if (kResidual) {
+                    const double Sb = (double)(rl * sl * qsun[b]);
+                    const double rb = (Sb - (double)x[bi]) + (double)rl * (double)acc[n];
+                    y[bi] = (XT)rb;
+                    part += fabs(rb);
+                } else {
+                    const float src = rhs ? rhs[bi] : rl * sl * qsun[b];
+                    const float yv = src + rl * (float)acc[n];
+                    y[bi] = (XT)yv;
+                    part += fabs((double)yv - (double)x[bi]);
+                }
+            }
+        }
+    }
+    return part;
+}
+
+template <int D, class XT, class AccT, bool kResidual>
+__global__ __launch_bounds__(256) void k_spmm_wide(
+    int N, int nl, int groups, const long long *__restrict__ adj_ptr, const long long *__restrict__ nodeoff,
+    const int *__restrict__ rev, const float *__restrict__ q, const float *__restrict__ qsun,
+    const float *__restrict__ tau_s, const float *__restrict__ tau_a, const float *__restrict__ abs_scale,
+    const float *__restrict__ brho, const float *__restrict__ bsrc, const float *__restrict__ rhs,
+    const XT *__restrict__ x, XT *__restrict__ y, double *__restrict__ partial) {
+    __shared__ double red[256];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lam = blockIdx.y * 64 + lane;
+    const bool lv = lam < nl;
+    const float s = lv ? abs_scale[lam] : 0.f;
+    double part = 0.0;
+    for (int g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int l = __builtin_amdgcn_readfirstlane(g * 4 + w);
+        if (l >= N) break;
+        const int d = (int)(adj_ptr[l + 1] - adj_ptr[l]);
+        const int bucket = (d + 7) >> 3;
+#define SG_NODE(DB)                                                                                              \
+    part += wide_node<DB, XT, AccT, kResidual>(l, lane, lam, lv, s, nl, adj_ptr, nodeoff, rev, q, qsun, tau_s, \
+                                               tau_a, brho, bsrc, rhs, x, y)
+        if (bucket <= 1) { SG_NODE(8); }
+        else if (bucket == 2) { if constexpr (D >= 16) SG_NODE(16); }
+        else if (bucket == 3) { if constexpr (D >= 24) SG_NODE(24); }
+        else if (bucket == 4) { if constexpr (D >= 32) SG_NODE(32); }
+        else if (bucket == 5) { if constexpr (D >= 40) SG_NODE(40); }
+        else if (bucket == 6) { if constexpr (D >= 48) SG_NODE(48); }
+        else if (bucket == 7) { if constexpr (D >= 56) SG_NODE(56); }
+        else { if constexpr (D >= 64) SG_NODE(64); }
+#undef SG_NODE
+    }
+    red[threadIdx.x] = part;
+    __syncthreads();
+    if (w == 0 && lv) {
+        double t = 0.0;
+        for (int ww = 0; ww < 4; ++ww) t += red[ww * 64 + lane];
+        partial[(long long)blockIdx.x * nl + lam] = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_lam(const double *__restrict__ partial, int nblk, int nl,
+                                                   double *__restrict__ out) {
+    const int lam = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lam >= nl) return;
+    double t = 0.0;
+    for (int b = 0; b < nblk; ++b) t += partial[(long long)b * nl + lam];
+    out[lam] = t;
+}
+
+__global__ void k_lam_scale_to_f32(const double *__restrict__ a, const double *__restrict__ sc, int nl,
+                                   float *__restrict__ b, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        b[i] = (float)(a[i] * sc[i % nl]);
+}
+
+__global__ void k_lam_axpy(double *__restrict__ x, const float *__restrict__ d, const double *__restrict__ sc, int nl,
+                           long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        x[i] += (double)d[i] / sc[i % nl];
+}
+
+__global__ void k_f32_to_64(const float *__restrict__ a, double *__restrict__ b, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        b[i] = (double)a[i];
+}
+
+__global__ void k_fill_f32(float *__restrict__ a, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        a[i] = 0.f;
+}
+
+struct PhaseMixB {
+    double g[4];
+    int n;
+};
+
+__device__ __forceinline__ double theta_mix_b(const PhaseMixB &pm, const float *__restrict__ frac, int nvox, int v,
+                                              double mu) {
+    double th = 0.0;
+    for (int c = 0; c < pm.n; ++c) {
+        const double f = frac ? (double)frac[(long long)c * nvox + v] : 1.0;
+        th += f * hg_phase(pm.g[c], mu);
+    }
+    return th;
+}
+
+// J[l][lambda]: one wavefront per node; lane m evaluates in-edge m's phase function
+// once, then the lanes (wavelengths) accumulate in FP64.
+__global__ __launch_bounds__(64) void k_bnode_J(int N, int nvox, int nl, const long long *__restrict__ adj_ptr,
+                                               const int *__restrict__ adj_idx, const int *__restrict__ rev,
+                                               const int *__restrict__ pos, const float *__restrict__ tau_s,
+                                               const float *__restrict__ tau_a, const float *__restrict__ abs_scale,
+                                               const float *__restrict__ bsrc, const double *__restrict__ phi,
+                                               PhaseMixB pm, const float *__restrict__ frac, double sx, double sy,
+                                               double sz, double vx, double vy, double vz, int multiple,
+                                               double *__restrict__ J) {
+    __shared__ double th[64];
+    const int l = blockIdx.x;
+    const int lane = threadIdx.x;
+    const long long off = adj_ptr[l];
+    const int d = (int)(adj_ptr[l + 1] - off);
+    const bool vol = l < nvox;
+    if (lane < d) {
+        double t = 1.0;
+        if (vol) {
+            const int j = adj_idx[off + lane];
+            const long long Dx = (long long)pos[3 * l] - pos[3 * j], Dy = (long long)pos[3 * l + 1] - pos[3 * j + 1],
+                            Dz = (long long)pos[3 * l + 2] - pos[3 * j + 2];
+            const double nrm = sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
+            const double mu = ((double)Dx / nrm) * vx + ((double)Dy / nrm) * vy + ((double)Dz / nrm) * vz;
+            t = theta_mix_b(pm, frac, nvox, l, mu);
+        }
+        th[lane] = t;
+    }
+    const double th_sun = vol ? theta_mix_b(pm, frac, nvox, l, sx * vx + sy * vy + sz * vz) : 1.0;
+    __syncthreads();
+    for (int l0 = 0; l0 < nl; l0 += 64) {
+        const int lam = l0 + lane;
+        if (lam >= nl) continue;
+        const float s = abs_scale[lam];
+        double acc = th_sun * (double)bsrc[(long long)l * nl + lam];  // T_sun (x mu0 on the surface)
+        if (multiple) {
+            for (int m = 0; m < d; ++m) {
+                const long long e = off + m;
+                const double T = (double)expf(-(tau_s[e] + s * tau_a[e]));
+                acc += th[m] * T * phi[(long long)rev[e] * nl + lam];
+            }
+        }
+        J[(long long)l * nl + lam] = acc;
+    }
+}
+
+// One wavefront per pixel, lanes = wavelengths: the voxel walk is the same for all
+// lanes, each accumulates its own wavelength in FP64.
+__global__ __launch_bounds__(64) void k_bpixels(int nx, int ny, int nz, int nl, const float *__restrict__ mu_s,
+                                               const float *__restrict__ mu_a, const float *__restrict__ abs_scale,
+                                               double len_view, long long vdx, long long vdy, long long vdz,
+                                               long long sdx, long long sdy, long long sdz, double len_sun,
+                                               const float *__restrict__ albedo, const double *__restrict__ J,
+                                               int surface, double mu0, double *__restrict__ out) {
+    const int p = blockIdx.x;
+    const int lane = threadIdx.x;
+    const long long ix = p % nx, iy = p / nx;
+    const long long px = ix * kFx + kFx / 2, py = iy * kFx + kFx / 2;
+    const long long nvox = (long long)nx * ny * nz;
+    const double a_pi = (double)albedo[p] / 3.14159265358979323846;
+    for (int l0 = 0; l0 < nl; l0 += 64) {
+        const int lam = min(l0 + lane, nl - 1);
+        const double s = (double)abs_scale[lam];
+        double tau_tot = 0.0;
+        voxel_walk(nx, ny, nz, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
+            const long long v = x + (long long)nx * (y + (long long)ny * z);
+            tau_tot += ((double)mu_s[v] + s * (double)mu_a[v]) * ((double)num / (double)den * len_view);
+            return true;
+        });
+        double I = 0.0, cum = 0.0;
+        voxel_walk(nx, ny, nz, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
+            const long long v = x + (long long)nx * (y + (long long)ny * z);
+            const double ms = (double)mu_s[v];
+            const double me = ms + s * (double)mu_a[v];
+            const double tk = me * ((double)num / (double)den * len_view);
+            const double om = me > 0.0 ? ms / me : 0.0;
+            I += exp(-(tau_tot - (cum + tk))) * (om * (-expm1(-tk))) * J[v * nl + lam];
+            cum += tk;
+            return true;
+        });
+        if (surface) {
+            I += exp(-tau_tot) * a_pi * J[(nvox + p) * nl + lam];
+        } else {
+            double ts = 0.0;
+            voxel_walk(nx, ny, nz, px, py, 0, sdx, sdy, sdz, true, [&](int x, int y, int z, long long num, long long den) {
+                const long long v = x + (long long)nx * (y + (long long)ny * z);
+                ts += ((double)mu_s[v] + s * (double)mu_a[v]) * ((double)num / (double)den * len_sun);
+                return true;
+            });
+            I += exp(-tau_tot) * a_pi * mu0 * exp(-ts);
+        }
+        if (l0 + lane < nl) out[(long long)(l0 + lane) * nx * ny + p] = I;
+    }
+}
+
+inline int grid_for(long long n) {
+    long long g = (n + 255) / 256;
+    return (int)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
+}
+
+}  // namespace
+
+void launch_bnode_coef(Scene &s, hipStream_t st) {
+    const long long n = (long long)s.N * s.n_lambda;
+    hipLaunchKernelGGL(k_bnode_coef, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.N, s.nvox, s.n_lambda, s.mu_s,
+                       s.mu_a, s.albedo, (const float *)s.tsun_s, (const float *)s.tsun_a, s.abs_scale_d,
+                       (float)s.voxel_m, (float)s.mu0, s.weight_mode, s.brho, s.bsrc);
+}
+
+template <class XT, class AccT, bool kRes>
+static bool launch_wide(Scene &s, hipStream_t st, int grid, const float *rhs, const XT *x, XT *y, double *partial) {
+    const int groups = (s.N + 3) / 4;
+    dim3 gr(grid, (s.n_lambda + 63) / 64);
+#define SG_WIDE(DD)                                                                                              \
+    hipLaunchKernelGGL((k_spmm_wide<DD, XT, AccT, kRes>), gr, dim3(256), 0, st, s.N, s.n_lambda, groups, s.adj_ptr, \
+                       s.nodeoff, s.rev, s.q, s.qsun, (const float *)s.tau_s, (const float *)s.tau_a, s.abs_scale_d,  \
+                       s.brho, s.bsrc, rhs, x, y, partial)
+    if (s.dmax <= 16) SG_WIDE(16);
+    else if (s.dmax <= 24) SG_WIDE(24);
+    else if (s.dmax <= 32) SG_WIDE(32);
+    else if (s.dmax <= 40) SG_WIDE(40);
+    else if (s.dmax <= 48) SG_WIDE(48);
+    else if (s.dmax <= 56) SG_WIDE(56);
+    else SG_WIDE(64);
+#undef SG_WIDE
+    return true;
+}
+
+int batched_groups(const Scene &s) { return (s.N + 3) / 4; }
+
+void launch_spmm(Scene &s, hipStream_t st, int grid, const float *rhs, const float *x, float *y, double *partial) {
+    launch_wide<float, float, false>(s, st, grid, rhs, x, y, partial);
+}
+
+void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, double *r64, double *partial) {
+    launch_wide<double, double, true>(s, st, grid, nullptr, x64, r64, partial);
+}
+
+void launch_reduce_lam(const double *partial, int nblk, int nl, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_lam, dim3((nl + 255) / 256), dim3(256), 0, st, partial, nblk, nl, out);
+}
+
+void launch_lam_scale_to_f32(const double *a, const double *sc, int nl, float *b, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_lam_scale_to_f32, dim3(grid_for(n)), dim3(256), 0, st, a, sc, nl, b, n);
+}
+
+void launch_lam_axpy(double *x, const float *d, const double *sc, int nl, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_lam_axpy, dim3(grid_for(n)), dim3(256), 0, st, x, d, sc, nl, n);
+}
+
+void launch_f32_to_64(const float *a, double *b, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_f32_to_64, dim3(grid_for(n)), dim3(256), 0, st, a, b, n);
+}
+
+void launch_fill_f32(float *a, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n)), dim3(256), 0, st, a, n);
+}
+
+void launch_batched_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance) {
+    PhaseMixB pm;
+    pm.n = s.n_phase;
+    for (int i = 0; i < 4; ++i) pm.g[i] = s.hg_g[i];
+    hipLaunchKernelGGL(k_bnode_J, dim3(s.N), dim3(64), 0, st, s.N, s.nvox, s.n_lambda, s.adj_ptr, s.adj_idx, s.rev,
+                       s.pos, (const float *)s.tau_s, (const float *)s.tau_a, s.abs_scale_d, s.bsrc, phi, pm, s.frac,
+                       s.sun_in[0], s.sun_in[1], s.sun_in[2], s.view_u[0], s.view_u[1], s.view_u[2],
+                       scatter_order == 1 ? 0 : 1, s.J);
+    const double fx = s.voxel_m / 65536.0;
+    const double lv = sqrt((double)s.view[0] * s.view[0] + (double)s.view[1] * s.view[1] + (double)s.view[2] * s.view[2]) * fx;
+    const double ls = sqrt((double)s.sun[0] * s.sun[0] + (double)s.sun[1] * s.sun[1] + (double)s.sun[2] * s.sun[2]) * fx;
+    hipLaunchKernelGGL(k_bpixels, dim3(s.npx), dim3(64), 0, st, s.nx, s.ny, s.nz, s.n_lambda, s.mu_s, s.mu_a,
+                       s.abs_scale_d, lv, (long long)s.view[0], (long long)s.view[1], (long long)s.view[2],
+                       (long long)s.sun[0], (long long)s.sun[1], (long long)s.sun[2], ls, s.albedo, s.J, s.surface,
+                       s.mu0, radiance);
+}
+
+}  // namespace sg

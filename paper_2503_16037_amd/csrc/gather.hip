@@ -31,6 +31,7 @@ __device__ __forceinline__ double theta_mix(const PhaseMix &pm, const float *__r
     return th;
 }
 
+// One wavefront per node: lane m takes in-edge m's term, then a fixed-order butterfly sum.
 template <class Real>
 __global__ __launch_bounds__(256) void k_node_J(int N, int nvox, const long long *__restrict__ adj_ptr,
                                                const int *__restrict__ adj_idx, const int *__restrict__ rev,
@@ -39,28 +40,33 @@ __global__ __launch_bounds__(256) void k_node_J(int N, int nvox, const long long
                                                PhaseMix pm, const float *__restrict__ frac, double sx, double sy,
                                                double sz, double vx, double vy, double vz, double mu0,
                                                int multiple, double *__restrict__ J) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (l >= N) return;
     const long long off = adj_ptr[l], end = adj_ptr[l + 1];
-    double acc;
-    if (l < nvox) {
-        acc = theta_mix(pm, frac, nvox, l, sx * vx + sy * vy + sz * vz) * (double)Tsun[l];
-        if (multiple) {
-            const long long Px = pos[3 * l], Py = pos[3 * l + 1], Pz = pos[3 * l + 2];
-            for (long long e = off; e < end; ++e) {
+    const int d = (int)(end - off);
+    const bool vol = l < nvox;
+    double acc = 0.0;
+    if (multiple) {
+        for (int m = lane; m < d; m += 64) {
+            const long long e = off + m;
+            double th = 1.0;
+            if (vol) {
                 const int j = adj_idx[e];
-                const long long Dx = Px - pos[3 * j], Dy = Py - pos[3 * j + 1], Dz = Pz - pos[3 * j + 2];
-                const double nrm = sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
-                const double mu = ((double)Dx / nrm) * vx + ((double)Dy / nrm) * vy + ((double)Dz / nrm) * vz;
-                acc += theta_mix(pm, frac, nvox, l, mu) * (double)T[e] * phi[rev[e]];
+                const long long Dx = (long long)pos[3 * l] - pos[3 * j], Dy = (long long)pos[3 * l + 1] - pos[3 * j + 1],
+                                Dz = (long long)pos[3 * l + 2] - pos[3 * j + 2];
+                const double inv = 1.0 / sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
+                th = theta_mix(pm, frac, nvox, l, ((double)Dx * vx + (double)Dy * vy + (double)Dz * vz) * inv);
             }
+            acc += th * (double)T[e] * phi[rev[e]];
         }
-    } else {
-        acc = mu0 * (double)Tsun[l];
-        if (multiple)
-            for (long long e = off; e < end; ++e) acc += (double)T[e] * phi[rev[e]];
     }
-    J[l] = acc;
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        const double src = vol ? theta_mix(pm, frac, nvox, l, sx * vx + sy * vy + sz * vz) * (double)Tsun[l]
+                               : mu0 * (double)Tsun[l];
+        J[l] = src + acc;
+    }
 }
 
 __global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, const float *__restrict__ mu_s,
@@ -118,7 +124,7 @@ void launch_gather(Scene &s, hipStream_t st, const double *phi, int scatter_orde
     PhaseMix pm;
     pm.n = s.n_phase;
     for (int i = 0; i < 4; ++i) pm.g[i] = s.hg_g[i];
-    hipLaunchKernelGGL((k_node_J<Real>), dim3((s.N + 255) / 256), dim3(256), 0, st, s.N, s.nvox, s.adj_ptr, s.adj_idx,
+    hipLaunchKernelGGL((k_node_J<Real>), dim3((s.N + 3) / 4), dim3(256), 0, st, s.N, s.nvox, s.adj_ptr, s.adj_idx,
                        s.rev, s.pos, (const Real *)s.T, (const Real *)s.Tsun, phi, pm, s.frac, s.sun_in[0],
                        s.sun_in[1], s.sun_in[2], s.view_u[0], s.view_u[1], s.view_u[2], s.mu0,
                        scatter_order == 1 ? 0 : 1, s.J);

@@ -15,6 +15,7 @@
 namespace sg {
 
 void set_error(const std::string &msg);
+std::string t_last_error();
 
 struct Ctx {
     int device = 0;
@@ -75,13 +76,16 @@ struct Scene {
     // batched arrays (n_lambda > 1, FP32)
     float *q = nullptr;                   // [nnz] phase-cell weights in K layout
     float *bS = nullptr, *bx = nullptr, *by = nullptr;  // [E][n_lambda]
-    float *brho = nullptr;                // [N][n_lambda] (export)
+    float *brho = nullptr;                // [N][n_lambda] node weights
+    float *bsrc = nullptr;                // [N][n_lambda] T_sun (x mu0 on the surface)
+    double *lam_buf = nullptr;            // [36 * n_lambda] per-wavelength norms and scales
 
     // FP64 solve state
     double *x64 = nullptr, *r64 = nullptr;  // [E * n_lambda]
     double *gm_V = nullptr;                 // GMRES basis [(m+1) * E]
     int gm_m = 0;
     double *partial = nullptr;  // block partial sums
+    unsigned *counter = nullptr;  // arrival counter of persistent reductions (self re-arming)
     int n_partial = 0;
     double *scal = nullptr;  // device scalars
     double *J = nullptr;     // [N * n_lambda] node radiance toward the sensor
@@ -92,6 +96,15 @@ struct Scene {
     int last_scatter_order = 0;
     std::mutex mu;
 };
+
+// ---- scene lifecycle (api.cpp) ----
+sg_status create_scene(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Scene &s);
+void free_scene(Scene *s);
+sg_status solve_scene(Scene &s, const sg_solve_opts &o, hipStream_t st, double *radiance, int on_dev,
+                      sg_solve_info *info);
+sg_status check_opts(const sg_solve_opts *opts, sg_solve_opts &o);
+// device bytes a scene reserves (validates the description; *st = its status)
+uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st);
 
 // ---- launchers (defined in the .hip files) ----
 void launch_structure(Scene &s, hipStream_t st);
@@ -105,9 +118,9 @@ template <class Real>
 void launch_qbuild(Scene &s, hipStream_t st, int write_q);
 
 template <class Real>
-void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *partial_out);
+void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *norm_out);
 template <class Real>
-void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x64, double *r64, double *partial_out);
+void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x64, double *r64, double *norm_out);
 template <class Real>
 void launch_apply_imk64(Scene &s, hipStream_t st, const double *v, double *w);
 int spmv_blocks(const Scene &s);
@@ -136,12 +149,16 @@ void launch_gather(Scene &s, hipStream_t st, const double *phi, int scatter_orde
 void launch_trace(Scene &s, hipStream_t st, int kind, const long long *ids, int n, int cap, int *vox, double *dt,
                   int *count);
 
-// batched
-void launch_batched_march_and_weights(Scene &s, hipStream_t st);
-void launch_batched_source(Scene &s, hipStream_t st);
-void launch_spmm(Scene &s, hipStream_t st, const float *S, const float *x, float *y, double *partial, int use_source);
-void launch_batched_residual64(Scene &s, hipStream_t st, const double *x64, double *r64, double *partial);
+// batched wavelengths
+int batched_groups(const Scene &s);
+void launch_bnode_coef(Scene &s, hipStream_t st);
+void launch_spmm(Scene &s, hipStream_t st, int grid, const float *rhs, const float *x, float *y, double *partial);
+void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, double *r64, double *partial);
+void launch_reduce_lam(const double *partial, int nblk, int nl, double *out, hipStream_t st);
+void launch_lam_scale_to_f32(const double *a, const double *sc, int nl, float *b, long long n, hipStream_t st);
+void launch_lam_axpy(double *x, const float *d, const double *sc, int nl, long long n, hipStream_t st);
+void launch_f32_to_64(const float *a, double *b, long long n, hipStream_t st);
+void launch_fill_f32(float *a, long long n, hipStream_t st);
 void launch_batched_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance);
-int spmm_blocks(const Scene &s);
 
 }  // namespace sg

@@ -43,18 +43,30 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
     else if (threadIdx.x < 6) bb[threadIdx.x] = -(1 << 30);
     __syncthreads();
     const long long e0 = sptr[0], e1 = sptr[nl];
-    // bounding box of all end voxels of the block's edges
+    // bounding box of all end voxels of the block's edges: per-thread, then per wave
+    // (butterfly), then one LDS atomic per wave and coordinate
+    int mnx = 1 << 30, mny = 1 << 30, mnz = 1 << 30, mxx = -(1 << 30), mxy = -(1 << 30), mxz = -(1 << 30);
     for (long long e = e0 + threadIdx.x; e < e1; e += kMarchThreads) {
         int vx, vy, vz;
         node_voxel(pos, adj_idx[e], vx, vy, vz);
-        atomicMin(&bb[0], vx); atomicMin(&bb[1], vy); atomicMin(&bb[2], vz);
-        atomicMax(&bb[3], vx); atomicMax(&bb[4], vy); atomicMax(&bb[5], vz);
+        mnx = min(mnx, vx); mny = min(mny, vy); mnz = min(mnz, vz);
+        mxx = max(mxx, vx); mxy = max(mxy, vy); mxz = max(mxz, vz);
     }
     if (threadIdx.x < nl) {
         int vx, vy, vz;
         node_voxel(pos, l0 + threadIdx.x, vx, vy, vz);
-        atomicMin(&bb[0], vx); atomicMin(&bb[1], vy); atomicMin(&bb[2], vz);
-        atomicMax(&bb[3], vx); atomicMax(&bb[4], vy); atomicMax(&bb[5], vz);
+        mnx = min(mnx, vx); mny = min(mny, vy); mnz = min(mnz, vz);
+        mxx = max(mxx, vx); mxy = max(mxy, vy); mxz = max(mxz, vz);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mnx = min(mnx, __shfl_xor(mnx, o, 64)); mny = min(mny, __shfl_xor(mny, o, 64));
+        mnz = min(mnz, __shfl_xor(mnz, o, 64)); mxx = max(mxx, __shfl_xor(mxx, o, 64));
+        mxy = max(mxy, __shfl_xor(mxy, o, 64)); mxz = max(mxz, __shfl_xor(mxz, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&bb[0], mnx); atomicMin(&bb[1], mny); atomicMin(&bb[2], mnz);
+        atomicMax(&bb[3], mxx); atomicMax(&bb[4], mxy); atomicMax(&bb[5], mxz);
     }
     __syncthreads();
     if (e0 == e1) return;

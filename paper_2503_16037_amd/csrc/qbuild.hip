@@ -127,14 +127,18 @@ __global__ __launch_bounds__(64) void k_qbuild(
             bins[lane] = 0ull;
         }
         __syncthreads();
+        // argmax with ties to the lowest index: the index moves only on a strict
+        // increase, and the running maximum (fmax) equals the kept value on ties
         int o0 = 0, o1 = 0;
-        double b0 = 0.0, b1 = 0.0;
+        double b0 = -__builtin_inf(), b1 = -__builtin_inf();
         for (int m = 0; m < d; ++m) {
             const double qx = rx[m], qy = ry[m], qz = rz[m];
             const double v0 = fma(p0z, qz, fma(p0y, qy, p0x * qx));
             const double v1 = fma(p1z, qz, fma(p1y, qy, p1x * qx));
-            if (m == 0 || v0 > b0) { b0 = v0; o0 = m; }
-            if (m == 0 || v1 > b1) { b1 = v1; o1 = m; }
+            o0 = v0 > b0 ? m : o0;
+            o1 = v1 > b1 ? m : o1;
+            b0 = fmax(b0, v0);
+            b1 = fmax(b1, v1);
         }
         if (has0) atomicAdd(&bins[o0], w0);
         if (has1) atomicAdd(&bins[o1], w1);
@@ -144,13 +148,13 @@ __global__ __launch_bounds__(64) void k_qbuild(
             const long long b = off + lane;
             if (surf) {
                 for (int m = 0; m < d; ++m) {
-                    if (kWriteQ) blk[lane * d + m] = (BlkT)Q;
+                    if (kWriteQ) blk[m * d + lane] = (BlkT)Q;
                     else blk[lane * d + m] = (BlkT)(T[off + m] * rl * (Real)Q);
                 }
                 if (!kWriteQ) S[b] = rl * mu0 * tsun * (Real)Q;
                 qsun[b] = (float)Q;
             } else if (a < d) {
-                if (kWriteQ) blk[lane * d + a] = (BlkT)Q;
+                if (kWriteQ) blk[a * d + lane] = (BlkT)Q;  // Q-only output is column-major in the block
                 else blk[lane * d + a] = (BlkT)(T[off + a] * rl * (Real)Q);
             } else {
                 if (!kWriteQ) S[b] = tsun * rl * (Real)Q;

@@ -8,6 +8,8 @@
 // never reads a column index.  Every reduction has a fixed order (wave
 // butterfly, then block, then one final block), so results are bit-identical
 // from run to run.
+#include <algorithm>
+
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -19,78 +21,129 @@ constexpr int kSpmvThreads = 256;
 constexpr int kNodesPerSpmvBlock = kSpmvThreads / 64;
 constexpr int kVecThreads = 256;
 
-// y = S + K x for one wavefront per node; partial[block] = sum |y - x| (FP64).
+// Copy n consecutive elements from global memory to this wavefront's LDS slice
+// with eight loads in flight per lane before the LDS writes.
+template <class T, class U>
+__device__ __forceinline__ void stage_block(U *__restrict__ dst, const T *__restrict__ src, int n, int lane) {
+    constexpr int kU = 8;
+    for (int t0 = lane; t0 < n; t0 += 64 * kU) {
+        T v[kU];
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+            const int t = t0 + j * 64;
+            v[j] = t < n ? src[t] : (T)0;
+        }
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+            const int t = t0 + j * 64;
+            if (t < n) dst[t] = (U)v[j];
+        }
+    }
+}
+
+// Final step of a persistent kernel's norm: the block's partial goes to
+// partial[block]; the last block to arrive sums all partials in block order
+// into *out and re-arms the counter (so no clearing is needed between launches).
+__device__ __forceinline__ void finish_norm(double block_total, double *__restrict__ partial,
+                                            unsigned *__restrict__ counter, double *__restrict__ out) {
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = block_total;
+        __threadfence();
+        const unsigned ticket = atomicAdd(counter, 1u);
+        last = ticket == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        double t = 0.0;
+        for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) t += ((volatile double *)partial)[i];
+        t = block_sum<kSpmvThreads>(t);
+        if (threadIdx.x == 0) {
+            *out = t;
+            *counter = 0u;
+        }
+    }
+}
+
+// y = S + K x, persistent over node groups, one wavefront per node; *out = sum |y - x|.
+// Each wavefront stages its node's block and inputs in its own LDS slice, so no
+// workgroup barrier is needed (a wavefront's LDS operations complete in order).
 template <class Real>
-__global__ __launch_bounds__(kSpmvThreads) void k_spmv(int N, const long long *__restrict__ adj_ptr,
+__global__ __launch_bounds__(kSpmvThreads) void k_spmv(int N, int groups, const long long *__restrict__ adj_ptr,
                                                       const long long *__restrict__ nodeoff,
                                                       const int *__restrict__ rev, const Real *__restrict__ val,
                                                       const Real *__restrict__ S, const Real *__restrict__ x,
-                                                      Real *__restrict__ y, double *__restrict__ partial, int dmax,
-                                                      int stage) {
+                                                      Real *__restrict__ y, double *__restrict__ partial,
+                                                      unsigned *__restrict__ counter, double *__restrict__ out,
+                                                      int dmax, int stage) {
     extern __shared__ unsigned char smem_raw[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int per_wave = stage ? dmax * dmax + dmax : dmax;
     Real *xg = reinterpret_cast<Real *>(smem_raw) + (size_t)w * per_wave;
     Real *blk = xg + dmax;
-    const int l = blockIdx.x * kNodesPerSpmvBlock + w;
-    long long off = 0, base = 0;
-    int d = 0;
-    if (l < N) {
-        off = adj_ptr[l];
-        d = (int)(adj_ptr[l + 1] - off);
-        base = nodeoff[l];
-        if (stage)
-            for (int t = lane; t < d * d; t += 64) blk[t] = val[base + t];
-        if (lane < d) xg[lane] = x[rev[off + lane]];
-    }
-    __syncthreads();
     double r = 0.0;
-    if (lane < d) {
-        Real acc = 0;
-        const Real *row = stage ? blk + lane * d : val + base + (long long)lane * d;
-        for (int m = 0; m < d; ++m) acc += row[m] * xg[m];
-        const long long b = off + lane;
-        const Real yn = S[b] + acc;
-        y[b] = yn;
-        r = fabs((double)yn - (double)x[b]);
+    for (int g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int l = g * kNodesPerSpmvBlock + w;
+        if (l >= N) break;
+        const long long off = adj_ptr[l];
+        const int d = (int)(adj_ptr[l + 1] - off);
+        const long long base = nodeoff[l];
+        if (lane < d) xg[lane] = x[rev[off + lane]];
+        if (stage) stage_block(blk, val + base, d * d, lane);
+        __builtin_amdgcn_wave_barrier();
+        if (lane < d) {
+            Real acc = 0;
+            const Real *row = stage ? blk + lane * d : val + base + (long long)lane * d;
+            for (int m = 0; m < d; ++m) acc += row[m] * xg[m];
+            const long long b = off + lane;
+            const Real yn = S[b] + acc;
+            y[b] = yn;
+            r += fabs((double)yn - (double)x[b]);
+        }
+        __builtin_amdgcn_wave_barrier();
     }
     const double t = block_sum<kSpmvThreads>(r);
-    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+    finish_norm(t, partial, counter, out);
 }
 
-// r = S - x + K x in FP64 (K values promoted); partial[block] = sum |r|.
+// r = S - x + K x in FP64 (K values promoted), persistent; *out = sum |r|.
 template <class Real>
-__global__ __launch_bounds__(kSpmvThreads) void k_residual64(int N, const long long *__restrict__ adj_ptr,
+__global__ __launch_bounds__(kSpmvThreads) void k_residual64(int N, int groups, const long long *__restrict__ adj_ptr,
                                                             const long long *__restrict__ nodeoff,
                                                             const int *__restrict__ rev, const Real *__restrict__ val,
                                                             const Real *__restrict__ S, const double *__restrict__ x,
                                                             double *__restrict__ r, double *__restrict__ partial,
-                                                            int dmax) {
+                                                            unsigned *__restrict__ counter, double *__restrict__ out,
+                                                            int dmax, int stage) {
     extern __shared__ unsigned char smem_raw[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double *xg = reinterpret_cast<double *>(smem_raw) + (size_t)w * dmax;
-    const int l = blockIdx.x * kNodesPerSpmvBlock + w;
-    long long off = 0, base = 0;
-    int d = 0;
-    if (l < N) {
-        off = adj_ptr[l];
-        d = (int)(adj_ptr[l + 1] - off);
-        base = nodeoff[l];
-        if (lane < d) xg[lane] = x[rev[off + lane]];
-    }
-    __syncthreads();
+    const size_t per_wave = (size_t)dmax * sizeof(double) + (stage ? (size_t)dmax * dmax * sizeof(Real) : 0);
+    double *xg = reinterpret_cast<double *>(smem_raw + w * per_wave);
+    Real *blk = reinterpret_cast<Real *>(xg + dmax);
     double a = 0.0;
-    if (lane < d) {
-        double acc = 0.0;
-        const Real *row = val + base + (long long)lane * d;
-        for (int m = 0; m < d; ++m) acc += (double)row[m] * xg[m];
-        const long long b = off + lane;
-        const double rb = ((double)S[b] - x[b]) + acc;
-        r[b] = rb;
-        a = fabs(rb);
+    for (int g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int l = g * kNodesPerSpmvBlock + w;
+        if (l >= N) break;
+        const long long off = adj_ptr[l];
+        const int d = (int)(adj_ptr[l + 1] - off);
+        const long long base = nodeoff[l];
+        if (lane < d) xg[lane] = x[rev[off + lane]];
+        if (stage) stage_block(blk, val + base, d * d, lane);
+        __builtin_amdgcn_wave_barrier();
+        if (lane < d) {
+            double acc = 0.0;
+            const Real *row = stage ? blk + lane * d : val + base + (long long)lane * d;
+            for (int m = 0; m < d; ++m) acc += (double)row[m] * xg[m];
+            const long long b = off + lane;
+            const double rb = ((double)S[b] - x[b]) + acc;
+            r[b] = rb;
+            a += fabs(rb);
+        }
+        __builtin_amdgcn_wave_barrier();
     }
     const double t = block_sum<kSpmvThreads>(a);
-    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+    finish_norm(t, partial, counter, out);
 }
 
 // w = v - K v in FP64.
@@ -228,23 +281,33 @@ inline int grid_for(long long n) {
 
 int spmv_blocks(const Scene &s) { return (s.N + kNodesPerSpmvBlock - 1) / kNodesPerSpmvBlock; }
 
+// persistent grid: at most 8 workgroups per compute unit
+static int persistent_grid(const Scene &s) { return std::max(1, std::min(spmv_blocks(s), 256 * 8)); }
+
 template <class Real>
-void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *partial_out) {
+void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *out) {
     size_t shm = (size_t)kNodesPerSpmvBlock * (s.dmax * s.dmax + s.dmax) * sizeof(Real);
     int stage = 1;
     if (shm > 64 * 1024) {  // block does not fit: read rows straight from memory
         stage = 0;
         shm = (size_t)kNodesPerSpmvBlock * s.dmax * sizeof(Real);
     }
-    hipLaunchKernelGGL((k_spmv<Real>), dim3(spmv_blocks(s)), dim3(kSpmvThreads), shm, st, s.N, s.adj_ptr, s.nodeoff,
-                       s.rev, (const Real *)s.val, S, x, y, partial_out, s.dmax, stage);
+    hipLaunchKernelGGL((k_spmv<Real>), dim3(persistent_grid(s)), dim3(kSpmvThreads), shm, st, s.N, spmv_blocks(s),
+                       s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x, y, s.partial, s.counter, out, s.dmax,
+                       stage);
 }
 
 template <class Real>
-void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x64, double *r64, double *partial_out) {
-    const size_t shm = (size_t)kNodesPerSpmvBlock * s.dmax * sizeof(double);
-    hipLaunchKernelGGL((k_residual64<Real>), dim3(spmv_blocks(s)), dim3(kSpmvThreads), shm, st, s.N, s.adj_ptr,
-                       s.nodeoff, s.rev, (const Real *)s.val, S, x64, r64, partial_out, s.dmax);
+void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x64, double *r64, double *out) {
+    size_t shm = (size_t)kNodesPerSpmvBlock * s.dmax * (sizeof(double) + (size_t)s.dmax * sizeof(Real));
+    int stage = 1;
+    if (shm > 64 * 1024) {
+        stage = 0;
+        shm = (size_t)kNodesPerSpmvBlock * s.dmax * sizeof(double);
+    }
+    hipLaunchKernelGGL((k_residual64<Real>), dim3(persistent_grid(s)), dim3(kSpmvThreads), shm, st, s.N,
+                       spmv_blocks(s), s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x64, r64, s.partial,
+                       s.counter, out, s.dmax, stage);
 }
 
 template <class Real>

@@ -91,6 +91,7 @@ def lib():
                 "sg_scene_create": (I32, [P, P, P, P]),
                 "sg_scene_destroy": (I32, [P]),
                 "sg_scene_sizes": (I32, [P, P, P, P, P, P, P]),
+                "sg_scene_reservation": (I32, [P, P]),
                 "sg_solve": (I32, [P, P, P, P, I32, P]),
                 "sg_export_csr": (I32, [P, I32, P, P, P]),
                 "sg_export_vector": (I32, [P, I32, P]),
@@ -289,6 +290,15 @@ class Scene:
         return vox, dt, cnt
 
 
+def scene_reservation(scene) -> int:
+    """Device bytes a scene would reserve (host-side validation only)."""
+    keep: list = []
+    desc = make_desc(scene, keep)
+    b = C.c_uint64()
+    _check(lib().sg_scene_reservation(C.byref(desc), C.byref(b)))
+    return b.value
+
+
 class Server:
     """Continuous-batching server (sg_server_*)."""
 
@@ -339,6 +349,10 @@ class Server:
         d = info.as_dict()
         d["status"] = st
         return rad.reshape(shp), d
+
+    @staticmethod
+    def reservation(scene) -> int:
+        return scene_reservation(scene)
 
     def latencies(self, cap=100000):
         ms = np.zeros(cap, np.float64)

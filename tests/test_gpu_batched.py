@@ -1,0 +1,99 @@
+"""Batched wavelengths (one graph, one set of phase cells, many absorption multipliers).
+
+Every wavelength must match the FP64 oracle run with mu_a scaled by its multiplier
+(1e-4 relative per pixel) and the same wavelength solved alone through the
+single-wavelength path.  Wavelength counts cover every lane-tile shape of the SpMM
+(several nodes per wavefront, one node per wavefront, more than 64 wavelengths).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_16037_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2503_16037_amd import sgrt
+    c = sgrt.Context(0)
+    yield c
+    c.close()
+
+
+def rel_err(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(np.abs(np.asarray(b)), 1e-300)
+
+
+@pytest.mark.parametrize("n_lambda", [3, 17, 64, 70])
+def test_batched_matches_oracle_per_wavelength(ctx, n_lambda):
+    from paper_2503_16037_amd import sgrt
+    sc = scenes.make_batched(nx=14, ny=12, nz=8, n_lambda=n_lambda)
+    say("batched scene", sc.name)
+    with sgrt.Scene(ctx, sc) as g:
+        rad, info = g.solve(timing=True)
+        assert rad.shape == (n_lambda, sc.ny, sc.nx)
+        assert info["converged"] == 1
+        lams = sorted(set([0, n_lambda - 1, int(np.argmin(sc.abs_scale)), int(np.argmax(sc.abs_scale))]))
+        for k in lams:
+            ora = oracle.run(sc, abs_scale=float(sc.abs_scale[k]))
+            err = rel_err(rad[k], ora["radiance"])
+            say("  lambda", k, "scale", float(sc.abs_scale[k]), "max rel err", err.max())
+            assert err.max() < 1e-4
+        phi = g.export_vector("phi")
+        S = g.export_vector("source")
+        ora = oracle.run(sc, abs_scale=float(sc.abs_scale[lams[-1]]))
+        k = lams[-1]
+        m = ora["S"] > 1e-30
+        assert rel_err(S[k][m], ora["S"][m]).max() < 3e-5
+        assert np.abs(phi[k] - ora["phi"]).max() < 1e-5 * ora["phi"].max()
+        _, _, val = g.export_csr(lam=k, cols=False)
+        big = ora["val"] > 1e-9 * ora["val"].max()
+        assert rel_err(val[big], ora["val"][big]).max() < 5e-5
+
+
+def test_batched_equals_single_wavelength_solves(ctx):
+    from paper_2503_16037_amd import sgrt
+    sc = scenes.make_batched(nx=16, ny=16, nz=8, n_lambda=6)
+    say("batched vs single", sc.name)
+    with sgrt.Scene(ctx, sc) as g:
+        rad, _ = g.solve()
+    for k in range(sc.n_lambda):
+        one = sc.with_(abs_scale=sc.abs_scale[k:k + 1].copy())
+        with sgrt.Scene(ctx, one) as g1:
+            r1, _ = g1.solve()
+        assert rel_err(rad[k], r1).max() < 2e-5
+
+
+def test_batched_single_scatter(ctx):
+    from paper_2503_16037_amd import sgrt
+    sc = scenes.make_batched(nx=10, ny=10, nz=6, n_lambda=5)
+    say("batched single scatter", sc.name)
+    with sgrt.Scene(ctx, sc) as g:
+        rad, _ = g.solve(scatter_order=1)
+    for k in (0, 4):
+        ora = oracle.run(sc, abs_scale=float(sc.abs_scale[k]), scatter_order=1)
+        assert rel_err(rad[k], ora["radiance"]).max() < 1e-4
+
+
+def test_batched_full_size_sampled_wavelengths(ctx):
+    from paper_2503_16037_amd import sgrt
+    sc = scenes.make_batched()
+    say("batched full size", sc.name, sc.n_edges, sc.nnz())
+    with sgrt.Scene(ctx, sc) as g:
+        rad, info = g.solve(timing=True)
+        say("  info", info)
+        assert info["converged"] == 1
+    for k in (int(np.argmin(sc.abs_scale)), int(np.argmax(sc.abs_scale)), 17):
+        ora = oracle.run(sc, abs_scale=float(sc.abs_scale[k]), want_matrix=False)
+        err = rel_err(rad[k], ora["radiance"])
+        say("  lambda", k, "max / p99 rel err", err.max(), np.percentile(err, 99))
+        assert err.max() < 1e-4

@@ -1,0 +1,157 @@
+"""Serving (sg_server_*): continuous batching of scenes of uneven size.
+
+Each served result must be bit-identical to the same scene solved alone
+through the plain one-scene path, whatever else is on the device; scenes
+larger than the budget are rejected; a full queue answers SG_E_BUSY; every
+finished request records its arrival-to-completion latency.
+"""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_16037_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2503_16037_amd import sgrt
+    c = sgrt.Context(0)
+    yield c
+    c.close()
+
+
+def small_stream(n, max_voxels=6000):
+    return [scenes.make_served(i, max_voxels=max_voxels) for i in range(n)]
+
+
+def test_served_results_equal_solo_solves(ctx):
+    from paper_2503_16037_amd import sgrt
+    stream = small_stream(10)
+    say("served mix", [s.name for s in stream])
+    solo = []
+    for sc in stream:
+        with sgrt.Scene(ctx, sc) as g:
+            r, _ = g.solve()
+            solo.append(np.asarray(r).reshape(sc.n_lambda, sc.ny, sc.nx))
+    srv = sgrt.Server(ctx, max_resident=4, queue_cap=64, n_streams=4)
+    try:
+        tickets = [srv.submit(sc) for sc in stream]
+        assert all(t is not None for t in tickets)
+        out = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    for sc, (rad, info), ref in zip(stream, out, solo):
+        assert info["status"] == 0 and info["converged"] == 1
+        assert np.array_equal(rad, ref), sc.name
+    # spot-check two against the oracle
+    for k in (0, 3):
+        sc = stream[k]
+        ora = oracle.run(sc, abs_scale=float(sc.abs_scale[0]))
+        err = np.abs(out[k][0][0] - ora["radiance"]) / np.abs(ora["radiance"])
+        assert err.max() < 1e-4
+
+
+def test_served_mix_with_concurrent_arrivals(ctx):
+    from paper_2503_16037_amd import sgrt
+    stream = small_stream(8, max_voxels=4000)
+    say("concurrent arrivals")
+    srv = sgrt.Server(ctx, max_resident=3, queue_cap=64, n_streams=2)
+    tickets = [None] * len(stream)
+
+    def submitter():
+        for i, sc in enumerate(stream):
+            tickets[i] = srv.submit(sc)
+            time.sleep(0.002)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    res = [srv.wait(t) for t in tickets]
+    lat = srv.latencies()
+    srv.close()
+    assert len(lat) == len(stream) and np.all(lat > 0)
+    for sc, (rad, info) in zip(stream, res):
+        with sgrt.Scene(ctx, sc) as g:
+            ref, _ = g.solve()
+        assert np.array_equal(rad.reshape(np.asarray(ref).shape), np.asarray(ref))
+
+
+def test_over_budget_scene_is_rejected():
+    from paper_2503_16037_amd import sgrt
+    say("over budget")
+    with sgrt.Context(0, hbm_budget_bytes=8 << 20) as small:
+        srv = sgrt.Server(small, max_resident=2, queue_cap=4, n_streams=1)
+        try:
+            big = scenes.make_plume(nx=32, ny=32, nz=16)
+            with pytest.raises(sgrt.SgError) as e:
+                srv.submit(big)
+            assert e.value.status == sgrt.SG_E_NOMEM
+            tiny = scenes.make_random_small(0, nx=3, ny=3, nz=2, kscale=2.0)
+            t = srv.submit(tiny)
+            rad, info = srv.wait(t)
+            assert info["status"] == 0
+        finally:
+            srv.close()
+
+
+def test_budget_serialises_scenes_that_fit_one_at_a_time():
+    from paper_2503_16037_amd import sgrt
+    sc = scenes.make_plume(nx=20, ny=20, nz=10)
+    say("budget for one scene at a time")
+    with sgrt.Context(0) as c0:
+        with sgrt.Scene(c0, sc) as g:
+            need = g.sizes["device_bytes"]
+            ref, _ = g.solve()
+    with sgrt.Context(0, hbm_budget_bytes=int(need * 1.5)) as c1:
+        srv = sgrt.Server(c1, max_resident=4, queue_cap=8, n_streams=2)
+        try:
+            ts = [srv.submit(sc) for _ in range(4)]
+            for t in ts:
+                rad, info = srv.wait(t)
+                assert info["status"] == 0
+                assert np.array_equal(rad[0], ref)
+        finally:
+            srv.close()
+
+
+def test_queue_full_reports_busy(ctx):
+    from paper_2503_16037_amd import sgrt
+    say("queue back-pressure")
+    sc = scenes.make_plume(nx=48, ny=48, nz=24)
+    srv = sgrt.Server(ctx, max_resident=1, queue_cap=2, n_streams=1)
+    try:
+        got = [srv.submit(sc) for _ in range(6)]
+        assert any(t is None for t in got)
+        for t in got:
+            if t is not None:
+                _, info = srv.wait(t)
+                assert info["status"] == 0
+    finally:
+        srv.close()
+
+
+def test_reservation_estimate_matches_created_scene(ctx):
+    """The server admits by the reservation a scene will make; it must equal what the
+    scene actually reserves (single and batched wavelengths)."""
+    from paper_2503_16037_amd import sgrt
+    for sc in (scenes.make_random_small(1, nx=5, ny=4, nz=3, two_phase=True, kscale=2.0),
+               scenes.make_batched(nx=10, ny=9, nz=6, n_lambda=7)):
+        with sgrt.Scene(ctx, sc) as g:
+            created = g.sizes["device_bytes"]
+        srv = sgrt.Server(ctx, max_resident=1, queue_cap=2, n_streams=1)
+        try:
+            est = srv.reservation(sc)
+        finally:
+            srv.close()
+        assert est == created, (sc.name, est, created)
