@@ -149,20 +149,26 @@ typedef struct sg_solve_opts {
     int32_t precision;     /* SG_FP32: march, matrix and sweeps in FP32, residual and pixel
                               accumulation in FP64; SG_FP64: everything in FP64 */
     int32_t solver;        /* SG_SOLVER_AUTO: Neumann sweeps, GMRES if they stall */
-    double rtol;           /* target of ||S - (I - K) phi||_1 / ||S||_1 (<= 0: 1e-6 FP32, 1e-12 FP64) */
+    double rtol;           /* target of the per-edge relative residual max_e |r_e| / (|phi_e| + 1e-30),
+                              r = S - (I - K) phi in FP64; it bounds the error of every edge,
+                              including edges many orders of magnitude darker than the mean
+                              (<= 0: 1e-6 FP32, 1e-12 FP64) */
     int32_t max_sweeps;    /* cap on matrix sweeps of all kinds (<= 0: 2000) */
     int32_t gmres_restart; /* GMRES(m) restart length, 2..64 (<= 0: 32) */
     int32_t scatter_order; /* 0: multiple scattering; 1: single scattering only (no solve) */
     int32_t build_col_idx; /* 1: also materialise the CSR column index array */
     int32_t timing;        /* 1: per-stage HIP-event timings into sg_solve_info */
+    int32_t flags;         /* SG_NO_GRAPHS: launch sweep chunks one by one instead of replaying
+                              captured HIP graphs; SG_NO_AUTOTUNE: default launch shapes */
 } sg_solve_opts;
+enum { SG_NO_GRAPHS = 1, SG_NO_AUTOTUNE = 2 };
 
 typedef struct sg_solve_info {
     int32_t converged;      /* 1 if every wavelength reached rtol */
     int32_t sweeps;         /* matrix sweeps (FP32 + FP64 residual + GMRES products) */
     int32_t gmres_used;     /* 1 if GMRES ran for any wavelength */
     int32_t refinements;    /* FP64 residual evaluations */
-    double rel_residual;    /* max over wavelengths of the final FP64 relative residual */
+    double rel_residual;    /* max over wavelengths of the final per-edge relative residual (see rtol) */
     double ms_structure;    /* timings (timing = 1): CSR structure from the adjacency */
     double ms_march;        /* edge and sun transmittances */
     double ms_qbuild;       /* phase cells, matrix values and source */

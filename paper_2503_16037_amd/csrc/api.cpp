@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -26,6 +28,14 @@ void set_error(const std::string &msg) { t_err = msg; }
 std::string t_last_error() { return t_err; }
 
 namespace {
+
+bool sg_log() {
+    static const bool on = [] {
+        const char *v = std::getenv("SG_LOG");
+        return v && v[0] && v[0] != '0';
+    }();
+    return on;
+}
 
 sg_status fail(sg_status st, const std::string &msg) {
     set_error(msg);
@@ -201,21 +211,28 @@ void fill_default_opts(sg_solve_opts &o) {
     o.abi_version = SG_ABI_VERSION;
 }
 
-// HIP-event timing of the stages of one solve.
-struct Timing {
+// Launch policy and HIP-event timing of one solve.  With timing on, sweeps are
+// launched one by one with an event pair around each sweep kernel; otherwise
+// chunks of sweeps replay captured graphs (unless disabled).
+struct Exec {
     bool on = false;
+    bool graphs = true, autotune = true;
     hipStream_t st = nullptr;
     std::vector<hipEvent_t> ev;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> spmv;
-    hipEvent_t mark() {
+    hipEvent_t fresh() {  // an event for a launcher to record
         hipEvent_t e = nullptr;
         if (!on) return e;
         (void)hipEventCreate(&e);
-        (void)hipEventRecord(e, st);
         ev.push_back(e);
         return e;
     }
-    ~Timing() {
+    hipEvent_t mark() {
+        hipEvent_t e = fresh();
+        if (e) (void)hipEventRecord(e, st);
+        return e;
+    }
+    ~Exec() {
         for (auto e : ev) (void)hipEventDestroy(e);
     }
     double between(hipEvent_t a, hipEvent_t b) {
@@ -240,6 +257,7 @@ sg_status ensure_real(Scene &s) {
         }
     };
     if (s.real_bytes) {
+        clear_graphs(s);  // captured chunks hold the old buffers
         const size_t ob = (size_t)s.real_bytes;
         drop(s.tau_s, s.E * ob); drop(s.tau_a, s.E * ob); drop(s.T, s.E * ob);
         drop(s.tsun_s, s.N * ob); drop(s.tsun_a, s.N * ob); drop(s.Tsun, s.N * ob); drop(s.rho, s.N * ob);
@@ -279,49 +297,82 @@ struct SolveStats {
     double rel = 0.0;
 };
 
-// FP32/FP64 Neumann sweeps x <- rhs + K x from x = 0 until the monitored
-// update ||x_new - x||_1 <= stop, or the sweep ratio shows a stall (>= 0.95 or
-// growth).  Returns 1 on a stall.  The solution ends in *xfinal.
+// FP32/FP64 Neumann sweeps x <- rhs + K x from x = 0.  Every sweep yields two measures
+// of its update dx: the L1 norm, which shrinks at least by the factor max_a T_a rho < 1
+// per sweep and so gives the sweep ratio q, and the largest per-edge relative update
+// max |dx_e| / |x_e|, which bounds the error of every edge, bright or deep in shadow.
+// relative != 0: stop once the relative measure is (predicted) below stop; otherwise
+// once the L1 update is below stop times the first one (sum |rhs|).  A ratio q >= 0.95
+// or growth after three sweeps, with the relative measure not falling either, is a
+// stall.  The solution ends in xa.
 template <class Real>
-sg_status neumann(Scene &s, hipStream_t st, Timing &tm, const Real *rhs, Real *&xa, Real *&xb, double stop,
-                  int max_sweeps, SolveStats &ss, int &stalled) {
+sg_status neumann(Scene &s, hipStream_t st, Exec &tm, const Real *rhs, Real *&xa, Real *&xb, int relative,
+                  double stop, int max_sweeps, SolveStats &ss, int &stalled) {
     Ctx *ctx = s.ctx;
     launch_fill<Real>(xa, (Real)0, s.E, st);
-    std::vector<double> hist;
+    const int grid = spmv_grid<Real>(s, st, rhs, xa, xb, tm.autotune);
+    std::vector<double> l1, rel;
     int chunk = 2;
     stalled = 0;
     double host[64];
+    double *meas = s.scal + 128;  // [32][2] measures of the chunk's sweeps
     while (true) {
         chunk = std::max(1, std::min(chunk, 32));
-        for (int c = 0; c < chunk; ++c) {
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (tm.on) e0 = tm.mark();
-            launch_spmv<Real>(s, st, rhs, xa, xb, s.scal + 16 + c);
-            if (tm.on) { e1 = tm.mark(); tm.spmv.push_back({e0, e1}); }
-            std::swap(xa, xb);
-            ++ss.sweeps;
+        if (tm.on) {
+            for (int c = 0; c < chunk; ++c) {
+                hipEvent_t e0 = tm.mark(), e1 = tm.fresh();
+                launch_spmv<Real>(s, st, rhs, xa, xb, meas + 2 * c, grid, e1);
+                tm.spmv.push_back({e0, e1});
+                std::swap(xa, xb);
+            }
+        } else {
+            const GraphKey key{1, (uintptr_t)chunk, (uintptr_t)rhs, (uintptr_t)xa, (uintptr_t)xb, (uintptr_t)grid,
+                               sizeof(Real), 0};
+            Real *a0 = xa, *b0 = xb;
+            SG_TRY(run_chunk(s, st, key, tm.graphs, [&]() {
+                Real *a = a0, *b = b0;
+                for (int c = 0; c < chunk; ++c) {
+                    launch_spmv<Real>(s, st, rhs, a, b, meas + 2 * c, grid, nullptr);
+                    std::swap(a, b);
+                }
+            }));
+            if (chunk & 1) std::swap(xa, xb);
         }
+        ss.sweeps += chunk;
         SG_HIP(hipGetLastError());
-        SG_TRY(read_scalars(s, st, s.scal + 16, host, chunk));
-        for (int c = 0; c < chunk; ++c) hist.push_back(host[c]);
-        const double r = hist.back();
-        if (!std::isfinite(r)) { stalled = 1; break; }
-        double q = 0.5;
-        if (hist.size() >= 2) q = r / hist[hist.size() - 2];
-        // r is the residual of the previous iterate; the current one's is about q r
-        if (r <= stop || (hist.size() >= 2 && q < 0.9 && q * r <= 0.5 * stop)) break;
+        SG_TRY(read_scalars(s, st, meas, host, 2 * chunk));
+        for (int c = 0; c < chunk; ++c) {
+            l1.push_back(host[2 * c]);
+            rel.push_back(host[2 * c + 1]);
+        }
+        if (!relative && l1.size() == (size_t)chunk) stop *= l1[0];  // first sweep from 0: sum |rhs|
+        const size_t k = l1.size();
+        const double r = relative ? rel.back() : l1.back();
+        if (sg_log())
+            fprintf(stderr, "[sgrt] sweeps %d chunk %d: L1 update %.3e, max relative %.3e (stop %.3e)\n", ss.sweeps,
+                    chunk, l1.back(), rel.back(), stop);
+        if (!std::isfinite(l1.back()) || !std::isfinite(rel.back())) { stalled = 1; break; }
+        const double q = k >= 2 && l1[k - 2] > 0 ? l1.back() / l1[k - 2] : 0.5;
+        // the measured update belongs to the previous iterate; the current one's is about q r
+        const double qr = relative && k >= 2 && rel[k - 2] > 0 ? std::max(q, rel.back() / rel[k - 2]) : q;
+        if (r <= stop || (k >= 2 && qr < 0.9 && qr * r <= 0.5 * stop)) break;
         if (ss.sweeps >= max_sweeps) break;
-        if (hist.size() >= 3 && (q >= 0.95 || q > 1.0)) { stalled = 1; break; }
-        q = std::min(std::max(q, 1e-12), 0.95);
-        const double need = std::log(stop / r) / std::log(q);
-        chunk = (int)std::ceil(std::max(1.0, need));
+        // a stall: neither measure still falls (the L1 update alone flattens once it
+        // reaches rounding while dark edges still converge)
+        const double q2 = k >= 2 && rel[k - 2] > 0 ? rel.back() / rel[k - 2] : 0.0;
+        if (k >= 3 && q >= 0.95 && (!relative || q2 >= 0.95)) { stalled = 1; break; }
+        // sweeps still needed at the asymptotic rate: the smaller ratio (the relative one is
+        // near 1 until light has reached the dark edges, the L1 one once it hits rounding)
+        const double qa = relative && q2 > 0 ? std::min(q, q2) : q;
+        const double qc = std::min(std::max(qa, 1e-12), 0.95);
+        chunk = (int)std::ceil(std::max(1.0, std::log(stop / r) / std::log(qc)));
     }
     return SG_OK;
 }
 
 template <class Real>
-sg_status gmres64(Scene &s, hipStream_t st, Timing &tm, const Real *S, double nS1, double rtol, int m,
-                  int max_sweeps, SolveStats &ss) {
+sg_status gmres64(Scene &s, hipStream_t st, Exec &tm, const Real *S, double rtol, int m, int max_sweeps,
+                  SolveStats &ss) {
     Ctx *ctx = s.ctx;
     const int64_t E = s.E;
     if (!s.gm_V || s.gm_m < m) {
@@ -342,9 +393,9 @@ sg_status gmres64(Scene &s, hipStream_t st, Timing &tm, const Real *S, double nS
         launch_residual64<Real>(s, st, S, s.x64, s.r64, s.scal);
         ++ss.sweeps;
         ++ss.refinements;
-        double r1;
-        SG_TRY(read_scalars(s, st, s.scal, &r1, 1));
-        ss.rel = r1 / nS1;
+        double m2[2];
+        SG_TRY(read_scalars(s, st, s.scal, m2, 2));
+        ss.rel = m2[1];  // max over edges of |r| / |x|
         if (ss.rel <= rtol || ss.sweeps >= max_sweeps) break;
         launch_dot_multi(s.r64, E, 1, s.r64, E, s.partial, nbv, s.scal, st);
         double beta2;
@@ -408,7 +459,7 @@ sg_status gmres64(Scene &s, hipStream_t st, Timing &tm, const Real *S, double nS
 }
 
 template <class Real>
-sg_status solve_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Timing &tm, SolveStats &ss) {
+sg_status solve_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Exec &tm, SolveStats &ss) {
     Ctx *ctx = s.ctx;
     const int64_t E = s.E;
     const double rtol = o.rtol > 0 ? o.rtol : (sizeof(Real) == 4 ? 1e-6 : 1e-12);
@@ -428,8 +479,9 @@ sg_status solve_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Timing 
     if (!use_gmres) {
         Real *xa = (Real *)s.x, *xb = (Real *)s.y;
         int stalled = 0;
-        const double floor_rel = sizeof(Real) == 4 ? 2e-7 : 1e-15;
-        SG_TRY(neumann<Real>(s, st, tm, S, xa, xb, std::max(0.3 * rtol, floor_rel) * nS1, max_sweeps, ss, stalled));
+        // per-edge relative updates settle at a few units of rounding: never ask for less
+        const double floor_rel = sizeof(Real) == 4 ? 4e-6 : 1e-14;
+        SG_TRY(neumann<Real>(s, st, tm, S, xa, xb, 1, std::max(0.3 * rtol, floor_rel), max_sweeps, ss, stalled));
         launch_to64<Real>(xa, s.x64, E, st);
         if (stalled && o.solver == SG_SOLVER_AUTO) use_gmres = 1;
         // FP64 residual and iterative refinement
@@ -437,23 +489,24 @@ sg_status solve_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Timing 
             launch_residual64<Real>(s, st, S, s.x64, s.r64, s.scal);
             ++ss.sweeps;
             ++ss.refinements;
-            double r1;
-            SG_TRY(read_scalars(s, st, s.scal, &r1, 1));
-            ss.rel = r1 / nS1;
+            double m2[2];
+            SG_TRY(read_scalars(s, st, s.scal, m2, 2));
+            ss.rel = m2[1];  // max over edges of |r| / |x|
+            if (sg_log()) fprintf(stderr, "[sgrt] FP64 residual after %d sweeps: %.3e\n", ss.sweeps, ss.rel);
             if (ss.rel <= rtol) { ss.converged = 1; break; }
-            if (ss.sweeps >= max_sweeps) break;
-            // correction (I - K) d = r by sweeps in the working precision, with r scaled to
-            // the magnitude of S so that it stays well inside the FP32 range
-            const double sc = nS1 / r1;
+            if (ss.sweeps >= max_sweeps || !std::isfinite(ss.rel)) break;
+            // correction (I - K) d = r by sweeps in the working precision; r / rel is at most
+            // |x| per edge, which keeps it well inside the FP32 range
+            const double sc = 1.0 / ss.rel;
             Real *crhs = (Real *)s.c_rhs, *c0 = (Real *)s.c_a, *c1 = (Real *)s.c_b;
             launch_scaled_to_real<Real>(s.r64, sc, crhs, E, st);
             int stalled2 = 0;
-            SG_TRY(neumann<Real>(s, st, tm, crhs, c0, c1, std::max(1e-5, floor_rel) * nS1, max_sweeps, ss, stalled2));
+            SG_TRY(neumann<Real>(s, st, tm, crhs, c0, c1, 0, std::max(1e-5, floor_rel), max_sweeps, ss, stalled2));
             launch_axpy_real_to64<Real>(s.x64, c0, 1.0 / sc, E, st);
             if (stalled2 && o.solver == SG_SOLVER_AUTO) use_gmres = 1;
         }
     }
-    if (use_gmres) SG_TRY(gmres64<Real>(s, st, tm, S, nS1, rtol, m, max_sweeps, ss));
+    if (use_gmres) SG_TRY(gmres64<Real>(s, st, tm, S, rtol, m, max_sweeps, ss));
     SG_HIP(hipGetLastError());
     return SG_OK;
 }
@@ -463,8 +516,10 @@ sg_status solve_single(Scene &s, const sg_solve_opts &o, hipStream_t st, double 
                        sg_solve_info *info) {
     Ctx *ctx = s.ctx;
     SG_TRY(ensure_real<Real>(s));
-    Timing tm;
+    Exec tm;
     tm.on = o.timing != 0;
+    tm.graphs = !(o.flags & SG_NO_GRAPHS) && !tm.on;
+    tm.autotune = !(o.flags & SG_NO_AUTOTUNE);
     tm.st = st;
     const float scale = s.abs_scale.empty() ? 1.0f : s.abs_scale[0];
     hipEvent_t e0 = tm.mark();
@@ -531,40 +586,61 @@ sg_status solve_single(Scene &s, const sg_solve_opts &o, hipStream_t st, double 
 
 
 // Neumann sweeps for all wavelengths at once: x <- rhs + K x (rhs = NULL: the solar
-// source built on the fly).  Each wavelength stops being monitored once its update
-// falls below stop_rel * norm[lambda]; stall = a monitored wavelength whose sweep
-// ratio reaches 0.95.  The first sweep from x = 0 yields sum |rhs| per wavelength.
-sg_status neumann_batched(Scene &s, hipStream_t st, Timing &tm, const float *rhs, float *&xa, float *&xb,
-                          double stop_rel, int max_sweeps, SolveStats &ss, std::vector<double> &norm0,
-                          int &stalled) {
+// source built on the fly), with the two measures of the single-wavelength sweeps per
+// wavelength (L1 update for the ratio and the stall test, largest per-edge relative
+// update for the stop when relative != 0, else L1 below stop times the first sweep's).
+// A wavelength is done once its stop is met or predicted; stall = a wavelength not done
+// whose L1 ratio (and relative ratio, when that decides the stop) reaches 0.95.  Only the first sweep and the last two of each chunk
+// compute measures.
+sg_status neumann_batched(Scene &s, hipStream_t st, Exec &tm, const float *rhs, float *&xa, float *&xb,
+                          int relative, double stop, int max_sweeps, SolveStats &ss, int &stalled) {
     Ctx *ctx = s.ctx;
     const int nl = s.n_lambda;
     const long long n = (long long)s.E * nl;
-    const int grid = std::max(1, std::min({batched_groups(s), 2048, s.n_partial / nl}));
     launch_fill_f32(xa, n, st);
-    std::vector<double> host((size_t)32 * nl), prev(nl, -1.0), last(nl, 0.0);
+    const int grid = spmm_grid(s, st, xa, xb, tm.autotune);
+    std::vector<double> host((size_t)64 * nl);
+    std::vector<double> l1p(nl, -1.0), l1(nl, 0.0), relp(nl, -1.0), rel(nl, 0.0), l1first(nl, 0.0);
     std::vector<int> done(nl, 0);
-    norm0.assign(nl, 0.0);
-    int chunk = 1, first = 1;
+    int chunk = 3, first = 1;  // two measured sweeps after the first give a ratio
     stalled = 0;
-    double *hist = s.lam_buf + 4 * nl;  // [32][nl]
+    double *hist = s.lam_buf + 4 * nl;  // [32][nl][2]
     while (true) {
         chunk = std::max(1, std::min(chunk, 32));
-        for (int c = 0; c < chunk; ++c) {
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (tm.on) e0 = tm.mark();
-            launch_spmm(s, st, grid, rhs, xa, xb, s.partial);
-            if (tm.on) { e1 = tm.mark(); tm.spmv.push_back({e0, e1}); }
-            launch_reduce_lam(s.partial, grid, nl, hist + (size_t)c * nl, st);
-            std::swap(xa, xb);
-            ++ss.sweeps;
+        const int c_mon = std::max(0, chunk - 2);
+        auto sweep = [&](int c, const float *a, float *b, hipEvent_t after) {
+            const int mon = (first && c == 0) || c >= c_mon;
+            launch_spmm(s, st, grid, rhs, a, b, mon);
+            if (after) (void)hipEventRecord(after, st);
+            if (mon) launch_measures(s, nl, hist + (size_t)c * nl * 2, st);
+        };
+        if (tm.on) {
+            for (int c = 0; c < chunk; ++c) {
+                hipEvent_t e0 = tm.mark(), e1 = tm.fresh();
+                sweep(c, xa, xb, e1);
+                tm.spmv.push_back({e0, e1});
+                std::swap(xa, xb);
+            }
+        } else {
+            const GraphKey key{2, (uintptr_t)chunk, (uintptr_t)rhs, (uintptr_t)xa, (uintptr_t)xb, (uintptr_t)grid,
+                               (uintptr_t)first, 0};
+            float *a0 = xa, *b0 = xb;
+            SG_TRY(run_chunk(s, st, key, tm.graphs, [&]() {
+                float *a = a0, *b = b0;
+                for (int c = 0; c < chunk; ++c) {
+                    sweep(c, a, b, nullptr);
+                    std::swap(a, b);
+                }
+            }));
+            if (chunk & 1) std::swap(xa, xb);
         }
+        ss.sweeps += chunk;
         SG_HIP(hipGetLastError());
-        SG_TRY(read_scalars(s, st, hist, host.data(), chunk * nl));
-        int c0 = 0;
+        SG_TRY(read_scalars(s, st, hist, host.data(), chunk * nl * 2));
+        int c0 = c_mon;
         if (first) {
-            for (int k = 0; k < nl; ++k) norm0[k] = host[k];
-            c0 = 1;
+            for (int k = 0; k < nl; ++k) l1first[k] = host[2 * k];
+            c0 = std::max(1, c_mon);
             first = 0;
         }
         bool all = true;
@@ -572,60 +648,80 @@ sg_status neumann_batched(Scene &s, hipStream_t st, Timing &tm, const float *rhs
         for (int k = 0; k < nl; ++k) {
             if (done[k]) continue;
             for (int c = c0; c < chunk; ++c) {
-                prev[k] = last[k];
-                last[k] = host[(size_t)c * nl + k];
+                l1p[k] = l1[k];
+                relp[k] = rel[k];
+                l1[k] = host[((size_t)c * nl + k) * 2];
+                rel[k] = host[((size_t)c * nl + k) * 2 + 1];
             }
             if (chunk == c0) { all = false; continue; }
-            const double stop = stop_rel * norm0[k];
-            if (!std::isfinite(last[k])) { stalled = 1; continue; }
-            if (last[k] <= stop) { done[k] = 1; continue; }
+            if (!std::isfinite(l1[k]) || !std::isfinite(rel[k])) { stalled = 1; continue; }
+            const double stop_k = relative ? stop : stop * l1first[k];
+            const double r = relative ? rel[k] : l1[k];
+            const double q = l1p[k] > 0 ? l1[k] / l1p[k] : 0.5;
+            const double qr = relative && relp[k] > 0 ? std::max(q, rel[k] / relp[k]) : q;
+            // the measured update belongs to the previous iterate; the current one's is about q r
+            if (r <= stop_k || (l1p[k] > 0 && qr < 0.9 && qr * r <= 0.5 * stop_k)) { done[k] = 1; continue; }
             all = false;
-            double q = prev[k] > 0 ? last[k] / prev[k] : 0.5;
-            if (prev[k] > 0 && ss.sweeps >= 4 && q >= 0.95) stalled = 1;
-            q = std::min(std::max(q, 1e-12), 0.95);
-            need = std::max(need, std::log(stop / last[k]) / std::log(q));
+            const double q2 = relp[k] > 0 ? rel[k] / relp[k] : 0.0;
+            if (l1p[k] > 0 && ss.sweeps >= 4 && q >= 0.95 && (!relative || q2 >= 0.95)) stalled = 1;
+            const double qa = relative && q2 > 0 ? std::min(q, q2) : q;
+            const double qc = std::min(std::max(qa, 1e-12), 0.95);
+            need = std::max(need, std::log(stop_k / r) / std::log(qc));
+        }
+        if (sg_log()) {
+            double worst = 0.0;
+            int nd = 0;
+            for (int k = 0; k < nl; ++k) {
+                nd += done[k];
+                worst = std::max(worst, relative ? rel[k] : (l1first[k] > 0 ? l1[k] / l1first[k] : 0.0));
+            }
+            fprintf(stderr, "[sgrt] batched sweeps %d chunk %d: %d/%d wavelengths done, worst measure %.3e\n",
+                    ss.sweeps, chunk, nd, nl, worst);
         }
         if (all || stalled || ss.sweeps >= max_sweeps) break;
         chunk = (int)std::ceil(need);
+        if (chunk >= 2) chunk = std::max(chunk, 3);  // keep two monitored sweeps plus work between
     }
     return SG_OK;
 }
 
-sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Timing &tm, SolveStats &ss) {
+sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Exec &tm, SolveStats &ss) {
     Ctx *ctx = s.ctx;
     const int nl = s.n_lambda;
     const long long n = (long long)s.E * nl;
     const double rtol = o.rtol > 0 ? o.rtol : 1e-6;
     const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 2000;
     if (o.solver == SG_SOLVER_GMRES) return fail(SG_E_INVALID, "GMRES is available for single-wavelength scenes");
-    const int rgrid = std::max(1, std::min({batched_groups(s), 2048, s.n_partial / nl}));
+    const int rgrid = std::max(1, std::min(batched_groups(s), 2048));  // FP64 pass: default shape
     float *xa = s.bx, *xb = s.by;
-    std::vector<double> nS, tmp;
     int stalled = 0;
-    SG_TRY(neumann_batched(s, st, tm, nullptr, xa, xb, 0.3 * rtol, max_sweeps, ss, nS, stalled));
+    // per-edge relative updates settle at a few FP32 rounding units: never ask for less
+    SG_TRY(neumann_batched(s, st, tm, nullptr, xa, xb, 1, std::max(0.3 * rtol, 4e-6), max_sweeps, ss, stalled));
     launch_f32_to_64(xa, s.x64, n, st);
-    std::vector<double> nr(nl), sc(nl);
+    std::vector<double> m2((size_t)2 * nl), sc(nl);
     double *d_sc = s.lam_buf;  // [nl]
     for (int it = 0; it < 10; ++it) {
-        launch_bresidual64(s, st, rgrid, s.x64, s.r64, s.partial);
-        launch_reduce_lam(s.partial, rgrid, nl, s.lam_buf + nl, st);
+        launch_bresidual64(s, st, rgrid, s.x64, s.r64);
+        launch_measures(s, nl, s.lam_buf + nl, st);  // [nl][2]
         ++ss.sweeps;
         ++ss.refinements;
-        SG_TRY(read_scalars(s, st, s.lam_buf + nl, nr.data(), nl));
+        SG_TRY(read_scalars(s, st, s.lam_buf + nl, m2.data(), 2 * nl));
         double worst = 0.0;
         for (int k = 0; k < nl; ++k) {
-            const double rel = nS[k] > 0 ? nr[k] / nS[k] : 0.0;
-            worst = std::max(worst, rel);
-            sc[k] = nr[k] > 0 ? nS[k] / nr[k] : 1.0;
+            const double rel = m2[2 * k + 1];  // max over edges of |r| / |x|
+            worst = std::max(worst, std::isfinite(rel) ? rel : HUGE_VAL);
+            // r / rel is at most |x| per edge: well inside the FP32 range
+            sc[k] = rel > 0 ? 1.0 / rel : 1.0;
         }
         ss.rel = worst;
+        if (sg_log()) fprintf(stderr, "[sgrt] FP64 residual after %d sweeps: worst relative %.3e\n", ss.sweeps, worst);
         if (worst <= rtol) { ss.converged = 1; break; }
-        if (stalled || ss.sweeps >= max_sweeps) break;
+        if (stalled || ss.sweeps >= max_sweeps || !std::isfinite(worst)) break;
         SG_HIP(hipMemcpyAsync(d_sc, sc.data(), sizeof(double) * nl, hipMemcpyHostToDevice, st));
         launch_lam_scale_to_f32(s.r64, d_sc, nl, s.bS, n, st);
         float *ca = s.bx, *cb = s.by;
         int st2 = 0;
-        SG_TRY(neumann_batched(s, st, tm, s.bS, ca, cb, 1e-5, max_sweeps, ss, tmp, st2));
+        SG_TRY(neumann_batched(s, st, tm, s.bS, ca, cb, 0, 1e-5, max_sweeps, ss, st2));
         launch_lam_axpy(s.x64, ca, d_sc, nl, n, st);
         if (st2) stalled = 1;
     }
@@ -636,8 +732,10 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
 sg_status solve_batched(Scene &s, const sg_solve_opts &o, hipStream_t st, double *radiance, int on_dev,
                         sg_solve_info *info) {
     Ctx *ctx = s.ctx;
-    Timing tm;
+    Exec tm;
     tm.on = o.timing != 0;
+    tm.graphs = !(o.flags & SG_NO_GRAPHS) && !tm.on;
+    tm.autotune = !(o.flags & SG_NO_AUTOTUNE);
     tm.st = st;
     hipEvent_t e0 = tm.mark();
     launch_structure(s, st);
@@ -758,10 +856,11 @@ sg_status create_scene(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Scene &
 namespace {
 
 void free_scene_impl(Scene *s) {
+    clear_graphs(*s);
     void *ptrs[] = {s->mu_s, s->mu_a, s->frac, s->albedo, s->abs_scale_d, s->pos, s->adj_ptr, s->adj_idx, s->lat,
                     s->tab, s->rev, s->nodeoff, s->row_ptr, s->col_idx, s->scan_tmp, s->tau_s, s->tau_a, s->tsun_s,
                     s->tsun_a, s->T, s->Tsun, s->rho, s->val, s->S, s->x, s->y, s->c_rhs, s->c_a, s->c_b, s->qsun,
-                    s->q, s->bS, s->bx, s->by, s->brho, s->bsrc, s->lam_buf, s->x64, s->r64, s->gm_V, s->partial, s->counter, s->scal, s->J, s->pix};
+                    s->q, s->bS, s->bx, s->by, s->brho, s->bsrc, s->lam_buf, s->x64, s->r64, s->gm_V, s->partial, s->meas, s->meas_part, s->scal, s->J, s->pix};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->ctx) release(s->ctx, s->bytes);
@@ -824,9 +923,9 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     SG_TRY(dalloc(s, &s.r64, (size_t)s.E * nl));
     s.n_partial = std::max(spmv_blocks(s), 65 * 1024);
     SG_TRY(dalloc(s, &s.partial, (size_t)s.n_partial));
+    SG_TRY(dalloc(s, &s.meas, (size_t)s.N * nl));
+    SG_TRY(dalloc(s, &s.meas_part, (size_t)node_chunks(s.N) * nl * 2));
     SG_TRY(dalloc(s, &s.scal, 256));
-    SG_TRY(dalloc(s, &s.counter, 64));
-    SG_HIP(hipMemsetAsync(s.counter, 0, 64 * sizeof(unsigned), st));
     SG_TRY(dalloc(s, &s.J, (size_t)s.N * nl));
     SG_TRY(dalloc(s, &s.pix, (size_t)s.npx * nl));
     if (nl == 1) {
@@ -843,7 +942,7 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
         SG_TRY(dalloc(s, &s.by, (size_t)s.E * nl));
         SG_TRY(dalloc(s, &s.brho, (size_t)s.N * nl));
         SG_TRY(dalloc(s, &s.bsrc, (size_t)s.N * nl));
-        SG_TRY(dalloc(s, &s.lam_buf, (size_t)36 * nl));
+        SG_TRY(dalloc(s, &s.lam_buf, (size_t)68 * nl));
         SG_TRY(dalloc(s, &s.abs_scale_d, (size_t)nl));
         SG_TRY(upload(s, s.abs_scale_d, s.abs_scale.data(), sizeof(float) * nl, st));
     }
@@ -966,12 +1065,13 @@ uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st) {
     uint64_t b = a(nvox, 4) * 2 + (np > 1 ? a(np * nvox, 4) : 0) + a(npx, 4) + a(3 * n, 4) + a(n + 1, 8) +
                  a(e, 4) + a(3 * nf, 8) + a((np + 1) * nf, 8);
     b += a(e, 4) + a(n + 1, 8) + a(e + 1, 8) + a(n / 2048 + 2, 8) + a(e, 4);
-    b += a(e * nl, 8) * 2 + a(std::max<uint64_t>((n + 3) / 4, 65 * 1024), 8) + a(256, 8) + a(64, 4) +
+    b += a(e * nl, 8) * 2 + a(std::max<uint64_t>((n + 3) / 4, 65 * 1024), 8) +
+         a(n * nl, 8) + a(((n + kNodeChunk - 1) / kNodeChunk) * nl * 2, 8) + a(256, 8) +
          a(n * nl, 8) + a(npx * nl, 8);
     if (nl == 1) {
         b += a(e, 4) * 9 + a(n, 4) * 4 + a(z, 4);
     } else {
-        b += a(e, 4) * 2 + a(n, 4) * 2 + a(z + 64, 4) + a(e * nl, 4) * 3 + a(n * nl, 4) * 2 + a(36 * nl, 8) +
+        b += a(e, 4) * 2 + a(n, 4) * 2 + a(z + 64, 4) + a(e * nl, 4) * 3 + a(n * nl, 4) * 2 + a(68 * nl, 8) +
              a(nl, 4);
     }
     return b;

@@ -50,9 +50,16 @@ __global__ __launch_bounds__(256) void k_bnode_coef(int N, int nvox, int nl, con
 // accumulated in registers, the row count rounded up to a multiple of 8 (DB) so the
 // column loads are unguarded (the Q array is padded past its end by 64 floats).
 // kResidual: FP64 residual r = S - x + K x of an FP64 iterate instead of a sweep.
+// exp(-(tau_s + s tau_a)) as one hardware exp2; its relative error (~|tau| 1e-7) is
+// below that of the FP32 path integral itself.  The sweep and the FP64 residual use
+// the same function, so iterative refinement sees one matrix.
+__device__ __forceinline__ float edge_T(float ts, float ta, float s) {
+    return __builtin_amdgcn_exp2f(-(ts + s * ta) * 1.4426950408889634f);
+}
+
 template <int DB, class XT, class AccT, bool kResidual>
-__device__ __forceinline__ double wide_node(int l, int lane, int lam, bool lv, float s, int nl,
-                                            const long long *__restrict__ adj_ptr,
+__device__ __forceinline__ float2 wide_node(int l, int lane, int lam, bool lv, float s, int nl, int monitor,
+                                            float *__restrict__ qs, const long long *__restrict__ adj_ptr,
                                             const long long *__restrict__ nodeoff, const int *__restrict__ rev,
                                             const float *__restrict__ q, const float *__restrict__ qsun,
                                             const float *__restrict__ tau_s, const float *__restrict__ tau_a,
@@ -69,6 +76,19 @@ __device__ __forceinline__ double wide_node(int l, int lane, int lam, bool lv, f
         rv = rev[off + lane];
         ts = tau_s[off + lane];
         ta = tau_a[off + lane];
+    }
+    // the node's phase-cell block into this wavefront's LDS slice, eight loads in flight
+    {
+        const int nq = d * d;
+        for (int t0 = lane; t0 < nq; t0 += 64 * kU) {
+            float v[kU];
+#pragma unroll
+            for (int j = 0; j < kU; ++j) v[j] = t0 + j * 64 < nq ? q[base + t0 + j * 64] : 0.f;
+#pragma unroll
+            for (int j = 0; j < kU; ++j)
+                if (t0 + j * 64 < nq) qs[t0 + j * 64] = v[j];
+        }
+        __builtin_amdgcn_wave_barrier();
     }
     AccT acc[DB];
 #pragma unroll
@@ -87,14 +107,14 @@ __device__ __forceinline__ double wide_node(int l, int lane, int lam, bool lv, f
             if (m < d) {
                 const float tsm = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ts), m));
                 const float tam = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ta), m));
-                const AccT xm = (AccT)expf(-(tsm + s * tam)) * (AccT)xv[j];
-                const float *qm = q + base + (long long)m * d;  // column m: Q[n][m], n contiguous
+                const AccT xm = (AccT)edge_T(tsm, tam, s) * (AccT)xv[j];
+                const float *qm = qs + m * d;  // column m: Q[n][m], n contiguous (LDS, uniform address)
 #pragma unroll
                 for (int n = 0; n < DB; ++n) acc[n] += (AccT)qm[n] * xm;
             }
         }
     }
-    double part = 0.0;
+    double sum = 0.0, mrel = 0.0;  // convergence measures of this node's rows
     if (lv) {
         const float rl = brho[(long long)l * nl + lam];
         const float sl = bsrc[(long long)l * nl + lam];
@@ -107,17 +127,22 @@ __device__ __forceinline__ double wide_node(int l, int lane, int lam, bool lv, f
                     const double Sb = (double)(rl * sl * qsun[b]);
                     const double rb = (Sb - (double)x[bi]) + (double)rl * (double)acc[n];
                     y[bi] = (XT)rb;
-                    part += fabs(rb);
+                    sum += fabs(rb);
+                    mrel = fmax(mrel, fabs(rb) / (fabs((double)x[bi]) + kRelFloor));
                 } else {
                     const float src = rhs ? rhs[bi] : rl * sl * qsun[b];
                     const float yv = src + rl * (float)acc[n];
                     y[bi] = (XT)yv;
-                    part += fabs((double)yv - (double)x[bi]);
+                    if (monitor) {
+                        const double du = fabs((double)yv - (double)x[bi]);
+                        sum += du;
+                        mrel = fmax(mrel, du / (fabs((double)yv) + kRelFloor));
+                    }
                 }
             }
         }
     }
-    return part;
+    return make_float2((float)sum, (float)mrel);
 }
 
 template <int D, class XT, class AccT, bool kResidual>
@@ -126,21 +151,23 @@ __global__ __launch_bounds__(256) void k_spmm_wide(
     const int *__restrict__ rev, const float *__restrict__ q, const float *__restrict__ qsun,
     const float *__restrict__ tau_s, const float *__restrict__ tau_a, const float *__restrict__ abs_scale,
     const float *__restrict__ brho, const float *__restrict__ bsrc, const float *__restrict__ rhs,
-    const XT *__restrict__ x, XT *__restrict__ y, double *__restrict__ partial) {
-    __shared__ double red[256];
+    const XT *__restrict__ x, XT *__restrict__ y, float2 *__restrict__ meas, int monitor, int dmax) {
+    extern __shared__ float qs_all[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lam = blockIdx.y * 64 + lane;
     const bool lv = lam < nl;
     const float s = lv ? abs_scale[lam] : 0.f;
-    double part = 0.0;
+    float *qs = qs_all + (size_t)w * (dmax * dmax + 64);  // + padding: whole-column reads past d
+    const int waves = blockDim.x >> 6;
     for (int g = blockIdx.x; g < groups; g += gridDim.x) {
-        const int l = __builtin_amdgcn_readfirstlane(g * 4 + w);
+        const int l = __builtin_amdgcn_readfirstlane(g * waves + w);
         if (l >= N) break;
         const int d = (int)(adj_ptr[l + 1] - adj_ptr[l]);
         const int bucket = (d + 7) >> 3;
+        float2 part = make_float2(0.f, 0.f);
 #define SG_NODE(DB)                                                                                              \
-    part += wide_node<DB, XT, AccT, kResidual>(l, lane, lam, lv, s, nl, adj_ptr, nodeoff, rev, q, qsun, tau_s, \
-                                               tau_a, brho, bsrc, rhs, x, y)
+    part = wide_node<DB, XT, AccT, kResidual>(l, lane, lam, lv, s, nl, monitor, qs, adj_ptr, nodeoff, rev, q, \
+                                              qsun, tau_s, tau_a, brho, bsrc, rhs, x, y)
         if (bucket <= 1) { SG_NODE(8); }
         else if (bucket == 2) { if constexpr (D >= 16) SG_NODE(16); }
         else if (bucket == 3) { if constexpr (D >= 24) SG_NODE(24); }
@@ -150,23 +177,8 @@ __global__ __launch_bounds__(256) void k_spmm_wide(
         else if (bucket == 7) { if constexpr (D >= 56) SG_NODE(56); }
         else { if constexpr (D >= 64) SG_NODE(64); }
 #undef SG_NODE
+        if (monitor && lv) meas[(long long)l * nl + lam] = part;  // per node and wavelength
     }
-    red[threadIdx.x] = part;
-    __syncthreads();
-    if (w == 0 && lv) {
-        double t = 0.0;
-        for (int ww = 0; ww < 4; ++ww) t += red[ww * 64 + lane];
-        partial[(long long)blockIdx.x * nl + lam] = t;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_reduce_lam(const double *__restrict__ partial, int nblk, int nl,
-                                                   double *__restrict__ out) {
-    const int lam = blockIdx.x * blockDim.x + threadIdx.x;
-    if (lam >= nl) return;
-    double t = 0.0;
-    for (int b = 0; b < nblk; ++b) t += partial[(long long)b * nl + lam];
-    out[lam] = t;
 }
 
 __global__ void k_lam_scale_to_f32(const double *__restrict__ a, const double *__restrict__ sc, int nl,
@@ -244,7 +256,7 @@ __global__ __launch_bounds__(64) void k_bnode_J(int N, int nvox, int nl, const l
         if (multiple) {
             for (int m = 0; m < d; ++m) {
                 const long long e = off + m;
-                const double T = (double)expf(-(tau_s[e] + s * tau_a[e]));
+                const double T = (double)edge_T(tau_s[e], tau_a[e], s);
                 acc += th[m] * T * phi[(long long)rev[e] * nl + lam];
             }
         }
@@ -315,14 +327,19 @@ void launch_bnode_coef(Scene &s, hipStream_t st) {
                        (float)s.voxel_m, (float)s.mu0, s.weight_mode, s.brho, s.bsrc);
 }
 
+// wavefronts per workgroup: four unless the LDS slices of the phase-cell blocks would pass 60 KB
+int wide_waves(const Scene &s) { return (size_t)4 * (s.dmax * s.dmax + 64) * sizeof(float) <= 60 * 1024 ? 4 : 2; }
+
 template <class XT, class AccT, bool kRes>
-static bool launch_wide(Scene &s, hipStream_t st, int grid, const float *rhs, const XT *x, XT *y, double *partial) {
-    const int groups = (s.N + 3) / 4;
+static bool launch_wide(Scene &s, hipStream_t st, int grid, const float *rhs, const XT *x, XT *y, int monitor) {
+    const int waves = wide_waves(s);
+    const int groups = (s.N + waves - 1) / waves;
     dim3 gr(grid, (s.n_lambda + 63) / 64);
-#define SG_WIDE(DD)                                                                                              \
-    hipLaunchKernelGGL((k_spmm_wide<DD, XT, AccT, kRes>), gr, dim3(256), 0, st, s.N, s.n_lambda, groups, s.adj_ptr, \
-                       s.nodeoff, s.rev, s.q, s.qsun, (const float *)s.tau_s, (const float *)s.tau_a, s.abs_scale_d,  \
-                       s.brho, s.bsrc, rhs, x, y, partial)
+    const size_t shm = (size_t)waves * (s.dmax * s.dmax + 64) * sizeof(float);
+#define SG_WIDE(DD)                                                                                                 \
+    hipLaunchKernelGGL((k_spmm_wide<DD, XT, AccT, kRes>), gr, dim3(64 * waves), shm, st, s.N, s.n_lambda, groups,     \
+                       s.adj_ptr, s.nodeoff, s.rev, s.q, s.qsun, (const float *)s.tau_s, (const float *)s.tau_a,      \
+                       s.abs_scale_d, s.brho, s.bsrc, rhs, x, y, s.meas, monitor, s.dmax)
     if (s.dmax <= 16) SG_WIDE(16);
     else if (s.dmax <= 24) SG_WIDE(24);
     else if (s.dmax <= 32) SG_WIDE(32);
@@ -334,18 +351,14 @@ static bool launch_wide(Scene &s, hipStream_t st, int grid, const float *rhs, co
     return true;
 }
 
-int batched_groups(const Scene &s) { return (s.N + 3) / 4; }
+int batched_groups(const Scene &s) { return (s.N + wide_waves(s) - 1) / wide_waves(s); }
 
-void launch_spmm(Scene &s, hipStream_t st, int grid, const float *rhs, const float *x, float *y, double *partial) {
-    launch_wide<float, float, false>(s, st, grid, rhs, x, y, partial);
+void launch_spmm(Scene &s, hipStream_t st, int grid, const float *rhs, const float *x, float *y, int monitor) {
+    launch_wide<float, float, false>(s, st, grid, rhs, x, y, monitor);
 }
 
-void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, double *r64, double *partial) {
-    launch_wide<double, double, true>(s, st, grid, nullptr, x64, r64, partial);
-}
-
-void launch_reduce_lam(const double *partial, int nblk, int nl, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_lam, dim3((nl + 255) / 256), dim3(256), 0, st, partial, nblk, nl, out);
+void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, double *r64) {
+    launch_wide<double, double, true>(s, st, grid, nullptr, x64, r64, 1);
 }
 
 void launch_lam_scale_to_f32(const double *a, const double *sc, int nl, float *b, long long n, hipStream_t st) {

@@ -91,6 +91,32 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Block maximum; every thread must call it; returns the result in thread 0.
+template <int kThreads>
+__device__ __forceinline__ double block_max(double v) {
+    __shared__ double part[kThreads / kWave];
+    v = wave_max(v);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) part[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < kThreads / kWave; ++i) t = fmax(t, part[i]);
+    }
+    __syncthreads();
+    return t;
+}
+
+// Floor of the per-edge relative convergence measures |change| / (|value| + kRelFloor):
+// radiances below it (in units of the solar flux) count as absolute.
+constexpr double kRelFloor = 1e-30;
+
 // Deterministic block sum; every thread must call it; returns the total in thread 0.
 template <int kThreads>
 __device__ __forceinline__ double block_sum(double v) {

@@ -4,7 +4,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <atomic>
+#include <functional>
+#include <map>
 #include <cstdint>
 #include <mutex>
 #include <string>
@@ -16,6 +19,13 @@ namespace sg {
 
 void set_error(const std::string &msg);
 std::string t_last_error();
+
+// a captured chunk of sweeps: key = (kind, chunk length, buffers and flags it was recorded with)
+using GraphKey = std::array<uintptr_t, 8>;
+struct SceneGraph {
+    int seen = 0;                   // times the chunk ran; captured on the second
+    hipGraphExec_t exec = nullptr;
+};
 
 struct Ctx {
     int device = 0;
@@ -78,18 +88,23 @@ struct Scene {
     float *bS = nullptr, *bx = nullptr, *by = nullptr;  // [E][n_lambda]
     float *brho = nullptr;                // [N][n_lambda] node weights
     float *bsrc = nullptr;                // [N][n_lambda] T_sun (x mu0 on the surface)
-    double *lam_buf = nullptr;            // [36 * n_lambda] per-wavelength norms and scales
+    double *lam_buf = nullptr;            // [68 * n_lambda] per-wavelength scales and measures
 
     // FP64 solve state
     double *x64 = nullptr, *r64 = nullptr;  // [E * n_lambda]
     double *gm_V = nullptr;                 // GMRES basis [(m+1) * E]
     int gm_m = 0;
-    double *partial = nullptr;  // block partial sums
-    unsigned *counter = nullptr;  // arrival counter of persistent reductions (self re-arming)
+    double *partial = nullptr;  // block partial sums (GMRES dot products)
+    float2 *meas = nullptr;      // [N][n_lambda] per-node (sum, max relative) of the last sweep's changes
+    double *meas_part = nullptr;  // [node_chunks(N)][n_lambda][2] chunk reductions of meas
     int n_partial = 0;
     double *scal = nullptr;  // device scalars
     double *J = nullptr;     // [N * n_lambda] node radiance toward the sensor
     double *pix = nullptr;   // [n_lambda * npx] radiance staging for host outputs
+
+    std::map<GraphKey, SceneGraph> graphs;  // captured sweep chunks
+    int spmv_grid = 0, spmm_grid = 0;       // tuned launch shapes (0 = not tuned yet)
+    int spmv_grid_bytes = 0;                // element size spmv_grid was tuned for
 
     bool solved = false;
     int last_precision = 0;
@@ -106,6 +121,16 @@ sg_status check_opts(const sg_solve_opts *opts, sg_solve_opts &o);
 // device bytes a scene reserves (validates the description; *st = its status)
 uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st);
 
+// ---- runtime.cpp ----
+// persistent grid of the single-wavelength sweep (0 = default shape when autotune is off)
+template <class Real>
+int spmv_grid(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, bool autotune);
+// persistent grid of the batched sweep
+int spmm_grid(Scene &s, hipStream_t st, const float *x, float *y, bool autotune);
+// runs body() (kernel launches only) directly, or as a captured graph replay
+sg_status run_chunk(Scene &s, hipStream_t st, const GraphKey &key, bool use_graphs, const std::function<void()> &body);
+void clear_graphs(Scene &s);
+
 // ---- launchers (defined in the .hip files) ----
 void launch_structure(Scene &s, hipStream_t st);
 void launch_col_idx(Scene &s, hipStream_t st);
@@ -118,13 +143,22 @@ template <class Real>
 void launch_qbuild(Scene &s, hipStream_t st, int write_q);
 
 template <class Real>
-void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *norm_out);
+// one sweep y = S + K x; out[0..1] = measures of y - x (see launch_measures);
+// after: an event recorded right after the sweep kernel
+void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *out, int grid = 0,
+                 hipEvent_t after = nullptr);
 template <class Real>
 void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x64, double *r64, double *norm_out);
 template <class Real>
 void launch_apply_imk64(Scene &s, hipStream_t st, const double *v, double *w);
 int spmv_blocks(const Scene &s);
 void launch_reduce(const double *partial, int n, double *out, hipStream_t st);
+// Convergence measures of the last sweep or residual, reduced over nodes:
+// out[2 lambda] = sum over edges of |change|, out[2 lambda + 1] = max over edges of
+// |change| / (|value| + 1e-30), for lambda < nl.
+constexpr int kNodeChunk = 2048;
+inline int node_chunks(int N) { return (N + kNodeChunk - 1) / kNodeChunk; }
+void launch_measures(Scene &s, int nl, double *out, hipStream_t st);
 void launch_dot_multi(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial, int nblk,
                       double *out, hipStream_t st);
 void launch_axpy_multi(double *w, const double *V, int64_t ld, int k, const double *h, int64_t n, hipStream_t st);
@@ -152,9 +186,11 @@ void launch_trace(Scene &s, hipStream_t st, int kind, const long long *ids, int 
 // batched wavelengths
 int batched_groups(const Scene &s);
 void launch_bnode_coef(Scene &s, hipStream_t st);
-void launch_spmm(Scene &s, hipStream_t st, int grid, const float *rhs, const float *x, float *y, double *partial);
-void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, double *r64, double *partial);
-void launch_reduce_lam(const double *partial, int nblk, int nl, double *out, hipStream_t st);
+// one batched sweep y = rhs + K x for all wavelengths (rhs = NULL: the solar source);
+// monitor != 0: per-node measures of y - x to s.meas
+void launch_spmm(Scene &s, hipStream_t st, int grid, const float *rhs, const float *x, float *y, int monitor);
+// r64 = S + K x64 - x64 in FP64 for all wavelengths; per-node measures of r relative to x to s.meas
+void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, double *r64);
 void launch_lam_scale_to_f32(const double *a, const double *sc, int nl, float *b, long long n, hipStream_t st);
 void launch_lam_axpy(double *x, const float *d, const double *sc, int nl, long long n, hipStream_t st);
 void launch_f32_to_64(const float *a, double *b, long long n, hipStream_t st);

@@ -21,6 +21,76 @@ constexpr int kSpmvThreads = 256;
 constexpr int kNodesPerSpmvBlock = kSpmvThreads / 64;
 constexpr int kVecThreads = 256;
 
+// Convergence measures of a sweep.  Every node writes meas[node][lambda] = (sum over
+// its rows of |change|, max over its rows of |change| / (|value| + kRelFloor)); two
+// fixed-shape kernels reduce them over nodes in FP64, chunk c of kNodeChunk consecutive
+// nodes -> part[c][lambda][2], then over the chunks in order, so the result does not
+// depend on how the sweep kernel was launched.
+__global__ __launch_bounds__(kSpmvThreads) void k_measure_chunks(const float2 *__restrict__ meas, int N, int nl,
+                                                                double *__restrict__ part) {
+    const int c = blockIdx.x, n0 = c * kNodeChunk, n1 = min(N, n0 + kNodeChunk);
+    if (nl == 1) {
+        double t = 0.0, u = 0.0;
+        for (int i = n0 + (int)threadIdx.x; i < n1; i += kSpmvThreads) {
+            const float2 m = meas[i];
+            t += (double)m.x;
+            u = fmax(u, (double)m.y);
+        }
+        t = block_sum<kSpmvThreads>(t);
+        u = block_max<kSpmvThreads>(u);
+        if (threadIdx.x == 0) {
+            part[2 * c] = t;
+            part[2 * c + 1] = u;
+        }
+        return;
+    }
+    // lanes over wavelengths (coalesced rows), wavefronts over nodes
+    constexpr int kW = kSpmvThreads / 64;
+    __shared__ double red[kW][64][2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int l0 = 0; l0 < nl; l0 += 64) {
+        const int lam = l0 + lane;
+        double t = 0.0, u = 0.0;
+        if (lam < nl)
+            for (int i = n0 + w; i < n1; i += kW) {
+                const float2 m = meas[(long long)i * nl + lam];
+                t += (double)m.x;
+                u = fmax(u, (double)m.y);
+            }
+        red[w][lane][0] = t;
+        red[w][lane][1] = u;
+        __syncthreads();
+        if (w == 0 && lam < nl) {
+            double tt = 0.0, uu = 0.0;
+#pragma unroll
+            for (int k = 0; k < kW; ++k) {
+                tt += red[k][lane][0];
+                uu = fmax(uu, red[k][lane][1]);
+            }
+            part[((long long)c * nl + lam) * 2] = tt;
+            part[((long long)c * nl + lam) * 2 + 1] = uu;
+        }
+        __syncthreads();
+    }
+}
+
+// out[2 lambda] = sum, out[2 lambda + 1] = max over the chunks (one workgroup per wavelength)
+__global__ __launch_bounds__(kSpmvThreads) void k_measure_nodes(const double *__restrict__ part, int nc, int nl,
+                                                               double *__restrict__ out) {
+    const int lam = blockIdx.x;
+    double t = 0.0, u = 0.0;
+    for (int i = threadIdx.x; i < nc; i += kSpmvThreads) {
+        t += part[((long long)i * nl + lam) * 2];
+        u = fmax(u, part[((long long)i * nl + lam) * 2 + 1]);
+    }
+    t = block_sum<kSpmvThreads>(t);
+    u = block_max<kSpmvThreads>(u);
+    if (threadIdx.x == 0) {
+        out[2 * lam] = t;
+        out[2 * lam + 1] = u;
+    }
+}
+
 // Copy n consecutive elements from global memory to this wavefront's LDS slice
 // with eight loads in flight per lane before the LDS writes.
 template <class T, class U>
@@ -41,32 +111,9 @@ __device__ __forceinline__ void stage_block(U *__restrict__ dst, const T *__rest
     }
 }
 
-// Final step of a persistent kernel's norm: the block's partial goes to
-// partial[block]; the last block to arrive sums all partials in block order
-// into *out and re-arms the counter (so no clearing is needed between launches).
-__device__ __forceinline__ void finish_norm(double block_total, double *__restrict__ partial,
-                                            unsigned *__restrict__ counter, double *__restrict__ out) {
-    __shared__ bool last;
-    if (threadIdx.x == 0) {
-        partial[blockIdx.x] = block_total;
-        __threadfence();
-        const unsigned ticket = atomicAdd(counter, 1u);
-        last = ticket == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (last) {
-        __threadfence();
-        double t = 0.0;
-        for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) t += ((volatile double *)partial)[i];
-        t = block_sum<kSpmvThreads>(t);
-        if (threadIdx.x == 0) {
-            *out = t;
-            *counter = 0u;
-        }
-    }
-}
-
-// y = S + K x, persistent over node groups, one wavefront per node; *out = sum |y - x|.
+// y = S + K x, persistent over node groups, one wavefront per node; meas[node] = (sum,
+// max relative) of the node's updates y - x, reduced by separate kernels (so no
+// cross-XCD fence is needed).
 // Each wavefront stages its node's block and inputs in its own LDS slice, so no
 // workgroup barrier is needed (a wavefront's LDS operations complete in order).
 template <class Real>
@@ -74,15 +121,14 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int N, int groups, const 
                                                       const long long *__restrict__ nodeoff,
                                                       const int *__restrict__ rev, const Real *__restrict__ val,
                                                       const Real *__restrict__ S, const Real *__restrict__ x,
-                                                      Real *__restrict__ y, double *__restrict__ partial,
-                                                      unsigned *__restrict__ counter, double *__restrict__ out,
-                                                      int dmax, int stage) {
+                                                      Real *__restrict__ y, float2 *__restrict__ meas, int dmax,
+                                                      int stage) {
     extern __shared__ unsigned char smem_raw[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int per_wave = stage ? dmax * dmax + dmax : dmax;
     Real *xg = reinterpret_cast<Real *>(smem_raw) + (size_t)w * per_wave;
     Real *blk = xg + dmax;
-    double r = 0.0;
+    double r = 0.0, u = 0.0;
     for (int g = blockIdx.x; g < groups; g += gridDim.x) {
         const int l = g * kNodesPerSpmvBlock + w;
         if (l >= N) break;
@@ -99,29 +145,33 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int N, int groups, const 
             const long long b = off + lane;
             const Real yn = S[b] + acc;
             y[b] = yn;
-            r += fabs((double)yn - (double)x[b]);
+            r = fabs((double)yn - (double)x[b]);
+            u = r / (fabs((double)yn) + kRelFloor);
         }
+        r = wave_sum(r);
+        u = wave_max(u);
+        if (lane == 0) meas[l] = make_float2((float)r, (float)u);
+        r = 0.0;
+        u = 0.0;
         __builtin_amdgcn_wave_barrier();
     }
-    const double t = block_sum<kSpmvThreads>(r);
-    finish_norm(t, partial, counter, out);
 }
 
-// r = S - x + K x in FP64 (K values promoted), persistent; *out = sum |r|.
+// r = S - x + K x in FP64 (K values promoted), persistent; meas[node] = (sum |r|,
+// max |r| / (|x| + kRelFloor)) over the node's rows.
 template <class Real>
 __global__ __launch_bounds__(kSpmvThreads) void k_residual64(int N, int groups, const long long *__restrict__ adj_ptr,
                                                             const long long *__restrict__ nodeoff,
                                                             const int *__restrict__ rev, const Real *__restrict__ val,
                                                             const Real *__restrict__ S, const double *__restrict__ x,
-                                                            double *__restrict__ r, double *__restrict__ partial,
-                                                            unsigned *__restrict__ counter, double *__restrict__ out,
+                                                            double *__restrict__ r, float2 *__restrict__ meas,
                                                             int dmax, int stage) {
     extern __shared__ unsigned char smem_raw[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const size_t per_wave = (size_t)dmax * sizeof(double) + (stage ? (size_t)dmax * dmax * sizeof(Real) : 0);
     double *xg = reinterpret_cast<double *>(smem_raw + w * per_wave);
     Real *blk = reinterpret_cast<Real *>(xg + dmax);
-    double a = 0.0;
+    double a = 0.0, u = 0.0;
     for (int g = blockIdx.x; g < groups; g += gridDim.x) {
         const int l = g * kNodesPerSpmvBlock + w;
         if (l >= N) break;
@@ -138,12 +188,16 @@ __global__ __launch_bounds__(kSpmvThreads) void k_residual64(int N, int groups, 
             const long long b = off + lane;
             const double rb = ((double)S[b] - x[b]) + acc;
             r[b] = rb;
-            a += fabs(rb);
+            a = fabs(rb);
+            u = a / (fabs(x[b]) + kRelFloor);
         }
+        a = wave_sum(a);
+        u = wave_max(u);
+        if (lane == 0) meas[l] = make_float2((float)a, (float)u);
+        a = 0.0;
+        u = 0.0;
         __builtin_amdgcn_wave_barrier();
     }
-    const double t = block_sum<kSpmvThreads>(a);
-    finish_norm(t, partial, counter, out);
 }
 
 // w = v - K v in FP64.
@@ -285,16 +339,20 @@ int spmv_blocks(const Scene &s) { return (s.N + kNodesPerSpmvBlock - 1) / kNodes
 static int persistent_grid(const Scene &s) { return std::max(1, std::min(spmv_blocks(s), 256 * 8)); }
 
 template <class Real>
-void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *out) {
+void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *out, int grid,
+                 hipEvent_t after) {
     size_t shm = (size_t)kNodesPerSpmvBlock * (s.dmax * s.dmax + s.dmax) * sizeof(Real);
     int stage = 1;
     if (shm > 64 * 1024) {  // block does not fit: read rows straight from memory
         stage = 0;
         shm = (size_t)kNodesPerSpmvBlock * s.dmax * sizeof(Real);
     }
-    hipLaunchKernelGGL((k_spmv<Real>), dim3(persistent_grid(s)), dim3(kSpmvThreads), shm, st, s.N, spmv_blocks(s),
-                       s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x, y, s.partial, s.counter, out, s.dmax,
-                       stage);
+    if (grid <= 0) grid = persistent_grid(s);
+    grid = std::min(grid, spmv_blocks(s));
+    hipLaunchKernelGGL((k_spmv<Real>), dim3(grid), dim3(kSpmvThreads), shm, st, s.N, spmv_blocks(s),
+                       s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x, y, s.meas, s.dmax, stage);
+    if (after) (void)hipEventRecord(after, st);
+    launch_measures(s, 1, out, st);
 }
 
 template <class Real>
@@ -306,8 +364,9 @@ void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x6
         shm = (size_t)kNodesPerSpmvBlock * s.dmax * sizeof(double);
     }
     hipLaunchKernelGGL((k_residual64<Real>), dim3(persistent_grid(s)), dim3(kSpmvThreads), shm, st, s.N,
-                       spmv_blocks(s), s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x64, r64, s.partial,
-                       s.counter, out, s.dmax, stage);
+                       spmv_blocks(s), s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x64, r64, s.meas,
+                       s.dmax, stage);
+    launch_measures(s, 1, out, st);
 }
 
 template <class Real>
@@ -315,6 +374,14 @@ void launch_apply_imk64(Scene &s, hipStream_t st, const double *v, double *w) {
     const size_t shm = (size_t)kNodesPerSpmvBlock * s.dmax * sizeof(double);
     hipLaunchKernelGGL((k_apply_imk64<Real>), dim3(spmv_blocks(s)), dim3(kSpmvThreads), shm, st, s.N, s.adj_ptr,
                        s.nodeoff, s.rev, (const Real *)s.val, v, w, s.dmax);
+}
+
+void launch_measures(Scene &s, int nl, double *out, hipStream_t st) {
+    const int nc = node_chunks(s.N);
+    hipLaunchKernelGGL(k_measure_chunks, dim3(nc), dim3(kSpmvThreads), 0, st, (const float2 *)s.meas, s.N, nl,
+                       s.meas_part);
+    hipLaunchKernelGGL(k_measure_nodes, dim3(nl), dim3(kSpmvThreads), 0, st, (const double *)s.meas_part, nc, nl,
+                       out);
 }
 
 void launch_reduce(const double *partial, int n, double *out, hipStream_t st) {
@@ -371,7 +438,7 @@ void launch_fill(Real *a, Real v, int64_t n, hipStream_t st) {
 }
 
 #define SG_INST(R)                                                                                           \
-    template void launch_spmv<R>(Scene &, hipStream_t, const R *, const R *, R *, double *);               \
+    template void launch_spmv<R>(Scene &, hipStream_t, const R *, const R *, R *, double *, int, hipEvent_t);               \
     template void launch_residual64<R>(Scene &, hipStream_t, const R *, const double *, double *, double *); \
     template void launch_apply_imk64<R>(Scene &, hipStream_t, const double *, double *);                  \
     template void launch_to64<R>(const R *, double *, int64_t, hipStream_t);                               \

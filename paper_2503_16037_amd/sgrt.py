@@ -43,7 +43,7 @@ class SceneDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("precision", C.c_int32), ("solver", C.c_int32), ("rtol", C.c_double),
                 ("max_sweeps", C.c_int32), ("gmres_restart", C.c_int32), ("scatter_order", C.c_int32),
-                ("build_col_idx", C.c_int32), ("timing", C.c_int32)]
+                ("build_col_idx", C.c_int32), ("timing", C.c_int32), ("flags", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -162,8 +162,11 @@ def make_desc(scene, keep: list) -> SceneDesc:
     return d
 
 
+SG_NO_GRAPHS, SG_NO_AUTOTUNE = 1, 2
+
+
 def make_opts(precision="fp32", solver="auto", rtol=0.0, max_sweeps=0, gmres_restart=0, scatter_order=0,
-              build_col_idx=False, timing=False) -> SolveOpts:
+              build_col_idx=False, timing=False, graphs=True, autotune=True) -> SolveOpts:
     o = SolveOpts()
     o.abi_version = ABI_VERSION
     o.precision = SG_FP64 if precision in ("fp64", SG_FP64) else SG_FP32
@@ -174,6 +177,7 @@ def make_opts(precision="fp32", solver="auto", rtol=0.0, max_sweeps=0, gmres_res
     o.scatter_order = int(scatter_order)
     o.build_col_idx = 1 if build_col_idx else 0
     o.timing = 1 if timing else 0
+    o.flags = (0 if graphs else SG_NO_GRAPHS) | (0 if autotune else SG_NO_AUTOTUNE)
     return o
 
 

@@ -97,3 +97,17 @@ def test_batched_full_size_sampled_wavelengths(ctx):
         err = rel_err(rad[k], ora["radiance"])
         say("  lambda", k, "max / p99 rel err", err.max(), np.percentile(err, 99))
         assert err.max() < 1e-4
+
+
+def test_batched_deep_shadow_pixels(ctx):
+    """Every wavelength of a thick cloud at a 70 deg sun (pixels down to 1e-7 of the
+    median) meets the per-pixel bar."""
+    from paper_2503_16037_amd import sgrt
+    sc = scenes.make_served(3, max_voxels=6000)
+    say("batched deep shadow", sc.name)
+    with sgrt.Scene(ctx, sc) as g:
+        rad, info = g.solve()
+    assert info["converged"] == 1
+    for k in range(sc.n_lambda):
+        o = oracle.run(sc, abs_scale=float(sc.abs_scale[k]))["radiance"]
+        assert rel_err(rad[k], o).max() <= 1e-4, k

@@ -1,0 +1,76 @@
+"""Launch policy must not change results: graph replays, per-launch timing,
+the tuned persistent grid and the default grid all give bit-identical
+radiance and flux vectors, on several solves in a row of the same scene
+(graphs are captured on the second run of a chunk and replayed after that),
+with other eager work and synchronisations between the replays."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2503_16037_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2503_16037_amd import sgrt
+    c = sgrt.Context(0)
+    yield c
+    c.close()
+
+
+POLICIES = [dict(graphs=False, autotune=False), dict(graphs=False, autotune=True),
+            dict(timing=True), dict(graphs=True, autotune=True)]
+
+
+def _solve_all(ctx, sc, **kw):
+    from paper_2503_16037_amd import sgrt
+    out = []
+    with sgrt.Scene(ctx, sc) as g:
+        for pol in POLICIES:
+            for rep in range(3):
+                rad, info = g.solve(**kw, **pol)
+                phi = g.export_vector("phi")
+                out.append((pol, rep, np.array(rad), phi, info))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_single_wavelength_policies_bit_identical(ctx, precision):
+    sc = scenes.make_plume(nx=24, ny=20, nz=12)
+    say("single", precision, sc.name)
+    res = _solve_all(ctx, sc, precision=precision)
+    ref = res[0]
+    for pol, rep, rad, phi, info in res[1:]:
+        assert info["converged"] == 1
+        assert info["sweeps"] == ref[4]["sweeps"], (pol, rep)
+        assert np.array_equal(rad, ref[2]), (pol, rep)
+        assert np.array_equal(phi, ref[3]), (pol, rep)
+
+
+def test_batched_policies_bit_identical(ctx):
+    sc = scenes.make_batched(nx=20, ny=18, nz=10, n_lambda=24)
+    say("batched", sc.name)
+    res = _solve_all(ctx, sc)
+    ref = res[0]
+    for pol, rep, rad, phi, info in res[1:]:
+        assert info["converged"] == 1
+        assert info["sweeps"] == ref[4]["sweeps"], (pol, rep)
+        assert np.array_equal(rad, ref[2]), (pol, rep)
+        assert np.array_equal(phi, ref[3]), (pol, rep)
+
+
+def test_timing_reports_sweep_kernels(ctx):
+    from paper_2503_16037_amd import sgrt
+    sc = scenes.make_plume(nx=24, ny=20, nz=12)
+    with sgrt.Scene(ctx, sc) as g:
+        _, info = g.solve(timing=True)
+    assert info["spmv_launches"] >= info["sweeps"] - info["refinements"] > 0
+    assert 0 < info["ms_spmv_sum"] <= info["ms_solve"] <= info["ms_total"]
