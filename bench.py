@@ -62,6 +62,31 @@ def qbuild_flops(scene) -> float:
     return 5.0 * float((n_in * d).sum()) * scene.n_fib
 
 
+def bench_copy(args):
+    """Calibration of the HBM byte counters: a plain device copy of known size (read
+    and write 512 MiB each per dispatch).  rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of
+    this command gives the counters' reading for known traffic."""
+    import torch
+    n = 128 << 20
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    nbytes = 4 * n
+    print(json.dumps({"metric": "device copy (counter calibration)", "value": round(2 * nbytes / ms / 1e6, 1),
+                      "unit": "GB/s", "bytes_read_per_dispatch": nbytes, "bytes_written_per_dispatch": nbytes,
+                      "ms_per_copy": round(ms, 4), "steps": args.steps}), flush=True)
+
+
 def _gen_served(i):
     from paper_2503_16037_amd import scenes
     return scenes.make_served(i)
@@ -164,6 +189,9 @@ def main():
 
     if args.workload == "served":
         bench_served(args)
+        return
+    if args.workload == "copy":
+        bench_copy(args)
         return
 
     import torch

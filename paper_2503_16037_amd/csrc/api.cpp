@@ -311,28 +311,32 @@ sg_status neumann(Scene &s, hipStream_t st, Exec &tm, const Real *rhs, Real *&xa
     Ctx *ctx = s.ctx;
     launch_fill<Real>(xa, (Real)0, s.E, st);
     const int grid = spmv_grid<Real>(s, st, rhs, xa, xb, tm.autotune);
-    std::vector<double> l1, rel;
-    int chunk = 2;
+    std::vector<double> l1, rel;  // measures of consecutive monitored sweeps
+    int chunk = 2, first = 1;
     stalled = 0;
     double host[64];
     double *meas = s.scal + 128;  // [32][2] measures of the chunk's sweeps
     while (true) {
         chunk = std::max(1, std::min(chunk, 32));
+        // only the sweeps whose measures are read (the first one, and the last two of
+        // each chunk) compute them
+        const int c_mon = std::max(0, chunk - 2);
+        auto out = [&](int c) { return (first && c == 0) || c >= c_mon ? meas + 2 * c : nullptr; };
         if (tm.on) {
             for (int c = 0; c < chunk; ++c) {
                 hipEvent_t e0 = tm.mark(), e1 = tm.fresh();
-                launch_spmv<Real>(s, st, rhs, xa, xb, meas + 2 * c, grid, e1);
+                launch_spmv<Real>(s, st, rhs, xa, xb, out(c), grid, e1);
                 tm.spmv.push_back({e0, e1});
                 std::swap(xa, xb);
             }
         } else {
             const GraphKey key{1, (uintptr_t)chunk, (uintptr_t)rhs, (uintptr_t)xa, (uintptr_t)xb, (uintptr_t)grid,
-                               sizeof(Real), 0};
+                               sizeof(Real), (uintptr_t)first};
             Real *a0 = xa, *b0 = xb;
             SG_TRY(run_chunk(s, st, key, tm.graphs, [&]() {
                 Real *a = a0, *b = b0;
                 for (int c = 0; c < chunk; ++c) {
-                    launch_spmv<Real>(s, st, rhs, a, b, meas + 2 * c, grid, nullptr);
+                    launch_spmv<Real>(s, st, rhs, a, b, out(c), grid, nullptr);
                     std::swap(a, b);
                 }
             }));
@@ -341,11 +345,13 @@ sg_status neumann(Scene &s, hipStream_t st, Exec &tm, const Real *rhs, Real *&xa
         ss.sweeps += chunk;
         SG_HIP(hipGetLastError());
         SG_TRY(read_scalars(s, st, meas, host, 2 * chunk));
-        for (int c = 0; c < chunk; ++c) {
+        // the first chunk (two sweeps) is monitored whole; later ones in their last two
+        for (int c = first ? 0 : c_mon; c < chunk; ++c) {
             l1.push_back(host[2 * c]);
             rel.push_back(host[2 * c + 1]);
         }
-        if (!relative && l1.size() == (size_t)chunk) stop *= l1[0];  // first sweep from 0: sum |rhs|
+        if (first && !relative) stop *= host[0];  // first sweep from 0: sum |rhs|
+        first = 0;
         const size_t k = l1.size();
         const double r = relative ? rel.back() : l1.back();
         if (sg_log())
@@ -1138,13 +1144,26 @@ sg_status sg_export_csr(sg_scene *scene, int32_t lambda, int64_t *row_ptr, int32
                         val[no[l] + n * d + m] = (double)(T * r * q[no[l] + m * d + n]);
                     }
             }
-        } else if (s.real_bytes == 4) {
-            std::vector<float> tmp(s.nnz);
-            SG_HIP(hipMemcpyAsync(tmp.data(), s.val, sizeof(float) * s.nnz, hipMemcpyDeviceToHost, st));
-            SG_HIP(hipStreamSynchronize(st));
-            for (int64_t i = 0; i < s.nnz; ++i) val[i] = tmp[i];
         } else {
-            SG_HIP(hipMemcpyAsync(val, s.val, sizeof(double) * s.nnz, hipMemcpyDeviceToHost, st));
+            // the device blocks are column-major; CSR rows are row-major within each block
+            std::vector<double> tmp(s.nnz);
+            std::vector<int64_t> ap(s.N + 1), no(s.N + 1);
+            if (s.real_bytes == 4) {
+                std::vector<float> t32(s.nnz);
+                SG_HIP(hipMemcpyAsync(t32.data(), s.val, sizeof(float) * s.nnz, hipMemcpyDeviceToHost, st));
+                SG_HIP(hipStreamSynchronize(st));
+                for (int64_t i = 0; i < s.nnz; ++i) tmp[i] = t32[i];
+            } else {
+                SG_HIP(hipMemcpyAsync(tmp.data(), s.val, sizeof(double) * s.nnz, hipMemcpyDeviceToHost, st));
+            }
+            SG_HIP(hipMemcpyAsync(ap.data(), s.adj_ptr, sizeof(int64_t) * (s.N + 1), hipMemcpyDeviceToHost, st));
+            SG_HIP(hipMemcpyAsync(no.data(), s.nodeoff, sizeof(int64_t) * (s.N + 1), hipMemcpyDeviceToHost, st));
+            SG_HIP(hipStreamSynchronize(st));
+            for (int64_t l = 0; l < s.N; ++l) {
+                const int64_t d = ap[l + 1] - ap[l];
+                for (int64_t n = 0; n < d; ++n)
+                    for (int64_t m = 0; m < d; ++m) val[no[l] + n * d + m] = tmp[no[l] + m * d + n];
+            }
         }
     }
     SG_HIP(hipStreamSynchronize(st));

@@ -146,16 +146,17 @@ __global__ __launch_bounds__(64) void k_qbuild(
         if (lane < d) {
             const double Q = (double)(long long)bins[lane] * kUnfix;
             const long long b = off + lane;
+            // blocks are column-major: element (row = out-edge lane, column = in-edge m) at m d + lane
             if (surf) {
                 for (int m = 0; m < d; ++m) {
                     if (kWriteQ) blk[m * d + lane] = (BlkT)Q;
-                    else blk[lane * d + m] = (BlkT)(T[off + m] * rl * (Real)Q);
+                    else blk[m * d + lane] = (BlkT)(T[off + m] * rl * (Real)Q);
                 }
                 if (!kWriteQ) S[b] = rl * mu0 * tsun * (Real)Q;
                 qsun[b] = (float)Q;
             } else if (a < d) {
-                if (kWriteQ) blk[a * d + lane] = (BlkT)Q;  // Q-only output is column-major in the block
-                else blk[lane * d + a] = (BlkT)(T[off + a] * rl * (Real)Q);
+                if (kWriteQ) blk[a * d + lane] = (BlkT)Q;
+                else blk[a * d + lane] = (BlkT)(T[off + a] * rl * (Real)Q);
             } else {
                 if (!kWriteQ) S[b] = tsun * rl * (Real)Q;
                 qsun[b] = (float)Q;

@@ -110,7 +110,7 @@ int spmv_grid(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, b
     auto it = g_tuned.find(k);
     int grid = it != g_tuned.end() ? it->second : 0;
     if (!grid) {
-        double *scratch = s.scal + 200;  // two measures
+        double *scratch = s.scal + 200;  // two measures (the tuned sweeps are monitored ones)
         grid = time_candidates(st, grid_candidates(spmv_blocks(s)),
                                [&](int g) { launch_spmv<Real>(s, st, S, x, y, scratch, g); });
         if (grid) store_cache_locked(k, grid);

@@ -3,7 +3,8 @@
 // sg_submit copies a scene description on the host and queues it.  Worker
 // threads (one per resident slot, each bound to one of n_streams device
 // streams) admit the head of the queue when a slot is free and the scene's
-// reserved bytes fit the context's HBM budget, upload it, solve it (every
+// reserved bytes, added to those of the admitted scenes, fit the context's HBM
+// budget, upload it, solve it (every
 // scene keeps its own device state, so a result does not depend on what else
 // is running) and release its memory, which admits the next request.  Work of
 // different resident scenes overlaps on the device through their streams.
@@ -97,6 +98,7 @@ struct Server {
     std::vector<double> latencies;
     uint64_t next_ticket = 1;
     int running = 0;
+    uint64_t reserved = 0;  // reservations of the admitted requests
     bool stop = false;
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
@@ -125,12 +127,16 @@ struct Server {
                         continue;
                     }
                     Request *h = pending.front();
+                    // admitted requests may not have allocated yet: admit by reservations,
+                    // plus whatever the context holds beyond them (scenes outside the server)
                     const uint64_t used = ctx->used.load();
-                    const bool fits = used + h->bytes <= ctx->budget;
+                    const uint64_t outside = used > reserved ? used - reserved : 0;
+                    const bool fits = reserved + h->bytes + outside <= ctx->budget;
                     if (fits || running == 0) {
                         pending.pop_front();
                         r = h;
                         ++running;
+                        reserved += h->bytes;
                         break;
                     }
                     cv.wait(lk);  // a finishing scene releases memory
@@ -143,6 +149,7 @@ struct Server {
                 delete sc;
                 std::unique_lock<std::mutex> lk(mu);
                 --running;
+                reserved -= r->bytes;
                 if (running == 0) {  // nothing else holds memory: it will never fit
                     lk.unlock();
                     finish(r, SG_E_NOMEM, "scene does not fit the HBM budget");
@@ -163,6 +170,7 @@ struct Server {
             {
                 std::lock_guard<std::mutex> lk(mu);
                 --running;
+                reserved -= r->bytes;
             }
             finish(r, s, err);
         }

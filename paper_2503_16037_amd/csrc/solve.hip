@@ -3,9 +3,9 @@
 // FP64 residuals for iterative refinement and the pieces of a GMRES fallback.
 //
 // The sweep is node-blocked: node l owns a dense d_l x d_l block of K (rows
-// = its out-edges, columns = its in-edges), so a wavefront stages the block
-// in LDS with coalesced loads, gathers the d_l inputs x[rev(out(l))] once and
-// never reads a column index.  Every reduction has a fixed order (wave
+// = its out-edges, columns = its in-edges), stored column-major, so a
+// wavefront (lane = row) reads each column with one coalesced load, gathers
+// the d_l inputs x[rev(out(l))] once and never reads a column index.  Every reduction has a fixed order (wave
 // butterfly, then block, then one final block), so results are bit-identical
 // from run to run.
 #include <algorithm>
@@ -91,69 +91,112 @@ __global__ __launch_bounds__(kSpmvThreads) void k_measure_nodes(const double *__
     }
 }
 
-// Copy n consecutive elements from global memory to this wavefront's LDS slice
-// with eight loads in flight per lane before the LDS writes.
-template <class T, class U>
-__device__ __forceinline__ void stage_block(U *__restrict__ dst, const T *__restrict__ src, int n, int lane) {
-    constexpr int kU = 8;
-    for (int t0 = lane; t0 < n; t0 += 64 * kU) {
-        T v[kU];
-#pragma unroll
-        for (int j = 0; j < kU; ++j) {
-            const int t = t0 + j * 64;
-            v[j] = t < n ? src[t] : (T)0;
-        }
-#pragma unroll
-        for (int j = 0; j < kU; ++j) {
-            const int t = t0 + j * 64;
-            if (t < n) dst[t] = (U)v[j];
-        }
-    }
+// Broadcast lane m's value to the whole wavefront (m wave-uniform).
+__device__ __forceinline__ float bcast(float v, int m) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), m));
+}
+__device__ __forceinline__ double bcast(double v, int m) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), m);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), m);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// y = S + K x, persistent over node groups, one wavefront per node; meas[node] = (sum,
-// max relative) of the node's updates y - x, reduced by separate kernels (so no
-// cross-XCD fence is needed).
-// Each wavefront stages its node's block and inputs in its own LDS slice, so no
-// workgroup barrier is needed (a wavefront's LDS operations complete in order).
+// Row lane of node block K_l times the gathered inputs: sum over m < d of K[lane][m] xg_m,
+// in increasing m.  The block (d^2 values at blk_g, column-major: element (row n,
+// column m) at m d + n) is copied to this wavefront's LDS slice with flat coalesced
+// loads, kStage per lane in flight; rows are then read from LDS without bank conflicts
+// (consecutive lanes, consecutive addresses).  The caller issues its other loads around
+// this call; xl holds the input of in-edge `lane` (lane m's value is broadcast).
+// blk == NULL: no LDS slice, every lane reads its row from memory.
+template <class Acc, class Real, class XT>
+__device__ __forceinline__ Acc node_row(const Real *__restrict__ blk_g, Real *__restrict__ blk, int d, int lane,
+                                        XT xl) {
+    if (!blk) {  // no LDS slice (FP64 blocks of large degree): columns straight from memory
+        Acc acc = (Acc)0;
+        if (lane < d)
+            for (int m = 0; m < d; ++m) acc += (Acc)blk_g[(long long)m * d + lane] * (Acc)bcast(xl, m);
+        return acc;
+    }
+    // branch-free: out-of-range lanes reload and rewrite the last element, so the loads
+    // are issued back to back and waited for once
+    constexpr int kStage = 16;
+    const int nq = d * d;
+    for (int t0 = 0; t0 < nq; t0 += 64 * kStage) {
+        Real v[kStage];
+#pragma unroll
+        for (int j = 0; j < kStage; ++j) v[j] = blk_g[min(t0 + j * 64 + lane, nq - 1)];
+#pragma unroll
+        for (int j = 0; j < kStage; ++j) blk[min(t0 + j * 64 + lane, nq - 1)] = v[j];
+    }
+    __builtin_amdgcn_wave_barrier();
+    Acc acc = (Acc)0;
+    const int n = min(lane, d - 1);
+    for (int m = 0; m < d; ++m) acc += (Acc)blk[m * d + n] * (Acc)bcast(xl, m);
+    __builtin_amdgcn_wave_barrier();  // the slice is rewritten by the next node
+    return acc;
+}
+
+// A node's edge range and block offset (off, d, base); zeros past the last node.
+struct NodeMeta {
+    long long off, base;
+    int d;
+};
+__device__ __forceinline__ NodeMeta load_meta(const long long *__restrict__ adj_ptr,
+                                              const long long *__restrict__ nodeoff, int l, int N) {
+    NodeMeta m{0, 0, 0};
+    if (l < N) {
+        m.off = adj_ptr[l];
+        m.d = (int)(adj_ptr[l + 1] - m.off);
+        m.base = nodeoff[l];
+    }
+    return m;
+}
+
+// y = S + K x, persistent over groups of four nodes, one wavefront per node.  With
+// monitor != 0, meas[node] = (sum, max relative) of the node's updates y - x.
 template <class Real>
 __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int N, int groups, const long long *__restrict__ adj_ptr,
                                                       const long long *__restrict__ nodeoff,
                                                       const int *__restrict__ rev, const Real *__restrict__ val,
                                                       const Real *__restrict__ S, const Real *__restrict__ x,
-                                                      Real *__restrict__ y, float2 *__restrict__ meas, int dmax,
-                                                      int stage) {
+                                                      Real *__restrict__ y, float2 *__restrict__ meas, int monitor,
+                                                      int dmax) {
     extern __shared__ unsigned char smem_raw[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int per_wave = stage ? dmax * dmax + dmax : dmax;
-    Real *xg = reinterpret_cast<Real *>(smem_raw) + (size_t)w * per_wave;
-    Real *blk = xg + dmax;
-    double r = 0.0, u = 0.0;
-    for (int g = blockIdx.x; g < groups; g += gridDim.x) {
-        const int l = g * kNodesPerSpmvBlock + w;
-        if (l >= N) break;
-        const long long off = adj_ptr[l];
-        const int d = (int)(adj_ptr[l + 1] - off);
-        const long long base = nodeoff[l];
-        if (lane < d) xg[lane] = x[rev[off + lane]];
-        if (stage) stage_block(blk, val + base, d * d, lane);
-        __builtin_amdgcn_wave_barrier();
-        if (lane < d) {
-            Real acc = 0;
-            const Real *row = stage ? blk + lane * d : val + base + (long long)lane * d;
-            for (int m = 0; m < d; ++m) acc += row[m] * xg[m];
-            const long long b = off + lane;
-            const Real yn = S[b] + acc;
+    Real *blk = dmax ? reinterpret_cast<Real *>(smem_raw) + (size_t)w * dmax * dmax : nullptr;
+    // node metadata is loaded one node ahead, so its latency overlaps the current node
+    const int step = gridDim.x * kNodesPerSpmvBlock;
+    int l = __builtin_amdgcn_readfirstlane(blockIdx.x * kNodesPerSpmvBlock + w);
+    NodeMeta nm = load_meta(adj_ptr, nodeoff, l, N);
+    for (; l < N; l += step) {
+        const NodeMeta cur = nm;
+        nm = load_meta(adj_ptr, nodeoff, l + step, N);
+        const long long off = cur.off, base = cur.base;
+        const int d = cur.d;
+        if (d == 0) {
+            if (monitor && lane == 0) meas[l] = make_float2(0.f, 0.f);
+            continue;
+        }
+        const bool act = lane < d;
+        const long long b = off + min(lane, d - 1);  // lanes past d repeat the last row
+        // the index load first, so that the gather waits for it alone
+        const int rv = rev[b];
+        const Real sb = S[b], xb = x[b];
+        const Real xl = x[rv];
+        const Real acc = node_row<Real>(val + base, blk, d, lane, xl);
+        double r = 0.0, u = 0.0;
+        if (act) {
+            const Real yn = sb + acc;
             y[b] = yn;
-            r = fabs((double)yn - (double)x[b]);
+            r = fabs((double)yn - (double)xb);
             u = r / (fabs((double)yn) + kRelFloor);
         }
-        r = wave_sum(r);
-        u = wave_max(u);
-        if (lane == 0) meas[l] = make_float2((float)r, (float)u);
-        r = 0.0;
-        u = 0.0;
-        __builtin_amdgcn_wave_barrier();
+        if (monitor) {
+            r = wave_sum(r);
+            u = wave_max(u);
+            if (lane == 0) meas[l] = make_float2((float)r, (float)u);
+        }
     }
 }
 
@@ -165,38 +208,38 @@ __global__ __launch_bounds__(kSpmvThreads) void k_residual64(int N, int groups, 
                                                             const int *__restrict__ rev, const Real *__restrict__ val,
                                                             const Real *__restrict__ S, const double *__restrict__ x,
                                                             double *__restrict__ r, float2 *__restrict__ meas,
-                                                            int dmax, int stage) {
+                                                            int dmax) {
     extern __shared__ unsigned char smem_raw[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const size_t per_wave = (size_t)dmax * sizeof(double) + (stage ? (size_t)dmax * dmax * sizeof(Real) : 0);
-    double *xg = reinterpret_cast<double *>(smem_raw + w * per_wave);
-    Real *blk = reinterpret_cast<Real *>(xg + dmax);
-    double a = 0.0, u = 0.0;
-    for (int g = blockIdx.x; g < groups; g += gridDim.x) {
-        const int l = g * kNodesPerSpmvBlock + w;
-        if (l >= N) break;
-        const long long off = adj_ptr[l];
-        const int d = (int)(adj_ptr[l + 1] - off);
-        const long long base = nodeoff[l];
-        if (lane < d) xg[lane] = x[rev[off + lane]];
-        if (stage) stage_block(blk, val + base, d * d, lane);
-        __builtin_amdgcn_wave_barrier();
-        if (lane < d) {
-            double acc = 0.0;
-            const Real *row = stage ? blk + lane * d : val + base + (long long)lane * d;
-            for (int m = 0; m < d; ++m) acc += (double)row[m] * xg[m];
-            const long long b = off + lane;
-            const double rb = ((double)S[b] - x[b]) + acc;
+    Real *blk = dmax ? reinterpret_cast<Real *>(smem_raw) + (size_t)w * dmax * dmax : nullptr;
+    const int step = gridDim.x * kNodesPerSpmvBlock;
+    int l = __builtin_amdgcn_readfirstlane(blockIdx.x * kNodesPerSpmvBlock + w);
+    NodeMeta nm = load_meta(adj_ptr, nodeoff, l, N);
+    for (; l < N; l += step) {
+        const NodeMeta cur = nm;
+        nm = load_meta(adj_ptr, nodeoff, l + step, N);
+        const long long off = cur.off, base = cur.base;
+        const int d = cur.d;
+        if (d == 0) {
+            if (lane == 0) meas[l] = make_float2(0.f, 0.f);
+            continue;
+        }
+        const bool act = lane < d;
+        const long long b = off + min(lane, d - 1);
+        const int rv = rev[b];
+        const double sb = (double)S[b], xb = x[b];
+        const double xl = x[rv];
+        const double acc = node_row<double>(val + base, blk, d, lane, xl);
+        double a = 0.0, u = 0.0;
+        if (act) {
+            const double rb = (sb - xb) + acc;
             r[b] = rb;
             a = fabs(rb);
-            u = a / (fabs(x[b]) + kRelFloor);
+            u = a / (fabs(xb) + kRelFloor);
         }
         a = wave_sum(a);
         u = wave_max(u);
         if (lane == 0) meas[l] = make_float2((float)a, (float)u);
-        a = 0.0;
-        u = 0.0;
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -209,24 +252,18 @@ __global__ __launch_bounds__(kSpmvThreads) void k_apply_imk64(int N, const long 
                                                              int dmax) {
     extern __shared__ unsigned char smem_raw[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double *xg = reinterpret_cast<double *>(smem_raw) + (size_t)w * dmax;
-    const int l = blockIdx.x * kNodesPerSpmvBlock + w;
-    long long off = 0, base = 0;
-    int d = 0;
-    if (l < N) {
-        off = adj_ptr[l];
-        d = (int)(adj_ptr[l + 1] - off);
-        base = nodeoff[l];
-        if (lane < d) xg[lane] = v[rev[off + lane]];
-    }
-    __syncthreads();
-    if (lane < d) {
-        double acc = 0.0;
-        const Real *row = val + base + (long long)lane * d;
-        for (int m = 0; m < d; ++m) acc += (double)row[m] * xg[m];
-        const long long b = off + lane;
-        wv[b] = v[b] - acc;
-    }
+    Real *blk = dmax ? reinterpret_cast<Real *>(smem_raw) + (size_t)w * dmax * dmax : nullptr;
+    const int l = __builtin_amdgcn_readfirstlane(blockIdx.x * kNodesPerSpmvBlock + w);
+    if (l >= N) return;
+    const long long off = adj_ptr[l];
+    const int d = (int)(adj_ptr[l + 1] - off);
+    if (d == 0) return;
+    const long long base = nodeoff[l];
+    const bool act = lane < d;
+    const long long b = off + min(lane, d - 1);
+    const double xl = v[rev[b]];
+    const double acc = node_row<double>(val + base, blk, d, lane, xl);
+    if (act) wv[b] = v[b] - acc;
 }
 
 __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ partial, int n, double *__restrict__ out) {
@@ -335,45 +372,42 @@ inline int grid_for(long long n) {
 
 int spmv_blocks(const Scene &s) { return (s.N + kNodesPerSpmvBlock - 1) / kNodesPerSpmvBlock; }
 
+// LDS of a sweep workgroup: one node block per wavefront, at most 64 KiB (FP32 always
+// fits, dmax <= 64); beyond it (FP64, dmax > 45) the kernels read rows from memory
+template <class Real>
+static size_t block_lds(const Scene &s) {
+    const size_t b = (size_t)kNodesPerSpmvBlock * s.dmax * s.dmax * sizeof(Real);
+    return b <= 64 * 1024 ? b : 0;
+}
+template <class Real>
+static int lds_dmax(const Scene &s) { return block_lds<Real>(s) ? s.dmax : 0; }
+
 // persistent grid: at most 8 workgroups per compute unit
 static int persistent_grid(const Scene &s) { return std::max(1, std::min(spmv_blocks(s), 256 * 8)); }
 
 template <class Real>
 void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *out, int grid,
                  hipEvent_t after) {
-    size_t shm = (size_t)kNodesPerSpmvBlock * (s.dmax * s.dmax + s.dmax) * sizeof(Real);
-    int stage = 1;
-    if (shm > 64 * 1024) {  // block does not fit: read rows straight from memory
-        stage = 0;
-        shm = (size_t)kNodesPerSpmvBlock * s.dmax * sizeof(Real);
-    }
     if (grid <= 0) grid = persistent_grid(s);
     grid = std::min(grid, spmv_blocks(s));
-    hipLaunchKernelGGL((k_spmv<Real>), dim3(grid), dim3(kSpmvThreads), shm, st, s.N, spmv_blocks(s),
-                       s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x, y, s.meas, s.dmax, stage);
+    hipLaunchKernelGGL((k_spmv<Real>), dim3(grid), dim3(kSpmvThreads), block_lds<Real>(s), st, s.N, spmv_blocks(s),
+                       s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x, y, s.meas, out ? 1 : 0, lds_dmax<Real>(s));
     if (after) (void)hipEventRecord(after, st);
-    launch_measures(s, 1, out, st);
+    if (out) launch_measures(s, 1, out, st);
 }
 
 template <class Real>
 void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x64, double *r64, double *out) {
-    size_t shm = (size_t)kNodesPerSpmvBlock * s.dmax * (sizeof(double) + (size_t)s.dmax * sizeof(Real));
-    int stage = 1;
-    if (shm > 64 * 1024) {
-        stage = 0;
-        shm = (size_t)kNodesPerSpmvBlock * s.dmax * sizeof(double);
-    }
-    hipLaunchKernelGGL((k_residual64<Real>), dim3(persistent_grid(s)), dim3(kSpmvThreads), shm, st, s.N,
-                       spmv_blocks(s), s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x64, r64, s.meas,
-                       s.dmax, stage);
+    hipLaunchKernelGGL((k_residual64<Real>), dim3(persistent_grid(s)), dim3(kSpmvThreads), block_lds<Real>(s), st,
+                       s.N, spmv_blocks(s), s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x64, r64, s.meas,
+                       lds_dmax<Real>(s));
     launch_measures(s, 1, out, st);
 }
 
 template <class Real>
 void launch_apply_imk64(Scene &s, hipStream_t st, const double *v, double *w) {
-    const size_t shm = (size_t)kNodesPerSpmvBlock * s.dmax * sizeof(double);
-    hipLaunchKernelGGL((k_apply_imk64<Real>), dim3(spmv_blocks(s)), dim3(kSpmvThreads), shm, st, s.N, s.adj_ptr,
-                       s.nodeoff, s.rev, (const Real *)s.val, v, w, s.dmax);
+    hipLaunchKernelGGL((k_apply_imk64<Real>), dim3(spmv_blocks(s)), dim3(kSpmvThreads), block_lds<Real>(s), st, s.N,
+                       s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, v, w, lds_dmax<Real>(s));
 }
 
 void launch_measures(Scene &s, int nl, double *out, hipStream_t st) {
