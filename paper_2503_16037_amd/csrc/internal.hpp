@@ -152,7 +152,6 @@ void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x6
 template <class Real>
 void launch_apply_imk64(Scene &s, hipStream_t st, const double *v, double *w);
 int spmv_blocks(const Scene &s);
-void launch_reduce(const double *partial, int n, double *out, hipStream_t st);
 // Convergence measures of the last sweep or residual, reduced over nodes:
 // out[2 lambda] = sum over edges of |change|, out[2 lambda + 1] = max over edges of
 // |change| / (|value| + 1e-30), for lambda < nl.
@@ -162,7 +161,6 @@ void launch_measures(Scene &s, int nl, double *out, hipStream_t st);
 void launch_dot_multi(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial, int nblk,
                       double *out, hipStream_t st);
 void launch_axpy_multi(double *w, const double *V, int64_t ld, int k, const double *h, int64_t n, hipStream_t st);
-void launch_norm1_64(const double *v, int64_t n, double *partial, int nblk, double *out, hipStream_t st);
 
 template <class Real>
 void launch_to64(const Real *a, double *b, int64_t n, hipStream_t st);
@@ -170,12 +168,9 @@ template <class Real>
 void launch_scaled_to_real(const double *a, double scale, Real *b, int64_t n, hipStream_t st);
 template <class Real>
 void launch_axpy_real_to64(double *x64, const Real *d, double alpha, int64_t n, hipStream_t st);
-void launch_axpy64(double *y, const double *x, double alpha, int64_t n, hipStream_t st);
 void launch_scale64(double *x, double alpha, int64_t n, hipStream_t st);
 template <class Real>
 void launch_fill(Real *a, Real v, int64_t n, hipStream_t st);
-template <class Real>
-void launch_norm1_real(const Real *v, int64_t n, double *partial, int nblk, double *out, hipStream_t st);
 
 template <class Real>
 void launch_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance);

@@ -266,23 +266,6 @@ __global__ __launch_bounds__(kSpmvThreads) void k_apply_imk64(int N, const long 
     if (act) wv[b] = v[b] - acc;
 }
 
-__global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ partial, int n, double *__restrict__ out) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += 1024) s += partial[i];
-    const double t = block_sum<1024>(s);
-    if (threadIdx.x == 0) *out = t;
-}
-
-template <class Real>
-__global__ __launch_bounds__(kVecThreads) void k_norm1(const Real *__restrict__ v, long long n,
-                                                      double *__restrict__ partial) {
-    double s = 0.0;
-    for (long long i = blockIdx.x * (long long)kVecThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kVecThreads)
-        s += fabs((double)v[i]);
-    const double t = block_sum<kVecThreads>(s);
-    if (threadIdx.x == 0) partial[blockIdx.x] = t;
-}
-
 // partial[j * nblk + block] = sum_i V[j][i] w[i], j < k (one pass over w).
 __global__ __launch_bounds__(kVecThreads) void k_dot_multi(const double *__restrict__ V, long long ld, int k,
                                                           const double *__restrict__ w, long long n,
@@ -343,11 +326,6 @@ template <class Real>
 __global__ void k_axpy_real_to64(double *__restrict__ x, const Real *__restrict__ d, double alpha, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         x[i] += alpha * (double)d[i];
-}
-
-__global__ void k_axpy64(double *__restrict__ y, const double *__restrict__ x, double alpha, long long n) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        y[i] += alpha * x[i];
 }
 
 __global__ void k_scale64(double *__restrict__ x, double alpha, long long n) {
@@ -418,10 +396,6 @@ void launch_measures(Scene &s, int nl, double *out, hipStream_t st) {
                        out);
 }
 
-void launch_reduce(const double *partial, int n, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, n, out);
-}
-
 void launch_dot_multi(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial, int nblk,
                       double *out, hipStream_t st) {
     hipLaunchKernelGGL(k_dot_multi, dim3(nblk), dim3(kVecThreads), 0, st, V, (long long)ld, k, w, (long long)n, partial);
@@ -430,17 +404,6 @@ void launch_dot_multi(const double *V, int64_t ld, int k, const double *w, int64
 
 void launch_axpy_multi(double *w, const double *V, int64_t ld, int k, const double *h, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_axpy_multi, dim3(grid_for(n)), dim3(kVecThreads), 0, st, w, V, (long long)ld, k, h, (long long)n);
-}
-
-void launch_norm1_64(const double *v, int64_t n, double *partial, int nblk, double *out, hipStream_t st) {
-    hipLaunchKernelGGL((k_norm1<double>), dim3(nblk), dim3(kVecThreads), 0, st, v, (long long)n, partial);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, nblk, out);
-}
-
-template <class Real>
-void launch_norm1_real(const Real *v, int64_t n, double *partial, int nblk, double *out, hipStream_t st) {
-    hipLaunchKernelGGL((k_norm1<Real>), dim3(nblk), dim3(kVecThreads), 0, st, v, (long long)n, partial);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, nblk, out);
 }
 
 template <class Real>
@@ -456,10 +419,6 @@ void launch_scaled_to_real(const double *a, double scale, Real *b, int64_t n, hi
 template <class Real>
 void launch_axpy_real_to64(double *x64, const Real *d, double alpha, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL((k_axpy_real_to64<Real>), dim3(grid_for(n)), dim3(kVecThreads), 0, st, x64, d, alpha, (long long)n);
-}
-
-void launch_axpy64(double *y, const double *x, double alpha, int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_axpy64, dim3(grid_for(n)), dim3(kVecThreads), 0, st, y, x, alpha, (long long)n);
 }
 
 void launch_scale64(double *x, double alpha, int64_t n, hipStream_t st) {
@@ -479,7 +438,7 @@ void launch_fill(Real *a, Real v, int64_t n, hipStream_t st) {
     template void launch_scaled_to_real<R>(const double *, double, R *, int64_t, hipStream_t);             \
     template void launch_axpy_real_to64<R>(double *, const R *, double, int64_t, hipStream_t);             \
     template void launch_fill<R>(R *, R, int64_t, hipStream_t);                                            \
-    template void launch_norm1_real<R>(const R *, int64_t, double *, int, double *, hipStream_t);
+
 SG_INST(float)
 SG_INST(double)
 #undef SG_INST

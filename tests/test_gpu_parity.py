@@ -239,6 +239,27 @@ def test_plume_full_size(ctx):
         assert rel_err(tau, ora["tau"]).max() < 1e-5
 
 
+def test_cloud_full_size(ctx):
+    """The 128 x 128 x 48 cloud (18.3 M couplings, 424 M nonzeros; single-scattering
+    albedo 0.999, sun at 70 deg): every pixel against the oracle, the structure
+    bit-exact, and the transmittances of all edges."""
+    sc = scenes.make_cloud()
+    say("cloud full size", sc.name, sc.n_edges)
+    ora = oracle.run(sc, want_matrix=False)
+    say("  oracle done", ora["solve"])
+    with _scene(ctx, sc) as g:
+        rad, info = g.solve(timing=True)
+        say("  gpu info", info)
+        assert info["converged"] == 1
+        err = rel_err(rad, ora["radiance"])
+        say("  max / p99 pixel rel err", err.max(), np.percentile(err, 99))
+        assert err.max() < 1e-4
+        rp, _, _ = g.export_csr(values=False)
+        assert np.array_equal(rp, ora["row_ptr"])
+        tau = g.export_vector("tau_s") + g.export_vector("tau_a")
+        assert rel_err(tau, ora["tau"]).max() < 1e-5
+
+
 @pytest.mark.parametrize("precision,bar", [("fp32", 1e-4), ("fp64", 1e-10)])
 def test_deep_shadow_pixels(ctx, precision, bar):
     """A thick conservative-scattering cloud at a 70 deg sun: some pixels carry 1e-7 of
