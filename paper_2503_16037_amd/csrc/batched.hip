@@ -70,23 +70,20 @@ __device__ __forceinline__ float2 wide_node(int l, int lane, int lam, bool lv, f
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
     const long long base = nodeoff[l];
-    int rv = 0;
-    float ts = 0.f, ta = 0.f;
-    if (lane < d) {
-        rv = rev[off + lane];
-        ts = tau_s[off + lane];
-        ta = tau_a[off + lane];
-    }
-    // the node's phase-cell block into this wavefront's LDS slice, eight loads in flight
+    // per in-edge data in lane m (lanes past d repeat the last in-edge), then the node's
+    // phase-cell block into this wavefront's LDS slice; all loads branch-free, so they
+    // are issued back to back (out-of-range lanes reload and rewrite the last element)
+    const long long em = off + min(lane, d - 1);
+    const int rv = rev[em];
+    const float ts = tau_s[em], ta = tau_a[em];
     {
         const int nq = d * d;
         for (int t0 = lane; t0 < nq; t0 += 64 * kU) {
             float v[kU];
 #pragma unroll
-            for (int j = 0; j < kU; ++j) v[j] = t0 + j * 64 < nq ? q[base + t0 + j * 64] : 0.f;
+            for (int j = 0; j < kU; ++j) v[j] = q[base + min(t0 + j * 64, nq - 1)];
 #pragma unroll
-            for (int j = 0; j < kU; ++j)
-                if (t0 + j * 64 < nq) qs[t0 + j * 64] = v[j];
+            for (int j = 0; j < kU; ++j) qs[min(t0 + j * 64, nq - 1)] = v[j];
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -145,8 +142,14 @@ __device__ __forceinline__ float2 wide_node(int l, int lane, int lam, bool lv, f
     return make_float2((float)sum, (float)mrel);
 }
 
+// Occupancy hint for the FP32 sweep: at the requested waves per SIMD the compiler fits
+// every instantiation without spilling (72 VGPRs at D = 40 instead of 98).  The FP64
+// residual (run once per refinement) keeps its natural allocation.
+template <int D, bool kResidual>
+constexpr int wide_waves_per_eu() { return kResidual ? 1 : (D <= 40 ? 7 : 5); }
+
 template <int D, class XT, class AccT, bool kResidual>
-__global__ __launch_bounds__(256) void k_spmm_wide(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(wide_waves_per_eu<D, kResidual>()))) void k_spmm_wide(
     int N, int nl, int groups, const long long *__restrict__ adj_ptr, const long long *__restrict__ nodeoff,
     const int *__restrict__ rev, const float *__restrict__ q, const float *__restrict__ qsun,
     const float *__restrict__ tau_s, const float *__restrict__ tau_a, const float *__restrict__ abs_scale,
@@ -163,6 +166,10 @@ __global__ __launch_bounds__(256) void k_spmm_wide(
         const int l = __builtin_amdgcn_readfirstlane(g * waves + w);
         if (l >= N) break;
         const int d = (int)(adj_ptr[l + 1] - adj_ptr[l]);
+        if (d == 0) {  // an isolated node: no rows
+            if (monitor && lv) meas[(long long)l * nl + lam] = make_float2(0.f, 0.f);
+            continue;
+        }
         const int bucket = (d + 7) >> 3;
         float2 part = make_float2(0.f, 0.f);
 #define SG_NODE(DB)                                                                                              \
