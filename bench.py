@@ -44,14 +44,15 @@ def make_workload(name: str):
 
 
 def spmv_bytes(n_nodes: int, n_edges: int, nnz: int, real_bytes: int = 4, n_lambda: int = 1) -> int:
-    """Algorithmic HBM bytes of one sweep y = S + K x (node-blocked, no column index).
-    One wavelength: values nnz, per edge S, y, x (own), x (gathered once), rev; per node
-    adj_ptr and the block offset.  n wavelengths: phase cells nnz (shared), per edge
-    tau_s, tau_a, rev, Qsun and per (edge, wavelength) y, x (own), x (gathered); per
-    (node, wavelength) rho and the solar factor."""
+    """Algorithmic HBM bytes of one sweep y = S + K x (node-blocked, no column index), for a
+    sweep that computes no convergence measure (those that do also read the previous x).
+    One wavelength: values nnz, per edge S, y, x (gathered once), rev; per node adj_ptr
+    and the block offset.  n wavelengths: phase cells nnz (shared), per edge tau_s, tau_a,
+    rev, Qsun and per (edge, wavelength) y and x (gathered once); per (node, wavelength)
+    rho and the solar factor."""
     if n_lambda == 1:
-        return real_bytes * nnz + n_edges * (4 * real_bytes + 4) + n_nodes * 16
-    return 4 * nnz + n_edges * 16 + n_edges * n_lambda * 12 + n_nodes * (16 + 8 * n_lambda)
+        return real_bytes * nnz + n_edges * (3 * real_bytes + 4) + n_nodes * 16
+    return 4 * nnz + n_edges * 16 + n_edges * n_lambda * 8 + n_nodes * (16 + 8 * n_lambda)
 
 
 def qbuild_ops(scene) -> float:
@@ -89,6 +90,23 @@ def bench_copy(args):
     print(json.dumps({"metric": "device copy (counter calibration)", "value": round(2 * nbytes / ms / 1e6, 1),
                       "unit": "GB/s", "bytes_read_per_dispatch": nbytes, "bytes_written_per_dispatch": nbytes,
                       "ms_per_copy": round(ms, 4), "steps": args.steps}), flush=True)
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    (profiles/traffic.json, FETCH_SIZE and WRITE_SIZE scaled by a device-copy calibration),
+    or None when the kernel's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    srcs = {"k_qbuild": ["qbuild.hip"], "k_spmv": ["solve.hip"], "k_spmm_wide": ["batched.hip"]}[kernel]
+    try:
+        rec = json.load(open(path))["kernels"][f"{kernel}@{workload}"]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in srcs + ["device.hpp"]:
+        h.update(open(os.path.join(ROOT, "paper_2503_16037_amd", "csrc", f), "rb").read())
+    return int(rec["bytes"]) if h.hexdigest()[:16] == rec["source_sha256_16"] else None
 
 
 def _gen_served(i):
@@ -234,13 +252,14 @@ def main():
         achieved = qops / (stages["ms_qbuild"] * 1e-3) / 1e12
         roof = {"kernel": "k_qbuild (phase cells + K values + source)", "bound": "alu",
                 "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "T FP64 lane-op/s",
-                "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
+                "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": measured_traffic("k_qbuild", args.workload),
                 "algorithmic_per_launch": qops, "avg_launch_ms": round(stages["ms_qbuild"], 4)}
     else:
         achieved = sbytes / (spmv_avg_ms * 1e-3) / 1e9
         roof = {"kernel": "k_spmv (FP32 sweep)" if g.n_lambda == 1 else "k_spmm (FP32, all wavelengths)",
                 "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic("k_spmv" if g.n_lambda == 1 else "k_spmm_wide", args.workload),
                 "algorithmic_per_launch": sbytes, "avg_launch_ms": round(spmv_avg_ms, 5)}
     sweep_roof = {"kernel": "k_spmv", "avg_launch_ms": round(spmv_avg_ms, 5), "bytes_per_launch": sbytes,
                   "achieved_GBs": round(sbytes / max(spmv_avg_ms, 1e-9) / 1e6, 1),

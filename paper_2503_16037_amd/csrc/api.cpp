@@ -309,7 +309,6 @@ template <class Real>
 sg_status neumann(Scene &s, hipStream_t st, Exec &tm, const Real *rhs, Real *&xa, Real *&xb, int relative,
                   double stop, int max_sweeps, SolveStats &ss, int &stalled) {
     Ctx *ctx = s.ctx;
-    launch_fill<Real>(xa, (Real)0, s.E, st);
     const int grid = spmv_grid<Real>(s, st, rhs, xa, xb, tm.autotune);
     std::vector<double> l1, rel;  // measures of consecutive monitored sweeps
     int chunk = 2, first = 1;
@@ -322,11 +321,17 @@ sg_status neumann(Scene &s, hipStream_t st, Exec &tm, const Real *rhs, Real *&xa
         // each chunk) compute them
         const int c_mon = std::max(0, chunk - 2);
         auto out = [&](int c) { return (first && c == 0) || c >= c_mon ? meas + 2 * c : nullptr; };
+        // the first iterate from x = 0 is rhs itself: a copy instead of a sweep
+        const int n_copy = first ? 1 : 0;
         if (tm.on) {
             for (int c = 0; c < chunk; ++c) {
-                hipEvent_t e0 = tm.mark(), e1 = tm.fresh();
-                launch_spmv<Real>(s, st, rhs, xa, xb, out(c), grid, e1);
-                tm.spmv.push_back({e0, e1});
+                if (c < n_copy) {
+                    launch_first<Real>(s, st, rhs, xb, out(c));
+                } else {
+                    hipEvent_t e0 = tm.mark(), e1 = tm.fresh();
+                    launch_spmv<Real>(s, st, rhs, xa, xb, out(c), grid, e1);
+                    tm.spmv.push_back({e0, e1});
+                }
                 std::swap(xa, xb);
             }
         } else {
@@ -336,13 +341,14 @@ sg_status neumann(Scene &s, hipStream_t st, Exec &tm, const Real *rhs, Real *&xa
             SG_TRY(run_chunk(s, st, key, tm.graphs, [&]() {
                 Real *a = a0, *b = b0;
                 for (int c = 0; c < chunk; ++c) {
-                    launch_spmv<Real>(s, st, rhs, a, b, out(c), grid, nullptr);
+                    if (c < n_copy) launch_first<Real>(s, st, rhs, b, out(c));
+                    else launch_spmv<Real>(s, st, rhs, a, b, out(c), grid, nullptr);
                     std::swap(a, b);
                 }
             }));
             if (chunk & 1) std::swap(xa, xb);
         }
-        ss.sweeps += chunk;
+        ss.sweeps += chunk - n_copy;
         SG_HIP(hipGetLastError());
         SG_TRY(read_scalars(s, st, meas, host, 2 * chunk));
         // the first chunk (two sweeps) is monitored whole; later ones in their last two
@@ -596,7 +602,6 @@ sg_status neumann_batched(Scene &s, hipStream_t st, Exec &tm, const float *rhs, 
     Ctx *ctx = s.ctx;
     const int nl = s.n_lambda;
     const long long n = (long long)s.E * nl;
-    launch_fill_f32(xa, n, st);
     const int grid = spmm_grid(s, st, xa, xb, tm.autotune);
     std::vector<double> host((size_t)64 * nl);
     std::vector<double> l1p(nl, -1.0), l1(nl, 0.0), relp(nl, -1.0), rel(nl, 0.0), l1first(nl, 0.0);
@@ -607,17 +612,24 @@ sg_status neumann_batched(Scene &s, hipStream_t st, Exec &tm, const float *rhs, 
     while (true) {
         chunk = std::max(1, std::min(chunk, 32));
         const int c_mon = std::max(0, chunk - 2);
+        // the first iterate from x = 0 is rhs itself: a copy instead of a sweep
+        const int n_copy = first ? 1 : 0;
         auto sweep = [&](int c, const float *a, float *b, hipEvent_t after) {
             const int mon = (first && c == 0) || c >= c_mon;
-            launch_spmm(s, st, grid, rhs, a, b, mon);
+            if (c < n_copy) launch_bfirst(s, st, rhs, b);
+            else launch_spmm(s, st, grid, rhs, a, b, mon);
             if (after) (void)hipEventRecord(after, st);
             if (mon) launch_measures(s, nl, hist + (size_t)c * nl * 2, st);
         };
         if (tm.on) {
             for (int c = 0; c < chunk; ++c) {
-                hipEvent_t e0 = tm.mark(), e1 = tm.fresh();
-                sweep(c, xa, xb, e1);
-                tm.spmv.push_back({e0, e1});
+                if (c < n_copy) {
+                    sweep(c, xa, xb, nullptr);
+                } else {
+                    hipEvent_t e0 = tm.mark(), e1 = tm.fresh();
+                    sweep(c, xa, xb, e1);
+                    tm.spmv.push_back({e0, e1});
+                }
                 std::swap(xa, xb);
             }
         } else {
@@ -633,7 +645,7 @@ sg_status neumann_batched(Scene &s, hipStream_t st, Exec &tm, const float *rhs, 
             }));
             if (chunk & 1) std::swap(xa, xb);
         }
-        ss.sweeps += chunk;
+        ss.sweeps += chunk - n_copy;
         SG_HIP(hipGetLastError());
         SG_TRY(read_scalars(s, st, hist, host.data(), chunk * nl * 2));
         int c0 = c_mon;
@@ -923,7 +935,7 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     s.n_partial = std::max(spmv_blocks(s), 65 * 1024);
     SG_TRY(dalloc(s, &s.partial, (size_t)s.n_partial));
     SG_TRY(dalloc(s, &s.meas, (size_t)s.N * nl));
-    SG_TRY(dalloc(s, &s.meas_part, (size_t)node_chunks(s.N) * nl * 2));
+    SG_TRY(dalloc(s, &s.meas_part, (size_t)node_chunks(s.N, nl) * nl * 2));
     SG_TRY(dalloc(s, &s.scal, 256));
     SG_TRY(dalloc(s, &s.J, (size_t)s.N * nl));
     SG_TRY(dalloc(s, &s.pix, (size_t)s.npx * nl));
@@ -1065,7 +1077,7 @@ uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st) {
                  a(e, 4) + a(3 * nf, 8) + a((np + 1) * nf, 8);
     b += a(e, 4) + a(n + 1, 8) + a(e + 1, 8) + a(n / 2048 + 2, 8) + a(e, 4);
     b += a(e * nl, 8) * 2 + a(std::max<uint64_t>((n + 3) / 4, 65 * 1024), 8) +
-         a(n * nl, 8) + a(((n + kNodeChunk - 1) / kNodeChunk) * nl * 2, 8) + a(256, 8) +
+         a(n * nl, 8) + a((uint64_t)node_chunks((int)n, (int)nl) * nl * 2, 8) + a(256, 8) +
          a(n * nl, 8) + a(npx * nl, 8);
     if (nl == 1) {
         b += a(e, 4) * 9 + a(n, 4) * 4 + a(z, 4);

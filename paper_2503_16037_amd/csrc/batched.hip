@@ -188,6 +188,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(wide_waves_
     }
 }
 
+// The first batched Neumann iterate from x = 0: x = rhs, or the solar source
+// rho_l s_l Qsun_b, computed as the sweep computes it (plus rho_l times a zero sum), so
+// it has the sweep's bits; measures per (node, wavelength).
+__global__ __launch_bounds__(256) void k_bfirst(int N, int nl, const long long *__restrict__ adj_ptr,
+                                                const float *__restrict__ qsun, const float *__restrict__ brho,
+                                                const float *__restrict__ bsrc, const float *__restrict__ rhs,
+                                                float *__restrict__ x, float2 *__restrict__ meas) {
+    const int lane = threadIdx.x & 63;
+    const int l = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int lam = blockIdx.y * 64 + lane;
+    if (l >= N || lam >= nl) return;
+    const long long off = adj_ptr[l];
+    const int d = (int)(adj_ptr[l + 1] - off);
+    const float rl = brho[(long long)l * nl + lam], sl = bsrc[(long long)l * nl + lam];
+    double sum = 0.0, mrel = 0.0;
+    for (int n = 0; n < d; ++n) {
+        const long long bi = (off + n) * nl + lam;
+        const float src = rhs ? rhs[bi] : rl * sl * qsun[off + n];
+        const float yv = src + rl * 0.0f;
+        x[bi] = yv;
+        const double du = fabs((double)yv);
+        sum += du;
+        mrel = fmax(mrel, du / (du + kRelFloor));
+    }
+    meas[(long long)l * nl + lam] = make_float2((float)sum, (float)mrel);
+}
+
 __global__ void k_lam_scale_to_f32(const double *__restrict__ a, const double *__restrict__ sc, int nl,
                                    float *__restrict__ b, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -366,6 +393,12 @@ void launch_spmm(Scene &s, hipStream_t st, int grid, const float *rhs, const flo
 
 void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, double *r64) {
     launch_wide<double, double, true>(s, st, grid, nullptr, x64, r64, 1);
+}
+
+void launch_bfirst(Scene &s, hipStream_t st, const float *rhs, float *x) {
+    dim3 gr((s.N + 3) / 4, (s.n_lambda + 63) / 64);
+    hipLaunchKernelGGL(k_bfirst, gr, dim3(256), 0, st, s.N, s.n_lambda, s.adj_ptr, s.qsun, s.brho, s.bsrc, rhs, x,
+                       s.meas);
 }
 
 void launch_lam_scale_to_f32(const double *a, const double *sc, int nl, float *b, long long n, hipStream_t st) {

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <atomic>
 #include <functional>
@@ -96,7 +97,7 @@ struct Scene {
     int gm_m = 0;
     double *partial = nullptr;  // block partial sums (GMRES dot products)
     float2 *meas = nullptr;      // [N][n_lambda] per-node (sum, max relative) of the last sweep's changes
-    double *meas_part = nullptr;  // [node_chunks(N)][n_lambda][2] chunk reductions of meas
+    double *meas_part = nullptr;  // [node_chunks(N, n_lambda)][n_lambda][2] chunk reductions of meas
     int n_partial = 0;
     double *scal = nullptr;  // device scalars
     double *J = nullptr;     // [N * n_lambda] node radiance toward the sensor
@@ -122,11 +123,12 @@ sg_status check_opts(const sg_solve_opts *opts, sg_solve_opts &o);
 uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st);
 
 // ---- runtime.cpp ----
-// persistent grid of the single-wavelength sweep (0 = default shape when autotune is off)
+// persistent grid of the single-wavelength sweep (0 = default shape when autotune is off);
+// x and y are scratch vectors that tuning may overwrite
 template <class Real>
-int spmv_grid(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, bool autotune);
-// persistent grid of the batched sweep
-int spmm_grid(Scene &s, hipStream_t st, const float *x, float *y, bool autotune);
+int spmv_grid(Scene &s, hipStream_t st, const Real *S, Real *x, Real *y, bool autotune);
+// persistent grid of the batched sweep (x, y: scratch as above)
+int spmm_grid(Scene &s, hipStream_t st, float *x, float *y, bool autotune);
 // runs body() (kernel launches only) directly, or as a captured graph replay
 sg_status run_chunk(Scene &s, hipStream_t st, const GraphKey &key, bool use_graphs, const std::function<void()> &body);
 void clear_graphs(Scene &s);
@@ -147,6 +149,9 @@ template <class Real>
 // after: an event recorded right after the sweep kernel
 void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *out, int grid = 0,
                  hipEvent_t after = nullptr);
+// the first Neumann iterate from x = 0: x = rhs; out[0..1] = measures of that update
+template <class Real>
+void launch_first(Scene &s, hipStream_t st, const Real *rhs, Real *x, double *out);
 template <class Real>
 void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x64, double *r64, double *norm_out);
 template <class Real>
@@ -155,8 +160,15 @@ int spmv_blocks(const Scene &s);
 // Convergence measures of the last sweep or residual, reduced over nodes:
 // out[2 lambda] = sum over edges of |change|, out[2 lambda + 1] = max over edges of
 // |change| / (|value| + 1e-30), for lambda < nl.
-constexpr int kNodeChunk = 2048;
-inline int node_chunks(int N) { return (N + kNodeChunk - 1) / kNodeChunk; }
+// nodes per reduction chunk: 2048 for one wavelength; about sqrt(N) for several, which
+// balances the chunk pass (chunk length) against the final pass (number of chunks)
+inline int node_chunk(int N, int nl) {
+    if (nl == 1) return 2048;
+    int c = 32;
+    while ((long long)c * c < N) c *= 2;
+    return c;
+}
+inline int node_chunks(int N, int nl) { return (N + node_chunk(N, nl) - 1) / node_chunk(N, nl); }
 void launch_measures(Scene &s, int nl, double *out, hipStream_t st);
 void launch_dot_multi(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial, int nblk,
                       double *out, hipStream_t st);
@@ -181,6 +193,9 @@ void launch_trace(Scene &s, hipStream_t st, int kind, const long long *ids, int 
 // batched wavelengths
 int batched_groups(const Scene &s);
 void launch_bnode_coef(Scene &s, hipStream_t st);
+// the first batched Neumann iterate from x = 0: x = rhs (NULL: the solar source), with
+// per-node measures to s.meas
+void launch_bfirst(Scene &s, hipStream_t st, const float *rhs, float *x);
 // one batched sweep y = rhs + K x for all wavelengths (rhs = NULL: the solar source);
 // monitor != 0: per-node measures of y - x to s.meas
 void launch_spmm(Scene &s, hipStream_t st, int grid, const float *rhs, const float *x, float *y, int monitor);

@@ -44,7 +44,6 @@ __global__ __launch_bounds__(64) void k_qbuild(
     double *sx = smem, *sy = smem + 64, *sz = smem + 128;
     double *rx = smem + 192, *ry = smem + 256, *rz = smem + 320;
     unsigned long long *bins = reinterpret_cast<unsigned long long *>(smem + 384);
-    BlkT *blk = reinterpret_cast<BlkT *>(smem + 448);
 
     const int l = blockIdx.x;
     const int lane = threadIdx.x;
@@ -100,6 +99,9 @@ __global__ __launch_bounds__(64) void k_qbuild(
 
     const Real rl = rho ? rho[l] : (Real)0;
     const Real tsun = Tsun ? Tsun[l] : (Real)0;
+    // the node's block, column-major: element (row = out-edge n, column = in-edge m) at
+    // m d + n, so each column is one coalesced store of d values
+    BlkT *blk = val + nodeoff[l];
     const int n_in = surf ? 1 : d + 1;
     for (int a = 0; a < n_in; ++a) {
         if (lane < d) {
@@ -146,7 +148,6 @@ __global__ __launch_bounds__(64) void k_qbuild(
         if (lane < d) {
             const double Q = (double)(long long)bins[lane] * kUnfix;
             const long long b = off + lane;
-            // blocks are column-major: element (row = out-edge lane, column = in-edge m) at m d + lane
             if (surf) {
                 for (int m = 0; m < d; ++m) {
                     if (kWriteQ) blk[m * d + lane] = (BlkT)Q;
@@ -164,23 +165,19 @@ __global__ __launch_bounds__(64) void k_qbuild(
         }
         __syncthreads();
     }
-    const long long base = nodeoff[l];
-    for (int t = lane; t < d * d; t += 64) val[base + t] = blk[t];
 }
 
 }  // namespace
 
 template <class Real>
 void launch_qbuild(Scene &s, hipStream_t st, int write_q) {
-    const size_t shm_base = 448 * sizeof(double);
+    const size_t shm = 448 * sizeof(double);
     if (write_q) {
-        const size_t shm = shm_base + (size_t)s.dmax * s.dmax * sizeof(float);
         hipLaunchKernelGGL((k_qbuild<Real, float, true>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
                            s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
                            s.sun_in[2], (Real)s.mu0, (const Real *)nullptr, (const Real *)nullptr,
                            (const Real *)nullptr, s.nodeoff, s.q, (Real *)nullptr, s.qsun);
     } else {
-        const size_t shm = shm_base + (size_t)s.dmax * s.dmax * sizeof(Real);
         hipLaunchKernelGGL((k_qbuild<Real, Real, false>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
                            s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
                            s.sun_in[2], (Real)s.mu0, (const Real *)s.T, (const Real *)s.rho, (const Real *)s.Tsun,

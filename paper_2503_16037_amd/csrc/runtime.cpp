@@ -101,7 +101,7 @@ std::vector<int> grid_candidates(int groups) {
 }  // namespace
 
 template <class Real>
-int spmv_grid(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, bool autotune) {
+int spmv_grid(Scene &s, hipStream_t st, const Real *S, Real *x, Real *y, bool autotune) {
     if (!autotune) return 0;
     if (s.spmv_grid > 0 && s.spmv_grid_bytes == (int)sizeof(Real)) return s.spmv_grid;
     const TuneKey k{0, s.N, s.E, s.nnz, s.dmax, 1, (long long)sizeof(Real)};
@@ -111,6 +111,7 @@ int spmv_grid(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, b
     int grid = it != g_tuned.end() ? it->second : 0;
     if (!grid) {
         double *scratch = s.scal + 200;  // two measures (the tuned sweeps are monitored ones)
+        launch_fill<Real>(x, (Real)0, s.E, st);  // x and y are scratch vectors here
         grid = time_candidates(st, grid_candidates(spmv_blocks(s)),
                                [&](int g) { launch_spmv<Real>(s, st, S, x, y, scratch, g); });
         if (grid) store_cache_locked(k, grid);
@@ -120,7 +121,7 @@ int spmv_grid(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, b
     return grid;
 }
 
-int spmm_grid(Scene &s, hipStream_t st, const float *x, float *y, bool autotune) {
+int spmm_grid(Scene &s, hipStream_t st, float *x, float *y, bool autotune) {
     const int groups = batched_groups(s);
     const int fallback = std::max(1, std::min(groups, 2048));
     if (!autotune) return fallback;
@@ -131,6 +132,7 @@ int spmm_grid(Scene &s, hipStream_t st, const float *x, float *y, bool autotune)
     auto it = g_tuned.find(k);
     int grid = it != g_tuned.end() ? it->second : 0;
     if (!grid) {
+        launch_fill_f32(x, (long long)s.E * s.n_lambda, st);  // x and y are scratch vectors here
         grid = time_candidates(st, grid_candidates(groups), [&](int g) { launch_spmm(s, st, g, nullptr, x, y, 1); });
         if (grid) store_cache_locked(k, grid);
     }
@@ -138,8 +140,8 @@ int spmm_grid(Scene &s, hipStream_t st, const float *x, float *y, bool autotune)
     return s.spmm_grid;
 }
 
-template int spmv_grid<float>(Scene &, hipStream_t, const float *, const float *, float *, bool);
-template int spmv_grid<double>(Scene &, hipStream_t, const double *, const double *, double *, bool);
+template int spmv_grid<float>(Scene &, hipStream_t, const float *, float *, float *, bool);
+template int spmv_grid<double>(Scene &, hipStream_t, const double *, double *, double *, bool);
 
 sg_status run_chunk(Scene &s, hipStream_t st, const GraphKey &key, bool use_graphs, const std::function<void()> &body) {
     if (!use_graphs) {

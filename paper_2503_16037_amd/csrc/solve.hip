@@ -23,12 +23,13 @@ constexpr int kVecThreads = 256;
 
 // Convergence measures of a sweep.  Every node writes meas[node][lambda] = (sum over
 // its rows of |change|, max over its rows of |change| / (|value| + kRelFloor)); two
-// fixed-shape kernels reduce them over nodes in FP64, chunk c of kNodeChunk consecutive
-// nodes -> part[c][lambda][2], then over the chunks in order, so the result does not
-// depend on how the sweep kernel was launched.
+// fixed-shape kernels reduce them over nodes in FP64: chunk c of node_chunk(N, nl)
+// consecutive nodes -> part[c][lambda][2], then over the chunks in a fixed order, so the
+// result does not depend on how the sweep kernel was launched.  With several wavelengths
+// the lanes run over wavelengths (coalesced rows) and the wavefronts over nodes.
 __global__ __launch_bounds__(kSpmvThreads) void k_measure_chunks(const float2 *__restrict__ meas, int N, int nl,
-                                                                double *__restrict__ part) {
-    const int c = blockIdx.x, n0 = c * kNodeChunk, n1 = min(N, n0 + kNodeChunk);
+                                                                int cn, double *__restrict__ part) {
+    const int c = blockIdx.x, n0 = c * cn, n1 = min(N, n0 + cn);
     if (nl == 1) {
         double t = 0.0, u = 0.0;
         for (int i = n0 + (int)threadIdx.x; i < n1; i += kSpmvThreads) {
@@ -44,50 +45,73 @@ __global__ __launch_bounds__(kSpmvThreads) void k_measure_chunks(const float2 *_
         }
         return;
     }
-    // lanes over wavelengths (coalesced rows), wavefronts over nodes
     constexpr int kW = kSpmvThreads / 64;
     __shared__ double red[kW][64][2];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int l0 = 0; l0 < nl; l0 += 64) {
-        const int lam = l0 + lane;
-        double t = 0.0, u = 0.0;
-        if (lam < nl)
-            for (int i = n0 + w; i < n1; i += kW) {
-                const float2 m = meas[(long long)i * nl + lam];
-                t += (double)m.x;
-                u = fmax(u, (double)m.y);
-            }
-        red[w][lane][0] = t;
-        red[w][lane][1] = u;
-        __syncthreads();
-        if (w == 0 && lam < nl) {
-            double tt = 0.0, uu = 0.0;
-#pragma unroll
-            for (int k = 0; k < kW; ++k) {
-                tt += red[k][lane][0];
-                uu = fmax(uu, red[k][lane][1]);
-            }
-            part[((long long)c * nl + lam) * 2] = tt;
-            part[((long long)c * nl + lam) * 2 + 1] = uu;
+    const int lam = blockIdx.y * 64 + lane;
+    double t = 0.0, u = 0.0;
+    if (lam < nl)
+#pragma unroll 8
+        for (int i = n0 + w; i < n1; i += kW) {
+            const float2 m = meas[(long long)i * nl + lam];
+            t += (double)m.x;
+            u = fmax(u, (double)m.y);
         }
-        __syncthreads();
+    red[w][lane][0] = t;
+    red[w][lane][1] = u;
+    __syncthreads();
+    if (w == 0 && lam < nl) {
+        double tt = 0.0, uu = 0.0;
+#pragma unroll
+        for (int k = 0; k < kW; ++k) {
+            tt += red[k][lane][0];
+            uu = fmax(uu, red[k][lane][1]);
+        }
+        part[((long long)c * nl + lam) * 2] = tt;
+        part[((long long)c * nl + lam) * 2 + 1] = uu;
     }
 }
 
-// out[2 lambda] = sum, out[2 lambda + 1] = max over the chunks (one workgroup per wavelength)
+// out[2 lambda] = sum, out[2 lambda + 1] = max over the nc chunks
 __global__ __launch_bounds__(kSpmvThreads) void k_measure_nodes(const double *__restrict__ part, int nc, int nl,
                                                                double *__restrict__ out) {
-    const int lam = blockIdx.x;
-    double t = 0.0, u = 0.0;
-    for (int i = threadIdx.x; i < nc; i += kSpmvThreads) {
-        t += part[((long long)i * nl + lam) * 2];
-        u = fmax(u, part[((long long)i * nl + lam) * 2 + 1]);
+    if (nl == 1) {
+        double t = 0.0, u = 0.0;
+        for (int i = threadIdx.x; i < nc; i += kSpmvThreads) {
+            t += part[2 * i];
+            u = fmax(u, part[2 * i + 1]);
+        }
+        t = block_sum<kSpmvThreads>(t);
+        u = block_max<kSpmvThreads>(u);
+        if (threadIdx.x == 0) {
+            out[0] = t;
+            out[1] = u;
+        }
+        return;
     }
-    t = block_sum<kSpmvThreads>(t);
-    u = block_max<kSpmvThreads>(u);
-    if (threadIdx.x == 0) {
-        out[2 * lam] = t;
-        out[2 * lam + 1] = u;
+    constexpr int kW = kSpmvThreads / 64;
+    __shared__ double red[kW][64][2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lam = blockIdx.x * 64 + lane;
+    double t = 0.0, u = 0.0;
+    if (lam < nl)
+#pragma unroll 8
+        for (int i = w; i < nc; i += kW) {
+            t += part[((long long)i * nl + lam) * 2];
+            u = fmax(u, part[((long long)i * nl + lam) * 2 + 1]);
+        }
+    red[w][lane][0] = t;
+    red[w][lane][1] = u;
+    __syncthreads();
+    if (w == 0 && lam < nl) {
+        double tt = 0.0, uu = 0.0;
+#pragma unroll
+        for (int k = 0; k < kW; ++k) {
+            tt += red[k][lane][0];
+            uu = fmax(uu, red[k][lane][1]);
+        }
+        out[2 * lam] = tt;
+        out[2 * lam + 1] = uu;
     }
 }
 
@@ -182,7 +206,8 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int N, int groups, const 
         const long long b = off + min(lane, d - 1);  // lanes past d repeat the last row
         // the index load first, so that the gather waits for it alone
         const int rv = rev[b];
-        const Real sb = S[b], xb = x[b];
+        const Real sb = S[b];
+        const Real xb = monitor ? x[b] : (Real)0;  // the previous value only for the measures
         const Real xl = x[rv];
         const Real acc = node_row<Real>(val + base, blk, d, lane, xl);
         double r = 0.0, u = 0.0;
@@ -198,6 +223,29 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int N, int groups, const 
             if (lane == 0) meas[l] = make_float2((float)r, (float)u);
         }
     }
+}
+
+// The first Neumann iterate from x = 0 is the right-hand side itself: x = rhs, with the
+// node measures of that update (a sweep would add K 0 = 0 and give the same bits).
+template <class Real>
+__global__ __launch_bounds__(kSpmvThreads) void k_first(int N, const long long *__restrict__ adj_ptr,
+                                                       const Real *__restrict__ rhs, Real *__restrict__ x,
+                                                       float2 *__restrict__ meas) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int l = __builtin_amdgcn_readfirstlane(blockIdx.x * kNodesPerSpmvBlock + w);
+    if (l >= N) return;
+    const long long off = adj_ptr[l];
+    const int d = (int)(adj_ptr[l + 1] - off);
+    double r = 0.0, u = 0.0;
+    if (lane < d) {
+        const Real v = rhs[off + lane];
+        x[off + lane] = v;
+        r = fabs((double)v);
+        u = r / (r + kRelFloor);
+    }
+    r = wave_sum(r);
+    u = wave_max(u);
+    if (lane == 0) meas[l] = make_float2((float)r, (float)u);
 }
 
 // r = S - x + K x in FP64 (K values promoted), persistent; meas[node] = (sum |r|,
@@ -375,6 +423,13 @@ void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y
 }
 
 template <class Real>
+void launch_first(Scene &s, hipStream_t st, const Real *rhs, Real *x, double *out) {
+    hipLaunchKernelGGL((k_first<Real>), dim3(spmv_blocks(s)), dim3(kSpmvThreads), 0, st, s.N, s.adj_ptr, rhs, x,
+                       s.meas);
+    launch_measures(s, 1, out, st);
+}
+
+template <class Real>
 void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x64, double *r64, double *out) {
     hipLaunchKernelGGL((k_residual64<Real>), dim3(persistent_grid(s)), dim3(kSpmvThreads), block_lds<Real>(s), st,
                        s.N, spmv_blocks(s), s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x64, r64, s.meas,
@@ -389,11 +444,12 @@ void launch_apply_imk64(Scene &s, hipStream_t st, const double *v, double *w) {
 }
 
 void launch_measures(Scene &s, int nl, double *out, hipStream_t st) {
-    const int nc = node_chunks(s.N);
-    hipLaunchKernelGGL(k_measure_chunks, dim3(nc), dim3(kSpmvThreads), 0, st, (const float2 *)s.meas, s.N, nl,
-                       s.meas_part);
-    hipLaunchKernelGGL(k_measure_nodes, dim3(nl), dim3(kSpmvThreads), 0, st, (const double *)s.meas_part, nc, nl,
-                       out);
+    const int cn = node_chunk(s.N, nl), nc = (s.N + cn - 1) / cn;
+    const int lt = (nl + 63) / 64;
+    hipLaunchKernelGGL(k_measure_chunks, dim3(nc, nl == 1 ? 1 : lt), dim3(kSpmvThreads), 0, st,
+                       (const float2 *)s.meas, s.N, nl, cn, s.meas_part);
+    hipLaunchKernelGGL(k_measure_nodes, dim3(nl == 1 ? 1 : lt), dim3(kSpmvThreads), 0, st,
+                       (const double *)s.meas_part, nc, nl, out);
 }
 
 void launch_dot_multi(const double *V, int64_t ld, int k, const double *w, int64_t n, double *partial, int nblk,
@@ -433,6 +489,7 @@ void launch_fill(Real *a, Real v, int64_t n, hipStream_t st) {
 #define SG_INST(R)                                                                                           \
     template void launch_spmv<R>(Scene &, hipStream_t, const R *, const R *, R *, double *, int, hipEvent_t);               \
     template void launch_residual64<R>(Scene &, hipStream_t, const R *, const double *, double *, double *); \
+    template void launch_first<R>(Scene &, hipStream_t, const R *, R *, double *);                          \
     template void launch_apply_imk64<R>(Scene &, hipStream_t, const double *, double *);                  \
     template void launch_to64<R>(const R *, double *, int64_t, hipStream_t);                               \
     template void launch_scaled_to_real<R>(const double *, double, R *, int64_t, hipStream_t);             \
