@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -198,10 +199,7 @@ sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz,
             if (j == l) return fail(SG_E_INVALID, "self loop");
             if (e > ap[l] && d->adj_idx[e - 1] >= j) return fail(SG_E_INVALID, "adjacency rows must be strictly ascending");
             if (l >= nvox && j >= nvox) return fail(SG_E_INVALID, "surface-surface pair");
-            const int32_t *b = d->adj_idx + ap[j], *en = d->adj_idx + ap[j + 1];
-            const int32_t *it = std::lower_bound(b, en, (int32_t)l);
-            if (it == en || *it != l) return fail(SG_E_INVALID, "adjacency is not symmetric");
-        }
+        }  // symmetry is checked on the device once the adjacency is uploaded
     }
     return SG_OK;
 }
@@ -884,10 +882,16 @@ sg_status upload(Scene &s, void *dst, const void *src, size_t bytes, hipStream_t
     return SG_OK;
 }
 
+double host_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Scene &s) {
     int64_t N, E, nnz;
     int dmax;
+    const double t0 = host_ms();
     SG_TRY(validate(d, N, E, nnz, dmax));
+    const double t1 = host_ms();
     s.ctx = ctx;
     s.nx = d->nx; s.ny = d->ny; s.nz = d->nz;
     s.voxel_m = d->voxel_m;
@@ -958,6 +962,7 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
         SG_TRY(upload(s, s.abs_scale_d, s.abs_scale.data(), sizeof(float) * nl, st));
     }
 
+    const double t2 = host_ms();
     // host-side staging of the inputs
     std::vector<int32_t> pos((size_t)3 * s.N);
     std::memcpy(pos.data(), d->vol_pos_fx, sizeof(int32_t) * 3 * (size_t)s.nvox);
@@ -982,7 +987,19 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     if (s.E) SG_TRY(upload(s, s.adj_idx, d->adj_idx, sizeof(int32_t) * (size_t)s.E, st));
     SG_TRY(upload(s, s.lat, lat.data(), sizeof(double) * lat.size(), st));
     SG_TRY(upload(s, s.tab, tab.data(), sizeof(double) * tab.size(), st));
+    if (s.E) {
+        unsigned *bad = reinterpret_cast<unsigned *>(s.scal);
+        SG_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned), st));
+        launch_check_symmetric(s, bad, st);
+        unsigned nbad = 0;
+        SG_HIP(hipMemcpyAsync(&nbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+        SG_HIP(hipStreamSynchronize(st));
+        if (nbad) return fail(SG_E_INVALID, "adjacency is not symmetric (" + std::to_string(nbad) + " edges)");
+    }
     SG_HIP(hipStreamSynchronize(st));
+    if (sg_log())
+        fprintf(stderr, "[sgrt] scene create: validate %.2f ms, allocate %.2f ms, upload %.2f ms (%zu MB reserved)\n",
+                t1 - t0, t2 - t1, host_ms() - t2, (size_t)(s.bytes >> 20));
     return SG_OK;
 }
 
@@ -1042,6 +1059,7 @@ sg_status solve_scene(Scene &s, const sg_solve_opts &o, hipStream_t st, double *
     Ctx *ctx = s.ctx;
     std::lock_guard<std::mutex> lk(s.mu);
     SG_HIP(hipSetDevice(ctx->device));
+    ++s.solves;
     if (s.n_lambda > 1) {
         if (o.precision != SG_FP32) return fail(SG_E_INVALID, "several wavelengths are solved in FP32 only");
         return solve_batched(s, o, st, radiance, on_dev, info);

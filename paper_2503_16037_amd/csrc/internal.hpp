@@ -107,6 +107,7 @@ struct Scene {
     int spmv_grid = 0, spmm_grid = 0;       // tuned launch shapes (0 = not tuned yet)
     int spmv_grid_bytes = 0;                // element size spmv_grid was tuned for
 
+    int solves = 0;  // solves started on this scene
     bool solved = false;
     int last_precision = 0;
     int last_scatter_order = 0;
@@ -136,6 +137,8 @@ void clear_graphs(Scene &s);
 // ---- launchers (defined in the .hip files) ----
 void launch_structure(Scene &s, hipStream_t st);
 void launch_col_idx(Scene &s, hipStream_t st);
+// *bad += number of edges whose reverse edge is missing (*bad zeroed by the caller)
+void launch_check_symmetric(Scene &s, unsigned *bad, hipStream_t st);
 
 template <class Real>
 void launch_march(Scene &s, hipStream_t st, float scale, int use_lds);

@@ -4,10 +4,11 @@
 // Autotuner.  The persistent sweep kernels take any grid size, and their
 // results do not depend on it (every output element and every per-node norm
 // contribution is produced by one wavefront in a fixed order; the norms are
-// reduced by fixed-shape kernels).  The tuner times a short list of grid sizes
-// with HIP events on the scene's own data and keeps the fastest, per problem
-// shape, for the life of the process; SG_AUTOTUNE_CACHE names an optional text
-// file that keeps the choices across processes (one line per shape).
+// reduced by fixed-shape kernels).  From a scene's second solve on, the tuner
+// times a short list of grid sizes with HIP events on the scene's own data and
+// keeps the fastest, per problem shape, for the life of the process (a scene
+// solved once, as in serving, never pays for tuning); SG_AUTOTUNE_CACHE names
+// an optional text file that keeps the choices across processes.
 //
 // Graphs.  A chunk of sweeps is a fixed sequence of kernel launches on fixed
 // buffers.  The second time a scene runs the same chunk it is captured on the
@@ -109,6 +110,7 @@ int spmv_grid(Scene &s, hipStream_t st, const Real *S, Real *x, Real *y, bool au
     load_cache_locked();
     auto it = g_tuned.find(k);
     int grid = it != g_tuned.end() ? it->second : 0;
+    if (!grid && s.solves < 2) return 0;  // a scene's first solve does not tune
     if (!grid) {
         double *scratch = s.scal + 200;  // two measures (the tuned sweeps are monitored ones)
         launch_fill<Real>(x, (Real)0, s.E, st);  // x and y are scratch vectors here
@@ -123,7 +125,7 @@ int spmv_grid(Scene &s, hipStream_t st, const Real *S, Real *x, Real *y, bool au
 
 int spmm_grid(Scene &s, hipStream_t st, float *x, float *y, bool autotune) {
     const int groups = batched_groups(s);
-    const int fallback = std::max(1, std::min(groups, 2048));
+    const int fallback = groups;  // one node group per workgroup
     if (!autotune) return fallback;
     if (s.spmm_grid > 0) return s.spmm_grid;
     const TuneKey k{1, s.N, s.E, s.nnz, s.dmax, s.n_lambda, 4};
@@ -131,6 +133,7 @@ int spmm_grid(Scene &s, hipStream_t st, float *x, float *y, bool autotune) {
     load_cache_locked();
     auto it = g_tuned.find(k);
     int grid = it != g_tuned.end() ? it->second : 0;
+    if (!grid && s.solves < 2) return fallback;  // a scene's first solve does not tune
     if (!grid) {
         launch_fill_f32(x, (long long)s.E * s.n_lambda, st);  // x and y are scratch vectors here
         grid = time_candidates(st, grid_candidates(groups), [&](int g) { launch_spmm(s, st, g, nullptr, x, y, 1); });

@@ -408,13 +408,14 @@ static size_t block_lds(const Scene &s) {
 template <class Real>
 static int lds_dmax(const Scene &s) { return block_lds<Real>(s) ? s.dmax : 0; }
 
-// persistent grid: at most 8 workgroups per compute unit
-static int persistent_grid(const Scene &s) { return std::max(1, std::min(spmv_blocks(s), 256 * 8)); }
+// default launch shape of the sweeps: one group of four nodes per workgroup (the kernels
+// also run persistent over fewer workgroups; the tuner measures both)
+static int default_grid(const Scene &s) { return spmv_blocks(s); }
 
 template <class Real>
 void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *out, int grid,
                  hipEvent_t after) {
-    if (grid <= 0) grid = persistent_grid(s);
+    if (grid <= 0) grid = default_grid(s);
     grid = std::min(grid, spmv_blocks(s));
     hipLaunchKernelGGL((k_spmv<Real>), dim3(grid), dim3(kSpmvThreads), block_lds<Real>(s), st, s.N, spmv_blocks(s),
                        s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x, y, s.meas, out ? 1 : 0, lds_dmax<Real>(s));
@@ -431,7 +432,7 @@ void launch_first(Scene &s, hipStream_t st, const Real *rhs, Real *x, double *ou
 
 template <class Real>
 void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x64, double *r64, double *out) {
-    hipLaunchKernelGGL((k_residual64<Real>), dim3(persistent_grid(s)), dim3(kSpmvThreads), block_lds<Real>(s), st,
+    hipLaunchKernelGGL((k_residual64<Real>), dim3(default_grid(s)), dim3(kSpmvThreads), block_lds<Real>(s), st,
                        s.N, spmv_blocks(s), s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x64, r64, s.meas,
                        lds_dmax<Real>(s));
     launch_measures(s, 1, out, st);

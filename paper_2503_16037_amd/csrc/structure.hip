@@ -109,6 +109,27 @@ __global__ __launch_bounds__(256) void k_rev(int N, const long long *__restrict_
     }
 }
 
+// Symmetry of the adjacency (every edge l -> j has its reverse j -> l): counts the
+// edges whose reverse is missing (one wave per node, the search of k_rev).
+__global__ __launch_bounds__(256) void k_check_symmetric(int N, const long long *__restrict__ adj_ptr,
+                                                        const int *__restrict__ adj_idx, unsigned *__restrict__ bad) {
+    const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (l >= N) return;
+    const long long off = adj_ptr[l];
+    const int d = (int)(adj_ptr[l + 1] - off);
+    for (int m = lane; m < d; m += 64) {
+        const int j = adj_idx[off + m];
+        const long long end = adj_ptr[j + 1];
+        long long lo = adj_ptr[j], hi = end;
+        while (lo < hi) {
+            const long long mid = (lo + hi) >> 1;
+            if (adj_idx[mid] < l) lo = mid + 1; else hi = mid;
+        }
+        if (lo == end || adj_idx[lo] != l) atomicAdd(bad, 1u);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_row_ptr(int N, long long E, const long long *__restrict__ adj_ptr,
                                                 const long long *__restrict__ nodeoff,
                                                 long long *__restrict__ row_ptr) {
@@ -146,6 +167,11 @@ void launch_structure(Scene &s, hipStream_t st) {
     const int nb = (N + 3) / 4;
     hipLaunchKernelGGL(k_rev, dim3(nb), dim3(256), 0, st, N, s.adj_ptr, s.adj_idx, s.rev);
     hipLaunchKernelGGL(k_row_ptr, dim3(nb), dim3(256), 0, st, N, (long long)s.E, s.adj_ptr, s.nodeoff, s.row_ptr);
+}
+
+void launch_check_symmetric(Scene &s, unsigned *bad, hipStream_t st) {
+    const int nb = (s.N + 3) / 4;
+    hipLaunchKernelGGL(k_check_symmetric, dim3(nb), dim3(256), 0, st, s.N, s.adj_ptr, s.adj_idx, bad);
 }
 
 void launch_col_idx(Scene &s, hipStream_t st) {

@@ -88,6 +88,15 @@ class Scene:
         d = self.degrees().astype(np.int64)
         return int((d * d).sum())
 
+    def nbytes(self) -> int:
+        """Bytes of the input arrays handed to the library."""
+        arrs = [self.mu_s, self.mu_a, self.hg_g, self.vol_pos_fx, self.adj_ptr, self.adj_idx, self.surf_albedo]
+        if self.phase_frac is not None:
+            arrs.append(self.phase_frac)
+        if self.abs_scale is not None:
+            arrs.append(self.abs_scale)
+        return int(sum(a.nbytes for a in arrs))
+
     def all_positions(self) -> np.ndarray:
         """int64 [N, 3] positions of every node (volume then surface)."""
         pos = self.vol_pos_fx.astype(np.int64)
