@@ -54,29 +54,17 @@ sg_status device_fail(Ctx *ctx, const char *what, hipError_t e) {
         if (e_ != hipSuccess) return device_fail(ctx, #call, e_);      \
     } while (0)
 
-bool reserve(Ctx *ctx, uint64_t bytes) {
-    uint64_t cur = ctx->used.load();
-    while (true) {
-        if (cur + bytes > ctx->budget) return false;
-        if (ctx->used.compare_exchange_weak(cur, cur + bytes)) return true;
-    }
-}
-
-void release(Ctx *ctx, uint64_t bytes) { ctx->used.fetch_sub(bytes); }
 
 // Device allocation tracked against the context budget.
 template <class T>
 sg_status dalloc(Scene &s, T **p, size_t count) {
     Ctx *ctx = s.ctx;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    if (!reserve(ctx, bytes)) return fail(SG_E_NOMEM, "HBM budget exceeded");
-    hipError_t e = hipMalloc((void **)p, bytes);
-    if (e != hipSuccess) {
-        release(ctx, bytes);
-        (void)hipGetLastError();
-        return fail(SG_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    }
-    s.bytes += bytes;
+    void *q = nullptr;
+    const sg_status st = pool_alloc(ctx, bytes, &q);
+    if (st != SG_OK) return st;
+    *p = static_cast<T *>(q);
+    s.bytes += pool_round(bytes);
     return SG_OK;
 }
 
@@ -248,9 +236,8 @@ sg_status ensure_real(Scene &s) {
     Ctx *ctx = s.ctx;
     auto drop = [&](void *&p, size_t n) {
         if (p) {
-            (void)hipFree(p);
-            release(ctx, n);
-            s.bytes -= n;
+            pool_free(ctx, p);
+            s.bytes -= pool_round(n);
             p = nullptr;
         }
     };
@@ -387,9 +374,8 @@ sg_status gmres64(Scene &s, hipStream_t st, Exec &tm, const Real *S, double rtol
     const int64_t E = s.E;
     if (!s.gm_V || s.gm_m < m) {
         if (s.gm_V) {
-            (void)hipFree(s.gm_V);
-            release(ctx, (size_t)(s.gm_m + 1) * E * sizeof(double));
-            s.bytes -= (size_t)(s.gm_m + 1) * E * sizeof(double);
+            pool_free(ctx, s.gm_V);
+            s.bytes -= pool_round((size_t)(s.gm_m + 1) * E * sizeof(double));
             s.gm_V = nullptr;
         }
         SG_TRY(dalloc(s, &s.gm_V, (size_t)(m + 1) * E));
@@ -844,6 +830,7 @@ sg_status sg_ctx_destroy(sg_ctx *ctx) {
     if (!ctx) return fail(SG_E_INVALID, "ctx is NULL");
     if (ctx->n_scenes.load() != 0) return fail(SG_E_STATE, "context still has scenes");
     (void)hipSetDevice(ctx->device);
+    pool_trim(ctx, 0);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return SG_OK;
@@ -870,9 +857,8 @@ void free_scene_impl(Scene *s) {
                     s->tab, s->rev, s->nodeoff, s->row_ptr, s->col_idx, s->scan_tmp, s->tau_s, s->tau_a, s->tsun_s,
                     s->tsun_a, s->T, s->Tsun, s->rho, s->val, s->S, s->x, s->y, s->c_rhs, s->c_a, s->c_b, s->qsun,
                     s->q, s->bS, s->bx, s->by, s->brho, s->bsrc, s->lam_buf, s->x64, s->r64, s->gm_V, s->partial, s->meas, s->meas_part, s->scal, s->J, s->pix};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
-    if (s->ctx) release(s->ctx, s->bytes);
+    if (s->ctx)
+        for (void *p : ptrs) pool_free(s->ctx, p);
     s->bytes = 0;
 }
 
@@ -1086,8 +1072,9 @@ uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st) {
     int dmax;
     *st = validate(d, N, E, nnz, dmax);
     if (*st != SG_OK) return 0;
-    // mirrors the allocations of create_scene (each at least one element)
-    auto a = [](uint64_t count, uint64_t size) { return std::max<uint64_t>(count, 1) * size; };
+    // mirrors the allocations of create_scene (each at least one element, rounded as
+    // the pool rounds)
+    auto a = [](uint64_t count, uint64_t size) { return pool_round(std::max<uint64_t>(count, 1) * size); };
     const uint64_t nvox = (uint64_t)d->nx * d->ny * d->nz, npx = (uint64_t)d->nx * d->ny;
     const uint64_t nl = (uint64_t)d->n_lambda, nf = (uint64_t)d->n_fib, np = (uint64_t)d->n_phase;
     const uint64_t n = (uint64_t)N, e = (uint64_t)E, z = (uint64_t)nnz;

@@ -9,6 +9,7 @@
 #include <atomic>
 #include <functional>
 #include <map>
+#include <unordered_map>
 #include <cstdint>
 #include <mutex>
 #include <string>
@@ -28,6 +29,14 @@ struct SceneGraph {
     hipGraphExec_t exec = nullptr;
 };
 
+// Caching pool of device blocks (pool.cpp): size -> free block, and every block's size.
+struct Pool {
+    std::mutex mu;
+    std::multimap<uint64_t, void *> free_blocks;
+    std::unordered_map<void *, uint64_t> sizes;
+    uint64_t cached = 0;  // bytes in free_blocks
+};
+
 struct Ctx {
     int device = 0;
     uint64_t budget = 0;
@@ -35,7 +44,15 @@ struct Ctx {
     std::atomic<int> sticky{0};
     std::atomic<int> n_scenes{0};
     hipStream_t stream = nullptr;
+    Pool pool;
 };
+
+// ---- pool.cpp ----
+uint64_t pool_round(uint64_t bytes);  // the size the pool allocates for a request
+// a block of at least `bytes`, counted in ctx->used; SG_E_NOMEM beyond the budget
+sg_status pool_alloc(Ctx *ctx, uint64_t bytes, void **out);
+void pool_free(Ctx *ctx, void *ptr);  // back to the cache (NULL and foreign pointers ignored)
+void pool_trim(Ctx *ctx, uint64_t keep);  // release cached blocks down to `keep` bytes
 
 // Device arrays of one scene.  "Real" arrays hold float in FP32 solves and
 // double in FP64 solves; they are allocated for the precision of the first
