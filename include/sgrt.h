@@ -69,14 +69,18 @@ typedef struct sg_server sg_server;
 
 /*
  * Create a context on HIP device `hip_device`.  hbm_budget_bytes caps the
- * device memory the context's scenes may hold (0 = 90% of the device's
- * free memory at creation).  The context owns one default-priority HIP
- * stream, used when a call passes hip_stream = NULL.
+ * device memory the context holds (0 = 90% of the device's free memory at
+ * creation): the blocks of its live scenes plus the freed blocks it keeps
+ * for reuse by later scenes (a caching pool; kept blocks are released when
+ * a new allocation needs the room, and by sg_ctx_destroy).  The context
+ * owns one default-priority HIP stream, used when a call passes
+ * hip_stream = NULL.
  * Errors: SG_E_INVALID (bad device), SG_E_DEVICE.
  */
 sg_status sg_ctx_create(int32_t hip_device, uint64_t hbm_budget_bytes, sg_ctx **out);
 
-/* Destroy a context.  All its scenes must have been destroyed first (else SG_E_STATE). */
+/* Destroy a context and release its device memory.  All its scenes must have
+   been destroyed first (else SG_E_STATE). */
 sg_status sg_ctx_destroy(sg_ctx *ctx);
 
 /*
@@ -112,7 +116,10 @@ typedef struct sg_scene_desc {
 } sg_scene_desc;
 
 /*
- * Validate a scene on the host, copy it to the device and reserve the device
+ * Validate a scene (sizes, finite and bounded values, node positions strictly
+ * inside their voxels, strictly ascending adjacency rows without self loops
+ * or surface-surface pairs on the host; symmetry of the adjacency on the
+ * device after the upload), copy it to the device and reserve the device
  * memory of its FP32 solves (sg_solve allocates nothing for them).  FP64
  * solves, the optional CSR column index and the GMRES basis allocate their
  * arrays on first use and keep them until sg_scene_destroy.  The copies are
@@ -136,8 +143,9 @@ sg_status sg_scene_sizes(const sg_scene *scene, int64_t *n_nodes, int64_t *n_edg
 
 /*
  * Device bytes sg_scene_create would reserve for this description (validated
- * on the host; no device work).  Used for admission against an HBM budget.
- * Errors: those of validation (SG_E_ABI, SG_E_INVALID).
+ * on the host, except the adjacency's symmetry, which sg_scene_create checks
+ * on the device; no device work).  Used for admission against an HBM budget.
+ * Errors: those of host validation (SG_E_ABI, SG_E_INVALID).
  */
 sg_status sg_scene_reservation(const sg_scene_desc *desc, uint64_t *bytes);
 
@@ -245,9 +253,11 @@ typedef struct sg_server_opts {
 
 /*
  * Start a server on a context.  It admits queued scenes when a resident
- * slot is free and their reserved bytes fit the context's HBM budget,
- * overlaps the resident scenes' work on n_streams device streams, and
- * completes each ticket independently.
+ * slot is free and their reserved bytes, added to those of the admitted
+ * scenes, fit the context's HBM budget, overlaps the resident scenes' work
+ * on n_streams device streams, and completes each ticket independently.
+ * A scene whose adjacency is not symmetric is refused when it is admitted:
+ * its ticket completes with SG_E_INVALID.
  */
 sg_status sg_server_create(sg_ctx *ctx, const sg_server_opts *opts, sg_server **out);
 
