@@ -264,38 +264,37 @@ void or_rotation(const double u[3], double R[9]) {
     R[6] = ux;                R[7] = uy;                R[8] = c;
 }
 
-/* r = R s, each row as fma(R2, s2, fma(R1, s1, R0 * s0)). */
-static void rot_apply(const double R[9], const double s[3], double r[3]) {
-    for (int k = 0; k < 3; ++k) r[k] = fma(R[3 * k + 2], s[2], fma(R[3 * k + 1], s[1], R[3 * k] * s[0]));
+/* q = R^T p, each component as fma(R2k, p2, fma(R1k, p1, R0k * p0)). */
+static void rot_apply_t(const double R[9], const double p[3], double q[3]) {
+    for (int k = 0; k < 3; ++k) q[k] = fma(R[6 + k], p[2], fma(R[3 + k], p[1], R[k] * p[0]));
 }
 
-/* p . r as fma(p2, r2, fma(p1, r1, p0 * r0)). */
-static double dot3(const double p[3], const double r[3]) {
-    return fma(p[2], r[2], fma(p[1], r[1], p[0] * r[0]));
+/* q . s as fma(q2, s2, fma(q1, s1, q0 * s0)). */
+static double dot3(const double q[3], const double s[3]) {
+    return fma(q[2], s[2], fma(q[1], s[1], q[0] * s[0]));
 }
 
 /*
- * Lattice ownership (Eq. 7 and the definition of Sigma after it): lattice
- * point i belongs to the outgoing direction m with the largest p_i . r_m,
- * where r_m = R(u) s_m for an incoming propagation direction u (u == NULL:
- * no rotation, the Lambertian surface case).  Ties go to the smallest m,
- * which also drops a second coupling in exactly the same direction.
+ * Lattice ownership (Eq. 7 and the definition of Sigma after it): with the
+ * lattice rotated so that its pole is the incoming propagation direction u,
+ * lattice point i belongs to the outgoing direction m with the largest
+ * p_i . (R(u) s_m), evaluated as q_i . s_m with q_i = R(u)^T p_i (the same
+ * dot product; u == NULL: no rotation, the Lambertian surface case).  Ties
+ * go to the smallest m, which also drops a second coupling in exactly the
+ * same direction.
  */
 void or_ownership(const double *u, int d, const double *s /* [d][3] */, int N, const double *p,
                   int32_t *own) {
     double R[9];
-    double *r = (double *)malloc(sizeof(double) * 3 * (d > 0 ? d : 1));
-    if (u) {
-        or_rotation(u, R);
-        for (int m = 0; m < d; ++m) rot_apply(R, s + 3 * m, r + 3 * m);
-    } else {
-        memcpy(r, s, sizeof(double) * 3 * d);
-    }
+    if (u) or_rotation(u, R);
     for (int i = 0; i < N; ++i) {
+        double q[3];
+        if (u) rot_apply_t(R, p + 3 * i, q);
+        else memcpy(q, p + 3 * i, sizeof q);
         int best = -1;
         double bv = 0.0;
         for (int m = 0; m < d; ++m) {
-            double v = dot3(p + 3 * i, r + 3 * m);
+            double v = dot3(q, s + 3 * m);
             if (best < 0 || v > bv) {
                 best = m;
                 bv = v;
@@ -303,7 +302,6 @@ void or_ownership(const double *u, int d, const double *s /* [d][3] */, int N, c
         }
         own[i] = best;
     }
-    free(r);
 }
 
 /* ==================================================================== */
