@@ -585,7 +585,6 @@ sg_status neumann_batched(Scene &s, hipStream_t st, Exec &tm, const float *rhs, 
                           int relative, double stop, int max_sweeps, SolveStats &ss, int &stalled) {
     Ctx *ctx = s.ctx;
     const int nl = s.n_lambda;
-    const long long n = (long long)s.E * nl;
     const int grid = spmm_grid(s, st, xa, xb, tm.autotune);
     std::vector<double> host((size_t)64 * nl);
     std::vector<double> l1p(nl, -1.0), l1(nl, 0.0), relp(nl, -1.0), rel(nl, 0.0), l1first(nl, 0.0);

@@ -1,14 +1,18 @@
 // Phase-cell weights (Sec. 2, Eq. 7; Fibonacci lattice of Sec. 3) fused with the
 // flux-matrix values (Eq. 6) and the direct-solar source (Eq. 9).
 //
-// One 64-lane wavefront per node l.  Lane m holds out-edge m's unit direction;
-// each lane holds lattice points i = lane and lane + 64.  For every incoming
-// propagation direction u (each in-edge, then the sunlight) the out-directions
-// are rotated by the minimal rotation taking u to +z, each lattice point is
-// owned by the out-direction with the largest dot product (ties: lowest index),
-// and the owners' phase weights are summed in 2^-52 fixed point with LDS
-// integer atomics (exact, so the sum is independent of the order).
-// Surface nodes use the unrotated lattice with cosine weights (Lambertian).
+// One 64-lane wavefront per node l.  For every incoming propagation direction u
+// (each in-edge, then the sunlight) the lattice is rotated so that its pole is u,
+// each lattice point is owned by the out-edge direction s_m with the largest dot
+// product (ties: lowest index), and the owners' phase weights are summed in 2^-52
+// fixed point with LDS integer atomics (exact, so the sum is independent of the
+// order).  Surface nodes use the unrotated lattice with cosine weights (Lambertian).
+//
+// The incoming directions are processed in groups of G; the G x N_fib (direction,
+// lattice point) pairs are spread over the lanes, eight per lane, so every out-edge
+// direction read from LDS serves eight dot products per lane: the kernel is bound by
+// FP64 issue, not by LDS broadcasts.  Each direction's column of the node block
+// (column-major) is one coalesced store.
 //
 // The ownership decision is an argmax over double-precision dot products; it is
 // written with this exact operation sequence (also followed by the FP64 CPU
@@ -16,9 +20,9 @@
 //   s_m  = D_m / sqrt(Dx^2 + Dy^2 + Dz^2)             (exact integer sum)
 //   h    = 1 / (1 + u_z);  xy = (u_x u_y) h
 //   R    = [[u_z + (u_y u_y) h, -xy, -u_x], [-xy, u_z + (u_x u_x) h, -u_y], [u_x, u_y, u_z]]
-//          (R = diag(1, -1, -1) when 1 + u_z < 1e-12)
-//   r_mk = fma(R_k2, s_m2, fma(R_k1, s_m1, R_k0 s_m0))
-//   v_im = fma(p_i2, r_m2, fma(p_i1, r_m1, p_i0 r_m0))
+//          (R = diag(1, -1, -1) when 1 + u_z < 1e-12; the identity on the surface)
+//   q_ik = fma(R_2k, p_i2, fma(R_1k, p_i1, R_0k p_i0))      (q_i = R^T p_i)
+//   v_im = fma(q_i2, s_m2, fma(q_i1, s_m1, q_i0 s_m0))      (= p_i . R s_m)
 // with no other contraction, hence the pragma below and -ffp-contract=off.
 #include "device.hpp"
 #include "internal.hpp"
@@ -31,6 +35,12 @@ namespace {
 
 constexpr double kFix = 4503599627370496.0;  // 2^52
 constexpr double kUnfix = 1.0 / 4503599627370496.0;
+constexpr int kQSlots = 8;     // (direction, lattice point) pairs per lane in a group
+constexpr int kQMaxGroup = 8;  // incoming directions per group
+
+// LDS layout of a node (doubles): sites [3][64], rotations [kQMaxGroup][9], lattice
+// weights [128] (fixed point), bins [kQMaxGroup][64] (fixed point)
+constexpr int kQLds = 192 + kQMaxGroup * 9 + 128 + kQMaxGroup * 64;
 
 template <class Real, class BlkT, bool kWriteQ>
 __global__ __launch_bounds__(64) void k_qbuild(
@@ -38,12 +48,13 @@ __global__ __launch_bounds__(64) void k_qbuild(
     const int *__restrict__ pos, const double *__restrict__ lat, const double *__restrict__ tab, int NF, int n_phase,
     const float *__restrict__ frac, double sun_x, double sun_y, double sun_z, Real mu0, const Real *__restrict__ T,
     const Real *__restrict__ rho, const Real *__restrict__ Tsun, const long long *__restrict__ nodeoff,
-    BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun) {
+    BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun, int group) {
 #pragma clang fp contract(off)
-    extern __shared__ double smem[];
+    __shared__ double smem[kQLds];
     double *sx = smem, *sy = smem + 64, *sz = smem + 128;
-    double *rx = smem + 192, *ry = smem + 256, *rz = smem + 320;
-    unsigned long long *bins = reinterpret_cast<unsigned long long *>(smem + 384);
+    double *Rg = smem + 192;
+    unsigned long long *wq = reinterpret_cast<unsigned long long *>(smem + 192 + kQMaxGroup * 9);
+    unsigned long long *bins = wq + 128;
 
     const int l = blockIdx.x;
     const int lane = threadIdx.x;
@@ -62,27 +73,8 @@ __global__ __launch_bounds__(64) void k_qbuild(
         sy[lane] = (double)Dy / nrm;
         sz[lane] = (double)Dz / nrm;
     }
-    // lattice points and their phase weights in fixed point
-    const bool has0 = lane < NF, has1 = lane + 64 < NF;
-    double p0x = 0, p0y = 0, p0z = 0, p1x = 0, p1y = 0, p1z = 0;
-    unsigned long long w0 = 0, w1 = 0;
-    if (has0) {
-        p0x = lat[3 * lane]; p0y = lat[3 * lane + 1]; p0z = lat[3 * lane + 2];
-        double w;
-        if (surf) {
-            w = tab[n_phase * NF + lane];
-        } else {
-            w = 0.0;
-            for (int k = 0; k < n_phase; ++k) {
-                const double f = frac ? (double)frac[(long long)k * nvox + l] : 1.0;
-                w = w + f * tab[k * NF + lane];
-            }
-        }
-        w0 = (unsigned long long)llrint(w * kFix);
-    }
-    if (has1) {
-        const int i = lane + 64;
-        p1x = lat[3 * i]; p1y = lat[3 * i + 1]; p1z = lat[3 * i + 2];
+    // phase weights of the lattice points in fixed point
+    for (int i = lane; i < NF; i += 64) {
         double w;
         if (surf) {
             w = tab[n_phase * NF + i];
@@ -93,71 +85,91 @@ __global__ __launch_bounds__(64) void k_qbuild(
                 w = w + f * tab[k * NF + i];
             }
         }
-        w1 = (unsigned long long)llrint(w * kFix);
+        wq[i] = (unsigned long long)llrint(w * kFix);
     }
-    __syncthreads();
 
     const Real rl = rho ? rho[l] : (Real)0;
     const Real tsun = Tsun ? Tsun[l] : (Real)0;
-    // the node's block, column-major: element (row = out-edge n, column = in-edge m) at
-    // m d + n, so each column is one coalesced store of d values
-    BlkT *blk = val + nodeoff[l];
+    BlkT *blk = val + nodeoff[l];  // column-major: element (row n, column m) at m d + n
     const int n_in = surf ? 1 : d + 1;
-    for (int a = 0; a < n_in; ++a) {
-        if (lane < d) {
-            const double s0 = sx[lane], s1 = sy[lane], s2 = sz[lane];
+    for (int a0 = 0; a0 < n_in; a0 += group) {
+        const int ng = min(group, n_in - a0);
+        // rotations of this group's incoming directions, and empty bins
+        if (lane < ng) {
+            const int a = a0 + lane;
+            double *R = Rg + 9 * lane;
             if (surf) {
-                rx[lane] = s0; ry[lane] = s1; rz[lane] = s2;
+                R[0] = 1.0; R[1] = 0.0; R[2] = 0.0; R[3] = 0.0; R[4] = 1.0; R[5] = 0.0; R[6] = 0.0; R[7] = 0.0;
+                R[8] = 1.0;
             } else {
                 double ux, uy, uz;
                 if (a < d) { ux = -sx[a]; uy = -sy[a]; uz = -sz[a]; }
                 else { ux = sun_x; uy = sun_y; uz = sun_z; }
-                double R0, R1, R2, R3, R4, R5, R6, R7, R8;
                 if (1.0 + uz < 1e-12) {
-                    R0 = 1.0; R1 = 0.0; R2 = 0.0; R3 = 0.0; R4 = -1.0; R5 = 0.0; R6 = 0.0; R7 = 0.0; R8 = -1.0;
+                    R[0] = 1.0; R[1] = 0.0; R[2] = 0.0; R[3] = 0.0; R[4] = -1.0; R[5] = 0.0; R[6] = 0.0;
+                    R[7] = 0.0; R[8] = -1.0;
                 } else {
                     const double h = 1.0 / (1.0 + uz);
                     const double xy = (ux * uy) * h;
-                    R0 = uz + (uy * uy) * h; R1 = -xy; R2 = -ux;
-                    R3 = -xy; R4 = uz + (ux * ux) * h; R5 = -uy;
-                    R6 = ux; R7 = uy; R8 = uz;
+                    R[0] = uz + (uy * uy) * h; R[1] = -xy; R[2] = -ux;
+                    R[3] = -xy; R[4] = uz + (ux * ux) * h; R[5] = -uy;
+                    R[6] = ux; R[7] = uy; R[8] = uz;
                 }
-                rx[lane] = fma(R2, s2, fma(R1, s1, R0 * s0));
-                ry[lane] = fma(R5, s2, fma(R4, s1, R3 * s0));
-                rz[lane] = fma(R8, s2, fma(R7, s1, R6 * s0));
             }
-            bins[lane] = 0ull;
         }
+        for (int t = lane; t < ng * 64; t += 64) bins[t] = 0ull;
         __syncthreads();
-        // argmax with ties to the lowest index: the index moves only on a strict
-        // increase, and the running maximum (fmax) equals the kept value on ties
-        int o0 = 0, o1 = 0;
-        double b0 = -__builtin_inf(), b1 = -__builtin_inf();
+        // this lane's pairs: q = R^T p for each, then the running argmax over the sites
+        double q0[kQSlots], q1[kQSlots], q2[kQSlots], best[kQSlots];
+        int own[kQSlots];
+#pragma unroll
+        for (int j = 0; j < kQSlots; ++j) {
+            const int p = min(j * 64 + lane, ng * NF - 1);  // past the last pair: a repeat, not counted
+            const int al = p / NF, i = p - al * NF;
+            const double *R = Rg + 9 * al;
+            const double x = lat[3 * i], y = lat[3 * i + 1], z = lat[3 * i + 2];
+            q0[j] = fma(R[6], z, fma(R[3], y, R[0] * x));
+            q1[j] = fma(R[7], z, fma(R[4], y, R[1] * x));
+            q2[j] = fma(R[8], z, fma(R[5], y, R[2] * x));
+            best[j] = -__builtin_inf();
+            own[j] = 0;
+        }
+        // ties go to the lowest index: the index moves only on a strict increase, and
+        // the running maximum (fmax) equals the kept value on ties
+#pragma unroll 2
         for (int m = 0; m < d; ++m) {
-            const double qx = rx[m], qy = ry[m], qz = rz[m];
-            const double v0 = fma(p0z, qz, fma(p0y, qy, p0x * qx));
-            const double v1 = fma(p1z, qz, fma(p1y, qy, p1x * qx));
-            o0 = v0 > b0 ? m : o0;
-            o1 = v1 > b1 ? m : o1;
-            b0 = fmax(b0, v0);
-            b1 = fmax(b1, v1);
+            const double tx = sx[m], ty = sy[m], tz = sz[m];
+#pragma unroll
+            for (int j = 0; j < kQSlots; ++j) {
+                const double v = fma(q2[j], tz, fma(q1[j], ty, q0[j] * tx));
+                own[j] = v > best[j] ? m : own[j];
+                best[j] = fmax(best[j], v);
+            }
         }
-        if (has0) atomicAdd(&bins[o0], w0);
-        if (has1) atomicAdd(&bins[o1], w1);
+#pragma unroll
+        for (int j = 0; j < kQSlots; ++j) {
+            const int p = j * 64 + lane;
+            if (p < ng * NF) {
+                const int al = p / NF;
+                atomicAdd(&bins[al * 64 + own[j]], wq[p - al * NF]);
+            }
+        }
         __syncthreads();
-        if (lane < d) {
-            const double Q = (double)(long long)bins[lane] * kUnfix;
-            const long long b = off + lane;
+        // this group's columns: pair t = (a - a0) d + m is column a, row m
+        for (int t = lane; t < ng * d; t += 64) {
+            const int al = t / d, m = t - al * d, a = a0 + al;
+            const double Q = (double)(long long)bins[al * 64 + m] * kUnfix;
+            const long long b = off + m;
             if (surf) {
-                for (int m = 0; m < d; ++m) {
-                    if (kWriteQ) blk[m * d + lane] = (BlkT)Q;
-                    else blk[m * d + lane] = (BlkT)(T[off + m] * rl * (Real)Q);
+                for (int c = 0; c < d; ++c) {
+                    if (kWriteQ) blk[c * d + m] = (BlkT)Q;
+                    else blk[c * d + m] = (BlkT)(T[off + c] * rl * (Real)Q);
                 }
                 if (!kWriteQ) S[b] = rl * mu0 * tsun * (Real)Q;
                 qsun[b] = (float)Q;
             } else if (a < d) {
-                if (kWriteQ) blk[a * d + lane] = (BlkT)Q;
-                else blk[a * d + lane] = (BlkT)(T[off + a] * rl * (Real)Q);
+                if (kWriteQ) blk[a * d + m] = (BlkT)Q;
+                else blk[a * d + m] = (BlkT)(T[off + a] * rl * (Real)Q);
             } else {
                 if (!kWriteQ) S[b] = tsun * rl * (Real)Q;
                 qsun[b] = (float)Q;
@@ -167,21 +179,25 @@ __global__ __launch_bounds__(64) void k_qbuild(
     }
 }
 
+// directions per group: as many as fill the lanes' pair slots
+int qbuild_group(int NF) { return std::max(1, std::min(kQMaxGroup, kQSlots * 64 / NF)); }
+
 }  // namespace
 
 template <class Real>
 void launch_qbuild(Scene &s, hipStream_t st, int write_q) {
-    const size_t shm = 448 * sizeof(double);
+    const size_t shm = 0;
+    const int group = qbuild_group(s.n_fib);
     if (write_q) {
         hipLaunchKernelGGL((k_qbuild<Real, float, true>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
                            s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
                            s.sun_in[2], (Real)s.mu0, (const Real *)nullptr, (const Real *)nullptr,
-                           (const Real *)nullptr, s.nodeoff, s.q, (Real *)nullptr, s.qsun);
+                           (const Real *)nullptr, s.nodeoff, s.q, (Real *)nullptr, s.qsun, group);
     } else {
         hipLaunchKernelGGL((k_qbuild<Real, Real, false>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
                            s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
                            s.sun_in[2], (Real)s.mu0, (const Real *)s.T, (const Real *)s.rho, (const Real *)s.Tsun,
-                           s.nodeoff, (Real *)s.val, (Real *)s.S, s.qsun);
+                           s.nodeoff, (Real *)s.val, (Real *)s.S, s.qsun, group);
     }
 }
 
