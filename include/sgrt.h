@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define SG_ABI_VERSION 1u
+#define SG_ABI_VERSION 2u
 
 typedef int32_t sg_status;
 enum {
@@ -168,6 +168,14 @@ typedef struct sg_solve_opts {
     int32_t timing;        /* 1: per-stage HIP-event timings into sg_solve_info */
     int32_t flags;         /* SG_NO_GRAPHS: launch sweep chunks one by one instead of replaying
                               captured HIP graphs; SG_NO_AUTOTUNE: default launch shapes */
+    int32_t lambda_tile;   /* scenes of several wavelengths: wavelength lanes per node in the
+                              sweep kernels, 8, 16, 32 or 64 (a wavefront then holds 64 /
+                              lambda_tile nodes); at least n_lambda unless 64 (more than 64
+                              wavelengths take several 64-lane tiles).  0: the library's choice
+                              (8 or 16 when they hold n_lambda, else 64; from a scene's second
+                              solve on, the autotuner's).  A set tile uses the default grid.
+                              The tile does not change any result bit.  Ignored for one
+                              wavelength. */
 } sg_solve_opts;
 enum { SG_NO_GRAPHS = 1, SG_NO_AUTOTUNE = 2 };
 

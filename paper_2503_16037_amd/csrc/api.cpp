@@ -581,11 +581,10 @@ sg_status solve_single(Scene &s, const sg_solve_opts &o, hipStream_t st, double 
 // A wavelength is done once its stop is met or predicted; stall = a wavelength not done
 // whose L1 ratio (and relative ratio, when that decides the stop) reaches 0.95.  Only the first sweep and the last two of each chunk
 // compute measures.
-sg_status neumann_batched(Scene &s, hipStream_t st, Exec &tm, const float *rhs, float *&xa, float *&xb,
+sg_status neumann_batched(Scene &s, hipStream_t st, Exec &tm, int grid, const float *rhs, float *&xa, float *&xb,
                           int relative, double stop, int max_sweeps, SolveStats &ss, int &stalled) {
     Ctx *ctx = s.ctx;
     const int nl = s.n_lambda;
-    const int grid = spmm_grid(s, st, xa, xb, tm.autotune);
     std::vector<double> host((size_t)64 * nl);
     std::vector<double> l1p(nl, -1.0), l1(nl, 0.0), relp(nl, -1.0), rel(nl, 0.0), l1first(nl, 0.0);
     std::vector<int> done(nl, 0);
@@ -617,7 +616,7 @@ sg_status neumann_batched(Scene &s, hipStream_t st, Exec &tm, const float *rhs, 
             }
         } else {
             const GraphKey key{2, (uintptr_t)chunk, (uintptr_t)rhs, (uintptr_t)xa, (uintptr_t)xb, (uintptr_t)grid,
-                               (uintptr_t)first, 0};
+                               (uintptr_t)first, (uintptr_t)s.tile};
             float *a0 = xa, *b0 = xb;
             SG_TRY(run_chunk(s, st, key, tm.graphs, [&]() {
                 float *a = a0, *b = b0;
@@ -686,11 +685,16 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
     const double rtol = o.rtol > 0 ? o.rtol : 1e-6;
     const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 2000;
     if (o.solver == SG_SOLVER_GMRES) return fail(SG_E_INVALID, "GMRES is available for single-wavelength scenes");
-    const int rgrid = std::max(1, std::min(batched_groups(s), 2048));  // FP64 pass: default shape
+    if (o.lambda_tile > 0 && o.lambda_tile < 64 && o.lambda_tile < smallest_tile(nl))
+        return fail(SG_E_INVALID, "lambda_tile " + std::to_string(o.lambda_tile) + " is narrower than the " +
+                                      std::to_string(nl) + " wavelengths");
     float *xa = s.bx, *xb = s.by;
+    const int grid = spmm_grid(s, st, xa, xb, tm.autotune, o.lambda_tile);  // sets s.tile
+    const int rgrid = batched_groups(s);  // FP64 pass: the tile's default grid
     int stalled = 0;
     // per-edge relative updates settle at a few FP32 rounding units: never ask for less
-    SG_TRY(neumann_batched(s, st, tm, nullptr, xa, xb, 1, std::max(0.3 * rtol, 4e-6), max_sweeps, ss, stalled));
+    SG_TRY(neumann_batched(s, st, tm, grid, nullptr, xa, xb, 1, std::max(0.3 * rtol, 4e-6), max_sweeps, ss,
+                           stalled));
     launch_f32_to_64(xa, s.x64, n, st);
     std::vector<double> m2((size_t)2 * nl), sc(nl);
     double *d_sc = s.lam_buf;  // [nl]
@@ -715,7 +719,7 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
         launch_lam_scale_to_f32(s.r64, d_sc, nl, s.bS, n, st);
         float *ca = s.bx, *cb = s.by;
         int st2 = 0;
-        SG_TRY(neumann_batched(s, st, tm, s.bS, ca, cb, 0, 1e-5, max_sweeps, ss, st2));
+        SG_TRY(neumann_batched(s, st, tm, grid, s.bS, ca, cb, 0, 1e-5, max_sweeps, ss, st2));
         launch_lam_axpy(s.x64, ca, d_sc, nl, n, st);
         if (st2) stalled = 1;
     }
@@ -1063,6 +1067,8 @@ sg_status check_opts(const sg_solve_opts *opts, sg_solve_opts &o) {
     if (o.precision != SG_FP32 && o.precision != SG_FP64) return fail(SG_E_INVALID, "precision must be SG_FP32 or SG_FP64");
     if (o.solver < 0 || o.solver > 2) return fail(SG_E_INVALID, "bad solver");
     if (o.scatter_order != 0 && o.scatter_order != 1) return fail(SG_E_INVALID, "scatter_order must be 0 or 1");
+    if (o.lambda_tile != 0 && o.lambda_tile != 8 && o.lambda_tile != 16 && o.lambda_tile != 32 && o.lambda_tile != 64)
+        return fail(SG_E_INVALID, "lambda_tile must be 0, 8, 16, 32 or 64");
     return SG_OK;
 }
 

@@ -215,6 +215,136 @@ __global__ __launch_bounds__(256) void k_bfirst(int N, int nl, const long long *
     meas[(long long)l * nl + lam] = make_float2((float)sum, (float)mrel);
 }
 
+// ---- wavelength tiles narrower than a wavefront -------------------------------------
+// For n_lambda <= 32 a wavefront holds 64 / W node slots of W wavelength lanes each, so
+// a small wavelength count does not leave lanes idle.  Each slot's in-edge data (rev,
+// tau_s, tau_a) goes to a small LDS slice; the phase-cell columns are read straight
+// from memory with 16-byte loads (the lanes of a slot share the addresses, so each
+// load costs one request per slot).  Per lane the arithmetic is exactly that of the
+// full-wavefront kernel (same expressions, columns in the same order), so the two give
+// the same bits.
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+
+template <int DB, class XT, class AccT, bool kResidual>
+__device__ __forceinline__ float2 pack_node(int l, int lam, bool lv, float s, int nl, int monitor, long long off,
+                                            int d, long long base, int dw, const int *__restrict__ srv,
+                                            const float *__restrict__ sts, const float *__restrict__ sta,
+                                            const float *__restrict__ q, const float *__restrict__ qsun,
+                                            const float *__restrict__ brho, const float *__restrict__ bsrc,
+                                            const float *__restrict__ rhs, const XT *__restrict__ x,
+                                            XT *__restrict__ y) {
+    AccT acc[DB];
+#pragma unroll
+    for (int n = 0; n < DB; ++n) acc[n] = (AccT)0;
+    for (int m = 0; m < dw; ++m) {
+        // slots with fewer in-edges repeat their last column with a zero input: adding
+        // Q * 0 leaves every valid row's sum unchanged
+        const bool mv = m < d;
+        const int mc = min(m, d - 1);
+        const XT xin = (mv && lv) ? x[(long long)srv[mc] * nl + lam] : (XT)0;
+        const AccT xm = (AccT)edge_T(sts[mc], sta[mc], s) * (AccT)xin;
+        const f4u *qm = reinterpret_cast<const f4u *>(q + base + (long long)mc * d);
+#pragma unroll
+        for (int c = 0; c < DB / 4; ++c) {
+            const f4u v = qm[c];
+            acc[4 * c] += (AccT)v.x * xm;
+            acc[4 * c + 1] += (AccT)v.y * xm;
+            acc[4 * c + 2] += (AccT)v.z * xm;
+            acc[4 * c + 3] += (AccT)v.w * xm;
+        }
+    }
+    double sum = 0.0, mrel = 0.0;
+    if (lv) {
+        const float rl = brho[(long long)l * nl + lam];
+        const float sl = bsrc[(long long)l * nl + lam];
+#pragma unroll
+        for (int n = 0; n < DB; ++n) {
+            if (n < d) {
+                const long long b = off + n;
+                const long long bi = b * nl + lam;
+                if (kResidual) {
+                    const double Sb = (double)(rl * sl * qsun[b]);
+                    const double rb = (Sb - (double)x[bi]) + (double)rl * (double)acc[n];
+                    y[bi] = (XT)rb;
+                    sum += fabs(rb);
+                    mrel = fmax(mrel, fabs(rb) / (fabs((double)x[bi]) + kRelFloor));
+                } else {
+                    const float src = rhs ? rhs[bi] : rl * sl * qsun[b];
+                    const float yv = src + rl * (float)acc[n];
+                    y[bi] = (XT)yv;
+                    if (monitor) {
+                        const double du = fabs((double)yv - (double)x[bi]);
+                        sum += du;
+                        mrel = fmax(mrel, du / (fabs((double)yv) + kRelFloor));
+                    }
+                }
+            }
+        }
+    }
+    return make_float2((float)sum, (float)mrel);
+}
+
+template <int W, int D, class XT, class AccT, bool kResidual>
+__global__ __launch_bounds__(256) void k_spmm_pack(
+    int N, int nl, int groups, const long long *__restrict__ adj_ptr, const long long *__restrict__ nodeoff,
+    const int *__restrict__ rev, const float *__restrict__ q, const float *__restrict__ qsun,
+    const float *__restrict__ tau_s, const float *__restrict__ tau_a, const float *__restrict__ abs_scale,
+    const float *__restrict__ brho, const float *__restrict__ bsrc, const float *__restrict__ rhs,
+    const XT *__restrict__ x, XT *__restrict__ y, float2 *__restrict__ meas, int monitor) {
+    constexpr int P = 64 / W;  // node slots per wavefront
+    __shared__ int srv_all[4][P][64];
+    __shared__ float sts_all[4][P][64], sta_all[4][P][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int k = lane / W, lam = lane - k * W;
+    const bool lam_ok = lam < nl;
+    const float s = lam_ok ? abs_scale[lam] : 0.f;
+    int *srv = srv_all[w][k];
+    float *sts = sts_all[w][k], *sta = sta_all[w][k];
+    for (int g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int l0 = __builtin_amdgcn_readfirstlane((g * 4 + w) * P);
+        if (l0 >= N) break;
+        const int l = l0 + k;
+        const bool node_ok = l < N;
+        long long off = 0, base = 0;
+        int d = 0;
+        if (node_ok) {
+            off = adj_ptr[l];
+            d = (int)(adj_ptr[l + 1] - off);
+            base = nodeoff[l];
+        }
+        for (int m = lam; m < d; m += W) {
+            const long long e = off + m;
+            srv[m] = rev[e];
+            sts[m] = tau_s[e];
+            sta[m] = tau_a[e];
+        }
+        __builtin_amdgcn_wave_barrier();
+        int dw = d;  // the wavefront's largest degree (uniform loop bound)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) dw = max(dw, __shfl_xor(dw, o, 64));
+        dw = __builtin_amdgcn_readfirstlane(dw);
+        const bool lv = node_ok && lam_ok && d > 0;
+        float2 part = make_float2(0.f, 0.f);
+        if (dw > 0) {
+            const int bucket = (dw + 7) >> 3;
+#define SG_PACK(DB)                                                                                        \
+    part = pack_node<DB, XT, AccT, kResidual>(l, lam, lv, s, nl, monitor, off, max(d, 1), base, dw, srv, sts, \
+                                              sta, q, qsun, brho, bsrc, rhs, x, y)
+            if (bucket <= 1) { SG_PACK(8); }
+            else if (bucket == 2) { if constexpr (D >= 16) SG_PACK(16); }
+            else if (bucket == 3) { if constexpr (D >= 24) SG_PACK(24); }
+            else if (bucket == 4) { if constexpr (D >= 32) SG_PACK(32); }
+            else if (bucket == 5) { if constexpr (D >= 40) SG_PACK(40); }
+            else if (bucket == 6) { if constexpr (D >= 48) SG_PACK(48); }
+            else if (bucket == 7) { if constexpr (D >= 56) SG_PACK(56); }
+            else { if constexpr (D >= 64) SG_PACK(64); }
+#undef SG_PACK
+        }
+        if (monitor && node_ok && lam_ok) meas[(long long)l * nl + lam] = part;
+        __builtin_amdgcn_wave_barrier();  // the slices are rewritten by the next group
+    }
+}
+
 __global__ void k_lam_scale_to_f32(const double *__restrict__ a, const double *__restrict__ sc, int nl,
                                    float *__restrict__ b, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -364,10 +494,48 @@ void launch_bnode_coef(Scene &s, hipStream_t st) {
 // wavefronts per workgroup: four unless the LDS slices of the phase-cell blocks would pass 60 KB
 int wide_waves(const Scene &s) { return (size_t)4 * (s.dmax * s.dmax + 64) * sizeof(float) <= 60 * 1024 ? 4 : 2; }
 
+// Wavelength lanes per node: 8, 16, 32 or 64 (counts above 64 use several 64-lane
+// columns of the full-wavefront kernel).  The narrow tiles read the phase-cell columns
+// through the vector cache, once per node slot; the full-wavefront kernel stages them
+// in LDS.  Measured on MI355X, 8 and 16 lanes beat the full wavefront by up to 2x while
+// 32 lanes lose to it by about 1.5x, so 32 is left to the autotuner.
+int smallest_tile(int n_lambda) { return n_lambda <= 8 ? 8 : n_lambda <= 16 ? 16 : n_lambda <= 32 ? 32 : 64; }
+int default_tile(int n_lambda) { return smallest_tile(n_lambda) <= 16 ? smallest_tile(n_lambda) : 64; }
+
+static int lambda_tile(const Scene &s) { return s.tile >= smallest_tile(s.n_lambda) ? s.tile : 64; }
+
+int batched_groups(const Scene &s) {
+    const int W = lambda_tile(s);
+    if (W < 64) return (s.N + 4 * (64 / W) - 1) / (4 * (64 / W));
+    return (s.N + wide_waves(s) - 1) / wide_waves(s);
+}
+
+template <int W, class XT, class AccT, bool kRes>
+static void launch_pack(Scene &s, hipStream_t st, int grid, const float *rhs, const XT *x, XT *y, int monitor) {
+    const int groups = batched_groups(s);
+#define SG_PK(DD)                                                                                                  \
+    hipLaunchKernelGGL((k_spmm_pack<W, DD, XT, AccT, kRes>), dim3(grid), dim3(256), 0, st, s.N, s.n_lambda, groups,  \
+                       s.adj_ptr, s.nodeoff, s.rev, s.q, s.qsun, (const float *)s.tau_s, (const float *)s.tau_a,      \
+                       s.abs_scale_d, s.brho, s.bsrc, rhs, x, y, s.meas, monitor)
+    if (s.dmax <= 16) SG_PK(16);
+    else if (s.dmax <= 24) SG_PK(24);
+    else if (s.dmax <= 32) SG_PK(32);
+    else if (s.dmax <= 40) SG_PK(40);
+    else if (s.dmax <= 48) SG_PK(48);
+    else if (s.dmax <= 56) SG_PK(56);
+    else SG_PK(64);
+#undef SG_PK
+}
+
 template <class XT, class AccT, bool kRes>
-static bool launch_wide(Scene &s, hipStream_t st, int grid, const float *rhs, const XT *x, XT *y, int monitor) {
+static void launch_wide(Scene &s, hipStream_t st, int grid, const float *rhs, const XT *x, XT *y, int monitor) {
+    const int W = lambda_tile(s);
+    grid = std::max(1, std::min(grid, batched_groups(s)));
+    if (W == 8) return launch_pack<8, XT, AccT, kRes>(s, st, grid, rhs, x, y, monitor);
+    if (W == 16) return launch_pack<16, XT, AccT, kRes>(s, st, grid, rhs, x, y, monitor);
+    if (W == 32) return launch_pack<32, XT, AccT, kRes>(s, st, grid, rhs, x, y, monitor);
     const int waves = wide_waves(s);
-    const int groups = (s.N + waves - 1) / waves;
+    const int groups = batched_groups(s);
     dim3 gr(grid, (s.n_lambda + 63) / 64);
     const size_t shm = (size_t)waves * (s.dmax * s.dmax + 64) * sizeof(float);
 #define SG_WIDE(DD)                                                                                                 \
@@ -382,10 +550,7 @@ static bool launch_wide(Scene &s, hipStream_t st, int grid, const float *rhs, co
     else if (s.dmax <= 56) SG_WIDE(56);
     else SG_WIDE(64);
 #undef SG_WIDE
-    return true;
 }
-
-int batched_groups(const Scene &s) { return (s.N + wide_waves(s) - 1) / wide_waves(s); }
 
 void launch_spmm(Scene &s, hipStream_t st, int grid, const float *rhs, const float *x, float *y, int monitor) {
     launch_wide<float, float, false>(s, st, grid, rhs, x, y, monitor);

@@ -122,6 +122,8 @@ struct Scene {
 
     std::map<GraphKey, SceneGraph> graphs;  // captured sweep chunks
     int spmv_grid = 0, spmm_grid = 0;       // tuned launch shapes (0 = not tuned yet)
+    int spmm_tile = 0;                      // tuned wavelength tile of the batched sweeps
+    int tile = 64;                          // wavelength tile of the current batched solve
     int spmv_grid_bytes = 0;                // element size spmv_grid was tuned for
 
     int solves = 0;  // solves started on this scene
@@ -146,7 +148,9 @@ uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st);
 template <class Real>
 int spmv_grid(Scene &s, hipStream_t st, const Real *S, Real *x, Real *y, bool autotune);
 // persistent grid of the batched sweep (x, y: scratch as above)
-int spmm_grid(Scene &s, hipStream_t st, float *x, float *y, bool autotune);
+// launch shape of the batched sweeps: sets s.tile (force_tile > 0: that tile, default
+// grid) and returns the grid
+int spmm_grid(Scene &s, hipStream_t st, float *x, float *y, bool autotune, int force_tile);
 // runs body() (kernel launches only) directly, or as a captured graph replay
 sg_status run_chunk(Scene &s, hipStream_t st, const GraphKey &key, bool use_graphs, const std::function<void()> &body);
 void clear_graphs(Scene &s);
@@ -211,7 +215,9 @@ void launch_trace(Scene &s, hipStream_t st, int kind, const long long *ids, int 
                   int *count);
 
 // batched wavelengths
-int batched_groups(const Scene &s);
+int smallest_tile(int n_lambda);  // the narrowest of 8, 16, 32, 64 lanes that holds n_lambda
+int default_tile(int n_lambda);   // the untuned choice
+int batched_groups(const Scene &s);  // node groups of the batched sweep at tile s.tile
 void launch_bnode_coef(Scene &s, hipStream_t st);
 // the first batched Neumann iterate from x = 0: x = rhs (NULL: the solar source), with
 // per-node measures to s.meas

@@ -1,14 +1,15 @@
 // Host runtime around the sweep kernels: a launch-shape autotuner and the
 // replay of fixed chunks of sweeps as HIP graphs.
 //
-// Autotuner.  The persistent sweep kernels take any grid size, and their
-// results do not depend on it (every output element and every per-node norm
-// contribution is produced by one wavefront in a fixed order; the norms are
-// reduced by fixed-shape kernels).  From a scene's second solve on, the tuner
-// times a short list of grid sizes with HIP events on the scene's own data and
-// keeps the fastest, per problem shape, for the life of the process (a scene
-// solved once, as in serving, never pays for tuning); SG_AUTOTUNE_CACHE names
-// an optional text file that keeps the choices across processes.
+// Autotuner.  The persistent sweep kernels take any grid size, and the batched
+// sweep any wavelength tile that holds the scene's wavelengths; their results do
+// not depend on either (every output element and every per-node norm contribution
+// is produced by one lane in a fixed order; the norms are reduced by fixed-shape
+// kernels).  From a scene's second solve on, the tuner times a short list of
+// launch shapes with HIP events on the scene's own data and keeps the fastest, per
+// problem shape, for the life of the process (a scene solved once, as in serving,
+// never pays for tuning); SG_AUTOTUNE_CACHE names an optional text file that keeps
+// the choices across processes.
 //
 // Graphs.  A chunk of sweeps is a fixed sequence of kernel launches on fixed
 // buffers.  The second time a scene runs the same chunk it is captured on the
@@ -32,9 +33,12 @@ namespace sg {
 namespace {
 
 using TuneKey = std::array<long long, 7>;  // kind, N, E, nnz, dmax, n_lambda, element bytes
+struct Shape {
+    int grid = 0, tile = 0;  // tile: batched sweeps only
+};
 
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tuned;
+std::map<TuneKey, Shape> g_tuned;
 bool g_cache_loaded = false;
 
 const char *cache_path() {
@@ -50,52 +54,53 @@ void load_cache_locked() {
     FILE *f = std::fopen(p, "r");
     if (!f) return;
     TuneKey k;
-    int grid;
-    while (std::fscanf(f, "%lld %lld %lld %lld %lld %lld %lld %d", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6],
-                       &grid) == 8)
-        if (grid > 0) g_tuned[k] = grid;
+    Shape v;
+    while (std::fscanf(f, "%lld %lld %lld %lld %lld %lld %lld %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6],
+                       &v.grid, &v.tile) == 9)
+        if (v.grid > 0) g_tuned[k] = v;
     std::fclose(f);
 }
 
-void store_cache_locked(const TuneKey &k, int grid) {
-    g_tuned[k] = grid;
+void store_cache_locked(const TuneKey &k, Shape v) {
+    g_tuned[k] = v;
     const char *p = cache_path();
     if (!p) return;
     FILE *f = std::fopen(p, "a");
     if (!f) return;
-    std::fprintf(f, "%lld %lld %lld %lld %lld %lld %lld %d\n", k[0], k[1], k[2], k[3], k[4], k[5], k[6], grid);
+    std::fprintf(f, "%lld %lld %lld %lld %lld %lld %lld %d %d\n", k[0], k[1], k[2], k[3], k[4], k[5], k[6], v.grid,
+                 v.tile);
     std::fclose(f);
 }
 
-// Times launch(grid) for every candidate (one warm-up launch, then three timed
-// launches each) and returns the fastest; 0 if the device reports an error.
+// Times every candidate shape (one warm-up launch, then three timed launches each)
+// and returns the fastest; {0, 0} if the device reports an error.
 template <class F>
-int time_candidates(hipStream_t st, const std::vector<int> &cands, F &&launch) {
+Shape time_candidates(hipStream_t st, const std::vector<Shape> &cands, F &&launch) {
     hipEvent_t a = nullptr, b = nullptr;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return 0;
-    int best = 0;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return Shape{};
+    Shape best;
     float best_ms = 0.0f;
-    for (int g : cands) {
-        launch(g);
+    for (const Shape &c : cands) {
+        launch(c);
         (void)hipEventRecord(a, st);
-        for (int r = 0; r < 3; ++r) launch(g);
+        for (int r = 0; r < 3; ++r) launch(c);
         (void)hipEventRecord(b, st);
-        if (hipEventSynchronize(b) != hipSuccess) { best = 0; break; }
+        if (hipEventSynchronize(b) != hipSuccess) { best = Shape{}; break; }
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, a, b);
-        if (!best || ms < best_ms) { best = g; best_ms = ms; }
+        if (!best.grid || ms < best_ms) { best = c; best_ms = ms; }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    if (hipGetLastError() != hipSuccess) return 0;
+    if (hipGetLastError() != hipSuccess) return Shape{};
     return best;
 }
 
-std::vector<int> grid_candidates(int groups) {
-    std::vector<int> c;
+std::vector<Shape> grid_candidates(int groups, int tile = 0) {
+    std::vector<Shape> c;
     for (int g : {256, 512, 768, 1024, 1536, 2048, 3072, 4096})
-        if (g < groups) c.push_back(g);
-    c.push_back(groups);  // one node group per workgroup
+        if (g < groups) c.push_back({g, tile});
+    c.push_back({groups, tile});  // one node group per workgroup
     return c;
 }
 
@@ -109,37 +114,58 @@ int spmv_grid(Scene &s, hipStream_t st, const Real *S, Real *x, Real *y, bool au
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_cache_locked();
     auto it = g_tuned.find(k);
-    int grid = it != g_tuned.end() ? it->second : 0;
+    int grid = it != g_tuned.end() ? it->second.grid : 0;
     if (!grid && s.solves < 2) return 0;  // a scene's first solve does not tune
     if (!grid) {
         double *scratch = s.scal + 200;  // two measures (the tuned sweeps are monitored ones)
         launch_fill<Real>(x, (Real)0, s.E, st);  // x and y are scratch vectors here
         grid = time_candidates(st, grid_candidates(spmv_blocks(s)),
-                               [&](int g) { launch_spmv<Real>(s, st, S, x, y, scratch, g); });
-        if (grid) store_cache_locked(k, grid);
+                               [&](const Shape &c) { launch_spmv<Real>(s, st, S, x, y, scratch, c.grid); })
+                   .grid;
+        if (grid) store_cache_locked(k, Shape{grid, 0});
     }
     s.spmv_grid = grid;
     s.spmv_grid_bytes = (int)sizeof(Real);
     return grid;
 }
 
-int spmm_grid(Scene &s, hipStream_t st, float *x, float *y, bool autotune) {
-    const int groups = batched_groups(s);
-    const int fallback = groups;  // one node group per workgroup
+int spmm_grid(Scene &s, hipStream_t st, float *x, float *y, bool autotune, int force_tile) {
+    if (force_tile > 0) {
+        s.tile = force_tile;
+        return batched_groups(s);
+    }
+    s.tile = default_tile(s.n_lambda);
+    const int fallback = batched_groups(s);  // one node group per workgroup
     if (!autotune) return fallback;
-    if (s.spmm_grid > 0) return s.spmm_grid;
+    if (s.spmm_grid > 0) {
+        s.tile = s.spmm_tile;
+        return s.spmm_grid;
+    }
     const TuneKey k{1, s.N, s.E, s.nnz, s.dmax, s.n_lambda, 4};
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_cache_locked();
     auto it = g_tuned.find(k);
-    int grid = it != g_tuned.end() ? it->second : 0;
-    if (!grid && s.solves < 2) return fallback;  // a scene's first solve does not tune
-    if (!grid) {
+    Shape best = it != g_tuned.end() ? it->second : Shape{};
+    if (!best.grid && s.solves < 2) return fallback;  // a scene's first solve does not tune
+    if (!best.grid) {
         launch_fill_f32(x, (long long)s.E * s.n_lambda, st);  // x and y are scratch vectors here
-        grid = time_candidates(st, grid_candidates(groups), [&](int g) { launch_spmm(s, st, g, nullptr, x, y, 1); });
-        if (grid) store_cache_locked(k, grid);
+        // the narrowest tile that holds the wavelengths, and the full wavefront
+        std::vector<Shape> cands;
+        for (int W : {smallest_tile(s.n_lambda), 64}) {
+            if (!cands.empty() && cands.back().tile == W) break;
+            s.tile = W;
+            for (const Shape &c : grid_candidates(batched_groups(s), W)) cands.push_back(c);
+        }
+        best = time_candidates(st, cands, [&](const Shape &c) {
+            s.tile = c.tile;
+            launch_spmm(s, st, c.grid, nullptr, x, y, 1);
+        });
+        if (best.grid) store_cache_locked(k, best);
     }
-    s.spmm_grid = grid ? grid : fallback;
+    if (!best.grid || best.tile < smallest_tile(s.n_lambda)) best = Shape{fallback, default_tile(s.n_lambda)};
+    s.spmm_grid = best.grid;
+    s.spmm_tile = best.tile;
+    s.tile = best.tile;
     return s.spmm_grid;
 }
 

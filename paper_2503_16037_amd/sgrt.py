@@ -15,7 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsgrt.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 SG_OK, SG_E_INVALID, SG_E_NOMEM, SG_E_DEVICE, SG_E_NOCONV, SG_E_BUSY, SG_E_ABI, SG_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 SG_FP32, SG_FP64 = 0, 1
@@ -43,7 +43,8 @@ class SceneDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("precision", C.c_int32), ("solver", C.c_int32), ("rtol", C.c_double),
                 ("max_sweeps", C.c_int32), ("gmres_restart", C.c_int32), ("scatter_order", C.c_int32),
-                ("build_col_idx", C.c_int32), ("timing", C.c_int32), ("flags", C.c_int32)]
+                ("build_col_idx", C.c_int32), ("timing", C.c_int32), ("flags", C.c_int32),
+                ("lambda_tile", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -166,7 +167,7 @@ SG_NO_GRAPHS, SG_NO_AUTOTUNE = 1, 2
 
 
 def make_opts(precision="fp32", solver="auto", rtol=0.0, max_sweeps=0, gmres_restart=0, scatter_order=0,
-              build_col_idx=False, timing=False, graphs=True, autotune=True) -> SolveOpts:
+              build_col_idx=False, timing=False, graphs=True, autotune=True, lambda_tile=0) -> SolveOpts:
     o = SolveOpts()
     o.abi_version = ABI_VERSION
     o.precision = SG_FP64 if precision in ("fp64", SG_FP64) else SG_FP32
@@ -178,6 +179,7 @@ def make_opts(precision="fp32", solver="auto", rtol=0.0, max_sweeps=0, gmres_res
     o.build_col_idx = 1 if build_col_idx else 0
     o.timing = 1 if timing else 0
     o.flags = (0 if graphs else SG_NO_GRAPHS) | (0 if autotune else SG_NO_AUTOTUNE)
+    o.lambda_tile = int(lambda_tile)
     return o
 
 

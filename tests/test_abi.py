@@ -24,7 +24,9 @@ def test_library_exports_every_declared_symbol():
     L = ctypes.CDLL(sgrt.LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(L, n)]
     assert not missing, missing
-    assert L.sg_abi_version() == 1
+    hdr = open(os.path.join(ROOT, "include", "sgrt.h")).read()
+    version = int(re.search(r"#define SG_ABI_VERSION (\d+)u", hdr).group(1))
+    assert L.sg_abi_version() == version == sgrt.ABI_VERSION
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

@@ -111,3 +111,38 @@ def test_batched_deep_shadow_pixels(ctx):
     for k in range(sc.n_lambda):
         o = oracle.run(sc, abs_scale=float(sc.abs_scale[k]))["radiance"]
         assert rel_err(rad[k], o).max() <= 1e-4, k
+
+
+@pytest.mark.parametrize("n_lambda", [3, 12, 22])
+def test_lambda_tiles_give_identical_bits(ctx, n_lambda):
+    """Every wavelength tile that holds the wavelengths (several nodes per wavefront
+    down to one) computes the same bits: same sweeps, same radiance."""
+    from paper_2503_16037_amd import sgrt
+    sc = scenes.make_batched(nx=15, ny=13, nz=9, n_lambda=n_lambda, seed=11)
+    tiles = [t for t in (8, 16, 32, 64) if t >= n_lambda]
+    with sgrt.Scene(ctx, sc) as g:
+        runs = {}
+        for t in tiles:
+            say("tile", t, "scene", sc.name)
+            runs[t] = g.solve(lambda_tile=t)
+        auto = g.solve()
+    rad64, info64 = runs[64]
+    assert info64["converged"] == 1
+    for t in tiles + ["auto"]:
+        rad, info = auto if t == "auto" else runs[t]
+        assert info["sweeps"] == info64["sweeps"], t
+        assert np.array_equal(rad, rad64), t
+    ora = oracle.run(sc, abs_scale=float(sc.abs_scale[n_lambda - 1]))
+    assert rel_err(rad64[n_lambda - 1], ora["radiance"]).max() < 1e-4
+
+
+def test_lambda_tile_rejected_when_invalid(ctx):
+    from paper_2503_16037_amd import sgrt
+    sc = scenes.make_batched(nx=8, ny=8, nz=6, n_lambda=12)
+    with sgrt.Scene(ctx, sc) as g:
+        for bad in (8, 7, 128):
+            with pytest.raises(sgrt.SgError) as e:
+                g.solve(lambda_tile=bad)
+            assert e.value.status == sgrt.SG_E_INVALID
+        rad, info = g.solve(lambda_tile=16)
+        assert info["converged"] == 1
