@@ -9,10 +9,10 @@
 // order).  Surface nodes use the unrotated lattice with cosine weights (Lambertian).
 //
 // The incoming directions are processed in groups of G; the G x N_fib (direction,
-// lattice point) pairs are spread over the lanes, eight per lane, so every out-edge
-// direction read from LDS serves eight dot products per lane: the kernel is bound by
-// FP64 issue, not by LDS broadcasts.  Each direction's column of the node block
-// (column-major) is one coalesced store.
+// lattice point) pairs are spread over the lanes, up to eight per lane, so every
+// out-edge direction read from LDS serves eight dot products per lane: the kernel is
+// bound by FP64 issue, not by LDS broadcasts.  Each direction's column of the node
+// block (column-major) is one coalesced store.
 //
 // The ownership decision is an argmax over double-precision dot products; it is
 // written with this exact operation sequence (also followed by the FP64 CPU
@@ -39,8 +39,34 @@ constexpr int kQSlots = 8;     // (direction, lattice point) pairs per lane in a
 constexpr int kQMaxGroup = 8;  // incoming directions per group
 
 // LDS layout of a node (doubles): sites [3][64], rotations [kQMaxGroup][9], lattice
-// weights [128] (fixed point), bins [kQMaxGroup][64] (fixed point)
-constexpr int kQLds = 192 + kQMaxGroup * 9 + 128 + kQMaxGroup * 64;
+// weights [128] (fixed point), bins [kQMaxGroup][64] (fixed point), lattice [3][128]
+constexpr int kQLds = 192 + kQMaxGroup * 9 + 128 + kQMaxGroup * 64 + 384;
+
+// p / n for 0 <= p < 1024 and 1 <= n <= 128 with one FP32 multiply: (p + 1/2) / n is at
+// least 1/(2n) >= 2^-8 away from an integer, far above the rounding error of the
+// product (below 2^-12 here, also with a reciprocal a few ulp off)
+__device__ __forceinline__ int small_div(int p, float inv_n) { return (int)(((float)p + 0.5f) * inv_n); }
+
+// Running argmax over the node's out-edge directions for the lane's slots of
+// (direction, lattice point) pairs.  Ties go to the lowest index: the index moves only
+// on a strict increase, and the running maximum (fmax) equals the kept value on ties.
+// (Slots past a group's last pair, which hold repeats, are scanned too: one code path
+// keeps the kernel at 128 VGPRs, four waves per SIMD.)
+__device__ __forceinline__ void own_scan(int d, const double *sx, const double *sy, const double *sz,
+                                         const double (&q0)[kQSlots], const double (&q1)[kQSlots],
+                                         const double (&q2)[kQSlots], double (&best)[kQSlots], int (&own)[kQSlots]) {
+#pragma clang fp contract(off)
+#pragma unroll 2
+    for (int m = 0; m < d; ++m) {
+        const double tx = sx[m], ty = sy[m], tz = sz[m];
+#pragma unroll
+        for (int j = 0; j < kQSlots; ++j) {
+            const double v = fma(q2[j], tz, fma(q1[j], ty, q0[j] * tx));
+            own[j] = v > best[j] ? m : own[j];
+            best[j] = fmax(best[j], v);
+        }
+    }
+}
 
 template <class Real, class BlkT, bool kWriteQ>
 __global__ __launch_bounds__(64) void k_qbuild(
@@ -55,6 +81,7 @@ __global__ __launch_bounds__(64) void k_qbuild(
     double *Rg = smem + 192;
     unsigned long long *wq = reinterpret_cast<unsigned long long *>(smem + 192 + kQMaxGroup * 9);
     unsigned long long *bins = wq + 128;
+    double *lt = smem + 192 + kQMaxGroup * 9 + 128 + kQMaxGroup * 64;  // lattice, one array per axis
 
     const int l = blockIdx.x;
     const int lane = threadIdx.x;
@@ -73,6 +100,12 @@ __global__ __launch_bounds__(64) void k_qbuild(
         sy[lane] = (double)Dy / nrm;
         sz[lane] = (double)Dz / nrm;
     }
+    for (int i = lane; i < NF; i += 64) {
+        lt[i] = lat[3 * i];
+        lt[128 + i] = lat[3 * i + 1];
+        lt[256 + i] = lat[3 * i + 2];
+    }
+    const float inv_nf = 1.0f / (float)NF, inv_d = 1.0f / (float)d;
     // phase weights of the lattice points in fixed point
     for (int i = lane; i < NF; i += 64) {
         double w;
@@ -120,44 +153,34 @@ __global__ __launch_bounds__(64) void k_qbuild(
         for (int t = lane; t < ng * 64; t += 64) bins[t] = 0ull;
         __syncthreads();
         // this lane's pairs: q = R^T p for each, then the running argmax over the sites
+        const int np = ng * NF;  // pairs of this group
         double q0[kQSlots], q1[kQSlots], q2[kQSlots], best[kQSlots];
         int own[kQSlots];
 #pragma unroll
         for (int j = 0; j < kQSlots; ++j) {
-            const int p = min(j * 64 + lane, ng * NF - 1);  // past the last pair: a repeat, not counted
-            const int al = p / NF, i = p - al * NF;
+            const int p = min(j * 64 + lane, np - 1);  // past the last pair: a repeat, not counted
+            const int al = small_div(p, inv_nf), i = p - al * NF;
             const double *R = Rg + 9 * al;
-            const double x = lat[3 * i], y = lat[3 * i + 1], z = lat[3 * i + 2];
+            const double x = lt[i], y = lt[128 + i], z = lt[256 + i];
             q0[j] = fma(R[6], z, fma(R[3], y, R[0] * x));
             q1[j] = fma(R[7], z, fma(R[4], y, R[1] * x));
             q2[j] = fma(R[8], z, fma(R[5], y, R[2] * x));
             best[j] = -__builtin_inf();
             own[j] = 0;
         }
-        // ties go to the lowest index: the index moves only on a strict increase, and
-        // the running maximum (fmax) equals the kept value on ties
-#pragma unroll 2
-        for (int m = 0; m < d; ++m) {
-            const double tx = sx[m], ty = sy[m], tz = sz[m];
-#pragma unroll
-            for (int j = 0; j < kQSlots; ++j) {
-                const double v = fma(q2[j], tz, fma(q1[j], ty, q0[j] * tx));
-                own[j] = v > best[j] ? m : own[j];
-                best[j] = fmax(best[j], v);
-            }
-        }
+        own_scan(d, sx, sy, sz, q0, q1, q2, best, own);
 #pragma unroll
         for (int j = 0; j < kQSlots; ++j) {
             const int p = j * 64 + lane;
-            if (p < ng * NF) {
-                const int al = p / NF;
+            if (p < np) {
+                const int al = small_div(p, inv_nf);
                 atomicAdd(&bins[al * 64 + own[j]], wq[p - al * NF]);
             }
         }
         __syncthreads();
         // this group's columns: pair t = (a - a0) d + m is column a, row m
         for (int t = lane; t < ng * d; t += 64) {
-            const int al = t / d, m = t - al * d, a = a0 + al;
+            const int al = small_div(t, inv_d), m = t - al * d, a = a0 + al;
             const double Q = (double)(long long)bins[al * 64 + m] * kUnfix;
             const long long b = off + m;
             if (surf) {

@@ -62,6 +62,32 @@ def test_served_results_equal_solo_solves(ctx):
         assert err.max() < 1e-4
 
 
+def test_served_sample_of_twenty_matches_oracle(ctx):
+    """Twenty requests of the seeded served stream (seeds 5000..5019, plume and cloud, 1..32
+    wavelengths; grids halved until they hold at most 4000 voxels), solved through the
+    server: for each, the smallest, largest and last absorption multipliers meet the
+    per-pixel bar against the FP64 oracle."""
+    from paper_2503_16037_amd import sgrt
+    stream = small_stream(20, max_voxels=4000)
+    srv = sgrt.Server(ctx, max_resident=4, queue_cap=64, n_streams=4)
+    try:
+        tickets = [srv.submit(sc) for sc in stream]
+        assert all(t is not None for t in tickets)
+        out = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    worst = 0.0
+    for sc, (rad, info) in zip(stream, out):
+        assert info["status"] == 0 and info["converged"] == 1, sc.name
+        lams = sorted({int(np.argmin(sc.abs_scale)), int(np.argmax(sc.abs_scale)), sc.n_lambda - 1})
+        for k in lams:
+            ora = oracle.run(sc, abs_scale=float(sc.abs_scale[k]), want_matrix=False)
+            err = np.abs(rad[k] - ora["radiance"]) / np.abs(ora["radiance"])
+            worst = max(worst, float(err.max()))
+            assert err.max() < 1e-4, (sc.name, k, float(err.max()))
+    say("served sample of 20: worst per-pixel rel err", worst)
+
+
 def test_served_mix_with_concurrent_arrivals(ctx):
     from paper_2503_16037_amd import sgrt
     stream = small_stream(8, max_voxels=4000)
