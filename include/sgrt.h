@@ -193,7 +193,9 @@ typedef struct sg_solve_info {
     double ms_total;
     double ms_spmv_sum;     /* summed duration of the FP32/FP64 sweep kernel launches */
     int32_t spmv_launches;  /* their number */
-    int32_t reserved;
+    int32_t spmv_monitored; /* how many of them also computed the convergence measures (these
+                               read the previous iterate too: 4 more bytes per edge and
+                               wavelength in FP32) */
     int64_t n_nodes, n_edges, nnz;
 } sg_solve_info;
 

@@ -206,6 +206,7 @@ struct Exec {
     hipStream_t st = nullptr;
     std::vector<hipEvent_t> ev;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> spmv;
+    int monitored = 0;  // timed sweeps that computed the convergence measures
     hipEvent_t fresh() {  // an event for a launcher to record
         hipEvent_t e = nullptr;
         if (!on) return e;
@@ -316,6 +317,7 @@ sg_status neumann(Scene &s, hipStream_t st, Exec &tm, const Real *rhs, Real *&xa
                     hipEvent_t e0 = tm.mark(), e1 = tm.fresh();
                     launch_spmv<Real>(s, st, rhs, xa, xb, out(c), grid, e1);
                     tm.spmv.push_back({e0, e1});
+                    tm.monitored += out(c) != nullptr;
                 }
                 std::swap(xa, xb);
             }
@@ -567,6 +569,7 @@ sg_status solve_single(Scene &s, const sg_solve_opts &o, hipStream_t st, double 
             for (auto &p : tm.spmv) sum += tm.between(p.first, p.second);
             info->ms_spmv_sum = sum;
             info->spmv_launches = (int)tm.spmv.size();
+            info->spmv_monitored = tm.monitored;
         }
     }
     if (!ss.converged) return fail(SG_E_NOCONV, "solve stopped at relative residual " + std::to_string(ss.rel));
@@ -611,6 +614,7 @@ sg_status neumann_batched(Scene &s, hipStream_t st, Exec &tm, int grid, const fl
                     hipEvent_t e0 = tm.mark(), e1 = tm.fresh();
                     sweep(c, xa, xb, e1);
                     tm.spmv.push_back({e0, e1});
+                    tm.monitored += (first && c == 0) || c >= c_mon;
                 }
                 std::swap(xa, xb);
             }
@@ -790,6 +794,7 @@ sg_status solve_batched(Scene &s, const sg_solve_opts &o, hipStream_t st, double
             for (auto &p : tm.spmv) sum += tm.between(p.first, p.second);
             info->ms_spmv_sum = sum;
             info->spmv_launches = (int)tm.spmv.size();
+            info->spmv_monitored = tm.monitored;
         }
     }
     if (!ss.converged) return fail(SG_E_NOCONV, "solve stopped at relative residual " + std::to_string(ss.rel));

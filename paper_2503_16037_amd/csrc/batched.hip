@@ -10,8 +10,8 @@
 // The SpMM keeps the wavelengths in the lanes of a wavefront (lambda fastest in
 // every [E][n_lambda] array), so each node's phase-cell block Q (shared by all
 // wavelengths, column-major within the block) is read once per sweep for all
-// of them, through scalar loads when a wavefront holds a single node.  The
-// grid is persistent: a fixed set of workgroups strides over node groups.
+// of them.  The grid is persistent: a fixed set of workgroups strides over node
+// groups.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -43,12 +43,14 @@ __global__ __launch_bounds__(256) void k_bnode_coef(int N, int nvox, int nl, con
     bsrc[i] = l < nvox ? ts : mu0 * ts;
 }
 
-// One node per wavefront, lanes = wavelengths (tiles of 64).  The node index is
-// wave-uniform, so the phase-cell block Q comes through scalar loads; the node's
-// in-edge list and optical depths are loaded once, coalesced, and broadcast with
-// readlane; eight input gathers are in flight at a time; the node's rows are
-// accumulated in registers, the row count rounded up to a multiple of 8 (DB) so the
-// column loads are unguarded (the Q array is padded past its end by 64 floats).
+// One node per wavefront, lanes = wavelengths (tiles of 64).  The node's phase-cell
+// block Q is staged, coalesced, in the wavefront's LDS slice and its entries are read
+// as broadcasts (measured: reading the columns through scalar loads instead exposes
+// their latency, 1.4x slower at 64 wavelengths); the in-edge list and optical depths
+// are loaded once, coalesced, and broadcast with readlane; eight input gathers are in
+// flight at a time; the node's rows are accumulated in registers, the row count
+// rounded up to a multiple of 8 (DB) so the column reads are unguarded (the LDS slice
+// is padded past the block by 64 floats).
 // kResidual: FP64 residual r = S - x + K x of an FP64 iterate instead of a sweep.
 // exp(-(tau_s + s tau_a)) as one hardware exp2; its relative error (~|tau| 1e-7) is
 // below that of the FP32 path integral itself.  The sweep and the FP64 residual use

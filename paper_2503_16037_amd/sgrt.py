@@ -52,11 +52,11 @@ class SolveInfo(C.Structure):
                 ("refinements", C.c_int32), ("rel_residual", C.c_double), ("ms_structure", C.c_double),
                 ("ms_march", C.c_double), ("ms_qbuild", C.c_double), ("ms_solve", C.c_double),
                 ("ms_gather", C.c_double), ("ms_total", C.c_double), ("ms_spmv_sum", C.c_double),
-                ("spmv_launches", C.c_int32), ("reserved", C.c_int32), ("n_nodes", C.c_int64),
+                ("spmv_launches", C.c_int32), ("spmv_monitored", C.c_int32), ("n_nodes", C.c_int64),
                 ("n_edges", C.c_int64), ("nnz", C.c_int64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class ServerOpts(C.Structure):
