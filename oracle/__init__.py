@@ -70,6 +70,11 @@ def lib():
             L.or_num_threads.argtypes = []
             L.or_tails.restype = None
             L.or_tails.argtypes = [C.c_int64, P, C.c_int64, P]
+            L.or_coupling_nodes.restype = C.c_int64
+            L.or_coupling_nodes.argtypes = [C.c_int, C.c_int, C.c_int, P, P, C.c_int, P, P, P, P]
+            L.or_coupling_graph.restype = C.c_int64
+            L.or_coupling_graph.argtypes = [C.c_int, C.c_int, C.c_int, P, P, C.c_int, P, C.c_int64, C.c_double,
+                                            P, P, C.c_int64]
             _lib = L
         return _lib
 
@@ -241,3 +246,44 @@ def run(scene, abs_scale: float = 1.0, scatter_order: int = 0, tol: float = 1e-1
         for k in ("col", "val"):
             res.pop(k)
     return res
+
+
+# ------------------------------------------------------------------------------------------
+# the scattering graph (Sec. 2, Eq. 4; Sec. 3)
+# ------------------------------------------------------------------------------------------
+
+def _graph_inputs(scene):
+    pos = np.ascontiguousarray(scene.vol_pos_fx, np.int32)
+    mus = np.ascontiguousarray(scene.mu_s, np.float32)
+    alb = np.ascontiguousarray(scene.surf_albedo, np.float32)
+    return pos, mus, alb
+
+
+def coupling_nodes(scene):
+    """Node positions (fixed point, [N][3]), coupling coefficients mu [N] (surface:
+    albedo x the largest mu_s) and the centred, per-axis scaled coordinates q [N][3]."""
+    pos, mus, alb = _graph_inputs(scene)
+    N = scene.nx * scene.ny * scene.nz + (scene.nx * scene.ny if scene.surface_nodes else 0)
+    P = np.zeros((N, 3), np.int64)
+    mu = np.zeros(N, np.float64)
+    q = np.zeros((N, 3), np.float64)
+    lib().or_coupling_nodes(scene.nx, scene.ny, scene.nz, _p(pos), _p(mus), int(bool(scene.surface_nodes)),
+                            _p(alb), _p(P), _p(mu), _p(q))
+    return P, mu, q
+
+
+def coupling_graph(scene, n_pairs: int = 0, c_min: float = 0.0):
+    """The scattering graph of the scene's nodes: the n_pairs strongest couplings
+    (Eq. 4), or every coupling above c_min when n_pairs is 0.  Returns the symmetric
+    adjacency (adj_ptr int64 [N+1], adj_idx int32 [2 * pairs]), rows ascending."""
+    pos, mus, alb = _graph_inputs(scene)
+    N = scene.nx * scene.ny * scene.nz + (scene.nx * scene.ny if scene.surface_nodes else 0)
+    adj_ptr = np.zeros(N + 1, np.int64)
+    cap = 2 * n_pairs if n_pairs > 0 else 0
+    while True:
+        adj_idx = np.zeros(max(cap, 1), np.int32)
+        E = lib().or_coupling_graph(scene.nx, scene.ny, scene.nz, _p(pos), _p(mus), int(bool(scene.surface_nodes)),
+                                    _p(alb), int(n_pairs), float(c_min), _p(adj_ptr), _p(adj_idx), cap)
+        if E >= 0:
+            return adj_ptr, adj_idx[:E].copy()
+        cap = int(adj_ptr[-1])

@@ -774,3 +774,181 @@ int or_num_threads(void) {
 void or_tails(int64_t N, const int64_t *adj_ptr, int64_t E, int64_t *tail) {
     for (int64_t e = 0; e < E; ++e) tail[e] = tail_of(adj_ptr, N, e);
 }
+
+/* ==================================================================== */
+/* O9: the scattering graph (Sec. 2, Eq. 4; relative positions and the  */
+/* coupling of Lambertian surface nodes, Sec. 3)                        */
+/* ==================================================================== */
+/*
+ * Nodes: the node of every voxel (id = voxel index, position vol_pos_fx) and,
+ * with surface nodes on, one node per column at (i + 1/2, j + 1/2, 0) voxels
+ * (id nvox + i + nx j), as in the scene.
+ *
+ * The scattering coefficient of the coupling is that of the node's voxel; a
+ * surface node takes A times the largest mu_s of the medium (Sec. 3).
+ *
+ * Relative positions (Sec. 3): the node positions are centred, scaled to unit
+ * standard deviation per axis and expressed on the principal axes of the
+ * scaled set.  The last step is a rotation and changes no distance, so the
+ * coupling is evaluated on the centred, scaled coordinates:
+ *   mean_a = S1_a / N                        S1, S2: exact integer sums
+ *   var_a  = (N S2_a - S1_a^2) / (N N)       exact numerator, one rounding, divide
+ *   q_ia   = (p_ia - mean_a) / sqrt(var_a)   (0 on an axis of zero variance)
+ * Coupling (Eq. 4): C = sqrt(mu_i mu_j) / |q_i - q_j|.  Ranking and the
+ * threshold use its square, evaluated as
+ *   k = (mu_i * mu_j) / ((u*u + v*v) + w*w),   (u, v, w) = q_i - q_j,
+ * which orders pairs as C does (the square root is monotone).
+ * Candidates: pairs i < j with k > 0 that are not both surface nodes (two
+ * points of the ground are joined along the ground, not through the medium).
+ * Selection: n_pairs > 0: the n_pairs candidates of largest k, ties to the
+ * lexicographically smaller (i, j) (the paper's experiments fix the number of
+ * couplings); otherwise every candidate with k > c_min * c_min (the threshold
+ * of Sec. 2).  Output: the symmetric adjacency in CSR, rows ascending.
+ */
+typedef struct {
+    double k;
+    int64_t i, j;
+} or_pair;
+
+/* a ranks before b */
+static int pair_before(const or_pair *a, const or_pair *b) {
+    if (a->k != b->k) return a->k > b->k;
+    if (a->i != b->i) return a->i < b->i;
+    return a->j < b->j;
+}
+
+/* min-heap on rank: h[0] is the candidate ranked last among those kept */
+static void heap_down(or_pair *h, int64_t n, int64_t p) {
+    for (;;) {
+        int64_t c = 2 * p + 1, w = p;
+        if (c < n && pair_before(&h[w], &h[c])) w = c;
+        if (c + 1 < n && pair_before(&h[w], &h[c + 1])) w = c + 1;
+        if (w == p) return;
+        or_pair t = h[p];
+        h[p] = h[w];
+        h[w] = t;
+        p = w;
+    }
+}
+static void heap_up(or_pair *h, int64_t p) {
+    while (p > 0) {
+        int64_t a = (p - 1) / 2;
+        if (!pair_before(&h[a], &h[p])) return;
+        or_pair t = h[p];
+        h[p] = h[a];
+        h[a] = t;
+        p = a;
+    }
+}
+
+static int cmp_i32(const void *a, const void *b) {
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Node positions (fixed point), coupling coefficients and the scaled coordinates
+   q [N][3]; returns N. */
+int64_t or_coupling_nodes(int nx, int ny, int nz, const int32_t *vol_pos_fx, const float *mu_s, int surface,
+                          const float *albedo, int64_t *pos /* [N][3] */, double *mu /* [N] */, double *q) {
+    const int64_t nvox = (int64_t)nx * ny * nz, nsurf = surface ? (int64_t)nx * ny : 0, N = nvox + nsurf;
+    double mmax = 0.0;
+    for (int64_t v = 0; v < nvox; ++v) mmax = fmax(mmax, (double)mu_s[v]);
+    for (int64_t l = 0; l < N; ++l) {
+        if (l < nvox) {
+            for (int a = 0; a < 3; ++a) pos[3 * l + a] = vol_pos_fx[3 * l + a];
+            mu[l] = (double)mu_s[l];
+        } else {
+            const int64_t c = l - nvox, i = c % nx, j = c / nx;
+            pos[3 * l] = i * FXS + FXS / 2;
+            pos[3 * l + 1] = j * FXS + FXS / 2;
+            pos[3 * l + 2] = 0;
+            mu[l] = (double)albedo[c] * mmax;
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        __int128 s1 = 0, s2 = 0;
+        for (int64_t l = 0; l < N; ++l) {
+            s1 += pos[3 * l + a];
+            s2 += (__int128)pos[3 * l + a] * pos[3 * l + a];
+        }
+        const double mean = (double)s1 / (double)N;
+        const double var = (double)((__int128)N * s2 - s1 * s1) / ((double)N * (double)N);
+        const double sd = sqrt(var);
+        for (int64_t l = 0; l < N; ++l) q[3 * l + a] = var > 0.0 ? ((double)pos[3 * l + a] - mean) / sd : 0.0;
+    }
+    return N;
+}
+
+static double coupling_key(const double *q, const double *mu, int64_t i, int64_t j) {
+    const double u = q[3 * i] - q[3 * j], v = q[3 * i + 1] - q[3 * j + 1], w = q[3 * i + 2] - q[3 * j + 2];
+    const double d2 = (u * u + v * v) + w * w;
+    return (mu[i] * mu[j]) / d2;
+}
+
+/* The selected pairs as a symmetric CSR adjacency over the N nodes; returns the
+   number of directed edges (twice the pairs), or -1 when it exceeds cap (then
+   adj_idx is not written). */
+int64_t or_coupling_graph(int nx, int ny, int nz, const int32_t *vol_pos_fx, const float *mu_s, int surface,
+                          const float *albedo, int64_t n_pairs, double c_min, int64_t *adj_ptr /* [N+1] */,
+                          int32_t *adj_idx, int64_t cap) {
+    const int64_t nvox = (int64_t)nx * ny * nz, N = nvox + (surface ? (int64_t)nx * ny : 0);
+    int64_t *pos = malloc(sizeof(int64_t) * 3 * N);
+    double *mu = malloc(sizeof(double) * N), *q = malloc(sizeof(double) * 3 * N);
+    or_coupling_nodes(nx, ny, nz, vol_pos_fx, mu_s, surface, albedo, pos, mu, q);
+    or_pair *sel = NULL;
+    int64_t ns = 0, scap = 0;
+    if (n_pairs > 0) {
+        sel = malloc(sizeof(or_pair) * n_pairs);
+        for (int64_t i = 0; i < N; ++i)
+            for (int64_t j = i + 1; j < N; ++j) {
+                if (i >= nvox && j >= nvox) continue;
+                or_pair c = {coupling_key(q, mu, i, j), i, j};
+                if (!(c.k > 0.0)) continue;
+                if (ns < n_pairs) {
+                    sel[ns] = c;
+                    heap_up(sel, ns++);
+                } else if (pair_before(&c, &sel[0])) {
+                    sel[0] = c;
+                    heap_down(sel, ns, 0);
+                }
+            }
+    } else {
+        const double t = c_min * c_min;
+        for (int64_t i = 0; i < N; ++i)
+            for (int64_t j = i + 1; j < N; ++j) {
+                if (i >= nvox && j >= nvox) continue;
+                const double k = coupling_key(q, mu, i, j);
+                if (!(k > t)) continue;
+                if (ns == scap) {
+                    scap = scap ? 2 * scap : 1024;
+                    sel = realloc(sel, sizeof(or_pair) * scap);
+                }
+                sel[ns].k = k;
+                sel[ns].i = i;
+                sel[ns++].j = j;
+            }
+    }
+    for (int64_t l = 0; l <= N; ++l) adj_ptr[l] = 0;
+    for (int64_t s = 0; s < ns; ++s) {
+        ++adj_ptr[sel[s].i + 1];
+        ++adj_ptr[sel[s].j + 1];
+    }
+    for (int64_t l = 0; l < N; ++l) adj_ptr[l + 1] += adj_ptr[l];
+    const int64_t E = adj_ptr[N];
+    if (E <= cap) {
+        int64_t *fill = malloc(sizeof(int64_t) * (N + 1));
+        memcpy(fill, adj_ptr, sizeof(int64_t) * (N + 1));
+        for (int64_t s = 0; s < ns; ++s) {
+            adj_idx[fill[sel[s].i]++] = (int32_t)sel[s].j;
+            adj_idx[fill[sel[s].j]++] = (int32_t)sel[s].i;
+        }
+        for (int64_t l = 0; l < N; ++l)
+            qsort(adj_idx + adj_ptr[l], (size_t)(adj_ptr[l + 1] - adj_ptr[l]), sizeof(int32_t), cmp_i32);
+        free(fill);
+    }
+    free(sel);
+    free(pos);
+    free(mu);
+    free(q);
+    return E <= cap ? E : -1;
+}
