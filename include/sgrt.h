@@ -250,6 +250,51 @@ sg_status sg_trace(sg_scene *scene, int32_t kind, const int64_t *ids, int32_t n_
                    int32_t *voxels, double *dt, int32_t *count);
 
 /* ------------------------------------------------------------------------------------ */
+/* The scattering graph itself (Sec. 2, Eq. 4; Sec. 3)                                   */
+/* ------------------------------------------------------------------------------------ */
+
+/*
+ * Nodes as in sg_scene_desc: one per voxel (id = voxel index, position vol_pos_fx)
+ * and, with surface_nodes, one per column at (i + 1/2, j + 1/2, 0) voxels (id
+ * nvox + i + nx j).  A node's coupling coefficient is its voxel's mu_s; a surface
+ * node's is surf_albedo times the largest mu_s of the medium (Sec. 3).
+ */
+typedef struct sg_graph_desc {
+    uint32_t abi_version;       /* SG_ABI_VERSION */
+    int32_t nx, ny, nz;         /* grid, 1..1024 each */
+    const float *mu_s;          /* [nz][ny][nx], finite, >= 0 */
+    const int32_t *vol_pos_fx;  /* [nz*ny*nx][3], 2^16 units per voxel, strictly inside the node's voxel */
+    int32_t surface_nodes;      /* 1: one surface node per column */
+    const float *surf_albedo;   /* [ny][nx] in [0, 1] (read when surface_nodes) */
+    int64_t n_pairs;            /* > 0: keep the n_pairs strongest couplings */
+    double c_min;               /* n_pairs == 0: keep every coupling above c_min (>= 0) */
+} sg_graph_desc;
+
+/*
+ * Build the scattering graph G(R, L) of Sec. 2 on the device.  Positions are
+ * taken relative (Sec. 3): centred and scaled to unit standard deviation per
+ * axis (their projection on the principal axes, a rotation, changes no
+ * distance).  The coupling of nodes i, j is Eq. 4, C = sqrt(mu_i mu_j) / |q_i -
+ * q_j| on those coordinates, ranked through C^2 = mu_i mu_j / |q_i - q_j|^2
+ * evaluated in FP64 with the fixed operation order
+ *   (mu_i * mu_j) / ((u*u + v*v) + w*w),  (u, v, w) = q_i - q_j,
+ *   q_a = (p_a - mean_a) / sqrt(var_a),  mean and variance from exact integer sums.
+ * Candidate pairs: i != j, C > 0, not both surface nodes.  Selected: the n_pairs
+ * candidates with the largest C (equal couplings: the lexicographically smaller
+ * pair (min(i,j), max(i,j)) first; all candidates if fewer), or, with n_pairs =
+ * 0, every candidate with C^2 > c_min^2.
+ * Output (host buffers, caller-owned): the symmetric adjacency in the form
+ * sg_scene_desc takes, adj_ptr [N+1] and adj_idx [n_edges] with each row
+ * ascending; n_edges = twice the selected pairs.  When adj_idx is NULL or
+ * cap < n_edges, only adj_ptr (if not NULL) and *n_edges are written (a size
+ * query; the work is redone by the next call).  Node degrees are not capped:
+ * sg_scene_create accepts degrees up to 64.
+ * Errors: SG_E_ABI, SG_E_INVALID (with the reason), SG_E_NOMEM, SG_E_DEVICE.
+ */
+sg_status sg_graph_build(sg_ctx *ctx, const sg_graph_desc *desc, void *hip_stream, int64_t *adj_ptr,
+                         int32_t *adj_idx, int64_t cap, int64_t *n_edges);
+
+/* ------------------------------------------------------------------------------------ */
 /* Serving: continuous batching of many scenes on one device                             */
 /* ------------------------------------------------------------------------------------ */
 

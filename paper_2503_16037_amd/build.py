@@ -2,9 +2,9 @@
 
 Every source is compiled in-tree into ``_build/`` and linked into
 ``paper_2503_16037_amd/libsgrt.so``.  Packed FP32 instructions are disabled
-for all device code; the phase-cell kernel and the host runtime are compiled
-without floating-point contraction (their operation order is part of the
-definition of lattice ownership).
+for all device code; the phase-cell kernel, the graph builder and the host
+runtime are compiled without floating-point contraction (their operation order
+is part of the definition of lattice ownership and of the coupling ranking).
 """
 from __future__ import annotations
 
@@ -22,7 +22,7 @@ ARCH = os.environ.get("SGRT_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", os.path.join(ROOT, "include")]
-NO_CONTRACT = {"qbuild.hip", "api.cpp"}
+NO_CONTRACT = {"qbuild.hip", "api.cpp", "graph.hip"}
 # the phase-cell kernel sees only finite values: without NaN semantics the running maximum of
 # the ownership argmax needs no canonicalisation (no effect on any finite result)
 EXTRA = {"qbuild.hip": ["-fno-honor-nans"]}

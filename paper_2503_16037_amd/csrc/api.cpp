@@ -806,7 +806,6 @@ sg_status solve_batched(Scene &s, const sg_solve_opts &o, hipStream_t st, double
 
 using namespace sg;
 
-struct sg_ctx : public sg::Ctx {};
 struct sg_scene : public sg::Scene {};
 
 extern "C" {

@@ -1,0 +1,543 @@
+// The scattering graph G(R, L) (Sec. 2, Eq. 4) of a scene's nodes, built on the
+// device: which node pairs are coupled.
+//
+// Relative positions (Sec. 3): node positions are centred and scaled to unit
+// standard deviation per axis; their projection on the principal axes that
+// follows is a rotation and leaves every distance, hence every coupling,
+// unchanged, so the couplings are evaluated on the scaled coordinates q.  The
+// coupling C = sqrt(mu_i mu_j) / |q_i - q_j| (Eq. 4) is ranked through its square
+//   k = (mu_i * mu_j) / ((u*u + v*v) + w*w),   (u, v, w) = q_i - q_j,
+// in FP64 with exactly this operation order (no contraction: the selection is an
+// integer decision taken from these values); surface nodes couple with
+// albedo x the largest mu_s (Sec. 3) and two surface nodes never couple.
+//
+// Pruning.  A pair with k >= t satisfies |q_i - q_j|^2 <= mu_i mu_max / t, so for a
+// threshold t every partner of node i lies in an axis-aligned box of voxels around
+// it (half-width sqrt(mu_i mu_max / t) standard deviations per axis).  One wavefront
+// per node walks its box in increasing node id (x fastest, then y, z, then the
+// surface row), computes k for the partners of higher id and compacts the
+// qualifying pairs in that order with a ballot prefix, so the candidate list is
+// ordered by (i, j).  A stable radix sort on k (descending) then ranks them with
+// equal couplings in (i, j) order.
+//   threshold mode: t = c_min^2, keep k > t;
+//   top-n mode: t = the lowest threshold whose boxes hold at most a fixed budget
+//   of cells (bisection on the box volumes); if at least n pairs have k >= t, the
+//   n best of them are the answer; otherwise every pair is streamed in node chunks
+//   through a running best-n list.
+// The adjacency is assembled from the sorted directed pair codes (tail N + head).
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+#include <cstdlib>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace sg {
+
+namespace {
+
+// box cells a candidate pass may visit (SG_GRAPH_CELL_BUDGET overrides it, e.g. to
+// exercise the streamed path on small inputs)
+unsigned long long cell_budget() {
+    const char *v = std::getenv("SG_GRAPH_CELL_BUDGET");
+    const unsigned long long b = v ? std::strtoull(v, nullptr, 10) : 0ull;
+    return b ? b : (1ull << 26);
+}
+
+struct Geo {
+    int nx, ny, nz, surface;
+    long long nvox, N;
+    double mean[3], sd[3];  // per-axis centre and scale (sd = 0: the axis is ignored)
+    double mu_max;
+};
+
+sg_status gfail(sg_status st, const std::string &msg) {
+    set_error(msg);
+    return st;
+}
+
+#define GHIP(call)                                                                                   \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) {                                                                      \
+            ctx->sticky.store(1);                                                                    \
+            return gfail(SG_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));            \
+        }                                                                                            \
+    } while (0)
+#define GTRY(x)                          \
+    do {                                 \
+        sg_status st_ = (x);             \
+        if (st_ != SG_OK) return st_;    \
+    } while (0)
+
+// device blocks from the context pool, released on scope exit
+struct Dev {
+    Ctx *ctx;
+    std::vector<void *> blocks;
+    explicit Dev(Ctx *c) : ctx(c) {}
+    ~Dev() {
+        for (void *p : blocks) pool_free(ctx, p);
+    }
+    template <class T>
+    sg_status get(T **p, size_t n) {
+        void *q = nullptr;
+        GTRY(pool_alloc(ctx, std::max<size_t>(n, 1) * sizeof(T), &q));
+        blocks.push_back(q);
+        *p = static_cast<T *>(q);
+        return SG_OK;
+    }
+    void release(void *p) {  // one block back to the pool before scope exit
+        for (auto it = blocks.begin(); it != blocks.end(); ++it)
+            if (*it == p) {
+                pool_free(ctx, p);
+                blocks.erase(it);
+                return;
+            }
+    }
+};
+
+// ---- kernels ---------------------------------------------------------------------------
+
+// fixed-point position, coupling coefficient and scaled coordinates of every node
+__global__ void k_graph_nodes(Geo g, const int *__restrict__ pos, const float *__restrict__ mu_s,
+                              const float *__restrict__ albedo, long long *__restrict__ P, double *__restrict__ q,
+                              double *__restrict__ mu) {
+#pragma clang fp contract(off)
+    const long long l = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (l >= g.N) return;
+    long long p[3];
+    if (l < g.nvox) {
+        p[0] = pos[3 * l];
+        p[1] = pos[3 * l + 1];
+        p[2] = pos[3 * l + 2];
+        mu[l] = (double)mu_s[l];
+    } else {
+        const long long c = l - g.nvox;
+        p[0] = (c % g.nx) * kFx + kFx / 2;
+        p[1] = (c / g.nx) * kFx + kFx / 2;
+        p[2] = 0;
+        mu[l] = (double)albedo[c] * g.mu_max;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        P[3 * l + a] = p[a];
+        q[3 * l + a] = g.sd[a] > 0.0 ? ((double)p[a] - g.mean[a]) / g.sd[a] : 0.0;
+    }
+}
+
+__device__ __forceinline__ double pair_key(const double *__restrict__ q, const double *__restrict__ mu, long long i,
+                                           long long j) {
+#pragma clang fp contract(off)
+    const double u = q[3 * i] - q[3 * j], v = q[3 * i + 1] - q[3 * j + 1], w = q[3 * i + 2] - q[3 * j + 2];
+    const double d2 = (u * u + v * v) + w * w;
+    return (mu[i] * mu[j]) / d2;
+}
+
+// The box of node i's possible partners at threshold t: voxel index ranges per axis
+// (lo > hi: empty) and whether the surface row is inside.
+struct Box {
+    long long lo[3], hi[3];
+    bool surf;
+};
+
+__device__ __forceinline__ Box node_box(const Geo &g, const long long *__restrict__ P, const double *__restrict__ mu,
+                                        long long i, double t) {
+    Box b;
+    const double mi = mu[i];
+    const long long n[3] = {g.nx, g.ny, g.nz};
+    // k = 0 for every pair of this node, or a surface node (its pairs with volume
+    // nodes are found from the volume side; two surface nodes never couple)
+    if (!(mi > 0.0) || i >= g.nvox) {
+        for (int a = 0; a < 3; ++a) { b.lo[a] = 1; b.hi[a] = 0; }
+        b.surf = false;
+        return b;
+    }
+    // radius in standard deviations; t = 0 (or an overflow): unbounded
+    const double rho = t > 0.0 ? sqrt(mi * g.mu_max / t) * (1.0 + 1e-9) : __builtin_inf();
+    bool low_z = false;
+    for (int a = 0; a < 3; ++a) {
+        const double r = g.sd[a] > 0.0 ? rho * g.sd[a] + 1.0 : __builtin_inf();  // fixed-point units
+        const double pa = (double)P[3 * i + a];
+        const double flo = floor((pa - r) / (double)kFx), fhi = floor((pa + r) / (double)kFx);
+        b.lo[a] = flo < 0.0 ? 0 : (flo > (double)(n[a] - 1) ? n[a] : (long long)flo);
+        b.hi[a] = fhi > (double)(n[a] - 1) ? n[a] - 1 : (fhi < 0.0 ? -1 : (long long)fhi);
+        if (a == 2) low_z = pa - r <= 0.0;
+    }
+    b.surf = g.surface && low_z;
+    return b;
+}
+
+__device__ __forceinline__ unsigned long long box_cells(const Box &b) {
+    unsigned long long v = 1;
+    for (int a = 0; a < 3; ++a) v *= b.hi[a] >= b.lo[a] ? (unsigned long long)(b.hi[a] - b.lo[a] + 1) : 0ull;
+    if (b.surf) v += (unsigned long long)(b.hi[0] >= b.lo[0] ? b.hi[0] - b.lo[0] + 1 : 0) *
+                     (unsigned long long)(b.hi[1] >= b.lo[1] ? b.hi[1] - b.lo[1] + 1 : 0);
+    return v;
+}
+
+// total box cells of all nodes at threshold t (one thread per node)
+__global__ void k_graph_cells(Geo g, const long long *__restrict__ P, const double *__restrict__ mu, double t,
+                              unsigned long long *__restrict__ total) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    unsigned long long v = 0;
+    if (i < g.N) v = box_cells(node_box(g, P, mu, i, t));
+    // wavefront sum, then one atomic per wavefront
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(total, v);
+}
+
+// Candidate pairs (i, j), j > i, of nodes i in [n0, n1) with k >= t (strict: k > t),
+// k > 0.  kFill = false: count[i - n0] = their number; kFill = true: write them at
+// off[i - n0] in increasing j.  One wavefront per node, grid-stride over nodes.
+template <bool kFill>
+__global__ __launch_bounds__(256) void k_graph_pairs(Geo g, const long long *__restrict__ P,
+                                                     const double *__restrict__ q, const double *__restrict__ mu,
+                                                     double t, int strict, long long n0, long long n1,
+                                                     unsigned long long *__restrict__ count,
+                                                     const unsigned long long *__restrict__ off,
+                                                     double *__restrict__ keys,
+                                                     unsigned long long *__restrict__ codes) {
+    const int lane = threadIdx.x & 63;
+    const long long waves = (long long)gridDim.x * (blockDim.x >> 6);
+    for (long long i = n0 + blockIdx.x * (long long)(blockDim.x >> 6) + (threadIdx.x >> 6); i < n1; i += waves) {
+        const Box b = node_box(g, P, mu, i, t);
+        const long long bx = b.hi[0] - b.lo[0] + 1, by = b.hi[1] - b.lo[1] + 1, bz = b.hi[2] - b.lo[2] + 1;
+        const long long nv = (bx > 0 && by > 0 && bz > 0) ? bx * by * bz : 0;
+        const long long ns = (b.surf && bx > 0 && by > 0) ? bx * by : 0;
+        unsigned long long run = kFill ? off[i - n0] : 0ull;
+        for (long long c0 = 0; c0 < nv + ns; c0 += 64) {
+            const long long c = c0 + lane;
+            long long j = -1;
+            if (c < nv) {
+                const long long cx = b.lo[0] + c % bx, cy = b.lo[1] + (c / bx) % by, cz = b.lo[2] + c / (bx * by);
+                j = cx + g.nx * (cy + g.ny * cz);
+            } else if (c < nv + ns) {
+                const long long s = c - nv;
+                j = g.nvox + (b.lo[0] + s % bx) + g.nx * (b.lo[1] + s / bx);
+            }
+            bool ok = false;
+            double k = 0.0;
+            if (j > i) {
+                k = pair_key(q, mu, i, j);
+                ok = k > 0.0 && (strict ? k > t : k >= t);
+            }
+            const unsigned long long m = __ballot(ok);
+            if (kFill && ok) {
+                const unsigned long long at = run + __popcll(m & ((1ull << lane) - 1ull));
+                keys[at] = k;
+                codes[at] = (unsigned long long)i * (unsigned long long)g.N + (unsigned long long)j;
+            }
+            run += __popcll(m);
+        }
+        if (!kFill && lane == 0) count[i - n0] = run;
+    }
+}
+
+// directed pair codes (tail N + head) of the selected pairs, and the degree of every tail
+__global__ void k_graph_directed(long long n, long long N, const unsigned long long *__restrict__ pair,
+                                 unsigned long long *__restrict__ dir, int *__restrict__ deg) {
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const unsigned long long c = pair[s];
+    const unsigned long long i = c / (unsigned long long)N, j = c % (unsigned long long)N;
+    dir[2 * s] = i * (unsigned long long)N + j;
+    dir[2 * s + 1] = j * (unsigned long long)N + i;
+    atomicAdd(&deg[i], 1);
+    atomicAdd(&deg[j], 1);
+}
+
+__global__ void k_graph_heads(long long E, long long N, const unsigned long long *__restrict__ dir,
+                              int *__restrict__ head) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e < E) head[e] = (int)(dir[e] % (unsigned long long)N);
+}
+
+__global__ void k_graph_ptr(long long N, const int *__restrict__ deg, const long long *__restrict__ excl,
+                            long long *__restrict__ ptr) {
+    const long long l = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (l < N) ptr[l] = excl[l];
+    if (l == N - 1) ptr[N] = excl[l] + deg[l];
+}
+
+__global__ void k_graph_widen(long long n, const int *__restrict__ a, long long *__restrict__ b) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+unsigned blocks_for(long long n, int threads) { return (unsigned)std::max<long long>(1, (n + threads - 1) / threads); }
+
+// ---- host driver ---------------------------------------------------------------------
+
+struct Builder {
+    Ctx *ctx;
+    hipStream_t st;
+    Geo g;
+    Dev dev;
+    long long *P = nullptr;
+    double *q = nullptr, *mu = nullptr;
+    unsigned long long *scal = nullptr;
+    Builder(Ctx *c, hipStream_t s) : ctx(c), st(s), dev(c) {}
+
+    sg_status cells(double t, unsigned long long &out) {
+        GHIP(hipMemsetAsync(scal, 0, sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(k_graph_cells, dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, P, mu, t, scal);
+        GHIP(hipGetLastError());
+        GHIP(hipMemcpyAsync(&out, scal, sizeof(out), hipMemcpyDeviceToHost, st));
+        GHIP(hipStreamSynchronize(st));
+        return SG_OK;
+    }
+
+    // candidates of nodes [n0, n1) at threshold t, appended after `have` entries of
+    // (keys, codes), which are reallocated to fit
+    sg_status pairs(double t, int strict, long long n0, long long n1, double *&keys, unsigned long long *&codes,
+                    unsigned long long &have) {
+        const long long n = n1 - n0;
+        if (n <= 0) return SG_OK;
+        Dev tmp(ctx);
+        unsigned long long *cnt = nullptr, *off = nullptr;
+        GTRY(tmp.get(&cnt, n + 1));
+        GTRY(tmp.get(&off, n + 1));
+        GHIP(hipMemsetAsync(cnt + n, 0, sizeof(unsigned long long), st));
+        const unsigned grid = std::min<unsigned>(blocks_for(n, 4), 65536u);
+        hipLaunchKernelGGL((k_graph_pairs<false>), dim3(grid), dim3(256), 0, st, g, P, q, mu, t, strict, n0, n1, cnt,
+                           nullptr, nullptr, nullptr);
+        GHIP(hipGetLastError());
+        // off = have + exclusive sum of the counts; off[n] = the new total
+        size_t tb = 0;
+        GHIP(hipcub::DeviceScan::ExclusiveScan(nullptr, tb, cnt, off, hipcub::Sum(), (unsigned long long)have,
+                                               (int)n + 1, st));
+        unsigned char *tsp = nullptr;
+        GTRY(tmp.get(&tsp, tb));
+        GHIP(hipcub::DeviceScan::ExclusiveScan(tsp, tb, cnt, off, hipcub::Sum(), (unsigned long long)have, (int)n + 1,
+                                               st));
+        unsigned long long total = 0;
+        GHIP(hipMemcpyAsync(&total, off + n, sizeof(total), hipMemcpyDeviceToHost, st));
+        GHIP(hipStreamSynchronize(st));
+        if (total >= (1ull << 31)) return gfail(SG_E_NOMEM, "more than 2^31 coupling candidates");
+        if (total > have) {
+            double *nk = nullptr;
+            unsigned long long *nc = nullptr;
+            GTRY(dev.get(&nk, total));
+            GTRY(dev.get(&nc, total));
+            if (have) {
+                GHIP(hipMemcpyAsync(nk, keys, sizeof(double) * have, hipMemcpyDeviceToDevice, st));
+                GHIP(hipMemcpyAsync(nc, codes, sizeof(unsigned long long) * have, hipMemcpyDeviceToDevice, st));
+            }
+            hipLaunchKernelGGL((k_graph_pairs<true>), dim3(grid), dim3(256), 0, st, g, P, q, mu, t, strict, n0, n1,
+                               nullptr, off, nk, nc);
+            GHIP(hipGetLastError());
+            GHIP(hipStreamSynchronize(st));  // the scan's scratch is released at return
+            dev.release(keys);
+            dev.release(codes);
+            keys = nk;
+            codes = nc;
+        }
+        have = total;
+        return SG_OK;
+    }
+
+    // stable sort by key, descending (equal keys keep their order), in place
+    sg_status sort_desc(double *&keys, unsigned long long *&codes, unsigned long long n) {
+        if (n < 2) return SG_OK;
+        Dev tmp(ctx);
+        double *k2 = nullptr;
+        unsigned long long *c2 = nullptr;
+        GTRY(dev.get(&k2, n));
+        GTRY(dev.get(&c2, n));
+        size_t tb = 0;
+        GHIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, keys, k2, codes, c2, (int)n, 0, 64, st));
+        unsigned char *tsp = nullptr;
+        GTRY(tmp.get(&tsp, tb));
+        GHIP(hipcub::DeviceRadixSort::SortPairsDescending(tsp, tb, keys, k2, codes, c2, (int)n, 0, 64, st));
+        GHIP(hipStreamSynchronize(st));
+        dev.release(keys);
+        dev.release(codes);
+        keys = k2;
+        codes = c2;
+        return SG_OK;
+    }
+};
+
+}  // namespace
+
+sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t *adj_ptr, int32_t *adj_idx,
+                      int64_t cap, int64_t *n_edges) {
+    if (!d) return gfail(SG_E_INVALID, "desc is NULL");
+    if (d->abi_version != SG_ABI_VERSION) return gfail(SG_E_ABI, "graph desc abi_version mismatch");
+    if (!n_edges) return gfail(SG_E_INVALID, "n_edges is NULL");
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nx > 1024 || d->ny > 1024 || d->nz > 1024)
+        return gfail(SG_E_INVALID, "grid dimensions must be in 1..1024");
+    if (!d->mu_s || !d->vol_pos_fx || (d->surface_nodes && !d->surf_albedo))
+        return gfail(SG_E_INVALID, "a required array is NULL");
+    if (d->n_pairs < 0) return gfail(SG_E_INVALID, "n_pairs must be >= 0");
+    if (d->n_pairs == 0 && !(d->c_min >= 0.0 && std::isfinite(d->c_min)))
+        return gfail(SG_E_INVALID, "c_min must be finite and >= 0");
+    const long long nvox = (long long)d->nx * d->ny * d->nz;
+    const long long N = nvox + (d->surface_nodes ? (long long)d->nx * d->ny : 0);
+    if (N >= (1LL << 31)) return gfail(SG_E_INVALID, "too many nodes");
+    float mmax = 0.0f;
+    for (long long v = 0; v < nvox; ++v) {
+        const float a = d->mu_s[v];
+        if (!(a >= 0.0f) || !std::isfinite(a)) return gfail(SG_E_INVALID, "mu_s must be finite and >= 0");
+        mmax = std::max(mmax, a);
+    }
+    if (d->surface_nodes)
+        for (long long c = 0; c < (long long)d->nx * d->ny; ++c)
+            if (!(d->surf_albedo[c] >= 0.0f) || !(d->surf_albedo[c] <= 1.0f))
+                return gfail(SG_E_INVALID, "surf_albedo must be in [0, 1]");
+    // exact integer moments of the positions, per axis
+    __int128 s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0};
+    for (long long v = 0; v < nvox; ++v) {
+        const long long c[3] = {v % d->nx, (v / d->nx) % d->ny, v / ((long long)d->nx * d->ny)};
+        for (int a = 0; a < 3; ++a) {
+            const long long p = d->vol_pos_fx[3 * v + a];
+            if (!(p > c[a] * kFx && p < (c[a] + 1) * kFx))
+                return gfail(SG_E_INVALID, "node position not strictly inside its voxel (node " + std::to_string(v) + ")");
+            s1[a] += p;
+            s2[a] += (__int128)p * p;
+        }
+    }
+    if (d->surface_nodes)
+        for (long long c = 0; c < (long long)d->nx * d->ny; ++c) {
+            const long long p[3] = {(c % d->nx) * kFx + kFx / 2, (c / d->nx) * kFx + kFx / 2, 0};
+            for (int a = 0; a < 3; ++a) {
+                s1[a] += p[a];
+                s2[a] += (__int128)p[a] * p[a];
+            }
+        }
+    Builder B(ctx, st);
+    Geo &g = B.g;
+    g.nx = d->nx;
+    g.ny = d->ny;
+    g.nz = d->nz;
+    g.surface = d->surface_nodes ? 1 : 0;
+    g.nvox = nvox;
+    g.N = N;
+    g.mu_max = (double)mmax;
+    for (int a = 0; a < 3; ++a) {
+        g.mean[a] = (double)s1[a] / (double)N;
+        const double var = (double)((__int128)N * s2[a] - s1[a] * s1[a]) / ((double)N * (double)N);
+        g.sd[a] = var > 0.0 ? std::sqrt(var) : 0.0;
+    }
+
+    // node arrays
+    int *pos = nullptr;
+    float *mus = nullptr, *alb = nullptr;
+    GTRY(B.dev.get(&pos, 3 * nvox));
+    GTRY(B.dev.get(&mus, nvox));
+    GTRY(B.dev.get(&alb, (long long)d->nx * d->ny));
+    GTRY(B.dev.get(&B.P, 3 * N));
+    GTRY(B.dev.get(&B.q, 3 * N));
+    GTRY(B.dev.get(&B.mu, N));
+    GTRY(B.dev.get(&B.scal, 4));
+    GHIP(hipMemcpyAsync(pos, d->vol_pos_fx, sizeof(int) * 3 * nvox, hipMemcpyHostToDevice, st));
+    GHIP(hipMemcpyAsync(mus, d->mu_s, sizeof(float) * nvox, hipMemcpyHostToDevice, st));
+    if (d->surface_nodes)
+        GHIP(hipMemcpyAsync(alb, d->surf_albedo, sizeof(float) * d->nx * d->ny, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_graph_nodes, dim3(blocks_for(N, 256)), dim3(256), 0, st, g, pos, mus, alb, B.P, B.q, B.mu);
+    GHIP(hipGetLastError());
+
+    // candidates and selection
+    double *keys = nullptr;
+    unsigned long long *codes = nullptr, have = 0, n_sel = 0;
+    if (d->n_pairs == 0) {
+        GTRY(B.pairs(d->c_min * d->c_min, 1, 0, N, keys, codes, have));
+        n_sel = have;
+    } else {
+        // the lowest threshold (bisection in the exponent) whose boxes fit the cell budget
+        const unsigned long long budget = cell_budget();
+        double t_fit = 0.0;
+        unsigned long long cells = 0;
+        GTRY(B.cells(0.0, cells));
+        if (cells > budget) {
+            double lo = 1e-300, hi = 1e300;
+            GTRY(B.cells(hi, cells));
+            if (cells > budget) return gfail(SG_E_NOMEM, "coupling candidates exceed the cell budget");
+            for (int it = 0; it < 64; ++it) {
+                const double mid = std::sqrt(lo) * std::sqrt(hi);
+                if (!(mid > lo && mid < hi)) break;
+                GTRY(B.cells(mid, cells));
+                if (cells <= budget) hi = mid;
+                else lo = mid;
+            }
+            t_fit = hi;
+        }
+        GTRY(B.pairs(t_fit, 0, 0, N, keys, codes, have));
+        if (have >= (unsigned long long)d->n_pairs || t_fit == 0.0) {
+            GTRY(B.sort_desc(keys, codes, have));
+            n_sel = std::min<unsigned long long>(have, (unsigned long long)d->n_pairs);
+        } else {
+            // every pair, streamed in node chunks through a running best-n list
+            have = 0;
+            const long long chunk = std::max<long long>(1, (long long)(budget / (unsigned long long)N));
+            for (long long n0 = 0; n0 < N; n0 += chunk) {
+                GTRY(B.pairs(0.0, 1, n0, std::min(N, n0 + chunk), keys, codes, have));
+                GTRY(B.sort_desc(keys, codes, have));
+                have = std::min<unsigned long long>(have, (unsigned long long)d->n_pairs);
+            }
+            n_sel = have;
+        }
+    }
+
+    // adjacency: directed codes sorted ascending give the rows in order
+    const long long E = 2 * (long long)n_sel;
+    *n_edges = E;
+    if (E >= (1LL << 31) - 1) return gfail(SG_E_INVALID, "too many edges");
+    Dev tmp(ctx);
+    unsigned long long *dir = nullptr, *dir2 = nullptr;
+    int *deg = nullptr, *head = nullptr;
+    long long *deg64 = nullptr, *excl = nullptr, *ptr = nullptr;
+    GTRY(tmp.get(&dir, E));
+    GTRY(tmp.get(&dir2, E));
+    GTRY(tmp.get(&deg, N));
+    GTRY(tmp.get(&head, E));
+    GTRY(tmp.get(&deg64, N));
+    GTRY(tmp.get(&excl, N));
+    GTRY(tmp.get(&ptr, N + 1));
+    GHIP(hipMemsetAsync(deg, 0, sizeof(int) * N, st));
+    if (n_sel) {
+        hipLaunchKernelGGL(k_graph_directed, dim3(blocks_for((long long)n_sel, 256)), dim3(256), 0, st,
+                           (long long)n_sel, N, codes, dir, deg);
+        GHIP(hipGetLastError());
+        size_t tb = 0;
+        GHIP(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, dir, dir2, (int)E, 0, 64, st));
+        unsigned char *tsp = nullptr;
+        GTRY(tmp.get(&tsp, tb));
+        GHIP(hipcub::DeviceRadixSort::SortKeys(tsp, tb, dir, dir2, (int)E, 0, 64, st));
+        hipLaunchKernelGGL(k_graph_heads, dim3(blocks_for(E, 256)), dim3(256), 0, st, E, N, dir2, head);
+        GHIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_graph_widen, dim3(blocks_for(N, 256)), dim3(256), 0, st, N, deg, deg64);
+    GHIP(hipGetLastError());
+    {
+        size_t tb = 0;
+        GHIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, deg64, excl, (int)N, st));
+        unsigned char *tsp = nullptr;
+        GTRY(tmp.get(&tsp, tb));
+        GHIP(hipcub::DeviceScan::ExclusiveSum(tsp, tb, deg64, excl, (int)N, st));
+    }
+    hipLaunchKernelGGL(k_graph_ptr, dim3(blocks_for(N, 256)), dim3(256), 0, st, N, deg, excl, ptr);
+    GHIP(hipGetLastError());
+    if (adj_ptr) GHIP(hipMemcpyAsync(adj_ptr, ptr, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToHost, st));
+    if (adj_idx && cap >= E && E > 0)
+        GHIP(hipMemcpyAsync(adj_idx, head, sizeof(int32_t) * E, hipMemcpyDeviceToHost, st));
+    GHIP(hipStreamSynchronize(st));
+    return SG_OK;
+}
+
+}  // namespace sg
+
+extern "C" sg_status sg_graph_build(sg_ctx *ctx, const sg_graph_desc *desc, void *hip_stream, int64_t *adj_ptr,
+                                    int32_t *adj_idx, int64_t cap, int64_t *n_edges) {
+    if (!ctx) return sg::gfail(SG_E_INVALID, "ctx is NULL");
+    if (ctx->sticky.load()) return sg::gfail(SG_E_DEVICE, "context is in a failed state");
+    if (hipSetDevice(ctx->device) != hipSuccess) return sg::gfail(SG_E_DEVICE, "hipSetDevice failed");
+    return sg::graph_build(ctx, desc, hip_stream ? (hipStream_t)hip_stream : ctx->stream, adj_ptr, adj_idx, cap,
+                           n_edges);
+}

@@ -234,3 +234,6 @@ void launch_fill_f32(float *a, long long n, hipStream_t st);
 void launch_batched_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance);
 
 }  // namespace sg
+
+// the public handle of a context
+struct sg_ctx : public sg::Ctx {};

@@ -40,6 +40,12 @@ class SceneDesc(C.Structure):
                 ("abs_scale", C.c_void_p)]
 
 
+class GraphDesc(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("mu_s", C.c_void_p), ("vol_pos_fx", C.c_void_p), ("surface_nodes", C.c_int32),
+                ("surf_albedo", C.c_void_p), ("n_pairs", C.c_int64), ("c_min", C.c_double)]
+
+
 class SolveOpts(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("precision", C.c_int32), ("solver", C.c_int32), ("rtol", C.c_double),
                 ("max_sweeps", C.c_int32), ("gmres_restart", C.c_int32), ("scatter_order", C.c_int32),
@@ -103,6 +109,7 @@ def lib():
                 "sg_wait": (I32, [P, U64, P, P]),
                 "sg_server_latencies": (I32, [P, P, I32, P]),
                 "sg_server_destroy": (I32, [P]),
+                "sg_graph_build": (I32, [P, P, P, P, P, I64, P]),
             }
             for name, (res, args) in sigs.items():
                 f = getattr(L, name)
@@ -370,3 +377,37 @@ class Server:
         if self.handle:
             _check(lib().sg_server_destroy(self.handle))
             self.handle = None
+
+
+def graph_build(ctx: Context, scene, n_pairs: int = 0, c_min: float = 0.0, stream=None):
+    """sg_graph_build: the scattering graph of the scene's nodes (the n_pairs strongest
+    couplings, or those above c_min when n_pairs is 0).  Returns (adj_ptr int64 [N+1],
+    adj_idx int32 [n_edges]), the form a scene's adjacency takes."""
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a
+
+    d = GraphDesc()
+    d.abi_version = ABI_VERSION
+    d.nx, d.ny, d.nz = int(scene.nx), int(scene.ny), int(scene.nz)
+    d.mu_s = _ptr(arr(scene.mu_s, np.float32))
+    d.vol_pos_fx = _ptr(arr(scene.vol_pos_fx, np.int32))
+    d.surface_nodes = 1 if scene.surface_nodes else 0
+    d.surf_albedo = _ptr(arr(scene.surf_albedo, np.float32))
+    d.n_pairs = int(n_pairs)
+    d.c_min = float(c_min)
+    N = d.nx * d.ny * d.nz + (d.nx * d.ny if d.surface_nodes else 0)
+    adj_ptr = np.zeros(N + 1, np.int64)
+    ne = C.c_int64(0)
+    cap = 2 * int(n_pairs)
+    adj_idx = np.zeros(max(cap, 1), np.int32)
+    _check(lib().sg_graph_build(ctx.handle, C.byref(d), _stream_ptr(stream), _ptr(adj_ptr),
+                                _ptr(adj_idx) if cap else None, cap, C.byref(ne)))
+    if ne.value > cap:  # threshold mode: the size is known now
+        adj_idx = np.zeros(ne.value, np.int32)
+        _check(lib().sg_graph_build(ctx.handle, C.byref(d), _stream_ptr(stream), _ptr(adj_ptr), _ptr(adj_idx),
+                                    ne.value, C.byref(ne)))
+    return adj_ptr, adj_idx[:ne.value].copy()
