@@ -288,11 +288,24 @@ typedef struct sg_graph_desc {
  * ascending; n_edges = twice the selected pairs.  When adj_idx is NULL or
  * cap < n_edges, only adj_ptr (if not NULL) and *n_edges are written (a size
  * query; the work is redone by the next call).  Node degrees are not capped:
- * sg_scene_create accepts degrees up to 64.
+ * sg_scene_create accepts degrees up to 64.  info (optional) receives counts
+ * and timings of the build.
  * Errors: SG_E_ABI, SG_E_INVALID (with the reason), SG_E_NOMEM, SG_E_DEVICE.
  */
+typedef struct sg_graph_info {
+    int64_t candidates;      /* pairs ranked (C^2 >= threshold; in threshold mode, selected) */
+    int64_t pairs_evaluated; /* couplings computed to find the ranked candidates (pairs j > i in
+                                the boxes, counted once; the fill kernel recomputes those it keeps) */
+    double threshold;        /* C^2 bound of the last candidate pass (0: every pair) */
+    int32_t streamed;        /* 1: every pair went through the streamed best-n list */
+    int32_t passes;          /* candidate passes, each a count and a fill kernel over the boxes */
+    double ms_total;         /* wall time of the call */
+    double ms_pairs;         /* summed kernel time of the candidate passes (HIP events) */
+    double ms_sort;          /* summed time of the ranking and adjacency sorts (HIP events) */
+} sg_graph_info;
+
 sg_status sg_graph_build(sg_ctx *ctx, const sg_graph_desc *desc, void *hip_stream, int64_t *adj_ptr,
-                         int32_t *adj_idx, int64_t cap, int64_t *n_edges);
+                         int32_t *adj_idx, int64_t cap, int64_t *n_edges, sg_graph_info *info /* or NULL */);
 
 /* ------------------------------------------------------------------------------------ */
 /* Serving: continuous batching of many scenes on one device                             */

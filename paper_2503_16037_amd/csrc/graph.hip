@@ -13,12 +13,15 @@
 //
 // Pruning.  A pair with k >= t satisfies |q_i - q_j|^2 <= mu_i mu_max / t, so for a
 // threshold t every partner of node i lies in an axis-aligned box of voxels around
-// it (half-width sqrt(mu_i mu_max / t) standard deviations per axis).  One wavefront
-// per node walks its box in increasing node id (x fastest, then y, z, then the
-// surface row), computes k for the partners of higher id and compacts the
-// qualifying pairs in that order with a ballot prefix, so the candidate list is
-// ordered by (i, j).  A stable radix sort on k (descending) then ranks them with
-// equal couplings in (i, j) order.
+// it (half-width sqrt(mu_i mu_max / t) standard deviations per axis).  Box sizes
+// differ by orders of magnitude (a strongly scattering node reaches far), so the
+// cells of all boxes are flattened, node after node and within a box in increasing
+// partner id (x fastest, then y, z, then the surface row), and evaluated one per
+// thread; each thread finds its node by binary search in the prefix sum of the box
+// sizes.  k is computed for the partners of higher id and the qualifying pairs are
+// compacted in cell order (ballot and workgroup prefix, then the workgroups'
+// prefix sum), so the candidate list is ordered by (i, j).  A stable radix sort on
+// k (descending) then ranks them with equal couplings in (i, j) order.
 //   threshold mode: t = c_min^2, keep k > t;
 //   top-n mode: t = the lowest threshold whose boxes hold at most a fixed budget
 //   of cells (bisection on the box volumes); if at least n pairs have k >= t, the
@@ -27,6 +30,7 @@
 // The adjacency is assembled from the sorted directed pair codes (tail N + head).
 #include <hipcub/hipcub.hpp>
 
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <memory>
@@ -192,50 +196,136 @@ __global__ void k_graph_cells(Geo g, const long long *__restrict__ P, const doub
     if ((threadIdx.x & 63) == 0) atomicAdd(total, v);
 }
 
-// Candidate pairs (i, j), j > i, of nodes i in [n0, n1) with k >= t (strict: k > t),
-// k > 0.  kFill = false: count[i - n0] = their number; kFill = true: write them at
-// off[i - n0] in increasing j.  One wavefront per node, grid-stride over nodes.
+// Boxes of nodes n0 + r (r < n) at threshold t, stored as (lo x, lo y, lo z, extent
+// x, y, z, surface row, 0), and their cell counts (volume cells + surface cells);
+// cells[n] = 0 closes the array for the exclusive scan.
+__global__ void k_graph_boxes(Geo g, const long long *__restrict__ P, const double *__restrict__ mu, double t,
+                              long long n0, long long n, int *__restrict__ box, unsigned long long *__restrict__ cells) {
+    const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (r > n) return;
+    if (r == n) {
+        cells[n] = 0;
+        return;
+    }
+    const Box b = node_box(g, P, mu, n0 + r, t);
+    long long e[3];
+    for (int a = 0; a < 3; ++a) e[a] = b.hi[a] >= b.lo[a] ? b.hi[a] - b.lo[a] + 1 : 0;
+    const unsigned long long nv = (unsigned long long)e[0] * e[1] * e[2];
+    const unsigned long long ns = b.surf ? (unsigned long long)e[0] * e[1] : 0ull;
+    int *o = box + 8 * r;
+    o[0] = (int)b.lo[0]; o[1] = (int)b.lo[1]; o[2] = (int)b.lo[2];
+    o[3] = (int)e[0]; o[4] = (int)e[1]; o[5] = (int)e[2];
+    o[6] = b.surf ? 1 : 0; o[7] = 0;
+    cells[r] = nv + ns;
+}
+
+constexpr int kEvalRounds = 8;  // a workgroup covers kEvalRounds x 256 consecutive cells
+
+// last r in [a, b) with coff[r] <= c (coff ascending, coff[a] <= c)
+__device__ __forceinline__ long long owner(const unsigned long long *__restrict__ coff, long long a, long long b,
+                                           unsigned long long c) {
+    while (b - a > 1) {
+        const long long m = (a + b) >> 1;
+        if (coff[m] <= c) a = m;
+        else b = m;
+    }
+    return a;
+}
+
+// The cells of all boxes, flattened in node order (a node's cells in increasing
+// partner id), one thread per cell: the partner j > i is evaluated and the pairs
+// with k >= t (strict: k > t), k > 0 are counted per workgroup (kFill = false:
+// bcount) or written in cell order at the workgroup's offset (kFill = true), so the
+// list stays ordered by (i, j).  evals: the evaluated pairs (count pass).
 template <bool kFill>
-__global__ __launch_bounds__(256) void k_graph_pairs(Geo g, const long long *__restrict__ P,
-                                                     const double *__restrict__ q, const double *__restrict__ mu,
-                                                     double t, int strict, long long n0, long long n1,
-                                                     unsigned long long *__restrict__ count,
-                                                     const unsigned long long *__restrict__ off,
-                                                     double *__restrict__ keys,
-                                                     unsigned long long *__restrict__ codes) {
-    const int lane = threadIdx.x & 63;
-    const long long waves = (long long)gridDim.x * (blockDim.x >> 6);
-    for (long long i = n0 + blockIdx.x * (long long)(blockDim.x >> 6) + (threadIdx.x >> 6); i < n1; i += waves) {
-        const Box b = node_box(g, P, mu, i, t);
-        const long long bx = b.hi[0] - b.lo[0] + 1, by = b.hi[1] - b.lo[1] + 1, bz = b.hi[2] - b.lo[2] + 1;
-        const long long nv = (bx > 0 && by > 0 && bz > 0) ? bx * by * bz : 0;
-        const long long ns = (b.surf && bx > 0 && by > 0) ? bx * by : 0;
-        unsigned long long run = kFill ? off[i - n0] : 0ull;
-        for (long long c0 = 0; c0 < nv + ns; c0 += 64) {
-            const long long c = c0 + lane;
-            long long j = -1;
-            if (c < nv) {
-                const long long cx = b.lo[0] + c % bx, cy = b.lo[1] + (c / bx) % by, cz = b.lo[2] + c / (bx * by);
-                j = cx + g.nx * (cy + g.ny * cz);
-            } else if (c < nv + ns) {
-                const long long s = c - nv;
-                j = g.nvox + (b.lo[0] + s % bx) + g.nx * (b.lo[1] + s / bx);
+__global__ __launch_bounds__(256) void k_graph_eval(Geo g, const double *__restrict__ q,
+                                                    const double *__restrict__ mu, double t, int strict, long long n0,
+                                                    long long n, const int *__restrict__ box,
+                                                    const unsigned long long *__restrict__ coff, unsigned long long T,
+                                                    unsigned long long *__restrict__ bcount,
+                                                    const unsigned long long *__restrict__ boff,
+                                                    double *__restrict__ keys, unsigned long long *__restrict__ codes,
+                                                    unsigned long long *__restrict__ evals) {
+    constexpr int kCells = kEvalRounds * 256;
+    __shared__ unsigned int wcnt[4];
+    __shared__ long long range[2];
+    __shared__ unsigned long long scoff[kCells];  // box starts of the workgroup's nodes, when they fit
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned long long base = (unsigned long long)blockIdx.x * kCells;
+    unsigned long long run = kFill ? boff[blockIdx.x] : 0ull, ev = 0ull;
+    // the nodes owning this workgroup's cells: [fb, lb]
+    if (threadIdx.x == 0) {
+        const long long fb = owner(coff, 0, n, base);
+        const unsigned long long cl = base + kCells - 1 < T ? base + kCells - 1 : T - 1;
+        range[0] = fb;
+        range[1] = owner(coff, fb, n, cl);
+    }
+    __syncthreads();
+    const long long fb = range[0], lb = range[1];
+    const bool staged = lb - fb + 1 <= kCells;
+    if (staged)
+        for (long long x = threadIdx.x; x <= lb - fb; x += blockDim.x) scoff[x] = coff[fb + x];
+    __syncthreads();
+    for (int rd = 0; rd < kEvalRounds; ++rd) {
+        const unsigned long long c0 = base + (unsigned long long)rd * 256 + (unsigned long long)w * 64;
+        const unsigned long long c = c0 + lane;
+        bool ok = false, eval = false;
+        double k = 0.0;
+        long long i = 0, j = 0;
+        if (c < T) {
+            {
+                long long r;
+                if (staged) {  // last x with scoff[x] <= c, in LDS
+                    long long a = 0, b = lb - fb + 1;
+                    while (b - a > 1) {
+                        const long long m2 = (a + b) >> 1;
+                        if (scoff[m2] <= c) a = m2;
+                        else b = m2;
+                    }
+                    r = fb + a;
+                } else {
+                    r = owner(coff, fb, lb + 1, c);
+                }
+                const int *o = box + 8 * r;
+                // a box has at most 1024^3 + 1024^2 cells: 32-bit index arithmetic
+                const unsigned bx = (unsigned)o[3], by = (unsigned)o[4], bz = (unsigned)o[5];
+                const unsigned nv = bx * by * bz;
+                const unsigned lc = (unsigned)(c - (staged ? scoff[r - fb] : coff[r]));
+                i = n0 + r;
+                if (lc < nv) {
+                    const unsigned yz = lc / bx, cx = lc - yz * bx, cz = yz / by, cy = yz - cz * by;
+                    j = ((long long)o[0] + cx) + (long long)g.nx * (((long long)o[1] + cy) + (long long)g.ny * ((long long)o[2] + cz));
+                } else {
+                    const unsigned sl = lc - nv, sy = sl / bx, sx = sl - sy * bx;
+                    j = g.nvox + ((long long)o[0] + sx) + (long long)g.nx * ((long long)o[1] + sy);
+                }
+                eval = j > i;
+                if (eval) {
+                    k = pair_key(q, mu, i, j);
+                    ok = k > 0.0 && (strict ? k > t : k >= t);
+                }
             }
-            bool ok = false;
-            double k = 0.0;
-            if (j > i) {
-                k = pair_key(q, mu, i, j);
-                ok = k > 0.0 && (strict ? k > t : k >= t);
-            }
-            const unsigned long long m = __ballot(ok);
-            if (kFill && ok) {
-                const unsigned long long at = run + __popcll(m & ((1ull << lane) - 1ull));
-                keys[at] = k;
-                codes[at] = (unsigned long long)i * (unsigned long long)g.N + (unsigned long long)j;
-            }
-            run += __popcll(m);
         }
-        if (!kFill && lane == 0) count[i - n0] = run;
+        const unsigned long long m = __ballot(ok);
+        if (!kFill) ev += __popcll(__ballot(eval));
+        if (lane == 0) wcnt[w] = (unsigned int)__popcll(m);
+        __syncthreads();
+        unsigned long long before = 0, total = 0;
+        for (int v = 0; v < 4; ++v) {
+            before += v < w ? wcnt[v] : 0u;
+            total += wcnt[v];
+        }
+        if (kFill && ok) {
+            const unsigned long long at = run + before + __popcll(m & ((1ull << lane) - 1ull));
+            keys[at] = k;
+            codes[at] = (unsigned long long)i * (unsigned long long)g.N + (unsigned long long)j;
+        }
+        run += total;
+        __syncthreads();  // wcnt is rewritten by the next round
+    }
+    if (!kFill) {
+        if (threadIdx.x == 0) bcount[blockIdx.x] = run;
+        if (lane == 0 && ev) atomicAdd(evals, ev);
     }
 }
 
@@ -281,8 +371,32 @@ struct Builder {
     Dev dev;
     long long *P = nullptr;
     double *q = nullptr, *mu = nullptr;
-    unsigned long long *scal = nullptr;
+    unsigned long long *scal = nullptr;  // [0] cell total, [1] evaluated pairs
+    // build statistics: candidate passes, summed kernel times (HIP event pairs)
+    int passes = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs, ev_sort;
     Builder(Ctx *c, hipStream_t s) : ctx(c), st(s), dev(c) {}
+    ~Builder() {
+        for (auto &e : ev_pairs) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+        for (auto &e : ev_sort) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    }
+    // an event pair recording around whatever the caller enqueues next
+    std::pair<hipEvent_t, hipEvent_t> *mark(std::vector<std::pair<hipEvent_t, hipEvent_t>> &v) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (hipEventCreate(&a) != hipSuccess) return nullptr;
+        if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return nullptr; }
+        v.push_back({a, b});
+        (void)hipEventRecord(a, st);
+        return &v.back();
+    }
+    static double total_ms(const std::vector<std::pair<hipEvent_t, hipEvent_t>> &v) {
+        double t = 0.0;
+        for (auto &e : v) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) t += ms;
+        }
+        return t;
+    }
 
     sg_status cells(double t, unsigned long long &out) {
         GHIP(hipMemsetAsync(scal, 0, sizeof(unsigned long long), st));
@@ -300,24 +414,46 @@ struct Builder {
         const long long n = n1 - n0;
         if (n <= 0) return SG_OK;
         Dev tmp(ctx);
-        unsigned long long *cnt = nullptr, *off = nullptr;
-        GTRY(tmp.get(&cnt, n + 1));
-        GTRY(tmp.get(&off, n + 1));
-        GHIP(hipMemsetAsync(cnt + n, 0, sizeof(unsigned long long), st));
-        const unsigned grid = std::min<unsigned>(blocks_for(n, 4), 65536u);
-        hipLaunchKernelGGL((k_graph_pairs<false>), dim3(grid), dim3(256), 0, st, g, P, q, mu, t, strict, n0, n1, cnt,
-                           nullptr, nullptr, nullptr);
+        int *box = nullptr;
+        unsigned long long *cells = nullptr, *coff = nullptr;
+        GTRY(tmp.get(&box, 8 * n));
+        GTRY(tmp.get(&cells, n + 1));
+        GTRY(tmp.get(&coff, n + 1));
+        hipLaunchKernelGGL(k_graph_boxes, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st, g, P, mu, t, n0, n, box,
+                           cells);
         GHIP(hipGetLastError());
-        // off = have + exclusive sum of the counts; off[n] = the new total
         size_t tb = 0;
-        GHIP(hipcub::DeviceScan::ExclusiveScan(nullptr, tb, cnt, off, hipcub::Sum(), (unsigned long long)have,
-                                               (int)n + 1, st));
+        GHIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cells, coff, (int)n + 1, st));
         unsigned char *tsp = nullptr;
         GTRY(tmp.get(&tsp, tb));
-        GHIP(hipcub::DeviceScan::ExclusiveScan(tsp, tb, cnt, off, hipcub::Sum(), (unsigned long long)have, (int)n + 1,
-                                               st));
+        GHIP(hipcub::DeviceScan::ExclusiveSum(tsp, tb, cells, coff, (int)n + 1, st));
+        unsigned long long T = 0;
+        GHIP(hipMemcpyAsync(&T, coff + n, sizeof(T), hipMemcpyDeviceToHost, st));
+        GHIP(hipStreamSynchronize(st));
+        if (T == 0) return SG_OK;
+        const unsigned long long per = (unsigned long long)kEvalRounds * 256;
+        const unsigned long long nb = (T + per - 1) / per;
+        if (nb >= (1ull << 31)) return gfail(SG_E_NOMEM, "coupling boxes too large");
+        unsigned long long *bcount = nullptr, *boff = nullptr;
+        GTRY(tmp.get(&bcount, nb + 1));
+        GTRY(tmp.get(&boff, nb + 1));
+        GHIP(hipMemsetAsync(bcount + nb, 0, sizeof(unsigned long long), st));
+        ++passes;
+        auto *e0 = mark(ev_pairs);
+        hipLaunchKernelGGL((k_graph_eval<false>), dim3((unsigned)nb), dim3(256), 0, st, g, q, mu, t, strict, n0, n,
+                           box, coff, T, bcount, nullptr, nullptr, nullptr, scal + 1);
+        if (e0) (void)hipEventRecord(e0->second, st);
+        GHIP(hipGetLastError());
+        // boff = have + exclusive sum of the workgroup counts; boff[nb] = the new total
+        size_t tb2 = 0;
+        GHIP(hipcub::DeviceScan::ExclusiveScan(nullptr, tb2, bcount, boff, hipcub::Sum(), (unsigned long long)have,
+                                               (int)nb + 1, st));
+        unsigned char *tsp2 = nullptr;
+        GTRY(tmp.get(&tsp2, tb2));
+        GHIP(hipcub::DeviceScan::ExclusiveScan(tsp2, tb2, bcount, boff, hipcub::Sum(), (unsigned long long)have,
+                                               (int)nb + 1, st));
         unsigned long long total = 0;
-        GHIP(hipMemcpyAsync(&total, off + n, sizeof(total), hipMemcpyDeviceToHost, st));
+        GHIP(hipMemcpyAsync(&total, boff + nb, sizeof(total), hipMemcpyDeviceToHost, st));
         GHIP(hipStreamSynchronize(st));
         if (total >= (1ull << 31)) return gfail(SG_E_NOMEM, "more than 2^31 coupling candidates");
         if (total > have) {
@@ -329,10 +465,12 @@ struct Builder {
                 GHIP(hipMemcpyAsync(nk, keys, sizeof(double) * have, hipMemcpyDeviceToDevice, st));
                 GHIP(hipMemcpyAsync(nc, codes, sizeof(unsigned long long) * have, hipMemcpyDeviceToDevice, st));
             }
-            hipLaunchKernelGGL((k_graph_pairs<true>), dim3(grid), dim3(256), 0, st, g, P, q, mu, t, strict, n0, n1,
-                               nullptr, off, nk, nc);
+            auto *e1 = mark(ev_pairs);
+            hipLaunchKernelGGL((k_graph_eval<true>), dim3((unsigned)nb), dim3(256), 0, st, g, q, mu, t, strict, n0, n,
+                               box, coff, T, nullptr, boff, nk, nc, nullptr);
+            if (e1) (void)hipEventRecord(e1->second, st);
             GHIP(hipGetLastError());
-            GHIP(hipStreamSynchronize(st));  // the scan's scratch is released at return
+            GHIP(hipStreamSynchronize(st));  // the scratch above is released at return
             dev.release(keys);
             dev.release(codes);
             keys = nk;
@@ -354,7 +492,9 @@ struct Builder {
         GHIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, keys, k2, codes, c2, (int)n, 0, 64, st));
         unsigned char *tsp = nullptr;
         GTRY(tmp.get(&tsp, tb));
+        auto *e = mark(ev_sort);
         GHIP(hipcub::DeviceRadixSort::SortPairsDescending(tsp, tb, keys, k2, codes, c2, (int)n, 0, 64, st));
+        if (e) (void)hipEventRecord(e->second, st);
         GHIP(hipStreamSynchronize(st));
         dev.release(keys);
         dev.release(codes);
@@ -367,7 +507,8 @@ struct Builder {
 }  // namespace
 
 sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t *adj_ptr, int32_t *adj_idx,
-                      int64_t cap, int64_t *n_edges) {
+                      int64_t cap, int64_t *n_edges, sg_graph_info *info) {
+    const auto t_start = std::chrono::steady_clock::now();
     if (!d) return gfail(SG_E_INVALID, "desc is NULL");
     if (d->abi_version != SG_ABI_VERSION) return gfail(SG_E_ABI, "graph desc abi_version mismatch");
     if (!n_edges) return gfail(SG_E_INVALID, "n_edges is NULL");
@@ -436,6 +577,7 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
     GTRY(B.dev.get(&B.q, 3 * N));
     GTRY(B.dev.get(&B.mu, N));
     GTRY(B.dev.get(&B.scal, 4));
+    GHIP(hipMemsetAsync(B.scal, 0, 4 * sizeof(unsigned long long), st));
     GHIP(hipMemcpyAsync(pos, d->vol_pos_fx, sizeof(int) * 3 * nvox, hipMemcpyHostToDevice, st));
     GHIP(hipMemcpyAsync(mus, d->mu_s, sizeof(float) * nvox, hipMemcpyHostToDevice, st));
     if (d->surface_nodes)
@@ -445,10 +587,13 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
 
     // candidates and selection
     double *keys = nullptr;
-    unsigned long long *codes = nullptr, have = 0, n_sel = 0;
+    unsigned long long *codes = nullptr, have = 0, n_sel = 0, ranked = 0;
+    double t_used = 0.0;
+    int streamed = 0;
     if (d->n_pairs == 0) {
-        GTRY(B.pairs(d->c_min * d->c_min, 1, 0, N, keys, codes, have));
-        n_sel = have;
+        t_used = d->c_min * d->c_min;
+        GTRY(B.pairs(t_used, 1, 0, N, keys, codes, have));
+        n_sel = ranked = have;
     } else {
         // the lowest threshold (bisection in the exponent) whose boxes fit the cell budget
         const unsigned long long budget = cell_budget();
@@ -459,7 +604,9 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
             double lo = 1e-300, hi = 1e300;
             GTRY(B.cells(hi, cells));
             if (cells > budget) return gfail(SG_E_NOMEM, "coupling candidates exceed the cell budget");
-            for (int it = 0; it < 64; ++it) {
+            // geometric bisection to a factor of two: any threshold within the budget
+            // gives the same selection, a tighter one only fewer candidates
+            while (hi > 2.0 * lo) {
                 const double mid = std::sqrt(lo) * std::sqrt(hi);
                 if (!(mid > lo && mid < hi)) break;
                 GTRY(B.cells(mid, cells));
@@ -469,15 +616,21 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
             t_fit = hi;
         }
         GTRY(B.pairs(t_fit, 0, 0, N, keys, codes, have));
+        t_used = t_fit;
+        ranked = have;
         if (have >= (unsigned long long)d->n_pairs || t_fit == 0.0) {
             GTRY(B.sort_desc(keys, codes, have));
             n_sel = std::min<unsigned long long>(have, (unsigned long long)d->n_pairs);
         } else {
             // every pair, streamed in node chunks through a running best-n list
+            streamed = 1;
+            t_used = 0.0;
+            GHIP(hipMemsetAsync(B.scal + 1, 0, sizeof(unsigned long long), st));
             have = 0;
             const long long chunk = std::max<long long>(1, (long long)(budget / (unsigned long long)N));
             for (long long n0 = 0; n0 < N; n0 += chunk) {
                 GTRY(B.pairs(0.0, 1, n0, std::min(N, n0 + chunk), keys, codes, have));
+                ranked += have;
                 GTRY(B.sort_desc(keys, codes, have));
                 have = std::min<unsigned long long>(have, (unsigned long long)d->n_pairs);
             }
@@ -509,7 +662,9 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
         GHIP(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, dir, dir2, (int)E, 0, 64, st));
         unsigned char *tsp = nullptr;
         GTRY(tmp.get(&tsp, tb));
+        auto *e = B.mark(B.ev_sort);
         GHIP(hipcub::DeviceRadixSort::SortKeys(tsp, tb, dir, dir2, (int)E, 0, 64, st));
+        if (e) (void)hipEventRecord(e->second, st);
         hipLaunchKernelGGL(k_graph_heads, dim3(blocks_for(E, 256)), dim3(256), 0, st, E, N, dir2, head);
         GHIP(hipGetLastError());
     }
@@ -527,17 +682,30 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
     if (adj_ptr) GHIP(hipMemcpyAsync(adj_ptr, ptr, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToHost, st));
     if (adj_idx && cap >= E && E > 0)
         GHIP(hipMemcpyAsync(adj_idx, head, sizeof(int32_t) * E, hipMemcpyDeviceToHost, st));
+    unsigned long long evals = 0;
+    GHIP(hipMemcpyAsync(&evals, B.scal + 1, sizeof(evals), hipMemcpyDeviceToHost, st));
     GHIP(hipStreamSynchronize(st));
+    if (info) {
+        info->candidates = (int64_t)ranked;
+        info->pairs_evaluated = (int64_t)evals;
+        info->threshold = t_used;
+        info->streamed = streamed;
+        info->passes = B.passes;
+        info->ms_pairs = Builder::total_ms(B.ev_pairs);
+        info->ms_sort = Builder::total_ms(B.ev_sort);
+        info->ms_total =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
     return SG_OK;
 }
 
 }  // namespace sg
 
 extern "C" sg_status sg_graph_build(sg_ctx *ctx, const sg_graph_desc *desc, void *hip_stream, int64_t *adj_ptr,
-                                    int32_t *adj_idx, int64_t cap, int64_t *n_edges) {
+                                    int32_t *adj_idx, int64_t cap, int64_t *n_edges, sg_graph_info *info) {
     if (!ctx) return sg::gfail(SG_E_INVALID, "ctx is NULL");
     if (ctx->sticky.load()) return sg::gfail(SG_E_DEVICE, "context is in a failed state");
     if (hipSetDevice(ctx->device) != hipSuccess) return sg::gfail(SG_E_DEVICE, "hipSetDevice failed");
     return sg::graph_build(ctx, desc, hip_stream ? (hipStream_t)hip_stream : ctx->stream, adj_ptr, adj_idx, cap,
-                           n_edges);
+                           n_edges, info);
 }

@@ -46,6 +46,15 @@ class GraphDesc(C.Structure):
                 ("surf_albedo", C.c_void_p), ("n_pairs", C.c_int64), ("c_min", C.c_double)]
 
 
+class GraphInfo(C.Structure):
+    _fields_ = [("candidates", C.c_int64), ("pairs_evaluated", C.c_int64), ("threshold", C.c_double),
+                ("streamed", C.c_int32), ("passes", C.c_int32), ("ms_total", C.c_double),
+                ("ms_pairs", C.c_double), ("ms_sort", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class SolveOpts(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("precision", C.c_int32), ("solver", C.c_int32), ("rtol", C.c_double),
                 ("max_sweeps", C.c_int32), ("gmres_restart", C.c_int32), ("scatter_order", C.c_int32),
@@ -109,7 +118,7 @@ def lib():
                 "sg_wait": (I32, [P, U64, P, P]),
                 "sg_server_latencies": (I32, [P, P, I32, P]),
                 "sg_server_destroy": (I32, [P]),
-                "sg_graph_build": (I32, [P, P, P, P, P, I64, P]),
+                "sg_graph_build": (I32, [P, P, P, P, P, I64, P, P]),
             }
             for name, (res, args) in sigs.items():
                 f = getattr(L, name)
@@ -379,10 +388,11 @@ class Server:
             self.handle = None
 
 
-def graph_build(ctx: Context, scene, n_pairs: int = 0, c_min: float = 0.0, stream=None):
+def graph_build(ctx: Context, scene, n_pairs: int = 0, c_min: float = 0.0, stream=None, info: bool = False):
     """sg_graph_build: the scattering graph of the scene's nodes (the n_pairs strongest
     couplings, or those above c_min when n_pairs is 0).  Returns (adj_ptr int64 [N+1],
-    adj_idx int32 [n_edges]), the form a scene's adjacency takes."""
+    adj_idx int32 [n_edges]), the form a scene's adjacency takes, and with info=True
+    also the build statistics (sg_graph_info) as a dict."""
     keep = []
 
     def arr(a, dt):
@@ -404,10 +414,12 @@ def graph_build(ctx: Context, scene, n_pairs: int = 0, c_min: float = 0.0, strea
     ne = C.c_int64(0)
     cap = 2 * int(n_pairs)
     adj_idx = np.zeros(max(cap, 1), np.int32)
+    gi = GraphInfo()
     _check(lib().sg_graph_build(ctx.handle, C.byref(d), _stream_ptr(stream), _ptr(adj_ptr),
-                                _ptr(adj_idx) if cap else None, cap, C.byref(ne)))
+                                _ptr(adj_idx) if cap else None, cap, C.byref(ne), C.byref(gi)))
     if ne.value > cap:  # threshold mode: the size is known now
         adj_idx = np.zeros(ne.value, np.int32)
         _check(lib().sg_graph_build(ctx.handle, C.byref(d), _stream_ptr(stream), _ptr(adj_ptr), _ptr(adj_idx),
-                                    ne.value, C.byref(ne)))
-    return adj_ptr, adj_idx[:ne.value].copy()
+                                    ne.value, C.byref(ne), C.byref(gi)))
+    out = (adj_ptr, adj_idx[:ne.value].copy())
+    return out + (gi.as_dict(),) if info else out
