@@ -68,6 +68,10 @@ def lib():
             L.or_run.argtypes = [P, P]
             L.or_num_threads.restype = C.c_int
             L.or_num_threads.argtypes = []
+            L.or_phase_value.restype = C.c_double
+            L.or_phase_value.argtypes = [C.c_int, C.c_double, P, C.c_int, C.c_double]
+            L.or_table_integral.restype = C.c_double
+            L.or_table_integral.argtypes = [P, C.c_int]
             L.or_tails.restype = None
             L.or_tails.argtypes = [C.c_int64, P, C.c_int64, P]
             L.or_coupling_nodes.restype = C.c_int64
@@ -175,7 +179,8 @@ class _Scene(C.Structure):
                 ("phase_frac", C.c_void_p), ("pos", C.c_void_p), ("surface", C.c_int),
                 ("adj_ptr", C.c_void_p), ("adj_idx", C.c_void_p), ("albedo", C.c_void_p),
                 ("sun_dir", C.c_void_p), ("view_dir", C.c_void_p), ("n_fib", C.c_int),
-                ("node_weight_mode", C.c_int), ("scatter_order", C.c_int), ("tol", C.c_double)]
+                ("node_weight_mode", C.c_int), ("scatter_order", C.c_int), ("tol", C.c_double),
+                ("phase_kind", C.c_void_p), ("lut_n", C.c_int), ("lut", C.c_void_p)]
 
 
 class _Out(C.Structure):
@@ -227,9 +232,14 @@ def run(scene, abs_scale: float = 1.0, scatter_order: int = 0, tol: float = 1e-1
     E = int(adj_ptr[-1])
     nnz = int(lib().or_nnz(N, _p(adj_ptr)))
 
+    kind = getattr(scene, "phase_kind", None)
+    lut = getattr(scene, "phase_lut", None)
+    kind = None if kind is None else arr(kind, np.int32)
+    lut = None if lut is None else arr(lut, np.float64)
     sc = _Scene(scene.nx, scene.ny, scene.nz, float(scene.voxel_m), _p(mu_s), _p(mu_a), len(hg_g), _p(hg_g),
                 _p(pf), _p(pos), int(scene.surface_nodes), _p(adj_ptr), _p(adj_idx), _p(alb), _p(sun),
-                _p(view), int(scene.n_fib), int(scene.node_weight_mode), int(scatter_order), float(tol))
+                _p(view), int(scene.n_fib), int(scene.node_weight_mode), int(scatter_order), float(tol),
+                _p(kind), 0 if lut is None else int(lut.shape[-1]), _p(lut))
     res = dict(tau=np.zeros(E), tau_sun=np.zeros(N), rho=np.zeros(N), row_ptr=np.zeros(E + 1, np.int64),
                col=np.zeros(nnz, np.int32), val=np.zeros(nnz), S=np.zeros(E), phi=np.zeros(E),
                radiance=np.zeros(scene.nx * scene.ny), stats=np.zeros(4))
@@ -287,3 +297,10 @@ def coupling_graph(scene, n_pairs: int = 0, c_min: float = 0.0):
         if E >= 0:
             return adj_ptr, adj_idx[:E].copy()
         cap = int(adj_ptr[-1])
+
+
+def phase_value(kind: int, mu: float, g: float = 0.0, row=None) -> float:
+    """A phase-function component at cos(theta) = mu, normalised over the sphere
+    (0 Henyey-Greenstein g, 1 Rayleigh, 2 the table row)."""
+    r = None if row is None else np.ascontiguousarray(row, np.float64)
+    return float(lib().or_phase_value(int(kind), float(g), _p(r), 0 if r is None else len(r), float(mu)))

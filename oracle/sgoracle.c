@@ -326,7 +326,40 @@ typedef struct {
     int node_weight_mode;
     int scatter_order; /* 0 = multiple scattering, 1 = single scattering only */
     double tol;        /* target of the solve: L1 update / ||S||_1, and 10 tol per edge (relative) */
+    const int *phase_kind; /* [n_phase] 0 Henyey-Greenstein, 1 Rayleigh, 2 table; NULL: all 0 */
+    int lut_n;             /* samples per table row */
+    const double *lut;     /* [n_phase][lut_n] tables in mu = cos(theta) on [-1, 1] */
 } or_scene;
+
+/*
+ * Phase-function components (Sec. 3: Rayleigh scattering, or a particle phase
+ * function given as a look-up table), each normalised over the sphere.  A table
+ * holds samples at mu_m = -1 + 2 m / (n - 1), linear in mu between them; its
+ * interpolant integrates over the sphere to 2 pi x the trapezoid rule in mu.
+ */
+double or_table_integral(const double *row, int n) {
+    double sum = 0.0;
+    for (int m = 0; m < n; ++m) sum += row[m];
+    return (2.0 * M_PI) * ((2.0 / (double)(n - 1)) * (sum - 0.5 * (row[0] + row[n - 1])));
+}
+
+double or_phase_value(int kind, double g, const double *row, int n, double mu) {
+    if (kind == 1) return (3.0 / (16.0 * M_PI)) * (1.0 + mu * mu);
+    if (kind == 2) {
+        const double x = (mu + 1.0) * (0.5 * (double)(n - 1));
+        int m = (int)floor(x);
+        if (m < 0) m = 0;
+        if (m > n - 2) m = n - 2;
+        const double f = x - (double)m;
+        return (row[m] * (1.0 - f) + row[m + 1] * f) / or_table_integral(row, n);
+    }
+    return hg(g, mu);
+}
+
+static double phase_of(const or_scene *sc, int c, double mu) {
+    const int kind = sc->phase_kind ? sc->phase_kind[c] : 0;
+    return or_phase_value(kind, sc->hg_g[c], sc->lut ? sc->lut + (size_t)c * sc->lut_n : NULL, sc->lut_n, mu);
+}
 
 typedef struct {
     double *tau;      /* [E]   optical depth of the edge's pair (lower id -> higher id) */
@@ -607,7 +640,15 @@ int or_run(const or_scene *sc, or_out *out) {
     double *lat = (double *)malloc(sizeof(double) * 3 * NF);
     or_lattice(NF, lat);
     double *tab = (double *)malloc(sizeof(double) * NF * sc->n_phase);
-    for (int k = 0; k < sc->n_phase; ++k) or_hg_table(sc->hg_g[k], NF, lat, tab + (size_t)k * NF);
+    for (int k = 0; k < sc->n_phase; ++k) {
+        /* the component toward each lattice point (cosine p_i,z to the pole), normalised */
+        double *t = tab + (size_t)k * NF, s = 0.0;
+        for (int i = 0; i < NF; ++i) {
+            t[i] = phase_of(sc, k, lat[3 * i + 2]);
+            s += t[i];
+        }
+        for (int i = 0; i < NF; ++i) t[i] = t[i] / s;
+    }
 
     double sun_u[3], sun_in[3];
     unit_of(sc->sun_dir, sun_u);
@@ -716,7 +757,7 @@ int or_run(const or_scene *sc, or_out *out) {
                 double th_sun = 0.0;
                 for (int c = 0; c < sc->n_phase; ++c) {
                     double f = sc->phase_frac ? sc->phase_frac[(size_t)c * nvox + v] : 1.0;
-                    th_sun += f * hg(sc->hg_g[c], sun_in[0] * vu[0] + sun_in[1] * vu[1] + sun_in[2] * vu[2]);
+                    th_sun += f * phase_of(sc, c, sun_in[0] * vu[0] + sun_in[1] * vu[1] + sun_in[2] * vu[2]);
                 }
                 double J = th_sun * exp(-out->tau_sun[v]);
                 if (sc->scatter_order != 1) {
@@ -730,7 +771,7 @@ int or_run(const or_scene *sc, or_out *out) {
                         double th = 0.0;
                         for (int c = 0; c < sc->n_phase; ++c) {
                             double f = sc->phase_frac ? sc->phase_frac[(size_t)c * nvox + v] : 1.0;
-                            th += f * hg(sc->hg_g[c], mu);
+                            th += f * phase_of(sc, c, mu);
                         }
                         int64_t a = edge_rev(sc, e, v);
                         J += th * exp(-out->tau[e]) * out->phi[a];

@@ -59,6 +59,8 @@ class Scene:
     node_weight_mode: int = 0   # 0 = bounded scattering probability, 1 = literal mu_s * voxel edge
     abs_scale: Optional[np.ndarray] = None  # float32 [n_lambda] multipliers of mu_a (batched wavelengths)
     angles: tuple = (0.0, 0.0, 0.0, 0.0)    # (sza, saa, vza, vaa) in degrees, informational
+    phase_kind: Optional[np.ndarray] = None  # int32 [n_phase]: 0 Henyey-Greenstein, 1 Rayleigh, 2 table
+    phase_lut: Optional[np.ndarray] = None   # float64 [n_phase, n] tables in cos(theta) on [-1, 1]
 
     # ---- derived sizes (no method arithmetic) ----
     @property
@@ -93,8 +95,9 @@ class Scene:
         arrs = [self.mu_s, self.mu_a, self.hg_g, self.vol_pos_fx, self.adj_ptr, self.adj_idx, self.surf_albedo]
         if self.phase_frac is not None:
             arrs.append(self.phase_frac)
-        if self.abs_scale is not None:
-            arrs.append(self.abs_scale)
+        for a in (self.abs_scale, self.phase_kind, self.phase_lut):
+            if a is not None:
+                arrs.append(a)
         return int(sum(a.nbytes for a in arrs))
 
     def all_positions(self) -> np.ndarray:
@@ -111,8 +114,9 @@ class Scene:
             h.update(np.ascontiguousarray(a).tobytes())
         if self.phase_frac is not None:
             h.update(np.ascontiguousarray(self.phase_frac).tobytes())
-        if self.abs_scale is not None:
-            h.update(np.ascontiguousarray(self.abs_scale).tobytes())
+        for a in (self.abs_scale, self.phase_kind, self.phase_lut):
+            if a is not None:
+                h.update(np.ascontiguousarray(a).tobytes())
         h.update(repr((self.nx, self.ny, self.nz, self.voxel_m, self.surface_nodes, self.n_fib,
                        self.node_weight_mode)).encode())
         return h.hexdigest()[:16]
