@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define SG_ABI_VERSION 2u
+#define SG_ABI_VERSION 3u
 
 typedef int32_t sg_status;
 enum {
@@ -94,8 +94,9 @@ typedef struct sg_scene_desc {
     double voxel_m;            /* voxel edge in metres, > 0 */
     const float *mu_s;         /* [nz][ny][nx] scattering coefficient, 1/m, finite, >= 0 */
     const float *mu_a;         /* [nz][ny][nx] absorption coefficient, 1/m, finite, >= 0 */
-    int32_t n_phase;           /* 1..4 Henyey-Greenstein components */
-    const double *hg_g;        /* [n_phase] asymmetry parameters, |g| < 1 */
+    int32_t n_phase;           /* 1..4 phase-function components (kinds below) */
+    const double *hg_g;        /* [n_phase] Henyey-Greenstein asymmetry parameters, |g| < 1
+                                  (read for Henyey-Greenstein components) */
     const float *phase_frac;   /* [n_phase][nz][ny][nx] mixing fractions (by scattering
                                   coefficient); NULL iff n_phase == 1 */
     const int32_t *vol_pos_fx; /* [nz*ny*nx][3] node positions (x, y, z), fixed point,
@@ -113,7 +114,19 @@ typedef struct sg_scene_desc {
     int32_t n_lambda;          /* wavelengths solved together, 1..256 */
     const float *abs_scale;    /* [n_lambda] multipliers of mu_a per wavelength (> 0);
                                   NULL means one wavelength with multiplier 1 */
+    /* Phase-function kinds (Sec. 3: Rayleigh scattering, or a particle phase function
+       given as a look-up table), per component; NULL: all Henyey-Greenstein.  Every
+       component is normalised to integrate to 1 over the sphere. */
+    const int32_t *phase_kind; /* [n_phase]: SG_PHASE_HG (hg_g[k]), SG_PHASE_RAYLEIGH
+                                  ((3 / 16 pi)(1 + cos^2)), SG_PHASE_TABLE (row k of phase_lut) */
+    int32_t phase_lut_n;       /* samples per table row, 2..4096 (when a component is a table) */
+    const double *phase_lut;   /* [n_phase][phase_lut_n]: the phase function at cos(theta) =
+                                  -1 + 2 m / (phase_lut_n - 1), finite, >= 0, not all zero in a
+                                  table row; linear in cos(theta) between samples, scaled by the
+                                  exact integral of that interpolant (rows of other kinds are
+                                  not read) */
 } sg_scene_desc;
+enum { SG_PHASE_HG = 0, SG_PHASE_RAYLEIGH = 1, SG_PHASE_TABLE = 2 };
 
 /*
  * Validate a scene (sizes, finite and bounded values, node positions strictly

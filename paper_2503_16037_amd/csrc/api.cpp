@@ -93,14 +93,44 @@ void host_lattice(int N, std::vector<double> &p) {
 
 // Per-component Henyey-Greenstein table normalised over the lattice, then the
 // Lambertian cosine weights max(0, z_i) / sum_j max(0, z_j).
-void host_tables(int N, const std::vector<double> &p, int n_phase, const double *g, std::vector<double> &t) {
+// A phase table row at cos(theta) = mu: linear between the samples at -1 + 2 m / (n - 1)
+// (unscaled).
+double table_value(const double *row, int n, double mu) {
+    const double x = (mu + 1.0) * (0.5 * (double)(n - 1));
+    int m = (int)std::floor(x);
+    m = m < 0 ? 0 : (m > n - 2 ? n - 2 : m);
+    const double f = x - (double)m;
+    return row[m] * (1.0 - f) + row[m + 1] * f;
+}
+
+// Integral over the sphere of a table row's interpolant: 2 pi x the trapezoid rule in mu
+// (exact for the piecewise-linear interpolant).
+double table_integral(const double *row, int n) {
+    double sum = 0.0;
+    for (int m = 0; m < n; ++m) sum += row[m];
+    const double trap = sum - 0.5 * (row[0] + row[n - 1]);
+    return (2.0 * M_PI) * ((2.0 / (double)(n - 1)) * trap);
+}
+
+// Lattice weights of every phase component (the value toward lattice point i, whose
+// angle to the pole has cosine p_i,z, normalised to sum 1), then the Lambertian
+// cosine weights.
+void host_tables(int N, const std::vector<double> &p, int n_phase, const int *kind, const double *g,
+                 const double *lut, int lut_n, std::vector<double> &t) {
     t.assign((size_t)(n_phase + 1) * N, 0.0);
     for (int k = 0; k < n_phase; ++k) {
         double s = 0.0;
         for (int i = 0; i < N; ++i) {
             const double mu = p[3 * i + 2];
-            const double den = 1.0 + g[k] * g[k] - 2.0 * g[k] * mu;
-            const double v = (1.0 - g[k] * g[k]) / (4.0 * M_PI * den * std::sqrt(den));
+            double v;
+            if (kind[k] == SG_PHASE_RAYLEIGH) {
+                v = 1.0 + mu * mu;
+            } else if (kind[k] == SG_PHASE_TABLE) {
+                v = table_value(lut + (size_t)k * lut_n, lut_n, mu);
+            } else {
+                const double den = 1.0 + g[k] * g[k] - 2.0 * g[k] * mu;
+                v = (1.0 - g[k] * g[k]) / (4.0 * M_PI * den * std::sqrt(den));
+            }
             t[(size_t)k * N + i] = v;
             s += v;
         }
@@ -130,8 +160,26 @@ sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz,
     if (d->n_phase < 1 || d->n_phase > 4) return fail(SG_E_INVALID, "n_phase must be 1..4");
     if ((d->n_phase > 1) != (d->phase_frac != nullptr))
         return fail(SG_E_INVALID, "phase_frac must be given iff n_phase > 1");
-    for (int k = 0; k < d->n_phase; ++k)
-        if (!(std::fabs(d->hg_g[k]) < 1.0)) return fail(SG_E_INVALID, "|g| must be < 1");
+    bool any_table = false;
+    for (int k = 0; k < d->n_phase; ++k) {
+        const int kind = d->phase_kind ? d->phase_kind[k] : SG_PHASE_HG;
+        if (kind != SG_PHASE_HG && kind != SG_PHASE_RAYLEIGH && kind != SG_PHASE_TABLE)
+            return fail(SG_E_INVALID, "phase_kind must be SG_PHASE_HG, SG_PHASE_RAYLEIGH or SG_PHASE_TABLE");
+        if (kind == SG_PHASE_HG && !(std::fabs(d->hg_g[k]) < 1.0)) return fail(SG_E_INVALID, "|g| must be < 1");
+        any_table = any_table || kind == SG_PHASE_TABLE;
+    }
+    if (any_table) {
+        if (!d->phase_lut || d->phase_lut_n < 2 || d->phase_lut_n > 4096)
+            return fail(SG_E_INVALID, "a table phase function needs phase_lut and phase_lut_n in 2..4096");
+        for (int k = 0; k < d->n_phase; ++k) {
+            if (d->phase_kind[k] != SG_PHASE_TABLE) continue;
+            const double *row = d->phase_lut + (size_t)k * d->phase_lut_n;
+            for (int m = 0; m < d->phase_lut_n; ++m)
+                if (!(row[m] >= 0.0) || !std::isfinite(row[m]))
+                    return fail(SG_E_INVALID, "phase_lut values must be finite and >= 0");
+            if (!(table_integral(row, d->phase_lut_n) > 0.0)) return fail(SG_E_INVALID, "a phase_lut row is all zero");
+        }
+    }
     if (d->n_fib < 1 || d->n_fib > 128) return fail(SG_E_INVALID, "n_fib must be 1..128");
     if (d->node_weight_mode != 0 && d->node_weight_mode != 1) return fail(SG_E_INVALID, "node_weight_mode must be 0 or 1");
     if (d->n_lambda < 1 || d->n_lambda > 256) return fail(SG_E_INVALID, "n_lambda must be 1..256");
@@ -861,7 +909,7 @@ namespace {
 void free_scene_impl(Scene *s) {
     clear_graphs(*s);
     void *ptrs[] = {s->mu_s, s->mu_a, s->frac, s->albedo, s->abs_scale_d, s->pos, s->adj_ptr, s->adj_idx, s->lat,
-                    s->tab, s->rev, s->nodeoff, s->row_ptr, s->col_idx, s->scan_tmp, s->tau_s, s->tau_a, s->tsun_s,
+                    s->tab, s->lut, s->rev, s->nodeoff, s->row_ptr, s->col_idx, s->scan_tmp, s->tau_s, s->tau_a, s->tsun_s,
                     s->tsun_a, s->T, s->Tsun, s->rho, s->val, s->S, s->x, s->y, s->c_rhs, s->c_a, s->c_b, s->qsun,
                     s->q, s->bS, s->bx, s->by, s->brho, s->bsrc, s->lam_buf, s->x64, s->r64, s->gm_V, s->partial, s->meas, s->meas_part, s->scal, s->J, s->pix};
     if (s->ctx)
@@ -895,7 +943,14 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     s.nnz = nnz;
     s.dmax = std::max(dmax, 1);
     s.n_phase = d->n_phase;
-    for (int k = 0; k < d->n_phase; ++k) s.hg_g[k] = d->hg_g[k];
+    for (int k = 0; k < d->n_phase; ++k) {
+        s.hg_g[k] = d->hg_g[k];
+        s.phase_kind[k] = d->phase_kind ? d->phase_kind[k] : SG_PHASE_HG;
+        if (s.phase_kind[k] == SG_PHASE_TABLE) {
+            s.lut_n = d->phase_lut_n;
+            s.lut_scale[k] = 1.0 / table_integral(d->phase_lut + (size_t)k * d->phase_lut_n, d->phase_lut_n);
+        }
+    }
     s.n_fib = d->n_fib;
     s.surface = d->surface_nodes ? 1 : 0;
     s.weight_mode = d->node_weight_mode;
@@ -920,6 +975,7 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     SG_TRY(dalloc(s, &s.adj_idx, (size_t)s.E));
     SG_TRY(dalloc(s, &s.lat, (size_t)3 * s.n_fib));
     SG_TRY(dalloc(s, &s.tab, (size_t)(s.n_phase + 1) * s.n_fib));
+    if (s.lut_n) SG_TRY(dalloc(s, &s.lut, (size_t)s.n_phase * s.lut_n));
     // structure
     SG_TRY(dalloc(s, &s.rev, (size_t)s.E));
     SG_TRY(dalloc(s, &s.nodeoff, (size_t)s.N + 1));
@@ -970,7 +1026,8 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     }
     std::vector<double> lat, tab;
     host_lattice(s.n_fib, lat);
-    host_tables(s.n_fib, lat, s.n_phase, s.hg_g, tab);
+    host_tables(s.n_fib, lat, s.n_phase, s.phase_kind, s.hg_g, d->phase_lut, s.lut_n, tab);
+    if (s.lut) SG_TRY(upload(s, s.lut, d->phase_lut, sizeof(double) * s.n_phase * (size_t)s.lut_n, st));
     SG_TRY(upload(s, s.mu_s, d->mu_s, sizeof(float) * s.nvox, st));
     SG_TRY(upload(s, s.mu_a, d->mu_a, sizeof(float) * s.nvox, st));
     if (s.frac) SG_TRY(upload(s, s.frac, d->phase_frac, sizeof(float) * s.n_phase * (size_t)s.nvox, st));
@@ -1087,8 +1144,10 @@ uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st) {
     const uint64_t nvox = (uint64_t)d->nx * d->ny * d->nz, npx = (uint64_t)d->nx * d->ny;
     const uint64_t nl = (uint64_t)d->n_lambda, nf = (uint64_t)d->n_fib, np = (uint64_t)d->n_phase;
     const uint64_t n = (uint64_t)N, e = (uint64_t)E, z = (uint64_t)nnz;
+    bool table = false;
+    for (int k = 0; k < d->n_phase; ++k) table = table || (d->phase_kind && d->phase_kind[k] == SG_PHASE_TABLE);
     uint64_t b = a(nvox, 4) * 2 + (np > 1 ? a(np * nvox, 4) : 0) + a(npx, 4) + a(3 * n, 4) + a(n + 1, 8) +
-                 a(e, 4) + a(3 * nf, 8) + a((np + 1) * nf, 8);
+                 a(e, 4) + a(3 * nf, 8) + a((np + 1) * nf, 8) + (table ? a(np * (uint64_t)d->phase_lut_n, 8) : 0);
     b += a(e, 4) + a(n + 1, 8) + a(e + 1, 8) + a(n / 2048 + 2, 8) + a(e, 4);
     b += a(e * nl, 8) * 2 + a(std::max<uint64_t>((n + 3) / 4, 65 * 1024), 8) +
          a(n * nl, 8) + a((uint64_t)node_chunks((int)n, (int)nl) * nl * 2, 8) + a(256, 8) +

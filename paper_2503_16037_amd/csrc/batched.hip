@@ -369,17 +369,12 @@ __global__ void k_fill_f32(float *__restrict__ a, long long n) {
         a[i] = 0.f;
 }
 
-struct PhaseMixB {
-    double g[4];
-    int n;
-};
-
-__device__ __forceinline__ double theta_mix_b(const PhaseMixB &pm, const float *__restrict__ frac, int nvox, int v,
+__device__ __forceinline__ double theta_mix_b(const PhaseSet &pm, const float *__restrict__ frac, int nvox, int v,
                                               double mu) {
     double th = 0.0;
     for (int c = 0; c < pm.n; ++c) {
         const double f = frac ? (double)frac[(long long)c * nvox + v] : 1.0;
-        th += f * hg_phase(pm.g[c], mu);
+        th += f * phase_theta(pm, c, mu);
     }
     return th;
 }
@@ -391,7 +386,7 @@ __global__ __launch_bounds__(64) void k_bnode_J(int N, int nvox, int nl, const l
                                                const int *__restrict__ pos, const float *__restrict__ tau_s,
                                                const float *__restrict__ tau_a, const float *__restrict__ abs_scale,
                                                const float *__restrict__ bsrc, const double *__restrict__ phi,
-                                               PhaseMixB pm, const float *__restrict__ frac, double sx, double sy,
+                                               PhaseSet pm, const float *__restrict__ frac, double sx, double sy,
                                                double sz, double vx, double vy, double vz, int multiple,
                                                double *__restrict__ J) {
     __shared__ double th[64];
@@ -585,9 +580,7 @@ void launch_fill_f32(float *a, long long n, hipStream_t st) {
 }
 
 void launch_batched_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance) {
-    PhaseMixB pm;
-    pm.n = s.n_phase;
-    for (int i = 0; i < 4; ++i) pm.g[i] = s.hg_g[i];
+    const PhaseSet pm = phase_set(s);
     hipLaunchKernelGGL(k_bnode_J, dim3(s.N), dim3(64), 0, st, s.N, s.nvox, s.n_lambda, s.adj_ptr, s.adj_idx, s.rev,
                        s.pos, (const float *)s.tau_s, (const float *)s.tau_a, s.abs_scale_d, s.bsrc, phi, pm, s.frac,
                        s.sun_in[0], s.sun_in[1], s.sun_in[2], s.view_u[0], s.view_u[1], s.view_u[2],

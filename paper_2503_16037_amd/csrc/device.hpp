@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "internal.hpp"
+
 namespace sg {
 
 constexpr long long kFx = 65536;  // fixed-point units per voxel edge
@@ -82,6 +84,21 @@ __device__ __forceinline__ Real ratio(long long num, long long den) {
 __device__ __forceinline__ double hg_phase(double g, double mu) {
     const double den = 1.0 + g * g - 2.0 * g * mu;
     return (1.0 - g * g) / (4.0 * 3.14159265358979323846 * den * sqrt(den));
+}
+
+// Component c at cos(theta) = mu, normalised over the sphere.
+__device__ __forceinline__ double phase_theta(const PhaseSet &ps, int c, double mu) {
+    if (ps.kind[c] == 1) return (3.0 / (16.0 * 3.14159265358979323846)) * (1.0 + mu * mu);
+    if (ps.kind[c] == 2) {
+        const int n = ps.lut_n;
+        const double x = (mu + 1.0) * (0.5 * (double)(n - 1));
+        int m = (int)floor(x);
+        m = m < 0 ? 0 : (m > n - 2 ? n - 2 : m);
+        const double f = x - (double)m;
+        const double *row = ps.lut + (long long)c * n;
+        return (row[m] * (1.0 - f) + row[m + 1] * f) * ps.scale[c];
+    }
+    return hg_phase(ps.g[c], mu);
 }
 
 // Deterministic sum over a 64-lane wavefront (fixed butterfly order).

@@ -16,17 +16,12 @@ namespace sg {
 
 namespace {
 
-struct PhaseMix {
-    double g[4];
-    int n;
-};
-
-__device__ __forceinline__ double theta_mix(const PhaseMix &pm, const float *__restrict__ frac, int nvox, int v,
+__device__ __forceinline__ double theta_mix(const PhaseSet &pm, const float *__restrict__ frac, int nvox, int v,
                                             double mu) {
     double th = 0.0;
     for (int c = 0; c < pm.n; ++c) {
         const double f = frac ? (double)frac[(long long)c * nvox + v] : 1.0;
-        th += f * hg_phase(pm.g[c], mu);
+        th += f * phase_theta(pm, c, mu);
     }
     return th;
 }
@@ -37,7 +32,7 @@ __global__ __launch_bounds__(256) void k_node_J(int N, int nvox, const long long
                                                const int *__restrict__ adj_idx, const int *__restrict__ rev,
                                                const int *__restrict__ pos, const Real *__restrict__ T,
                                                const Real *__restrict__ Tsun, const double *__restrict__ phi,
-                                               PhaseMix pm, const float *__restrict__ frac, double sx, double sy,
+                                               PhaseSet pm, const float *__restrict__ frac, double sx, double sy,
                                                double sz, double vx, double vy, double vz, double mu0,
                                                int multiple, double *__restrict__ J) {
     const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -121,9 +116,7 @@ __global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, const flo
 
 template <class Real>
 void launch_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance) {
-    PhaseMix pm;
-    pm.n = s.n_phase;
-    for (int i = 0; i < 4; ++i) pm.g[i] = s.hg_g[i];
+    const PhaseSet pm = phase_set(s);
     hipLaunchKernelGGL((k_node_J<Real>), dim3((s.N + 3) / 4), dim3(256), 0, st, s.N, s.nvox, s.adj_ptr, s.adj_idx,
                        s.rev, s.pos, (const Real *)s.T, (const Real *)s.Tsun, phi, pm, s.frac, s.sun_in[0],
                        s.sun_in[1], s.sun_in[2], s.view_u[0], s.view_u[1], s.view_u[2], s.mu0,

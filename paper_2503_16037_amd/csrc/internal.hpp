@@ -67,6 +67,10 @@ struct Scene {
     int dmax = 0;
     int n_phase = 1;
     double hg_g[4] = {0, 0, 0, 0};
+    int phase_kind[4] = {0, 0, 0, 0};  // SG_PHASE_HG, SG_PHASE_RAYLEIGH, SG_PHASE_TABLE
+    int lut_n = 0;                     // samples per phase table row (0: no table)
+    double lut_scale[4] = {1, 1, 1, 1};  // 1 / integral over the sphere of each table row
+    double *lut = nullptr;             // [n_phase][lut_n] phase tables (device)
     int n_fib = 100;
     int surface = 1;
     int weight_mode = 0;
@@ -132,6 +136,30 @@ struct Scene {
     int last_scatter_order = 0;
     std::mutex mu;
 };
+
+// The phase-function components of a scene (Sec. 3): kind 0 Henyey-Greenstein (g),
+// 1 Rayleigh, 2 a table in cos(theta) (row c of lut, lut_n samples at -1 + 2 m /
+// (lut_n - 1), linear between them, times scale[c] = 1 / its integral over the
+// sphere).  Passed to kernels by value; lut in device memory.
+struct PhaseSet {
+    double g[4], scale[4];
+    int kind[4];
+    int n, lut_n;
+    const double *lut;
+};
+
+inline PhaseSet phase_set(const Scene &s) {
+    PhaseSet p;
+    for (int c = 0; c < 4; ++c) {
+        p.g[c] = s.hg_g[c];
+        p.scale[c] = s.lut_scale[c];
+        p.kind[c] = s.phase_kind[c];
+    }
+    p.n = s.n_phase;
+    p.lut_n = s.lut_n;
+    p.lut = s.lut;
+    return p;
+}
 
 // ---- scene lifecycle (api.cpp) ----
 sg_status create_scene(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Scene &s);

@@ -38,7 +38,8 @@ struct Request {
     // owned copy of the description
     sg_scene_desc d{};
     std::vector<float> mu_s, mu_a, frac, albedo, abs_scale;
-    std::vector<double> g;
+    std::vector<double> g, lut;
+    std::vector<int32_t> kinds;
     std::vector<int32_t> pos, adj_idx;
     std::vector<int64_t> adj_ptr;
     // results
@@ -59,6 +60,12 @@ struct Request {
         albedo.assign(src->surf_albedo, src->surf_albedo + npx);
         if (src->abs_scale) abs_scale.assign(src->abs_scale, src->abs_scale + src->n_lambda);
         g.assign(src->hg_g, src->hg_g + src->n_phase);
+        if (src->phase_kind) {
+            kinds.assign(src->phase_kind, src->phase_kind + src->n_phase);
+            bool table = false;
+            for (int k = 0; k < src->n_phase; ++k) table = table || src->phase_kind[k] == SG_PHASE_TABLE;
+            if (table) lut.assign(src->phase_lut, src->phase_lut + (size_t)src->n_phase * src->phase_lut_n);
+        }
         pos.assign(src->vol_pos_fx, src->vol_pos_fx + 3 * nvox);
         adj_ptr.assign(src->adj_ptr, src->adj_ptr + N + 1);
         if (E) adj_idx.assign(src->adj_idx, src->adj_idx + E);
@@ -72,6 +79,8 @@ struct Request {
         d.surf_albedo = albedo.data();
         d.abs_scale = abs_scale.empty() ? nullptr : abs_scale.data();
         d.hg_g = g.data();
+        d.phase_kind = kinds.empty() ? nullptr : kinds.data();
+        d.phase_lut = lut.empty() ? nullptr : lut.data();
         d.vol_pos_fx = pos.data();
         d.adj_ptr = adj_ptr.data();
         d.adj_idx = adj_idx.empty() ? nullptr : adj_idx.data();
