@@ -72,6 +72,10 @@ def lib():
             L.or_phase_value.argtypes = [C.c_int, C.c_double, P, C.c_int, C.c_double]
             L.or_table_integral.restype = C.c_double
             L.or_table_integral.argtypes = [P, C.c_int]
+            L.or_hull_adjacency.restype = C.c_int
+            L.or_hull_adjacency.argtypes = [C.c_int, P, C.c_int, P, P]
+            L.or_colours.restype = C.c_int
+            L.or_colours.argtypes = [P, C.c_int, P, C.c_int, C.c_int, P]
             L.or_tails.restype = None
             L.or_tails.argtypes = [C.c_int64, P, C.c_int64, P]
             L.or_coupling_nodes.restype = C.c_int64
@@ -180,7 +184,7 @@ class _Scene(C.Structure):
                 ("adj_ptr", C.c_void_p), ("adj_idx", C.c_void_p), ("albedo", C.c_void_p),
                 ("sun_dir", C.c_void_p), ("view_dir", C.c_void_p), ("n_fib", C.c_int),
                 ("node_weight_mode", C.c_int), ("scatter_order", C.c_int), ("tol", C.c_double),
-                ("phase_kind", C.c_void_p), ("lut_n", C.c_int), ("lut", C.c_void_p)]
+                ("phase_kind", C.c_void_p), ("lut_n", C.c_int), ("lut", C.c_void_p), ("sigma_mode", C.c_int)]
 
 
 class _Out(C.Structure):
@@ -239,7 +243,7 @@ def run(scene, abs_scale: float = 1.0, scatter_order: int = 0, tol: float = 1e-1
     sc = _Scene(scene.nx, scene.ny, scene.nz, float(scene.voxel_m), _p(mu_s), _p(mu_a), len(hg_g), _p(hg_g),
                 _p(pf), _p(pos), int(scene.surface_nodes), _p(adj_ptr), _p(adj_idx), _p(alb), _p(sun),
                 _p(view), int(scene.n_fib), int(scene.node_weight_mode), int(scatter_order), float(tol),
-                _p(kind), 0 if lut is None else int(lut.shape[-1]), _p(lut))
+                _p(kind), 0 if lut is None else int(lut.shape[-1]), _p(lut), int(getattr(scene, "sigma_mode", 0)))
     res = dict(tau=np.zeros(E), tau_sun=np.zeros(N), rho=np.zeros(N), row_ptr=np.zeros(E + 1, np.int64),
                col=np.zeros(nnz, np.int32), val=np.zeros(nnz), S=np.zeros(E), phi=np.zeros(E),
                radiance=np.zeros(scene.nx * scene.ny), stats=np.zeros(4))
@@ -304,3 +308,25 @@ def phase_value(kind: int, mu: float, g: float = 0.0, row=None) -> float:
     (0 Henyey-Greenstein g, 1 Rayleigh, 2 the table row)."""
     r = None if row is None else np.ascontiguousarray(row, np.float64)
     return float(lib().or_phase_value(int(kind), float(g), _p(r), 0 if r is None else len(r), float(mu)))
+
+
+def hull_adjacency(N: int, maxnb: int = 16):
+    """Neighbour lists of the N-point lattice along its convex hull's edges."""
+    p = lattice(N)
+    nb = np.zeros((N, maxnb), np.int32)
+    nnb = np.zeros(N, np.int32)
+    dm = lib().or_hull_adjacency(N, _p(p), maxnb, _p(nb), _p(nnb))
+    if dm < 0:
+        raise ValueError("a lattice point has more hull neighbours than maxnb")
+    return [nb[i, :nnb[i]].tolist() for i in range(N)]
+
+
+def colours(u, dirs, N: int) -> np.ndarray:
+    """Colour of every lattice point for incoming direction u (None: no rotation) and
+    unit out-directions dirs [d][3]: nearest-point seeds, then flood fill (Sec. 3)."""
+    s = np.ascontiguousarray(dirs, np.float64)
+    uu = None if u is None else np.ascontiguousarray(u, np.float64)
+    col = np.zeros(N, np.int32)
+    if lib().or_colours(_p(uu), int(s.shape[0]), _p(s), N, 16, _p(col)) < 0:
+        raise ValueError("hull degree above 16")
+    return col

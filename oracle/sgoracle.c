@@ -329,6 +329,7 @@ typedef struct {
     const int *phase_kind; /* [n_phase] 0 Henyey-Greenstein, 1 Rayleigh, 2 table; NULL: all 0 */
     int lut_n;             /* samples per table row */
     const double *lut;     /* [n_phase][lut_n] tables in mu = cos(theta) on [-1, 1] */
+    int sigma_mode;        /* 0: Voronoi ownership of the lattice; 1: nearest-point colouring + flood fill */
 } or_scene;
 
 /*
@@ -571,6 +572,154 @@ static void node_q(int is_surface, const double *u, int d, const double *s, int 
 }
 
 /* Exported for the phase-cell pins. */
+/*
+ * The paper's own discretisation of Sigma (Sec. 3): each out-edge direction,
+ * rotated with the lattice, colours its closest lattice point, and the colours
+ * are spread over the rest of the lattice by flood fill along the edges of the
+ * lattice's convex hull.
+ *
+ * Hull edges: (i, j) is an edge when some k makes (i, j, k) a face, i.e. no lattice
+ * point lies strictly on each side of the plane through p_i, p_j, p_k:
+ *   d1 = p_j - p_i, d2 = p_k - p_i, n = d1 x d2 (components (d1y d2z - d1z d2y,
+ *   d1z d2x - d1x d2z, d1x d2y - d1y d2x)), s_l = (n_x e_x + n_y e_y) + n_z e_z with
+ *   e = p_l - p_i (no contraction); coplanar points do not count against a face,
+ *   so both diagonals of a coplanar quadrilateral are edges.  Below 4 points every
+ *   pair is an edge.  Lists ascending; returns the largest degree (-1 above maxnb).
+ */
+int or_hull_adjacency(int N, const double *p, int maxnb, int32_t *nb /* [N][maxnb] */, int32_t *nnb /* [N] */) {
+    unsigned char *adj = (unsigned char *)calloc((size_t)N * N, 1);
+    if (N < 4) {
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) adj[(size_t)i * N + j] = i != j;
+    } else {
+        for (int i = 0; i < N; ++i)
+            for (int j = i + 1; j < N; ++j)
+                for (int k = j + 1; k < N; ++k) {
+                    double d1[3], d2[3], n[3];
+                    for (int a = 0; a < 3; ++a) {
+                        d1[a] = p[3 * j + a] - p[3 * i + a];
+                        d2[a] = p[3 * k + a] - p[3 * i + a];
+                    }
+                    n[0] = d1[1] * d2[2] - d1[2] * d2[1];
+                    n[1] = d1[2] * d2[0] - d1[0] * d2[2];
+                    n[2] = d1[0] * d2[1] - d1[1] * d2[0];
+                    int pos = 0, neg = 0;
+                    for (int l = 0; l < N && !(pos && neg); ++l) {
+                        if (l == i || l == j || l == k) continue;
+                        const double e0 = p[3 * l] - p[3 * i], e1 = p[3 * l + 1] - p[3 * i + 1],
+                                     e2 = p[3 * l + 2] - p[3 * i + 2];
+                        const double sl = (n[0] * e0 + n[1] * e1) + n[2] * e2;
+                        if (sl > 0.0) pos = 1;
+                        else if (sl < 0.0) neg = 1;
+                    }
+                    if (pos && neg) continue;
+                    adj[(size_t)i * N + j] = adj[(size_t)j * N + i] = 1;
+                    adj[(size_t)i * N + k] = adj[(size_t)k * N + i] = 1;
+                    adj[(size_t)j * N + k] = adj[(size_t)k * N + j] = 1;
+                }
+    }
+    int dmax = 0;
+    for (int i = 0; i < N; ++i) {
+        int c = 0;
+        for (int j = 0; j < N; ++j)
+            if (adj[(size_t)i * N + j]) {
+                if (c < maxnb) nb[(size_t)i * maxnb + c] = j;
+                ++c;
+            }
+        nnb[i] = c < maxnb ? c : maxnb;
+        if (c > dmax) dmax = c;
+    }
+    free(adj);
+    return dmax <= maxnb ? dmax : -1;
+}
+
+/*
+ * Colours of one node and incoming direction: seeds, then flood fill.
+ *   seeds: for m = 0, 1, ...: the closest lattice point i*(m) = argmax_i v_im (the
+ *   same v_im = q_i . s_m as the Voronoi ownership; ties to the lowest i) takes
+ *   colour m, unless an earlier direction claimed it with a value >= v (a point
+ *   claimed twice goes to the closer direction, ties to the lower index; the other
+ *   direction then owns no lattice point);
+ *   fill: in synchronous rounds, every uncoloured point takes the colour of its
+ *   coloured neighbour of lowest index (colours of the previous round), until every
+ *   point is coloured.
+ * The paper gives no rule for conflicts or for several coloured neighbours; these
+ * are the readings taken.
+ */
+static void colour_points(const double *u, int d, const double *s, int N, const double *p, const int32_t *nb,
+                          const int32_t *nnb, int maxnb, int32_t *col) {
+    double R[9];
+    if (u) or_rotation(u, R);
+    double *q = (double *)malloc(sizeof(double) * 3 * N), *cv = (double *)malloc(sizeof(double) * N);
+    int32_t *snap = (int32_t *)malloc(sizeof(int32_t) * N);
+    for (int i = 0; i < N; ++i) {
+        if (u) rot_apply_t(R, p + 3 * i, q + 3 * i);
+        else memcpy(q + 3 * i, p + 3 * i, sizeof(double) * 3);
+        col[i] = -1;
+        cv[i] = 0.0;
+    }
+    for (int m = 0; m < d; ++m) {
+        int bi = 0;
+        double bv = dot3(q, s + 3 * m);
+        for (int i = 1; i < N; ++i) {
+            const double v = dot3(q + 3 * i, s + 3 * m);
+            if (v > bv) {
+                bv = v;
+                bi = i;
+            }
+        }
+        if (col[bi] < 0 || bv > cv[bi]) {
+            col[bi] = m;
+            cv[bi] = bv;
+        }
+    }
+    for (int round = 0; round < N; ++round) {
+        int missing = 0;
+        memcpy(snap, col, sizeof(int32_t) * N);
+        for (int i = 0; i < N; ++i) {
+            if (snap[i] >= 0) continue;
+            for (int t = 0; t < nnb[i]; ++t) {
+                const int j = nb[(size_t)i * maxnb + t];
+                if (snap[j] >= 0) {
+                    col[i] = snap[j];
+                    break;
+                }
+            }
+            missing += col[i] < 0;
+        }
+        if (!missing) break;
+    }
+    free(q);
+    free(cv);
+    free(snap);
+}
+
+static void colour_q(int is_surface, const double *u, int d, const double *s, int N, const double *lat,
+                     const int32_t *nb, const int32_t *nnb, int maxnb, const double *w, double *Q, int32_t *col) {
+    colour_points(is_surface ? NULL : u, d, s, N, lat, nb, nnb, maxnb, col);
+    for (int m = 0; m < d; ++m) Q[m] = 0.0;
+    double tot = 0.0;
+    if (is_surface)
+        for (int i = 0; i < N; ++i) tot += fmax(0.0, lat[3 * i + 2]);
+    for (int i = 0; i < N; ++i) {
+        if (col[i] < 0) continue;
+        Q[col[i]] += is_surface ? fmax(0.0, lat[3 * i + 2]) / tot : w[i];
+    }
+}
+
+/* Colours of one incoming direction, for the pins (u == NULL: no rotation). */
+int or_colours(const double *u, int d, const double *s, int N, int maxnb, int32_t *col) {
+    double *lat = (double *)malloc(sizeof(double) * 3 * N);
+    int32_t *nb = (int32_t *)malloc(sizeof(int32_t) * (size_t)N * maxnb), *nnb = (int32_t *)malloc(sizeof(int32_t) * N);
+    or_lattice(N, lat);
+    const int dm = or_hull_adjacency(N, lat, maxnb, nb, nnb);
+    if (dm >= 0) colour_points(u, d, s, N, lat, nb, nnb, maxnb, col);
+    free(lat);
+    free(nb);
+    free(nnb);
+    return dm;
+}
+
 void or_node_q(int is_surface, const double *u, int d, const double *s, int N, const double *w, double *Q) {
     double *lat = (double *)malloc(sizeof(double) * 3 * N);
     int32_t *own = (int32_t *)malloc(sizeof(int32_t) * N);
@@ -649,6 +798,17 @@ int or_run(const or_scene *sc, or_out *out) {
         }
         for (int i = 0; i < NF; ++i) t[i] = t[i] / s;
     }
+    /* hull adjacency of the lattice, for the colouring of Sigma */
+    enum { MAXNB = 16 };
+    int32_t *hnb = NULL, *hnnb = NULL;
+    if (sc->sigma_mode == 1) {
+        hnb = (int32_t *)malloc(sizeof(int32_t) * NF * MAXNB);
+        hnnb = (int32_t *)malloc(sizeof(int32_t) * NF);
+        if (or_hull_adjacency(NF, lat, MAXNB, hnb, hnnb) < 0) {
+            free(hnb); free(hnnb); free(lat); free(tab);
+            return 7;
+        }
+    }
 
     double sun_u[3], sun_in[3];
     unit_of(sc->sun_dir, sun_u);
@@ -702,7 +862,8 @@ int or_run(const or_scene *sc, or_out *out) {
             /* columns: in-edges a_m = rev[m] (ascending, since heads are ascending) */
             for (int m = 0; m < d; ++m) {
                 double u[3] = {-s[3 * m], -s[3 * m + 1], -s[3 * m + 2]}; /* propagation of (j -> l) */
-                node_q(is_surf, u, d, s, NF, lat, w, Q, own);
+                if (sc->sigma_mode == 1) colour_q(is_surf, u, d, s, NF, lat, hnb, hnnb, MAXNB, w, Q, own);
+                else node_q(is_surf, u, d, s, NF, lat, w, Q, own);
                 double Ta = exp(-out->tau[off + m]); /* same pair as rev[m] */
                 for (int n = 0; n < d; ++n) {
                     int64_t b = off + n;
@@ -712,7 +873,8 @@ int or_run(const or_scene *sc, or_out *out) {
                 }
             }
             /* source (Eq. 9): sunlight arriving at l along sun_in */
-            node_q(is_surf, sun_in, d, s, NF, lat, w, Q, own);
+            if (sc->sigma_mode == 1) colour_q(is_surf, sun_in, d, s, NF, lat, hnb, hnnb, MAXNB, w, Q, own);
+            else node_q(is_surf, sun_in, d, s, NF, lat, w, Q, own);
             double Ts = exp(-out->tau_sun[l]);
             for (int n = 0; n < d; ++n) {
                 if (is_surf) out->S[off + n] = out->rho[l] * mu0 * Ts * Q[n];
@@ -799,7 +961,7 @@ int or_run(const or_scene *sc, or_out *out) {
         free(vox);
         free(dtv);
     }
-    free(lat); free(tab); free(mu_e); free(omega);
+    free(lat); free(tab); free(mu_e); free(omega); free(hnb); free(hnnb);
     return 0;
 }
 

@@ -61,6 +61,7 @@ class Scene:
     angles: tuple = (0.0, 0.0, 0.0, 0.0)    # (sza, saa, vza, vaa) in degrees, informational
     phase_kind: Optional[np.ndarray] = None  # int32 [n_phase]: 0 Henyey-Greenstein, 1 Rayleigh, 2 table
     phase_lut: Optional[np.ndarray] = None   # float64 [n_phase, n] tables in cos(theta) on [-1, 1]
+    sigma_mode: int = 0         # 0 = Voronoi ownership of the lattice, 1 = nearest-point colouring + flood fill
 
     # ---- derived sizes (no method arithmetic) ----
     @property
@@ -118,7 +119,7 @@ class Scene:
             if a is not None:
                 h.update(np.ascontiguousarray(a).tobytes())
         h.update(repr((self.nx, self.ny, self.nz, self.voxel_m, self.surface_nodes, self.n_fib,
-                       self.node_weight_mode)).encode())
+                       self.node_weight_mode, self.sigma_mode)).encode())
         return h.hexdigest()[:16]
 
     def with_(self, **kw) -> "Scene":
