@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define SG_ABI_VERSION 3u
+#define SG_ABI_VERSION 4u
 
 typedef int32_t sg_status;
 enum {
@@ -125,7 +125,16 @@ typedef struct sg_scene_desc {
                                   table row; linear in cos(theta) between samples, scaled by the
                                   exact integral of that interpolant (rows of other kinds are
                                   not read) */
+    int32_t sigma_mode;        /* the cells Sigma of Eq. 7 on the lattice: SG_SIGMA_VORONOI (0)
+                                  each lattice point to the out-direction of largest dot
+                                  product; SG_SIGMA_COLOUR (1) the paper's procedure (Sec. 3):
+                                  each out-direction colours its closest lattice point (a point
+                                  claimed twice goes to the closer direction, ties to the lower
+                                  index) and the colours spread by flood fill along the edges
+                                  of the lattice's convex hull, in rounds, an uncoloured point
+                                  taking the colour of its lowest-index coloured neighbour */
 } sg_scene_desc;
+enum { SG_SIGMA_VORONOI = 0, SG_SIGMA_COLOUR = 1 };
 enum { SG_PHASE_HG = 0, SG_PHASE_RAYLEIGH = 1, SG_PHASE_TABLE = 2 };
 
 /*

@@ -93,6 +93,50 @@ void host_lattice(int N, std::vector<double> &p) {
 
 // Per-component Henyey-Greenstein table normalised over the lattice, then the
 // Lambertian cosine weights max(0, z_i) / sum_j max(0, z_j).
+// Neighbour lists of the lattice along the edges of its convex hull (the adjacency the
+// flood fill of the colouring mode walks): (i, j) is an edge when some k makes (i, j, k)
+// a face, i.e. no lattice point lies strictly on both sides of the plane through the
+// three (coplanar points do not count against it), tested as s_l = (n_x e_x + n_y e_y)
+// + n_z e_z with n = (p_j - p_i) x (p_k - p_i), e = p_l - p_i; below 4 points every pair.
+// nb [N][kHullNb] ascending and nnb [N]; false when a point has more neighbours.
+bool host_hull(int N, const std::vector<double> &p, std::vector<int> &nb, std::vector<int> &nnb) {
+    std::vector<unsigned char> adj((size_t)N * N, 0);
+    if (N < 4) {
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) adj[(size_t)i * N + j] = i != j;
+    } else {
+        for (int i = 0; i < N; ++i)
+            for (int j = i + 1; j < N; ++j)
+                for (int k = j + 1; k < N; ++k) {
+                    const double ax = p[3 * j] - p[3 * i], ay = p[3 * j + 1] - p[3 * i + 1], az = p[3 * j + 2] - p[3 * i + 2];
+                    const double bx = p[3 * k] - p[3 * i], by = p[3 * k + 1] - p[3 * i + 1], bz = p[3 * k + 2] - p[3 * i + 2];
+                    const double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+                    bool above = false, below = false;
+                    for (int l = 0; l < N && !(above && below); ++l) {
+                        if (l == i || l == j || l == k) continue;
+                        const double sl = (nx * (p[3 * l] - p[3 * i]) + ny * (p[3 * l + 1] - p[3 * i + 1])) +
+                                          nz * (p[3 * l + 2] - p[3 * i + 2]);
+                        above = above || sl > 0.0;
+                        below = below || sl < 0.0;
+                    }
+                    if (above && below) continue;
+                    for (auto e : {std::make_pair(i, j), std::make_pair(i, k), std::make_pair(j, k)}) {
+                        adj[(size_t)e.first * N + e.second] = 1;
+                        adj[(size_t)e.second * N + e.first] = 1;
+                    }
+                }
+    }
+    nb.assign((size_t)N * kHullNb, 0);
+    nnb.assign(N, 0);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            if (adj[(size_t)i * N + j]) {
+                if (nnb[i] == kHullNb) return false;
+                nb[(size_t)i * kHullNb + nnb[i]++] = j;
+            }
+    return true;
+}
+
 // A phase table row at cos(theta) = mu: linear between the samples at -1 + 2 m / (n - 1)
 // (unscaled).
 double table_value(const double *row, int n, double mu) {
@@ -181,6 +225,8 @@ sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz,
         }
     }
     if (d->n_fib < 1 || d->n_fib > 128) return fail(SG_E_INVALID, "n_fib must be 1..128");
+    if (d->sigma_mode != SG_SIGMA_VORONOI && d->sigma_mode != SG_SIGMA_COLOUR)
+        return fail(SG_E_INVALID, "sigma_mode must be SG_SIGMA_VORONOI or SG_SIGMA_COLOUR");
     if (d->node_weight_mode != 0 && d->node_weight_mode != 1) return fail(SG_E_INVALID, "node_weight_mode must be 0 or 1");
     if (d->n_lambda < 1 || d->n_lambda > 256) return fail(SG_E_INVALID, "n_lambda must be 1..256");
     if (d->n_lambda > 1 && !d->abs_scale) return fail(SG_E_INVALID, "abs_scale required when n_lambda > 1");
@@ -909,7 +955,7 @@ namespace {
 void free_scene_impl(Scene *s) {
     clear_graphs(*s);
     void *ptrs[] = {s->mu_s, s->mu_a, s->frac, s->albedo, s->abs_scale_d, s->pos, s->adj_ptr, s->adj_idx, s->lat,
-                    s->tab, s->lut, s->rev, s->nodeoff, s->row_ptr, s->col_idx, s->scan_tmp, s->tau_s, s->tau_a, s->tsun_s,
+                    s->tab, s->lut, s->hull, s->rev, s->nodeoff, s->row_ptr, s->col_idx, s->scan_tmp, s->tau_s, s->tau_a, s->tsun_s,
                     s->tsun_a, s->T, s->Tsun, s->rho, s->val, s->S, s->x, s->y, s->c_rhs, s->c_a, s->c_b, s->qsun,
                     s->q, s->bS, s->bx, s->by, s->brho, s->bsrc, s->lam_buf, s->x64, s->r64, s->gm_V, s->partial, s->meas, s->meas_part, s->scal, s->J, s->pix};
     if (s->ctx)
@@ -952,6 +998,7 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
         }
     }
     s.n_fib = d->n_fib;
+    s.sigma_mode = d->sigma_mode;
     s.surface = d->surface_nodes ? 1 : 0;
     s.weight_mode = d->node_weight_mode;
     s.n_lambda = d->n_lambda;
@@ -976,6 +1023,7 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     SG_TRY(dalloc(s, &s.lat, (size_t)3 * s.n_fib));
     SG_TRY(dalloc(s, &s.tab, (size_t)(s.n_phase + 1) * s.n_fib));
     if (s.lut_n) SG_TRY(dalloc(s, &s.lut, (size_t)s.n_phase * s.lut_n));
+    if (s.sigma_mode == SG_SIGMA_COLOUR) SG_TRY(dalloc(s, &s.hull, (size_t)s.n_fib * (kHullNb + 1)));
     // structure
     SG_TRY(dalloc(s, &s.rev, (size_t)s.E));
     SG_TRY(dalloc(s, &s.nodeoff, (size_t)s.N + 1));
@@ -1028,6 +1076,26 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     host_lattice(s.n_fib, lat);
     host_tables(s.n_fib, lat, s.n_phase, s.phase_kind, s.hg_g, d->phase_lut, s.lut_n, tab);
     if (s.lut) SG_TRY(upload(s, s.lut, d->phase_lut, sizeof(double) * s.n_phase * (size_t)s.lut_n, st));
+    std::vector<int> hull;  // [n_fib][kHullNb] neighbours, then [n_fib] counts
+    if (s.hull) {
+        static std::mutex mu;
+        static std::map<int, std::vector<int>> cache;  // per lattice size (the lattice is fixed by it)
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = cache.find(s.n_fib);
+            if (it != cache.end()) hull = it->second;
+        }
+        if (hull.empty()) {
+            std::vector<int> nb, nnb;
+            if (!host_hull(s.n_fib, lat, nb, nnb))
+                return fail(SG_E_INVALID, "a lattice point has more than 16 hull neighbours");
+            hull = nb;
+            hull.insert(hull.end(), nnb.begin(), nnb.end());
+            std::lock_guard<std::mutex> lk(mu);
+            cache[s.n_fib] = hull;
+        }
+        SG_TRY(upload(s, s.hull, hull.data(), sizeof(int) * hull.size(), st));
+    }
     SG_TRY(upload(s, s.mu_s, d->mu_s, sizeof(float) * s.nvox, st));
     SG_TRY(upload(s, s.mu_a, d->mu_a, sizeof(float) * s.nvox, st));
     if (s.frac) SG_TRY(upload(s, s.frac, d->phase_frac, sizeof(float) * s.n_phase * (size_t)s.nvox, st));
@@ -1147,7 +1215,8 @@ uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st) {
     bool table = false;
     for (int k = 0; k < d->n_phase; ++k) table = table || (d->phase_kind && d->phase_kind[k] == SG_PHASE_TABLE);
     uint64_t b = a(nvox, 4) * 2 + (np > 1 ? a(np * nvox, 4) : 0) + a(npx, 4) + a(3 * n, 4) + a(n + 1, 8) +
-                 a(e, 4) + a(3 * nf, 8) + a((np + 1) * nf, 8) + (table ? a(np * (uint64_t)d->phase_lut_n, 8) : 0);
+                 a(e, 4) + a(3 * nf, 8) + a((np + 1) * nf, 8) + (table ? a(np * (uint64_t)d->phase_lut_n, 8) : 0) +
+                 (d->sigma_mode == SG_SIGMA_COLOUR ? a(nf * (kHullNb + 1), 4) : 0);
     b += a(e, 4) + a(n + 1, 8) + a(e + 1, 8) + a(n / 2048 + 2, 8) + a(e, 4);
     b += a(e * nl, 8) * 2 + a(std::max<uint64_t>((n + 3) / 4, 65 * 1024), 8) +
          a(n * nl, 8) + a((uint64_t)node_chunks((int)n, (int)nl) * nl * 2, 8) + a(256, 8) +

@@ -19,6 +19,8 @@
 
 namespace sg {
 
+constexpr int kHullNb = 16;  // neighbour slots per lattice point (hull adjacency)
+
 void set_error(const std::string &msg);
 std::string t_last_error();
 
@@ -71,6 +73,8 @@ struct Scene {
     int lut_n = 0;                     // samples per phase table row (0: no table)
     double lut_scale[4] = {1, 1, 1, 1};  // 1 / integral over the sphere of each table row
     double *lut = nullptr;             // [n_phase][lut_n] phase tables (device)
+    int sigma_mode = 0;                // SG_SIGMA_VORONOI or SG_SIGMA_COLOUR
+    int *hull = nullptr;               // colouring: [n_fib][kHullNb] hull neighbours, then [n_fib] counts
     int n_fib = 100;
     int surface = 1;
     int weight_mode = 0;

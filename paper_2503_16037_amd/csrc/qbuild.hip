@@ -205,12 +205,193 @@ __global__ __launch_bounds__(64) void k_qbuild(
 // directions per group: as many as fill the lanes' pair slots
 int qbuild_group(int NF) { return std::max(1, std::min(kQMaxGroup, kQSlots * 64 / NF)); }
 
+// The paper's discretisation of Sigma (Sec. 3), for scenes that ask for it: per
+// incoming direction, every out-edge direction colours its closest lattice point and
+// the colours spread over the lattice by flood fill along the edges of its convex
+// hull.  One 64-lane wavefront per node, lattice points i and i + 64 in lane i.
+//   seeds: for m = 0, 1, ...: the lattice point of largest v_im (the Voronoi
+//   ownership's dot products, same operation sequence; ties to the lowest i) takes
+//   colour m unless it was claimed with a value >= v_im by an earlier direction;
+//   fill: in rounds, every uncoloured point takes the colour its lowest-index
+//   coloured neighbour had at the start of the round, until all are coloured (the
+//   hull graph is connected and there is at least one seed).
+// Q(u -> m) is the fixed-point sum of the phase weights of colour m, as in k_qbuild.
+template <class Real, class BlkT, bool kWriteQ>
+__global__ __launch_bounds__(64) void k_qcolour(
+    int N, int nvox, const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx,
+    const int *__restrict__ pos, const double *__restrict__ lat, const double *__restrict__ tab, int NF, int n_phase,
+    const float *__restrict__ frac, double sun_x, double sun_y, double sun_z, Real mu0, const Real *__restrict__ T,
+    const Real *__restrict__ rho, const Real *__restrict__ Tsun, const long long *__restrict__ nodeoff,
+    BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun, const int *__restrict__ hull) {
+#pragma clang fp contract(off)
+    __shared__ double sx[64], sy[64], sz[64], lt[3][128];
+    __shared__ unsigned long long wq[128], bins[64];
+    __shared__ int nbr[128][kHullNb], nnb[128], col[128], snap[128];
+
+    const int l = blockIdx.x;
+    const int lane = threadIdx.x;
+    const long long off = adj_ptr[l];
+    const int d = (int)(adj_ptr[l + 1] - off);
+    if (d == 0) return;
+    const bool surf = l >= nvox;
+    if (lane < d) {
+        const int j = adj_idx[off + lane];
+        const long long Dx = (long long)pos[3 * j] - pos[3 * l];
+        const long long Dy = (long long)pos[3 * j + 1] - pos[3 * l + 1];
+        const long long Dz = (long long)pos[3 * j + 2] - pos[3 * l + 2];
+        const double nrm = sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
+        sx[lane] = (double)Dx / nrm;
+        sy[lane] = (double)Dy / nrm;
+        sz[lane] = (double)Dz / nrm;
+    }
+    for (int i = lane; i < NF; i += 64) {
+        lt[0][i] = lat[3 * i];
+        lt[1][i] = lat[3 * i + 1];
+        lt[2][i] = lat[3 * i + 2];
+        double w;
+        if (surf) {
+            w = tab[n_phase * NF + i];
+        } else {
+            w = 0.0;
+            for (int k = 0; k < n_phase; ++k) {
+                const double f = frac ? (double)frac[(long long)k * nvox + l] : 1.0;
+                w = w + f * tab[k * NF + i];
+            }
+        }
+        wq[i] = (unsigned long long)llrint(w * kFix);
+        nnb[i] = hull[NF * kHullNb + i];
+        for (int t = 0; t < kHullNb; ++t) nbr[i][t] = hull[i * kHullNb + t];
+    }
+    __syncthreads();
+
+    const Real rl = rho ? rho[l] : (Real)0;
+    const Real tsun = Tsun ? Tsun[l] : (Real)0;
+    BlkT *blk = val + nodeoff[l];  // column-major: element (row n, column m) at m d + n
+    const int n_in = surf ? 1 : d + 1;
+    const int i0 = lane, i1 = lane + 64;
+    const bool ok0 = i0 < NF, ok1 = i1 < NF;
+    for (int a = 0; a < n_in; ++a) {
+        // rotation of this incoming direction (every lane, the same values)
+        double R[9];
+        if (surf) {
+            R[0] = 1.0; R[1] = 0.0; R[2] = 0.0; R[3] = 0.0; R[4] = 1.0; R[5] = 0.0; R[6] = 0.0; R[7] = 0.0; R[8] = 1.0;
+        } else {
+            double ux, uy, uz;
+            if (a < d) { ux = -sx[a]; uy = -sy[a]; uz = -sz[a]; }
+            else { ux = sun_x; uy = sun_y; uz = sun_z; }
+            if (1.0 + uz < 1e-12) {
+                R[0] = 1.0; R[1] = 0.0; R[2] = 0.0; R[3] = 0.0; R[4] = -1.0; R[5] = 0.0; R[6] = 0.0; R[7] = 0.0;
+                R[8] = -1.0;
+            } else {
+                const double h = 1.0 / (1.0 + uz);
+                const double xy = (ux * uy) * h;
+                R[0] = uz + (uy * uy) * h; R[1] = -xy; R[2] = -ux;
+                R[3] = -xy; R[4] = uz + (ux * ux) * h; R[5] = -uy;
+                R[6] = ux; R[7] = uy; R[8] = uz;
+            }
+        }
+        double q[2][3];
+        for (int h2 = 0; h2 < 2; ++h2) {
+            const int i = min(h2 ? i1 : i0, NF - 1);
+            const double x = lt[0][i], y = lt[1][i], z = lt[2][i];
+            q[h2][0] = fma(R[6], z, fma(R[3], y, R[0] * x));
+            q[h2][1] = fma(R[7], z, fma(R[4], y, R[1] * x));
+            q[h2][2] = fma(R[8], z, fma(R[5], y, R[2] * x));
+        }
+        // seeds
+        int c0 = -1, c1 = -1;
+        double cv0 = 0.0, cv1 = 0.0;
+        for (int m = 0; m < d; ++m) {
+            const double tx = sx[m], ty = sy[m], tz = sz[m];
+            const double v0 = ok0 ? fma(q[0][2], tz, fma(q[0][1], ty, q[0][0] * tx)) : -__builtin_inf();
+            const double v1 = ok1 ? fma(q[1][2], tz, fma(q[1][1], ty, q[1][0] * tx)) : -__builtin_inf();
+            double bv = v1 > v0 ? v1 : v0;
+            int bi = v1 > v0 ? i1 : i0;
+            // wavefront argmax, ties to the lower index: every lane ends with the same pair
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(bv, o, 64);
+                const int oi = __shfl_xor(bi, o, 64);
+                const bool take = ov > bv || (ov == bv && oi < bi);
+                bv = take ? ov : bv;
+                bi = take ? oi : bi;
+            }
+            if (bi == i0 && (c0 < 0 || bv > cv0)) { c0 = m; cv0 = bv; }
+            if (bi == i1 && (c1 < 0 || bv > cv1)) { c1 = m; cv1 = bv; }
+        }
+        if (ok0) col[i0] = c0;
+        if (ok1) col[i1] = c1;
+        __syncthreads();
+        // flood fill in rounds
+        for (int round = 0; round < NF; ++round) {
+            if (ok0) snap[i0] = col[i0];
+            if (ok1) snap[i1] = col[i1];
+            __syncthreads();
+            bool missing = false;
+            for (int h2 = 0; h2 < 2; ++h2) {
+                const int i = h2 ? i1 : i0;
+                if (i >= NF || snap[i] >= 0) continue;
+                for (int t = 0; t < nnb[i]; ++t) {
+                    const int c = snap[nbr[i][t]];
+                    if (c >= 0) {
+                        col[i] = c;
+                        break;
+                    }
+                }
+                missing = missing || col[i] < 0;
+            }
+            const bool any = __ballot(missing) != 0ull;
+            __syncthreads();
+            if (!any) break;
+        }
+        // cells: fixed-point sums per colour, then this direction's column
+        if (lane < d) bins[lane] = 0ull;
+        __syncthreads();
+        if (ok0 && col[i0] >= 0) atomicAdd(&bins[col[i0]], wq[i0]);
+        if (ok1 && col[i1] >= 0) atomicAdd(&bins[col[i1]], wq[i1]);
+        __syncthreads();
+        if (lane < d) {
+            const int m = lane;
+            const double Q = (double)(long long)bins[m] * kUnfix;
+            const long long b = off + m;
+            if (surf) {
+                for (int c = 0; c < d; ++c) {
+                    if (kWriteQ) blk[c * d + m] = (BlkT)Q;
+                    else blk[c * d + m] = (BlkT)(T[off + c] * rl * (Real)Q);
+                }
+                if (!kWriteQ) S[b] = rl * mu0 * tsun * (Real)Q;
+                qsun[b] = (float)Q;
+            } else if (a < d) {
+                if (kWriteQ) blk[a * d + m] = (BlkT)Q;
+                else blk[a * d + m] = (BlkT)(T[off + a] * rl * (Real)Q);
+            } else {
+                if (!kWriteQ) S[b] = tsun * rl * (Real)Q;
+                qsun[b] = (float)Q;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 template <class Real>
 void launch_qbuild(Scene &s, hipStream_t st, int write_q) {
     const size_t shm = 0;
     const int group = qbuild_group(s.n_fib);
+    if (s.sigma_mode == SG_SIGMA_COLOUR) {
+        if (write_q) {
+            hipLaunchKernelGGL((k_qcolour<Real, float, true>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
+                               s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
+                               s.sun_in[2], (Real)s.mu0, (const Real *)nullptr, (const Real *)nullptr,
+                               (const Real *)nullptr, s.nodeoff, s.q, (Real *)nullptr, s.qsun, s.hull);
+        } else {
+            hipLaunchKernelGGL((k_qcolour<Real, Real, false>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
+                               s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
+                               s.sun_in[2], (Real)s.mu0, (const Real *)s.T, (const Real *)s.rho,
+                               (const Real *)s.Tsun, s.nodeoff, (Real *)s.val, (Real *)s.S, s.qsun, s.hull);
+        }
+        return;
+    }
     if (write_q) {
         hipLaunchKernelGGL((k_qbuild<Real, float, true>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
                            s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
