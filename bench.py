@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--served", type=int, default=40, help="requests of the served stream (workload served)")
     ap.add_argument("--resident", type=int, default=4, help="resident scenes of the server (workload served)")
+    ap.add_argument("--sigma", default="voronoi", choices=["voronoi", "colour"],
+                    help="phase cells: Voronoi ownership (default) or the paper's colouring with flood fill")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
@@ -297,6 +299,9 @@ def main():
     from paper_2503_16037_amd import sgrt
 
     scene, wl_name = make_workload(args.workload)
+    if args.sigma == "colour":
+        scene = scene.with_(sigma_mode=1)
+        wl_name += ", phase cells by nearest-point colouring and flood fill"
     ctx = sgrt.Context(0)
     torch.cuda.synchronize()
     t_up = time.perf_counter()
@@ -335,7 +340,8 @@ def main():
     qops = qbuild_ops(scene)
     if stages["ms_qbuild"] >= spmv_per_step_ms and g.n_lambda == 1:
         achieved = qops / (stages["ms_qbuild"] * 1e-3) / 1e12
-        roof = {"kernel": "k_qbuild (phase cells + K values + source)", "bound": "alu",
+        roof = {"kernel": ("k_qcolour" if args.sigma == "colour" else "k_qbuild") + " (phase cells + K values + source)",
+                "bound": "alu",
                 "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "T FP64 lane-op/s",
                 "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": measured_traffic("k_qbuild", args.workload),
                 "algorithmic_per_launch": qops, "avg_launch_ms": round(stages["ms_qbuild"], 4)}
