@@ -189,11 +189,14 @@ __device__ __forceinline__ unsigned long long box_cells(const Box &b) {
 __global__ void k_graph_cells(Geo g, const long long *__restrict__ P, const double *__restrict__ mu, double t,
                               unsigned long long *__restrict__ total) {
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    __shared__ unsigned long long wsum[4];
     unsigned long long v = 0;
     if (i < g.N) v = box_cells(node_box(g, P, mu, i, t));
-    // wavefront sum, then one atomic per wavefront
+    // wavefront sums, then one atomic per workgroup
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0) atomicAdd(total, v);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(total, wsum[0] + wsum[1] + wsum[2] + wsum[3]);
 }
 
 // Boxes of nodes n0 + r (r < n) at threshold t, stored as (lo x, lo y, lo z, extent
@@ -236,7 +239,7 @@ __device__ __forceinline__ long long owner(const unsigned long long *__restrict_
 // partner id), one thread per cell: the partner j > i is evaluated and the pairs
 // with k >= t (strict: k > t), k > 0 are counted per workgroup (kFill = false:
 // bcount) or written in cell order at the workgroup's offset (kFill = true), so the
-// list stays ordered by (i, j).  evals: the evaluated pairs (count pass).
+// list stays ordered by (i, j).  bev: the evaluated pairs per workgroup (count pass).
 template <bool kFill>
 __global__ __launch_bounds__(256) void k_graph_eval(Geo g, const double *__restrict__ q,
                                                     const double *__restrict__ mu, double t, int strict, long long n0,
@@ -245,9 +248,10 @@ __global__ __launch_bounds__(256) void k_graph_eval(Geo g, const double *__restr
                                                     unsigned long long *__restrict__ bcount,
                                                     const unsigned long long *__restrict__ boff,
                                                     double *__restrict__ keys, unsigned long long *__restrict__ codes,
-                                                    unsigned long long *__restrict__ evals) {
+                                                    unsigned long long *__restrict__ bev) {
     constexpr int kCells = kEvalRounds * 256;
     __shared__ unsigned int wcnt[4];
+    __shared__ unsigned long long wev[4];
     __shared__ long long range[2];
     __shared__ unsigned long long scoff[kCells];  // box starts of the workgroup's nodes, when they fit
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -324,22 +328,24 @@ __global__ __launch_bounds__(256) void k_graph_eval(Geo g, const double *__restr
         __syncthreads();  // wcnt is rewritten by the next round
     }
     if (!kFill) {
-        if (threadIdx.x == 0) bcount[blockIdx.x] = run;
-        if (lane == 0 && ev) atomicAdd(evals, ev);
+        if (lane == 0) wev[w] = ev;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            bcount[blockIdx.x] = run;
+            bev[blockIdx.x] = wev[0] + wev[1] + wev[2] + wev[3];
+        }
     }
 }
 
-// directed pair codes (tail N + head) of the selected pairs, and the degree of every tail
+// directed pair codes (tail N + head) of the selected pairs, both directions
 __global__ void k_graph_directed(long long n, long long N, const unsigned long long *__restrict__ pair,
-                                 unsigned long long *__restrict__ dir, int *__restrict__ deg) {
+                                 unsigned long long *__restrict__ dir) {
     const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (s >= n) return;
     const unsigned long long c = pair[s];
     const unsigned long long i = c / (unsigned long long)N, j = c % (unsigned long long)N;
     dir[2 * s] = i * (unsigned long long)N + j;
     dir[2 * s + 1] = j * (unsigned long long)N + i;
-    atomicAdd(&deg[i], 1);
-    atomicAdd(&deg[j], 1);
 }
 
 __global__ void k_graph_heads(long long E, long long N, const unsigned long long *__restrict__ dir,
@@ -348,16 +354,19 @@ __global__ void k_graph_heads(long long E, long long N, const unsigned long long
     if (e < E) head[e] = (int)(dir[e] % (unsigned long long)N);
 }
 
-__global__ void k_graph_ptr(long long N, const int *__restrict__ deg, const long long *__restrict__ excl,
-                            long long *__restrict__ ptr) {
+// row pointers from the sorted directed codes: ptr[l] = first e with dir[e] >= l N
+__global__ void k_graph_rowptr(long long N, long long E, const unsigned long long *__restrict__ dir,
+                               long long *__restrict__ ptr) {
     const long long l = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (l < N) ptr[l] = excl[l];
-    if (l == N - 1) ptr[N] = excl[l] + deg[l];
-}
-
-__global__ void k_graph_widen(long long n, const int *__restrict__ a, long long *__restrict__ b) {
-    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i < n) b[i] = a[i];
+    if (l > N) return;
+    const unsigned long long key = (unsigned long long)l * (unsigned long long)N;
+    long long a = 0, b = E;  // dir[0, a) < key <= dir[b, E)
+    while (a < b) {
+        const long long m = (a + b) >> 1;
+        if (dir[m] < key) a = m + 1;
+        else b = m;
+    }
+    ptr[l] = a;
 }
 
 unsigned blocks_for(long long n, int threads) { return (unsigned)std::max<long long>(1, (n + threads - 1) / threads); }
@@ -374,6 +383,7 @@ struct Builder {
     unsigned long long *scal = nullptr;  // [0] cell total, [1] evaluated pairs
     // build statistics: candidate passes, summed kernel times (HIP event pairs)
     int passes = 0;
+    unsigned long long evals = 0;  // pairs evaluated by the count passes
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs, ev_sort;
     Builder(Ctx *c, hipStream_t s) : ctx(c), st(s), dev(c) {}
     ~Builder() {
@@ -434,14 +444,16 @@ struct Builder {
         const unsigned long long per = (unsigned long long)kEvalRounds * 256;
         const unsigned long long nb = (T + per - 1) / per;
         if (nb >= (1ull << 31)) return gfail(SG_E_NOMEM, "coupling boxes too large");
-        unsigned long long *bcount = nullptr, *boff = nullptr;
+        unsigned long long *bcount = nullptr, *boff = nullptr, *bev = nullptr, *evsum = nullptr;
         GTRY(tmp.get(&bcount, nb + 1));
         GTRY(tmp.get(&boff, nb + 1));
+        GTRY(tmp.get(&bev, nb));
+        GTRY(tmp.get(&evsum, 1));
         GHIP(hipMemsetAsync(bcount + nb, 0, sizeof(unsigned long long), st));
         ++passes;
         auto *e0 = mark(ev_pairs);
         hipLaunchKernelGGL((k_graph_eval<false>), dim3((unsigned)nb), dim3(256), 0, st, g, q, mu, t, strict, n0, n,
-                           box, coff, T, bcount, nullptr, nullptr, nullptr, scal + 1);
+                           box, coff, T, bcount, nullptr, nullptr, nullptr, bev);
         if (e0) (void)hipEventRecord(e0->second, st);
         GHIP(hipGetLastError());
         // boff = have + exclusive sum of the workgroup counts; boff[nb] = the new total
@@ -452,9 +464,16 @@ struct Builder {
         GTRY(tmp.get(&tsp2, tb2));
         GHIP(hipcub::DeviceScan::ExclusiveScan(tsp2, tb2, bcount, boff, hipcub::Sum(), (unsigned long long)have,
                                                (int)nb + 1, st));
-        unsigned long long total = 0;
+        size_t tb3 = 0;
+        GHIP(hipcub::DeviceReduce::Sum(nullptr, tb3, bev, evsum, (int)nb, st));
+        unsigned char *tsp3 = nullptr;
+        GTRY(tmp.get(&tsp3, tb3));
+        GHIP(hipcub::DeviceReduce::Sum(tsp3, tb3, bev, evsum, (int)nb, st));
+        unsigned long long total = 0, ev = 0;
         GHIP(hipMemcpyAsync(&total, boff + nb, sizeof(total), hipMemcpyDeviceToHost, st));
+        GHIP(hipMemcpyAsync(&ev, evsum, sizeof(ev), hipMemcpyDeviceToHost, st));
         GHIP(hipStreamSynchronize(st));
+        evals += ev;
         if (total >= (1ull << 31)) return gfail(SG_E_NOMEM, "more than 2^31 coupling candidates");
         if (total > have) {
             double *nk = nullptr;
@@ -625,7 +644,7 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
             // every pair, streamed in node chunks through a running best-n list
             streamed = 1;
             t_used = 0.0;
-            GHIP(hipMemsetAsync(B.scal + 1, 0, sizeof(unsigned long long), st));
+            B.evals = 0;
             have = 0;
             const long long chunk = std::max<long long>(1, (long long)(budget / (unsigned long long)N));
             for (long long n0 = 0; n0 < N; n0 += chunk) {
@@ -644,19 +663,15 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
     if (E >= (1LL << 31) - 1) return gfail(SG_E_INVALID, "too many edges");
     Dev tmp(ctx);
     unsigned long long *dir = nullptr, *dir2 = nullptr;
-    int *deg = nullptr, *head = nullptr;
-    long long *deg64 = nullptr, *excl = nullptr, *ptr = nullptr;
+    int *head = nullptr;
+    long long *ptr = nullptr;
     GTRY(tmp.get(&dir, E));
     GTRY(tmp.get(&dir2, E));
-    GTRY(tmp.get(&deg, N));
     GTRY(tmp.get(&head, E));
-    GTRY(tmp.get(&deg64, N));
-    GTRY(tmp.get(&excl, N));
     GTRY(tmp.get(&ptr, N + 1));
-    GHIP(hipMemsetAsync(deg, 0, sizeof(int) * N, st));
     if (n_sel) {
         hipLaunchKernelGGL(k_graph_directed, dim3(blocks_for((long long)n_sel, 256)), dim3(256), 0, st,
-                           (long long)n_sel, N, codes, dir, deg);
+                           (long long)n_sel, N, codes, dir);
         GHIP(hipGetLastError());
         size_t tb = 0;
         GHIP(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, dir, dir2, (int)E, 0, 64, st));
@@ -668,26 +683,16 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
         hipLaunchKernelGGL(k_graph_heads, dim3(blocks_for(E, 256)), dim3(256), 0, st, E, N, dir2, head);
         GHIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_graph_widen, dim3(blocks_for(N, 256)), dim3(256), 0, st, N, deg, deg64);
-    GHIP(hipGetLastError());
-    {
-        size_t tb = 0;
-        GHIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, deg64, excl, (int)N, st));
-        unsigned char *tsp = nullptr;
-        GTRY(tmp.get(&tsp, tb));
-        GHIP(hipcub::DeviceScan::ExclusiveSum(tsp, tb, deg64, excl, (int)N, st));
-    }
-    hipLaunchKernelGGL(k_graph_ptr, dim3(blocks_for(N, 256)), dim3(256), 0, st, N, deg, excl, ptr);
+    hipLaunchKernelGGL(k_graph_rowptr, dim3(blocks_for(N + 1, 256)), dim3(256), 0, st, N, E,
+                       (const unsigned long long *)dir2, ptr);
     GHIP(hipGetLastError());
     if (adj_ptr) GHIP(hipMemcpyAsync(adj_ptr, ptr, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToHost, st));
     if (adj_idx && cap >= E && E > 0)
         GHIP(hipMemcpyAsync(adj_idx, head, sizeof(int32_t) * E, hipMemcpyDeviceToHost, st));
-    unsigned long long evals = 0;
-    GHIP(hipMemcpyAsync(&evals, B.scal + 1, sizeof(evals), hipMemcpyDeviceToHost, st));
     GHIP(hipStreamSynchronize(st));
     if (info) {
         info->candidates = (int64_t)ranked;
-        info->pairs_evaluated = (int64_t)evals;
+        info->pairs_evaluated = (int64_t)B.evals;
         info->threshold = t_used;
         info->streamed = streamed;
         info->passes = B.passes;
