@@ -391,7 +391,18 @@ def main():
                                    "cores": oracle.num_threads(), "kind": "oracle",
                                    "sample": f"one wavelength of {wl_name} ({sz['n_edges']} couplings), "
                                              f"FP64, all stages, {t_cpu:.2f} s"
-                                             + (f", x {g.n_lambda} wavelengths" if g.n_lambda > 1 else "")}
+                                             + (f", x {g.n_lambda} wavelengths" if g.n_lambda > 1 else ""),
+                                   "stages_s": {k: round(v, 4) for k, v in ref["stage_s"].items()}}
+            if args.workload in ("plain", "plume"):
+                # the same run on one thread
+                threads = oracle.num_threads()
+                oracle.set_threads(1)
+                t = time.perf_counter()
+                one = oracle.run(scene, want_matrix=False)
+                out["cpu_baseline"]["one_thread"] = {
+                    "s": round(time.perf_counter() - t, 3),
+                    "stages_s": {k: round(v, 4) for k, v in one["stage_s"].items()}}
+                oracle.set_threads(threads)
     g.close()
     ctx.close()
     print(json.dumps(out), flush=True)

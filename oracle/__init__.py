@@ -66,6 +66,8 @@ def lib():
             L.or_nnz.argtypes = [C.c_int64, P]
             L.or_run.restype = C.c_int
             L.or_run.argtypes = [P, P]
+            L.or_set_threads.restype = None
+            L.or_set_threads.argtypes = [C.c_int]
             L.or_num_threads.restype = C.c_int
             L.or_num_threads.argtypes = []
             L.or_phase_value.restype = C.c_double
@@ -93,6 +95,11 @@ def _p(a):
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the later calls (the pipeline's parallel loops)."""
+    lib().or_set_threads(int(n))
 
 
 # ------------------------------------------------------------------------------------------
@@ -246,7 +253,7 @@ def run(scene, abs_scale: float = 1.0, scatter_order: int = 0, tol: float = 1e-1
                 _p(kind), 0 if lut is None else int(lut.shape[-1]), _p(lut), int(getattr(scene, "sigma_mode", 0)))
     res = dict(tau=np.zeros(E), tau_sun=np.zeros(N), rho=np.zeros(N), row_ptr=np.zeros(E + 1, np.int64),
                col=np.zeros(nnz, np.int32), val=np.zeros(nnz), S=np.zeros(E), phi=np.zeros(E),
-               radiance=np.zeros(scene.nx * scene.ny), stats=np.zeros(4))
+               radiance=np.zeros(scene.nx * scene.ny), stats=np.zeros(8))
     out = _Out(*[_p(res[k]) for k in ("tau", "tau_sun", "rho", "row_ptr", "col", "val", "S", "phi",
                                        "radiance", "stats")])
     rc = lib().or_run(C.byref(sc), C.byref(out))
@@ -254,6 +261,7 @@ def run(scene, abs_scale: float = 1.0, scatter_order: int = 0, tol: float = 1e-1
         raise ValueError("oracle: invalid scene (code %d)" % rc)
     st = res.pop("stats")
     res["solve"] = dict(sweeps=int(st[0]), rel_residual=float(st[1]), gmres=bool(st[2]), gmres_iters=int(st[3]))
+    res["stage_s"] = dict(march=float(st[4]), matrix=float(st[5]), solve=float(st[6]), gather=float(st[7]))
     res["radiance"] = res["radiance"].reshape(scene.ny, scene.nx)
     res["nnz"] = nnz
     if not want_matrix:
