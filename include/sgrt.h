@@ -108,7 +108,8 @@ typedef struct sg_scene_desc {
     const float *surf_albedo;  /* [ny][nx] Lambertian albedo in [0, 1] */
     int32_t sun_dir[3];        /* integer vector toward the sun (z > 0), |components| <= 2^22 */
     int32_t view_dir[3];       /* integer vector toward the sensor (z > 0), |components| <= 2^22 */
-    int32_t n_fib;             /* Fibonacci lattice size, 1..128 (the paper uses 100) */
+    int32_t n_fib;             /* Fibonacci lattice size, 2..128 (the paper uses 100; one point
+                                  would lie on the horizon, leaving a surface node no cell) */
     int32_t node_weight_mode;  /* 0: rho = w (1 - exp(-mu_e * voxel_m)) (bounded scattering
                                   probability); 1: rho = mu_s * voxel_m (literal) */
     int32_t n_lambda;          /* wavelengths solved together, 1..256 */

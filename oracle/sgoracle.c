@@ -749,6 +749,9 @@ int or_run(const or_scene *sc, or_out *out) {
     const int64_t E = sc->adj_ptr[N];
     const double dx = sc->voxel_m;
     const int NF = sc->n_fib;
+    /* the Lambertian cells need a lattice point above the surface: with one point,
+       z_0 = 1 - 1/N = 0 lies on the horizon and the cosine weights are 0 / 0 */
+    if (NF < 2) return 8;
 
     /* wall time of the stages, for the benchmark's CPU baseline (stats[4..7]) */
     const double t_start = wall_s();

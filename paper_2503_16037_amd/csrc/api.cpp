@@ -224,7 +224,7 @@ sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz,
             if (!(table_integral(row, d->phase_lut_n) > 0.0)) return fail(SG_E_INVALID, "a phase_lut row is all zero");
         }
     }
-    if (d->n_fib < 1 || d->n_fib > 128) return fail(SG_E_INVALID, "n_fib must be 1..128");
+    if (d->n_fib < 2 || d->n_fib > 128) return fail(SG_E_INVALID, "n_fib must be 2..128");
     if (d->sigma_mode != SG_SIGMA_VORONOI && d->sigma_mode != SG_SIGMA_COLOUR)
         return fail(SG_E_INVALID, "sigma_mode must be SG_SIGMA_VORONOI or SG_SIGMA_COLOUR");
     if (d->node_weight_mode != 0 && d->node_weight_mode != 1) return fail(SG_E_INVALID, "node_weight_mode must be 0 or 1");
