@@ -194,6 +194,43 @@ def bench_served(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_nfib(args):
+    """Sensitivity to the lattice resolution (Sec. 3 integrates the phase function on a
+    Fibonacci lattice): a 48x48x24 cloud (g = 0.85, the most forward-peaked phase function
+    of the generators) solved with N_fib = 25..128 points, with the Voronoi cells and with
+    the paper's colouring; per-pixel differences against N_fib = 128 Voronoi, and the
+    phase-cell build time."""
+    import torch
+
+    from paper_2503_16037_amd import scenes, sgrt
+
+    base = scenes.make_cloud(nx=48, ny=48, nz=24, seed=3)
+    ctx = sgrt.Context(0)
+    res = {}
+    for mode, mname in ((0, "voronoi"), (1, "colour")):
+        for nf in (25, 50, 75, 100, 128):
+            sc = base.with_(n_fib=nf, sigma_mode=mode)
+            with sgrt.Scene(ctx, sc) as g:
+                g.solve()
+                rad, info = g.solve(timing=True)
+            torch.cuda.synchronize()
+            res[(mname, nf)] = (np.asarray(rad), info["ms_qbuild"], info["ms_total"])
+    ref = res[("voronoi", 128)][0]
+    table = []
+    for (mname, nf), (rad, ms_q, ms_t) in res.items():
+        d = np.abs(rad - ref) / np.abs(ref)
+        table.append({"cells": mname, "n_fib": nf, "mean_rel_diff": float(d.mean()), "p99_rel_diff": float(np.percentile(d, 99)),
+                      "max_rel_diff": float(d.max()), "ms_phase_cells": round(ms_q, 3), "ms_solve_total": round(ms_t, 3)})
+    ctx.close()
+    out = {"metric": "pixel radiance vs Fibonacci lattice size (n_fib sweep)", "value": table[-1]["mean_rel_diff"],
+           "unit": "mean relative difference of the 128-point colouring from the 128-point Voronoi cells",
+           "n_gpus": 1, "steps": len(table), "warmup": 1, "higher_is_better": False, "data": "synthetic",
+           "dtype": "f32", "vs_baseline": None, "scaling": "weak", "ms_per_step": None,
+           "config": {"workload": "cloud 48x48x24 (seed 3, g 0.85 in the clouds), n_fib 25..128, both cell definitions"},
+           "sweep": table}
+    print(json.dumps(out), flush=True)
+
+
 GRAPH_OPS_PER_PAIR = 10  # FP64 operations of one coupling: 3 subtractions, 4 products, 2 sums, 1 division
 
 
@@ -292,6 +329,9 @@ def main():
         return
     if args.workload == "graph":
         bench_graph(args)
+        return
+    if args.workload == "nfib":
+        bench_nfib(args)
         return
 
     import torch
