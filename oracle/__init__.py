@@ -48,6 +48,8 @@ def lib():
                 build(force=True)
             L = C.CDLL(_LIB)
             P = C.c_void_p
+            L.or_trace_p.restype = C.c_int
+            L.or_trace_p.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, C.c_int, P, P, C.c_int]
             L.or_trace.restype = C.c_int
             L.or_trace.argtypes = [C.c_int, C.c_int, C.c_int, P, P, C.c_int, P, P, C.c_int]
             L.or_lattice.restype = None
@@ -106,14 +108,15 @@ def set_threads(n: int) -> None:
 # stage functions (pins)
 # ------------------------------------------------------------------------------------------
 
-def trace(nx, ny, nz, P, D, is_ray, cap=None):
-    """Voxel ids and parameter lengths dt of the exact traversal of P + t D."""
+def trace(nx, ny, nz, P, D, is_ray, cap=None, periodic=0):
+    """Voxel ids and parameter lengths dt of the exact traversal of P + t D (periodic:
+    bit 0 x, bit 1 y repeat with the grid's period)."""
     P = np.ascontiguousarray(P, dtype=np.int64)
     D = np.ascontiguousarray(D, dtype=np.int64)
-    cap = cap or 4 * (nx + ny + nz) + 8
+    cap = cap or (65536 if periodic else 4 * (nx + ny + nz) + 8)
     vox = np.zeros(cap, np.int64)
     dt = np.zeros(cap, np.float64)
-    n = lib().or_trace(nx, ny, nz, _p(P), _p(D), int(is_ray), _p(vox), _p(dt), cap)
+    n = lib().or_trace_p(nx, ny, nz, int(periodic), _p(P), _p(D), int(is_ray), _p(vox), _p(dt), cap)
     if n < 0:
         raise ValueError("segment leaves the grid")
     return vox[:n].copy(), dt[:n].copy()
@@ -191,7 +194,8 @@ class _Scene(C.Structure):
                 ("adj_ptr", C.c_void_p), ("adj_idx", C.c_void_p), ("albedo", C.c_void_p),
                 ("sun_dir", C.c_void_p), ("view_dir", C.c_void_p), ("n_fib", C.c_int),
                 ("node_weight_mode", C.c_int), ("scatter_order", C.c_int), ("tol", C.c_double),
-                ("phase_kind", C.c_void_p), ("lut_n", C.c_int), ("lut", C.c_void_p), ("sigma_mode", C.c_int)]
+                ("phase_kind", C.c_void_p), ("lut_n", C.c_int), ("lut", C.c_void_p), ("sigma_mode", C.c_int),
+                ("periodic", C.c_int)]
 
 
 class _Out(C.Structure):
@@ -250,7 +254,8 @@ def run(scene, abs_scale: float = 1.0, scatter_order: int = 0, tol: float = 1e-1
     sc = _Scene(scene.nx, scene.ny, scene.nz, float(scene.voxel_m), _p(mu_s), _p(mu_a), len(hg_g), _p(hg_g),
                 _p(pf), _p(pos), int(scene.surface_nodes), _p(adj_ptr), _p(adj_idx), _p(alb), _p(sun),
                 _p(view), int(scene.n_fib), int(scene.node_weight_mode), int(scatter_order), float(tol),
-                _p(kind), 0 if lut is None else int(lut.shape[-1]), _p(lut), int(getattr(scene, "sigma_mode", 0)))
+                _p(kind), 0 if lut is None else int(lut.shape[-1]), _p(lut), int(getattr(scene, "sigma_mode", 0)),
+                int(getattr(scene, "periodic", 0)))
     res = dict(tau=np.zeros(E), tau_sun=np.zeros(N), rho=np.zeros(N), row_ptr=np.zeros(E + 1, np.int64),
                col=np.zeros(nnz, np.int32), val=np.zeros(nnz), S=np.zeros(E), phi=np.zeros(E),
                radiance=np.zeros(scene.nx * scene.ny), stats=np.zeros(8))

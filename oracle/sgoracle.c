@@ -86,8 +86,23 @@ static int64_t floor_div(int64_t a, int64_t b) {
  */
 typedef void (*visit_fn)(void *ctx, int64_t vox, double dt);
 
-static int dda_walk(int nx, int ny, int nz, const int64_t P[3], const int64_t D[3], int is_ray,
-                    visit_fn visit, void *ctx) {
+/*
+ * Periodic horizontal boundaries (plane-parallel slabs, Sec. 3): with bit 0 (x) or
+ * bit 1 (y) of `periodic` set, the medium repeats along that axis with the grid's
+ * period.  The walk then keeps its exact crossing times on the unwrapped line, never
+ * leaves through that axis, and visits the voxel whose index is wrapped into the grid
+ * (ix mod nx); a ray ends only through z.  A walk takes at most MAX_WALK_STEPS voxels
+ * (a ray close to horizontal in a clear periodic medium would otherwise run on).
+ */
+#define MAX_WALK_STEPS 65536
+
+static int64_t wrap_index(int64_t i, int64_t n) {
+    const int64_t r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+static int dda_walk_p(int nx, int ny, int nz, int periodic, const int64_t P[3], const int64_t D[3], int is_ray,
+                      visit_fn visit, void *ctx) {
     int64_t n[3] = {nx, ny, nz};
     int64_t idx[3], step[3];
     rat tn[3];
@@ -118,12 +133,13 @@ static int dda_walk(int nx, int ny, int nz, const int64_t P[3], const int64_t D[
     const rat tend = {1, 1};
     int count = 0;
     for (;;) {
-        int inside = idx[0] >= 0 && idx[0] < n[0] && idx[1] >= 0 && idx[1] < n[1] && idx[2] >= 0 &&
-                     idx[2] < n[2];
+        int inside = ((periodic & 1) || (idx[0] >= 0 && idx[0] < n[0])) &&
+                     ((periodic & 2) || (idx[1] >= 0 && idx[1] < n[1])) && idx[2] >= 0 && idx[2] < n[2];
         if (!inside) {
             if (is_ray) break;
             return -1;
         }
+        if (count >= MAX_WALK_STEPS) break;
         rat tmin = {1, 0}; /* +infinity */
         int have = 0;
         for (int k = 0; k < 3; ++k) {
@@ -141,7 +157,9 @@ static int dda_walk(int nx, int ny, int nz, const int64_t P[3], const int64_t D[
         int64_t num = tmin.n * tcur.d - tcur.n * tmin.d;
         int64_t den = tmin.d * tcur.d;
         double dt = (double)num / (double)den;
-        visit(ctx, idx[0] + (int64_t)nx * (idx[1] + (int64_t)ny * idx[2]), dt);
+        const int64_t wx = (periodic & 1) ? wrap_index(idx[0], nx) : idx[0];
+        const int64_t wy = (periodic & 2) ? wrap_index(idx[1], ny) : idx[1];
+        visit(ctx, wx + (int64_t)nx * (wy + (int64_t)ny * idx[2]), dt);
         ++count;
         if (last) break;
         for (int k = 0; k < 3; ++k) {
@@ -153,6 +171,23 @@ static int dda_walk(int nx, int ny, int nz, const int64_t P[3], const int64_t D[
         tcur = tmin;
     }
     return count;
+}
+
+static int dda_walk(int nx, int ny, int nz, const int64_t P[3], const int64_t D[3], int is_ray, visit_fn visit,
+                    void *ctx) {
+    return dda_walk_p(nx, ny, nz, 0, P, D, is_ray, visit, ctx);
+}
+
+/* The displacement from node a to node b: b - a, on a periodic axis the shortest of its
+   images (the scene guarantees it is shorter than half the period). */
+static void node_disp(const int64_t *pos, int64_t a, int64_t b, int nx, int ny, int periodic, int64_t D[3]) {
+    for (int k = 0; k < 3; ++k) D[k] = pos[3 * b + k] - pos[3 * a + k];
+    const int64_t W[2] = {(int64_t)nx * FXS, (int64_t)ny * FXS};
+    for (int k = 0; k < 2; ++k) {
+        if (!(periodic & (1 << k))) continue;
+        if (2 * D[k] > W[k]) D[k] -= W[k];
+        else if (2 * D[k] < -W[k]) D[k] += W[k];
+    }
 }
 
 typedef struct {
@@ -178,6 +213,14 @@ int or_trace(int nx, int ny, int nz, const int64_t *P, const int64_t *D, int is_
     return r < 0 ? r : b.n;
 }
 
+/* The same with periodic horizontal axes (bit 0: x, bit 1: y). */
+int or_trace_p(int nx, int ny, int nz, int periodic, const int64_t *P, const int64_t *D, int is_ray, int64_t *vox,
+               double *dt, int cap) {
+    trace_buf b = {vox, dt, cap, 0};
+    int r = dda_walk_p(nx, ny, nz, periodic, P, D, is_ray, trace_visit, &b);
+    return r < 0 ? r : b.n;
+}
+
 typedef struct {
     const double *mu_e;
     double tau; /* accumulated sum of mu_e * dt (dt in parameter units) */
@@ -195,10 +238,10 @@ static double param_length_m(const int64_t D[3], double voxel_m) {
 }
 
 /* Optical depth along a segment (is_ray = 0) or a ray to the grid exit. */
-static double optical_depth(int nx, int ny, int nz, const double *mu_e, double voxel_m,
+static double optical_depth(int nx, int ny, int nz, int periodic, const double *mu_e, double voxel_m,
                             const int64_t P[3], const int64_t D[3], int is_ray) {
     tau_acc a = {mu_e, 0.0};
-    dda_walk(nx, ny, nz, P, D, is_ray, tau_visit, &a);
+    dda_walk_p(nx, ny, nz, periodic, P, D, is_ray, tau_visit, &a);
     return a.tau * param_length_m(D, voxel_m);
 }
 
@@ -337,6 +380,7 @@ typedef struct {
     int lut_n;             /* samples per table row */
     const double *lut;     /* [n_phase][lut_n] tables in mu = cos(theta) on [-1, 1] */
     int sigma_mode;        /* 0: Voronoi ownership of the lattice; 1: nearest-point colouring + flood fill */
+    int periodic;          /* bit 0: periodic in x, bit 1: periodic in y (plane-parallel slabs) */
 } or_scene;
 
 /*
@@ -752,6 +796,26 @@ int or_run(const or_scene *sc, or_out *out) {
     /* the Lambertian cells need a lattice point above the surface: with one point,
        z_0 = 1 - 1/N = 0 lies on the horizon and the cosine weights are 0 / 0 */
     if (NF < 2) return 8;
+    /* periodic axes: only x and y; every node-to-node displacement must have a unique
+       shortest image (|D_k| != half the period), and the sun and view rays must reach the
+       top within the walk's step limit: a ray from height z crosses at most nz z-planes
+       and nz |D_x| / D_z + 1 x-planes (y alike), so the bound below covers every start */
+    if (sc->periodic & ~3) return 9;
+    if (sc->periodic) {
+        const int64_t W[2] = {(int64_t)nx * FXS, (int64_t)ny * FXS};
+        for (int64_t l = 0; l < N; ++l)
+            for (int64_t e = sc->adj_ptr[l]; e < sc->adj_ptr[l + 1]; ++e) {
+                int64_t D[3];
+                node_disp(sc->pos, l, sc->adj_idx[e], nx, ny, sc->periodic, D);
+                for (int k = 0; k < 2; ++k)
+                    if ((sc->periodic & (1 << k)) && 2 * (D[k] < 0 ? -D[k] : D[k]) == W[k]) return 9;
+            }
+        for (int r = 0; r < 2; ++r) {
+            const int64_t *d = r ? sc->view_dir : sc->sun_dir;
+            const int64_t ax = d[0] < 0 ? -d[0] : d[0], ay = d[1] < 0 ? -d[1] : d[1];
+            if (d[2] <= 0 || (int64_t)nz * (ax + ay + d[2]) + 4 * d[2] > (int64_t)MAX_WALK_STEPS * d[2]) return 9;
+        }
+    }
 
     /* wall time of the stages, for the benchmark's CPU baseline (stats[4..7]) */
     const double t_start = wall_s();
@@ -772,12 +836,10 @@ int or_run(const or_scene *sc, or_out *out) {
             int64_t j = sc->adj_idx[e];
             int64_t a = l < j ? l : j, b = l < j ? j : l;
             int64_t P[3], D[3];
-            for (int k = 0; k < 3; ++k) {
-                P[k] = sc->pos[3 * a + k];
-                D[k] = sc->pos[3 * b + k] - sc->pos[3 * a + k];
-            }
+            for (int k = 0; k < 3; ++k) P[k] = sc->pos[3 * a + k];
+            node_disp(sc->pos, a, b, nx, ny, sc->periodic, D);
             tau_acc acc = {mu_e, 0.0};
-            if (dda_walk(nx, ny, nz, P, D, 0, tau_visit, &acc) < 0) bad = 1;
+            if (dda_walk_p(nx, ny, nz, sc->periodic, P, D, 0, tau_visit, &acc) < 0) bad = 1;
             out->tau[e] = acc.tau * param_length_m(D, dx);
         }
     }
@@ -786,7 +848,7 @@ int or_run(const or_scene *sc, or_out *out) {
     /* O2: node -> sun optical depth to the grid exit */
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t l = 0; l < N; ++l) {
-        out->tau_sun[l] = optical_depth(nx, ny, nz, mu_e, dx, sc->pos + 3 * l, sc->sun_dir, 1);
+        out->tau_sun[l] = optical_depth(nx, ny, nz, sc->periodic, mu_e, dx, sc->pos + 3 * l, sc->sun_dir, 1);
     }
 
     /* O6: node weights (bounded scattering probability over one voxel edge; mode 1: mu_s * edge) */
@@ -861,7 +923,7 @@ int or_run(const or_scene *sc, or_out *out) {
             for (int m = 0; m < d; ++m) {
                 int64_t e = off + m, j = sc->adj_idx[e];
                 int64_t D[3];
-                for (int k = 0; k < 3; ++k) D[k] = sc->pos[3 * j + k] - sc->pos[3 * l + k];
+                node_disp(sc->pos, l, j, nx, ny, sc->periodic, D);
                 unit_of(D, s + 3 * m); /* out-direction of edge (l -> j) */
                 rev[m] = edge_rev(sc, e, l); /* in-edge (j -> l) */
             }
@@ -918,7 +980,7 @@ int or_run(const or_scene *sc, or_out *out) {
     const double Lview = param_length_m(sc->view_dir, dx);
 #pragma omp parallel
     {
-        int cap = 4 * (nx + ny + nz) + 8;
+        int cap = sc->periodic ? MAX_WALK_STEPS : 4 * (nx + ny + nz) + 8;
         int64_t *vox = (int64_t *)malloc(sizeof(int64_t) * cap);
         double *dtv = (double *)malloc(sizeof(double) * cap);
 #pragma omp for schedule(dynamic, 16)
@@ -926,7 +988,7 @@ int or_run(const or_scene *sc, or_out *out) {
             int64_t ix = p % nx, iy = p / nx;
             int64_t P[3] = {ix * FXS + FXS / 2, iy * FXS + FXS / 2, 0};
             trace_buf tb = {vox, dtv, cap, 0};
-            dda_walk(nx, ny, nz, P, sc->view_dir, 1, trace_visit, &tb);
+            dda_walk_p(nx, ny, nz, sc->periodic, P, sc->view_dir, 1, trace_visit, &tb);
             int nseg = tb.n;
             double Iv = 0.0;
             double tau_after = 0.0; /* optical depth between the segment's far end and the sensor */
@@ -946,7 +1008,7 @@ int or_run(const or_scene *sc, or_out *out) {
                     for (int64_t e = sc->adj_ptr[v]; e < sc->adj_ptr[v + 1]; ++e) {
                         int64_t j = sc->adj_idx[e];
                         int64_t D[3];
-                        for (int k2 = 0; k2 < 3; ++k2) D[k2] = sc->pos[3 * v + k2] - sc->pos[3 * j + k2];
+                        node_disp(sc->pos, j, v, nx, ny, sc->periodic, D);
                         double sa[3];
                         unit_of(D, sa); /* propagation direction of in-edge (j -> v) */
                         double mu = sa[0] * vu[0] + sa[1] * vu[1] + sa[2] * vu[2];
@@ -974,7 +1036,7 @@ int or_run(const or_scene *sc, or_out *out) {
                 }
                 Iv += Tsurf * (sc->albedo[p] / M_PI) * Js;
             } else {
-                Iv += Tsurf * (sc->albedo[p] / M_PI) * mu0 * exp(-optical_depth(nx, ny, nz, mu_e, dx, P, sc->sun_dir, 1));
+                Iv += Tsurf * (sc->albedo[p] / M_PI) * mu0 * exp(-optical_depth(nx, ny, nz, sc->periodic, mu_e, dx, P, sc->sun_dir, 1));
             }
             out->pix[p] = Iv;
         }

@@ -62,6 +62,7 @@ class Scene:
     phase_kind: Optional[np.ndarray] = None  # int32 [n_phase]: 0 Henyey-Greenstein, 1 Rayleigh, 2 table
     phase_lut: Optional[np.ndarray] = None   # float64 [n_phase, n] tables in cos(theta) on [-1, 1]
     sigma_mode: int = 0         # 0 = Voronoi ownership of the lattice, 1 = nearest-point colouring + flood fill
+    periodic: int = 0           # bit 0: x, bit 1: y repeat with the grid's period (plane-parallel slabs)
 
     # ---- derived sizes (no method arithmetic) ----
     @property
@@ -119,7 +120,7 @@ class Scene:
             if a is not None:
                 h.update(np.ascontiguousarray(a).tobytes())
         h.update(repr((self.nx, self.ny, self.nz, self.voxel_m, self.surface_nodes, self.n_fib,
-                       self.node_weight_mode, self.sigma_mode)).encode())
+                       self.node_weight_mode, self.sigma_mode, self.periodic)).encode())
         return h.hexdigest()[:16]
 
     def with_(self, **kw) -> "Scene":
@@ -232,6 +233,76 @@ def radius_graph(vol_pos_fx: np.ndarray, nx: int, ny: int, nz: int, radius_vox: 
     else:
         t = np.zeros(0, np.int64)
         h = np.zeros(0, np.int64)
+    return adjacency_from_pairs(n_nodes, t, h)
+
+
+def periodic_radius_graph(vol_pos_fx: np.ndarray, nx: int, ny: int, nz: int, radius_vox: float,
+                          periodic: int, surface: bool = True, jitter: float = 0.25):
+    """radius_graph with x (bit 0 of periodic) and/or y (bit 1) repeating with the grid's
+    period: distances use the shortest image along those axes.  Needs the grid wider
+    than twice the search reach along each periodic axis, so that every pair is found
+    once and its shortest image is unique."""
+    r2 = int(math.floor((radius_vox * FX) ** 2))
+    K = int(math.floor(radius_vox + 2 * jitter))
+    if (periodic & 1 and nx <= 2 * K + 1) or (periodic & 2 and ny <= 2 * K + 1):
+        raise ValueError("a periodic axis must be wider than twice the search reach")
+    W = np.array([nx * FX, ny * FX, 0], np.int64)
+    per = np.array([bool(periodic & 1), bool(periodic & 2), False])
+    vol = vol_pos_fx.astype(np.int64).reshape(nz, ny, nx, 3)
+    nvox = nx * ny * nz
+    vid = np.arange(nvox, dtype=np.int64).reshape(nz, ny, nx)
+
+    def shortest(d):
+        for k in (0, 1):
+            if per[k]:
+                d[..., k] -= W[k] * np.round(d[..., k] / W[k]).astype(np.int64)
+        return d
+
+    def shifted(a, dy, dx):  # a[y + dy, x + dx] with wrapping on the periodic axes
+        return np.roll(np.roll(a, -dy, axis=-2), -dx, axis=-1)
+
+    tails, heads = [], []
+    for dz in range(0, min(K, nz - 1) + 1):
+        for dy in range(-K, K + 1):
+            for dx in range(-K, K + 1):
+                if (dz, dy, dx) <= (0, 0, 0):
+                    continue
+                a_pos, a_id = vol[:nz - dz], vid[:nz - dz]
+                b_pos = shifted(vol[dz:].transpose(3, 0, 1, 2), dy, dx).transpose(1, 2, 3, 0)
+                b_id = shifted(vid[dz:], dy, dx)
+                # pairs whose offset leaves the grid on a non-periodic axis do not exist
+                ok = np.ones(a_id.shape, bool)
+                yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+                if not per[1]:
+                    ok &= ((yy + dy >= 0) & (yy + dy < ny))[None]
+                if not per[0]:
+                    ok &= ((xx + dx >= 0) & (xx + dx < nx))[None]
+                d = shortest(b_pos - a_pos)
+                m = ok & ((d * d).sum(axis=-1) <= r2)
+                tails.append(a_id[m])
+                heads.append(b_id[m])
+    n_nodes = nvox
+    if surface:
+        n_nodes = nvox + nx * ny
+        spos = surface_positions(nx, ny).reshape(ny, nx, 3).astype(np.int64)
+        sid = nvox + np.arange(nx * ny, dtype=np.int64).reshape(ny, nx)
+        yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+        for dz in range(0, min(K, nz - 1) + 1):
+            for dy in range(-K, K + 1):
+                for dx in range(-K, K + 1):
+                    v_pos = shifted(vol[dz].transpose(2, 0, 1), dy, dx).transpose(1, 2, 0)
+                    v_id = shifted(vid[dz], dy, dx)
+                    ok = np.ones((ny, nx), bool)
+                    if not per[1]:
+                        ok &= (yy + dy >= 0) & (yy + dy < ny)
+                    if not per[0]:
+                        ok &= (xx + dx >= 0) & (xx + dx < nx)
+                    d = shortest(v_pos - spos)
+                    m = ok & ((d * d).sum(axis=-1) <= r2)
+                    tails.append(sid[m])
+                    heads.append(v_id[m])
+    t = np.concatenate(tails) if tails else np.zeros(0, np.int64)
+    h = np.concatenate(heads) if heads else np.zeros(0, np.int64)
     return adjacency_from_pairs(n_nodes, t, h)
 
 
@@ -458,6 +529,31 @@ def make_random_small(seed, nx=3, ny=3, nz=3, dx=100.0, R=1.8, two_phase=False, 
         gg = [0.6]
     return _finish(f"rand-{nx}x{ny}x{nz}-s{seed}", seed, nx, ny, nz, dx, mu_s, mu_a, gg, frac, pos,
                    R, alb, sza, saa, vza, vaa, surface=surface)
+
+
+def make_slab(nx=12, ny=10, nz=6, dx=100.0, layers=(0.02, 0.01, 0.004, 0.002, 0.001, 0.0005), omega=0.9,
+              g=0.7, albedo=0.2, R=1.8, periodic=3, jitter=None, seed=13, sza=40.0, saa=30.0, vza=25.0,
+              vaa=120.0, n_lambda=0):
+    """Horizontally homogeneous layers (extinction layers[iz] in 1/m), periodic in x and y
+    (plane-parallel slab): with nodes at the voxel centres (jitter None) every column
+    sees the same medium, so every pixel has the same radiance."""
+    rng = np.random.default_rng(seed)
+    pos = (jittered_positions(rng, nx, ny, nz) if jitter is not None else
+           jittered_positions(rng, nx, ny, nz, jitter=0.0))
+    ke = np.broadcast_to(np.asarray(layers[:nz], np.float64)[:, None, None], (nz, ny, nx))
+    alb = np.full((ny, nx), albedo)
+    adj_ptr, adj_idx = periodic_radius_graph(pos, nx, ny, nz, R, periodic,
+                                             jitter=0.25 if jitter is None else jitter)
+    abs_scale = None
+    if n_lambda > 0:
+        abs_scale = np.geomspace(0.3, 3.0, n_lambda).astype(np.float32)
+    return Scene(name=f"slab-{nx}x{ny}x{nz}-p{periodic}", seed=seed, nx=nx, ny=ny, nz=nz, voxel_m=float(dx),
+                 mu_s=np.ascontiguousarray(omega * ke, dtype=np.float32),
+                 mu_a=np.ascontiguousarray((1 - omega) * ke, dtype=np.float32),
+                 hg_g=np.array([g]), phase_frac=None, vol_pos_fx=pos, surface_nodes=1, adj_ptr=adj_ptr,
+                 adj_idx=adj_idx, surf_albedo=np.ascontiguousarray(alb, dtype=np.float32),
+                 sun_dir=direction_fx(sza, saa), view_dir=direction_fx(vza, vaa), abs_scale=abs_scale,
+                 angles=(sza, saa, vza, vaa), periodic=periodic)
 
 
 def make_worked_example(dx=100.0, mu_e=0.002, omega=0.9, g=0.7, seed=11):

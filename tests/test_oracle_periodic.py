@@ -1,0 +1,184 @@
+"""Pins of the oracle's periodic horizontal boundaries (plane-parallel slabs, Sec. 3:
+the medium is a stack of flat layers bounded by parallel planes).
+
+A horizontally periodic grid stands for a medium of infinite horizontal extent.  The
+pins: the periodic walk is the ordinary walk on a grid tiled with copies of the medium
+(voxel ids taken modulo the period, parameter lengths bit for bit); the single-scattering
+radiance of a homogeneous layered slab is the closed plane-parallel form at every pixel;
+the full solve of such a slab is the same at every pixel; and a circular shift of a
+heterogeneous periodic medium shifts its image by the same amount.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_16037_amd import scenes
+
+S = scenes.FX
+
+
+@pytest.mark.parametrize("periodic", [1, 2, 3])
+def test_periodic_walk_equals_the_walk_on_a_tiled_grid(periodic):
+    rng = np.random.default_rng(7 + periodic)
+    nx, ny, nz = 5, 4, 3
+    for trial in range(300):
+        is_ray = trial % 2
+        P = np.array([rng.integers(0, nx * S), rng.integers(0, ny * S), rng.integers(0, nz * S)], np.int64)
+        if trial % 7 == 0:  # start on voxel planes
+            P[:2] = (P[:2] // S) * S
+        if is_ray:
+            D = rng.integers(-3 * S, 3 * S + 1, 3)
+            D[2] = rng.integers(S // 2, 2 * S)
+        else:
+            D = rng.integers(-2 * S, 2 * S + 1, 3)
+            # the segment stays inside in z
+            D[2] = rng.integers(-P[2], nz * S - P[2] + 1)
+        T = 2 * int(math.ceil((nz * S) * (abs(D[0]) + abs(D[1]) + S) / max(abs(D[2]), 1) / S / min(nx, ny))) + 3
+        if not is_ray:
+            T = 7
+        Tx = T if periodic & 1 else 1
+        Ty = T if periodic & 2 else 1
+        # non-periodic axes: keep the path inside the grid along them
+        if not periodic & 1:
+            D[0] = 0 if is_ray else min(max(D[0], -P[0]), nx * S - 1 - P[0])
+        if not periodic & 2:
+            D[1] = 0 if is_ray else min(max(D[1], -P[1]), ny * S - 1 - P[1])
+        if not D.any():
+            continue
+        Pt = P + np.array([(Tx // 2) * nx * S, (Ty // 2) * ny * S, 0], np.int64)
+        v_big, dt_big = oracle.trace(nx * Tx, ny * Ty, nz, Pt, D, is_ray)
+        v, dt = oracle.trace(nx, ny, nz, P, D, is_ray, periodic=periodic)
+        v_map = ((v_big % (nx * Tx)) % nx) + nx * (((v_big // (nx * Tx)) % (ny * Ty)) % ny + ny * (
+            v_big // (nx * Tx * ny * Ty)))
+        assert np.array_equal(v, v_map), (trial, P, D)
+        assert np.array_equal(dt, dt_big), (trial, P, D)
+
+
+def test_periodic_segment_may_cross_the_side_planes():
+    nx, ny, nz = 4, 4, 2
+    P = np.array([S // 4, S // 2, S // 2], np.int64)
+    D = np.array([-S // 2, 0, 0], np.int64)
+    with pytest.raises(ValueError):
+        oracle.trace(nx, ny, nz, P, D, 0)
+    v, dt = oracle.trace(nx, ny, nz, P, D, 0, periodic=1)
+    assert list(v % nx) == [0, nx - 1] and np.allclose(dt, [0.5, 0.5])
+
+
+def closed_single_scatter(sc, g):
+    """Single-scattering radiance of a homogeneous layered periodic slab with nodes at
+    the voxel centres, written out per layer: each layer contributes its scattered sun
+    (phase times the sun's transmittance to the layer's nodes at mid-layer) weighted by
+    the probability of scattering inside it along the line of sight and the view
+    transmittance above it; the Lambertian ground adds its reflected direct sun.  The
+    layers' coefficients and the albedo are read from the scene, as stored (float32)."""
+    dz = sc.voxel_m
+    s = np.asarray(sc.sun_dir, np.float64)
+    v = np.asarray(sc.view_dir, np.float64)
+    su, vu = s / np.linalg.norm(s), v / np.linalg.norm(v)
+    mu0, muv = su[2], vu[2]
+    mu = float(np.dot(-su, vu))
+    phase = (1 - g * g) / (4 * np.pi * (1 + g * g - 2 * g * mu) ** 1.5)
+    ms = np.asarray(sc.mu_s, np.float64)[:, 0, 0]
+    mu_e = ms + np.asarray(sc.mu_a, np.float64)[:, 0, 0]
+    I = 0.0
+    for iz in range(sc.nz):
+        omega = ms[iz] / mu_e[iz]
+        above = mu_e[iz + 1:].sum() * dz
+        tau_sun = (0.5 * mu_e[iz] * dz + above) / mu0
+        I += omega * phase * math.exp(-tau_sun) * math.exp(-above / muv) * (-math.expm1(-mu_e[iz] * dz / muv))
+    tot = mu_e.sum() * dz
+    albedo = float(np.asarray(sc.surf_albedo, np.float64)[0, 0])
+    I += math.exp(-tot / muv) * (albedo / np.pi) * mu0 * math.exp(-tot / mu0)
+    return I
+
+
+LAYERS = (0.004, 0.003, 0.002, 0.0015, 0.001, 0.0005)
+
+
+def test_slab_single_scatter_is_the_plane_parallel_closed_form():
+    sc = scenes.make_slab(layers=LAYERS, omega=0.9, g=0.7, albedo=0.2)
+    ref = closed_single_scatter(sc, 0.7)
+    pix = oracle.run(sc, scatter_order=1)["radiance"]
+    assert np.abs(pix - ref).max() <= 1e-12 * ref
+    # the bounded grid loses light at its sides: the same layers without the periodic
+    # boundary miss the closed form, so the pin above reads the flag
+    flat = scenes.make_slab(layers=LAYERS, omega=0.9, g=0.7, albedo=0.2, periodic=0)
+    pix0 = oracle.run(flat, scatter_order=1)["radiance"]
+    assert np.abs(pix0 - ref).max() > 1e-3 * ref
+
+
+def test_slab_full_solve_is_horizontally_uniform():
+    sc = scenes.make_slab(layers=LAYERS)
+    pix = oracle.run(sc)["radiance"]
+    assert (pix.max() - pix.min()) <= 1e-11 * pix.max()
+    # multiple scattering adds light over the single-scattering closed form
+    assert pix.min() > closed_single_scatter(sc, 0.7) * (1 + 1e-3)
+    flat = oracle.run(scenes.make_slab(layers=LAYERS, periodic=0))["radiance"]
+    assert (flat.max() - flat.min()) > 1e-3 * flat.max()
+
+
+def shifted_scene(sc, sx, sy):
+    """The same periodic medium with its origin moved by (sx, sy) voxels."""
+    nx, ny, nz = sc.nx, sc.ny, sc.nz
+    pos = np.asarray(sc.vol_pos_fx, np.int64).reshape(nz, ny, nx, 3)
+    pos = np.roll(pos, (sy, sx), axis=(1, 2)).copy()
+    pos[..., 0] = (pos[..., 0] + sx * S) % (nx * S)
+    pos[..., 1] = (pos[..., 1] + sy * S) % (ny * S)
+    pos = pos.reshape(-1, 3)
+    adj_ptr, adj_idx = scenes.periodic_radius_graph(pos, nx, ny, nz, 1.8, sc.periodic)
+    roll3 = lambda a: np.ascontiguousarray(np.roll(np.asarray(a).reshape(nz, ny, nx), (sy, sx), axis=(1, 2)))
+    return dataclasses.replace(sc, vol_pos_fx=pos.astype(np.int32), adj_ptr=adj_ptr, adj_idx=adj_idx,
+                               mu_s=roll3(sc.mu_s), mu_a=roll3(sc.mu_a),
+                               surf_albedo=np.ascontiguousarray(np.roll(sc.surf_albedo, (sy, sx), axis=(0, 1))))
+
+
+@pytest.mark.parametrize("periodic", [3, 1])
+def test_circular_shift_of_a_periodic_medium_shifts_the_image(periodic):
+    rng = np.random.default_rng(5)
+    sc = scenes.make_slab(nx=10, ny=9, nz=5, jitter=0.25, periodic=periodic, seed=3)
+    ke = rng.lognormal(np.log(0.003), 0.8, (sc.nz, sc.ny, sc.nx))
+    sc = dataclasses.replace(sc, mu_s=(0.9 * ke).astype(np.float32), mu_a=(0.1 * ke).astype(np.float32),
+                             surf_albedo=rng.uniform(0.05, 0.4, (sc.ny, sc.nx)).astype(np.float32))
+    sx, sy = (3, 4) if periodic == 3 else (3, 0)
+    base = oracle.run(sc)["radiance"]
+    moved = oracle.run(shifted_scene(sc, sx, sy))["radiance"]
+    assert np.abs(moved - np.roll(base, (sy, sx), axis=(0, 1))).max() <= 1e-10 * base.max()
+
+
+def test_periodic_scene_validation():
+    sc = scenes.make_slab(nx=6, ny=6, nz=3)
+    with pytest.raises(ValueError):
+        oracle.run(dataclasses.replace(sc, periodic=4))
+    # a sun so low that its rays would wind round the period beyond the walk's limit
+    with pytest.raises(ValueError):
+        oracle.run(dataclasses.replace(sc, sun_dir=scenes.direction_fx(89.999, 10.0)))
+    # a coupling of exactly half the period has two shortest images
+    two = scenes.make_slab(nx=6, ny=6, nz=3)
+    pos = np.asarray(two.vol_pos_fx, np.int64).copy()
+    a, b = 0, 3  # voxels (0,0,0) and (3,0,0): 3 voxels apart in a period of 6
+    adj_ptr = np.zeros(two.n_nodes + 1, np.int64)
+    adj_ptr[a + 1:] += 1
+    adj_ptr[b + 1:] += 1
+    adj_idx = np.array([b, a], np.int32)
+    bad = dataclasses.replace(two, vol_pos_fx=pos.astype(np.int32), adj_ptr=adj_ptr, adj_idx=adj_idx)
+    with pytest.raises(ValueError):
+        oracle.run(bad)
+    oracle.run(dataclasses.replace(bad, periodic=2))  # along x alone the pair is an ordinary edge
+
+
+def test_periodic_radius_graph():
+    rng = np.random.default_rng(2)
+    nx, ny, nz = 9, 8, 4
+    pos = scenes.jittered_positions(rng, nx, ny, nz)
+    ref = scenes.radius_graph(pos, nx, ny, nz, 1.8, surface=True, jitter=0.25)
+    got = scenes.periodic_radius_graph(pos, nx, ny, nz, 1.8, 0)
+    assert all(np.array_equal(x, y) for x, y in zip(ref, got))
+    # with nodes at the voxel centres every node of a layer has the same neighbourhood
+    sc = scenes.make_slab(nx=nx, ny=ny, nz=nz)
+    deg = np.diff(sc.adj_ptr)[:nx * ny * nz].reshape(nz, ny * nx)
+    assert (deg == deg[:, :1]).all()
+    with pytest.raises(ValueError):
+        scenes.periodic_radius_graph(pos, 4, 8, 4, 1.8, 1)
