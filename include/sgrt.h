@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define SG_ABI_VERSION 4u
+#define SG_ABI_VERSION 5u
 
 typedef int32_t sg_status;
 enum {
@@ -134,8 +134,19 @@ typedef struct sg_scene_desc {
                                   index) and the colours spread by flood fill along the edges
                                   of the lattice's convex hull, in rounds, an uncoloured point
                                   taking the colour of its lowest-index coloured neighbour */
+    int32_t periodic;          /* flat slabs of infinite horizontal extent (Sec. 3: media
+                                  bounded by parallel planes): bit 0 (SG_PERIODIC_X) and bit 1
+                                  (SG_PERIODIC_Y) make the grid repeat along that axis with
+                                  its period.  Every march then wraps voxel indices round the
+                                  period and ends only through z; node-to-node directions and
+                                  couplings use the shortest periodic image of the
+                                  displacement, which must be unique (no pair exactly half a
+                                  period apart).  The sun and view rays must reach the top
+                                  within 65536 voxels: nz (|d_x| + |d_y| + d_z) + 4 d_z <=
+                                  65536 d_z on both directions.  0: bounded grid */
 } sg_scene_desc;
 enum { SG_SIGMA_VORONOI = 0, SG_SIGMA_COLOUR = 1 };
+enum { SG_PERIODIC_X = 1, SG_PERIODIC_Y = 2 };
 enum { SG_PHASE_HG = 0, SG_PHASE_RAYLEIGH = 1, SG_PHASE_TABLE = 2 };
 
 /*
@@ -268,6 +279,8 @@ enum { SG_TRACE_EDGE = 0, SG_TRACE_SUN = 1, SG_TRACE_VIEW = 2 };
  * view_dir).  Host buffers: voxels [n_ids][cap] (int32 voxel ids), dt
  * [n_ids][cap] (parameter length inside the voxel, as double), count
  * [n_ids] (voxels of the path; a value > cap means truncated output).
+ * With periodic axes the edge walk follows the shortest periodic image and
+ * every voxel id is wrapped into the grid.
  */
 sg_status sg_trace(sg_scene *scene, int32_t kind, const int64_t *ids, int32_t n_ids, int32_t cap,
                    int32_t *voxels, double *dt, int32_t *count);

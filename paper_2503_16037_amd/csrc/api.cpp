@@ -283,6 +283,29 @@ sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz,
             if (l >= nvox && j >= nvox) return fail(SG_E_INVALID, "surface-surface pair");
         }  // symmetry is checked on the device once the adjacency is uploaded
     }
+    if (d->periodic & ~(SG_PERIODIC_X | SG_PERIODIC_Y))
+        return fail(SG_E_INVALID, "periodic must combine SG_PERIODIC_X and SG_PERIODIC_Y");
+    if (d->periodic) {
+        // a ray from height z crosses at most nz z-planes and nz |d_x| / d_z + 1 x-planes
+        // (y alike): this bound keeps every sun and view walk within the walk's limit
+        for (const int32_t *v : {d->sun_dir, d->view_dir}) {
+            const long long ax = std::llabs((long long)v[0]), ay = std::llabs((long long)v[1]), az = v[2];
+            if ((long long)d->nz * (ax + ay + az) + 4 * az > 65536LL * az)
+                return fail(SG_E_INVALID, "with periodic axes the sun and view rays must reach the top within 65536 voxels");
+        }
+        const auto coord = [&](int64_t l, int k) -> long long {
+            if (l < nvox) return d->vol_pos_fx[3 * l + k];
+            const int64_t c = l - nvox;  // surface node: the column's centre
+            return (k == 0 ? c % d->nx : c / d->nx) * 65536LL + 32768;
+        };
+        const long long W[2] = {(long long)d->nx * 65536, (long long)d->ny * 65536};
+        for (int64_t l = 0; l < N; ++l)
+            for (int64_t e = ap[l]; e < ap[l + 1]; ++e)
+                for (int k = 0; k < 2; ++k)
+                    if ((d->periodic >> k & 1) && 2 * std::llabs(coord(d->adj_idx[e], k) - coord(l, k)) == W[k])
+                        return fail(SG_E_INVALID, "a coupled pair is exactly half a period apart (node " +
+                                                      std::to_string(l) + ")");
+    }
     return SG_OK;
 }
 
@@ -999,6 +1022,7 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     }
     s.n_fib = d->n_fib;
     s.sigma_mode = d->sigma_mode;
+    s.periodic = d->periodic;
     s.surface = d->surface_nodes ? 1 : 0;
     s.weight_mode = d->node_weight_mode;
     s.n_lambda = d->n_lambda;

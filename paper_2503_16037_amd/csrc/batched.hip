@@ -388,7 +388,7 @@ __global__ __launch_bounds__(64) void k_bnode_J(int N, int nvox, int nl, const l
                                                const float *__restrict__ bsrc, const double *__restrict__ phi,
                                                PhaseSet pm, const float *__restrict__ frac, double sx, double sy,
                                                double sz, double vx, double vy, double vz, int multiple,
-                                               double *__restrict__ J) {
+                                               int per, long long wx, long long wy, double *__restrict__ J) {
     __shared__ double th[64];
     const int l = blockIdx.x;
     const int lane = threadIdx.x;
@@ -399,8 +399,9 @@ __global__ __launch_bounds__(64) void k_bnode_J(int N, int nvox, int nl, const l
         double t = 1.0;
         if (vol) {
             const int j = adj_idx[off + lane];
-            const long long Dx = (long long)pos[3 * l] - pos[3 * j], Dy = (long long)pos[3 * l + 1] - pos[3 * j + 1],
-                            Dz = (long long)pos[3 * l + 2] - pos[3 * j + 2];
+            const long long Dx = min_image((long long)pos[3 * l] - pos[3 * j], wx, per & 1);
+            const long long Dy = min_image((long long)pos[3 * l + 1] - pos[3 * j + 1], wy, per & 2);
+            const long long Dz = (long long)pos[3 * l + 2] - pos[3 * j + 2];
             const double nrm = sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
             const double mu = ((double)Dx / nrm) * vx + ((double)Dy / nrm) * vy + ((double)Dz / nrm) * vz;
             t = theta_mix_b(pm, frac, nvox, l, mu);
@@ -427,7 +428,7 @@ __global__ __launch_bounds__(64) void k_bnode_J(int N, int nvox, int nl, const l
 
 // One wavefront per pixel, lanes = wavelengths: the voxel walk is the same for all
 // lanes, each accumulates its own wavelength in FP64.
-__global__ __launch_bounds__(64) void k_bpixels(int nx, int ny, int nz, int nl, const float *__restrict__ mu_s,
+__global__ __launch_bounds__(64) void k_bpixels(int nx, int ny, int nz, int per, int nl, const float *__restrict__ mu_s,
                                                const float *__restrict__ mu_a, const float *__restrict__ abs_scale,
                                                double len_view, long long vdx, long long vdy, long long vdz,
                                                long long sdx, long long sdy, long long sdz, double len_sun,
@@ -443,13 +444,13 @@ __global__ __launch_bounds__(64) void k_bpixels(int nx, int ny, int nz, int nl, 
         const int lam = min(l0 + lane, nl - 1);
         const double s = (double)abs_scale[lam];
         double tau_tot = 0.0;
-        voxel_walk(nx, ny, nz, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
+        voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
             const long long v = x + (long long)nx * (y + (long long)ny * z);
             tau_tot += ((double)mu_s[v] + s * (double)mu_a[v]) * ((double)num / (double)den * len_view);
             return true;
         });
         double I = 0.0, cum = 0.0;
-        voxel_walk(nx, ny, nz, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
+        voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
             const long long v = x + (long long)nx * (y + (long long)ny * z);
             const double ms = (double)mu_s[v];
             const double me = ms + s * (double)mu_a[v];
@@ -463,7 +464,7 @@ __global__ __launch_bounds__(64) void k_bpixels(int nx, int ny, int nz, int nl, 
             I += exp(-tau_tot) * a_pi * J[(nvox + p) * nl + lam];
         } else {
             double ts = 0.0;
-            voxel_walk(nx, ny, nz, px, py, 0, sdx, sdy, sdz, true, [&](int x, int y, int z, long long num, long long den) {
+            voxel_walk(nx, ny, nz, per, px, py, 0, sdx, sdy, sdz, true, [&](int x, int y, int z, long long num, long long den) {
                 const long long v = x + (long long)nx * (y + (long long)ny * z);
                 ts += ((double)mu_s[v] + s * (double)mu_a[v]) * ((double)num / (double)den * len_sun);
                 return true;
@@ -584,12 +585,12 @@ void launch_batched_gather(Scene &s, hipStream_t st, const double *phi, int scat
     hipLaunchKernelGGL(k_bnode_J, dim3(s.N), dim3(64), 0, st, s.N, s.nvox, s.n_lambda, s.adj_ptr, s.adj_idx, s.rev,
                        s.pos, (const float *)s.tau_s, (const float *)s.tau_a, s.abs_scale_d, s.bsrc, phi, pm, s.frac,
                        s.sun_in[0], s.sun_in[1], s.sun_in[2], s.view_u[0], s.view_u[1], s.view_u[2],
-                       scatter_order == 1 ? 0 : 1, s.J);
+                       scatter_order == 1 ? 0 : 1, s.periodic, (long long)s.nx * kFx, (long long)s.ny * kFx, s.J);
     const double fx = s.voxel_m / 65536.0;
     const double lv = sqrt((double)s.view[0] * s.view[0] + (double)s.view[1] * s.view[1] + (double)s.view[2] * s.view[2]) * fx;
     const double ls = sqrt((double)s.sun[0] * s.sun[0] + (double)s.sun[1] * s.sun[1] + (double)s.sun[2] * s.sun[2]) * fx;
-    hipLaunchKernelGGL(k_bpixels, dim3(s.npx), dim3(64), 0, st, s.nx, s.ny, s.nz, s.n_lambda, s.mu_s, s.mu_a,
-                       s.abs_scale_d, lv, (long long)s.view[0], (long long)s.view[1], (long long)s.view[2],
+    hipLaunchKernelGGL(k_bpixels, dim3(s.npx), dim3(64), 0, st, s.nx, s.ny, s.nz, s.periodic, s.n_lambda, s.mu_s,
+                       s.mu_a, s.abs_scale_d, lv, (long long)s.view[0], (long long)s.view[1], (long long)s.view[2],
                        (long long)s.sun[0], (long long)s.sun[1], (long long)s.sun[2], ls, s.albedo, s.J, s.surface,
                        s.mu0, radiance);
 }

@@ -34,8 +34,26 @@ __device__ __forceinline__ long long floor_div_fx(long long a) {
 // stop the walk early.  Each lane leaves the loop on its own; the wavefront
 // retires the loop when the ballot of its live lanes is empty.  Magnitudes: grid
 // <= 1024 voxels per axis and |D| <= 2^26 keep every product below 2^63.
+//
+// Periodic horizontal axes (bit 0 of per: x, bit 1: y; plane-parallel slabs): the
+// crossing times stay on the unwrapped line, the walk never ends through such an
+// axis, and the visitor gets the index wrapped into the grid.  A periodic walk
+// takes at most kMaxWalk voxels; scenes whose sun or view rays could need more
+// are rejected at creation, so the limit only bounds the loop.  Unwrapped crossing
+// numerators then stay below kMaxWalk * kFx = 2^32, the products below 2^58.
+constexpr int kMaxWalk = 65536;
+
+__device__ __forceinline__ long long min_image(long long d, long long w, bool on) {
+    // the shortest periodic image of a displacement (|d| < w on input)
+    if (on) {
+        if (2 * d > w) d -= w;
+        else if (2 * d < -w) d += w;
+    }
+    return d;
+}
+
 template <class Visit>
-__device__ __forceinline__ int voxel_walk(int nx, int ny, int nz, long long px, long long py, long long pz,
+__device__ __forceinline__ int voxel_walk(int nx, int ny, int nz, int per, long long px, long long py, long long pz,
                                           long long dx, long long dy, long long dz, bool ray, Visit &&visit) {
     long long ix, iy, iz;
     int sx, sy, sz;
@@ -50,24 +68,35 @@ __device__ __forceinline__ int voxel_walk(int nx, int ny, int nz, long long px, 
     else if (dz < 0) { iz = floor_div_fx(pz + kFx - 1) - 1; sz = -1; nzn = pz - iz * kFx; dzd = -dz; }
     else { iz = floor_div_fx(pz); sz = 0; nzn = 1; dzd = 0; }
 
+    const bool wx_on = per & 1, wy_on = per & 2;
+    // wrapped indices (the start is at most one voxel outside on a periodic axis)
+    int wx = (int)ix, wy = (int)iy;
+    if (wx_on) wx = wx < 0 ? wx + nx : (wx >= nx ? wx - nx : wx);
+    if (wy_on) wy = wy < 0 ? wy + ny : (wy >= ny ? wy - ny : wy);
     long long cn = 0, cd = 1;  // current time
     int count = 0;
-    const int max_steps = nx + ny + nz + 2;
+    const int max_steps = per ? kMaxWalk : nx + ny + nz + 2;
     for (int it = 0; it < max_steps; ++it) {
-        if (ix < 0 || ix >= nx || iy < 0 || iy >= ny || iz < 0 || iz >= nz) break;
+        if ((!wx_on && (ix < 0 || ix >= nx)) || (!wy_on && (iy < 0 || iy >= ny)) || iz < 0 || iz >= nz) break;
         long long mn = nxn, md = dxd;
         if (nyn * md < mn * dyd) { mn = nyn; md = dyd; }
         if (nzn * md < mn * dzd) { mn = nzn; md = dzd; }
         bool last = false;
         if (!ray && mn >= md) { mn = 1; md = 1; last = true; }
         ++count;
-        if (!visit((int)ix, (int)iy, (int)iz, mn * cd - cn * md, md * cd)) break;
+        if (!visit(wx, wy, (int)iz, mn * cd - cn * md, md * cd)) break;
         if (last) break;
         const bool ex = nxn * md == mn * dxd;
         const bool ey = nyn * md == mn * dyd;
         const bool ez = nzn * md == mn * dzd;
-        if (ex) { ix += sx; nxn += kFx; }
-        if (ey) { iy += sy; nyn += kFx; }
+        if (ex) {
+            ix += sx; nxn += kFx; wx += sx;
+            wx = wx == nx ? 0 : (wx < 0 ? nx - 1 : wx);  // non-periodic: the loop ends first
+        }
+        if (ey) {
+            iy += sy; nyn += kFx; wy += sy;
+            wy = wy == ny ? 0 : (wy < 0 ? ny - 1 : wy);
+        }
         if (ez) { iz += sz; nzn += kFx; }
         cn = mn;
         cd = md;

@@ -34,7 +34,8 @@ __global__ __launch_bounds__(256) void k_node_J(int N, int nvox, const long long
                                                const Real *__restrict__ Tsun, const double *__restrict__ phi,
                                                PhaseSet pm, const float *__restrict__ frac, double sx, double sy,
                                                double sz, double vx, double vy, double vz, double mu0,
-                                               int multiple, double *__restrict__ J) {
+                                               int multiple, int per, long long wx, long long wy,
+                                               double *__restrict__ J) {
     const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (l >= N) return;
@@ -48,8 +49,9 @@ __global__ __launch_bounds__(256) void k_node_J(int N, int nvox, const long long
             double th = 1.0;
             if (vol) {
                 const int j = adj_idx[e];
-                const long long Dx = (long long)pos[3 * l] - pos[3 * j], Dy = (long long)pos[3 * l + 1] - pos[3 * j + 1],
-                                Dz = (long long)pos[3 * l + 2] - pos[3 * j + 2];
+                const long long Dx = min_image((long long)pos[3 * l] - pos[3 * j], wx, per & 1);
+                const long long Dy = min_image((long long)pos[3 * l + 1] - pos[3 * j + 1], wy, per & 2);
+                const long long Dz = (long long)pos[3 * l + 2] - pos[3 * j + 2];
                 const double inv = 1.0 / sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
                 th = theta_mix(pm, frac, nvox, l, ((double)Dx * vx + (double)Dy * vy + (double)Dz * vz) * inv);
             }
@@ -64,7 +66,7 @@ __global__ __launch_bounds__(256) void k_node_J(int N, int nvox, const long long
     }
 }
 
-__global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, const float *__restrict__ mu_s,
+__global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, int per, const float *__restrict__ mu_s,
                                               const float *__restrict__ mu_a, double scale, double len_view,
                                               long long vdx, long long vdy, long long vdz, long long sdx,
                                               long long sdy, long long sdz, double len_sun,
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, const flo
     const long long nvox = (long long)nx * ny * nz;
     // pass 1: optical depth of the whole line of sight
     double tau_tot = 0.0;
-    voxel_walk(nx, ny, nz, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
+    voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
         const long long v = x + (long long)nx * (y + (long long)ny * z);
         const double me = (double)mu_s[v] + scale * (double)mu_a[v];
         tau_tot += me * ((double)num / (double)den * len_view);
@@ -85,7 +87,7 @@ __global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, const flo
     });
     // pass 2: chords, each attenuated from its far end to the sensor
     double I = 0.0, cum = 0.0;
-    voxel_walk(nx, ny, nz, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
+    voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
         const long long v = x + (long long)nx * (y + (long long)ny * z);
         const double ms = (double)mu_s[v];
         const double me = ms + scale * (double)mu_a[v];
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, const flo
         I += exp(-tau_tot) * a_pi * J[nvox + p];
     } else {
         double ts = 0.0;
-        voxel_walk(nx, ny, nz, px, py, 0, sdx, sdy, sdz, true, [&](int x, int y, int z, long long num, long long den) {
+        voxel_walk(nx, ny, nz, per, px, py, 0, sdx, sdy, sdz, true, [&](int x, int y, int z, long long num, long long den) {
             const long long v = x + (long long)nx * (y + (long long)ny * z);
             ts += ((double)mu_s[v] + scale * (double)mu_a[v]) * ((double)num / (double)den * len_sun);
             return true;
@@ -120,12 +122,13 @@ void launch_gather(Scene &s, hipStream_t st, const double *phi, int scatter_orde
     hipLaunchKernelGGL((k_node_J<Real>), dim3((s.N + 3) / 4), dim3(256), 0, st, s.N, s.nvox, s.adj_ptr, s.adj_idx,
                        s.rev, s.pos, (const Real *)s.T, (const Real *)s.Tsun, phi, pm, s.frac, s.sun_in[0],
                        s.sun_in[1], s.sun_in[2], s.view_u[0], s.view_u[1], s.view_u[2], s.mu0,
-                       scatter_order == 1 ? 0 : 1, s.J);
+                       scatter_order == 1 ? 0 : 1, s.periodic, (long long)s.nx * kFx, (long long)s.ny * kFx, s.J);
     const double fx = s.voxel_m / 65536.0;
     const double lv = sqrt((double)s.view[0] * s.view[0] + (double)s.view[1] * s.view[1] + (double)s.view[2] * s.view[2]) * fx;
     const double ls = sqrt((double)s.sun[0] * s.sun[0] + (double)s.sun[1] * s.sun[1] + (double)s.sun[2] * s.sun[2]) * fx;
     const double scale = s.abs_scale.empty() ? 1.0 : (double)s.abs_scale[0];
-    hipLaunchKernelGGL(k_pixels, dim3((s.npx + 63) / 64), dim3(64), 0, st, s.nx, s.ny, s.nz, s.mu_s, s.mu_a, scale, lv,
+    hipLaunchKernelGGL(k_pixels, dim3((s.npx + 63) / 64), dim3(64), 0, st, s.nx, s.ny, s.nz, s.periodic, s.mu_s, s.mu_a, scale,
+                       lv,
                        (long long)s.view[0], (long long)s.view[1], (long long)s.view[2], (long long)s.sun[0],
                        (long long)s.sun[1], (long long)s.sun[2], ls, s.albedo, s.J, s.surface, s.mu0, radiance);
 }

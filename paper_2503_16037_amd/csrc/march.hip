@@ -28,7 +28,7 @@ __device__ __forceinline__ void node_voxel(const int *__restrict__ pos, int l, i
 
 template <class Real>
 __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
-    int N, int nx, int ny, int nz, const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx,
+    int N, int nx, int ny, int nz, int per, const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx,
     const int *__restrict__ pos, const float *__restrict__ mu_s, const float *__restrict__ mu_a, Real len_scale,
     Real scale, Real *__restrict__ tau_s, Real *__restrict__ tau_a, Real *__restrict__ T, int use_lds) {
     __shared__ float bs[kBrickCap];
@@ -91,17 +91,19 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
         const int j = adj_idx[e];
         const int a = min(l, j), b = max(l, j);
         const long long px = pos[3 * a], py = pos[3 * a + 1], pz = pos[3 * a + 2];
-        const long long dx = pos[3 * b] - px, dy = pos[3 * b + 1] - py, dz = pos[3 * b + 2] - pz;
+        const long long dx = min_image(pos[3 * b] - px, nx * kFx, per & 1);
+        const long long dy = min_image(pos[3 * b + 1] - py, ny * kFx, per & 2);
+        const long long dz = pos[3 * b + 2] - pz;
         Real ss = 0, sa = 0;
         if (lds) {
-            voxel_walk(nx, ny, nz, px, py, pz, dx, dy, dz, false, [&](int x, int y, int z, long long num, long long den) {
+            voxel_walk(nx, ny, nz, per, px, py, pz, dx, dy, dz, false, [&](int x, int y, int z, long long num, long long den) {
                 const int xo = x - bx0, yo = y - by0, zo = z - bz0;
                 const Real dt = ratio<Real>(num, den);
                 if ((unsigned)xo < (unsigned)bw && (unsigned)yo < (unsigned)bh && (unsigned)zo < (unsigned)bd) {
                     const int t = xo + bw * (yo + bh * zo);
                     ss += (Real)bs[t] * dt;
                     sa += (Real)ba[t] * dt;
-                } else {  // outside the staged brick (cannot happen for segments between the box's end voxels)
+                } else {  // outside the staged brick (only a periodic segment, wrapped round the grid)
                     const long long g = x + (long long)nx * (y + (long long)ny * z);
                     ss += (Real)mu_s[g] * dt;
                     sa += (Real)mu_a[g] * dt;
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
                 return true;
             });
         } else {
-            voxel_walk(nx, ny, nz, px, py, pz, dx, dy, dz, false, [&](int x, int y, int z, long long num, long long den) {
+            voxel_walk(nx, ny, nz, per, px, py, pz, dx, dy, dz, false, [&](int x, int y, int z, long long num, long long den) {
                 const long long vox = x + (long long)nx * (y + (long long)ny * z);
                 const Real dt = ratio<Real>(num, den);
                 ss += (Real)mu_s[vox] * dt;
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
 // soon as the smallest wavelength optical depth (tau_s + smin tau_a) passes the
 // cutoff where exp(-tau) is zero in the working precision.
 template <class Real>
-__global__ __launch_bounds__(256) void k_march_sun(int N, int nx, int ny, int nz, const int *__restrict__ pos,
+__global__ __launch_bounds__(256) void k_march_sun(int N, int nx, int ny, int nz, int per, const int *__restrict__ pos,
                                                   long long sdx, long long sdy, long long sdz,
                                                   const float *__restrict__ mu_s, const float *__restrict__ mu_a,
                                                   Real len_scale, Real smin, Real cutoff, Real scale,
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(256) void k_march_sun(int N, int nx, int ny, int nz
     const Real L = sqrt((Real)(sdx * sdx + sdy * sdy + sdz * sdz)) * len_scale;
     const Real lim = cutoff / L;
     Real ss = 0, sa = 0;
-    voxel_walk(nx, ny, nz, pos[3 * l], pos[3 * l + 1], pos[3 * l + 2], sdx, sdy, sdz, true,
+    voxel_walk(nx, ny, nz, per, pos[3 * l], pos[3 * l + 1], pos[3 * l + 2], sdx, sdy, sdz, true,
                [&](int x, int y, int z, long long num, long long den) {
                    const long long vox = x + (long long)nx * (y + (long long)ny * z);
                    const Real dt = ratio<Real>(num, den);
@@ -186,7 +188,8 @@ __device__ int edge_tail(const long long *__restrict__ adj_ptr, int N, long long
     return lo;
 }
 
-__global__ __launch_bounds__(64) void k_trace(int kind, int N, int nx, int ny, int nz, const long long *__restrict__ adj_ptr,
+__global__ __launch_bounds__(64) void k_trace(int kind, int N, int nx, int ny, int nz, int per,
+                                             const long long *__restrict__ adj_ptr,
                                              const int *__restrict__ adj_idx, const int *__restrict__ pos,
                                              long long sdx, long long sdy, long long sdz, long long vdx,
                                              long long vdy, long long vdz, const long long *__restrict__ ids,
@@ -202,7 +205,9 @@ __global__ __launch_bounds__(64) void k_trace(int kind, int N, int nx, int ny, i
         const int j = adj_idx[id];
         const int a = min(l, j), b = max(l, j);
         px = pos[3 * a]; py = pos[3 * a + 1]; pz = pos[3 * a + 2];
-        dx = pos[3 * b] - px; dy = pos[3 * b + 1] - py; dz = pos[3 * b + 2] - pz;
+        dx = min_image(pos[3 * b] - px, nx * kFx, per & 1);
+        dy = min_image(pos[3 * b + 1] - py, ny * kFx, per & 2);
+        dz = pos[3 * b + 2] - pz;
         ray = false;
     } else if (kind == 1) {
         px = pos[3 * id]; py = pos[3 * id + 1]; pz = pos[3 * id + 2];
@@ -213,7 +218,7 @@ __global__ __launch_bounds__(64) void k_trace(int kind, int N, int nx, int ny, i
         dx = vdx; dy = vdy; dz = vdz;
     }
     int k = 0;
-    const int c = voxel_walk(nx, ny, nz, px, py, pz, dx, dy, dz, ray, [&](int x, int y, int z, long long num, long long den) {
+    const int c = voxel_walk(nx, ny, nz, per, px, py, pz, dx, dy, dz, ray, [&](int x, int y, int z, long long num, long long den) {
         if (k < cap) {
             vox_out[(long long)t * cap + k] = x + nx * (y + ny * z);
             dt_out[(long long)t * cap + k] = (double)num / (double)den;
@@ -230,8 +235,8 @@ template <class Real>
 void launch_march(Scene &s, hipStream_t st, float scale, int use_lds) {
     const Real len_scale = (Real)(s.voxel_m / 65536.0);
     const int nb = (s.N + kNodesPerBlock - 1) / kNodesPerBlock;
-    hipLaunchKernelGGL((k_march_edges<Real>), dim3(nb), dim3(kMarchThreads), 0, st, s.N, s.nx, s.ny, s.nz, s.adj_ptr,
-                       s.adj_idx, s.pos, s.mu_s, s.mu_a, len_scale, (Real)scale, (Real *)s.tau_s, (Real *)s.tau_a,
+    hipLaunchKernelGGL((k_march_edges<Real>), dim3(nb), dim3(kMarchThreads), 0, st, s.N, s.nx, s.ny, s.nz, s.periodic,
+                       s.adj_ptr, s.adj_idx, s.pos, s.mu_s, s.mu_a, len_scale, (Real)scale, (Real *)s.tau_s, (Real *)s.tau_a,
                        (Real *)s.T, use_lds);
     float smin = scale;
     if (s.n_lambda > 1) {
@@ -239,8 +244,8 @@ void launch_march(Scene &s, hipStream_t st, float scale, int use_lds) {
         for (float v : s.abs_scale) smin = v < smin ? v : smin;
     }
     const Real cutoff = sizeof(Real) == 4 ? (Real)104.0 : (Real)746.0;
-    hipLaunchKernelGGL((k_march_sun<Real>), dim3((s.N + 255) / 256), dim3(256), 0, st, s.N, s.nx, s.ny, s.nz, s.pos,
-                       (long long)s.sun[0], (long long)s.sun[1], (long long)s.sun[2], s.mu_s, s.mu_a, len_scale,
+    hipLaunchKernelGGL((k_march_sun<Real>), dim3((s.N + 255) / 256), dim3(256), 0, st, s.N, s.nx, s.ny, s.nz, s.periodic,
+                       s.pos, (long long)s.sun[0], (long long)s.sun[1], (long long)s.sun[2], s.mu_s, s.mu_a, len_scale,
                        (Real)smin, cutoff, (Real)scale, (Real *)s.tsun_s, (Real *)s.tsun_a, (Real *)s.Tsun);
 }
 
@@ -252,7 +257,7 @@ void launch_node_weights(Scene &s, hipStream_t st, float scale) {
 
 void launch_trace(Scene &s, hipStream_t st, int kind, const long long *ids, int n, int cap, int *vox, double *dt,
                   int *count) {
-    hipLaunchKernelGGL(k_trace, dim3((n + 63) / 64), dim3(64), 0, st, kind, s.N, s.nx, s.ny, s.nz, s.adj_ptr, s.adj_idx,
+    hipLaunchKernelGGL(k_trace, dim3((n + 63) / 64), dim3(64), 0, st, kind, s.N, s.nx, s.ny, s.nz, s.periodic, s.adj_ptr, s.adj_idx,
                        s.pos, (long long)s.sun[0], (long long)s.sun[1], (long long)s.sun[2], (long long)s.view[0],
                        (long long)s.view[1], (long long)s.view[2], ids, n, cap, vox, dt, count);
 }

@@ -74,7 +74,8 @@ __global__ __launch_bounds__(64) void k_qbuild(
     const int *__restrict__ pos, const double *__restrict__ lat, const double *__restrict__ tab, int NF, int n_phase,
     const float *__restrict__ frac, double sun_x, double sun_y, double sun_z, Real mu0, const Real *__restrict__ T,
     const Real *__restrict__ rho, const Real *__restrict__ Tsun, const long long *__restrict__ nodeoff,
-    BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun, int group) {
+    BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun, int group, int per, long long wx,
+    long long wy) {
 #pragma clang fp contract(off)
     __shared__ double smem[kQLds];
     double *sx = smem, *sy = smem + 64, *sz = smem + 128;
@@ -92,8 +93,8 @@ __global__ __launch_bounds__(64) void k_qbuild(
 
     if (lane < d) {
         const int j = adj_idx[off + lane];
-        const long long Dx = (long long)pos[3 * j] - pos[3 * l];
-        const long long Dy = (long long)pos[3 * j + 1] - pos[3 * l + 1];
+        const long long Dx = min_image((long long)pos[3 * j] - pos[3 * l], wx, per & 1);
+        const long long Dy = min_image((long long)pos[3 * j + 1] - pos[3 * l + 1], wy, per & 2);
         const long long Dz = (long long)pos[3 * j + 2] - pos[3 * l + 2];
         const double nrm = sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
         sx[lane] = (double)Dx / nrm;
@@ -222,7 +223,8 @@ __global__ __launch_bounds__(64) void k_qcolour(
     const int *__restrict__ pos, const double *__restrict__ lat, const double *__restrict__ tab, int NF, int n_phase,
     const float *__restrict__ frac, double sun_x, double sun_y, double sun_z, Real mu0, const Real *__restrict__ T,
     const Real *__restrict__ rho, const Real *__restrict__ Tsun, const long long *__restrict__ nodeoff,
-    BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun, const int *__restrict__ hull) {
+    BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun, const int *__restrict__ hull, int per,
+    long long wx, long long wy) {
 #pragma clang fp contract(off)
     __shared__ double sx[64], sy[64], sz[64], lt[3][128];
     __shared__ unsigned long long wq[128], bins[64];
@@ -236,8 +238,8 @@ __global__ __launch_bounds__(64) void k_qcolour(
     const bool surf = l >= nvox;
     if (lane < d) {
         const int j = adj_idx[off + lane];
-        const long long Dx = (long long)pos[3 * j] - pos[3 * l];
-        const long long Dy = (long long)pos[3 * j + 1] - pos[3 * l + 1];
+        const long long Dx = min_image((long long)pos[3 * j] - pos[3 * l], wx, per & 1);
+        const long long Dy = min_image((long long)pos[3 * j + 1] - pos[3 * l + 1], wy, per & 2);
         const long long Dz = (long long)pos[3 * j + 2] - pos[3 * l + 2];
         const double nrm = sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
         sx[lane] = (double)Dx / nrm;
@@ -383,12 +385,14 @@ void launch_qbuild(Scene &s, hipStream_t st, int write_q) {
             hipLaunchKernelGGL((k_qcolour<Real, float, true>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
                                s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
                                s.sun_in[2], (Real)s.mu0, (const Real *)nullptr, (const Real *)nullptr,
-                               (const Real *)nullptr, s.nodeoff, s.q, (Real *)nullptr, s.qsun, s.hull);
+                               (const Real *)nullptr, s.nodeoff, s.q, (Real *)nullptr, s.qsun, s.hull, s.periodic,
+                               (long long)s.nx * kFx, (long long)s.ny * kFx);
         } else {
             hipLaunchKernelGGL((k_qcolour<Real, Real, false>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
                                s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
                                s.sun_in[2], (Real)s.mu0, (const Real *)s.T, (const Real *)s.rho,
-                               (const Real *)s.Tsun, s.nodeoff, (Real *)s.val, (Real *)s.S, s.qsun, s.hull);
+                               (const Real *)s.Tsun, s.nodeoff, (Real *)s.val, (Real *)s.S, s.qsun, s.hull, s.periodic,
+                               (long long)s.nx * kFx, (long long)s.ny * kFx);
         }
         return;
     }
@@ -396,12 +400,14 @@ void launch_qbuild(Scene &s, hipStream_t st, int write_q) {
         hipLaunchKernelGGL((k_qbuild<Real, float, true>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
                            s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
                            s.sun_in[2], (Real)s.mu0, (const Real *)nullptr, (const Real *)nullptr,
-                           (const Real *)nullptr, s.nodeoff, s.q, (Real *)nullptr, s.qsun, group);
+                           (const Real *)nullptr, s.nodeoff, s.q, (Real *)nullptr, s.qsun, group, s.periodic, (long long)s.nx * kFx,
+                           (long long)s.ny * kFx);
     } else {
         hipLaunchKernelGGL((k_qbuild<Real, Real, false>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
                            s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
                            s.sun_in[2], (Real)s.mu0, (const Real *)s.T, (const Real *)s.rho, (const Real *)s.Tsun,
-                           s.nodeoff, (Real *)s.val, (Real *)s.S, s.qsun, group);
+                           s.nodeoff, (Real *)s.val, (Real *)s.S, s.qsun, group, s.periodic, (long long)s.nx * kFx,
+                           (long long)s.ny * kFx);
     }
 }
 

@@ -15,7 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsgrt.so")
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 SG_OK, SG_E_INVALID, SG_E_NOMEM, SG_E_DEVICE, SG_E_NOCONV, SG_E_BUSY, SG_E_ABI, SG_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 SG_FP32, SG_FP64 = 0, 1
@@ -38,7 +38,8 @@ class SceneDesc(C.Structure):
                 ("surf_albedo", C.c_void_p), ("sun_dir", C.c_int32 * 3), ("view_dir", C.c_int32 * 3),
                 ("n_fib", C.c_int32), ("node_weight_mode", C.c_int32), ("n_lambda", C.c_int32),
                 ("abs_scale", C.c_void_p), ("phase_kind", C.c_void_p), ("phase_lut_n", C.c_int32),
-                ("phase_lut", C.c_void_p), ("sigma_mode", C.c_int32)]
+                ("phase_lut", C.c_void_p), ("sigma_mode", C.c_int32),
+                ("periodic", C.c_int32)]
 
 
 class GraphDesc(C.Structure):
@@ -175,6 +176,7 @@ def make_desc(scene, keep: list) -> SceneDesc:
     d.phase_lut = None if lut is None else _ptr(arr(lut, np.float64))
     d.phase_lut_n = 0 if lut is None else int(np.asarray(lut).shape[-1])
     d.sigma_mode = int(getattr(scene, "sigma_mode", 0))
+    d.periodic = int(getattr(scene, "periodic", 0))
     abs_scale = getattr(scene, "abs_scale", None)
     if abs_scale is None:
         d.n_lambda = 1
