@@ -40,6 +40,9 @@ def make_workload(name: str):
         return scenes.make_plain(), "plain-8x8x8 (seed 1), 1 wavelength"
     if name == "batched":
         return scenes.make_batched(), "batched plume-96x96x32 (seed 4), 64 wavelengths"
+    if name == "slab":
+        return (scenes.make_plume(periodic=3),
+                "plume-64x64x32 (seed 2) repeating in x and y (periodic slab), 1 wavelength")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -309,7 +312,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plume")
+    ap.add_argument("--workload", default="plume",
+                    help="plume | cloud | batched | plain | slab (periodic plume) | served | graph | nfib | copy")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--served", type=int, default=40, help="requests of the served stream (workload served)")

@@ -27,15 +27,16 @@ __device__ __forceinline__ double theta_mix(const PhaseSet &pm, const float *__r
 }
 
 // One wavefront per node: lane m takes in-edge m's term, then a fixed-order butterfly sum.
-template <class Real>
+template <class Real, bool kPer>
 __global__ __launch_bounds__(256) void k_node_J(int N, int nvox, const long long *__restrict__ adj_ptr,
                                                const int *__restrict__ adj_idx, const int *__restrict__ rev,
                                                const int *__restrict__ pos, const Real *__restrict__ T,
                                                const Real *__restrict__ Tsun, const double *__restrict__ phi,
                                                PhaseSet pm, const float *__restrict__ frac, double sx, double sy,
                                                double sz, double vx, double vy, double vz, double mu0,
-                                               int multiple, int per, long long wx, long long wy,
+                                               int multiple, int per_arg, long long wx, long long wy,
                                                double *__restrict__ J) {
+    const int per = kPer ? per_arg : 0;
     const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (l >= N) return;
@@ -119,10 +120,11 @@ __global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, int per, 
 template <class Real>
 void launch_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance) {
     const PhaseSet pm = phase_set(s);
-    hipLaunchKernelGGL((k_node_J<Real>), dim3((s.N + 3) / 4), dim3(256), 0, st, s.N, s.nvox, s.adj_ptr, s.adj_idx,
-                       s.rev, s.pos, (const Real *)s.T, (const Real *)s.Tsun, phi, pm, s.frac, s.sun_in[0],
-                       s.sun_in[1], s.sun_in[2], s.view_u[0], s.view_u[1], s.view_u[2], s.mu0,
-                       scatter_order == 1 ? 0 : 1, s.periodic, (long long)s.nx * kFx, (long long)s.ny * kFx, s.J);
+    const auto node_J = s.periodic ? k_node_J<Real, true> : k_node_J<Real, false>;
+    hipLaunchKernelGGL(node_J, dim3((s.N + 3) / 4), dim3(256), 0, st, s.N, s.nvox, s.adj_ptr, s.adj_idx, s.rev, s.pos,
+                       (const Real *)s.T, (const Real *)s.Tsun, phi, pm, s.frac, s.sun_in[0], s.sun_in[1], s.sun_in[2],
+                       s.view_u[0], s.view_u[1], s.view_u[2], s.mu0, scatter_order == 1 ? 0 : 1, s.periodic,
+                       (long long)s.nx * kFx, (long long)s.ny * kFx, s.J);
     const double fx = s.voxel_m / 65536.0;
     const double lv = sqrt((double)s.view[0] * s.view[0] + (double)s.view[1] * s.view[1] + (double)s.view[2] * s.view[2]) * fx;
     const double ls = sqrt((double)s.sun[0] * s.sun[0] + (double)s.sun[1] * s.sun[1] + (double)s.sun[2] * s.sun[2]) * fx;

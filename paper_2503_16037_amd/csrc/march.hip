@@ -26,11 +26,13 @@ __device__ __forceinline__ void node_voxel(const int *__restrict__ pos, int l, i
     vz = pos[3 * l + 2] >> 16;
 }
 
-template <class Real>
+// kPer = false: a bounded grid (per is ignored, and the periodic branches fold away)
+template <class Real, bool kPer>
 __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
-    int N, int nx, int ny, int nz, int per, const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx,
+    int N, int nx, int ny, int nz, int per_arg, const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx,
     const int *__restrict__ pos, const float *__restrict__ mu_s, const float *__restrict__ mu_a, Real len_scale,
     Real scale, Real *__restrict__ tau_s, Real *__restrict__ tau_a, Real *__restrict__ T, int use_lds) {
+    const int per = kPer ? per_arg : 0;
     __shared__ float bs[kBrickCap];
     __shared__ float ba[kBrickCap];
     __shared__ long long sptr[kNodesPerBlock + 1];
@@ -131,13 +133,14 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
 // Node -> sun optical depth, both channels, to the grid exit.  A lane stops as
 // soon as the smallest wavelength optical depth (tau_s + smin tau_a) passes the
 // cutoff where exp(-tau) is zero in the working precision.
-template <class Real>
-__global__ __launch_bounds__(256) void k_march_sun(int N, int nx, int ny, int nz, int per, const int *__restrict__ pos,
+template <class Real, bool kPer>
+__global__ __launch_bounds__(256) void k_march_sun(int N, int nx, int ny, int nz, int per_arg, const int *__restrict__ pos,
                                                   long long sdx, long long sdy, long long sdz,
                                                   const float *__restrict__ mu_s, const float *__restrict__ mu_a,
                                                   Real len_scale, Real smin, Real cutoff, Real scale,
                                                   Real *__restrict__ ts, Real *__restrict__ ta,
                                                   Real *__restrict__ Tsun) {
+    const int per = kPer ? per_arg : 0;
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= N) return;
     const Real L = sqrt((Real)(sdx * sdx + sdy * sdy + sdz * sdz)) * len_scale;
@@ -235,8 +238,10 @@ template <class Real>
 void launch_march(Scene &s, hipStream_t st, float scale, int use_lds) {
     const Real len_scale = (Real)(s.voxel_m / 65536.0);
     const int nb = (s.N + kNodesPerBlock - 1) / kNodesPerBlock;
-    hipLaunchKernelGGL((k_march_edges<Real>), dim3(nb), dim3(kMarchThreads), 0, st, s.N, s.nx, s.ny, s.nz, s.periodic,
-                       s.adj_ptr, s.adj_idx, s.pos, s.mu_s, s.mu_a, len_scale, (Real)scale, (Real *)s.tau_s, (Real *)s.tau_a,
+    // the bounded-grid instantiations carry no periodic branches
+    const auto edges = s.periodic ? k_march_edges<Real, true> : k_march_edges<Real, false>;
+    hipLaunchKernelGGL(edges, dim3(nb), dim3(kMarchThreads), 0, st, s.N, s.nx, s.ny, s.nz, s.periodic, s.adj_ptr,
+                       s.adj_idx, s.pos, s.mu_s, s.mu_a, len_scale, (Real)scale, (Real *)s.tau_s, (Real *)s.tau_a,
                        (Real *)s.T, use_lds);
     float smin = scale;
     if (s.n_lambda > 1) {
@@ -244,8 +249,9 @@ void launch_march(Scene &s, hipStream_t st, float scale, int use_lds) {
         for (float v : s.abs_scale) smin = v < smin ? v : smin;
     }
     const Real cutoff = sizeof(Real) == 4 ? (Real)104.0 : (Real)746.0;
-    hipLaunchKernelGGL((k_march_sun<Real>), dim3((s.N + 255) / 256), dim3(256), 0, st, s.N, s.nx, s.ny, s.nz, s.periodic,
-                       s.pos, (long long)s.sun[0], (long long)s.sun[1], (long long)s.sun[2], s.mu_s, s.mu_a, len_scale,
+    const auto sun = s.periodic ? k_march_sun<Real, true> : k_march_sun<Real, false>;
+    hipLaunchKernelGGL(sun, dim3((s.N + 255) / 256), dim3(256), 0, st, s.N, s.nx, s.ny, s.nz, s.periodic, s.pos,
+                       (long long)s.sun[0], (long long)s.sun[1], (long long)s.sun[2], s.mu_s, s.mu_a, len_scale,
                        (Real)smin, cutoff, (Real)scale, (Real *)s.tsun_s, (Real *)s.tsun_a, (Real *)s.Tsun);
 }
 
@@ -257,8 +263,8 @@ void launch_node_weights(Scene &s, hipStream_t st, float scale) {
 
 void launch_trace(Scene &s, hipStream_t st, int kind, const long long *ids, int n, int cap, int *vox, double *dt,
                   int *count) {
-    hipLaunchKernelGGL(k_trace, dim3((n + 63) / 64), dim3(64), 0, st, kind, s.N, s.nx, s.ny, s.nz, s.periodic, s.adj_ptr, s.adj_idx,
-                       s.pos, (long long)s.sun[0], (long long)s.sun[1], (long long)s.sun[2], (long long)s.view[0],
+    hipLaunchKernelGGL(k_trace, dim3((n + 63) / 64), dim3(64), 0, st, kind, s.N, s.nx, s.ny, s.nz, s.periodic,
+                       s.adj_ptr, s.adj_idx, s.pos, (long long)s.sun[0], (long long)s.sun[1], (long long)s.sun[2], (long long)s.view[0],
                        (long long)s.view[1], (long long)s.view[2], ids, n, cap, vox, dt, count);
 }
 

@@ -392,8 +392,11 @@ def cloud_field(rng, nx, ny, nz, dx, kmax=0.05):
 # --------------------------------------------------------------------------------------
 
 def _finish(name, seed, nx, ny, nz, dx, mu_s, mu_a, hg_g, phase_frac, pos, R, albedo,
-            sza, saa, vza, vaa, surface=True, n_fib=100, abs_scale=None):
-    adj_ptr, adj_idx = radius_graph(pos, nx, ny, nz, R, surface=surface)
+            sza, saa, vza, vaa, surface=True, n_fib=100, abs_scale=None, periodic=0):
+    if periodic:
+        adj_ptr, adj_idx = periodic_radius_graph(pos, nx, ny, nz, R, periodic, surface=surface)
+    else:
+        adj_ptr, adj_idx = radius_graph(pos, nx, ny, nz, R, surface=surface)
     return Scene(
         name=name, seed=seed, nx=nx, ny=ny, nz=nz, voxel_m=float(dx),
         mu_s=np.ascontiguousarray(mu_s, dtype=np.float32),
@@ -405,7 +408,7 @@ def _finish(name, seed, nx, ny, nz, dx, mu_s, mu_a, hg_g, phase_frac, pos, R, al
         surf_albedo=np.ascontiguousarray(albedo, dtype=np.float32),
         sun_dir=direction_fx(sza, saa), view_dir=direction_fx(vza, vaa),
         n_fib=n_fib, abs_scale=None if abs_scale is None else np.asarray(abs_scale, np.float32),
-        angles=(sza, saa, vza, vaa))
+        angles=(sza, saa, vza, vaa), periodic=periodic)
 
 
 def make_plain(seed=1, nx=8, ny=8, nz=8, dx=100.0, R=2.0):
@@ -421,9 +424,10 @@ def make_plain(seed=1, nx=8, ny=8, nz=8, dx=100.0, R=2.0):
                    30.0, 30.0, 0.0, 0.0)
 
 
-def make_plume(seed=2, nx=64, ny=64, nz=32, dx=50.0, R=1.8, name=None, n_lambda=0):
+def make_plume(seed=2, nx=64, ny=64, nz=32, dx=50.0, R=1.8, name=None, n_lambda=0, periodic=0):
     """Emission plume over a Rayleigh-like background; albedo 0.95, g 0.75,
-    surface albedo U[0.1, 0.3], SZA 50 / SAA 30, VZA 20 / VAA 120."""
+    surface albedo U[0.1, 0.3], SZA 50 / SAA 30, VZA 20 / VAA 120.  periodic: the grid
+    repeats along x (bit 0) and/or y (bit 1), the graph searches across the period."""
     rng = np.random.default_rng(seed)
     pos = jittered_positions(rng, nx, ny, nz)
     mu_e = rayleigh_background(nx, ny, nz, dx) + plume_field(rng, nx, ny, nz, dx)
@@ -431,8 +435,9 @@ def make_plume(seed=2, nx=64, ny=64, nz=32, dx=50.0, R=1.8, name=None, n_lambda=
     abs_scale = None
     if n_lambda > 0:
         abs_scale = 10.0 ** rng.uniform(-1.0, 1.0, size=n_lambda)
-    return _finish(name or f"plume-{nx}x{ny}x{nz}", seed, nx, ny, nz, dx, 0.95 * mu_e, 0.05 * mu_e,
-                   [0.75], None, pos, R, alb, 50.0, 30.0, 20.0, 120.0, abs_scale=abs_scale)
+    return _finish(name or f"plume-{nx}x{ny}x{nz}" + (f"-p{periodic}" if periodic else ""), seed, nx, ny, nz, dx,
+                   0.95 * mu_e, 0.05 * mu_e, [0.75], None, pos, R, alb, 50.0, 30.0, 20.0, 120.0,
+                   abs_scale=abs_scale, periodic=periodic)
 
 
 def make_cloud(seed=3, nx=128, ny=128, nz=48, dx=50.0, R=1.8, name=None, n_lambda=0):

@@ -162,3 +162,18 @@ def test_periodic_scene_checks(ctx):
         sgrt.Scene(ctx, half)
     with sgrt.Scene(ctx, dataclasses.replace(half, periodic=2)) as g:  # an ordinary pair along x
         g.solve(precision="fp64")
+
+
+def test_periodic_plume_full_size(ctx):
+    """The plume scene at its full size (64x64x32, 3.1 M couplings) repeating in x and y:
+    every pixel within the FP32 bar of the oracle."""
+    from paper_2503_16037_amd import sgrt
+    sc = scenes.make_plume(periodic=3)
+    say("periodic plume", sc.name, sc.n_edges)
+    ref = oracle.run(sc, want_matrix=False)["radiance"]
+    with sgrt.Scene(ctx, sc) as g:
+        rad, info = g.solve(precision="fp32")
+        assert info["converged"] == 1
+        err = rel_err(rad, ref)
+        say("  max pixel rel err", err.max())
+        assert err.max() < 1e-4
