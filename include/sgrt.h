@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define SG_ABI_VERSION 5u
+#define SG_ABI_VERSION 6u
 
 typedef int32_t sg_status;
 enum {
@@ -210,6 +210,16 @@ typedef struct sg_solve_opts {
                               solve on, the autotuner's).  A set tile uses the default grid.
                               The tile does not change any result bit.  Ignored for one
                               wavelength. */
+    /* Warm start of the solve of Eq. 8: an initial phi, e.g. a previous solve's (the layout
+       of sg_export_vector's SG_VEC_PHI: [n_lambda][E] doubles in the scene's edge order),
+       in host memory or, with warm_start_on_device = 1, device memory on the scene's
+       device; borrowed for the call.  The solve starts its FP64 iterative refinement from
+       it (residual r = S - (I - K) phi, correction sweeps, repeat) instead of from the
+       Neumann series of phi = 0, so a good start saves sweeps; the stopping rule and the
+       bar are unchanged.  Host values must be finite (SG_E_INVALID otherwise).  NULL: a
+       cold start.  Not accepted in sg_server_opts.solve (SG_E_INVALID). */
+    const double *warm_start;
+    int32_t warm_start_on_device;
 } sg_solve_opts;
 enum { SG_NO_GRAPHS = 1, SG_NO_AUTOTUNE = 2 };
 

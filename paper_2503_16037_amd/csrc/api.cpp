@@ -395,6 +395,35 @@ sg_status read_scalars(Scene &s, hipStream_t st, const double *dev, double *host
     return SG_OK;
 }
 
+// The warm start [n_lambda][E] into x64 ([E] for one wavelength, [E][n_lambda] for
+// several; staged through r64, which the first residual overwrites).
+sg_status load_warm_start(Scene &s, const sg_solve_opts &o, hipStream_t st) {
+    Ctx *ctx = s.ctx;
+    const size_t n = (size_t)s.E * s.n_lambda;
+    if (!o.warm_start_on_device)
+        for (size_t k = 0; k < n; ++k)
+            if (!std::isfinite(o.warm_start[k])) return fail(SG_E_INVALID, "warm_start values must be finite");
+    const hipMemcpyKind kind = o.warm_start_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    double *dst = s.n_lambda > 1 ? s.r64 : s.x64;
+    SG_HIP(hipMemcpyAsync(dst, o.warm_start, sizeof(double) * n, kind, st));
+    if (s.n_lambda > 1) launch_lam_to_edge_major(s.r64, s.x64, s.n_lambda, s.E, st);
+    return SG_OK;
+}
+
+// Stop of a correction solve (I - K) d = r, as the L1 update relative to the first one.
+// 1e-5 in general; the first two corrections of a warm start, whose residual rel may be
+// far below 1, only need d to about 0.1 rtol / rel (never coarser than 1e-2): the per-edge
+// FP64 residual that follows decides convergence either way.
+inline double correction_stop(bool warm, int it, double rel, double rtol) {
+    if (!warm || it >= 2 || !(rel > 0)) return 1e-5;
+    return std::min(1e-2, std::max(1e-5, 0.1 * rtol / rel));
+}
+
+// A warm start is kept only if it is better than phi = 0: its per-edge relative residual
+// max |r_e| / |phi_e| must be at most 1/2 (and finite), else the solve starts cold.  The
+// correction right-hand side r / rel is then at most |phi| per edge, inside the FP32 range.
+constexpr double kWarmKeep = 0.5;
+
 struct SolveStats {
     int sweeps = 0, refinements = 0, gmres_used = 0, converged = 0;
     double rel = 0.0;
@@ -584,22 +613,39 @@ sg_status solve_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Exec &t
     // a zero source needs no special case: every measure is zero from the first sweep
     launch_fill<double>(s.x64, 0.0, E, st);
     int use_gmres = o.solver == SG_SOLVER_GMRES;
+    bool warm = false, have_r = false;
+    if (o.warm_start) {
+        SG_TRY(load_warm_start(s, o, st));
+        launch_residual64<Real>(s, st, S, s.x64, s.r64, s.scal);
+        ++ss.sweeps;
+        ++ss.refinements;
+        double m2[2];
+        SG_TRY(read_scalars(s, st, s.scal, m2, 2));
+        ss.rel = m2[1];
+        warm = have_r = ss.rel <= kWarmKeep;
+        if (!warm) launch_fill<double>(s.x64, 0.0, E, st);
+    }
     if (!use_gmres) {
         Real *xa = (Real *)s.x, *xb = (Real *)s.y;
         int stalled = 0;
         // per-edge relative updates settle at a few units of rounding: never ask for less
         const double floor_rel = sizeof(Real) == 4 ? 4e-6 : 1e-14;
-        SG_TRY(neumann<Real>(s, st, tm, S, xa, xb, 1, std::max(0.3 * rtol, floor_rel), max_sweeps, ss, stalled));
-        launch_to64<Real>(xa, s.x64, E, st);
+        if (!warm) {  // a kept warm start goes straight to the refinement below
+            SG_TRY(neumann<Real>(s, st, tm, S, xa, xb, 1, std::max(0.3 * rtol, floor_rel), max_sweeps, ss, stalled));
+            launch_to64<Real>(xa, s.x64, E, st);
+        }
         if (stalled && o.solver == SG_SOLVER_AUTO) use_gmres = 1;
         // FP64 residual and iterative refinement
         for (int it = 0; !use_gmres && it < 12; ++it) {
-            launch_residual64<Real>(s, st, S, s.x64, s.r64, s.scal);
-            ++ss.sweeps;
-            ++ss.refinements;
-            double m2[2];
-            SG_TRY(read_scalars(s, st, s.scal, m2, 2));
-            ss.rel = m2[1];  // max over edges of |r| / |x|
+            if (!have_r) {
+                launch_residual64<Real>(s, st, S, s.x64, s.r64, s.scal);
+                ++ss.sweeps;
+                ++ss.refinements;
+                double m2[2];
+                SG_TRY(read_scalars(s, st, s.scal, m2, 2));
+                ss.rel = m2[1];  // max over edges of |r| / |x|
+            }
+            have_r = false;
             if (sg_log()) fprintf(stderr, "[sgrt] FP64 residual after %d sweeps: %.3e\n", ss.sweeps, ss.rel);
             if (ss.rel <= rtol) { ss.converged = 1; break; }
             if (ss.sweeps >= max_sweeps || !std::isfinite(ss.rel)) break;
@@ -609,7 +655,8 @@ sg_status solve_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Exec &t
             Real *crhs = (Real *)s.c_rhs, *c0 = (Real *)s.c_a, *c1 = (Real *)s.c_b;
             launch_scaled_to_real<Real>(s.r64, sc, crhs, E, st);
             int stalled2 = 0;
-            SG_TRY(neumann<Real>(s, st, tm, crhs, c0, c1, 0, std::max(1e-5, floor_rel), max_sweeps, ss, stalled2));
+            SG_TRY(neumann<Real>(s, st, tm, crhs, c0, c1, 0, std::max(correction_stop(warm, it, ss.rel, rtol), floor_rel),
+                                 max_sweeps, ss, stalled2));
             launch_axpy_real_to64<Real>(s.x64, c0, 1.0 / sc, E, st);
             if (stalled2 && o.solver == SG_SOLVER_AUTO) use_gmres = 1;
         }
@@ -813,25 +860,40 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
     const int grid = spmm_grid(s, st, xa, xb, tm.autotune, o.lambda_tile);  // sets s.tile
     const int rgrid = batched_groups(s);  // FP64 pass: the tile's default grid
     int stalled = 0;
-    // per-edge relative updates settle at a few FP32 rounding units: never ask for less
-    SG_TRY(neumann_batched(s, st, tm, grid, nullptr, xa, xb, 1, std::max(0.3 * rtol, 4e-6), max_sweeps, ss,
-                           stalled));
-    launch_f32_to_64(xa, s.x64, n, st);
     std::vector<double> m2((size_t)2 * nl), sc(nl);
     double *d_sc = s.lam_buf;  // [nl]
-    for (int it = 0; it < 10; ++it) {
+    // FP64 residual of x64 for every wavelength: the worst per-edge relative residual, and
+    // the scales r / rel (at most |x| per edge: well inside the FP32 range)
+    auto residual = [&](double &worst) -> sg_status {
         launch_bresidual64(s, st, rgrid, s.x64, s.r64);
         launch_measures(s, nl, s.lam_buf + nl, st);  // [nl][2]
         ++ss.sweeps;
         ++ss.refinements;
         SG_TRY(read_scalars(s, st, s.lam_buf + nl, m2.data(), 2 * nl));
-        double worst = 0.0;
+        worst = 0.0;
         for (int k = 0; k < nl; ++k) {
             const double rel = m2[2 * k + 1];  // max over edges of |r| / |x|
             worst = std::max(worst, std::isfinite(rel) ? rel : HUGE_VAL);
-            // r / rel is at most |x| per edge: well inside the FP32 range
             sc[k] = rel > 0 ? 1.0 / rel : 1.0;
         }
+        return SG_OK;
+    };
+    bool warm = false, have_r = false;
+    double worst = 0.0;
+    if (o.warm_start) {  // kept if better than zero for every wavelength
+        SG_TRY(load_warm_start(s, o, st));
+        SG_TRY(residual(worst));
+        warm = have_r = worst <= kWarmKeep;
+    }
+    if (!warm) {
+        // per-edge relative updates settle at a few FP32 rounding units: never ask for less
+        SG_TRY(neumann_batched(s, st, tm, grid, nullptr, xa, xb, 1, std::max(0.3 * rtol, 4e-6), max_sweeps, ss,
+                               stalled));
+        launch_f32_to_64(xa, s.x64, n, st);
+    }
+    for (int it = 0; it < 10; ++it) {
+        if (!have_r) SG_TRY(residual(worst));
+        have_r = false;
         ss.rel = worst;
         if (sg_log()) fprintf(stderr, "[sgrt] FP64 residual after %d sweeps: worst relative %.3e\n", ss.sweeps, worst);
         if (worst <= rtol) { ss.converged = 1; break; }
@@ -840,7 +902,8 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
         launch_lam_scale_to_f32(s.r64, d_sc, nl, s.bS, n, st);
         float *ca = s.bx, *cb = s.by;
         int st2 = 0;
-        SG_TRY(neumann_batched(s, st, tm, grid, s.bS, ca, cb, 0, 1e-5, max_sweeps, ss, st2));
+        SG_TRY(neumann_batched(s, st, tm, grid, s.bS, ca, cb, 0, correction_stop(warm, it, worst, rtol), max_sweeps,
+                               ss, st2));
         launch_lam_axpy(s.x64, ca, d_sc, nl, n, st);
         if (st2) stalled = 1;
     }
@@ -1222,8 +1285,11 @@ sg_status check_opts(const sg_solve_opts *opts, sg_solve_opts &o) {
     if (o.scatter_order != 0 && o.scatter_order != 1) return fail(SG_E_INVALID, "scatter_order must be 0 or 1");
     if (o.lambda_tile != 0 && o.lambda_tile != 8 && o.lambda_tile != 16 && o.lambda_tile != 32 && o.lambda_tile != 64)
         return fail(SG_E_INVALID, "lambda_tile must be 0, 8, 16, 32 or 64");
+    if (o.warm_start_on_device != 0 && o.warm_start_on_device != 1)
+        return fail(SG_E_INVALID, "warm_start_on_device must be 0 or 1");
     return SG_OK;
 }
+
 
 uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st) {
     int64_t N, E, nnz;

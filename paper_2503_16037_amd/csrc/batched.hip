@@ -359,6 +359,16 @@ __global__ void k_lam_axpy(double *__restrict__ x, const float *__restrict__ d, 
         x[i] += (double)d[i] / sc[i % nl];
 }
 
+// [nl][E] -> [E][nl] (edge-major, wavelength fastest): coalesced writes
+__global__ __launch_bounds__(256) void k_lam_to_edge_major(const double *__restrict__ src, double *__restrict__ dst,
+                                                          int nl, long long E) {
+    const long long n = E * nl;
+    for (long long t = blockIdx.x * 256LL + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
+        const long long e = t / nl, k = t - e * nl;
+        dst[t] = src[k * E + e];
+    }
+}
+
 __global__ void k_f32_to_64(const float *__restrict__ a, double *__restrict__ b, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         b[i] = (double)a[i];
@@ -570,6 +580,10 @@ void launch_lam_scale_to_f32(const double *a, const double *sc, int nl, float *b
 
 void launch_lam_axpy(double *x, const float *d, const double *sc, int nl, long long n, hipStream_t st) {
     hipLaunchKernelGGL(k_lam_axpy, dim3(grid_for(n)), dim3(256), 0, st, x, d, sc, nl, n);
+}
+
+void launch_lam_to_edge_major(const double *src, double *dst, int nl, long long E, hipStream_t st) {
+    hipLaunchKernelGGL(k_lam_to_edge_major, dim3(grid_for(E * nl)), dim3(256), 0, st, src, dst, nl, E);
 }
 
 void launch_f32_to_64(const float *a, double *b, long long n, hipStream_t st) {

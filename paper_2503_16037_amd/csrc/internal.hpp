@@ -263,6 +263,7 @@ void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, d
 void launch_lam_scale_to_f32(const double *a, const double *sc, int nl, float *b, long long n, hipStream_t st);
 void launch_lam_axpy(double *x, const float *d, const double *sc, int nl, long long n, hipStream_t st);
 void launch_f32_to_64(const float *a, double *b, long long n, hipStream_t st);
+void launch_lam_to_edge_major(const double *src, double *dst, int nl, long long E, hipStream_t st);
 void launch_fill_f32(float *a, long long n, hipStream_t st);
 void launch_batched_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance);
 

@@ -212,6 +212,10 @@ sg_status sg_server_create(sg_ctx *ctx_, const sg_server_opts *opts, sg_server *
     sg_solve_opts so;
     sg_status cs = check_opts(&opts->solve, so);
     if (cs != SG_OK) return cs;
+    if (so.warm_start) {
+        set_error("a warm start belongs to one scene: not accepted in the server's solve options");
+        return SG_E_INVALID;
+    }
     std::unique_ptr<sg_server> s(new sg_server());
     s->ctx = ctx;
     s->opts = *opts;

@@ -15,7 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsgrt.so")
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 SG_OK, SG_E_INVALID, SG_E_NOMEM, SG_E_DEVICE, SG_E_NOCONV, SG_E_BUSY, SG_E_ABI, SG_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 SG_FP32, SG_FP64 = 0, 1
@@ -61,7 +61,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("precision", C.c_int32), ("solver", C.c_int32), ("rtol", C.c_double),
                 ("max_sweeps", C.c_int32), ("gmres_restart", C.c_int32), ("scatter_order", C.c_int32),
                 ("build_col_idx", C.c_int32), ("timing", C.c_int32), ("flags", C.c_int32),
-                ("lambda_tile", C.c_int32)]
+                ("lambda_tile", C.c_int32), ("warm_start", C.c_void_p), ("warm_start_on_device", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -269,10 +269,23 @@ class Scene:
     def __exit__(self, *a):
         self.close()
 
-    def solve(self, out=None, stream=None, allow_noconv=False, **opts):
+    def solve(self, out=None, stream=None, allow_noconv=False, warm_start=None, **opts):
         """Solve; returns (radiance, info).  out: None (host numpy result) or a device
-        tensor of n_lambda * ny * nx float64 (radiance written in place)."""
+        tensor of n_lambda * ny * nx float64 (radiance written in place).  warm_start: an
+        initial phi of n_lambda * E float64 values ([n_lambda][E], as export_vector("phi")),
+        a host array or a device tensor."""
         o = make_opts(**opts)
+        if warm_start is not None:
+            n = self.n_lambda * self.sizes["n_edges"]
+            if hasattr(warm_start, "data_ptr"):
+                if warm_start.numel() != n or str(warm_start.dtype) != "torch.float64" or not warm_start.is_contiguous():
+                    raise ValueError("warm_start must be a contiguous float64 tensor of n_lambda * E values")
+                o.warm_start, o.warm_start_on_device = warm_start.data_ptr(), 1
+            else:
+                warm_start = np.ascontiguousarray(warm_start, np.float64).reshape(-1)
+                if warm_start.size != n:
+                    raise ValueError("warm_start must hold n_lambda * E values")
+                o.warm_start, o.warm_start_on_device = warm_start.ctypes.data, 0
         info = SolveInfo()
         npx = self.n_lambda * self.ny * self.nx
         if out is None:

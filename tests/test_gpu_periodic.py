@@ -177,3 +177,24 @@ def test_periodic_plume_full_size(ctx):
         err = rel_err(rad, ref)
         say("  max pixel rel err", err.max())
         assert err.max() < 1e-4
+
+
+def test_served_periodic_scenes_equal_solo_solves(ctx):
+    """The continuous-batching server carries the periodic flag: a mix of periodic and
+    bounded scenes served together gives the solo solves' results bit for bit."""
+    from paper_2503_16037_amd import sgrt
+    stream = [hetero_slab(3, seed=11), hetero_slab(0, seed=12), hetero_slab(1, seed=13, n_lambda=5),
+              hetero_slab(2, seed=14)]
+    solo = []
+    for sc in stream:
+        with sgrt.Scene(ctx, sc) as g:
+            r, _ = g.solve()
+            solo.append(np.asarray(r).reshape(sc.n_lambda, sc.ny, sc.nx))
+    srv = sgrt.Server(ctx, max_resident=2, queue_cap=8, n_streams=2)
+    try:
+        out = [srv.wait(t) for t in [srv.submit(sc) for sc in stream]]
+    finally:
+        srv.close()
+    for sc, (rad, info), ref in zip(stream, out, solo):
+        assert info["status"] == 0 and info["converged"] == 1
+        assert np.array_equal(rad, ref), sc.name
