@@ -388,10 +388,31 @@ sg_status ensure_real(Scene &s) {
 }
 
 // Read n doubles of device scalars after the stream drains.
+// Pinned host staging for the convergence scalars, one buffer per host thread (a thread runs
+// one solve at a time): a copy into pageable memory would go through a bounce buffer and
+// lengthen every host round trip of the solve policy.
+struct PinnedScalars {
+    double *p = nullptr;
+    size_t n = 0;
+    ~PinnedScalars() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
 sg_status read_scalars(Scene &s, hipStream_t st, const double *dev, double *host, int n) {
     Ctx *ctx = s.ctx;
-    SG_HIP(hipMemcpyAsync(host, dev, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    thread_local PinnedScalars buf;
+    if (buf.n < (size_t)n) {
+        if (buf.p) (void)hipHostFree(buf.p);
+        buf.p = nullptr;
+        buf.n = 0;
+        const size_t want = std::max<size_t>((size_t)n, 1024);
+        SG_HIP(hipHostMalloc((void **)&buf.p, sizeof(double) * want, hipHostMallocDefault));
+        buf.n = want;
+    }
+    SG_HIP(hipMemcpyAsync(buf.p, dev, sizeof(double) * n, hipMemcpyDeviceToHost, st));
     SG_HIP(hipStreamSynchronize(st));
+    std::memcpy(host, buf.p, sizeof(double) * n);
     return SG_OK;
 }
 
