@@ -98,8 +98,17 @@ def closed_single_scatter(sc, g):
 LAYERS = (0.004, 0.003, 0.002, 0.0015, 0.001, 0.0005)
 
 
-def test_slab_single_scatter_is_the_plane_parallel_closed_form():
+def without_surface_nodes(sc):
+    adj_ptr, adj_idx = scenes.periodic_radius_graph(np.asarray(sc.vol_pos_fx), sc.nx, sc.ny, sc.nz, 1.8,
+                                                    sc.periodic, surface=False)
+    return dataclasses.replace(sc, surface_nodes=0, adj_ptr=adj_ptr, adj_idx=adj_idx)
+
+
+@pytest.mark.parametrize("surface", [1, 0])
+def test_slab_single_scatter_is_the_plane_parallel_closed_form(surface):
     sc = scenes.make_slab(layers=LAYERS, omega=0.9, g=0.7, albedo=0.2)
+    if not surface:  # the ground's direct beam then comes from the gather's own sun march
+        sc = without_surface_nodes(sc)
     ref = closed_single_scatter(sc, 0.7)
     pix = oracle.run(sc, scatter_order=1)["radiance"]
     assert np.abs(pix - ref).max() <= 1e-12 * ref
