@@ -198,3 +198,19 @@ def test_served_periodic_scenes_equal_solo_solves(ctx):
     for sc, (rad, info), ref in zip(stream, out, solo):
         assert info["status"] == 0 and info["converged"] == 1
         assert np.array_equal(rad, ref), sc.name
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_periodic_without_surface_nodes(ctx, precision):
+    """No surface nodes: the pixel gather marches the sun from the ground itself, wrapping
+    round the period like every other march."""
+    from paper_2503_16037_amd import sgrt
+    sc = hetero_slab(3, seed=21, sza=65.0, saa=10.0)
+    adj_ptr, adj_idx = scenes.periodic_radius_graph(np.asarray(sc.vol_pos_fx), sc.nx, sc.ny, sc.nz, 1.8, 3,
+                                                    surface=False)
+    sc = dataclasses.replace(sc, surface_nodes=0, adj_ptr=adj_ptr, adj_idx=adj_idx)
+    ref = oracle.run(sc)["radiance"]
+    with sgrt.Scene(ctx, sc) as g:
+        rad, info = g.solve(precision=precision)
+        assert info["converged"] == 1
+        assert rel_err(rad, ref).max() < (1e-10 if precision == "fp64" else 1e-4)
