@@ -14,7 +14,8 @@
  * Conventions used throughout:
  *  - fixed-point positions, 65536 units per voxel edge, absolute in the box
  *    [0, nx] x [0, ny] x [0, nz] voxels; the surface is the plane z = 0 and
- *    the medium outside the box is vacuum;
+ *    the medium outside the box is vacuum, unless the scene repeats along x
+ *    and/or y (sg_scene_desc.periodic: a plane-parallel slab);
  *  - node ids: volume node of voxel (ix, iy, iz) = ix + nx*(iy + ny*iz),
  *    exactly one per voxel; surface node of column (ix, iy) =
  *    nx*ny*nz + ix + nx*iy at the column centre on z = 0;
