@@ -226,9 +226,13 @@ __global__ __launch_bounds__(64) void k_qcolour(
     BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun, const int *__restrict__ hull, int per,
     long long wx, long long wy) {
 #pragma clang fp contract(off)
+    constexpr int kCM = 8;  // out-directions per seed chunk
     __shared__ double sx[64], sy[64], sz[64], lt[3][128];
+    __shared__ double vbuf[128][kCM + 1];  // the chunk's v_im, lattice-point major (padded row)
+    __shared__ double seed_v[64];
     __shared__ unsigned long long wq[128], bins[64];
-    __shared__ int nbr[128][kHullNb], nnb[128], col[128], snap[128];
+    __shared__ int nnb[128], col[128], snap[128], seed_pt[64];
+    __shared__ unsigned char nbr[128][kHullNb];  // lattice indices are below 128
 
     const int l = blockIdx.x;
     const int lane = threadIdx.x;
@@ -262,7 +266,7 @@ __global__ __launch_bounds__(64) void k_qcolour(
         }
         wq[i] = (unsigned long long)llrint(w * kFix);
         nnb[i] = hull[NF * kHullNb + i];
-        for (int t = 0; t < kHullNb; ++t) nbr[i][t] = hull[i * kHullNb + t];
+        for (int t = 0; t < kHullNb; ++t) nbr[i][t] = (unsigned char)hull[i * kHullNb + t];
     }
     __syncthreads();
 
@@ -300,30 +304,64 @@ __global__ __launch_bounds__(64) void k_qcolour(
             q[h2][1] = fma(R[7], z, fma(R[4], y, R[1] * x));
             q[h2][2] = fma(R[8], z, fma(R[5], y, R[2] * x));
         }
-        // seeds
-        int c0 = -1, c1 = -1;
-        double cv0 = 0.0, cv1 = 0.0;
-        for (int m = 0; m < d; ++m) {
-            const double tx = sx[m], ty = sy[m], tz = sz[m];
-            const double v0 = ok0 ? fma(q[0][2], tz, fma(q[0][1], ty, q[0][0] * tx)) : -__builtin_inf();
-            const double v1 = ok1 ? fma(q[1][2], tz, fma(q[1][1], ty, q[1][0] * tx)) : -__builtin_inf();
-            double bv = v1 > v0 ? v1 : v0;
-            int bi = v1 > v0 ? i1 : i0;
-            // wavefront argmax, ties to the lower index: every lane ends with the same pair
-            for (int o = 32; o > 0; o >>= 1) {
+        // seeds: for every out-direction m the lattice point of largest v_im, ties to the
+        // lowest i.  Chunks of kCM directions: the lanes write v_im of their lattice points
+        // to LDS, then lane (m, g) scans points 16 g .. 16 g + 15 for direction m in
+        // ascending order (strict >), and the eight groups combine by larger value, ties
+        // to the lower index; no serial cross-lane chain per direction.
+        for (int m0 = 0; m0 < d; m0 += kCM) {
+            const int nm = min(kCM, d - m0);
+            for (int mm = 0; mm < nm; ++mm) {
+                const double tx = sx[m0 + mm], ty = sy[m0 + mm], tz = sz[m0 + mm];
+                if (ok0) vbuf[i0][mm] = fma(q[0][2], tz, fma(q[0][1], ty, q[0][0] * tx));
+                if (ok1) vbuf[i1][mm] = fma(q[1][2], tz, fma(q[1][1], ty, q[1][0] * tx));
+            }
+            __syncthreads();
+            const int mm = lane % kCM, g = lane / kCM;
+            double bv = -__builtin_inf();
+            int bi = 0x7fffffff;
+            if (mm < nm) {
+                const int ib = min(NF, 16 * g + 16);
+                for (int i = 16 * g; i < ib; ++i) {
+                    const double v = vbuf[i][mm];
+                    if (v > bv) {
+                        bv = v;
+                        bi = i;
+                    }
+                }
+            }
+            for (int o = kCM; o < 64; o <<= 1) {
                 const double ov = __shfl_xor(bv, o, 64);
                 const int oi = __shfl_xor(bi, o, 64);
                 const bool take = ov > bv || (ov == bv && oi < bi);
                 bv = take ? ov : bv;
                 bi = take ? oi : bi;
             }
-            if (bi == i0 && (c0 < 0 || bv > cv0)) { c0 = m; cv0 = bv; }
-            if (bi == i1 && (c1 < 0 || bv > cv1)) { c1 = m; cv1 = bv; }
+            if (g == 0 && mm < nm) {
+                seed_v[m0 + mm] = bv;
+                seed_pt[m0 + mm] = bi;
+            }
+            __syncthreads();  // vbuf is rewritten by the next chunk
         }
-        if (ok0) col[i0] = c0;
-        if (ok1) col[i1] = c1;
+        // claims: a point seeded by several directions takes the largest value, ties to the
+        // lowest m (what claiming in order of m with a strictly larger value gives)
+        if (ok0) col[i0] = -1;
+        if (ok1) col[i1] = -1;
         __syncthreads();
-        // flood fill in rounds
+        if (lane < d) {
+            const int pt = seed_pt[lane];
+            const double v = seed_v[lane];
+            bool win = true;
+            for (int m2 = 0; m2 < d; ++m2) {
+                const double v2 = seed_v[m2];
+                if (m2 != lane && seed_pt[m2] == pt && (v2 > v || (v2 == v && m2 < lane))) win = false;
+            }
+            if (win && pt < NF) col[pt] = lane;
+        }
+        __syncthreads();
+        // flood fill in rounds: an uncoloured point takes the colour of the first coloured
+        // neighbour in its list (the snapshot of the round's start); the list's reads are
+        // independent, so they are issued together
         for (int round = 0; round < NF; ++round) {
             if (ok0) snap[i0] = col[i0];
             if (ok1) snap[i1] = col[i1];
@@ -332,14 +370,17 @@ __global__ __launch_bounds__(64) void k_qcolour(
             for (int h2 = 0; h2 < 2; ++h2) {
                 const int i = h2 ? i1 : i0;
                 if (i >= NF || snap[i] >= 0) continue;
-                for (int t = 0; t < nnb[i]; ++t) {
-                    const int c = snap[nbr[i][t]];
-                    if (c >= 0) {
-                        col[i] = c;
-                        break;
+                const int nn = nnb[i];
+                int c = -1;
+#pragma unroll
+                for (int t = kHullNb - 1; t >= 0; --t) {
+                    if (t < nn) {
+                        const int ct = snap[nbr[i][t]];
+                        c = ct >= 0 ? ct : c;
                     }
                 }
-                missing = missing || col[i] < 0;
+                col[i] = c;
+                missing = missing || c < 0;
             }
             const bool any = __ballot(missing) != 0ull;
             __syncthreads();
