@@ -359,9 +359,9 @@ __global__ __launch_bounds__(64) void k_qcolour(
             if (win && pt < NF) col[pt] = lane;
         }
         __syncthreads();
-        // flood fill in rounds: an uncoloured point takes the colour of the first coloured
-        // neighbour in its list (the snapshot of the round's start); the list's reads are
-        // independent, so they are issued together
+        // flood fill in rounds: an uncoloured point takes the colour of its lowest-index
+        // coloured neighbour (the lists ascend) in the snapshot of the round's start; the
+        // list's reads are independent, so they are issued together
         for (int round = 0; round < NF; ++round) {
             if (ok0) snap[i0] = col[i0];
             if (ok1) snap[i1] = col[i1];
