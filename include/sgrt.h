@@ -105,7 +105,11 @@ typedef struct sg_scene_desc {
     int32_t surface_nodes;     /* 1: one Lambertian node per column at z = 0; 0: none */
     const int64_t *adj_ptr;    /* [N + 1] symmetric adjacency CSR over node ids */
     const int32_t *adj_idx;    /* [E] heads, ascending within a row, no self loops,
-                                  no surface-surface pairs, node degree <= 64 */
+                                  no surface-surface pairs; node degree <= 4096 for one
+                                  wavelength with SG_SIGMA_VORONOI (nodes above 64 have
+                                  their own kernels: the strongest couplings of Eq. 4 gather
+                                  on dense nodes), <= 64 with several wavelengths or
+                                  SG_SIGMA_COLOUR */
     const float *surf_albedo;  /* [ny][nx] Lambertian albedo in [0, 1] */
     int32_t sun_dir[3];        /* integer vector toward the sun (z > 0), |components| <= 2^22 */
     int32_t view_dir[3];       /* integer vector toward the sensor (z > 0), |components| <= 2^22 */

@@ -20,6 +20,10 @@
 namespace sg {
 
 constexpr int kHullNb = 16;  // neighbour slots per lattice point (hull adjacency)
+// Largest node degree of a one-wavelength scene with Voronoi cells; wavelength batches and
+// the colouring of the phase cells keep every node's couplings within one wavefront (64).
+constexpr int kMaxDegree = 4096;
+constexpr int kMaxWaveDegree = 64;
 
 void set_error(const std::string &msg);
 std::string t_last_error();
@@ -67,6 +71,12 @@ struct Scene {
     int nvox = 0, N = 0, npx = 0;
     int64_t E = 0, nnz = 0;
     int dmax = 0;
+    // nodes of degree above 64 (handled by their own kernels: one workgroup per node in the
+    // sweeps, one per (node, incoming direction) in the phase cells)
+    int n_big = 0;
+    int *big = nullptr;           // [n_big] node ids, ascending
+    long long *bigdir = nullptr;  // [n_big + 1] prefix of their incoming-direction counts
+    long long n_bigdir = 0;
     int n_phase = 1;
     double hg_g[4] = {0, 0, 0, 0};
     int phase_kind[4] = {0, 0, 0, 0};  // SG_PHASE_HG, SG_PHASE_RAYLEIGH, SG_PHASE_TABLE

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(64) void k_qbuild(
     const int lane = threadIdx.x;
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
-    if (d == 0) return;
+    if (d == 0 || d > kWave) return;  // higher degree: k_qbuild_big
     const bool surf = l >= nvox;
 
     if (lane < d) {
@@ -202,6 +202,136 @@ __global__ __launch_bounds__(64) void k_qbuild(
         __syncthreads();
     }
 }
+
+// Nodes of degree above 64 (graphs whose strongest couplings gather on the dense nodes):
+// one 64-lane workgroup per (node, incoming direction), wg = bigdir[b] + a.  The
+// lattice points are the lanes' (i and i + 64); the node's out-edge directions are
+// formed in LDS 64 at a time and scanned in ascending order with the operation sequence
+// and tie rule of k_qbuild; the direction's d cell sums sit in LDS (dynamic, d words).
+template <class Real, class BlkT, bool kWriteQ>
+__global__ __launch_bounds__(64) void k_qbuild_big(
+    int nbig, const int *__restrict__ big, const long long *__restrict__ bigdir, int nvox,
+    const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx, const int *__restrict__ pos,
+    const double *__restrict__ lat, const double *__restrict__ tab, int NF, int n_phase,
+    const float *__restrict__ frac, double sun_x, double sun_y, double sun_z, Real mu0, const Real *__restrict__ T,
+    const Real *__restrict__ rho, const Real *__restrict__ Tsun, const long long *__restrict__ nodeoff,
+    BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun, int per, long long wx, long long wy) {
+#pragma clang fp contract(off)
+    extern __shared__ unsigned long long cell[];  // [d] fixed-point sums
+    __shared__ double cx[64], cy[64], cz[64];
+    __shared__ unsigned long long wq[128];
+    const long long wg = blockIdx.x;
+    int lo = 0, hi = nbig;  // the node b with bigdir[b] <= wg < bigdir[b + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (bigdir[mid] <= wg) lo = mid; else hi = mid;
+    }
+    const int l = big[lo];
+    const int a = (int)(wg - bigdir[lo]);
+    const int lane = threadIdx.x;
+    const long long off = adj_ptr[l];
+    const int d = (int)(adj_ptr[l + 1] - off);
+    const bool surf = l >= nvox;
+    // the unit direction of out-edge m (the operation sequence of k_qbuild)
+    auto edge_dir = [&](int m, double &ex, double &ey, double &ez) {
+        const int j = adj_idx[off + m];
+        const long long Dx = min_image((long long)pos[3 * j] - pos[3 * l], wx, per & 1);
+        const long long Dy = min_image((long long)pos[3 * j + 1] - pos[3 * l + 1], wy, per & 2);
+        const long long Dz = (long long)pos[3 * j + 2] - pos[3 * l + 2];
+        const double nrm = sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
+        ex = (double)Dx / nrm;
+        ey = (double)Dy / nrm;
+        ez = (double)Dz / nrm;
+    };
+    for (int i = lane; i < NF; i += 64) {
+        double w;
+        if (surf) {
+            w = tab[n_phase * NF + i];
+        } else {
+            w = 0.0;
+            for (int k = 0; k < n_phase; ++k) {
+                const double f = frac ? (double)frac[(long long)k * nvox + l] : 1.0;
+                w = w + f * tab[k * NF + i];
+            }
+        }
+        wq[i] = (unsigned long long)llrint(w * kFix);
+    }
+    for (int m = lane; m < d; m += 64) cell[m] = 0ull;
+    // the rotation of this incoming direction (every lane, the same values)
+    double R[9];
+    if (surf) {
+        R[0] = 1.0; R[1] = 0.0; R[2] = 0.0; R[3] = 0.0; R[4] = 1.0; R[5] = 0.0; R[6] = 0.0; R[7] = 0.0; R[8] = 1.0;
+    } else {
+        double ux, uy, uz;
+        if (a < d) {
+            edge_dir(a, ux, uy, uz);
+            ux = -ux; uy = -uy; uz = -uz;
+        } else {
+            ux = sun_x; uy = sun_y; uz = sun_z;
+        }
+        if (1.0 + uz < 1e-12) {
+            R[0] = 1.0; R[1] = 0.0; R[2] = 0.0; R[3] = 0.0; R[4] = -1.0; R[5] = 0.0; R[6] = 0.0; R[7] = 0.0;
+            R[8] = -1.0;
+        } else {
+            const double h = 1.0 / (1.0 + uz);
+            const double xy = (ux * uy) * h;
+            R[0] = uz + (uy * uy) * h; R[1] = -xy; R[2] = -ux;
+            R[3] = -xy; R[4] = uz + (ux * ux) * h; R[5] = -uy;
+            R[6] = ux; R[7] = uy; R[8] = uz;
+        }
+    }
+    const int i0 = lane, i1 = lane + 64;
+    double q[2][3], best[2];
+    int own[2] = {0, 0};
+    for (int h2 = 0; h2 < 2; ++h2) {
+        const int i = min(h2 ? i1 : i0, NF - 1);
+        const double x = lat[3 * i], y = lat[3 * i + 1], z = lat[3 * i + 2];
+        q[h2][0] = fma(R[6], z, fma(R[3], y, R[0] * x));
+        q[h2][1] = fma(R[7], z, fma(R[4], y, R[1] * x));
+        q[h2][2] = fma(R[8], z, fma(R[5], y, R[2] * x));
+        best[h2] = -__builtin_inf();
+    }
+    for (int m0 = 0; m0 < d; m0 += 64) {
+        const int nm = min(64, d - m0);
+        if (lane < nm) edge_dir(m0 + lane, cx[lane], cy[lane], cz[lane]);
+        __syncthreads();
+        for (int mm = 0; mm < nm; ++mm) {
+            const double tx = cx[mm], ty = cy[mm], tz = cz[mm];
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2) {
+                const double v = fma(q[h2][2], tz, fma(q[h2][1], ty, q[h2][0] * tx));
+                own[h2] = v > best[h2] ? m0 + mm : own[h2];
+                best[h2] = fmax(best[h2], v);
+            }
+        }
+        __syncthreads();  // the next chunk rewrites the directions
+    }
+    if (i0 < NF) atomicAdd(&cell[own[0]], wq[i0]);
+    if (i1 < NF) atomicAdd(&cell[own[1]], wq[i1]);
+    __syncthreads();
+    const Real rl = rho ? rho[l] : (Real)0;
+    const Real tsun = Tsun ? Tsun[l] : (Real)0;
+    BlkT *blk = val + nodeoff[l];  // column-major: element (row n, column m) at m d + n
+    for (int m = lane; m < d; m += 64) {
+        const double Q = (double)(long long)cell[m] * kUnfix;
+        const long long b = off + m;
+        if (surf) {
+            for (int c = 0; c < d; ++c) {
+                if (kWriteQ) blk[(long long)c * d + m] = (BlkT)Q;
+                else blk[(long long)c * d + m] = (BlkT)(T[off + c] * rl * (Real)Q);
+            }
+            if (!kWriteQ) S[b] = rl * mu0 * tsun * (Real)Q;
+            qsun[b] = (float)Q;
+        } else if (a < d) {
+            if (kWriteQ) blk[(long long)a * d + m] = (BlkT)Q;
+            else blk[(long long)a * d + m] = (BlkT)(T[off + a] * rl * (Real)Q);
+        } else {
+            if (!kWriteQ) S[b] = tsun * rl * (Real)Q;
+            qsun[b] = (float)Q;
+        }
+    }
+}
+
 
 // directions per group: as many as fill the lanes' pair slots
 int qbuild_group(int NF) { return std::max(1, std::min(kQMaxGroup, kQSlots * 64 / NF)); }
@@ -436,6 +566,21 @@ void launch_qbuild(Scene &s, hipStream_t st, int write_q) {
                                (long long)s.nx * kFx, (long long)s.ny * kFx);
         }
         return;
+    }
+    if (s.n_big) {  // nodes of degree above 64
+        const size_t cells = sizeof(unsigned long long) * s.dmax;
+        if (write_q)
+            hipLaunchKernelGGL((k_qbuild_big<Real, float, true>), dim3(s.n_bigdir), dim3(64), cells, st, s.n_big, s.big,
+                               s.bigdir, s.nvox, s.adj_ptr, s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac,
+                               s.sun_in[0], s.sun_in[1], s.sun_in[2], (Real)s.mu0, (const Real *)nullptr,
+                               (const Real *)nullptr, (const Real *)nullptr, s.nodeoff, s.q, (Real *)nullptr, s.qsun,
+                               s.periodic, (long long)s.nx * kFx, (long long)s.ny * kFx);
+        else
+            hipLaunchKernelGGL((k_qbuild_big<Real, Real, false>), dim3(s.n_bigdir), dim3(64), cells, st, s.n_big, s.big,
+                               s.bigdir, s.nvox, s.adj_ptr, s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac,
+                               s.sun_in[0], s.sun_in[1], s.sun_in[2], (Real)s.mu0, (const Real *)s.T,
+                               (const Real *)s.rho, (const Real *)s.Tsun, s.nodeoff, (Real *)s.val, (Real *)s.S, s.qsun,
+                               s.periodic, (long long)s.nx * kFx, (long long)s.ny * kFx);
     }
     if (write_q) {
         hipLaunchKernelGGL((k_qbuild<Real, float, true>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,

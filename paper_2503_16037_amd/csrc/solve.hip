@@ -198,6 +198,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int N, int groups, const 
         nm = load_meta(adj_ptr, nodeoff, l + step, N);
         const long long off = cur.off, base = cur.base;
         const int d = cur.d;
+        if (d > kWave) continue;  // a node of higher degree: k_spmv_big
         if (d == 0) {
             if (monitor && lane == 0) meas[l] = make_float2(0.f, 0.f);
             continue;
@@ -237,11 +238,12 @@ __global__ __launch_bounds__(kSpmvThreads) void k_first(int N, const long long *
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
     double r = 0.0, u = 0.0;
-    if (lane < d) {
-        const Real v = rhs[off + lane];
-        x[off + lane] = v;
-        r = fabs((double)v);
-        u = r / (r + kRelFloor);
+    for (int n = lane; n < d; n += kWave) {
+        const Real v = rhs[off + n];
+        x[off + n] = v;
+        const double a = fabs((double)v);
+        r += a;
+        u = fmax(u, a / (a + kRelFloor));
     }
     r = wave_sum(r);
     u = wave_max(u);
@@ -268,6 +270,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_residual64(int N, int groups, 
         nm = load_meta(adj_ptr, nodeoff, l + step, N);
         const long long off = cur.off, base = cur.base;
         const int d = cur.d;
+        if (d > kWave) continue;  // a node of higher degree: k_residual64_big
         if (d == 0) {
             if (lane == 0) meas[l] = make_float2(0.f, 0.f);
             continue;
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_apply_imk64(int N, const long 
     if (l >= N) return;
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
-    if (d == 0) return;
+    if (d == 0 || d > kWave) return;  // higher degree: k_apply_imk64_big
     const long long base = nodeoff[l];
     const bool act = lane < d;
     const long long b = off + min(lane, d - 1);
@@ -313,6 +316,95 @@ __global__ __launch_bounds__(kSpmvThreads) void k_apply_imk64(int N, const long 
     const double acc = node_row<double>(val + base, blk, d, lane, xl);
     if (act) wv[b] = v[b] - acc;
 }
+
+// Nodes of degree above 64 (graphs whose strongest couplings gather on the dense
+// nodes): one 256-thread workgroup per node, the node's gathered inputs staged in LDS,
+// each thread a set of rows r = t, t + 256, ..., every row's sum over the columns in
+// increasing order as in node_row; the node's measures by a fixed-order block
+// reduction.  big[] lists the nodes, in id order.
+template <class Real>
+__global__ __launch_bounds__(256) void k_spmv_big(const int *__restrict__ big, const long long *__restrict__ adj_ptr,
+                                                 const long long *__restrict__ nodeoff, const int *__restrict__ rev,
+                                                 const Real *__restrict__ val, const Real *__restrict__ S,
+                                                 const Real *__restrict__ x, Real *__restrict__ y,
+                                                 float2 *__restrict__ meas, int monitor) {
+    extern __shared__ unsigned char smem_raw[];
+    Real *xin = reinterpret_cast<Real *>(smem_raw);
+    const int l = big[blockIdx.x];
+    const long long off = adj_ptr[l], base = nodeoff[l];
+    const int d = (int)(adj_ptr[l + 1] - off);
+    for (int m = threadIdx.x; m < d; m += 256) xin[m] = x[rev[off + m]];
+    __syncthreads();
+    double r = 0.0, u = 0.0;
+    for (int n = threadIdx.x; n < d; n += 256) {
+        Real acc = (Real)0;
+        for (int m = 0; m < d; ++m) acc += val[base + (long long)m * d + n] * xin[m];
+        const Real yn = S[off + n] + acc;
+        y[off + n] = yn;
+        if (monitor) {
+            const double dr = fabs((double)yn - (double)x[off + n]);
+            r += dr;
+            u = fmax(u, dr / (fabs((double)yn) + kRelFloor));
+        }
+    }
+    if (monitor) {
+        r = block_sum<256>(r);
+        u = block_max<256>(u);
+        if (threadIdx.x == 0) meas[l] = make_float2((float)r, (float)u);
+    }
+}
+
+// r = S - x + K x in FP64 for the nodes of degree above 64 (see k_spmv_big).
+template <class Real>
+__global__ __launch_bounds__(256) void k_residual64_big(const int *__restrict__ big,
+                                                       const long long *__restrict__ adj_ptr,
+                                                       const long long *__restrict__ nodeoff,
+                                                       const int *__restrict__ rev, const Real *__restrict__ val,
+                                                       const Real *__restrict__ S, const double *__restrict__ x,
+                                                       double *__restrict__ res, float2 *__restrict__ meas) {
+    extern __shared__ unsigned char smem_raw[];
+    double *xin = reinterpret_cast<double *>(smem_raw);
+    const int l = big[blockIdx.x];
+    const long long off = adj_ptr[l], base = nodeoff[l];
+    const int d = (int)(adj_ptr[l + 1] - off);
+    for (int m = threadIdx.x; m < d; m += 256) xin[m] = x[rev[off + m]];
+    __syncthreads();
+    double a = 0.0, u = 0.0;
+    for (int n = threadIdx.x; n < d; n += 256) {
+        double acc = 0.0;
+        for (int m = 0; m < d; ++m) acc += (double)val[base + (long long)m * d + n] * xin[m];
+        const double xb = x[off + n];
+        const double rb = ((double)S[off + n] - xb) + acc;
+        res[off + n] = rb;
+        a += fabs(rb);
+        u = fmax(u, fabs(rb) / (fabs(xb) + kRelFloor));
+    }
+    a = block_sum<256>(a);
+    u = block_max<256>(u);
+    if (threadIdx.x == 0) meas[l] = make_float2((float)a, (float)u);
+}
+
+// w = v - K v in FP64 for the nodes of degree above 64.
+template <class Real>
+__global__ __launch_bounds__(256) void k_apply_imk64_big(const int *__restrict__ big,
+                                                        const long long *__restrict__ adj_ptr,
+                                                        const long long *__restrict__ nodeoff,
+                                                        const int *__restrict__ rev, const Real *__restrict__ val,
+                                                        const double *__restrict__ v, double *__restrict__ wv) {
+    extern __shared__ unsigned char smem_raw[];
+    double *xin = reinterpret_cast<double *>(smem_raw);
+    const int l = big[blockIdx.x];
+    const long long off = adj_ptr[l], base = nodeoff[l];
+    const int d = (int)(adj_ptr[l + 1] - off);
+    for (int m = threadIdx.x; m < d; m += 256) xin[m] = v[rev[off + m]];
+    __syncthreads();
+    for (int n = threadIdx.x; n < d; n += 256) {
+        double acc = 0.0;
+        for (int m = 0; m < d; ++m) acc += (double)val[base + (long long)m * d + n] * xin[m];
+        wv[off + n] = v[off + n] - acc;
+    }
+}
+
 
 // partial[j * nblk + block] = sum_i V[j][i] w[i], j < k (one pass over w).
 __global__ __launch_bounds__(kVecThreads) void k_dot_multi(const double *__restrict__ V, long long ld, int k,
@@ -402,11 +494,12 @@ int spmv_blocks(const Scene &s) { return (s.N + kNodesPerSpmvBlock - 1) / kNodes
 // fits, dmax <= 64); beyond it (FP64, dmax > 45) the kernels read rows from memory
 template <class Real>
 static size_t block_lds(const Scene &s) {
-    const size_t b = (size_t)kNodesPerSpmvBlock * s.dmax * s.dmax * sizeof(Real);
+    const int dm = std::min(s.dmax, kWave);  // nodes of higher degree have their own kernels
+    const size_t b = (size_t)kNodesPerSpmvBlock * dm * dm * sizeof(Real);
     return b <= 64 * 1024 ? b : 0;
 }
 template <class Real>
-static int lds_dmax(const Scene &s) { return block_lds<Real>(s) ? s.dmax : 0; }
+static int lds_dmax(const Scene &s) { return block_lds<Real>(s) ? std::min(s.dmax, kWave) : 0; }
 
 // default launch shape of the sweeps: one group of four nodes per workgroup (the kernels
 // also run persistent over fewer workgroups; the tuner measures both)
@@ -419,6 +512,9 @@ void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y
     grid = std::min(grid, spmv_blocks(s));
     hipLaunchKernelGGL((k_spmv<Real>), dim3(grid), dim3(kSpmvThreads), block_lds<Real>(s), st, s.N, spmv_blocks(s),
                        s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x, y, s.meas, out ? 1 : 0, lds_dmax<Real>(s));
+    if (s.n_big)
+        hipLaunchKernelGGL((k_spmv_big<Real>), dim3(s.n_big), dim3(256), sizeof(Real) * s.dmax, st, s.big, s.adj_ptr,
+                           s.nodeoff, s.rev, (const Real *)s.val, S, x, y, s.meas, out ? 1 : 0);
     if (after) (void)hipEventRecord(after, st);
     if (out) launch_measures(s, 1, out, st);
 }
@@ -435,6 +531,9 @@ void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x6
     hipLaunchKernelGGL((k_residual64<Real>), dim3(default_grid(s)), dim3(kSpmvThreads), block_lds<Real>(s), st,
                        s.N, spmv_blocks(s), s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x64, r64, s.meas,
                        lds_dmax<Real>(s));
+    if (s.n_big)
+        hipLaunchKernelGGL((k_residual64_big<Real>), dim3(s.n_big), dim3(256), sizeof(double) * s.dmax, st, s.big,
+                           s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x64, r64, s.meas);
     launch_measures(s, 1, out, st);
 }
 
@@ -442,6 +541,9 @@ template <class Real>
 void launch_apply_imk64(Scene &s, hipStream_t st, const double *v, double *w) {
     hipLaunchKernelGGL((k_apply_imk64<Real>), dim3(spmv_blocks(s)), dim3(kSpmvThreads), block_lds<Real>(s), st, s.N,
                        s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, v, w, lds_dmax<Real>(s));
+    if (s.n_big)
+        hipLaunchKernelGGL((k_apply_imk64_big<Real>), dim3(s.n_big), dim3(256), sizeof(double) * s.dmax, st, s.big,
+                           s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, v, w);
 }
 
 void launch_measures(Scene &s, int nl, double *out, hipStream_t st) {

@@ -1,0 +1,126 @@
+"""Nodes of degree above 64: the graphs of the paper's coupling selection (the strongest
+couplings, Eq. 4) gather their couplings on the optically dense nodes, with degrees in
+the hundreds.  Such nodes have their own kernels (phase cells per (node, incoming
+direction); sweeps, residuals and GMRES products per node).  Against the FP64 oracle on
+graphs the oracle builds itself: CSR structure exact, K values and pixels within the
+FP64 bar, pixels within the FP32 bar, the GMRES path, and the GPU graph builder's
+output solved end to end."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_16037_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2503_16037_amd import sgrt
+    c = sgrt.Context(0)
+    yield c
+    c.close()
+
+
+def rel_err(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+
+def coupled_scene(k, seed=4, periodic=0):
+    sc = scenes.make_random_small(seed, nx=8, ny=8, nz=6, kscale=2.0)
+    ap, ai = oracle.coupling_graph(sc, n_pairs=int(k * sc.nvox))
+    sc = dataclasses.replace(sc, adj_ptr=ap, adj_idx=ai)
+    d = np.diff(ap)
+    say("coupled scene k", k, "E", ap[-1], "max degree", d.max(), "nodes above 64", int((d > 64).sum()),
+        "surface nodes above 64", int((d[sc.nvox:] > 64).sum()))
+    assert d.max() > 64
+    return sc
+
+
+@pytest.mark.parametrize("k", [8, 20])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_high_degree_parity(ctx, k, precision):
+    from paper_2503_16037_amd import sgrt
+    sc = coupled_scene(k)
+    ora = oracle.run(sc)
+    with sgrt.Scene(ctx, sc) as g:
+        assert g.sizes["max_degree"] == int(np.diff(sc.adj_ptr).max())
+        rad, info = g.solve(precision=precision)
+        assert info["converged"] == 1
+        rp, col, val = g.export_csr()
+        assert np.array_equal(rp, ora["row_ptr"]) and np.array_equal(col, ora["col"])
+        if precision == "fp64":
+            assert rel_err(val, ora["val"]).max() < 1e-12
+            assert rel_err(rad, ora["radiance"]).max() < 1e-10
+        else:
+            big = ora["val"] > 1e-12 * ora["val"].max()
+            assert rel_err(val[big], ora["val"][big]).max() < 5e-5
+            assert rel_err(rad, ora["radiance"]).max() < 1e-4
+        say("  max pixel rel err", rel_err(rad, ora["radiance"]).max(), "sweeps", info["sweeps"])
+
+
+def test_high_degree_gmres(ctx):
+    from paper_2503_16037_amd import sgrt
+    sc = coupled_scene(12)
+    ref = oracle.run(sc)["radiance"]
+    with sgrt.Scene(ctx, sc) as g:
+        rad, info = g.solve(precision="fp64", solver="gmres")
+        assert info["converged"] == 1 and info["gmres_used"] == 1
+        assert rel_err(rad, ref).max() < 1e-10
+
+
+def test_high_degree_periodic(ctx):
+    from paper_2503_16037_amd import sgrt
+    sc = scenes.make_slab(nx=8, ny=8, nz=5, jitter=0.25, periodic=3, seed=9)
+    rng = np.random.default_rng(9)
+    ke = rng.lognormal(np.log(0.003), 1.2, (sc.nz, sc.ny, sc.nx))
+    sc = dataclasses.replace(sc, mu_s=(0.9 * ke).astype(np.float32), mu_a=(0.1 * ke).astype(np.float32))
+    # the coupling graph is built on the bounded grid; the scene then repeats it
+    ap, ai = oracle.coupling_graph(dataclasses.replace(sc, periodic=0), n_pairs=12 * sc.nvox)
+    sc = dataclasses.replace(sc, adj_ptr=ap, adj_idx=ai)
+    assert np.diff(ap).max() > 64
+    ref = oracle.run(sc)["radiance"]
+    with sgrt.Scene(ctx, sc) as g:
+        rad, info = g.solve(precision="fp64")
+        assert rel_err(rad, ref).max() < 1e-10
+
+
+def test_builder_graph_solved_end_to_end(ctx):
+    """The GPU graph builder's strongest couplings of a small plume (degrees up to about
+    130, hundreds of nodes above 64) go straight into a scene; every pixel meets the FP32
+    bar."""
+    from paper_2503_16037_amd import sgrt
+    sc = scenes.make_plume(nx=16, ny=16, nz=12, seed=6)
+    ap, ai = sgrt.graph_build(ctx, sc, n_pairs=12 * sc.nvox)
+    ap_o, ai_o = oracle.coupling_graph(sc, n_pairs=12 * sc.nvox)
+    assert np.array_equal(ap, ap_o) and np.array_equal(ai, ai_o)
+    d = np.diff(ap)
+    say("builder graph: max degree", d.max(), "nodes above 64", int((d > 64).sum()))
+    assert d.max() > 64
+    sc = dataclasses.replace(sc, adj_ptr=ap, adj_idx=ai)
+    ref = oracle.run(sc)["radiance"]
+    with sgrt.Scene(ctx, sc) as g:
+        rad, info = g.solve()
+        assert info["converged"] == 1
+        assert rel_err(rad, ref).max() < 1e-4
+
+
+def test_high_degree_limits(ctx):
+    """Several wavelengths and the colouring keep the one-wavefront limit of 64."""
+    from paper_2503_16037_amd import sgrt
+    sc = coupled_scene(8)
+    for bad in (dataclasses.replace(sc, abs_scale=np.array([1.0, 2.0], np.float32)),
+                dataclasses.replace(sc, sigma_mode=1)):
+        with pytest.raises(sgrt.SgError) as e:
+            sgrt.Scene(ctx, bad)
+        assert "64" in str(e.value)
