@@ -234,6 +234,60 @@ def bench_nfib(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_coupling(args):
+    """Pixel radiance against the amount of scattering coupling (the paper studies the
+    transmittance as a function of the number of couplings): the plume 64x64x32's nodes
+    coupled by their strongest couplings (Eq. 4), n = k x voxels for k = 1 .. 24, each
+    graph built on the GPU and solved; per-pixel differences against the largest graph,
+    the graph's size (couplings, nnz, degrees) and the times of the build and the solve."""
+    import torch
+
+    from paper_2503_16037_amd import scenes, sgrt
+
+    base = scenes.make_plume()
+    ctx = sgrt.Context(0)
+    ks = (1, 2, 4, 8, 11.5, 16, 24)
+    res = {}
+    for k in ks:
+        t = time.perf_counter()
+        ap, ai = sgrt.graph_build(ctx, base, n_pairs=int(k * base.nvox))
+        ms_build = (time.perf_counter() - t) * 1e3
+        sc = base.with_(adj_ptr=ap, adj_idx=ai)
+        deg = np.diff(ap)
+        with sgrt.Scene(ctx, sc) as g:
+            g.solve()
+            rad, info = g.solve(timing=True)
+            nnz = g.sizes["nnz"]
+        torch.cuda.synchronize()
+        res[k] = dict(rad=np.asarray(rad), couplings=int(ap[-1]), nnz=int(nnz), max_degree=int(deg.max()),
+                      nodes_above_64=int((deg > 64).sum()), uncoupled_nodes=int((deg == 0).sum()),
+                      ms_build=round(ms_build, 2), ms_qbuild=round(info["ms_qbuild"], 2),
+                      ms_solve=round(info["ms_solve"], 2), ms_total=round(info["ms_total"], 2), sweeps=info["sweeps"])
+    # the radius graph of the same nodes (every node coupled to its neighbours within 1.8 voxels)
+    with sgrt.Scene(ctx, base) as g:
+        g.solve()
+        rad_r, info_r = g.solve(timing=True)
+    ctx.close()
+    ref = res[ks[-1]]["rad"]
+    table = []
+    for k in ks:
+        r = res[k]
+        d = np.abs(r.pop("rad") - ref) / np.abs(ref)
+        table.append({"couplings_per_voxel": k, **r, "mean_rel_diff": float(d.mean()),
+                      "p99_rel_diff": float(np.percentile(d, 99)), "max_rel_diff": float(d.max())})
+    dr = np.abs(np.asarray(rad_r) - ref) / np.abs(ref)
+    out = {"metric": "pixel radiance vs amount of scattering coupling (strongest-coupling graphs)",
+           "value": table[-2]["mean_rel_diff"],
+           "unit": "mean relative difference of 16 from 24 couplings per voxel", "n_gpus": 1, "steps": len(table),
+           "warmup": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f32", "vs_baseline": None,
+           "scaling": "weak", "ms_per_step": None,
+           "config": {"workload": "plume-64x64x32 (seed 2) nodes, strongest couplings k x voxels, k = 1..24"},
+           "sweep": table,
+           "radius_graph": {"couplings": int(base.adj_ptr[-1]), "mean_rel_diff": float(dr.mean()),
+                            "p99_rel_diff": float(np.percentile(dr, 99)), "ms_total": round(info_r["ms_total"], 2)}}
+    print(json.dumps(out), flush=True)
+
+
 GRAPH_OPS_PER_PAIR = 10  # FP64 operations of one coupling: 3 subtractions, 4 products, 2 sums, 1 division
 
 
@@ -313,7 +367,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plume",
-                    help="plume | cloud | batched | plain | slab (periodic plume) | served | graph | nfib | copy")
+                    help="plume | cloud | batched | plain | slab (periodic plume) | served | graph | nfib | coupling | copy")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--served", type=int, default=40, help="requests of the served stream (workload served)")
@@ -336,6 +390,9 @@ def main():
         return
     if args.workload == "nfib":
         bench_nfib(args)
+        return
+    if args.workload == "coupling":
+        bench_coupling(args)
         return
 
     import torch
