@@ -1065,7 +1065,7 @@ namespace {
 
 void free_scene_impl(Scene *s) {
     clear_graphs(*s);
-    void *ptrs[] = {s->big, s->bigdir, s->mu_s, s->mu_a, s->frac, s->albedo, s->abs_scale_d, s->pos, s->adj_ptr, s->adj_idx, s->lat,
+    void *ptrs[] = {s->big, s->bigdir, s->bigrow, s->big_part, s->mu_s, s->mu_a, s->frac, s->albedo, s->abs_scale_d, s->pos, s->adj_ptr, s->adj_idx, s->lat,
                     s->tab, s->lut, s->hull, s->rev, s->nodeoff, s->row_ptr, s->col_idx, s->scan_tmp, s->tau_s, s->tau_a, s->tsun_s,
                     s->tsun_a, s->T, s->Tsun, s->rho, s->val, s->S, s->x, s->y, s->c_rhs, s->c_a, s->c_b, s->qsun,
                     s->q, s->bS, s->bx, s->by, s->brho, s->bsrc, s->lam_buf, s->x64, s->r64, s->gm_V, s->partial, s->meas, s->meas_part, s->scal, s->J, s->pix};
@@ -1134,20 +1134,25 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     SG_TRY(dalloc(s, &s.adj_idx, (size_t)s.E));
     // nodes of degree above one wavefront, and the prefix of their incoming directions
     // (in-edges and the sun; one for a surface node)
+    // and of their chunks of 256 rows (the sweeps' workgroups)
     std::vector<int> bigv;
-    std::vector<long long> bigdir(1, 0);
+    std::vector<long long> bigdir(1, 0), bigrow(1, 0);
     for (int64_t l = 0; l < s.N; ++l) {
         const int64_t deg = d->adj_ptr[l + 1] - d->adj_ptr[l];
         if (deg > kMaxWaveDegree) {
             bigv.push_back((int)l);
             bigdir.push_back(bigdir.back() + (l < s.nvox ? deg + 1 : 1));
+            bigrow.push_back(bigrow.back() + (deg + 255) / 256);
         }
     }
     s.n_big = (int)bigv.size();
     s.n_bigdir = bigdir.back();
+    s.n_bigrow = bigrow.back();
     if (s.n_big) {
         SG_TRY(dalloc(s, &s.big, bigv.size()));
         SG_TRY(dalloc(s, &s.bigdir, bigdir.size()));
+        SG_TRY(dalloc(s, &s.bigrow, bigrow.size()));
+        SG_TRY(dalloc(s, &s.big_part, (size_t)s.n_bigrow));
     }
     SG_TRY(dalloc(s, &s.lat, (size_t)3 * s.n_fib));
     SG_TRY(dalloc(s, &s.tab, (size_t)(s.n_phase + 1) * s.n_fib));
@@ -1235,6 +1240,7 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     if (s.n_big) {
         SG_TRY(upload(s, s.big, bigv.data(), sizeof(int) * bigv.size(), st));
         SG_TRY(upload(s, s.bigdir, bigdir.data(), sizeof(long long) * bigdir.size(), st));
+        SG_TRY(upload(s, s.bigrow, bigrow.data(), sizeof(long long) * bigrow.size(), st));
     }
     SG_TRY(upload(s, s.lat, lat.data(), sizeof(double) * lat.size(), st));
     SG_TRY(upload(s, s.tab, tab.data(), sizeof(double) * tab.size(), st));
@@ -1354,9 +1360,15 @@ uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st) {
                  a(e, 4) + a(3 * nf, 8) + a((np + 1) * nf, 8) + (table ? a(np * (uint64_t)d->phase_lut_n, 8) : 0) +
                  (d->sigma_mode == SG_SIGMA_COLOUR ? a(nf * (kHullNb + 1), 4) : 0);
     b += a(e, 4) + a(n + 1, 8) + a(e + 1, 8) + a(n / 2048 + 2, 8) + a(e, 4);
-    uint64_t n_big = 0;
-    for (int64_t l = 0; l < N; ++l) n_big += d->adj_ptr[l + 1] - d->adj_ptr[l] > kMaxWaveDegree;
-    if (n_big) b += a(n_big, 4) + a(n_big + 1, 8);
+    uint64_t n_big = 0, n_rows = 0;
+    for (int64_t l = 0; l < N; ++l) {
+        const int64_t deg = d->adj_ptr[l + 1] - d->adj_ptr[l];
+        if (deg > kMaxWaveDegree) {
+            ++n_big;
+            n_rows += (uint64_t)(deg + 255) / 256;
+        }
+    }
+    if (n_big) b += a(n_big, 4) + a(n_big + 1, 8) * 2 + a(n_rows, 16);
     b += a(e * nl, 8) * 2 + a(std::max<uint64_t>((n + 3) / 4, 65 * 1024), 8) +
          a(n * nl, 8) + a((uint64_t)node_chunks((int)n, (int)nl) * nl * 2, 8) + a(256, 8) +
          a(n * nl, 8) + a(npx * nl, 8);

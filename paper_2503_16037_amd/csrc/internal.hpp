@@ -77,6 +77,9 @@ struct Scene {
     int *big = nullptr;           // [n_big] node ids, ascending
     long long *bigdir = nullptr;  // [n_big + 1] prefix of their incoming-direction counts
     long long n_bigdir = 0;
+    long long *bigrow = nullptr;  // [n_big + 1] prefix of their chunks of 256 rows
+    long long n_bigrow = 0;
+    double2 *big_part = nullptr;  // [n_bigrow] per-chunk measures of the sweeps
     int n_phase = 1;
     double hg_g[4] = {0, 0, 0, 0};
     int phase_kind[4] = {0, 0, 0, 0};  // SG_PHASE_HG, SG_PHASE_RAYLEIGH, SG_PHASE_TABLE

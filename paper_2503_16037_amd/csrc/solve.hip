@@ -317,94 +317,142 @@ __global__ __launch_bounds__(kSpmvThreads) void k_apply_imk64(int N, const long 
     if (act) wv[b] = v[b] - acc;
 }
 
+// Row n of a node block of degree d times the staged inputs xin, summed in increasing
+// column order (as node_row); eight columns' values are loaded before their products so
+// that the loads overlap (32 measured slower).
+template <class Acc, class Real, class XT>
+__device__ __forceinline__ Acc big_row(const Real *__restrict__ blk, const XT *__restrict__ xin, int d, int n) {
+    constexpr int kB = 8;
+    Acc acc = (Acc)0;
+    int m = 0;
+    for (; m + kB <= d; m += kB) {
+        Real v[kB];
+#pragma unroll
+        for (int j = 0; j < kB; ++j) v[j] = blk[(long long)(m + j) * d + n];
+#pragma unroll
+        for (int j = 0; j < kB; ++j) acc += (Acc)v[j] * (Acc)xin[m + j];
+    }
+    for (; m < d; ++m) acc += (Acc)blk[(long long)m * d + n] * (Acc)xin[m];
+    return acc;
+}
+
 // Nodes of degree above 64 (graphs whose strongest couplings gather on the dense
-// nodes): one 256-thread workgroup per node, the node's gathered inputs staged in LDS,
-// each thread a set of rows r = t, t + 256, ..., every row's sum over the columns in
-// increasing order as in node_row; the node's measures by a fixed-order block
-// reduction.  big[] lists the nodes, in id order.
+// nodes): one 256-thread workgroup per (node, chunk of 256 rows), wg = bigrow[b] + c, so
+// that a node of thousands of couplings is spread over many CUs; each workgroup stages
+// the node's gathered inputs in LDS and each thread computes one row with the columns in
+// increasing order.  Measures: each chunk writes its (sum, max) in FP64 to part[wg], and
+// k_big_measures folds a node's chunks in order into meas[node].
+__device__ __forceinline__ int big_locate(int nbig, const long long *__restrict__ bigrow, long long wg) {
+    int lo = 0, hi = nbig;  // the node b with bigrow[b] <= wg < bigrow[b + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (bigrow[mid] <= wg) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 template <class Real>
-__global__ __launch_bounds__(256) void k_spmv_big(const int *__restrict__ big, const long long *__restrict__ adj_ptr,
+__global__ __launch_bounds__(256) void k_spmv_big(int nbig, const int *__restrict__ big,
+                                                 const long long *__restrict__ bigrow,
+                                                 const long long *__restrict__ adj_ptr,
                                                  const long long *__restrict__ nodeoff, const int *__restrict__ rev,
                                                  const Real *__restrict__ val, const Real *__restrict__ S,
                                                  const Real *__restrict__ x, Real *__restrict__ y,
-                                                 float2 *__restrict__ meas, int monitor) {
+                                                 double2 *__restrict__ part, int monitor) {
     extern __shared__ unsigned char smem_raw[];
     Real *xin = reinterpret_cast<Real *>(smem_raw);
-    const int l = big[blockIdx.x];
+    const long long wg = blockIdx.x;
+    const int b = big_locate(nbig, bigrow, wg);
+    const int l = big[b];
     const long long off = adj_ptr[l], base = nodeoff[l];
     const int d = (int)(adj_ptr[l + 1] - off);
     for (int m = threadIdx.x; m < d; m += 256) xin[m] = x[rev[off + m]];
     __syncthreads();
+    const int n = (int)(wg - bigrow[b]) * 256 + threadIdx.x;
     double r = 0.0, u = 0.0;
-    for (int n = threadIdx.x; n < d; n += 256) {
-        Real acc = (Real)0;
-        for (int m = 0; m < d; ++m) acc += val[base + (long long)m * d + n] * xin[m];
+    if (n < d) {
+        const Real acc = big_row<Real>(val + base, xin, d, n);
         const Real yn = S[off + n] + acc;
         y[off + n] = yn;
         if (monitor) {
-            const double dr = fabs((double)yn - (double)x[off + n]);
-            r += dr;
-            u = fmax(u, dr / (fabs((double)yn) + kRelFloor));
+            r = fabs((double)yn - (double)x[off + n]);
+            u = r / (fabs((double)yn) + kRelFloor);
         }
     }
     if (monitor) {
         r = block_sum<256>(r);
         u = block_max<256>(u);
-        if (threadIdx.x == 0) meas[l] = make_float2((float)r, (float)u);
+        if (threadIdx.x == 0) part[wg] = make_double2(r, u);
     }
 }
 
 // r = S - x + K x in FP64 for the nodes of degree above 64 (see k_spmv_big).
 template <class Real>
-__global__ __launch_bounds__(256) void k_residual64_big(const int *__restrict__ big,
+__global__ __launch_bounds__(256) void k_residual64_big(int nbig, const int *__restrict__ big,
+                                                       const long long *__restrict__ bigrow,
                                                        const long long *__restrict__ adj_ptr,
                                                        const long long *__restrict__ nodeoff,
                                                        const int *__restrict__ rev, const Real *__restrict__ val,
                                                        const Real *__restrict__ S, const double *__restrict__ x,
-                                                       double *__restrict__ res, float2 *__restrict__ meas) {
+                                                       double *__restrict__ res, double2 *__restrict__ part) {
     extern __shared__ unsigned char smem_raw[];
     double *xin = reinterpret_cast<double *>(smem_raw);
-    const int l = big[blockIdx.x];
+    const long long wg = blockIdx.x;
+    const int b = big_locate(nbig, bigrow, wg);
+    const int l = big[b];
     const long long off = adj_ptr[l], base = nodeoff[l];
     const int d = (int)(adj_ptr[l + 1] - off);
     for (int m = threadIdx.x; m < d; m += 256) xin[m] = x[rev[off + m]];
     __syncthreads();
+    const int n = (int)(wg - bigrow[b]) * 256 + threadIdx.x;
     double a = 0.0, u = 0.0;
-    for (int n = threadIdx.x; n < d; n += 256) {
-        double acc = 0.0;
-        for (int m = 0; m < d; ++m) acc += (double)val[base + (long long)m * d + n] * xin[m];
+    if (n < d) {
+        const double acc = big_row<double>(val + base, xin, d, n);
         const double xb = x[off + n];
         const double rb = ((double)S[off + n] - xb) + acc;
         res[off + n] = rb;
-        a += fabs(rb);
-        u = fmax(u, fabs(rb) / (fabs(xb) + kRelFloor));
+        a = fabs(rb);
+        u = a / (fabs(xb) + kRelFloor);
     }
     a = block_sum<256>(a);
     u = block_max<256>(u);
-    if (threadIdx.x == 0) meas[l] = make_float2((float)a, (float)u);
+    if (threadIdx.x == 0) part[wg] = make_double2(a, u);
 }
 
 // w = v - K v in FP64 for the nodes of degree above 64.
 template <class Real>
-__global__ __launch_bounds__(256) void k_apply_imk64_big(const int *__restrict__ big,
+__global__ __launch_bounds__(256) void k_apply_imk64_big(int nbig, const int *__restrict__ big,
+                                                        const long long *__restrict__ bigrow,
                                                         const long long *__restrict__ adj_ptr,
                                                         const long long *__restrict__ nodeoff,
                                                         const int *__restrict__ rev, const Real *__restrict__ val,
                                                         const double *__restrict__ v, double *__restrict__ wv) {
     extern __shared__ unsigned char smem_raw[];
     double *xin = reinterpret_cast<double *>(smem_raw);
-    const int l = big[blockIdx.x];
+    const long long wg = blockIdx.x;
+    const int b = big_locate(nbig, bigrow, wg);
+    const int l = big[b];
     const long long off = adj_ptr[l], base = nodeoff[l];
     const int d = (int)(adj_ptr[l + 1] - off);
     for (int m = threadIdx.x; m < d; m += 256) xin[m] = v[rev[off + m]];
     __syncthreads();
-    for (int n = threadIdx.x; n < d; n += 256) {
-        double acc = 0.0;
-        for (int m = 0; m < d; ++m) acc += (double)val[base + (long long)m * d + n] * xin[m];
-        wv[off + n] = v[off + n] - acc;
-    }
+    const int n = (int)(wg - bigrow[b]) * 256 + threadIdx.x;
+    if (n < d) wv[off + n] = v[off + n] - big_row<double>(val + base, xin, d, n);
 }
 
+// meas[node] of the nodes of degree above 64: their chunks' (sum, max) folded in order.
+__global__ __launch_bounds__(256) void k_big_measures(int nbig, const int *__restrict__ big,
+                                                     const long long *__restrict__ bigrow,
+                                                     const double2 *__restrict__ part, float2 *__restrict__ meas) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nbig) return;
+    double r = 0.0, u = 0.0;
+    for (long long c = bigrow[b]; c < bigrow[b + 1]; ++c) {
+        r += part[c].x;
+        u = fmax(u, part[c].y);
+    }
+    meas[big[b]] = make_float2((float)r, (float)u);
+}
 
 // partial[j * nblk + block] = sum_i V[j][i] w[i], j < k (one pass over w).
 __global__ __launch_bounds__(kVecThreads) void k_dot_multi(const double *__restrict__ V, long long ld, int k,
@@ -512,9 +560,14 @@ void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y
     grid = std::min(grid, spmv_blocks(s));
     hipLaunchKernelGGL((k_spmv<Real>), dim3(grid), dim3(kSpmvThreads), block_lds<Real>(s), st, s.N, spmv_blocks(s),
                        s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x, y, s.meas, out ? 1 : 0, lds_dmax<Real>(s));
-    if (s.n_big)
-        hipLaunchKernelGGL((k_spmv_big<Real>), dim3(s.n_big), dim3(256), sizeof(Real) * s.dmax, st, s.big, s.adj_ptr,
-                           s.nodeoff, s.rev, (const Real *)s.val, S, x, y, s.meas, out ? 1 : 0);
+    if (s.n_big) {
+        hipLaunchKernelGGL((k_spmv_big<Real>), dim3(s.n_bigrow), dim3(256), sizeof(Real) * s.dmax, st, s.n_big, s.big,
+                           s.bigrow, s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x, y, s.big_part,
+                           out ? 1 : 0);
+        if (out)
+            hipLaunchKernelGGL(k_big_measures, dim3((s.n_big + 255) / 256), dim3(256), 0, st, s.n_big, s.big, s.bigrow,
+                               s.big_part, s.meas);
+    }
     if (after) (void)hipEventRecord(after, st);
     if (out) launch_measures(s, 1, out, st);
 }
@@ -531,9 +584,12 @@ void launch_residual64(Scene &s, hipStream_t st, const Real *S, const double *x6
     hipLaunchKernelGGL((k_residual64<Real>), dim3(default_grid(s)), dim3(kSpmvThreads), block_lds<Real>(s), st,
                        s.N, spmv_blocks(s), s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x64, r64, s.meas,
                        lds_dmax<Real>(s));
-    if (s.n_big)
-        hipLaunchKernelGGL((k_residual64_big<Real>), dim3(s.n_big), dim3(256), sizeof(double) * s.dmax, st, s.big,
-                           s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x64, r64, s.meas);
+    if (s.n_big) {
+        hipLaunchKernelGGL((k_residual64_big<Real>), dim3(s.n_bigrow), dim3(256), sizeof(double) * s.dmax, st, s.n_big,
+                           s.big, s.bigrow, s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x64, r64, s.big_part);
+        hipLaunchKernelGGL(k_big_measures, dim3((s.n_big + 255) / 256), dim3(256), 0, st, s.n_big, s.big, s.bigrow,
+                           s.big_part, s.meas);
+    }
     launch_measures(s, 1, out, st);
 }
 
@@ -542,8 +598,8 @@ void launch_apply_imk64(Scene &s, hipStream_t st, const double *v, double *w) {
     hipLaunchKernelGGL((k_apply_imk64<Real>), dim3(spmv_blocks(s)), dim3(kSpmvThreads), block_lds<Real>(s), st, s.N,
                        s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, v, w, lds_dmax<Real>(s));
     if (s.n_big)
-        hipLaunchKernelGGL((k_apply_imk64_big<Real>), dim3(s.n_big), dim3(256), sizeof(double) * s.dmax, st, s.big,
-                           s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, v, w);
+        hipLaunchKernelGGL((k_apply_imk64_big<Real>), dim3(s.n_bigrow), dim3(256), sizeof(double) * s.dmax, st,
+                           s.n_big, s.big, s.bigrow, s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, v, w);
 }
 
 void launch_measures(Scene &s, int nl, double *out, hipStream_t st) {
