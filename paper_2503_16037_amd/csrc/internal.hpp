@@ -216,9 +216,10 @@ void launch_qbuild(Scene &s, hipStream_t st, int write_q);
 
 template <class Real>
 // one sweep y = S + K x; out[0..1] = measures of y - x (see launch_measures);
-// after: an event recorded right after the sweep kernel
+// after: an event recorded right after the sweep kernel; with_big = false leaves out the
+// nodes of degree above 64 (the launch-shape tuner times the regular kernel alone)
 void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *out, int grid = 0,
-                 hipEvent_t after = nullptr);
+                 hipEvent_t after = nullptr, bool with_big = true);
 // the first Neumann iterate from x = 0: x = rhs; out[0..1] = measures of that update
 template <class Real>
 void launch_first(Scene &s, hipStream_t st, const Real *rhs, Real *x, double *out);

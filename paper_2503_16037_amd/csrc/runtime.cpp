@@ -120,7 +120,7 @@ int spmv_grid(Scene &s, hipStream_t st, const Real *S, Real *x, Real *y, bool au
         double *scratch = s.scal + 200;  // two measures (the tuned sweeps are monitored ones)
         launch_fill<Real>(x, (Real)0, s.E, st);  // x and y are scratch vectors here
         grid = time_candidates(st, grid_candidates(spmv_blocks(s)),
-                               [&](const Shape &c) { launch_spmv<Real>(s, st, S, x, y, scratch, c.grid); })
+                               [&](const Shape &c) { launch_spmv<Real>(s, st, S, x, y, scratch, c.grid, nullptr, false); })
                    .grid;
         if (grid) store_cache_locked(k, Shape{grid, 0});
     }

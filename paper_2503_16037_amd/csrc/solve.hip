@@ -555,12 +555,12 @@ static int default_grid(const Scene &s) { return spmv_blocks(s); }
 
 template <class Real>
 void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y, double *out, int grid,
-                 hipEvent_t after) {
+                 hipEvent_t after, bool with_big) {
     if (grid <= 0) grid = default_grid(s);
     grid = std::min(grid, spmv_blocks(s));
     hipLaunchKernelGGL((k_spmv<Real>), dim3(grid), dim3(kSpmvThreads), block_lds<Real>(s), st, s.N, spmv_blocks(s),
                        s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x, y, s.meas, out ? 1 : 0, lds_dmax<Real>(s));
-    if (s.n_big) {
+    if (s.n_big && with_big) {
         hipLaunchKernelGGL((k_spmv_big<Real>), dim3(s.n_bigrow), dim3(256), sizeof(Real) * s.dmax, st, s.n_big, s.big,
                            s.bigrow, s.adj_ptr, s.nodeoff, s.rev, (const Real *)s.val, S, x, y, s.big_part,
                            out ? 1 : 0);
@@ -646,7 +646,7 @@ void launch_fill(Real *a, Real v, int64_t n, hipStream_t st) {
 }
 
 #define SG_INST(R)                                                                                           \
-    template void launch_spmv<R>(Scene &, hipStream_t, const R *, const R *, R *, double *, int, hipEvent_t);               \
+    template void launch_spmv<R>(Scene &, hipStream_t, const R *, const R *, R *, double *, int, hipEvent_t, bool);               \
     template void launch_residual64<R>(Scene &, hipStream_t, const R *, const double *, double *, double *); \
     template void launch_first<R>(Scene &, hipStream_t, const R *, R *, double *);                          \
     template void launch_apply_imk64<R>(Scene &, hipStream_t, const double *, double *);                  \
