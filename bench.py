@@ -246,7 +246,7 @@ def bench_coupling(args):
 
     base = scenes.make_plume()
     ctx = sgrt.Context(0)
-    ks = (1, 2, 4, 8, 11.5, 16, 24)
+    ks = (args.couplings,) if args.couplings else (1, 2, 4, 8, 11.5, 16, 24)
     res = {}
     for k in ks:
         t = time.perf_counter()
@@ -374,6 +374,8 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--served", type=int, default=40, help="requests of the served stream (workload served)")
     ap.add_argument("--resident", type=int, default=4, help="resident scenes of the server (workload served)")
+    ap.add_argument("--couplings", type=float, default=None,
+                    help="workload coupling: only this many couplings per voxel (for profiling)")
     ap.add_argument("--sigma", default="voronoi", choices=["voronoi", "colour"],
                     help="phase cells: Voronoi ownership (default) or the paper's colouring with flood fill")
     args = ap.parse_args()
