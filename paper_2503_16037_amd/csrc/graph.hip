@@ -46,12 +46,14 @@ namespace sg {
 
 namespace {
 
-// box cells a candidate pass may visit (SG_GRAPH_CELL_BUDGET overrides it, e.g. to
-// exercise the streamed path on small inputs)
-unsigned long long cell_budget() {
+// box cells a candidate pass may visit: 2^26 first, then 2^28 and 2^30 when the fitted
+// threshold leaves fewer than n candidates (SG_GRAPH_CELL_BUDGET fixes a single budget,
+// e.g. to exercise the streamed path on small inputs)
+std::vector<unsigned long long> cell_budgets() {
     const char *v = std::getenv("SG_GRAPH_CELL_BUDGET");
     const unsigned long long b = v ? std::strtoull(v, nullptr, 10) : 0ull;
-    return b ? b : (1ull << 26);
+    if (b) return {b};
+    return {1ull << 26, 1ull << 28, 1ull << 30};
 }
 
 struct Geo {
@@ -614,27 +616,36 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
         GTRY(B.pairs(t_used, 1, 0, N, keys, codes, have));
         n_sel = ranked = have;
     } else {
-        // the lowest threshold (bisection in the exponent) whose boxes fit the cell budget
-        const unsigned long long budget = cell_budget();
+        // the lowest threshold (bisection in the exponent) whose boxes fit the cell budget;
+        // a larger budget when that threshold leaves fewer than n candidates
+        const std::vector<unsigned long long> budgets = cell_budgets();
+        const unsigned long long budget = budgets.back();
         double t_fit = 0.0;
         unsigned long long cells = 0;
         GTRY(B.cells(0.0, cells));
-        if (cells > budget) {
-            double lo = 1e-300, hi = 1e300;
-            GTRY(B.cells(hi, cells));
-            if (cells > budget) return gfail(SG_E_NOMEM, "coupling candidates exceed the cell budget");
-            // geometric bisection to a factor of two: any threshold within the budget
-            // gives the same selection, a tighter one only fewer candidates
-            while (hi > 2.0 * lo) {
-                const double mid = std::sqrt(lo) * std::sqrt(hi);
-                if (!(mid > lo && mid < hi)) break;
-                GTRY(B.cells(mid, cells));
-                if (cells <= budget) hi = mid;
-                else lo = mid;
+        const unsigned long long all_cells = cells;
+        for (size_t k = 0; k < budgets.size(); ++k) {
+            const unsigned long long bk = budgets[k];
+            t_fit = 0.0;
+            if (all_cells > bk) {
+                double lo = 1e-300, hi = 1e300;
+                GTRY(B.cells(hi, cells));
+                if (cells > bk) return gfail(SG_E_NOMEM, "coupling candidates exceed the cell budget");
+                // geometric bisection to a factor of two: any threshold within the budget
+                // gives the same selection, a tighter one only fewer candidates
+                while (hi > 2.0 * lo) {
+                    const double mid = std::sqrt(lo) * std::sqrt(hi);
+                    if (!(mid > lo && mid < hi)) break;
+                    GTRY(B.cells(mid, cells));
+                    if (cells <= bk) hi = mid;
+                    else lo = mid;
+                }
+                t_fit = hi;
             }
-            t_fit = hi;
+            have = 0;  // a retry replaces the candidates of a smaller budget
+            GTRY(B.pairs(t_fit, 0, 0, N, keys, codes, have));
+            if (have >= (unsigned long long)d->n_pairs || t_fit == 0.0) break;
         }
-        GTRY(B.pairs(t_fit, 0, 0, N, keys, codes, have));
         t_used = t_fit;
         ranked = have;
         if (have >= (unsigned long long)d->n_pairs || t_fit == 0.0) {
