@@ -124,3 +124,35 @@ def test_high_degree_limits(ctx):
         with pytest.raises(sgrt.SgError) as e:
             sgrt.Scene(ctx, bad)
         assert "64" in str(e.value)
+
+
+def star_scene(n_leaves):
+    """A volume node coupled to n_leaves others of a 17x16x16 grid, nothing else coupled:
+    the largest degree a scene takes (4096) on one node."""
+    sc = scenes.make_random_small(8, nx=17, ny=16, nz=16, kscale=0.5)
+    nvox, N = sc.nvox, sc.n_nodes
+    c = nvox // 2
+    leaves = np.array([v for v in range(nvox) if v != c][:n_leaves], np.int64)
+    rows = [[] for _ in range(N)]
+    rows[c] = list(leaves)
+    for v in leaves:
+        rows[v] = [c]
+    ap = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    ai = np.concatenate([np.asarray(r, np.int32) for r in rows if r]).astype(np.int32)
+    return dataclasses.replace(sc, adj_ptr=ap, adj_idx=ai)
+
+
+def test_largest_degree_star(ctx):
+    from paper_2503_16037_amd import sgrt
+    sc = star_scene(4096)
+    assert np.diff(sc.adj_ptr).max() == 4096
+    ora = oracle.run(sc)
+    with sgrt.Scene(ctx, sc) as g:
+        rad, info = g.solve(precision="fp64")
+        assert info["converged"] == 1
+        rp, col, val = g.export_csr()
+        assert np.array_equal(rp, ora["row_ptr"]) and np.array_equal(col, ora["col"])
+        assert rel_err(val, ora["val"]).max() < 1e-12
+        assert rel_err(rad, ora["radiance"]).max() < 1e-10
+    with pytest.raises(sgrt.SgError):
+        sgrt.Scene(ctx, star_scene(4097))
