@@ -1132,8 +1132,8 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     SG_TRY(dalloc(s, &s.pos, (size_t)3 * s.N));
     SG_TRY(dalloc(s, &s.adj_ptr, (size_t)s.N + 1));
     SG_TRY(dalloc(s, &s.adj_idx, (size_t)s.E));
-    // nodes of degree above one wavefront, and the prefix of their incoming directions
-    // (in-edges and the sun; one for a surface node)
+    // nodes of degree above one wavefront, and the prefix of their groups of incoming
+    // directions (in-edges and the sun; one for a surface node; qbuild_group_big per group)
     // and of their chunks of 256 rows (the sweeps' workgroups)
     std::vector<int> bigv;
     std::vector<long long> bigdir(1, 0), bigrow(1, 0);
@@ -1141,7 +1141,8 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
         const int64_t deg = d->adj_ptr[l + 1] - d->adj_ptr[l];
         if (deg > kMaxWaveDegree) {
             bigv.push_back((int)l);
-            bigdir.push_back(bigdir.back() + (l < s.nvox ? deg + 1 : 1));
+            const int64_t n_in = l < s.nvox ? deg + 1 : 1, G = qbuild_group_big(s.n_fib);
+            bigdir.push_back(bigdir.back() + (n_in + G - 1) / G);
             bigrow.push_back(bigrow.back() + (deg + 255) / 256);
         }
     }

@@ -75,7 +75,7 @@ struct Scene {
     // sweeps, one per (node, incoming direction) in the phase cells)
     int n_big = 0;
     int *big = nullptr;           // [n_big] node ids, ascending
-    long long *bigdir = nullptr;  // [n_big + 1] prefix of their incoming-direction counts
+    long long *bigdir = nullptr;  // [n_big + 1] prefix of their groups of incoming directions
     long long n_bigdir = 0;
     long long *bigrow = nullptr;  // [n_big + 1] prefix of their chunks of 256 rows
     long long n_bigrow = 0;
@@ -213,6 +213,10 @@ template <class Real>
 void launch_node_weights(Scene &s, hipStream_t st, float scale);
 template <class Real>
 void launch_qbuild(Scene &s, hipStream_t st, int write_q);
+// incoming directions the phase-cell kernels take per group (a lattice of NF points), and
+// per workgroup of the kernel for nodes of degree above 64
+int qbuild_group(int NF);
+int qbuild_group_big(int NF);
 
 template <class Real>
 // one sweep y = S + K x; out[0..1] = measures of y - x (see launch_measures);

@@ -204,10 +204,25 @@ __global__ __launch_bounds__(64) void k_qbuild(
 }
 
 // Nodes of degree above 64 (graphs whose strongest couplings gather on the dense nodes):
-// one 64-lane workgroup per (node, incoming direction), wg = bigdir[b] + a.  The
-// lattice points are the lanes' (i and i + 64); the node's out-edge directions are
-// formed in LDS 64 at a time and scanned in ascending order with the operation sequence
-// and tie rule of k_qbuild; the direction's d cell sums sit in LDS (dynamic, d words).
+// one 64-lane workgroup per (node, group of `group` incoming directions), wg = bigdir[b] +
+// g.  The (direction, lattice point) pairs fill the lanes' eight slots as in k_qbuild, and
+// the node's out-edge directions are formed in LDS 64 at a time and scanned in ascending
+// order with k_qbuild's operation sequence and tie rule, so each direction read from LDS
+// serves eight dot products.  A direction's lattice points have at most N_fib distinct
+// owners among the d out-edges, so its cell sums go to a 256-slot open-addressing table in
+// LDS (owner -> fixed-point sum, exact integer atomics) rather than d words; the column is
+// then written by looking every row up (absent: 0).
+constexpr int kCellHash = 256;  // above the most owners a direction can have (N_fib <= 128)
+constexpr int kBigGroup = 5;    // directions per workgroup (the tables' LDS)
+
+constexpr unsigned short kNoOwner = 0xffff;  // owners are below 4096
+
+__device__ __forceinline__ int cell_find(const unsigned short *keys, int m) {
+    int h = m & (kCellHash - 1);
+    while (keys[h] != m && keys[h] != kNoOwner) h = (h + 1) & (kCellHash - 1);
+    return keys[h] == m ? h : -1;
+}
+
 template <class Real, class BlkT, bool kWriteQ>
 __global__ __launch_bounds__(64) void k_qbuild_big(
     int nbig, const int *__restrict__ big, const long long *__restrict__ bigdir, int nvox,
@@ -215,11 +230,12 @@ __global__ __launch_bounds__(64) void k_qbuild_big(
     const double *__restrict__ lat, const double *__restrict__ tab, int NF, int n_phase,
     const float *__restrict__ frac, double sun_x, double sun_y, double sun_z, Real mu0, const Real *__restrict__ T,
     const Real *__restrict__ rho, const Real *__restrict__ Tsun, const long long *__restrict__ nodeoff,
-    BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun, int per, long long wx, long long wy) {
+    BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun, int group, int per, long long wx,
+    long long wy) {
 #pragma clang fp contract(off)
-    extern __shared__ unsigned long long cell[];  // [d] fixed-point sums
-    __shared__ double cx[64], cy[64], cz[64];
-    __shared__ unsigned long long wq[128];
+    __shared__ double cx[64], cy[64], cz[64], Rg[kBigGroup * 9], lt[384];
+    __shared__ unsigned long long wq[128], hval[kBigGroup][kCellHash];
+    __shared__ unsigned short hkey[kBigGroup][kCellHash];
     const long long wg = blockIdx.x;
     int lo = 0, hi = nbig;  // the node b with bigdir[b] <= wg < bigdir[b + 1]
     while (hi - lo > 1) {
@@ -227,11 +243,13 @@ __global__ __launch_bounds__(64) void k_qbuild_big(
         if (bigdir[mid] <= wg) lo = mid; else hi = mid;
     }
     const int l = big[lo];
-    const int a = (int)(wg - bigdir[lo]);
     const int lane = threadIdx.x;
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
     const bool surf = l >= nvox;
+    const int n_in = surf ? 1 : d + 1;
+    const int a0 = (int)(wg - bigdir[lo]) * group;
+    const int ng = min(group, n_in - a0);
     // the unit direction of out-edge m (the operation sequence of k_qbuild)
     auto edge_dir = [&](int m, double &ex, double &ey, double &ez) {
         const int j = adj_idx[off + m];
@@ -244,6 +262,9 @@ __global__ __launch_bounds__(64) void k_qbuild_big(
         ez = (double)Dz / nrm;
     };
     for (int i = lane; i < NF; i += 64) {
+        lt[i] = lat[3 * i];
+        lt[128 + i] = lat[3 * i + 1];
+        lt[256 + i] = lat[3 * i + 2];
         double w;
         if (surf) {
             w = tab[n_phase * NF + i];
@@ -256,40 +277,53 @@ __global__ __launch_bounds__(64) void k_qbuild_big(
         }
         wq[i] = (unsigned long long)llrint(w * kFix);
     }
-    for (int m = lane; m < d; m += 64) cell[m] = 0ull;
-    // the rotation of this incoming direction (every lane, the same values)
-    double R[9];
-    if (surf) {
-        R[0] = 1.0; R[1] = 0.0; R[2] = 0.0; R[3] = 0.0; R[4] = 1.0; R[5] = 0.0; R[6] = 0.0; R[7] = 0.0; R[8] = 1.0;
-    } else {
-        double ux, uy, uz;
-        if (a < d) {
-            edge_dir(a, ux, uy, uz);
-            ux = -ux; uy = -uy; uz = -uz;
+    for (int t = lane; t < ng * kCellHash; t += 64) {
+        hkey[t / kCellHash][t % kCellHash] = kNoOwner;
+        hval[t / kCellHash][t % kCellHash] = 0ull;
+    }
+    // rotations of this group's incoming directions
+    if (lane < ng) {
+        const int a = a0 + lane;
+        double *R = Rg + 9 * lane;
+        if (surf) {
+            R[0] = 1.0; R[1] = 0.0; R[2] = 0.0; R[3] = 0.0; R[4] = 1.0; R[5] = 0.0; R[6] = 0.0; R[7] = 0.0; R[8] = 1.0;
         } else {
-            ux = sun_x; uy = sun_y; uz = sun_z;
-        }
-        if (1.0 + uz < 1e-12) {
-            R[0] = 1.0; R[1] = 0.0; R[2] = 0.0; R[3] = 0.0; R[4] = -1.0; R[5] = 0.0; R[6] = 0.0; R[7] = 0.0;
-            R[8] = -1.0;
-        } else {
-            const double h = 1.0 / (1.0 + uz);
-            const double xy = (ux * uy) * h;
-            R[0] = uz + (uy * uy) * h; R[1] = -xy; R[2] = -ux;
-            R[3] = -xy; R[4] = uz + (ux * ux) * h; R[5] = -uy;
-            R[6] = ux; R[7] = uy; R[8] = uz;
+            double ux, uy, uz;
+            if (a < d) {
+                edge_dir(a, ux, uy, uz);
+                ux = -ux; uy = -uy; uz = -uz;
+            } else {
+                ux = sun_x; uy = sun_y; uz = sun_z;
+            }
+            if (1.0 + uz < 1e-12) {
+                R[0] = 1.0; R[1] = 0.0; R[2] = 0.0; R[3] = 0.0; R[4] = -1.0; R[5] = 0.0; R[6] = 0.0; R[7] = 0.0;
+                R[8] = -1.0;
+            } else {
+                const double h = 1.0 / (1.0 + uz);
+                const double xy = (ux * uy) * h;
+                R[0] = uz + (uy * uy) * h; R[1] = -xy; R[2] = -ux;
+                R[3] = -xy; R[4] = uz + (ux * ux) * h; R[5] = -uy;
+                R[6] = ux; R[7] = uy; R[8] = uz;
+            }
         }
     }
-    const int i0 = lane, i1 = lane + 64;
-    double q[2][3], best[2];
-    int own[2] = {0, 0};
-    for (int h2 = 0; h2 < 2; ++h2) {
-        const int i = min(h2 ? i1 : i0, NF - 1);
-        const double x = lat[3 * i], y = lat[3 * i + 1], z = lat[3 * i + 2];
-        q[h2][0] = fma(R[6], z, fma(R[3], y, R[0] * x));
-        q[h2][1] = fma(R[7], z, fma(R[4], y, R[1] * x));
-        q[h2][2] = fma(R[8], z, fma(R[5], y, R[2] * x));
-        best[h2] = -__builtin_inf();
+    __syncthreads();
+    // this lane's pairs: q = R^T p
+    const int np = ng * NF;
+    const float inv_nf = 1.0f / (float)NF;
+    double q0[kQSlots], q1[kQSlots], q2[kQSlots], best[kQSlots];
+    int own[kQSlots];
+#pragma unroll
+    for (int j = 0; j < kQSlots; ++j) {
+        const int p = min(j * 64 + lane, np - 1);  // past the last pair: a repeat, not counted
+        const int al = small_div(p, inv_nf), i = p - al * NF;
+        const double *R = Rg + 9 * al;
+        const double x = lt[i], y = lt[128 + i], z = lt[256 + i];
+        q0[j] = fma(R[6], z, fma(R[3], y, R[0] * x));
+        q1[j] = fma(R[7], z, fma(R[4], y, R[1] * x));
+        q2[j] = fma(R[8], z, fma(R[5], y, R[2] * x));
+        best[j] = -__builtin_inf();
+        own[j] = 0;
     }
     for (int m0 = 0; m0 < d; m0 += 64) {
         const int nm = min(64, d - m0);
@@ -298,43 +332,59 @@ __global__ __launch_bounds__(64) void k_qbuild_big(
         for (int mm = 0; mm < nm; ++mm) {
             const double tx = cx[mm], ty = cy[mm], tz = cz[mm];
 #pragma unroll
-            for (int h2 = 0; h2 < 2; ++h2) {
-                const double v = fma(q[h2][2], tz, fma(q[h2][1], ty, q[h2][0] * tx));
-                own[h2] = v > best[h2] ? m0 + mm : own[h2];
-                best[h2] = fmax(best[h2], v);
+            for (int j = 0; j < kQSlots; ++j) {
+                const double v = fma(q2[j], tz, fma(q1[j], ty, q0[j] * tx));
+                own[j] = v > best[j] ? m0 + mm : own[j];
+                best[j] = fmax(best[j], v);
             }
         }
         __syncthreads();  // the next chunk rewrites the directions
     }
-    if (i0 < NF) atomicAdd(&cell[own[0]], wq[i0]);
-    if (i1 < NF) atomicAdd(&cell[own[1]], wq[i1]);
+    // cell sums: owner -> fixed-point sum in the direction's table
+#pragma unroll
+    for (int j = 0; j < kQSlots; ++j) {
+        const int p = j * 64 + lane;
+        if (p < np) {
+            const int al = small_div(p, inv_nf);
+            unsigned short *keys = hkey[al];
+            const unsigned short key = (unsigned short)own[j];
+            int h = own[j] & (kCellHash - 1);
+            while (true) {
+                const unsigned short old = atomicCAS(&keys[h], kNoOwner, key);
+                if (old == kNoOwner || old == key) break;
+                h = (h + 1) & (kCellHash - 1);
+            }
+            atomicAdd(&hval[al][h], wq[p - al * NF]);
+        }
+    }
     __syncthreads();
     const Real rl = rho ? rho[l] : (Real)0;
     const Real tsun = Tsun ? Tsun[l] : (Real)0;
     BlkT *blk = val + nodeoff[l];  // column-major: element (row n, column m) at m d + n
-    for (int m = lane; m < d; m += 64) {
-        const double Q = (double)(long long)cell[m] * kUnfix;
-        const long long b = off + m;
-        if (surf) {
-            for (int c = 0; c < d; ++c) {
-                if (kWriteQ) blk[(long long)c * d + m] = (BlkT)Q;
-                else blk[(long long)c * d + m] = (BlkT)(T[off + c] * rl * (Real)Q);
+    for (int al = 0; al < ng; ++al) {
+        const int a = a0 + al;
+        for (int m = lane; m < d; m += 64) {
+            const int h = cell_find(hkey[al], m);
+            const double Q = h < 0 ? 0.0 : (double)(long long)hval[al][h] * kUnfix;
+            const long long b = off + m;
+            if (surf) {
+                for (int c = 0; c < d; ++c) {
+                    if (kWriteQ) blk[(long long)c * d + m] = (BlkT)Q;
+                    else blk[(long long)c * d + m] = (BlkT)(T[off + c] * rl * (Real)Q);
+                }
+                if (!kWriteQ) S[b] = rl * mu0 * tsun * (Real)Q;
+                qsun[b] = (float)Q;
+            } else if (a < d) {
+                if (kWriteQ) blk[(long long)a * d + m] = (BlkT)Q;
+                else blk[(long long)a * d + m] = (BlkT)(T[off + a] * rl * (Real)Q);
+            } else {
+                if (!kWriteQ) S[b] = tsun * rl * (Real)Q;
+                qsun[b] = (float)Q;
             }
-            if (!kWriteQ) S[b] = rl * mu0 * tsun * (Real)Q;
-            qsun[b] = (float)Q;
-        } else if (a < d) {
-            if (kWriteQ) blk[(long long)a * d + m] = (BlkT)Q;
-            else blk[(long long)a * d + m] = (BlkT)(T[off + a] * rl * (Real)Q);
-        } else {
-            if (!kWriteQ) S[b] = tsun * rl * (Real)Q;
-            qsun[b] = (float)Q;
         }
     }
 }
 
-
-// directions per group: as many as fill the lanes' pair slots
-int qbuild_group(int NF) { return std::max(1, std::min(kQMaxGroup, kQSlots * 64 / NF)); }
 
 // The paper's discretisation of Sigma (Sec. 3), for scenes that ask for it: per
 // incoming direction, every out-edge direction colours its closest lattice point and
@@ -547,6 +597,10 @@ __global__ __launch_bounds__(64) void k_qcolour(
 
 }  // namespace
 
+// directions per group: as many as fill the lanes' pair slots
+int qbuild_group(int NF) { return std::max(1, std::min(kQMaxGroup, kQSlots * 64 / NF)); }
+int qbuild_group_big(int NF) { return std::min(qbuild_group(NF), kBigGroup); }
+
 template <class Real>
 void launch_qbuild(Scene &s, hipStream_t st, int write_q) {
     const size_t shm = 0;
@@ -568,19 +622,20 @@ void launch_qbuild(Scene &s, hipStream_t st, int write_q) {
         return;
     }
     if (s.n_big) {  // nodes of degree above 64
-        const size_t cells = sizeof(unsigned long long) * s.dmax;
         if (write_q)
-            hipLaunchKernelGGL((k_qbuild_big<Real, float, true>), dim3(s.n_bigdir), dim3(64), cells, st, s.n_big, s.big,
+            hipLaunchKernelGGL((k_qbuild_big<Real, float, true>), dim3(s.n_bigdir), dim3(64), 0, st, s.n_big, s.big,
                                s.bigdir, s.nvox, s.adj_ptr, s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac,
                                s.sun_in[0], s.sun_in[1], s.sun_in[2], (Real)s.mu0, (const Real *)nullptr,
                                (const Real *)nullptr, (const Real *)nullptr, s.nodeoff, s.q, (Real *)nullptr, s.qsun,
-                               s.periodic, (long long)s.nx * kFx, (long long)s.ny * kFx);
+                               qbuild_group_big(s.n_fib), s.periodic, (long long)s.nx * kFx,
+                               (long long)s.ny * kFx);
         else
-            hipLaunchKernelGGL((k_qbuild_big<Real, Real, false>), dim3(s.n_bigdir), dim3(64), cells, st, s.n_big, s.big,
+            hipLaunchKernelGGL((k_qbuild_big<Real, Real, false>), dim3(s.n_bigdir), dim3(64), 0, st, s.n_big, s.big,
                                s.bigdir, s.nvox, s.adj_ptr, s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac,
                                s.sun_in[0], s.sun_in[1], s.sun_in[2], (Real)s.mu0, (const Real *)s.T,
                                (const Real *)s.rho, (const Real *)s.Tsun, s.nodeoff, (Real *)s.val, (Real *)s.S, s.qsun,
-                               s.periodic, (long long)s.nx * kFx, (long long)s.ny * kFx);
+                               qbuild_group_big(s.n_fib), s.periodic, (long long)s.nx * kFx,
+                               (long long)s.ny * kFx);
     }
     if (write_q) {
         hipLaunchKernelGGL((k_qbuild<Real, float, true>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
