@@ -245,6 +245,8 @@ def bench_coupling(args):
     from paper_2503_16037_amd import scenes, sgrt
 
     base = scenes.make_plume()
+    if args.sigma == "colour":
+        base = base.with_(sigma_mode=1)
     ctx = sgrt.Context(0)
     ks = (args.couplings,) if args.couplings else (1, 2, 4, 8, 11.5, 16, 24)
     res = {}
@@ -283,7 +285,8 @@ def bench_coupling(args):
            "unit": "mean relative difference of the second largest graph from the largest", "n_gpus": 1, "steps": len(table),
            "warmup": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f32", "vs_baseline": None,
            "scaling": "weak", "ms_per_step": None,
-           "config": {"workload": "plume-64x64x32 (seed 2) nodes, strongest couplings k x voxels, k = 1..24"},
+           "config": {"workload": "plume-64x64x32 (seed 2) nodes, strongest couplings k x voxels, k = 1..24",
+                      "phase_cells": args.sigma},
            "sweep": table,
            "radius_graph": {"couplings": int(base.adj_ptr[-1]), "mean_rel_diff": float(dr.mean()),
                             "p99_rel_diff": float(np.percentile(dr, 99)), "ms_total": round(info_r["ms_total"], 2)}}

@@ -106,10 +106,9 @@ typedef struct sg_scene_desc {
     const int64_t *adj_ptr;    /* [N + 1] symmetric adjacency CSR over node ids */
     const int32_t *adj_idx;    /* [E] heads, ascending within a row, no self loops,
                                   no surface-surface pairs; node degree <= 4096 for one
-                                  wavelength with SG_SIGMA_VORONOI (nodes above 64 have
-                                  their own kernels: the strongest couplings of Eq. 4 gather
-                                  on dense nodes), <= 64 with several wavelengths or
-                                  SG_SIGMA_COLOUR */
+                                  wavelength (nodes above 64 have their own kernels: the
+                                  strongest couplings of Eq. 4 gather on dense nodes),
+                                  <= 64 with several wavelengths */
     const float *surf_albedo;  /* [ny][nx] Lambertian albedo in [0, 1] */
     int32_t sun_dir[3];        /* integer vector toward the sun (z > 0), |components| <= 2^22 */
     int32_t view_dir[3];       /* integer vector toward the sensor (z > 0), |components| <= 2^22 */
@@ -339,7 +338,8 @@ typedef struct sg_graph_desc {
  * ascending; n_edges = twice the selected pairs.  When adj_idx is NULL or
  * cap < n_edges, only adj_ptr (if not NULL) and *n_edges are written (a size
  * query; the work is redone by the next call).  Node degrees are not capped:
- * sg_scene_create accepts degrees up to 64.  info (optional) receives counts
+ * sg_scene_create accepts degrees up to 4096 for one wavelength and 64 for
+ * several.  info (optional) receives counts
  * and timings of the build.
  * Errors: SG_E_ABI, SG_E_INVALID (with the reason), SG_E_NOMEM, SG_E_DEVICE.
  */

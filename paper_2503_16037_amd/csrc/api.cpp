@@ -270,13 +270,13 @@ sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz,
     if (E > 0 && !d->adj_idx) return fail(SG_E_INVALID, "adj_idx is NULL");
     nnz = 0;
     dmax = 0;
-    const bool wave_only = d->n_lambda > 1 || d->sigma_mode == SG_SIGMA_COLOUR;
+    const bool wave_only = d->n_lambda > 1;
     const int64_t deg_cap = wave_only ? kMaxWaveDegree : kMaxDegree;
     for (int64_t l = 0; l < N; ++l) {
         const int64_t deg = ap[l + 1] - ap[l];
         if (deg > deg_cap)
             return fail(SG_E_INVALID, "node degree above " + std::to_string(deg_cap) + " (node " + std::to_string(l) +
-                                          (wave_only ? "; several wavelengths or SG_SIGMA_COLOUR allow 64)" : ")"));
+                                          (wave_only ? "; several wavelengths allow 64)" : ")"));
         dmax = std::max<int>(dmax, (int)deg);
         nnz += deg * deg;
         for (int64_t e = ap[l]; e < ap[l + 1]; ++e) {
@@ -1141,7 +1141,9 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
         const int64_t deg = d->adj_ptr[l + 1] - d->adj_ptr[l];
         if (deg > kMaxWaveDegree) {
             bigv.push_back((int)l);
-            const int64_t n_in = l < s.nvox ? deg + 1 : 1, G = qbuild_group_big(s.n_fib);
+            // one direction per workgroup for the colouring, groups for the Voronoi cells
+            const int64_t n_in = l < s.nvox ? deg + 1 : 1;
+            const int64_t G = s.sigma_mode == SG_SIGMA_COLOUR ? 1 : qbuild_group_big(s.n_fib);
             bigdir.push_back(bigdir.back() + (n_in + G - 1) / G);
             bigrow.push_back(bigrow.back() + (deg + 255) / 256);
         }

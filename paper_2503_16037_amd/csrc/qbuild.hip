@@ -418,7 +418,7 @@ __global__ __launch_bounds__(64) void k_qcolour(
     const int lane = threadIdx.x;
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
-    if (d == 0) return;
+    if (d == 0 || d > kWave) return;  // higher degree: k_qcolour_big
     const bool surf = l >= nvox;
     if (lane < d) {
         const int j = adj_idx[off + lane];
@@ -595,6 +595,203 @@ __global__ __launch_bounds__(64) void k_qcolour(
     }
 }
 
+// The colouring for nodes of degree above 64: one 64-lane workgroup per (node, incoming
+// direction), lattice points i and i + 64 in lane i, their rotated coordinates in LDS.
+//   seeds: lanes run over the out-directions m; each scans the lattice points in
+//   ascending order (strict >) for its seed and raises the point's best value (an
+//   order-preserving 64-bit key, atomic max); then every m whose seed value equals its
+//   point's best offers its index (atomic min): a point claimed several times goes to
+//   the largest value, ties to the lowest m, as claiming in order of m gives.
+//   fill and cells as in k_qcolour, the colours' sums in a hash table (at most N_fib
+//   colours among the d out-edges), the column written by looking up every row.
+__device__ __forceinline__ unsigned long long order_key(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double order_value(unsigned long long k) {
+    const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+template <class Real, class BlkT, bool kWriteQ>
+__global__ __launch_bounds__(64) void k_qcolour_big(
+    int nbig, const int *__restrict__ big, const long long *__restrict__ bigdir, int nvox,
+    const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx, const int *__restrict__ pos,
+    const double *__restrict__ lat, const double *__restrict__ tab, int NF, int n_phase,
+    const float *__restrict__ frac, double sun_x, double sun_y, double sun_z, Real mu0, const Real *__restrict__ T,
+    const Real *__restrict__ rho, const Real *__restrict__ Tsun, const long long *__restrict__ nodeoff,
+    BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun, const int *__restrict__ hull, int per,
+    long long wx, long long wy) {
+#pragma clang fp contract(off)
+    __shared__ double lq[3][128];
+    __shared__ unsigned long long bkey[128], wq[128], hval[kCellHash];
+    __shared__ int bown[128], col[128], snap[128], nnb[128];
+    __shared__ unsigned short hkey[kCellHash];
+    __shared__ unsigned char nbr[128][kHullNb];
+    __shared__ unsigned char seed_pt[kMaxDegree];
+    const long long wg = blockIdx.x;
+    int lo = 0, hi = nbig;  // the node b with bigdir[b] <= wg < bigdir[b + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (bigdir[mid] <= wg) lo = mid; else hi = mid;
+    }
+    const int l = big[lo];
+    const int a = (int)(wg - bigdir[lo]);
+    const int lane = threadIdx.x;
+    const long long off = adj_ptr[l];
+    const int d = (int)(adj_ptr[l + 1] - off);
+    const bool surf = l >= nvox;
+    auto edge_dir = [&](int m, double &ex, double &ey, double &ez) {
+        const int j = adj_idx[off + m];
+        const long long Dx = min_image((long long)pos[3 * j] - pos[3 * l], wx, per & 1);
+        const long long Dy = min_image((long long)pos[3 * j + 1] - pos[3 * l + 1], wy, per & 2);
+        const long long Dz = (long long)pos[3 * j + 2] - pos[3 * l + 2];
+        const double nrm = sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
+        ex = (double)Dx / nrm;
+        ey = (double)Dy / nrm;
+        ez = (double)Dz / nrm;
+    };
+    double R[9];
+    if (surf) {
+        R[0] = 1.0; R[1] = 0.0; R[2] = 0.0; R[3] = 0.0; R[4] = 1.0; R[5] = 0.0; R[6] = 0.0; R[7] = 0.0; R[8] = 1.0;
+    } else {
+        double ux, uy, uz;
+        if (a < d) {
+            edge_dir(a, ux, uy, uz);
+            ux = -ux; uy = -uy; uz = -uz;
+        } else {
+            ux = sun_x; uy = sun_y; uz = sun_z;
+        }
+        if (1.0 + uz < 1e-12) {
+            R[0] = 1.0; R[1] = 0.0; R[2] = 0.0; R[3] = 0.0; R[4] = -1.0; R[5] = 0.0; R[6] = 0.0; R[7] = 0.0;
+            R[8] = -1.0;
+        } else {
+            const double h = 1.0 / (1.0 + uz);
+            const double xy = (ux * uy) * h;
+            R[0] = uz + (uy * uy) * h; R[1] = -xy; R[2] = -ux;
+            R[3] = -xy; R[4] = uz + (ux * ux) * h; R[5] = -uy;
+            R[6] = ux; R[7] = uy; R[8] = uz;
+        }
+    }
+    for (int i = lane; i < NF; i += 64) {
+        const double x = lat[3 * i], y = lat[3 * i + 1], z = lat[3 * i + 2];
+        lq[0][i] = fma(R[6], z, fma(R[3], y, R[0] * x));
+        lq[1][i] = fma(R[7], z, fma(R[4], y, R[1] * x));
+        lq[2][i] = fma(R[8], z, fma(R[5], y, R[2] * x));
+        double w;
+        if (surf) {
+            w = tab[n_phase * NF + i];
+        } else {
+            w = 0.0;
+            for (int k = 0; k < n_phase; ++k) {
+                const double f = frac ? (double)frac[(long long)k * nvox + l] : 1.0;
+                w = w + f * tab[k * NF + i];
+            }
+        }
+        wq[i] = (unsigned long long)llrint(w * kFix);
+        nnb[i] = hull[NF * kHullNb + i];
+        for (int t = 0; t < kHullNb; ++t) nbr[i][t] = (unsigned char)hull[i * kHullNb + t];
+        bkey[i] = 0ull;
+        bown[i] = 0x7fffffff;
+    }
+    for (int t = lane; t < kCellHash; t += 64) {
+        hkey[t] = kNoOwner;
+        hval[t] = 0ull;
+    }
+    __syncthreads();
+    // seeds: each out-direction's closest lattice point, and the points' best values
+    for (int m = lane; m < d; m += 64) {
+        double tx, ty, tz;
+        edge_dir(m, tx, ty, tz);
+        double bv = fma(lq[2][0], tz, fma(lq[1][0], ty, lq[0][0] * tx));
+        int bi = 0;
+        for (int i = 1; i < NF; ++i) {
+            const double v = fma(lq[2][i], tz, fma(lq[1][i], ty, lq[0][i] * tx));
+            if (v > bv) {
+                bv = v;
+                bi = i;
+            }
+        }
+        seed_pt[m] = (unsigned char)bi;
+        atomicMax(&bkey[bi], order_key(bv));
+    }
+    __syncthreads();
+    for (int m = lane; m < d; m += 64) {
+        double tx, ty, tz;
+        edge_dir(m, tx, ty, tz);
+        const int bi = seed_pt[m];
+        const double v = fma(lq[2][bi], tz, fma(lq[1][bi], ty, lq[0][bi] * tx));
+        if (v == order_value(bkey[bi])) atomicMin(&bown[bi], m);
+    }
+    __syncthreads();
+    const int i0 = lane, i1 = lane + 64;
+    const bool ok0 = i0 < NF, ok1 = i1 < NF;
+    if (ok0) col[i0] = bown[i0] == 0x7fffffff ? -1 : bown[i0];
+    if (ok1) col[i1] = bown[i1] == 0x7fffffff ? -1 : bown[i1];
+    __syncthreads();
+    for (int round = 0; round < NF; ++round) {
+        if (ok0) snap[i0] = col[i0];
+        if (ok1) snap[i1] = col[i1];
+        __syncthreads();
+        bool missing = false;
+        for (int h2 = 0; h2 < 2; ++h2) {
+            const int i = h2 ? i1 : i0;
+            if (i >= NF || snap[i] >= 0) continue;
+            const int nn = nnb[i];
+            int c = -1;
+#pragma unroll
+            for (int t = kHullNb - 1; t >= 0; --t) {
+                if (t < nn) {
+                    const int ct = snap[nbr[i][t]];
+                    c = ct >= 0 ? ct : c;
+                }
+            }
+            col[i] = c;
+            missing = missing || c < 0;
+        }
+        const bool any = __ballot(missing) != 0ull;
+        __syncthreads();
+        if (!any) break;
+    }
+    // cells: colour -> fixed-point sum
+    for (int h2 = 0; h2 < 2; ++h2) {
+        const int i = h2 ? i1 : i0;
+        if (i >= NF || col[i] < 0) continue;
+        const unsigned short key = (unsigned short)col[i];
+        int h = col[i] & (kCellHash - 1);
+        while (true) {
+            const unsigned short old = atomicCAS(&hkey[h], kNoOwner, key);
+            if (old == kNoOwner || old == key) break;
+            h = (h + 1) & (kCellHash - 1);
+        }
+        atomicAdd(&hval[h], wq[i]);
+    }
+    __syncthreads();
+    const Real rl = rho ? rho[l] : (Real)0;
+    const Real tsun = Tsun ? Tsun[l] : (Real)0;
+    BlkT *blk = val + nodeoff[l];  // column-major: element (row n, column m) at m d + n
+    for (int m = lane; m < d; m += 64) {
+        const int h = cell_find(hkey, m);
+        const double Q = h < 0 ? 0.0 : (double)(long long)hval[h] * kUnfix;
+        const long long b = off + m;
+        if (surf) {
+            for (int c = 0; c < d; ++c) {
+                if (kWriteQ) blk[(long long)c * d + m] = (BlkT)Q;
+                else blk[(long long)c * d + m] = (BlkT)(T[off + c] * rl * (Real)Q);
+            }
+            if (!kWriteQ) S[b] = rl * mu0 * tsun * (Real)Q;
+            qsun[b] = (float)Q;
+        } else if (a < d) {
+            if (kWriteQ) blk[(long long)a * d + m] = (BlkT)Q;
+            else blk[(long long)a * d + m] = (BlkT)(T[off + a] * rl * (Real)Q);
+        } else {
+            if (!kWriteQ) S[b] = tsun * rl * (Real)Q;
+            qsun[b] = (float)Q;
+        }
+    }
+}
+
+
 }  // namespace
 
 // directions per group: as many as fill the lanes' pair slots
@@ -618,6 +815,22 @@ void launch_qbuild(Scene &s, hipStream_t st, int write_q) {
                                s.sun_in[2], (Real)s.mu0, (const Real *)s.T, (const Real *)s.rho,
                                (const Real *)s.Tsun, s.nodeoff, (Real *)s.val, (Real *)s.S, s.qsun, s.hull, s.periodic,
                                (long long)s.nx * kFx, (long long)s.ny * kFx);
+        }
+        if (s.n_big) {  // nodes of degree above 64: one workgroup per (node, incoming direction)
+            if (write_q)
+                hipLaunchKernelGGL((k_qcolour_big<Real, float, true>), dim3(s.n_bigdir), dim3(64), 0, st, s.n_big,
+                                   s.big, s.bigdir, s.nvox, s.adj_ptr, s.adj_idx, s.pos, s.lat, s.tab, s.n_fib,
+                                   s.n_phase, s.frac, s.sun_in[0], s.sun_in[1], s.sun_in[2], (Real)s.mu0,
+                                   (const Real *)nullptr, (const Real *)nullptr, (const Real *)nullptr, s.nodeoff, s.q,
+                                   (Real *)nullptr, s.qsun, s.hull, s.periodic, (long long)s.nx * kFx,
+                                   (long long)s.ny * kFx);
+            else
+                hipLaunchKernelGGL((k_qcolour_big<Real, Real, false>), dim3(s.n_bigdir), dim3(64), 0, st, s.n_big,
+                                   s.big, s.bigdir, s.nvox, s.adj_ptr, s.adj_idx, s.pos, s.lat, s.tab, s.n_fib,
+                                   s.n_phase, s.frac, s.sun_in[0], s.sun_in[1], s.sun_in[2], (Real)s.mu0,
+                                   (const Real *)s.T, (const Real *)s.rho, (const Real *)s.Tsun, s.nodeoff,
+                                   (Real *)s.val, (Real *)s.S, s.qsun, s.hull, s.periodic, (long long)s.nx * kFx,
+                                   (long long)s.ny * kFx);
         }
         return;
     }

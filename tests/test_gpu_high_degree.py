@@ -116,14 +116,30 @@ def test_builder_graph_solved_end_to_end(ctx):
 
 
 def test_high_degree_limits(ctx):
-    """Several wavelengths and the colouring keep the one-wavefront limit of 64."""
+    """Several wavelengths keep the one-wavefront limit of 64."""
     from paper_2503_16037_amd import sgrt
     sc = coupled_scene(8)
-    for bad in (dataclasses.replace(sc, abs_scale=np.array([1.0, 2.0], np.float32)),
-                dataclasses.replace(sc, sigma_mode=1)):
-        with pytest.raises(sgrt.SgError) as e:
-            sgrt.Scene(ctx, bad)
-        assert "64" in str(e.value)
+    with pytest.raises(sgrt.SgError) as e:
+        sgrt.Scene(ctx, dataclasses.replace(sc, abs_scale=np.array([1.0, 2.0], np.float32)))
+    assert "64" in str(e.value)
+
+
+@pytest.mark.parametrize("k", [8, 20])
+def test_high_degree_colouring(ctx, k):
+    """The paper's colouring of the phase cells on nodes above 64 couplings (one workgroup
+    per incoming direction): the sparsity pattern bit-exact, every phase weight and pixel
+    to the FP64 bar, surface nodes above 64 among them."""
+    from paper_2503_16037_amd import sgrt
+    sc = dataclasses.replace(coupled_scene(k), sigma_mode=1)
+    ora = oracle.run(sc)
+    with sgrt.Scene(ctx, sc) as g:
+        rad, info = g.solve(precision="fp64")
+        assert info["converged"] == 1
+        rp, col, val = g.export_csr()
+        assert np.array_equal(rp, ora["row_ptr"]) and np.array_equal(col, ora["col"])
+        assert rel_err(val, ora["val"]).max() < 1e-12
+        assert rel_err(rad, ora["radiance"]).max() < 1e-10
+        say("  colouring: max pixel rel err", rel_err(rad, ora["radiance"]).max(), "sweeps", info["sweeps"])
 
 
 def star_scene(n_leaves):
