@@ -613,6 +613,60 @@ __device__ __forceinline__ double order_value(unsigned long long k) {
     return __longlong_as_double((long long)b);
 }
 
+// unit vector of node l's out-edge m (the shortest periodic image)
+__device__ __forceinline__ void edge_unit(const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx,
+                                          const int *__restrict__ pos, int l, int m, int per, long long wx,
+                                          long long wy, double &ex, double &ey, double &ez) {
+    const int j = adj_idx[adj_ptr[l] + m];
+    const long long Dx = min_image((long long)pos[3 * j] - pos[3 * l], wx, per & 1);
+    const long long Dy = min_image((long long)pos[3 * j + 1] - pos[3 * l + 1], wy, per & 2);
+    const long long Dz = (long long)pos[3 * j + 2] - pos[3 * l + 2];
+    const double nrm = sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
+    ex = (double)Dx / nrm;
+    ey = (double)Dy / nrm;
+    ez = (double)Dz / nrm;
+}
+
+// seeds of S out-directions per lane (m0 + 64 s + lane, s < S): each scans the lattice
+// points in ascending order (strict >), so every point read from LDS serves S dot products;
+// then the point's best value is raised (order-preserving key, atomic max)
+template <int S>
+__device__ __forceinline__ void colour_seeds(int m0, int d, int NF, const double (*lq)[128],
+                                             const long long *__restrict__ adj_ptr,
+                                             const int *__restrict__ adj_idx, const int *__restrict__ pos, int l,
+                                             int per, long long wx, long long wy, unsigned char *seed_pt,
+                                             unsigned long long *bkey) {
+#pragma clang fp contract(off)
+    double tx[S], ty[S], tz[S], bv[S];
+    int bi[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int m = min(m0 + 64 * s + (int)threadIdx.x, d - 1);
+        edge_unit(adj_ptr, adj_idx, pos, l, m, per, wx, wy, tx[s], ty[s], tz[s]);
+        bv[s] = fma(lq[2][0], tz[s], fma(lq[1][0], ty[s], lq[0][0] * tx[s]));
+        bi[s] = 0;
+    }
+    for (int i = 1; i < NF; ++i) {
+        const double x = lq[0][i], y = lq[1][i], z = lq[2][i];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const double v = fma(z, tz[s], fma(y, ty[s], x * tx[s]));
+            if (v > bv[s]) {
+                bv[s] = v;
+                bi[s] = i;
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int m = m0 + 64 * s + (int)threadIdx.x;
+        if (m < d) {
+            seed_pt[m] = (unsigned char)bi[s];
+            atomicMax(&bkey[bi[s]], order_key(bv[s]));
+        }
+    }
+}
+
 template <class Real, class BlkT, bool kWriteQ>
 __global__ __launch_bounds__(64) void k_qcolour_big(
     int nbig, const int *__restrict__ big, const long long *__restrict__ bigdir, int nvox,
@@ -700,20 +754,12 @@ __global__ __launch_bounds__(64) void k_qcolour_big(
     }
     __syncthreads();
     // seeds: each out-direction's closest lattice point, and the points' best values
-    for (int m = lane; m < d; m += 64) {
-        double tx, ty, tz;
-        edge_dir(m, tx, ty, tz);
-        double bv = fma(lq[2][0], tz, fma(lq[1][0], ty, lq[0][0] * tx));
-        int bi = 0;
-        for (int i = 1; i < NF; ++i) {
-            const double v = fma(lq[2][i], tz, fma(lq[1][i], ty, lq[0][i] * tx));
-            if (v > bv) {
-                bv = v;
-                bi = i;
-            }
-        }
-        seed_pt[m] = (unsigned char)bi;
-        atomicMax(&bkey[bi], order_key(bv));
+    for (int m0 = 0; m0 < d; m0 += 4 * 64) {
+        const int left = d - m0;
+        if (left > 3 * 64) colour_seeds<4>(m0, d, NF, lq, adj_ptr, adj_idx, pos, l, per, wx, wy, seed_pt, bkey);
+        else if (left > 2 * 64) colour_seeds<3>(m0, d, NF, lq, adj_ptr, adj_idx, pos, l, per, wx, wy, seed_pt, bkey);
+        else if (left > 64) colour_seeds<2>(m0, d, NF, lq, adj_ptr, adj_idx, pos, l, per, wx, wy, seed_pt, bkey);
+        else colour_seeds<1>(m0, d, NF, lq, adj_ptr, adj_idx, pos, l, per, wx, wy, seed_pt, bkey);
     }
     __syncthreads();
     for (int m = lane; m < d; m += 64) {
