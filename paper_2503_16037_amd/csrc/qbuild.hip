@@ -397,6 +397,16 @@ __global__ __launch_bounds__(64) void k_qbuild_big(
 //   coloured neighbour had at the start of the round, until all are coloured (the
 //   hull graph is connected and there is at least one seed).
 // Q(u -> m) is the fixed-point sum of the phase weights of colour m, as in k_qbuild.
+// order-preserving 64-bit keys of doubles (for integer atomic max in LDS)
+__device__ __forceinline__ unsigned long long order_key(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double order_value(unsigned long long k) {
+    const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
 template <class Real, class BlkT, bool kWriteQ>
 __global__ __launch_bounds__(64) void k_qcolour(
     int N, int nvox, const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx,
@@ -406,13 +416,9 @@ __global__ __launch_bounds__(64) void k_qcolour(
     BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun, const int *__restrict__ hull, int per,
     long long wx, long long wy) {
 #pragma clang fp contract(off)
-    constexpr int kCM = 8;  // out-directions per seed chunk
-    __shared__ double sx[64], sy[64], sz[64], lt[3][128];
-    __shared__ double vbuf[128][kCM + 1];  // the chunk's v_im, lattice-point major (padded row)
-    __shared__ double seed_v[64];
-    __shared__ unsigned long long wq[128], bins[64];
-    __shared__ int nnb[128], col[128], snap[128], seed_pt[64];
-    __shared__ unsigned char nbr[128][kHullNb];  // lattice indices are below 128
+    __shared__ double sx[64], sy[64], sz[64], lq[3][128];  // sites; this direction's rotated lattice
+    __shared__ unsigned long long wq[128], bins[64], bkey[128];
+    __shared__ int col[128], snap[128];
 
     const int l = blockIdx.x;
     const int lane = threadIdx.x;
@@ -431,9 +437,6 @@ __global__ __launch_bounds__(64) void k_qcolour(
         sz[lane] = (double)Dz / nrm;
     }
     for (int i = lane; i < NF; i += 64) {
-        lt[0][i] = lat[3 * i];
-        lt[1][i] = lat[3 * i + 1];
-        lt[2][i] = lat[3 * i + 2];
         double w;
         if (surf) {
             w = tab[n_phase * NF + i];
@@ -445,8 +448,6 @@ __global__ __launch_bounds__(64) void k_qcolour(
             }
         }
         wq[i] = (unsigned long long)llrint(w * kFix);
-        nnb[i] = hull[NF * kHullNb + i];
-        for (int t = 0; t < kHullNb; ++t) nbr[i][t] = (unsigned char)hull[i * kHullNb + t];
     }
     __syncthreads();
 
@@ -456,6 +457,24 @@ __global__ __launch_bounds__(64) void k_qcolour(
     const int n_in = surf ? 1 : d + 1;
     const int i0 = lane, i1 = lane + 64;
     const bool ok0 = i0 < NF, ok1 = i1 < NF;
+    double px[2], py[2], pz[2];  // this lane's lattice points i0, i1
+    int nn[2];                    // and their hull neighbours, four indices (< 128) a word
+    unsigned nbw[2][kHullNb / 4];
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+        const int i = min(h2 ? i1 : i0, NF - 1);
+        px[h2] = lat[3 * i];
+        py[h2] = lat[3 * i + 1];
+        pz[h2] = lat[3 * i + 2];
+        nn[h2] = hull[NF * kHullNb + i];
+#pragma unroll
+        for (int w = 0; w < kHullNb / 4; ++w) {
+            unsigned v = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) v |= ((unsigned)hull[i * kHullNb + 4 * w + b] & 0xffu) << (8 * b);
+            nbw[h2][w] = v;
+        }
+    }
     for (int a = 0; a < n_in; ++a) {
         // rotation of this incoming direction (every lane, the same values)
         double R[9];
@@ -476,69 +495,40 @@ __global__ __launch_bounds__(64) void k_qcolour(
                 R[6] = ux; R[7] = uy; R[8] = uz;
             }
         }
-        double q[2][3];
+        // the rotated lattice (q_i = R^T p_i), and cleared claims
         for (int h2 = 0; h2 < 2; ++h2) {
-            const int i = min(h2 ? i1 : i0, NF - 1);
-            const double x = lt[0][i], y = lt[1][i], z = lt[2][i];
-            q[h2][0] = fma(R[6], z, fma(R[3], y, R[0] * x));
-            q[h2][1] = fma(R[7], z, fma(R[4], y, R[1] * x));
-            q[h2][2] = fma(R[8], z, fma(R[5], y, R[2] * x));
+            const int i = h2 ? i1 : i0;
+            if (i >= NF) continue;
+            const double x = px[h2], y = py[h2], z = pz[h2];
+            lq[0][i] = fma(R[6], z, fma(R[3], y, R[0] * x));
+            lq[1][i] = fma(R[7], z, fma(R[4], y, R[1] * x));
+            lq[2][i] = fma(R[8], z, fma(R[5], y, R[2] * x));
+            bkey[i] = 0ull;
+            col[i] = 0x7fffffff;
         }
-        // seeds: for every out-direction m the lattice point of largest v_im, ties to the
-        // lowest i.  Chunks of kCM directions: the lanes write v_im of their lattice points
-        // to LDS, then lane (m, g) scans points 16 g .. 16 g + 15 for direction m in
-        // ascending order (strict >), and the eight groups combine by larger value, ties
-        // to the lower index; no serial cross-lane chain per direction.
-        for (int m0 = 0; m0 < d; m0 += kCM) {
-            const int nm = min(kCM, d - m0);
-            for (int mm = 0; mm < nm; ++mm) {
-                const double tx = sx[m0 + mm], ty = sy[m0 + mm], tz = sz[m0 + mm];
-                if (ok0) vbuf[i0][mm] = fma(q[0][2], tz, fma(q[0][1], ty, q[0][0] * tx));
-                if (ok1) vbuf[i1][mm] = fma(q[1][2], tz, fma(q[1][1], ty, q[1][0] * tx));
-            }
-            __syncthreads();
-            const int mm = lane % kCM, g = lane / kCM;
-            double bv = -__builtin_inf();
-            int bi = 0x7fffffff;
-            if (mm < nm) {
-                const int ib = min(NF, 16 * g + 16);
-                for (int i = 16 * g; i < ib; ++i) {
-                    const double v = vbuf[i][mm];
-                    if (v > bv) {
-                        bv = v;
-                        bi = i;
-                    }
-                }
-            }
-            for (int o = kCM; o < 64; o <<= 1) {
-                const double ov = __shfl_xor(bv, o, 64);
-                const int oi = __shfl_xor(bi, o, 64);
-                const bool take = ov > bv || (ov == bv && oi < bi);
-                bv = take ? ov : bv;
-                bi = take ? oi : bi;
-            }
-            if (g == 0 && mm < nm) {
-                seed_v[m0 + mm] = bv;
-                seed_pt[m0 + mm] = bi;
-            }
-            __syncthreads();  // vbuf is rewritten by the next chunk
-        }
-        // claims: a point seeded by several directions takes the largest value, ties to the
-        // lowest m (what claiming in order of m with a strictly larger value gives)
-        if (ok0) col[i0] = -1;
-        if (ok1) col[i1] = -1;
         __syncthreads();
+        // seeds: lane m scans the lattice points in ascending order (strict >) for the
+        // largest v_im, and raises that point's best value; then every m whose seed value
+        // equals its point's best offers its index: a point seeded by several directions
+        // goes to the largest value, ties to the lowest m (claiming in order of m)
+        double bv = 0.0;
+        int bi = 0;
         if (lane < d) {
-            const int pt = seed_pt[lane];
-            const double v = seed_v[lane];
-            bool win = true;
-            for (int m2 = 0; m2 < d; ++m2) {
-                const double v2 = seed_v[m2];
-                if (m2 != lane && seed_pt[m2] == pt && (v2 > v || (v2 == v && m2 < lane))) win = false;
+            const double tx = sx[lane], ty = sy[lane], tz = sz[lane];
+            bv = fma(lq[2][0], tz, fma(lq[1][0], ty, lq[0][0] * tx));
+#pragma unroll 4
+            for (int i = 1; i < NF; ++i) {
+                const double v = fma(lq[2][i], tz, fma(lq[1][i], ty, lq[0][i] * tx));
+                bi = v > bv ? i : bi;
+                bv = fmax(bv, v);
             }
-            if (win && pt < NF) col[pt] = lane;
+            atomicMax(&bkey[bi], order_key(bv));
         }
         __syncthreads();
+        if (lane < d && bv == order_value(bkey[bi])) atomicMin(&col[bi], lane);
+        __syncthreads();
+        if (ok0 && col[i0] == 0x7fffffff) col[i0] = -1;  // each lane its own points
+        if (ok1 && col[i1] == 0x7fffffff) col[i1] = -1;
         // flood fill in rounds: an uncoloured point takes the colour of its lowest-index
         // coloured neighbour (the lists ascend) in the snapshot of the round's start; the
         // list's reads are independent, so they are issued together
@@ -547,15 +537,15 @@ __global__ __launch_bounds__(64) void k_qcolour(
             if (ok1) snap[i1] = col[i1];
             __syncthreads();
             bool missing = false;
+#pragma unroll
             for (int h2 = 0; h2 < 2; ++h2) {
                 const int i = h2 ? i1 : i0;
                 if (i >= NF || snap[i] >= 0) continue;
-                const int nn = nnb[i];
                 int c = -1;
 #pragma unroll
                 for (int t = kHullNb - 1; t >= 0; --t) {
-                    if (t < nn) {
-                        const int ct = snap[nbr[i][t]];
+                    if (t < nn[h2]) {
+                        const int ct = snap[(nbw[h2][t >> 2] >> (8 * (t & 3))) & 0xffu];
                         c = ct >= 0 ? ct : c;
                     }
                 }
@@ -604,14 +594,6 @@ __global__ __launch_bounds__(64) void k_qcolour(
 //   the largest value, ties to the lowest m, as claiming in order of m gives.
 //   fill and cells as in k_qcolour, the colours' sums in a hash table (at most N_fib
 //   colours among the d out-edges), the column written by looking up every row.
-__device__ __forceinline__ unsigned long long order_key(double v) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
-}
-__device__ __forceinline__ double order_value(unsigned long long k) {
-    const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
-    return __longlong_as_double((long long)b);
-}
 
 // unit vector of node l's out-edge m (the shortest periodic image)
 __device__ __forceinline__ void edge_unit(const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx,
