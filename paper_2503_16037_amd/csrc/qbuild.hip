@@ -417,8 +417,8 @@ __global__ __launch_bounds__(64) void k_qcolour(
     long long wx, long long wy) {
 #pragma clang fp contract(off)
     __shared__ double sx[64], sy[64], sz[64], lq[3][128];  // sites; this direction's rotated lattice
-    __shared__ unsigned long long wq[128], bins[64], bkey[128];
-    __shared__ int col[128], snap[128];
+    __shared__ unsigned long long wq[128], bins[64], bkey[128], mkey[64];
+    __shared__ int col[128], snap[128], mi[64];
 
     const int l = blockIdx.x;
     const int lane = threadIdx.x;
@@ -457,6 +457,8 @@ __global__ __launch_bounds__(64) void k_qcolour(
     const int n_in = surf ? 1 : d + 1;
     const int i0 = lane, i1 = lane + 64;
     const bool ok0 = i0 < NF, ok1 = i1 < NF;
+    const int P = min(4, kWave / d);             // lanes per out-direction in the seed scan
+    const int blk_pts = (NF + P - 1) / P;        // lattice points per lane
     double px[2], py[2], pz[2];  // this lane's lattice points i0, i1
     int nn[2];                    // and their hull neighbours, four indices (< 128) a word
     unsigned nbw[2][kHullNb / 4];
@@ -506,24 +508,45 @@ __global__ __launch_bounds__(64) void k_qcolour(
             bkey[i] = 0ull;
             col[i] = 0x7fffffff;
         }
+        if (lane < d) {
+            mkey[lane] = 0ull;
+            mi[lane] = 0x7fffffff;
+        }
         __syncthreads();
         // seeds: lane m scans the lattice points in ascending order (strict >) for the
         // largest v_im, and raises that point's best value; then every m whose seed value
         // equals its point's best offers its index: a point seeded by several directions
         // goes to the largest value, ties to the lowest m (claiming in order of m)
+        // (with P = 64 / d > 1 lanes per direction, lane m + part d scans the part-th block
+        // of points and the blocks combine by value, ties to the lower point)
         double bv = 0.0;
         int bi = 0;
-        if (lane < d) {
-            const double tx = sx[lane], ty = sy[lane], tz = sz[lane];
-            bv = fma(lq[2][0], tz, fma(lq[1][0], ty, lq[0][0] * tx));
+        const int part = lane / d;
+        const bool scans = part < P && part * blk_pts < NF;  // a block can be empty for tiny N_fib
+        if (scans) {
+            const int m = lane - part * d;
+            const int ib = part * blk_pts, ie = min(NF, ib + blk_pts);
+            const double tx = sx[m], ty = sy[m], tz = sz[m];
+            bv = fma(lq[2][ib], tz, fma(lq[1][ib], ty, lq[0][ib] * tx));
+            bi = ib;
 #pragma unroll 4
-            for (int i = 1; i < NF; ++i) {
+            for (int i = ib + 1; i < ie; ++i) {
                 const double v = fma(lq[2][i], tz, fma(lq[1][i], ty, lq[0][i] * tx));
                 bi = v > bv ? i : bi;
                 bv = fmax(bv, v);
             }
-            atomicMax(&bkey[bi], order_key(bv));
+            if (P > 1) atomicMax(&mkey[m], order_key(bv));
         }
+        if (P > 1) {
+            __syncthreads();
+            if (scans && bv == order_value(mkey[lane - part * d])) atomicMin(&mi[lane - part * d], bi);
+            __syncthreads();
+            if (lane < d) {
+                bi = mi[lane];
+                bv = order_value(mkey[lane]);
+            }
+        }
+        if (lane < d) atomicMax(&bkey[bi], order_key(bv));
         __syncthreads();
         if (lane < d && bv == order_value(bkey[bi])) atomicMin(&col[bi], lane);
         __syncthreads();

@@ -75,3 +75,21 @@ def test_colouring_reservation_and_validation(ctx):
     with pytest.raises(sgrt.SgError) as e:
         sgrt.Scene(ctx, sc.with_(sigma_mode=2))
     assert e.value.status == sgrt.SG_E_INVALID
+
+
+@pytest.mark.parametrize("n_fib", [4, 7, 13, 61, 128])
+def test_colouring_lattice_sizes(ctx, n_fib):
+    """Small and large lattices (with few points a direction's seed scan can leave blocks of
+    its lanes empty; 128 is the largest lattice): FP64 phase weights and pixels against the
+    oracle, the surface node's cosine cells included."""
+    from paper_2503_16037_amd import sgrt
+    sc = scenes.make_random_small(5, nx=6, ny=5, nz=4, two_phase=True).with_(sigma_mode=1, n_fib=n_fib)
+    ora = oracle.run(sc)
+    with sgrt.Scene(ctx, sc) as g:
+        rad, info = g.solve(precision="fp64")
+        assert info["converged"] == 1
+        _, _, val = g.export_csr(lam=0, cols=False)
+    big = ora["val"] > 1e-12 * ora["val"].max()
+    say("n_fib", n_fib, "radiance", rel(rad, ora["radiance"]), "K", rel(val[big], ora["val"][big]))
+    assert rel(val[big], ora["val"][big]) < 1e-12
+    assert rel(rad, ora["radiance"]) < 1e-10
