@@ -656,10 +656,8 @@ __device__ __forceinline__ void colour_seeds(int m0, int d, int NF, const double
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const double v = fma(z, tz[s], fma(y, ty[s], x * tx[s]));
-            if (v > bv[s]) {
-                bv[s] = v;
-                bi[s] = i;
-            }
+            bi[s] = v > bv[s] ? i : bi[s];  // moves only on a strict increase
+            bv[s] = fmax(bv[s], v);
         }
     }
 #pragma unroll
@@ -682,12 +680,13 @@ __global__ __launch_bounds__(64) void k_qcolour_big(
     BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun, const int *__restrict__ hull, int per,
     long long wx, long long wy) {
 #pragma clang fp contract(off)
-    __shared__ double lq[3][128];
-    __shared__ unsigned long long bkey[128], wq[128], hval[kCellHash];
-    __shared__ int bown[128], col[128], snap[128], nnb[128];
-    __shared__ unsigned short hkey[kCellHash];
-    __shared__ unsigned char nbr[128][kHullNb];
+    __shared__ double lq[3][128];  // the rotated lattice; after the claims, the cells' hash table
+    __shared__ unsigned long long bkey[128], wq[128];
+    __shared__ int col[128], snap[128];
     __shared__ unsigned char seed_pt[kMaxDegree];
+    static_assert(kCellHash * (sizeof(unsigned long long) + sizeof(unsigned short)) <= sizeof(lq), "hash in lq");
+    unsigned long long *hval = reinterpret_cast<unsigned long long *>(&lq[0][0]);
+    unsigned short *hkey = reinterpret_cast<unsigned short *>(hval + kCellHash);
     const long long wg = blockIdx.x;
     int lo = 0, hi = nbig;  // the node b with bigdir[b] <= wg < bigdir[b + 1]
     while (hi - lo > 1) {
@@ -748,14 +747,22 @@ __global__ __launch_bounds__(64) void k_qcolour_big(
             }
         }
         wq[i] = (unsigned long long)llrint(w * kFix);
-        nnb[i] = hull[NF * kHullNb + i];
-        for (int t = 0; t < kHullNb; ++t) nbr[i][t] = (unsigned char)hull[i * kHullNb + t];
         bkey[i] = 0ull;
-        bown[i] = 0x7fffffff;
+        col[i] = 0x7fffffff;
     }
-    for (int t = lane; t < kCellHash; t += 64) {
-        hkey[t] = kNoOwner;
-        hval[t] = 0ull;
+    int nn[2];  // this lane's lattice points' hull neighbours, four indices (< 128) a word
+    unsigned nbw[2][kHullNb / 4];
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+        const int i = min(h2 ? lane + 64 : lane, NF - 1);
+        nn[h2] = hull[NF * kHullNb + i];
+#pragma unroll
+        for (int w = 0; w < kHullNb / 4; ++w) {
+            unsigned v = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) v |= ((unsigned)hull[i * kHullNb + 4 * w + b] & 0xffu) << (8 * b);
+            nbw[h2][w] = v;
+        }
     }
     __syncthreads();
     // seeds: each out-direction's closest lattice point, and the points' best values
@@ -772,28 +779,31 @@ __global__ __launch_bounds__(64) void k_qcolour_big(
         edge_dir(m, tx, ty, tz);
         const int bi = seed_pt[m];
         const double v = fma(lq[2][bi], tz, fma(lq[1][bi], ty, lq[0][bi] * tx));
-        if (v == order_value(bkey[bi])) atomicMin(&bown[bi], m);
+        if (v == order_value(bkey[bi])) atomicMin(&col[bi], m);
     }
     __syncthreads();
+    for (int t = lane; t < kCellHash; t += 64) {  // lq is free now (the fill's barriers publish this)
+        hkey[t] = kNoOwner;
+        hval[t] = 0ull;
+    }
     const int i0 = lane, i1 = lane + 64;
     const bool ok0 = i0 < NF, ok1 = i1 < NF;
-    if (ok0) col[i0] = bown[i0] == 0x7fffffff ? -1 : bown[i0];
-    if (ok1) col[i1] = bown[i1] == 0x7fffffff ? -1 : bown[i1];
-    __syncthreads();
+    if (ok0 && col[i0] == 0x7fffffff) col[i0] = -1;  // each lane its own points
+    if (ok1 && col[i1] == 0x7fffffff) col[i1] = -1;
     for (int round = 0; round < NF; ++round) {
         if (ok0) snap[i0] = col[i0];
         if (ok1) snap[i1] = col[i1];
         __syncthreads();
         bool missing = false;
+#pragma unroll
         for (int h2 = 0; h2 < 2; ++h2) {
             const int i = h2 ? i1 : i0;
             if (i >= NF || snap[i] >= 0) continue;
-            const int nn = nnb[i];
             int c = -1;
 #pragma unroll
             for (int t = kHullNb - 1; t >= 0; --t) {
-                if (t < nn) {
-                    const int ct = snap[nbr[i][t]];
+                if (t < nn[h2]) {
+                    const int ct = snap[(nbw[h2][t >> 2] >> (8 * (t & 3))) & 0xffu];
                     c = ct >= 0 ? ct : c;
                 }
             }
