@@ -166,9 +166,10 @@ def star_scene(n_leaves):
     return dataclasses.replace(sc, adj_ptr=ap, adj_idx=ai)
 
 
-def test_largest_degree_star(ctx):
+@pytest.mark.parametrize("sigma_mode", [0, 1])
+def test_largest_degree_star(ctx, sigma_mode):
     from paper_2503_16037_amd import sgrt
-    sc = star_scene(4096)
+    sc = dataclasses.replace(star_scene(4096), sigma_mode=sigma_mode)
     assert np.diff(sc.adj_ptr).max() == 4096
     ora = oracle.run(sc)
     with sgrt.Scene(ctx, sc) as g:
