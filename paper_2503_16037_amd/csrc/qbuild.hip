@@ -50,8 +50,9 @@ __device__ __forceinline__ int small_div(int p, float inv_n) { return (int)(((fl
 // Running argmax over the node's out-edge directions for the lane's slots of
 // (direction, lattice point) pairs.  Ties go to the lowest index: the index moves only
 // on a strict increase, and the running maximum (fmax) equals the kept value on ties.
-// (Slots past a group's last pair, which hold repeats, are scanned too: one code path
-// keeps the kernel at 128 VGPRs, four waves per SIMD.)
+// Only the first S slots are scanned (S covers the group's pairs; slots past its last pair
+// within them hold repeats and are scanned too).
+template <int S>
 __device__ __forceinline__ void own_scan(int d, const double *sx, const double *sy, const double *sz,
                                          const double (&q0)[kQSlots], const double (&q1)[kQSlots],
                                          const double (&q2)[kQSlots], double (&best)[kQSlots], int (&own)[kQSlots]) {
@@ -60,7 +61,7 @@ __device__ __forceinline__ void own_scan(int d, const double *sx, const double *
     for (int m = 0; m < d; ++m) {
         const double tx = sx[m], ty = sy[m], tz = sz[m];
 #pragma unroll
-        for (int j = 0; j < kQSlots; ++j) {
+        for (int j = 0; j < S; ++j) {
             const double v = fma(q2[j], tz, fma(q1[j], ty, q0[j] * tx));
             own[j] = v > best[j] ? m : own[j];
             best[j] = fmax(best[j], v);
@@ -169,7 +170,11 @@ __global__ __launch_bounds__(64) void k_qbuild(
             best[j] = -__builtin_inf();
             own[j] = 0;
         }
-        own_scan(d, sx, sy, sz, q0, q1, q2, best, own);
+        // slots per lane that this group's pairs need (a node's last group is often short)
+        if (np <= 2 * 64) own_scan<2>(d, sx, sy, sz, q0, q1, q2, best, own);
+        else if (np <= 4 * 64) own_scan<4>(d, sx, sy, sz, q0, q1, q2, best, own);
+        else if (np <= 6 * 64) own_scan<6>(d, sx, sy, sz, q0, q1, q2, best, own);
+        else own_scan<kQSlots>(d, sx, sy, sz, q0, q1, q2, best, own);
 #pragma unroll
         for (int j = 0; j < kQSlots; ++j) {
             const int p = j * 64 + lane;
