@@ -58,16 +58,55 @@ def spmv_bytes(n_nodes: int, n_edges: int, nnz: int, real_bytes: int = 4, n_lamb
     return 4 * nnz + n_edges * 16 + n_edges * n_lambda * 8 + n_nodes * (16 + 8 * n_lambda)
 
 
-def qbuild_ops(scene) -> float:
-    """FP64 lane operations of the phase-cell ownership (Eq. 7): for every lattice point,
-    out-edge and incoming direction, a dot product (one multiply, two FMAs) and a running
-    argmax step (compare, select, max): 6.  Volume nodes see d + 1 incoming directions
-    (in-edges and the sun), surface nodes one."""
+# FP64 lane operations per (incoming direction, out-edge, lattice point) of the phase-cell
+# ownership (Eq. 7): the algorithmic count is 5 (a 3-term dot product as one multiply and two
+# FMAs, then a compare and a select of the running argmax); the kernel also keeps the running
+# maximum itself, a 6th operation, reported beside it
+QBUILD_OPS_PER_PAIR = 5
+QBUILD_OPS_ISSUED_PER_PAIR = 6
+
+
+def qbuild_pairs(scene) -> float:
+    """(incoming direction, out-edge, lattice point) triples of the phase cells: volume nodes
+    see d + 1 incoming directions (in-edges and the sun), surface nodes one."""
     d = np.diff(scene.adj_ptr).astype(np.float64)
     nvox = scene.nvox
     n_in = np.ones_like(d)
     n_in[:nvox] = d[:nvox] + 1.0
-    return 6.0 * float((n_in * d).sum()) * scene.n_fib
+    return float((n_in * d).sum()) * scene.n_fib
+
+
+def step_bytes(sz, nvox, infos_avg):
+    """Algorithmic HBM bytes of one whole solve of one wavelength (march + matrix + sweeps +
+    FP64 residuals + gather), FP32 working precision:
+      march: mu_s, mu_a (8 per voxel), positions and adjacency (20 per node, 4 per edge), the two
+        optical-depth channels of every undirected pair (4 per directed edge) and of the sun
+        path (8 per node), node weights (4 per node);
+      matrix: K values (4 nnz), the source and the sun's cell weight (8 per edge), the optical
+        depths read back (8 per edge);
+      sweeps: spmv_bytes per sweep (the previous iterate of monitored sweeps included);
+      FP64 residual: K values (4 nnz), per edge S (4), x64 (8), gathered x64 (8), r (8), rev (4),
+        per node 16;
+      gather: phi (8 per edge) and the node radiances (8 per node)."""
+    N, E, nnz = sz["n_nodes"], sz["n_edges"], sz["nnz"]
+    march = 8 * nvox + 20 * N + 4 * E + 4 * E + 8 * N + 4 * N
+    matrix = 4 * nnz + 8 * E + 8 * E
+    residual = 4 * nnz + 32 * E + 16 * N
+    gather = 8 * E + 8 * N
+    return march + matrix + infos_avg["sweep_bytes_total"] + infos_avg["refinements"] * residual + gather
+
+
+def host_cpu():
+    """The host's CPU model and the logical CPUs this process may run on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0))}
 
 
 def bench_copy(args):
@@ -149,7 +188,7 @@ def bench_served(args):
     serial_rate = n / serial_s
 
     def run_server(arrivals):
-        srv = sgrt.Server(ctx, max_resident=args.resident, queue_cap=4 * n, n_streams=min(args.resident, 8))
+        srv = sgrt.Server(ctx, max_resident=args.resident, queue_cap=4 * n, n_streams=args.resident)
         tickets = [None] * n
         t_start = time.perf_counter()
 
@@ -371,7 +410,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plume",
+    ap.add_argument("--workload", default="cloud",
                     help="plume | cloud | batched | plain | slab (periodic plume) | served | graph | nfib | coupling | copy")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -445,14 +484,18 @@ def main():
     monitored = sum(i["spmv_monitored"] for i in infos) / max(spmv_launches, 1)
     sbytes = spmv_bytes(sz["n_nodes"], sz["n_edges"], sz["nnz"], n_lambda=g.n_lambda) + \
         monitored * 4 * sz["n_edges"] * g.n_lambda
-    qops = qbuild_ops(scene)
+    qpairs = qbuild_pairs(scene)
+    qops = QBUILD_OPS_PER_PAIR * qpairs
     if stages["ms_qbuild"] >= spmv_per_step_ms and g.n_lambda == 1:
         achieved = qops / (stages["ms_qbuild"] * 1e-3) / 1e12
+        issued = QBUILD_OPS_ISSUED_PER_PAIR * qpairs / (stages["ms_qbuild"] * 1e-3) / 1e12
         roof = {"kernel": ("k_qcolour" if args.sigma == "colour" else "k_qbuild") + " (phase cells + K values + source)",
                 "bound": "alu",
                 "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "T FP64 lane-op/s",
                 "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": measured_traffic("k_qbuild", args.workload),
-                "algorithmic_per_launch": qops, "avg_launch_ms": round(stages["ms_qbuild"], 4)}
+                "algorithmic_per_launch": qops, "ops_per_pair": QBUILD_OPS_PER_PAIR,
+                "avg_launch_ms": round(stages["ms_qbuild"], 4),
+                "frac_with_running_max": round(issued / ALU_PEAK_TOPS, 4)}
     else:
         achieved = sbytes / (spmv_avg_ms * 1e-3) / 1e9
         roof = {"kernel": "k_spmv (FP32 sweep)" if g.n_lambda == 1 else "k_spmm (FP32, all wavelengths)",
@@ -465,6 +508,16 @@ def main():
                   "achieved_GBs": round(sbytes / max(spmv_avg_ms, 1e-9) / 1e6, 1),
                   "launches_per_step": spmv_launches / len(infos)}
 
+    step_hbm = None
+    if g.n_lambda == 1:
+        # bytes of the step: every timed sweep launch (monitored ones read the previous x too)
+        sweep_total = (spmv_bytes(sz["n_nodes"], sz["n_edges"], sz["nnz"]) * spmv_launches +
+                       4 * sz["n_edges"] * sum(i["spmv_monitored"] for i in infos)) / len(infos)
+        sb = step_bytes(sz, scene.nvox, {"sweep_bytes_total": sweep_total, "refinements": avg("refinements")})
+        step_hbm = {"bytes_per_step": round(sb), "achieved_GBs": round(sb / (ms_step * 1e-3) / 1e9, 1),
+                    "frac": round(sb / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "note": "algorithmic bytes of march + K write + sweeps + FP64 residuals + gather over the "
+                            "whole step's wall time; the phase cells are ALU-bound and count no bytes"}
     out = {"metric": METRIC, "value": round(scenes_per_s, 3), "unit": "scenes/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -478,7 +531,7 @@ def main():
            "sweeps_per_step": avg("sweeps"), "rel_residual": max(i["rel_residual"] for i in infos),
            "scene_upload": {"ms": round(upload_ms, 3), "bytes": upload_bytes,
                             "note": "sg_scene_create from host buffers, outside the timed region"},
-           "roofline": roof, "sweep_kernel": sweep_roof}
+           "roofline": roof, "sweep_kernel": sweep_roof, "step_hbm": step_hbm}
 
     if g.n_lambda > 1:
         out["wavelength_solves_per_s"] = round(scenes_per_s * g.n_lambda, 2)
@@ -497,6 +550,7 @@ def main():
             # the oracle solves one wavelength per run: a whole n-wavelength scene costs n runs
             out["cpu_baseline"] = {"value": round(1.0 / (t_cpu * g.n_lambda), 6), "unit": "scenes/s",
                                    "cores": oracle.num_threads(), "kind": "oracle",
+                                   "host": host_cpu(),
                                    "sample": f"one wavelength of {wl_name} ({sz['n_edges']} couplings), "
                                              f"FP64, all stages, {t_cpu:.2f} s"
                                              + (f", x {g.n_lambda} wavelengths" if g.n_lambda > 1 else ""),

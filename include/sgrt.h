@@ -366,17 +366,29 @@ typedef struct sg_server_opts {
     uint32_t abi_version;     /* SG_ABI_VERSION */
     int32_t max_resident;     /* scenes held on the device at once (>= 1) */
     int32_t queue_cap;        /* pending requests before sg_submit returns SG_E_BUSY (>= 1) */
-    int32_t n_streams;        /* concurrent device streams used by the scheduler (1..8) */
+    int32_t n_streams;        /* device streams of the scheduler (1..64), at least max_resident:
+                                 each resident slot runs on a stream of its own (a solve captures
+                                 its sweep chunks as HIP graphs, and a capture would take in the
+                                 launches of another slot on the same stream) */
     sg_solve_opts solve;      /* options applied to every request */
 } sg_server_opts;
 
 /*
  * Start a server on a context.  It admits queued scenes when a resident
- * slot is free and their reserved bytes, added to those of the admitted
- * scenes, fit the context's HBM budget, overlaps the resident scenes' work
- * on n_streams device streams, and completes each ticket independently.
- * A scene whose adjacency is not symmetric is refused when it is admitted:
- * its ticket completes with SG_E_INVALID.
+ * slot is free and their reserved bytes (sg_scene_reservation plus what a
+ * solve with opts->solve allocates: the FP64 arrays, the column index, the
+ * GMRES basis when GMRES is forced), added to those of the admitted scenes,
+ * fit the context's HBM budget, overlaps the resident scenes' work on their
+ * streams, and completes each ticket independently.  A request that runs out
+ * of budget in the mix (e.g. a solve falling back to GMRES, whose basis is
+ * not reserved in advance) is put back at the head of the queue with the
+ * basis added to its reservation and runs again once another request has
+ * finished; it ends with SG_E_NOMEM only if it does not fit alone.  Results
+ * are the same bits as the scene solved alone.  A scene whose adjacency is
+ * not symmetric is refused when it is admitted: its ticket completes with
+ * SG_E_INVALID.
+ * Errors: SG_E_ABI, SG_E_INVALID (max_resident > n_streams among others),
+ * SG_E_DEVICE.
  */
 sg_status sg_server_create(sg_ctx *ctx, const sg_server_opts *opts, sg_server **out);
 

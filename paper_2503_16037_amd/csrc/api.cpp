@@ -461,7 +461,8 @@ struct SolveStats {
 // relative != 0: stop once the relative measure is (predicted) below stop; otherwise
 // once the L1 update is below stop times the first one (sum |rhs|).  A ratio q >= 0.95
 // or growth after three sweeps, with the relative measure not falling either, is a
-// stall.  The solution ends in xa.
+// stall (stalled = 1); a measure that is not finite (the iterate overflowed) sets
+// stalled = 2.  The solution ends in xa.
 template <class Real>
 sg_status neumann(Scene &s, hipStream_t st, Exec &tm, const Real *rhs, Real *&xa, Real *&xb, int relative,
                   double stop, int max_sweeps, SolveStats &ss, int &stalled) {
@@ -521,7 +522,7 @@ sg_status neumann(Scene &s, hipStream_t st, Exec &tm, const Real *rhs, Real *&xa
         if (sg_log())
             fprintf(stderr, "[sgrt] sweeps %d chunk %d: L1 update %.3e, max relative %.3e (stop %.3e)\n", ss.sweeps,
                     chunk, l1.back(), rel.back(), stop);
-        if (!std::isfinite(l1.back()) || !std::isfinite(rel.back())) { stalled = 1; break; }
+        if (!std::isfinite(l1.back()) || !std::isfinite(rel.back())) { stalled = 2; break; }
         const double q = k >= 2 && l1[k - 2] > 0 ? l1.back() / l1[k - 2] : 0.5;
         // the measured update belongs to the previous iterate; the current one's is about q r
         const double qr = relative && k >= 2 && rel[k - 2] > 0 ? std::max(q, rel.back() / rel[k - 2]) : q;
@@ -551,7 +552,9 @@ sg_status gmres64(Scene &s, hipStream_t st, Exec &tm, const Real *S, double rtol
             s.bytes -= pool_round((size_t)(s.gm_m + 1) * E * sizeof(double));
             s.gm_V = nullptr;
         }
-        SG_TRY(dalloc(s, &s.gm_V, (size_t)(m + 1) * E));
+        const sg_status st_v = dalloc(s, &s.gm_V, (size_t)(m + 1) * E);
+        s.gm_nomem = st_v == SG_E_NOMEM;
+        if (st_v != SG_OK) return st_v;
         s.gm_m = m;
     }
     ss.gmres_used = 1;
@@ -564,17 +567,19 @@ sg_status gmres64(Scene &s, hipStream_t st, Exec &tm, const Real *S, double rtol
         ++ss.refinements;
         double m2[2];
         SG_TRY(read_scalars(s, st, s.scal, m2, 2));
-        ss.rel = m2[1];  // max over edges of |r| / |x|
+        ss.rel = std::isfinite(m2[0]) ? m2[1] : HUGE_VAL;  // max over edges of |r| / |x|
         if (ss.rel <= rtol || ss.sweeps >= max_sweeps) break;
         launch_dot_multi(s.r64, E, 1, s.r64, E, s.partial, nbv, s.scal, st);
         double beta2;
         SG_TRY(read_scalars(s, st, s.scal, &beta2, 1));
         const double beta = std::sqrt(beta2);
+        if (!std::isfinite(beta)) break;  // a non-finite iterate: reported as not converged
         SG_HIP(hipMemcpyAsync(V, s.r64, sizeof(double) * E, hipMemcpyDeviceToDevice, st));
         launch_scale64(V, 1.0 / beta, E, st);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int k = 0;
+        bool bad = false;  // a non-finite Krylov vector (e.g. K holds infinities): stop after this cycle
         for (; k < m && ss.sweeps < max_sweeps; ++k) {
             double *vk = V + (size_t)k * E, *w = V + (size_t)(k + 1) * E;
             launch_apply_imk64<Real>(s, st, vk, w);
@@ -593,6 +598,7 @@ sg_status gmres64(Scene &s, hipStream_t st, Exec &tm, const Real *S, double rtol
             double hn2;
             SG_TRY(read_scalars(s, st, s.scal, &hn2, 1));
             const double hn = std::sqrt(std::max(hn2, 0.0));
+            if (!std::isfinite(hn)) { bad = true; break; }
             if (hn > 0) launch_scale64(w, 1.0 / hn, E, st);
             for (int j = 0; j <= k; ++j) H[(size_t)j * m + k] = h[j];
             H[(size_t)(k + 1) * m + k] = hn;
@@ -622,6 +628,7 @@ sg_status gmres64(Scene &s, hipStream_t st, Exec &tm, const Real *S, double rtol
         SG_HIP(hipMemcpyAsync(s.scal + 64, ny.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
         launch_axpy_multi(s.x64, V, E, k, s.scal + 64, E, st);
         SG_HIP(hipStreamSynchronize(st));
+        if (bad) break;
     }
     ss.converged = ss.rel <= rtol;
     return SG_OK;
@@ -650,6 +657,9 @@ sg_status solve_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Exec &t
         warm = have_r = ss.rel <= kWarmKeep;
         if (!warm) launch_fill<double>(s.x64, 0.0, E, st);
     }
+    // an iterate that overflowed (a Neumann series that diverges fast, e.g. with the literal
+    // node weight) leaves x64 non-finite: GMRES then starts from x = 0
+    bool nonfinite = false;
     if (!use_gmres) {
         Real *xa = (Real *)s.x, *xb = (Real *)s.y;
         int stalled = 0;
@@ -658,6 +668,7 @@ sg_status solve_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Exec &t
         if (!warm) {  // a kept warm start goes straight to the refinement below
             SG_TRY(neumann<Real>(s, st, tm, S, xa, xb, 1, std::max(0.3 * rtol, floor_rel), max_sweeps, ss, stalled));
             launch_to64<Real>(xa, s.x64, E, st);
+            nonfinite = stalled == 2;
         }
         if (stalled && o.solver == SG_SOLVER_AUTO) use_gmres = 1;
         // FP64 residual and iterative refinement
@@ -668,12 +679,17 @@ sg_status solve_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Exec &t
                 ++ss.refinements;
                 double m2[2];
                 SG_TRY(read_scalars(s, st, s.scal, m2, 2));
-                ss.rel = m2[1];  // max over edges of |r| / |x|
+                ss.rel = std::isfinite(m2[0]) ? m2[1] : HUGE_VAL;  // max over edges of |r| / |x|
             }
             have_r = false;
             if (sg_log()) fprintf(stderr, "[sgrt] FP64 residual after %d sweeps: %.3e\n", ss.sweeps, ss.rel);
             if (ss.rel <= rtol) { ss.converged = 1; break; }
-            if (ss.sweeps >= max_sweeps || !std::isfinite(ss.rel)) break;
+            if (!std::isfinite(ss.rel)) {
+                nonfinite = true;
+                if (o.solver == SG_SOLVER_AUTO) use_gmres = 1;
+                break;
+            }
+            if (ss.sweeps >= max_sweeps) break;
             // correction (I - K) d = r by sweeps in the working precision; r / rel is at most
             // |x| per edge, which keeps it well inside the FP32 range
             const double sc = 1.0 / ss.rel;
@@ -682,10 +698,12 @@ sg_status solve_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Exec &t
             int stalled2 = 0;
             SG_TRY(neumann<Real>(s, st, tm, crhs, c0, c1, 0, std::max(correction_stop(warm, it, ss.rel, rtol), floor_rel),
                                  max_sweeps, ss, stalled2));
-            launch_axpy_real_to64<Real>(s.x64, c0, 1.0 / sc, E, st);
+            // a correction that overflowed is dropped (x64 stays the last finite iterate)
+            if (stalled2 != 2) launch_axpy_real_to64<Real>(s.x64, c0, 1.0 / sc, E, st);
             if (stalled2 && o.solver == SG_SOLVER_AUTO) use_gmres = 1;
         }
     }
+    if (use_gmres && nonfinite) launch_fill<double>(s.x64, 0.0, E, st);
     if (use_gmres) SG_TRY(gmres64<Real>(s, st, tm, S, rtol, m, max_sweeps, ss));
     SG_HIP(hipGetLastError());
     return SG_OK;
@@ -898,7 +916,7 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
         worst = 0.0;
         for (int k = 0; k < nl; ++k) {
             const double rel = m2[2 * k + 1];  // max over edges of |r| / |x|
-            worst = std::max(worst, std::isfinite(rel) ? rel : HUGE_VAL);
+            worst = std::max(worst, std::isfinite(rel) && std::isfinite(m2[2 * k]) ? rel : HUGE_VAL);
             sc[k] = rel > 0 ? 1.0 / rel : 1.0;
         }
         return SG_OK;
@@ -1347,6 +1365,16 @@ sg_status check_opts(const sg_solve_opts *opts, sg_solve_opts &o) {
 
 
 uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st) {
+    return reservations(d, nullptr, false, st);
+}
+
+uint64_t solve_reservation(const sg_scene_desc *d, const sg_solve_opts &o, bool with_gmres) {
+    sg_status st;
+    const uint64_t all = reservations(d, &o, with_gmres, &st);
+    return st == SG_OK ? all - reservations(d, nullptr, false, &st) : 0;
+}
+
+uint64_t reservations(const sg_scene_desc *d, const sg_solve_opts *o, bool with_gmres, sg_status *st) {
     int64_t N, E, nnz;
     int dmax;
     *st = validate(d, N, E, nnz, dmax);
@@ -1381,8 +1409,20 @@ uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st) {
         b += a(e, 4) * 2 + a(n, 4) * 2 + a(z + 64, 4) + a(e * nl, 4) * 3 + a(n * nl, 4) * 2 + a(68 * nl, 8) +
              a(nl, 4);
     }
+    if (o) {  // what a solve with these options allocates beyond the scene's arrays
+        if (o->build_col_idx) b += a(z, 4);
+        if (nl == 1) {
+            // FP64 solves trade the FP32 working arrays (released first) for FP64 ones
+            if (o->precision == SG_FP64) b += (a(e, 8) * 9 + a(n, 8) * 4 + a(z, 8)) - (a(e, 4) * 9 + a(n, 4) * 4 + a(z, 4));
+            if (with_gmres) {
+                const uint64_t m = o->gmres_restart > 0 ? (uint64_t)std::min(std::max(o->gmres_restart, 2), 64) : 32;
+                b += a((m + 1) * e, 8);
+            }
+        }
+    }
     return b;
 }
+
 }  // namespace sg
 
 extern "C" {

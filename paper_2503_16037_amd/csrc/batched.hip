@@ -127,7 +127,7 @@ __device__ __forceinline__ float2 wide_node(int l, int lane, int lam, bool lv, f
                     const double rb = (Sb - (double)x[bi]) + (double)rl * (double)acc[n];
                     y[bi] = (XT)rb;
                     sum += fabs(rb);
-                    mrel = fmax(mrel, fabs(rb) / (fabs((double)x[bi]) + kRelFloor));
+                    mrel = fmax(mrel, keep_nan(fabs(rb) / (fabs((double)x[bi]) + kRelFloor)));
                 } else {
                     const float src = rhs ? rhs[bi] : rl * sl * qsun[b];
                     const float yv = src + rl * (float)acc[n];
@@ -135,7 +135,7 @@ __device__ __forceinline__ float2 wide_node(int l, int lane, int lam, bool lv, f
                     if (monitor) {
                         const double du = fabs((double)yv - (double)x[bi]);
                         sum += du;
-                        mrel = fmax(mrel, du / (fabs((double)yv) + kRelFloor));
+                        mrel = fmax(mrel, keep_nan(du / (fabs((double)yv) + kRelFloor)));
                     }
                 }
             }
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_bfirst(int N, int nl, const long long *
         x[bi] = yv;
         const double du = fabs((double)yv);
         sum += du;
-        mrel = fmax(mrel, du / (du + kRelFloor));
+        mrel = fmax(mrel, keep_nan(du / (du + kRelFloor)));
     }
     meas[(long long)l * nl + lam] = make_float2((float)sum, (float)mrel);
 }
@@ -269,7 +269,7 @@ __device__ __forceinline__ float2 pack_node(int l, int lam, bool lv, float s, in
                     const double rb = (Sb - (double)x[bi]) + (double)rl * (double)acc[n];
                     y[bi] = (XT)rb;
                     sum += fabs(rb);
-                    mrel = fmax(mrel, fabs(rb) / (fabs((double)x[bi]) + kRelFloor));
+                    mrel = fmax(mrel, keep_nan(fabs(rb) / (fabs((double)x[bi]) + kRelFloor)));
                 } else {
                     const float src = rhs ? rhs[bi] : rl * sl * qsun[b];
                     const float yv = src + rl * (float)acc[n];
@@ -277,7 +277,7 @@ __device__ __forceinline__ float2 pack_node(int l, int lam, bool lv, float s, in
                     if (monitor) {
                         const double du = fabs((double)yv - (double)x[bi]);
                         sum += du;
-                        mrel = fmax(mrel, du / (fabs((double)yv) + kRelFloor));
+                        mrel = fmax(mrel, keep_nan(du / (fabs((double)yv) + kRelFloor)));
                     }
                 }
             }

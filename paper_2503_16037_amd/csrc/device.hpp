@@ -163,6 +163,11 @@ __device__ __forceinline__ double block_max(double v) {
 // radiances below it (in units of the solar flux) count as absolute.
 constexpr double kRelFloor = 1e-30;
 
+// A per-edge measure that is NaN (an overflowed iterate: inf - inf, inf / inf) becomes
+// +inf, so that the running maxima, which take fmax and drop NaN, keep it and the host
+// sees a non-finite measure instead of a zero.
+__device__ __forceinline__ double keep_nan(double v) { return v == v ? v : __builtin_huge_val(); }
+
 // Deterministic block sum; every thread must call it; returns the total in thread 0.
 template <int kThreads>
 __device__ __forceinline__ double block_sum(double v) {

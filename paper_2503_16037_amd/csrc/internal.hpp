@@ -134,6 +134,7 @@ struct Scene {
     double *x64 = nullptr, *r64 = nullptr;  // [E * n_lambda]
     double *gm_V = nullptr;                 // GMRES basis [(m+1) * E]
     int gm_m = 0;
+    bool gm_nomem = false;                  // the last solve ran out of budget allocating the basis
     double *partial = nullptr;  // block partial sums (GMRES dot products)
     float2 *meas = nullptr;      // [N][n_lambda] per-node (sum, max relative) of the last sweep's changes
     double *meas_part = nullptr;  // [node_chunks(N, n_lambda)][n_lambda][2] chunk reductions of meas
@@ -187,6 +188,11 @@ sg_status solve_scene(Scene &s, const sg_solve_opts &o, hipStream_t st, double *
 sg_status check_opts(const sg_solve_opts *opts, sg_solve_opts &o);
 // device bytes a scene reserves (validates the description; *st = its status)
 uint64_t scene_reservation(const sg_scene_desc *d, sg_status *st);
+// device bytes a solve with options o may allocate beyond the scene's reservation: the FP64
+// working arrays, the CSR column index, and (with_gmres) the GMRES basis (0 if d is invalid)
+uint64_t solve_reservation(const sg_scene_desc *d, const sg_solve_opts &o, bool with_gmres);
+// both in one validation: the scene's reservation plus, with o, its solve's (*st = status)
+uint64_t reservations(const sg_scene_desc *d, const sg_solve_opts *o, bool with_gmres, sg_status *st);
 
 // ---- runtime.cpp ----
 // persistent grid of the single-wavelength sweep (0 = default shape when autotune is off);

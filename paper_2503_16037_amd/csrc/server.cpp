@@ -1,13 +1,20 @@
 // Serving: continuous batching of scenes of uneven size on one device.
 //
 // sg_submit copies a scene description on the host and queues it.  Worker
-// threads (one per resident slot, each bound to one of n_streams device
-// streams) admit the head of the queue when a slot is free and the scene's
-// reserved bytes, added to those of the admitted scenes, fit the context's HBM
-// budget, upload it, solve it (every
+// threads (one per resident slot, each with a device stream of its own: a solve
+// captures its sweep chunks as HIP graphs, and a capture takes in every launch
+// made on its stream, so two workers never share one) admit the head of the
+// queue when a slot is free and the scene's reserved bytes (the scene's arrays
+// and what a solve with the server's options allocates), added to those of the
+// admitted scenes, fit the context's HBM budget, upload it, solve it (every
 // scene keeps its own device state, so a result does not depend on what else
-// is running) and release its memory, which admits the next request.  Work of
-// different resident scenes overlaps on the device through their streams.
+// is running) and release its memory, which admits the next request.  A request
+// that runs out of budget in the mix (its scene or its solve: a GMRES fallback
+// allocates its basis; the block cache may hand out blocks up to 5/4 of a
+// request) goes back to the head of the queue and runs again once memory frees
+// up, with the basis added to its reservation; alone, it runs once more on an
+// emptied cache before it fails.  Work of different resident scenes overlaps
+// on the device through their streams.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -33,7 +40,9 @@ double now_ms() {
 
 struct Request {
     uint64_t ticket = 0;
-    uint64_t bytes = 0;
+    uint64_t bytes = 0;        // reservation used for admission
+    bool gmres_added = false;  // bytes include the GMRES basis (after a solve ran out of budget)
+    bool retried_cold = false;  // ran again alone on an emptied block cache
     double t_arrival = 0.0, t_done = 0.0;
     // owned copy of the description
     sg_scene_desc d{};
@@ -106,6 +115,7 @@ struct Server {
     std::unordered_map<uint64_t, std::unique_ptr<Request>> tickets;
     std::vector<double> latencies;
     uint64_t next_ticket = 1;
+    uint64_t n_finished = 0;  // requests finished so far (a requeued request waits for the next one)
     int running = 0;
     uint64_t reserved = 0;  // reservations of the admitted requests
     bool stop = false;
@@ -119,12 +129,13 @@ struct Server {
         r->done = true;
         r->t_done = now_ms();
         latencies.push_back(r->t_done - r->t_arrival);
+        ++n_finished;
         cv.notify_all();
     }
 
     void worker(int w) {
         (void)hipSetDevice(ctx->device);
-        hipStream_t st = streams[w % streams.size()];
+        hipStream_t st = streams[w];
         while (true) {
             Request *r = nullptr;
             {
@@ -153,29 +164,48 @@ struct Server {
             }
             Scene *sc = new Scene();
             sg_status s = create_scene(ctx, &r->d, st, *sc);
+            if (s == SG_OK) s = solve_scene(*sc, opts.solve, st, r->radiance.data(), 0, &r->info);
+            std::string err;
+            if (s != SG_OK) err = t_last_error();
+            const bool gmres_nomem = sc->gm_nomem;
+            free_scene(sc);
+            delete sc;
             if (s == SG_E_NOMEM) {
-                free_scene(sc);
-                delete sc;
                 std::unique_lock<std::mutex> lk(mu);
                 --running;
                 reserved -= r->bytes;
-                if (running == 0) {  // nothing else holds memory: it will never fit
+                // the solve fell back to GMRES, whose basis the reservation left out
+                if (gmres_nomem && !r->gmres_added) {
+                    r->bytes += solve_reservation(&r->d, opts.solve, true) - solve_reservation(&r->d, opts.solve, false);
+                    r->gmres_added = true;
+                }
+                if (r->bytes > ctx->budget) {
                     lk.unlock();
                     finish(r, SG_E_NOMEM, "scene does not fit the HBM budget");
                     continue;
                 }
-                pending.push_front(r);  // retry when another scene finishes
-                cv.wait(lk);
+                if (running == 0) {
+                    // alone and still out of budget: the pool may have handed out cached blocks
+                    // larger than asked for (up to 5/4); with the cache released every block is
+                    // exact and the reservation bounds the scene's bytes, so run once more
+                    if (!r->retried_cold) {
+                        r->retried_cold = true;
+                        pool_trim(ctx, 0);
+                        pending.push_front(r);
+                        cv.notify_all();
+                        continue;
+                    }
+                    lk.unlock();
+                    finish(r, SG_E_NOMEM, err.empty() ? "scene does not fit the HBM budget" : err);
+                    continue;
+                }
+                // retry once another request has finished (others are running, so one will)
+                pending.push_front(r);
+                const uint64_t f0 = n_finished;
+                cv.wait(lk, [&] { return n_finished != f0; });
                 continue;
             }
-            std::string err;
-            if (s == SG_OK) {
-                r->drop_inputs();
-                s = solve_scene(*sc, opts.solve, st, r->radiance.data(), 0, &r->info);
-            }
-            if (s != SG_OK) err = t_last_error();
-            free_scene(sc);
-            delete sc;
+            r->drop_inputs();
             {
                 std::lock_guard<std::mutex> lk(mu);
                 --running;
@@ -205,8 +235,12 @@ sg_status sg_server_create(sg_ctx *ctx_, const sg_server_opts *opts, sg_server *
         set_error("server opts abi_version mismatch");
         return SG_E_ABI;
     }
-    if (opts->max_resident < 1 || opts->queue_cap < 1 || opts->n_streams < 1 || opts->n_streams > 8) {
-        set_error("max_resident >= 1, queue_cap >= 1, n_streams in 1..8 required");
+    if (opts->max_resident < 1 || opts->queue_cap < 1 || opts->n_streams < 1 || opts->n_streams > 64) {
+        set_error("max_resident >= 1, queue_cap >= 1, n_streams in 1..64 required");
+        return SG_E_INVALID;
+    }
+    if (opts->max_resident > opts->n_streams) {
+        set_error("every resident slot needs a stream of its own: max_resident <= n_streams required");
         return SG_E_INVALID;
     }
     sg_solve_opts so;
@@ -224,7 +258,7 @@ sg_status sg_server_create(sg_ctx *ctx_, const sg_server_opts *opts, sg_server *
         set_error("hipSetDevice failed");
         return SG_E_DEVICE;
     }
-    for (int i = 0; i < opts->n_streams; ++i) {
+    for (int i = 0; i < opts->max_resident; ++i) {  // one stream per worker
         hipStream_t st;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
             set_error("hipStreamCreate failed");
@@ -245,7 +279,7 @@ sg_status sg_submit(sg_server *srv, const sg_scene_desc *desc, uint64_t *ticket)
         return SG_E_INVALID;
     }
     sg_status st;
-    const uint64_t bytes = scene_reservation(desc, &st);
+    const uint64_t bytes = reservations(desc, &srv->opts.solve, srv->opts.solve.solver == SG_SOLVER_GMRES, &st);
     if (st != SG_OK) return st;
     if (bytes > srv->ctx->budget) {
         set_error("scene alone exceeds the HBM budget");

@@ -216,7 +216,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int N, int groups, const 
             const Real yn = sb + acc;
             y[b] = yn;
             r = fabs((double)yn - (double)xb);
-            u = r / (fabs((double)yn) + kRelFloor);
+            u = keep_nan(r / (fabs((double)yn) + kRelFloor));
         }
         if (monitor) {
             r = wave_sum(r);
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_first(int N, const long long *
         x[off + n] = v;
         const double a = fabs((double)v);
         r += a;
-        u = fmax(u, a / (a + kRelFloor));
+        u = fmax(u, keep_nan(a / (a + kRelFloor)));
     }
     r = wave_sum(r);
     u = wave_max(u);
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_residual64(int N, int groups, 
             const double rb = (sb - xb) + acc;
             r[b] = rb;
             a = fabs(rb);
-            u = a / (fabs(xb) + kRelFloor);
+            u = keep_nan(a / (fabs(xb) + kRelFloor));
         }
         a = wave_sum(a);
         u = wave_max(u);
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) void k_spmv_big(int nbig, const int *__restric
         y[off + n] = yn;
         if (monitor) {
             r = fabs((double)yn - (double)x[off + n]);
-            u = r / (fabs((double)yn) + kRelFloor);
+            u = keep_nan(r / (fabs((double)yn) + kRelFloor));
         }
     }
     if (monitor) {
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(256) void k_residual64_big(int nbig, const int *__r
         const double rb = ((double)S[off + n] - xb) + acc;
         res[off + n] = rb;
         a = fabs(rb);
-        u = a / (fabs(xb) + kRelFloor);
+        u = keep_nan(a / (fabs(xb) + kRelFloor));
     }
     a = block_sum<256>(a);
     u = block_max<256>(u);

@@ -110,3 +110,55 @@ def test_largest_degree_batched(ctx):
             err = rel(rad[k], oracle.run(sc, abs_scale=float(sc.abs_scale[k]))["radiance"])
             say("degree 64 batched", nl, k, err)
             assert err < 1e-4
+
+
+def top_cluster(mu_s_dx, seed=0):
+    """Four nodes of a 2 x 2 x 1 grid within 14 / 2^16 voxel of the midpoint of the top
+    face's shared corner line, fully coupled, with the literal node weight mu_s * voxel edge:
+    edges and sun paths are so short that K's spectral radius is about mu_s_dx / 2 and the
+    source about mu_s_dx (the FP64 oracle solves it by GMRES)."""
+    S = scenes.FX
+    rng = np.random.default_rng(seed)
+    sc = scenes.make_random_small(seed, nx=2, ny=2, nz=1, surface=False)
+    pos = []
+    for iy in range(2):
+        for ix in range(2):
+            p = np.array([S, S, S])
+            p[:2] += np.array([ix * 2 - 1, iy * 2 - 1]) * rng.integers(2, 14, 2)
+            p[2] -= rng.integers(2, 14)
+            pos.append(p)
+    a, b = np.triu_indices(4, 1)
+    adj_ptr, adj_idx = scenes.adjacency_from_pairs(4, a, b)
+    dx = sc.voxel_m
+    return sc.with_(vol_pos_fx=np.array(pos, np.int32), adj_ptr=adj_ptr, adj_idx=adj_idx,
+                    mu_s=np.full((1, 2, 2), mu_s_dx / dx, np.float32),
+                    mu_a=np.full((1, 2, 2), 0.1 * mu_s_dx / dx, np.float32), node_weight_mode=1)
+
+
+@pytest.mark.parametrize("n_lambda", [1, 3])
+def test_overflowing_neumann_series_ends_finite_or_unconverged(ctx, n_lambda):
+    """The literal node weight (mu_s times the voxel edge, 2000 here) on a tight cluster
+    makes the FP32 Neumann iterate grow about 1000-fold per sweep, so it overflows inside one
+    chunk of sweeps (inf - inf = NaN in the convergence measures).  The solve must not
+    report convergence on such an iterate: it ends converged with finite radiances (one
+    wavelength: GMRES restarted from zero, matching the oracle's GMRES solve) or reports
+    SG_E_NOCONV."""
+    from paper_2503_16037_amd import sgrt
+    sc = top_cluster(2000.0)
+    if n_lambda > 1:
+        sc = sc.with_(abs_scale=np.array([0.5, 1.0, 2.0][:n_lambda], np.float32))
+    say("overflowing Neumann series", sc.name, n_lambda)
+    with sgrt.Scene(ctx, sc) as g:
+        rad, info = g.solve(allow_noconv=True)
+    assert info["status"] in (0, sgrt.SG_E_NOCONV), info
+    if info["status"] == 0:
+        assert info["converged"] == 1 and np.all(np.isfinite(rad)), info
+        assert info["rel_residual"] <= 1e-6
+    else:
+        assert info["converged"] == 0 and not info["rel_residual"] <= 1e-6, info
+    if n_lambda == 1:  # GMRES from zero solves it, as the oracle does
+        assert info["status"] == 0 and info["gmres_used"] == 1
+        ora = oracle.run(sc)
+        assert ora["solve"]["gmres"]
+        scale = np.abs(ora["radiance"]).max()
+        assert np.abs(rad - ora["radiance"]).max() <= 1e-4 * scale

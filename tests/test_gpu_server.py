@@ -92,7 +92,7 @@ def test_served_mix_with_concurrent_arrivals(ctx):
     from paper_2503_16037_amd import sgrt
     stream = small_stream(8, max_voxels=4000)
     say("concurrent arrivals")
-    srv = sgrt.Server(ctx, max_resident=3, queue_cap=64, n_streams=2)
+    srv = sgrt.Server(ctx, max_resident=3, queue_cap=64, n_streams=3)
     tickets = [None] * len(stream)
 
     def submitter():
@@ -117,7 +117,7 @@ def test_over_budget_scene_is_rejected():
     from paper_2503_16037_amd import sgrt
     say("over budget")
     with sgrt.Context(0, hbm_budget_bytes=8 << 20) as small:
-        srv = sgrt.Server(small, max_resident=2, queue_cap=4, n_streams=1)
+        srv = sgrt.Server(small, max_resident=2, queue_cap=4, n_streams=2)
         try:
             big = scenes.make_plume(nx=32, ny=32, nz=16)
             with pytest.raises(sgrt.SgError) as e:
@@ -140,7 +140,7 @@ def test_budget_serialises_scenes_that_fit_one_at_a_time():
             need = g.sizes["device_bytes"]
             ref, _ = g.solve()
     with sgrt.Context(0, hbm_budget_bytes=int(need * 1.5)) as c1:
-        srv = sgrt.Server(c1, max_resident=4, queue_cap=8, n_streams=2)
+        srv = sgrt.Server(c1, max_resident=4, queue_cap=8, n_streams=4)
         try:
             ts = [srv.submit(sc) for _ in range(4)]
             for t in ts:
@@ -154,10 +154,13 @@ def test_budget_serialises_scenes_that_fit_one_at_a_time():
 def test_queue_full_reports_busy(ctx):
     from paper_2503_16037_amd import sgrt
     say("queue back-pressure")
-    sc = scenes.make_plume(nx=48, ny=48, nz=24)
+    # the one slot is busy with a cloud (tens of ms to create and solve) while four small
+    # scenes arrive: the queue holds two of them
+    head = scenes.make_cloud()
+    sc = scenes.make_plume(nx=16, ny=16, nz=8)
     srv = sgrt.Server(ctx, max_resident=1, queue_cap=2, n_streams=1)
     try:
-        got = [srv.submit(sc) for _ in range(6)]
+        got = [srv.submit(head)] + [srv.submit(sc) for _ in range(4)]
         assert any(t is None for t in got)
         for t in got:
             if t is not None:
@@ -181,3 +184,50 @@ def test_reservation_estimate_matches_created_scene(ctx):
         finally:
             srv.close()
         assert est == created, (sc.name, est, created)
+
+
+def test_resident_slots_need_streams_of_their_own(ctx):
+    """Two resident slots on one stream would let one slot's launches fall into the
+    other's graph capture: the server refuses max_resident > n_streams."""
+    from paper_2503_16037_amd import sgrt
+    with pytest.raises(sgrt.SgError) as e:
+        sgrt.Server(ctx, max_resident=3, queue_cap=4, n_streams=2)
+    assert e.value.status == sgrt.SG_E_INVALID
+
+
+def test_tight_budget_with_a_gmres_fallback_in_the_mix():
+    """A scene whose solve falls back to GMRES (literal node weight on clustered nodes)
+    allocates the GMRES basis during its solve, beyond its reservation.  Under a budget
+    that holds both scenes' reservations but not the basis besides, the request is put
+    back and solved again once the other has finished: both results equal their solo
+    solves bit for bit."""
+    from paper_2503_16037_amd import sgrt
+    from test_oracle_matrix_solve import clustered_scene
+    a = clustered_scene()
+    b = scenes.make_plume(nx=24, ny=24, nz=12)
+    say("tight budget with a GMRES fallback")
+    with sgrt.Context(0) as c0:
+        refs = []
+        for sc in (a, b):
+            with sgrt.Scene(c0, sc) as g:
+                r, info = g.solve()
+                refs.append(np.asarray(r))
+            if sc is a:
+                assert info["gmres_used"] == 1 and info["converged"] == 1
+        srv0 = sgrt.Server(c0, max_resident=1, queue_cap=2, n_streams=1)
+        try:
+            need = srv0.reservation(a) + srv0.reservation(b)
+        finally:
+            srv0.close()
+    with sgrt.Context(0, hbm_budget_bytes=need + 1024) as c1:
+        srv = sgrt.Server(c1, max_resident=2, queue_cap=8, n_streams=2)
+        try:
+            for order in ((b, a), (a, b), (b, a, b, a)):
+                ts = [srv.submit(sc) for sc in order]
+                for sc, t in zip(order, ts):
+                    rad, info = srv.wait(t)
+                    assert info["status"] == 0 and info["converged"] == 1, sc.name
+                    ref = refs[0 if sc is a else 1]
+                    assert np.array_equal(rad.reshape(ref.shape), ref), sc.name
+        finally:
+            srv.close()
