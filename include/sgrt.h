@@ -292,12 +292,33 @@ enum { SG_TRACE_EDGE = 0, SG_TRACE_SUN = 1, SG_TRACE_VIEW = 2 };
  * SG_TRACE_VIEW id = pixel ix + nx*iy (from its surface point along
  * view_dir).  Host buffers: voxels [n_ids][cap] (int32 voxel ids), dt
  * [n_ids][cap] (parameter length inside the voxel, as double), count
- * [n_ids] (voxels of the path; a value > cap means truncated output).
+ * [n_ids] (voxels of the path; a value > cap means truncated output); slots
+ * past a path's count hold voxel -1 and dt 0.
  * With periodic axes the edge walk follows the shortest periodic image and
  * every voxel id is wrapped into the grid.
+ * Errors: SG_E_INVALID (NULL buffers, bad kind, sizes <= 0, an id out of
+ * range), SG_E_DEVICE.
  */
 sg_status sg_trace(sg_scene *scene, int32_t kind, const int64_t *ids, int32_t n_ids, int32_t cap,
                    int32_t *voxels, double *dt, int32_t *count);
+
+/*
+ * sg_trace for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, outputs and errors, the same kernel, but no device
+ * allocation and no free.  The ids and the traversals are staged in a
+ * staging area the library holds on each GPU for the life of the process
+ * (sg_trace_noalloc_capacity() bytes, 16 MiB): a call needs about
+ * 12 n_ids cap + 12 n_ids bytes of it (each of its four arrays rounded up to
+ * 256 bytes) and larger calls are refused with SG_E_INVALID.  Calls on one
+ * GPU share that area: the library serialises them within the process (a
+ * per-device lock held until the call's stream has drained), so concurrent
+ * calls wait rather than race.  Host buffers, as for sg_trace.
+ */
+sg_status sg_trace_noalloc(sg_scene *scene, int32_t kind, const int64_t *ids, int32_t n_ids, int32_t cap,
+                           int32_t *voxels, double *dt, int32_t *count);
+/* Bytes of the staging area of sg_trace_noalloc on each GPU. */
+uint64_t sg_trace_noalloc_capacity(void);
 
 /* ------------------------------------------------------------------------------------ */
 /* The scattering graph itself (Sec. 2, Eq. 4; Sec. 3)                                   */

@@ -1029,7 +1029,6 @@ sg_status solve_batched(Scene &s, const sg_solve_opts &o, hipStream_t st, double
 
 using namespace sg;
 
-struct sg_scene : public sg::Scene {};
 
 extern "C" {
 
@@ -1051,6 +1050,7 @@ sg_status sg_ctx_create(int32_t hip_device, uint64_t hbm_budget_bytes, sg_ctx **
     c->device = hip_device;
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)fr);
     ctx = c.get();
+    SG_TRY(scratch_setup(hip_device));  // the allocation-free trace's staging on this device
     SG_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     *out = c.release();
     return SG_OK;

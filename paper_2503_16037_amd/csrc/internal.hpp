@@ -194,6 +194,13 @@ uint64_t solve_reservation(const sg_scene_desc *d, const sg_solve_opts &o, bool 
 // both in one validation: the scene's reservation plus, with o, its solve's (*st = status)
 uint64_t reservations(const sg_scene_desc *d, const sg_solve_opts *o, bool with_gmres, sg_status *st);
 
+// ---- noalloc.hip ----
+// looks up, once per device and with that device current, the device address of the
+// allocation-free trace's staging array (called by sg_ctx_create)
+sg_status scratch_setup(int device);
+// staging bytes of an allocation-free trace of n_ids paths of cap slots
+uint64_t trace_noalloc_bytes(int64_t n_ids, int64_t cap);
+
 // ---- runtime.cpp ----
 // persistent grid of the single-wavelength sweep (0 = default shape when autotune is off);
 // x and y are scratch vectors that tuning may overwrite
@@ -293,5 +300,6 @@ void launch_batched_gather(Scene &s, hipStream_t st, const double *phi, int scat
 
 }  // namespace sg
 
-// the public handle of a context
+// the public handles of a context and a scene
 struct sg_ctx : public sg::Ctx {};
+struct sg_scene : public sg::Scene {};

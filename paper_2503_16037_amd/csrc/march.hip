@@ -230,6 +230,10 @@ __global__ __launch_bounds__(64) void k_trace(int kind, int N, int nx, int ny, i
         return true;
     });
     count[t] = c;
+    for (int j = min(c, cap); j < cap; ++j) {  // slots past the path: defined filler
+        vox_out[(long long)t * cap + j] = -1;
+        dt_out[(long long)t * cap + j] = 0.0;
+    }
 }
 
 }  // namespace

@@ -114,6 +114,8 @@ def lib():
                 "sg_export_csr": (I32, [P, I32, P, P, P]),
                 "sg_export_vector": (I32, [P, I32, P]),
                 "sg_trace": (I32, [P, I32, P, I32, I32, P, P, P]),
+                "sg_trace_noalloc": (I32, [P, I32, P, I32, I32, P, P, P]),
+                "sg_trace_noalloc_capacity": (C.c_uint64, []),
                 "sg_server_create": (I32, [P, P, P]),
                 "sg_submit": (I32, [P, P, P]),
                 "sg_poll": (I32, [P, U64, P, P, P]),
@@ -331,6 +333,17 @@ class Scene:
         dt = np.zeros((n, cap), np.float64)
         cnt = np.zeros(n, np.int32)
         _check(lib().sg_trace(self.handle, TRACE[kind], _ptr(ids), n, cap, _ptr(vox), _ptr(dt), _ptr(cnt)))
+        return vox, dt, cnt
+
+    def trace_noalloc(self, kind: str, ids, cap: int = 512):
+        """trace() through the allocation-free entry point (staging in the library's
+        per-device area instead of per-call device buffers)."""
+        ids = np.ascontiguousarray(ids, np.int64)
+        n = ids.shape[0]
+        vox = np.zeros((n, cap), np.int32)
+        dt = np.zeros((n, cap), np.float64)
+        cnt = np.zeros(n, np.int32)
+        _check(lib().sg_trace_noalloc(self.handle, TRACE[kind], _ptr(ids), n, cap, _ptr(vox), _ptr(dt), _ptr(cnt)))
         return vox, dt, cnt
 
 
