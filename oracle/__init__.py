@@ -50,6 +50,9 @@ def lib():
             P = C.c_void_p
             L.or_trace_p.restype = C.c_int
             L.or_trace_p.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, C.c_int, P, P, C.c_int]
+            L.or_trace_many.restype = None
+            L.or_trace_many.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, P, P, C.c_int, C.c_int, P, P,
+                                        P]
             L.or_trace.restype = C.c_int
             L.or_trace.argtypes = [C.c_int, C.c_int, C.c_int, P, P, C.c_int, P, P, C.c_int]
             L.or_lattice.restype = None
@@ -120,6 +123,21 @@ def trace(nx, ny, nz, P, D, is_ray, cap=None, periodic=0):
     if n < 0:
         raise ValueError("segment leaves the grid")
     return vox[:n].copy(), dt[:n].copy()
+
+
+def trace_many(nx, ny, nz, P, D, is_ray, cap, periodic=0):
+    """trace() of many paths: P, D [n][3]; returns vox [n][cap] (int64), dt [n][cap] and the
+    voxel count of each path (which may exceed cap; slots past the path hold -1 and 0)."""
+    P = np.ascontiguousarray(np.broadcast_to(np.asarray(P, np.int64), (len(P), 3)))
+    D = np.ascontiguousarray(np.broadcast_to(np.asarray(D, np.int64), P.shape))
+    n = P.shape[0]
+    vox = np.zeros((n, cap), np.int64)
+    dt = np.zeros((n, cap), np.float64)
+    cnt = np.zeros(n, np.int64)
+    lib().or_trace_many(nx, ny, nz, int(periodic), n, _p(P), _p(D), int(is_ray), int(cap), _p(vox), _p(dt), _p(cnt))
+    if (cnt < 0).any():
+        raise ValueError("a segment leaves the grid")
+    return vox, dt, cnt
 
 
 def lattice(N: int) -> np.ndarray:

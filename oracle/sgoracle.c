@@ -221,6 +221,23 @@ int or_trace_p(int nx, int ny, int nz, int periodic, const int64_t *P, const int
     return r < 0 ? r : b.n;
 }
 
+/* Many walks at once (for checks of whole scenes): path k starts at P[k] along D[k];
+   its voxels and parameter lengths go to vox[k][cap], dt[k][cap] (slots past the path:
+   -1 and 0), its voxel count (which may exceed cap) to count[k], or a negative code. */
+void or_trace_many(int nx, int ny, int nz, int periodic, int64_t n, const int64_t *P, const int64_t *D,
+                   int is_ray, int cap, int64_t *vox, double *dt, int64_t *count) {
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t k = 0; k < n; ++k) {
+        trace_buf b = {vox + k * cap, dt + k * cap, cap, 0};
+        int r = dda_walk_p(nx, ny, nz, periodic, P + 3 * k, D + 3 * k, is_ray, trace_visit, &b);
+        count[k] = r < 0 ? r : b.n;
+        for (int j = b.n < cap ? b.n : cap; j < cap; ++j) {
+            vox[k * cap + j] = -1;
+            dt[k * cap + j] = 0.0;
+        }
+    }
+}
+
 typedef struct {
     const double *mu_e;
     double tau; /* accumulated sum of mu_e * dt (dt in parameter units) */

@@ -241,11 +241,12 @@ def test_plume_full_size(ctx):
 
 def test_cloud_full_size(ctx):
     """The 128 x 128 x 48 cloud (18.3 M couplings, 424 M nonzeros; single-scattering
-    albedo 0.999, sun at 70 deg): every pixel against the oracle, the structure
-    bit-exact, and the transmittances of all edges."""
+    albedo 0.999, sun at 70 deg): every pixel against the oracle, the structure (row
+    pointers and column indices) bit-exact, the K values, and the transmittances of all
+    edges."""
     sc = scenes.make_cloud()
     say("cloud full size", sc.name, sc.n_edges)
-    ora = oracle.run(sc, want_matrix=False)
+    ora = oracle.run(sc, want_matrix=True)
     say("  oracle done", ora["solve"])
     with _scene(ctx, sc) as g:
         rad, info = g.solve(timing=True)
@@ -254,8 +255,12 @@ def test_cloud_full_size(ctx):
         err = rel_err(rad, ora["radiance"])
         say("  max / p99 pixel rel err", err.max(), np.percentile(err, 99))
         assert err.max() < 1e-4
-        rp, _, _ = g.export_csr(values=False)
+        rp, col, val = g.export_csr()
         assert np.array_equal(rp, ora["row_ptr"])
+        assert np.array_equal(col, ora["col"])
+        big = ora["val"] > 1e-9 * ora["val"].max()
+        assert rel_err(val[big], ora["val"][big]).max() < 5e-5
+        del col, val
         tau = g.export_vector("tau_s") + g.export_vector("tau_a")
         assert rel_err(tau, ora["tau"]).max() < 1e-5
 
