@@ -788,30 +788,34 @@ sg_status solve_single(Scene &s, const sg_solve_opts &o, hipStream_t st, double 
 // source built on the fly), with the two measures of the single-wavelength sweeps per
 // wavelength (L1 update for the ratio and the stall test, largest per-edge relative
 // update for the stop when relative != 0, else L1 below stop times the first sweep's).
-// A wavelength is done once its stop is met or predicted; stall = a wavelength not done
-// whose L1 ratio (and relative ratio, when that decides the stop) reaches 0.95.  Only the first sweep and the last two of each chunk
-// compute measures.
+// Only the last sweep of each chunk computes the measures (and the first iterate, a copy
+// that reads no previous iterate): a measured sweep reads the previous iterate of every
+// edge and wavelength, half again the bytes of a plain sweep at 64 wavelengths.  The
+// convergence ratio per sweep is the ratio of two measures taken k sweeps apart, to the
+// power 1/k.  A wavelength is done once its stop is met or predicted; stall = a
+// wavelength not done whose L1 ratio (and relative ratio, when that decides the stop)
+// reaches 0.95; a measure that is not finite (an overflowed iterate) sets stalled = 2.
 sg_status neumann_batched(Scene &s, hipStream_t st, Exec &tm, int grid, const float *rhs, float *&xa, float *&xb,
                           int relative, double stop, int max_sweeps, SolveStats &ss, int &stalled) {
     Ctx *ctx = s.ctx;
     const int nl = s.n_lambda;
-    std::vector<double> host((size_t)64 * nl);
+    std::vector<double> host((size_t)4 * nl);
     std::vector<double> l1p(nl, -1.0), l1(nl, 0.0), relp(nl, -1.0), rel(nl, 0.0), l1first(nl, 0.0);
     std::vector<int> done(nl, 0);
-    int chunk = 3, first = 1;  // two measured sweeps after the first give a ratio
+    int chunk = 3, first = 1;  // the first iterate and the third: a ratio over two sweeps
+    int at = 0, at_prev = 0;   // sweep index of the last measure and of the one before
     stalled = 0;
-    double *hist = s.lam_buf + 4 * nl;  // [32][nl][2]
+    double *hist = s.lam_buf + 4 * nl;  // [2][nl][2]: the first iterate's and the chunk's last sweep's
     while (true) {
         chunk = std::max(1, std::min(chunk, 32));
-        const int c_mon = std::max(0, chunk - 2);
         // the first iterate from x = 0 is rhs itself: a copy instead of a sweep
         const int n_copy = first ? 1 : 0;
         auto sweep = [&](int c, const float *a, float *b, hipEvent_t after) {
-            const int mon = (first && c == 0) || c >= c_mon;
+            const int mon = (first && c == 0) || c == chunk - 1;
             if (c < n_copy) launch_bfirst(s, st, rhs, b);
             else launch_spmm(s, st, grid, rhs, a, b, mon);
             if (after) (void)hipEventRecord(after, st);
-            if (mon) launch_measures(s, nl, hist + (size_t)c * nl * 2, st);
+            if (mon) launch_measures(s, nl, hist + (size_t)(c == chunk - 1 ? 1 : 0) * nl * 2, st);
         };
         if (tm.on) {
             for (int c = 0; c < chunk; ++c) {
@@ -821,7 +825,7 @@ sg_status neumann_batched(Scene &s, hipStream_t st, Exec &tm, int grid, const fl
                     hipEvent_t e0 = tm.mark(), e1 = tm.fresh();
                     sweep(c, xa, xb, e1);
                     tm.spmv.push_back({e0, e1});
-                    tm.monitored += (first && c == 0) || c >= c_mon;
+                    tm.monitored += c == chunk - 1;
                 }
                 std::swap(xa, xb);
             }
@@ -840,33 +844,37 @@ sg_status neumann_batched(Scene &s, hipStream_t st, Exec &tm, int grid, const fl
         }
         ss.sweeps += chunk - n_copy;
         SG_HIP(hipGetLastError());
-        SG_TRY(read_scalars(s, st, hist, host.data(), chunk * nl * 2));
-        int c0 = c_mon;
-        if (first) {
-            for (int k = 0; k < nl; ++k) l1first[k] = host[2 * k];
-            c0 = std::max(1, c_mon);
-            first = 0;
+        SG_TRY(read_scalars(s, st, hist, host.data(), 4 * nl));
+        const double *last = host.data() + 2 * nl;  // [nl][2] of the chunk's last sweep
+        if (first) {  // the first iterate's measures: the starting point of the ratios
+            for (int k = 0; k < nl; ++k) {
+                l1first[k] = host[2 * k];
+                l1[k] = host[2 * k];
+                rel[k] = host[2 * k + 1];
+            }
+            at = 1;
         }
+        at_prev = at;
+        at += first ? chunk - 1 : chunk;
+        first = 0;
+        const double gap = (double)(at - at_prev);  // sweeps between the two measures
         bool all = true;
         double need = 1.0;
         for (int k = 0; k < nl; ++k) {
             if (done[k]) continue;
-            for (int c = c0; c < chunk; ++c) {
-                l1p[k] = l1[k];
-                relp[k] = rel[k];
-                l1[k] = host[((size_t)c * nl + k) * 2];
-                rel[k] = host[((size_t)c * nl + k) * 2 + 1];
-            }
-            if (chunk == c0) { all = false; continue; }
-            if (!std::isfinite(l1[k]) || !std::isfinite(rel[k])) { stalled = 1; continue; }
+            l1p[k] = l1[k];
+            relp[k] = rel[k];
+            l1[k] = last[2 * k];
+            rel[k] = last[2 * k + 1];
+            if (!std::isfinite(l1[k]) || !std::isfinite(rel[k])) { stalled = 2; continue; }
             const double stop_k = relative ? stop : stop * l1first[k];
             const double r = relative ? rel[k] : l1[k];
-            const double q = l1p[k] > 0 ? l1[k] / l1p[k] : 0.5;
-            const double qr = relative && relp[k] > 0 ? std::max(q, rel[k] / relp[k]) : q;
+            const double q = l1p[k] > 0 ? std::pow(l1[k] / l1p[k], 1.0 / gap) : 0.5;
+            const double q2 = relp[k] > 0 ? std::pow(rel[k] / relp[k], 1.0 / gap) : 0.0;
+            const double qr = relative && relp[k] > 0 ? std::max(q, q2) : q;
             // the measured update belongs to the previous iterate; the current one's is about q r
             if (r <= stop_k || (l1p[k] > 0 && qr < 0.9 && qr * r <= 0.5 * stop_k)) { done[k] = 1; continue; }
             all = false;
-            const double q2 = relp[k] > 0 ? rel[k] / relp[k] : 0.0;
             if (l1p[k] > 0 && ss.sweeps >= 4 && q >= 0.95 && (!relative || q2 >= 0.95)) stalled = 1;
             const double qa = relative && q2 > 0 ? std::min(q, q2) : q;
             const double qc = std::min(std::max(qa, 1e-12), 0.95);
@@ -884,7 +892,6 @@ sg_status neumann_batched(Scene &s, hipStream_t st, Exec &tm, int grid, const fl
         }
         if (all || stalled || ss.sweeps >= max_sweeps) break;
         chunk = (int)std::ceil(need);
-        if (chunk >= 2) chunk = std::max(chunk, 3);  // keep two monitored sweeps plus work between
     }
     return SG_OK;
 }
@@ -908,7 +915,7 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
     // FP64 residual of x64 for every wavelength: the worst per-edge relative residual, and
     // the scales r / rel (at most |x| per edge: well inside the FP32 range)
     auto residual = [&](double &worst) -> sg_status {
-        launch_bresidual64(s, st, rgrid, s.x64, s.r64);
+        launch_bresidual64(s, st, rgrid, s.x64, s.bS);  // r in FP32: the correction's right-hand side
         launch_measures(s, nl, s.lam_buf + nl, st);  // [nl][2]
         ++ss.sweeps;
         ++ss.refinements;
@@ -942,7 +949,7 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
         if (worst <= rtol) { ss.converged = 1; break; }
         if (stalled || ss.sweeps >= max_sweeps || !std::isfinite(worst)) break;
         SG_HIP(hipMemcpyAsync(d_sc, sc.data(), sizeof(double) * nl, hipMemcpyHostToDevice, st));
-        launch_lam_scale_to_f32(s.r64, d_sc, nl, s.bS, n, st);
+        launch_lam_scale_f32(s.bS, d_sc, nl, n, st);  // r / rel per wavelength
         float *ca = s.bx, *cb = s.by;
         int st2 = 0;
         SG_TRY(neumann_batched(s, st, tm, grid, s.bS, ca, cb, 0, correction_stop(warm, it, worst, rtol), max_sweeps,

@@ -59,7 +59,7 @@ __device__ __forceinline__ float edge_T(float ts, float ta, float s) {
     return __builtin_amdgcn_exp2f(-(ts + s * ta) * 1.4426950408889634f);
 }
 
-template <int DB, class XT, class AccT, bool kResidual>
+template <int DB, class XT, class YT, class AccT, bool kResidual>
 __device__ __forceinline__ float2 wide_node(int l, int lane, int lam, bool lv, float s, int nl, int monitor,
                                             float *__restrict__ qs, const long long *__restrict__ adj_ptr,
                                             const long long *__restrict__ nodeoff, const int *__restrict__ rev,
@@ -67,7 +67,7 @@ __device__ __forceinline__ float2 wide_node(int l, int lane, int lam, bool lv, f
                                             const float *__restrict__ tau_s, const float *__restrict__ tau_a,
                                             const float *__restrict__ brho, const float *__restrict__ bsrc,
                                             const float *__restrict__ rhs, const XT *__restrict__ x,
-                                            XT *__restrict__ y) {
+                                            YT *__restrict__ y) {
     constexpr int kU = 8;
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
@@ -125,13 +125,13 @@ __device__ __forceinline__ float2 wide_node(int l, int lane, int lam, bool lv, f
                 if (kResidual) {
                     const double Sb = (double)(rl * sl * qsun[b]);
                     const double rb = (Sb - (double)x[bi]) + (double)rl * (double)acc[n];
-                    y[bi] = (XT)rb;
+                    y[bi] = (YT)rb;
                     sum += fabs(rb);
                     mrel = fmax(mrel, keep_nan(fabs(rb) / (fabs((double)x[bi]) + kRelFloor)));
                 } else {
                     const float src = rhs ? rhs[bi] : rl * sl * qsun[b];
                     const float yv = src + rl * (float)acc[n];
-                    y[bi] = (XT)yv;
+                    y[bi] = (YT)yv;
                     if (monitor) {
                         const double du = fabs((double)yv - (double)x[bi]);
                         sum += du;
@@ -150,13 +150,13 @@ __device__ __forceinline__ float2 wide_node(int l, int lane, int lam, bool lv, f
 template <int D, bool kResidual>
 constexpr int wide_waves_per_eu() { return kResidual ? 1 : (D <= 40 ? 7 : 5); }
 
-template <int D, class XT, class AccT, bool kResidual>
+template <int D, class XT, class YT, class AccT, bool kResidual>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(wide_waves_per_eu<D, kResidual>()))) void k_spmm_wide(
     int N, int nl, int groups, const long long *__restrict__ adj_ptr, const long long *__restrict__ nodeoff,
     const int *__restrict__ rev, const float *__restrict__ q, const float *__restrict__ qsun,
     const float *__restrict__ tau_s, const float *__restrict__ tau_a, const float *__restrict__ abs_scale,
     const float *__restrict__ brho, const float *__restrict__ bsrc, const float *__restrict__ rhs,
-    const XT *__restrict__ x, XT *__restrict__ y, float2 *__restrict__ meas, int monitor, int dmax) {
+    const XT *__restrict__ x, YT *__restrict__ y, float2 *__restrict__ meas, int monitor, int dmax) {
     extern __shared__ float qs_all[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lam = blockIdx.y * 64 + lane;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(wide_waves_
         const int bucket = (d + 7) >> 3;
         float2 part = make_float2(0.f, 0.f);
 #define SG_NODE(DB)                                                                                              \
-    part = wide_node<DB, XT, AccT, kResidual>(l, lane, lam, lv, s, nl, monitor, qs, adj_ptr, nodeoff, rev, q, \
+    part = wide_node<DB, XT, YT, AccT, kResidual>(l, lane, lam, lv, s, nl, monitor, qs, adj_ptr, nodeoff, rev, q, \
                                               qsun, tau_s, tau_a, brho, bsrc, rhs, x, y)
         if (bucket <= 1) { SG_NODE(8); }
         else if (bucket == 2) { if constexpr (D >= 16) SG_NODE(16); }
@@ -227,14 +227,14 @@ __global__ __launch_bounds__(256) void k_bfirst(int N, int nl, const long long *
 // the same bits.
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 
-template <int DB, class XT, class AccT, bool kResidual>
+template <int DB, class XT, class YT, class AccT, bool kResidual>
 __device__ __forceinline__ float2 pack_node(int l, int lam, bool lv, float s, int nl, int monitor, long long off,
                                             int d, long long base, int dw, const int *__restrict__ srv,
                                             const float *__restrict__ sts, const float *__restrict__ sta,
                                             const float *__restrict__ q, const float *__restrict__ qsun,
                                             const float *__restrict__ brho, const float *__restrict__ bsrc,
                                             const float *__restrict__ rhs, const XT *__restrict__ x,
-                                            XT *__restrict__ y) {
+                                            YT *__restrict__ y) {
     AccT acc[DB];
 #pragma unroll
     for (int n = 0; n < DB; ++n) acc[n] = (AccT)0;
@@ -267,13 +267,13 @@ __device__ __forceinline__ float2 pack_node(int l, int lam, bool lv, float s, in
                 if (kResidual) {
                     const double Sb = (double)(rl * sl * qsun[b]);
                     const double rb = (Sb - (double)x[bi]) + (double)rl * (double)acc[n];
-                    y[bi] = (XT)rb;
+                    y[bi] = (YT)rb;
                     sum += fabs(rb);
                     mrel = fmax(mrel, keep_nan(fabs(rb) / (fabs((double)x[bi]) + kRelFloor)));
                 } else {
                     const float src = rhs ? rhs[bi] : rl * sl * qsun[b];
                     const float yv = src + rl * (float)acc[n];
-                    y[bi] = (XT)yv;
+                    y[bi] = (YT)yv;
                     if (monitor) {
                         const double du = fabs((double)yv - (double)x[bi]);
                         sum += du;
@@ -286,13 +286,13 @@ __device__ __forceinline__ float2 pack_node(int l, int lam, bool lv, float s, in
     return make_float2((float)sum, (float)mrel);
 }
 
-template <int W, int D, class XT, class AccT, bool kResidual>
+template <int W, int D, class XT, class YT, class AccT, bool kResidual>
 __global__ __launch_bounds__(256) void k_spmm_pack(
     int N, int nl, int groups, const long long *__restrict__ adj_ptr, const long long *__restrict__ nodeoff,
     const int *__restrict__ rev, const float *__restrict__ q, const float *__restrict__ qsun,
     const float *__restrict__ tau_s, const float *__restrict__ tau_a, const float *__restrict__ abs_scale,
     const float *__restrict__ brho, const float *__restrict__ bsrc, const float *__restrict__ rhs,
-    const XT *__restrict__ x, XT *__restrict__ y, float2 *__restrict__ meas, int monitor) {
+    const XT *__restrict__ x, YT *__restrict__ y, float2 *__restrict__ meas, int monitor) {
     constexpr int P = 64 / W;  // node slots per wavefront
     __shared__ int srv_all[4][P][64];
     __shared__ float sts_all[4][P][64], sta_all[4][P][64];
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(256) void k_spmm_pack(
         if (dw > 0) {
             const int bucket = (dw + 7) >> 3;
 #define SG_PACK(DB)                                                                                        \
-    part = pack_node<DB, XT, AccT, kResidual>(l, lam, lv, s, nl, monitor, off, max(d, 1), base, dw, srv, sts, \
+    part = pack_node<DB, XT, YT, AccT, kResidual>(l, lam, lv, s, nl, monitor, off, max(d, 1), base, dw, srv, sts, \
                                               sta, q, qsun, brho, bsrc, rhs, x, y)
             if (bucket <= 1) { SG_PACK(8); }
             else if (bucket == 2) { if constexpr (D >= 16) SG_PACK(16); }
@@ -347,10 +347,9 @@ __global__ __launch_bounds__(256) void k_spmm_pack(
     }
 }
 
-__global__ void k_lam_scale_to_f32(const double *__restrict__ a, const double *__restrict__ sc, int nl,
-                                   float *__restrict__ b, long long n) {
+__global__ void k_lam_scale_f32(float *__restrict__ b, const double *__restrict__ sc, int nl, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        b[i] = (float)(a[i] * sc[i % nl]);
+        b[i] = (float)((double)b[i] * sc[i % nl]);
 }
 
 __global__ void k_lam_axpy(double *__restrict__ x, const float *__restrict__ d, const double *__restrict__ sc, int nl,
@@ -518,11 +517,11 @@ int batched_groups(const Scene &s) {
     return (s.N + wide_waves(s) - 1) / wide_waves(s);
 }
 
-template <int W, class XT, class AccT, bool kRes>
-static void launch_pack(Scene &s, hipStream_t st, int grid, const float *rhs, const XT *x, XT *y, int monitor) {
+template <int W, class XT, class YT, class AccT, bool kRes>
+static void launch_pack(Scene &s, hipStream_t st, int grid, const float *rhs, const XT *x, YT *y, int monitor) {
     const int groups = batched_groups(s);
 #define SG_PK(DD)                                                                                                  \
-    hipLaunchKernelGGL((k_spmm_pack<W, DD, XT, AccT, kRes>), dim3(grid), dim3(256), 0, st, s.N, s.n_lambda, groups,  \
+    hipLaunchKernelGGL((k_spmm_pack<W, DD, XT, YT, AccT, kRes>), dim3(grid), dim3(256), 0, st, s.N, s.n_lambda, groups, \
                        s.adj_ptr, s.nodeoff, s.rev, s.q, s.qsun, (const float *)s.tau_s, (const float *)s.tau_a,      \
                        s.abs_scale_d, s.brho, s.bsrc, rhs, x, y, s.meas, monitor)
     if (s.dmax <= 16) SG_PK(16);
@@ -535,19 +534,19 @@ static void launch_pack(Scene &s, hipStream_t st, int grid, const float *rhs, co
 #undef SG_PK
 }
 
-template <class XT, class AccT, bool kRes>
-static void launch_wide(Scene &s, hipStream_t st, int grid, const float *rhs, const XT *x, XT *y, int monitor) {
+template <class XT, class YT, class AccT, bool kRes>
+static void launch_wide(Scene &s, hipStream_t st, int grid, const float *rhs, const XT *x, YT *y, int monitor) {
     const int W = lambda_tile(s);
     grid = std::max(1, std::min(grid, batched_groups(s)));
-    if (W == 8) return launch_pack<8, XT, AccT, kRes>(s, st, grid, rhs, x, y, monitor);
-    if (W == 16) return launch_pack<16, XT, AccT, kRes>(s, st, grid, rhs, x, y, monitor);
-    if (W == 32) return launch_pack<32, XT, AccT, kRes>(s, st, grid, rhs, x, y, monitor);
+    if (W == 8) return launch_pack<8, XT, YT, AccT, kRes>(s, st, grid, rhs, x, y, monitor);
+    if (W == 16) return launch_pack<16, XT, YT, AccT, kRes>(s, st, grid, rhs, x, y, monitor);
+    if (W == 32) return launch_pack<32, XT, YT, AccT, kRes>(s, st, grid, rhs, x, y, monitor);
     const int waves = wide_waves(s);
     const int groups = batched_groups(s);
     dim3 gr(grid, (s.n_lambda + 63) / 64);
     const size_t shm = (size_t)waves * (s.dmax * s.dmax + 64) * sizeof(float);
 #define SG_WIDE(DD)                                                                                                 \
-    hipLaunchKernelGGL((k_spmm_wide<DD, XT, AccT, kRes>), gr, dim3(64 * waves), shm, st, s.N, s.n_lambda, groups,     \
+    hipLaunchKernelGGL((k_spmm_wide<DD, XT, YT, AccT, kRes>), gr, dim3(64 * waves), shm, st, s.N, s.n_lambda, groups, \
                        s.adj_ptr, s.nodeoff, s.rev, s.q, s.qsun, (const float *)s.tau_s, (const float *)s.tau_a,      \
                        s.abs_scale_d, s.brho, s.bsrc, rhs, x, y, s.meas, monitor, s.dmax)
     if (s.dmax <= 16) SG_WIDE(16);
@@ -561,11 +560,11 @@ static void launch_wide(Scene &s, hipStream_t st, int grid, const float *rhs, co
 }
 
 void launch_spmm(Scene &s, hipStream_t st, int grid, const float *rhs, const float *x, float *y, int monitor) {
-    launch_wide<float, float, false>(s, st, grid, rhs, x, y, monitor);
+    launch_wide<float, float, float, false>(s, st, grid, rhs, x, y, monitor);
 }
 
-void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, double *r64) {
-    launch_wide<double, double, true>(s, st, grid, nullptr, x64, r64, 1);
+void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, float *r32) {
+    launch_wide<double, float, double, true>(s, st, grid, nullptr, x64, r32, 1);
 }
 
 void launch_bfirst(Scene &s, hipStream_t st, const float *rhs, float *x) {
@@ -574,8 +573,8 @@ void launch_bfirst(Scene &s, hipStream_t st, const float *rhs, float *x) {
                        s.meas);
 }
 
-void launch_lam_scale_to_f32(const double *a, const double *sc, int nl, float *b, long long n, hipStream_t st) {
-    hipLaunchKernelGGL(k_lam_scale_to_f32, dim3(grid_for(n)), dim3(256), 0, st, a, sc, nl, b, n);
+void launch_lam_scale_f32(float *b, const double *sc, int nl, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_lam_scale_f32, dim3(grid_for(n)), dim3(256), 0, st, b, sc, nl, n);
 }
 
 void launch_lam_axpy(double *x, const float *d, const double *sc, int nl, long long n, hipStream_t st) {

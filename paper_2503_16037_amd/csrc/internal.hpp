@@ -289,9 +289,11 @@ void launch_bfirst(Scene &s, hipStream_t st, const float *rhs, float *x);
 // one batched sweep y = rhs + K x for all wavelengths (rhs = NULL: the solar source);
 // monitor != 0: per-node measures of y - x to s.meas
 void launch_spmm(Scene &s, hipStream_t st, int grid, const float *rhs, const float *x, float *y, int monitor);
-// r64 = S + K x64 - x64 in FP64 for all wavelengths; per-node measures of r relative to x to s.meas
-void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, double *r64);
-void launch_lam_scale_to_f32(const double *a, const double *sc, int nl, float *b, long long n, hipStream_t st);
+// r = S + K x64 - x64 evaluated in FP64 for all wavelengths and stored in FP32 (the correction
+// solve takes it in FP32); per-node measures of r relative to x (from the FP64 values) to s.meas
+void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, float *r32);
+// b[e][lambda] *= sc[lambda] (FP32 values, FP64 scales)
+void launch_lam_scale_f32(float *b, const double *sc, int nl, long long n, hipStream_t st);
 void launch_lam_axpy(double *x, const float *d, const double *sc, int nl, long long n, hipStream_t st);
 void launch_f32_to_64(const float *a, double *b, long long n, hipStream_t st);
 void launch_lam_to_edge_major(const double *src, double *dst, int nl, long long E, hipStream_t st);
