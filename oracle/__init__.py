@@ -53,6 +53,9 @@ def lib():
             L.or_trace_many.restype = None
             L.or_trace_many.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, P, P, C.c_int, C.c_int, P, P,
                                         P]
+            L.or_los_nodes.restype = C.c_int
+            L.or_los_nodes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, C.c_double, C.c_int, C.c_double, P,
+                                       C.c_int64, P, P, P, C.c_int64, P]
             L.or_trace.restype = C.c_int
             L.or_trace.argtypes = [C.c_int, C.c_int, C.c_int, P, P, C.c_int, P, P, C.c_int]
             L.or_lattice.restype = None
@@ -86,10 +89,10 @@ def lib():
             L.or_tails.restype = None
             L.or_tails.argtypes = [C.c_int64, P, C.c_int64, P]
             L.or_coupling_nodes.restype = C.c_int64
-            L.or_coupling_nodes.argtypes = [C.c_int, C.c_int, C.c_int, P, P, C.c_int, P, P, P, P]
+            L.or_coupling_nodes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int64, P, P, C.c_int, P, P, P, P]
             L.or_coupling_graph.restype = C.c_int64
-            L.or_coupling_graph.argtypes = [C.c_int, C.c_int, C.c_int, P, P, C.c_int, P, C.c_int64, C.c_double,
-                                            P, P, C.c_int64]
+            L.or_coupling_graph.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int64, P, P, C.c_int, P, C.c_int64,
+                                            C.c_double, P, P, C.c_int64]
             _lib = L
         return _lib
 
@@ -138,6 +141,30 @@ def trace_many(nx, ny, nz, P, D, is_ray, cap, periodic=0):
     if (cnt < 0).any():
         raise ValueError("a segment leaves the grid")
     return vox, dt, cnt
+
+
+def los_nodes(nx, ny, nz, view_dir, voxel_m, mode="layer", step_m=0.0, periodic=0):
+    """Path points of the pixels' lines of sight (Sec. 2): node positions int64 [n][3],
+    los_ptr int64 [nx ny + 1] over the lines' elements, and per element its node los_node
+    int32 (-1: none) and its upper end los_t float64 along the line.  mode "layer": one
+    element per layer crossed; "step": one per step_m metres along the line."""
+    m = {"layer": 0, "step": 1}[mode]
+    D = np.ascontiguousarray(view_dir, np.int64)
+    npx = nx * ny
+    los_ptr = np.zeros(npx + 1, np.int64)
+    counts = np.zeros(2, np.int64)
+    cap = ecap = 0
+    while True:
+        pos = np.zeros((max(cap, 1), 3), np.int64)
+        los_node = np.zeros(max(ecap, 1), np.int32)
+        los_t = np.zeros(max(ecap, 1), np.float64)
+        rc = lib().or_los_nodes(nx, ny, nz, int(periodic), _p(D), float(voxel_m), m, float(step_m), _p(pos), cap,
+                                _p(los_ptr), _p(los_node), _p(los_t), ecap, _p(counts))
+        if rc < 0:
+            raise ValueError("los_nodes: bad arguments")
+        if rc == 0:
+            return pos[:counts[0]].copy(), los_ptr.copy(), los_node[:counts[1]].copy(), los_t[:counts[1]].copy()
+        cap, ecap = int(counts[0]), int(counts[1])
 
 
 def lattice(N: int) -> np.ndarray:
@@ -213,7 +240,8 @@ class _Scene(C.Structure):
                 ("sun_dir", C.c_void_p), ("view_dir", C.c_void_p), ("n_fib", C.c_int),
                 ("node_weight_mode", C.c_int), ("scatter_order", C.c_int), ("tol", C.c_double),
                 ("phase_kind", C.c_void_p), ("lut_n", C.c_int), ("lut", C.c_void_p), ("sigma_mode", C.c_int),
-                ("periodic", C.c_int)]
+                ("periodic", C.c_int), ("n_vol", C.c_int64), ("los_ptr", C.c_void_p), ("los_node", C.c_void_p),
+                ("los_t", C.c_void_p)]
 
 
 class _Out(C.Structure):
@@ -223,8 +251,10 @@ class _Out(C.Structure):
 
 
 def node_positions(scene) -> np.ndarray:
-    """int64 [N, 3]: the scene's volume positions then the surface node positions."""
-    pos = np.asarray(scene.vol_pos_fx, np.int64).reshape(-1, 3)
+    """int64 [N, 3]: the scene's volume positions (one per voxel, or the general nodes of a
+    scene that has node_pos_fx) then the surface node positions."""
+    general = getattr(scene, "node_pos_fx", None)
+    pos = np.asarray(scene.vol_pos_fx if general is None else general, np.int64).reshape(-1, 3)
     if scene.surface_nodes:
         iy, ix = np.meshgrid(np.arange(scene.ny), np.arange(scene.nx), indexing="ij")
         sp = np.zeros((scene.nx * scene.ny, 3), np.int64)
@@ -269,11 +299,16 @@ def run(scene, abs_scale: float = 1.0, scatter_order: int = 0, tol: float = 1e-1
     lut = getattr(scene, "phase_lut", None)
     kind = None if kind is None else arr(kind, np.int32)
     lut = None if lut is None else arr(lut, np.float64)
+    general = getattr(scene, "node_pos_fx", None)
+    n_vol = 0 if general is None else int(np.asarray(general).reshape(-1, 3).shape[0])
+    los_ptr = None if general is None else arr(scene.los_ptr, np.int64)
+    los_node = None if general is None else arr(scene.los_node, np.int32)
+    los_t = None if general is None else arr(scene.los_t, np.float64)
     sc = _Scene(scene.nx, scene.ny, scene.nz, float(scene.voxel_m), _p(mu_s), _p(mu_a), len(hg_g), _p(hg_g),
                 _p(pf), _p(pos), int(scene.surface_nodes), _p(adj_ptr), _p(adj_idx), _p(alb), _p(sun),
                 _p(view), int(scene.n_fib), int(scene.node_weight_mode), int(scatter_order), float(tol),
                 _p(kind), 0 if lut is None else int(lut.shape[-1]), _p(lut), int(getattr(scene, "sigma_mode", 0)),
-                int(getattr(scene, "periodic", 0)))
+                int(getattr(scene, "periodic", 0)), n_vol, _p(los_ptr), _p(los_node), _p(los_t))
     res = dict(tau=np.zeros(E), tau_sun=np.zeros(N), rho=np.zeros(N), row_ptr=np.zeros(E + 1, np.int64),
                col=np.zeros(nnz, np.int32), val=np.zeros(nnz), S=np.zeros(E), phi=np.zeros(E),
                radiance=np.zeros(scene.nx * scene.ny), stats=np.zeros(8))
@@ -298,21 +333,25 @@ def run(scene, abs_scale: float = 1.0, scatter_order: int = 0, tol: float = 1e-1
 # ------------------------------------------------------------------------------------------
 
 def _graph_inputs(scene):
-    pos = np.ascontiguousarray(scene.vol_pos_fx, np.int32)
+    general = getattr(scene, "node_pos_fx", None)
+    pos = np.ascontiguousarray(scene.vol_pos_fx if general is None else general, np.int32)
+    n_vol = 0 if general is None else int(pos.reshape(-1, 3).shape[0])
     mus = np.ascontiguousarray(scene.mu_s, np.float32)
     alb = np.ascontiguousarray(scene.surf_albedo, np.float32)
-    return pos, mus, alb
+    return pos, mus, alb, n_vol
 
 
 def coupling_nodes(scene):
-    """Node positions (fixed point, [N][3]), coupling coefficients mu [N] (surface:
-    albedo x the largest mu_s) and the centred, per-axis scaled coordinates q [N][3]."""
-    pos, mus, alb = _graph_inputs(scene)
-    N = scene.nx * scene.ny * scene.nz + (scene.nx * scene.ny if scene.surface_nodes else 0)
+    """Node positions (fixed point, [N][3]), coupling coefficients mu [N] (a volume node:
+    the mu_s of its voxel; surface: albedo x the largest mu_s) and the centred, per-axis
+    scaled coordinates q [N][3]."""
+    pos, mus, alb, n_vol = _graph_inputs(scene)
+    nv = n_vol if n_vol else scene.nx * scene.ny * scene.nz
+    N = nv + (scene.nx * scene.ny if scene.surface_nodes else 0)
     P = np.zeros((N, 3), np.int64)
     mu = np.zeros(N, np.float64)
     q = np.zeros((N, 3), np.float64)
-    lib().or_coupling_nodes(scene.nx, scene.ny, scene.nz, _p(pos), _p(mus), int(bool(scene.surface_nodes)),
+    lib().or_coupling_nodes(scene.nx, scene.ny, scene.nz, n_vol, _p(pos), _p(mus), int(bool(scene.surface_nodes)),
                             _p(alb), _p(P), _p(mu), _p(q))
     return P, mu, q
 
@@ -321,14 +360,16 @@ def coupling_graph(scene, n_pairs: int = 0, c_min: float = 0.0):
     """The scattering graph of the scene's nodes: the n_pairs strongest couplings
     (Eq. 4), or every coupling above c_min when n_pairs is 0.  Returns the symmetric
     adjacency (adj_ptr int64 [N+1], adj_idx int32 [2 * pairs]), rows ascending."""
-    pos, mus, alb = _graph_inputs(scene)
-    N = scene.nx * scene.ny * scene.nz + (scene.nx * scene.ny if scene.surface_nodes else 0)
+    pos, mus, alb, n_vol = _graph_inputs(scene)
+    nv = n_vol if n_vol else scene.nx * scene.ny * scene.nz
+    N = nv + (scene.nx * scene.ny if scene.surface_nodes else 0)
     adj_ptr = np.zeros(N + 1, np.int64)
     cap = 2 * n_pairs if n_pairs > 0 else 0
     while True:
         adj_idx = np.zeros(max(cap, 1), np.int32)
-        E = lib().or_coupling_graph(scene.nx, scene.ny, scene.nz, _p(pos), _p(mus), int(bool(scene.surface_nodes)),
-                                    _p(alb), int(n_pairs), float(c_min), _p(adj_ptr), _p(adj_idx), cap)
+        E = lib().or_coupling_graph(scene.nx, scene.ny, scene.nz, n_vol, _p(pos), _p(mus),
+                                    int(bool(scene.surface_nodes)), _p(alb), int(n_pairs), float(c_min), _p(adj_ptr),
+                                    _p(adj_idx), cap)
         if E >= 0:
             return adj_ptr, adj_idx[:E].copy()
         cap = int(adj_ptr[-1])

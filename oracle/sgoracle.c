@@ -238,6 +238,138 @@ void or_trace_many(int nx, int ny, int nz, int periodic, int64_t n, const int64_
     }
 }
 
+/* The voxel containing a volume node (floor of its fixed-point position; periodic axes
+   wrap); -1 outside the box or on its outer planes (z = 0 included: the ground). */
+static int64_t node_voxel(const int64_t p[3], int nx, int ny, int nz, int periodic) {
+    const int64_t n[3] = {nx, ny, nz};
+    int64_t v[3];
+    for (int k = 0; k < 3; ++k) {
+        int64_t c = p[k];
+        if (k < 2 && (periodic & (1 << k))) {
+            if (c < 0 || c >= n[k] * FXS) return -1;
+        } else if (c <= 0 || c >= n[k] * FXS) {
+            return -1;
+        }
+        v[k] = c / FXS;
+    }
+    return v[0] + (int64_t)nx * (v[1] + (int64_t)ny * v[2]);
+}
+
+/*
+ * Path points of the lines of sight (Sec. 2: the points of a line of sight are taken at
+ * constant distance intervals or at each layer of the medium; Sec. 3, step 1 of the
+ * algorithm).  Pixel p = i + nx j looks from its surface point P = ((i + 1/2), (j + 1/2),
+ * 0) voxels along the view direction D until the line leaves the grid; the exact walk
+ * splits it into voxel chords k of parameter length dt_k (t = 1 is one D), starting at
+ * t_k = dt_0 + ... + dt_(k-1) (summed in this order) and ending at t_exit.  The line is cut
+ * into elements [a, b]:
+ *   mode 0 (layers): one per layer of voxels it crosses, from the start of the layer's
+ *     first chord to the end of its last (D_z > 0: a layer's chords are consecutive);
+ *   mode 1 (constant step): [j h, min((j + 1) h, t_exit)] for j = 0, 1, ... while
+ *     j h < t_exit, h = step_m / (|D| voxel_m / 2^16) (the step in parameter units).
+ * Element [a, b] has a node at the rounded middle point: m = 0.5 (a + b), pos_c = P_c +
+ * floor(m D_c + 0.5) on each axis, wrapped into the period on periodic axes; a node outside
+ * the box or on its outer planes is not made (the element then carries -1).  Node ids follow
+ * the pixels, then the elements in order.  Outputs: pos [cap][3]; los_ptr [nx ny + 1]: pixel
+ * p's elements at los_ptr[p] ...; per element its node los_node and its end b in los_t
+ * [el_cap]; counts[0] = nodes, counts[1] = elements.  Returns 0, 1 when a capacity is too
+ * small (the counts are still written), or -1 for a bad argument.
+ */
+typedef struct {
+    int64_t *vox;
+    double *dt;
+    int64_t n, cap;
+} chord_buf;
+
+static void chord_visit(void *c, int64_t vox, double dt) {
+    chord_buf *b = (chord_buf *)c;
+    if (b->n < b->cap) {
+        b->vox[b->n] = vox;
+        b->dt[b->n] = dt;
+    }
+    b->n++;
+}
+
+int or_los_nodes(int nx, int ny, int nz, int periodic, const int64_t *view_dir, double voxel_m, int mode,
+                 double step_m, int64_t *pos, int64_t cap, int64_t *los_ptr, int32_t *los_node, double *los_t,
+                 int64_t el_cap, int64_t *counts) {
+    if (view_dir[2] <= 0 || (mode != 0 && mode != 1) || (mode == 1 && !(step_m > 0.0))) return -1;
+    const int64_t npx = (int64_t)nx * ny;
+    const int wcap = periodic ? MAX_WALK_STEPS : nx + ny + nz + 2;
+    int64_t *vox = (int64_t *)malloc(sizeof(int64_t) * wcap);
+    double *dt = (double *)malloc(sizeof(double) * wcap);
+    int64_t icap = wcap + 1; /* element arrays, grown for short steps */
+    double *ia = (double *)malloc(sizeof(double) * icap), *ib = (double *)malloc(sizeof(double) * icap);
+    const double plen = sqrt((double)(view_dir[0] * view_dir[0] + view_dir[1] * view_dir[1] + view_dir[2] * view_dir[2])) *
+                        (voxel_m / (double)FXS);
+    const double h = mode == 1 ? step_m / plen : 0.0;
+    int64_t nn = 0, ne = 0;
+    los_ptr[0] = 0;
+    for (int64_t p = 0; p < npx; ++p) {
+        const int64_t P[3] = {(p % nx) * FXS + FXS / 2, (p / nx) * FXS + FXS / 2, 0};
+        chord_buf cb = {vox, dt, 0, wcap};
+        dda_walk_p(nx, ny, nz, periodic, P, view_dir, 1, chord_visit, &cb);
+        const int64_t nk = cb.n;
+        int64_t ni = 0;
+        if (mode == 0) {
+            int64_t layer = -1;
+            double t = 0.0;
+            for (int64_t k = 0; k < nk; ++k) {
+                const int64_t z = vox[k] / npx;
+                if (z != layer) {
+                    layer = z;
+                    ia[ni] = t;
+                    ++ni;
+                }
+                t = t + dt[k];
+                ib[ni - 1] = t;
+            }
+        } else {
+            double t_exit = 0.0;
+            for (int64_t k = 0; k < nk; ++k) t_exit = t_exit + dt[k];
+            while ((double)ni * h < t_exit) {
+                if (ni == icap) {
+                    icap *= 2;
+                    ia = (double *)realloc(ia, sizeof(double) * icap);
+                    ib = (double *)realloc(ib, sizeof(double) * icap);
+                }
+                ia[ni] = (double)ni * h;
+                const double e = (double)(ni + 1) * h;
+                ib[ni] = e < t_exit ? e : t_exit;
+                ++ni;
+            }
+        }
+        for (int64_t j = 0; j < ni; ++j) {
+            const double m = 0.5 * (ia[j] + ib[j]);
+            int64_t q[3];
+            for (int c = 0; c < 3; ++c) {
+                q[c] = P[c] + (int64_t)floor(m * (double)view_dir[c] + 0.5);
+                if (c < 2 && (periodic & (1 << c))) {
+                    const int64_t W = (c ? ny : nx) * (int64_t)FXS;
+                    q[c] = ((q[c] % W) + W) % W;
+                }
+            }
+            int32_t id = -1;
+            if (node_voxel(q, nx, ny, nz, periodic) >= 0) {
+                id = (int32_t)nn;
+                if (nn < cap)
+                    for (int c = 0; c < 3; ++c) pos[3 * nn + c] = q[c];
+                ++nn;
+            }
+            if (ne + j < el_cap) {
+                los_node[ne + j] = id;
+                los_t[ne + j] = ib[j];
+            }
+        }
+        ne += ni;
+        los_ptr[p + 1] = ne;
+    }
+    free(vox); free(dt); free(ia); free(ib);
+    counts[0] = nn;
+    counts[1] = ne;
+    return nn > cap || ne > el_cap ? 1 : 0;
+}
+
 typedef struct {
     const double *mu_e;
     double tau; /* accumulated sum of mu_e * dt (dt in parameter units) */
@@ -398,6 +530,16 @@ typedef struct {
     const double *lut;     /* [n_phase][lut_n] tables in mu = cos(theta) on [-1, 1] */
     int sigma_mode;        /* 0: Voronoi ownership of the lattice; 1: nearest-point colouring + flood fill */
     int periodic;          /* bit 0: periodic in x, bit 1: periodic in y (plane-parallel slabs) */
+    /* Volume nodes.  n_vol = 0: one per voxel, node id = voxel id (pos [nvox] first).
+       n_vol > 0: n_vol nodes anywhere in the box (pos [n_vol] first; Sec. 2: the path points
+       of the lines of sight), each with the medium of the voxel that contains it; pixel p's
+       line of sight is then cut into elements e = los_ptr[p] ... los_ptr[p+1]-1, consecutive
+       from its surface point up to the parameters los_t[e] (t = 1 is one view_dir), element e
+       scattering toward the sensor the radiance of volume node los_node[e] (-1: none). */
+    int64_t n_vol;
+    const int64_t *los_ptr; /* [nx*ny + 1] */
+    const int32_t *los_node;
+    const double *los_t;
 } or_scene;
 
 /*
@@ -806,7 +948,8 @@ void or_node_q(int is_surface, const double *u, int d, const double *s, int N, c
 int or_run(const or_scene *sc, or_out *out) {
     const int nx = sc->nx, ny = sc->ny, nz = sc->nz;
     const int64_t nvox = (int64_t)nx * ny * nz;
-    const int64_t N = nvox + (sc->surface ? (int64_t)nx * ny : 0);
+    const int64_t nvol = sc->n_vol > 0 ? sc->n_vol : nvox;
+    const int64_t N = nvol + (sc->surface ? (int64_t)nx * ny : 0);
     const int64_t E = sc->adj_ptr[N];
     const double dx = sc->voxel_m;
     const int NF = sc->n_fib;
@@ -831,6 +974,25 @@ int or_run(const or_scene *sc, or_out *out) {
             const int64_t *d = r ? sc->view_dir : sc->sun_dir;
             const int64_t ax = d[0] < 0 ? -d[0] : d[0], ay = d[1] < 0 ? -d[1] : d[1];
             if (d[2] <= 0 || (int64_t)nz * (ax + ay + d[2]) + 4 * d[2] > (int64_t)MAX_WALK_STEPS * d[2]) return 9;
+        }
+    }
+
+    /* the voxel of every volume node; general nodes come with their lines of sight */
+    int64_t *nv = (int64_t *)malloc(sizeof(int64_t) * (nvol > 0 ? nvol : 1));
+    for (int64_t l = 0; l < nvol; ++l) {
+        nv[l] = sc->n_vol > 0 ? node_voxel(sc->pos + 3 * l, nx, ny, nz, sc->periodic) : l;
+        if (nv[l] < 0) { free(nv); return 10; }
+    }
+    if (sc->n_vol > 0) {
+        if (!sc->los_ptr || !sc->los_node || !sc->los_t || sc->los_ptr[0] != 0) { free(nv); return 11; }
+        for (int64_t p = 0; p < (int64_t)nx * ny; ++p) {
+            if (sc->los_ptr[p + 1] < sc->los_ptr[p]) { free(nv); return 11; }
+            double prev = 0.0;
+            for (int64_t e = sc->los_ptr[p]; e < sc->los_ptr[p + 1]; ++e) {
+                if (!(sc->los_t[e] > prev) || !isfinite(sc->los_t[e])) { free(nv); return 11; }
+                if (sc->los_node[e] < -1 || sc->los_node[e] >= nvol) { free(nv); return 11; }
+                prev = sc->los_t[e];
+            }
         }
     }
 
@@ -860,7 +1022,7 @@ int or_run(const or_scene *sc, or_out *out) {
             out->tau[e] = acc.tau * param_length_m(D, dx);
         }
     }
-    if (bad) { free(mu_e); free(omega); return -2; }
+    if (bad) { free(mu_e); free(omega); free(nv); return -2; }
 
     /* O2: node -> sun optical depth to the grid exit */
 #pragma omp parallel for schedule(dynamic, 256)
@@ -870,11 +1032,12 @@ int or_run(const or_scene *sc, or_out *out) {
 
     /* O6: node weights (bounded scattering probability over one voxel edge; mode 1: mu_s * edge) */
     for (int64_t l = 0; l < N; ++l) {
-        if (l < nvox) {
-            if (sc->node_weight_mode == 1) out->rho[l] = sc->mu_s[l] * dx;
-            else out->rho[l] = omega[l] * (-expm1(-mu_e[l] * dx));
+        if (l < nvol) {
+            const int64_t v = nv[l];
+            if (sc->node_weight_mode == 1) out->rho[l] = sc->mu_s[v] * dx;
+            else out->rho[l] = omega[v] * (-expm1(-mu_e[v] * dx));
         } else {
-            out->rho[l] = sc->albedo[l - nvox];
+            out->rho[l] = sc->albedo[l - nvol];
         }
     }
 
@@ -900,7 +1063,7 @@ int or_run(const or_scene *sc, or_out *out) {
         hnb = (int32_t *)malloc(sizeof(int32_t) * NF * MAXNB);
         hnnb = (int32_t *)malloc(sizeof(int32_t) * NF);
         if (or_hull_adjacency(NF, lat, MAXNB, hnb, hnnb) < 0) {
-            free(hnb); free(hnnb); free(lat); free(tab);
+            free(hnb); free(hnnb); free(lat); free(tab); free(mu_e); free(omega); free(nv);
             return 7;
         }
     }
@@ -936,7 +1099,7 @@ int or_run(const or_scene *sc, or_out *out) {
             int64_t off = sc->adj_ptr[l];
             int d = (int)(sc->adj_ptr[l + 1] - off);
             if (d == 0) continue;
-            int is_surf = l >= nvox;
+            int is_surf = l >= nvol;
             for (int m = 0; m < d; ++m) {
                 int64_t e = off + m, j = sc->adj_idx[e];
                 int64_t D[3];
@@ -948,7 +1111,7 @@ int or_run(const or_scene *sc, or_out *out) {
                 for (int i = 0; i < NF; ++i) {
                     double acc = 0.0;
                     for (int k = 0; k < sc->n_phase; ++k) {
-                        double f = sc->phase_frac ? sc->phase_frac[(size_t)k * nvox + l] : 1.0;
+                        double f = sc->phase_frac ? sc->phase_frac[(size_t)k * nvox + nv[l]] : 1.0;
                         acc += f * tab[(size_t)k * NF + i];
                     }
                     w[i] = acc;
@@ -991,15 +1154,62 @@ int or_run(const or_scene *sc, or_out *out) {
 
     const double t_solve = wall_s();
 
-    /* O9: gather (Eq. 11) along the line of sight of every pixel */
+    /* O9: gather (Eq. 11).  First every node's radiance toward the sensor: for a volume node
+       the sun's beam and the in-edges' fluxes weighted by the node's phase function toward
+       the sensor, for a surface node the Lambertian sum mu0 T_sun + sum T_a phi_a. */
     double vu[3];
     unit_of(sc->view_dir, vu);
     const double Lview = param_length_m(sc->view_dir, dx);
+    double *Jn = (double *)malloc(sizeof(double) * (N > 0 ? N : 1));
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t l = 0; l < N; ++l) {
+        if (l < nvol) {
+            const int64_t v = nv[l];
+            double th_sun = 0.0;
+            for (int c = 0; c < sc->n_phase; ++c) {
+                double f = sc->phase_frac ? sc->phase_frac[(size_t)c * nvox + v] : 1.0;
+                th_sun += f * phase_of(sc, c, sun_in[0] * vu[0] + sun_in[1] * vu[1] + sun_in[2] * vu[2]);
+            }
+            double J = th_sun * exp(-out->tau_sun[l]);
+            if (sc->scatter_order != 1) {
+                for (int64_t e = sc->adj_ptr[l]; e < sc->adj_ptr[l + 1]; ++e) {
+                    int64_t j = sc->adj_idx[e];
+                    int64_t D[3];
+                    node_disp(sc->pos, j, l, nx, ny, sc->periodic, D);
+                    double sa[3];
+                    unit_of(D, sa); /* propagation direction of in-edge (j -> l) */
+                    double mu = sa[0] * vu[0] + sa[1] * vu[1] + sa[2] * vu[2];
+                    double th = 0.0;
+                    for (int c = 0; c < sc->n_phase; ++c) {
+                        double f = sc->phase_frac ? sc->phase_frac[(size_t)c * nvox + v] : 1.0;
+                        th += f * phase_of(sc, c, mu);
+                    }
+                    int64_t a = edge_rev(sc, e, l);
+                    J += th * exp(-out->tau[e]) * out->phi[a];
+                }
+            }
+            Jn[l] = J;
+        } else {
+            double Js = mu0 * exp(-out->tau_sun[l]);
+            if (sc->scatter_order != 1) {
+                for (int64_t e = sc->adj_ptr[l]; e < sc->adj_ptr[l + 1]; ++e) {
+                    int64_t a = edge_rev(sc, e, l);
+                    Js += exp(-out->tau[e]) * out->phi[a];
+                }
+            }
+            Jn[l] = Js;
+        }
+    }
+    /* then along every pixel's line of sight: each voxel chord scatters toward the sensor
+       the radiance of its node (the voxel's own node, or the line-of-sight node it is
+       assigned to), weighted by the chord's scattering w (1 - exp(-mu_e s)) and the
+       transmittance above it; the ground adds its Lambertian term */
 #pragma omp parallel
     {
         int cap = sc->periodic ? MAX_WALK_STEPS : 4 * (nx + ny + nz) + 8;
         int64_t *vox = (int64_t *)malloc(sizeof(int64_t) * cap);
         double *dtv = (double *)malloc(sizeof(double) * cap);
+        double *tcum = (double *)malloc(sizeof(double) * (cap + 1));
 #pragma omp for schedule(dynamic, 16)
         for (int64_t p = 0; p < (int64_t)nx * ny; ++p) {
             int64_t ix = p % nx, iy = p / nx;
@@ -1009,49 +1219,52 @@ int or_run(const or_scene *sc, or_out *out) {
             int nseg = tb.n;
             double Iv = 0.0;
             double tau_after = 0.0; /* optical depth between the segment's far end and the sensor */
-            for (int k = nseg - 1; k >= 0; --k) {
-                int64_t v = vox[k];
-                double sk = dtv[k] * Lview;
-                double Tent = exp(-tau_after);
-                double wch = omega[v] * (-expm1(-mu_e[v] * sk));
-                /* the volume node of voxel v has id v */
-                double th_sun = 0.0;
-                for (int c = 0; c < sc->n_phase; ++c) {
-                    double f = sc->phase_frac ? sc->phase_frac[(size_t)c * nvox + v] : 1.0;
-                    th_sun += f * phase_of(sc, c, sun_in[0] * vu[0] + sun_in[1] * vu[1] + sun_in[2] * vu[2]);
+            if (sc->n_vol == 0) {
+                for (int k = nseg - 1; k >= 0; --k) {
+                    int64_t v = vox[k];
+                    double sk = dtv[k] * Lview;
+                    double Tent = exp(-tau_after);
+                    double wch = omega[v] * (-expm1(-mu_e[v] * sk));
+                    Iv += Tent * wch * Jn[v]; /* the voxel's own node */
+                    tau_after += mu_e[v] * sk;
                 }
-                double J = th_sun * exp(-out->tau_sun[v]);
-                if (sc->scatter_order != 1) {
-                    for (int64_t e = sc->adj_ptr[v]; e < sc->adj_ptr[v + 1]; ++e) {
-                        int64_t j = sc->adj_idx[e];
-                        int64_t D[3];
-                        node_disp(sc->pos, j, v, nx, ny, sc->periodic, D);
-                        double sa[3];
-                        unit_of(D, sa); /* propagation direction of in-edge (j -> v) */
-                        double mu = sa[0] * vu[0] + sa[1] * vu[1] + sa[2] * vu[2];
-                        double th = 0.0;
-                        for (int c = 0; c < sc->n_phase; ++c) {
-                            double f = sc->phase_frac ? sc->phase_frac[(size_t)c * nvox + v] : 1.0;
-                            th += f * phase_of(sc, c, mu);
+            } else {
+                /* the chords cut at the elements' ends: each piece scatters the radiance of
+                   its element's node; from the top down, as above.  Chord k spans [tcum[k],
+                   tcum[k+1]] of the line parameter (prefix sums of the walk's lengths). */
+                const int64_t e0 = sc->los_ptr[p], e1 = sc->los_ptr[p + 1];
+                tcum[0] = 0.0;
+                for (int k = 0; k < nseg; ++k) tcum[k + 1] = tcum[k] + dtv[k];
+                int64_t e = e1 - 1; /* the element holding the point just below `top` */
+                for (int k = nseg - 1; k >= 0; --k) {
+                    const int64_t v = vox[k];
+                    double top = tcum[k + 1];
+                    while (top > tcum[k]) {
+                        /* step e down to the element with start < top <= end (or, above the
+                           last end, keep e1 - 1) */
+                        while (e >= e0 && (e == e0 ? 0.0 : sc->los_t[e - 1]) >= top) --e;
+                        double bot = tcum[k];
+                        int64_t node = -1;
+                        if (e >= e0) {
+                            if (top <= sc->los_t[e]) {
+                                const double start = e == e0 ? 0.0 : sc->los_t[e - 1];
+                                if (start > bot) bot = start;
+                                node = sc->los_node[e];
+                            } else if (sc->los_t[e] > bot) {
+                                bot = sc->los_t[e]; /* the part above the last end: no node */
+                            }
                         }
-                        int64_t a = edge_rev(sc, e, v);
-                        J += th * exp(-out->tau[e]) * out->phi[a];
+                        const double sk = (top - bot) * Lview;
+                        const double wch = omega[v] * (-expm1(-mu_e[v] * sk));
+                        if (node >= 0) Iv += exp(-tau_after) * wch * Jn[node];
+                        tau_after += mu_e[v] * sk;
+                        top = bot;
                     }
                 }
-                Iv += Tent * wch * J;
-                tau_after += mu_e[v] * sk;
             }
             double Tsurf = exp(-tau_after);
             if (sc->surface) {
-                int64_t s = nvox + p;
-                double Js = mu0 * exp(-out->tau_sun[s]);
-                if (sc->scatter_order != 1) {
-                    for (int64_t e = sc->adj_ptr[s]; e < sc->adj_ptr[s + 1]; ++e) {
-                        int64_t a = edge_rev(sc, e, s);
-                        Js += exp(-out->tau[e]) * out->phi[a];
-                    }
-                }
-                Iv += Tsurf * (sc->albedo[p] / M_PI) * Js;
+                Iv += Tsurf * (sc->albedo[p] / M_PI) * Jn[nvol + p];
             } else {
                 Iv += Tsurf * (sc->albedo[p] / M_PI) * mu0 * exp(-optical_depth(nx, ny, nz, sc->periodic, mu_e, dx, P, sc->sun_dir, 1));
             }
@@ -1059,7 +1272,10 @@ int or_run(const or_scene *sc, or_out *out) {
         }
         free(vox);
         free(dtv);
+        free(tcum);
     }
+    free(Jn);
+    free(nv);
     free(lat); free(tab); free(mu_e); free(omega); free(hnb); free(hnnb);
     const double t_end = wall_s();
     out->stats[4] = t_march - t_start;   /* node properties, edge and sun marches, node weights */
@@ -1163,17 +1379,21 @@ static int cmp_i32(const void *a, const void *b) {
 
 /* Node positions (fixed point), coupling coefficients and the scaled coordinates
    q [N][3]; returns N. */
-int64_t or_coupling_nodes(int nx, int ny, int nz, const int32_t *vol_pos_fx, const float *mu_s, int surface,
-                          const float *albedo, int64_t *pos /* [N][3] */, double *mu /* [N] */, double *q) {
-    const int64_t nvox = (int64_t)nx * ny * nz, nsurf = surface ? (int64_t)nx * ny : 0, N = nvox + nsurf;
+int64_t or_coupling_nodes(int nx, int ny, int nz, int64_t n_vol, const int32_t *vol_pos_fx, const float *mu_s,
+                          int surface, const float *albedo, int64_t *pos /* [N][3] */, double *mu /* [N] */,
+                          double *q) {
+    const int64_t nvox = (int64_t)nx * ny * nz, nsurf = surface ? (int64_t)nx * ny : 0;
+    const int64_t nv = n_vol > 0 ? n_vol : nvox, N = nv + nsurf;  /* general nodes: n_vol of them */
     double mmax = 0.0;
     for (int64_t v = 0; v < nvox; ++v) mmax = fmax(mmax, (double)mu_s[v]);
     for (int64_t l = 0; l < N; ++l) {
-        if (l < nvox) {
+        if (l < nv) {
             for (int a = 0; a < 3; ++a) pos[3 * l + a] = vol_pos_fx[3 * l + a];
-            mu[l] = (double)mu_s[l];
+            /* the coupling coefficient of the node's voxel (node id = voxel id for one per voxel) */
+            const int64_t v = n_vol > 0 ? node_voxel(pos + 3 * l, nx, ny, nz, 0) : l;
+            mu[l] = v >= 0 ? (double)mu_s[v] : 0.0;
         } else {
-            const int64_t c = l - nvox, i = c % nx, j = c / nx;
+            const int64_t c = l - nv, i = c % nx, j = c / nx;
             pos[3 * l] = i * FXS + FXS / 2;
             pos[3 * l + 1] = j * FXS + FXS / 2;
             pos[3 * l + 2] = 0;
@@ -1203,13 +1423,13 @@ static double coupling_key(const double *q, const double *mu, int64_t i, int64_t
 /* The selected pairs as a symmetric CSR adjacency over the N nodes; returns the
    number of directed edges (twice the pairs), or -1 when it exceeds cap (then
    adj_idx is not written). */
-int64_t or_coupling_graph(int nx, int ny, int nz, const int32_t *vol_pos_fx, const float *mu_s, int surface,
-                          const float *albedo, int64_t n_pairs, double c_min, int64_t *adj_ptr /* [N+1] */,
-                          int32_t *adj_idx, int64_t cap) {
-    const int64_t nvox = (int64_t)nx * ny * nz, N = nvox + (surface ? (int64_t)nx * ny : 0);
+int64_t or_coupling_graph(int nx, int ny, int nz, int64_t n_vol, const int32_t *vol_pos_fx, const float *mu_s,
+                          int surface, const float *albedo, int64_t n_pairs, double c_min,
+                          int64_t *adj_ptr /* [N+1] */, int32_t *adj_idx, int64_t cap) {
+    const int64_t nvox = n_vol > 0 ? n_vol : (int64_t)nx * ny * nz, N = nvox + (surface ? (int64_t)nx * ny : 0);
     int64_t *pos = malloc(sizeof(int64_t) * 3 * N);
     double *mu = malloc(sizeof(double) * N), *q = malloc(sizeof(double) * 3 * N);
-    or_coupling_nodes(nx, ny, nz, vol_pos_fx, mu_s, surface, albedo, pos, mu, q);
+    or_coupling_nodes(nx, ny, nz, n_vol, vol_pos_fx, mu_s, surface, albedo, pos, mu, q);
     or_pair *sel = NULL;
     int64_t ns = 0, scap = 0;
     if (n_pairs > 0) {

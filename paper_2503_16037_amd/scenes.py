@@ -63,6 +63,11 @@ class Scene:
     phase_lut: Optional[np.ndarray] = None   # float64 [n_phase, n] tables in cos(theta) on [-1, 1]
     sigma_mode: int = 0         # 0 = Voronoi ownership of the lattice, 1 = nearest-point colouring + flood fill
     periodic: int = 0           # bit 0: x, bit 1: y repeat with the grid's period (plane-parallel slabs)
+    # general volume nodes (path points of the lines of sight) instead of one per voxel:
+    node_pos_fx: Optional[np.ndarray] = None  # int32 [n_vol, 3], anywhere inside the box
+    los_ptr: Optional[np.ndarray] = None      # int64 [nx*ny + 1]: pixel p's line-of-sight elements at los_ptr[p] ...
+    los_node: Optional[np.ndarray] = None     # int32 [elements]: each element's node (-1: none)
+    los_t: Optional[np.ndarray] = None        # float64 [elements]: each element's upper end along the line (t = 1: one view_dir)
 
     # ---- derived sizes (no method arithmetic) ----
     @property
@@ -70,8 +75,13 @@ class Scene:
         return self.nx * self.ny * self.nz
 
     @property
+    def n_vol(self) -> int:
+        """Volume nodes: one per voxel, or the general node set."""
+        return self.nvox if self.node_pos_fx is None else int(self.node_pos_fx.shape[0])
+
+    @property
     def n_nodes(self) -> int:
-        return self.nvox + (self.nx * self.ny if self.surface_nodes else 0)
+        return self.n_vol + (self.nx * self.ny if self.surface_nodes else 0)
 
     @property
     def n_edges(self) -> int:
@@ -97,14 +107,15 @@ class Scene:
         arrs = [self.mu_s, self.mu_a, self.hg_g, self.vol_pos_fx, self.adj_ptr, self.adj_idx, self.surf_albedo]
         if self.phase_frac is not None:
             arrs.append(self.phase_frac)
-        for a in (self.abs_scale, self.phase_kind, self.phase_lut):
+        for a in (self.abs_scale, self.phase_kind, self.phase_lut, self.node_pos_fx, self.los_ptr, self.los_node,
+                  self.los_t):
             if a is not None:
                 arrs.append(a)
         return int(sum(a.nbytes for a in arrs))
 
     def all_positions(self) -> np.ndarray:
         """int64 [N, 3] positions of every node (volume then surface)."""
-        pos = self.vol_pos_fx.astype(np.int64)
+        pos = (self.vol_pos_fx if self.node_pos_fx is None else self.node_pos_fx).astype(np.int64)
         if self.surface_nodes:
             pos = np.concatenate([pos, surface_positions(self.nx, self.ny)], axis=0)
         return pos
@@ -116,7 +127,8 @@ class Scene:
             h.update(np.ascontiguousarray(a).tobytes())
         if self.phase_frac is not None:
             h.update(np.ascontiguousarray(self.phase_frac).tobytes())
-        for a in (self.abs_scale, self.phase_kind, self.phase_lut):
+        for a in (self.abs_scale, self.phase_kind, self.phase_lut, self.node_pos_fx, self.los_ptr, self.los_node,
+                  self.los_t):
             if a is not None:
                 h.update(np.ascontiguousarray(a).tobytes())
         h.update(repr((self.nx, self.ny, self.nz, self.voxel_m, self.surface_nodes, self.n_fib,
@@ -304,6 +316,41 @@ def periodic_radius_graph(vol_pos_fx: np.ndarray, nx: int, ny: int, nz: int, rad
     t = np.concatenate(tails) if tails else np.zeros(0, np.int64)
     h = np.concatenate(heads) if heads else np.zeros(0, np.int64)
     return adjacency_from_pairs(n_nodes, t, h)
+
+
+def general_radius_graph(node_pos_fx: np.ndarray, nx: int, ny: int, radius_vox: float, surface: bool = True):
+    """Symmetric adjacency of a general node set (positions int [n, 3], then one surface
+    node per column when surface): every pair within radius_vox voxel edges, compared exactly
+    in integers, |P_a - P_b|^2 <= floor((radius_vox * FX)^2); no surface-surface pairs."""
+    from scipy.spatial import cKDTree
+    pos = np.asarray(node_pos_fx, np.int64).reshape(-1, 3)
+    n_vol = pos.shape[0]
+    if surface:
+        pos = np.concatenate([pos, surface_positions(nx, ny)], axis=0)
+    r2 = int(math.floor((radius_vox * FX) ** 2))
+    tree = cKDTree(pos.astype(np.float64))
+    pairs = tree.query_pairs(math.sqrt(r2) + 2.0, output_type="ndarray").astype(np.int64)
+    if len(pairs):
+        d = pos[pairs[:, 0]] - pos[pairs[:, 1]]
+        keep = ((d * d).sum(axis=1) <= r2) & ~((pairs[:, 0] >= n_vol) & (pairs[:, 1] >= n_vol))
+        pairs = pairs[keep]
+    return adjacency_from_pairs(pos.shape[0], pairs[:, 0], pairs[:, 1])
+
+
+def with_los_nodes(sc: "Scene", node_pos_fx, los_ptr, los_node, los_t, radius_vox=None, name=None) -> "Scene":
+    """The scene with general volume nodes on the pixels' lines of sight (positions, the
+    per-pixel elements with their nodes and ends) and, with radius_vox, the radius graph over
+    them (else an empty graph, to be replaced by the caller's)."""
+    pos = np.ascontiguousarray(np.asarray(node_pos_fx).reshape(-1, 3), dtype=np.int32)
+    n = pos.shape[0] + (sc.nx * sc.ny if sc.surface_nodes else 0)
+    if radius_vox is not None:
+        adj_ptr, adj_idx = general_radius_graph(pos, sc.nx, sc.ny, radius_vox, surface=bool(sc.surface_nodes))
+    else:
+        adj_ptr, adj_idx = np.zeros(n + 1, np.int64), np.zeros(0, np.int32)
+    return dataclasses.replace(sc, name=name or sc.name + "-los", node_pos_fx=pos,
+                               los_ptr=np.ascontiguousarray(los_ptr, dtype=np.int64),
+                               los_node=np.ascontiguousarray(los_node, dtype=np.int32),
+                               los_t=np.ascontiguousarray(los_t, dtype=np.float64), adj_ptr=adj_ptr, adj_idx=adj_idx)
 
 
 def adjacency_from_pairs(n_nodes: int, a: np.ndarray, b: np.ndarray):
