@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define SG_ABI_VERSION 6u
+#define SG_ABI_VERSION 7u
 
 typedef int32_t sg_status;
 enum {
@@ -148,6 +148,22 @@ typedef struct sg_scene_desc {
                                   period apart).  The sun and view rays must reach the top
                                   within 65536 voxels: nz (|d_x| + |d_y| + d_z) + 4 d_z <=
                                   65536 d_z on both directions.  0: bounded grid */
+    /* General volume nodes (Sec. 2: the nodes of the scattering graph are path points of the
+       lines of sight, e.g. those of sg_los_nodes).  n_nodes = 0: one node per voxel at
+       vol_pos_fx, node id = voxel id.  n_nodes > 0: n_nodes volume nodes at node_pos_fx
+       (vol_pos_fx is not read), each with the medium (mu_s, mu_a, phase fractions) of the voxel
+       that contains it, strictly inside the box (0 <= coordinate < period on periodic axes, the
+       ground z = 0 excluded); surface nodes follow with ids n_nodes + column.  The radiance of
+       pixel p then comes from its line of sight's elements e = los_ptr[p] .. los_ptr[p+1]-1,
+       consecutive from the pixel's surface point up to the line parameters los_t[e] (t = 1 is
+       one view_dir; strictly increasing, positive): element e scatters toward the sensor the
+       radiance of volume node los_node[e] (-1: none) with the exact chord weights of the voxels
+       it crosses (Eq. 11); the part of a line above its last element scatters nothing. */
+    int32_t n_nodes;
+    const int32_t *node_pos_fx; /* [n_nodes][3] */
+    const int64_t *los_ptr;     /* [nx*ny + 1], los_ptr[0] = 0 */
+    const int32_t *los_node;    /* [los_ptr[nx*ny]] */
+    const double *los_t;        /* [los_ptr[nx*ny]] */
 } sg_scene_desc;
 enum { SG_SIGMA_VORONOI = 0, SG_SIGMA_COLOUR = 1 };
 enum { SG_PERIODIC_X = 1, SG_PERIODIC_Y = 2 };
@@ -321,14 +337,53 @@ sg_status sg_trace_noalloc(sg_scene *scene, int32_t kind, const int64_t *ids, in
 uint64_t sg_trace_noalloc_capacity(void);
 
 /* ------------------------------------------------------------------------------------ */
+/* Scattering nodes on the lines of sight (Sec. 2; Sec. 3, step 1 of the algorithm)      */
+/* ------------------------------------------------------------------------------------ */
+
+typedef struct sg_los_desc {
+    uint32_t abi_version;   /* SG_ABI_VERSION */
+    int32_t nx, ny, nz;     /* grid, 1..1024 each */
+    double voxel_m;         /* voxel edge in metres, > 0 */
+    int32_t view_dir[3];    /* toward the sensor (z > 0), |components| <= 2^22 */
+    int32_t periodic;       /* as in sg_scene_desc */
+    int32_t mode;           /* SG_LOS_LAYER or SG_LOS_STEP */
+    double step_m;          /* SG_LOS_STEP: the distance between nodes along a line, metres (> 0) */
+} sg_los_desc;
+enum { SG_LOS_LAYER = 0, SG_LOS_STEP = 1 };
+
+/*
+ * Path points of the pixels' lines of sight (Sec. 2: a line of sight's points are taken at
+ * each layer of the medium or at constant distance intervals).  Pixel p = i + nx j looks from
+ * its surface point ((i + 1/2), (j + 1/2), 0) voxels along view_dir until the line leaves the
+ * grid; the exact voxel walk splits it into chords of parameter length dt_k (t = 1 is one
+ * view_dir), starting at t_k = dt_0 + ... + dt_(k-1) (summed in this order).  The line is cut
+ * into elements [a, b]: SG_LOS_LAYER, one per layer of voxels it crosses (from the start of
+ * the layer's first chord to the end of its last); SG_LOS_STEP, [j h, min((j + 1) h, t_exit)]
+ * for j = 0, 1, ... while j h < t_exit, with h = step_m / (|view_dir| voxel_m / 65536).  Each
+ * element gets a node at the rounded middle point: m = 0.5 (a + b), coordinate c = surface
+ * point_c + floor(m view_dir_c + 0.5) (FP64, that operation order), wrapped into the period
+ * on periodic axes; a node outside the box or on its outer planes is not made (the element
+ * then carries -1).  Node ids follow the pixels, then the elements in order.
+ * Outputs (host, caller-owned): node_pos_fx [n_nodes][3], los_ptr [nx*ny + 1], and per
+ * element los_node and los_t (its end b): the fields of the same names in sg_scene_desc.
+ * When a capacity is too small (or a buffer NULL) only the counts and los_ptr (if given) are
+ * written.  Errors: SG_E_ABI, SG_E_INVALID, SG_E_NOMEM, SG_E_DEVICE.
+ */
+sg_status sg_los_nodes(sg_ctx *ctx, const sg_los_desc *desc, void *hip_stream, int32_t *node_pos_fx,
+                       int64_t node_cap, int64_t *n_nodes, int64_t *los_ptr, int32_t *los_node, double *los_t,
+                       int64_t el_cap, int64_t *n_elements);
+
+/* ------------------------------------------------------------------------------------ */
 /* The scattering graph itself (Sec. 2, Eq. 4; Sec. 3)                                   */
 /* ------------------------------------------------------------------------------------ */
 
 /*
- * Nodes as in sg_scene_desc: one per voxel (id = voxel index, position vol_pos_fx)
- * and, with surface_nodes, one per column at (i + 1/2, j + 1/2, 0) voxels (id
- * nvox + i + nx j).  A node's coupling coefficient is its voxel's mu_s; a surface
- * node's is surf_albedo times the largest mu_s of the medium (Sec. 3).
+ * Nodes as in sg_scene_desc: one per voxel (id = voxel index, position vol_pos_fx),
+ * or the n_nodes general nodes at node_pos_fx, and, with surface_nodes, one per column
+ * at (i + 1/2, j + 1/2, 0) voxels (ids after the volume nodes).  A node's coupling
+ * coefficient is its voxel's mu_s; a surface node's is surf_albedo times the largest mu_s
+ * of the medium (Sec. 3).  General node sets have no voxel boxes to prune with: every pair
+ * is ranked (the lines of sight of a scene hold few nodes next to a voxel grid).
  */
 typedef struct sg_graph_desc {
     uint32_t abi_version;       /* SG_ABI_VERSION */
@@ -339,6 +394,9 @@ typedef struct sg_graph_desc {
     const float *surf_albedo;   /* [ny][nx] in [0, 1] (read when surface_nodes) */
     int64_t n_pairs;            /* > 0: keep the n_pairs strongest couplings */
     double c_min;               /* n_pairs == 0: keep every coupling above c_min (>= 0) */
+    int32_t n_nodes;            /* > 0: general volume nodes at node_pos_fx (as in sg_scene_desc;
+                                   a node couples with its voxel's mu_s), 0: one per voxel */
+    const int32_t *node_pos_fx; /* [n_nodes][3] */
 } sg_graph_desc;
 
 /*

@@ -1389,8 +1389,10 @@ int64_t or_coupling_nodes(int nx, int ny, int nz, int64_t n_vol, const int32_t *
     for (int64_t l = 0; l < N; ++l) {
         if (l < nv) {
             for (int a = 0; a < 3; ++a) pos[3 * l + a] = vol_pos_fx[3 * l + a];
-            /* the coupling coefficient of the node's voxel (node id = voxel id for one per voxel) */
-            const int64_t v = n_vol > 0 ? node_voxel(pos + 3 * l, nx, ny, nz, 0) : l;
+            /* the coupling coefficient of the node's voxel (node id = voxel id for one per voxel);
+               a general node on the x = 0 or y = 0 plane (a periodic wrap puts it there) is in
+               the first column, as for the scene's medium */
+            const int64_t v = n_vol > 0 ? node_voxel(pos + 3 * l, nx, ny, nz, 3) : l;
             mu[l] = v >= 0 ? (double)mu_s[v] : 0.0;
         } else {
             const int64_t c = l - nv, i = c % nx, j = c / nx;

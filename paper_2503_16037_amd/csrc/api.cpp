@@ -199,8 +199,14 @@ sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz,
     if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nx > 1024 || d->ny > 1024 || d->nz > 1024)
         return fail(SG_E_INVALID, "grid dimensions must be in 1..1024");
     if (!(d->voxel_m > 0.0) || !std::isfinite(d->voxel_m)) return fail(SG_E_INVALID, "voxel_m must be > 0");
-    if (!d->mu_s || !d->mu_a || !d->vol_pos_fx || !d->adj_ptr || !d->surf_albedo || !d->hg_g)
+    if (d->n_nodes < 0) return fail(SG_E_INVALID, "n_nodes must be >= 0");
+    const bool general = d->n_nodes > 0;
+    if (!d->mu_s || !d->mu_a || !(general ? d->node_pos_fx : d->vol_pos_fx) || !d->adj_ptr || !d->surf_albedo ||
+        !d->hg_g)
         return fail(SG_E_INVALID, "a required array is NULL");
+    if (general && !d->los_ptr) return fail(SG_E_INVALID, "general nodes need los_ptr");
+    if (general && d->los_ptr[(int64_t)d->nx * d->ny] > 0 && (!d->los_node || !d->los_t))
+        return fail(SG_E_INVALID, "general nodes need los_node and los_t");
     if (d->n_phase < 1 || d->n_phase > 4) return fail(SG_E_INVALID, "n_phase must be 1..4");
     if ((d->n_phase > 1) != (d->phase_frac != nullptr))
         return fail(SG_E_INVALID, "phase_frac must be given iff n_phase > 1");
@@ -240,7 +246,8 @@ sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz,
             if (std::abs((long long)v[k]) > (1LL << 22)) return fail(SG_E_INVALID, "direction components must be <= 2^22");
     }
     const int64_t nvox = (int64_t)d->nx * d->ny * d->nz;
-    N = nvox + (d->surface_nodes ? (int64_t)d->nx * d->ny : 0);
+    const int64_t nvol = general ? (int64_t)d->n_nodes : nvox;
+    N = nvol + (d->surface_nodes ? (int64_t)d->nx * d->ny : 0);
     for (int64_t v = 0; v < nvox; ++v) {
         const float a = d->mu_s[v], b = d->mu_a[v];
         if (!(a >= 0.0f) || !(b >= 0.0f) || !std::isfinite(a) || !std::isfinite(b))
@@ -253,13 +260,38 @@ sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz,
     for (int64_t v = 0; v < (int64_t)d->nx * d->ny; ++v)
         if (!(d->surf_albedo[v] >= 0.0f) || !(d->surf_albedo[v] <= 1.0f))
             return fail(SG_E_INVALID, "surf_albedo must be in [0, 1]");
-    for (int64_t v = 0; v < nvox; ++v) {
-        const int64_t ix = v % d->nx, iy = (v / d->nx) % d->ny, iz = v / ((int64_t)d->nx * d->ny);
-        const int64_t p[3] = {d->vol_pos_fx[3 * v], d->vol_pos_fx[3 * v + 1], d->vol_pos_fx[3 * v + 2]};
-        const int64_t c[3] = {ix, iy, iz};
-        for (int k = 0; k < 3; ++k)
-            if (!(p[k] > c[k] * 65536 && p[k] < (c[k] + 1) * 65536))
-                return fail(SG_E_INVALID, "node position not strictly inside its voxel (node " + std::to_string(v) + ")");
+    if (!general) {
+        for (int64_t v = 0; v < nvox; ++v) {
+            const int64_t ix = v % d->nx, iy = (v / d->nx) % d->ny, iz = v / ((int64_t)d->nx * d->ny);
+            const int64_t p[3] = {d->vol_pos_fx[3 * v], d->vol_pos_fx[3 * v + 1], d->vol_pos_fx[3 * v + 2]};
+            const int64_t c[3] = {ix, iy, iz};
+            for (int k = 0; k < 3; ++k)
+                if (!(p[k] > c[k] * 65536 && p[k] < (c[k] + 1) * 65536))
+                    return fail(SG_E_INVALID, "node position not strictly inside its voxel (node " + std::to_string(v) + ")");
+        }
+    } else {
+        const int64_t W[3] = {(int64_t)d->nx * 65536, (int64_t)d->ny * 65536, (int64_t)d->nz * 65536};
+        for (int64_t l = 0; l < nvol; ++l)
+            for (int k = 0; k < 3; ++k) {
+                const int64_t c = d->node_pos_fx[3 * l + k];
+                const bool per = k < 2 && (d->periodic >> k & 1);
+                if (per ? !(c >= 0 && c < W[k]) : !(c > 0 && c < W[k]))
+                    return fail(SG_E_INVALID, "general node outside the box (node " + std::to_string(l) + ")");
+            }
+        const int64_t npx = (int64_t)d->nx * d->ny;
+        if (d->los_ptr[0] != 0) return fail(SG_E_INVALID, "los_ptr[0] must be 0");
+        for (int64_t p = 0; p < npx; ++p) {
+            if (d->los_ptr[p + 1] < d->los_ptr[p]) return fail(SG_E_INVALID, "los_ptr must be non-decreasing");
+            double prev = 0.0;
+            for (int64_t e = d->los_ptr[p]; e < d->los_ptr[p + 1]; ++e) {
+                if (!(d->los_t[e] > prev) || !std::isfinite(d->los_t[e]))
+                    return fail(SG_E_INVALID, "los_t must be finite and strictly increasing from 0 (pixel " +
+                                                  std::to_string(p) + ")");
+                if (d->los_node[e] < -1 || d->los_node[e] >= nvol)
+                    return fail(SG_E_INVALID, "los_node out of range (pixel " + std::to_string(p) + ")");
+                prev = d->los_t[e];
+            }
+        }
     }
     const int64_t *ap = d->adj_ptr;
     if (ap[0] != 0) return fail(SG_E_INVALID, "adj_ptr[0] must be 0");
@@ -284,7 +316,7 @@ sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz,
             if (j < 0 || j >= N) return fail(SG_E_INVALID, "adjacency head out of range");
             if (j == l) return fail(SG_E_INVALID, "self loop");
             if (e > ap[l] && d->adj_idx[e - 1] >= j) return fail(SG_E_INVALID, "adjacency rows must be strictly ascending");
-            if (l >= nvox && j >= nvox) return fail(SG_E_INVALID, "surface-surface pair");
+            if (l >= nvol && j >= nvol) return fail(SG_E_INVALID, "surface-surface pair");
         }  // symmetry is checked on the device once the adjacency is uploaded
     }
     if (d->periodic & ~(SG_PERIODIC_X | SG_PERIODIC_Y))
@@ -298,8 +330,8 @@ sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz,
                 return fail(SG_E_INVALID, "with periodic axes the sun and view rays must reach the top within 65536 voxels");
         }
         const auto coord = [&](int64_t l, int k) -> long long {
-            if (l < nvox) return d->vol_pos_fx[3 * l + k];
-            const int64_t c = l - nvox;  // surface node: the column's centre
+            if (l < nvol) return general ? d->node_pos_fx[3 * l + k] : d->vol_pos_fx[3 * l + k];
+            const int64_t c = l - nvol;  // surface node: the column's centre
             return (k == 0 ? c % d->nx : c / d->nx) * 65536LL + 32768;
         };
         const long long W[2] = {(long long)d->nx * 65536, (long long)d->ny * 65536};
@@ -1093,7 +1125,8 @@ void free_scene_impl(Scene *s) {
     void *ptrs[] = {s->big, s->bigdir, s->bigrow, s->big_part, s->mu_s, s->mu_a, s->frac, s->albedo, s->abs_scale_d, s->pos, s->adj_ptr, s->adj_idx, s->lat,
                     s->tab, s->lut, s->hull, s->rev, s->nodeoff, s->row_ptr, s->col_idx, s->scan_tmp, s->tau_s, s->tau_a, s->tsun_s,
                     s->tsun_a, s->T, s->Tsun, s->rho, s->val, s->S, s->x, s->y, s->c_rhs, s->c_a, s->c_b, s->qsun,
-                    s->q, s->bS, s->bx, s->by, s->brho, s->bsrc, s->lam_buf, s->x64, s->r64, s->gm_V, s->partial, s->meas, s->meas_part, s->scal, s->J, s->pix};
+                    s->q, s->bS, s->bx, s->by, s->brho, s->bsrc, s->lam_buf, s->x64, s->r64, s->gm_V, s->partial, s->meas, s->meas_part, s->scal, s->J, s->pix,
+                    s->gmu_s, s->gmu_a, s->gfrac, s->los_ptr, s->los_node, s->los_t};
     if (s->ctx)
         for (void *p : ptrs) pool_free(s->ctx, p);
     s->bytes = 0;
@@ -1119,6 +1152,8 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     s.nx = d->nx; s.ny = d->ny; s.nz = d->nz;
     s.voxel_m = d->voxel_m;
     s.nvox = d->nx * d->ny * d->nz;
+    s.general = d->n_nodes > 0;
+    s.n_vol = s.general ? d->n_nodes : s.nvox;
     s.N = (int)N;
     s.npx = d->nx * d->ny;
     s.E = E;
@@ -1167,7 +1202,7 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
         if (deg > kMaxWaveDegree) {
             bigv.push_back((int)l);
             // one direction per workgroup for the colouring, groups for the Voronoi cells
-            const int64_t n_in = l < s.nvox ? deg + 1 : 1;
+            const int64_t n_in = l < s.n_vol ? deg + 1 : 1;
             const int64_t G = s.sigma_mode == SG_SIGMA_COLOUR ? 1 : qbuild_group_big(s.n_fib);
             bigdir.push_back(bigdir.back() + (n_in + G - 1) / G);
             bigrow.push_back(bigrow.back() + (deg + 255) / 256);
@@ -1181,6 +1216,16 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
         SG_TRY(dalloc(s, &s.bigdir, bigdir.size()));
         SG_TRY(dalloc(s, &s.bigrow, bigrow.size()));
         SG_TRY(dalloc(s, &s.big_part, (size_t)s.n_bigrow));
+    }
+    int64_t n_el = 0;
+    if (s.general) {
+        n_el = d->los_ptr[s.npx];
+        SG_TRY(dalloc(s, &s.gmu_s, (size_t)s.n_vol));
+        SG_TRY(dalloc(s, &s.gmu_a, (size_t)s.n_vol));
+        if (s.n_phase > 1) SG_TRY(dalloc(s, &s.gfrac, (size_t)s.n_phase * s.n_vol));
+        SG_TRY(dalloc(s, &s.los_ptr, (size_t)s.npx + 1));
+        SG_TRY(dalloc(s, &s.los_node, (size_t)n_el));
+        SG_TRY(dalloc(s, &s.los_t, (size_t)n_el));
     }
     SG_TRY(dalloc(s, &s.lat, (size_t)3 * s.n_fib));
     SG_TRY(dalloc(s, &s.tab, (size_t)(s.n_phase + 1) * s.n_fib));
@@ -1224,11 +1269,11 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     const double t2 = host_ms();
     // host-side staging of the inputs
     std::vector<int32_t> pos((size_t)3 * s.N);
-    std::memcpy(pos.data(), d->vol_pos_fx, sizeof(int32_t) * 3 * (size_t)s.nvox);
+    std::memcpy(pos.data(), s.general ? d->node_pos_fx : d->vol_pos_fx, sizeof(int32_t) * 3 * (size_t)s.n_vol);
     if (s.surface) {
         for (int iy = 0; iy < s.ny; ++iy)
             for (int ix = 0; ix < s.nx; ++ix) {
-                const size_t l = (size_t)s.nvox + ix + (size_t)s.nx * iy;
+                const size_t l = (size_t)s.n_vol + ix + (size_t)s.nx * iy;
                 pos[3 * l] = ix * 65536 + 32768;
                 pos[3 * l + 1] = iy * 65536 + 32768;
                 pos[3 * l + 2] = 0;
@@ -1261,6 +1306,29 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
     SG_TRY(upload(s, s.mu_s, d->mu_s, sizeof(float) * s.nvox, st));
     SG_TRY(upload(s, s.mu_a, d->mu_a, sizeof(float) * s.nvox, st));
     if (s.frac) SG_TRY(upload(s, s.frac, d->phase_frac, sizeof(float) * s.n_phase * (size_t)s.nvox, st));
+    std::vector<float> gms, gma, gfr;  // staged until the stream drains
+    if (s.general) {
+        // the medium of each general node: that of the voxel containing it
+        gms.resize(s.n_vol);
+        gma.resize(s.n_vol);
+        gfr.resize(s.frac ? (size_t)s.n_phase * s.n_vol : 0);
+        for (int l = 0; l < s.n_vol; ++l) {
+            const int64_t v = (int64_t)(pos[3 * l] >> 16) +
+                              (int64_t)s.nx * ((int64_t)(pos[3 * l + 1] >> 16) + (int64_t)s.ny * (pos[3 * l + 2] >> 16));
+            gms[l] = d->mu_s[v];
+            gma[l] = d->mu_a[v];
+            for (int k = 0; s.frac && k < s.n_phase; ++k)
+                gfr[(size_t)k * s.n_vol + l] = d->phase_frac[(size_t)k * s.nvox + v];
+        }
+        SG_TRY(upload(s, s.gmu_s, gms.data(), sizeof(float) * s.n_vol, st));
+        SG_TRY(upload(s, s.gmu_a, gma.data(), sizeof(float) * s.n_vol, st));
+        if (s.gfrac) SG_TRY(upload(s, s.gfrac, gfr.data(), sizeof(float) * gfr.size(), st));
+        SG_TRY(upload(s, s.los_ptr, d->los_ptr, sizeof(int64_t) * ((size_t)s.npx + 1), st));
+        if (n_el) {
+            SG_TRY(upload(s, s.los_node, d->los_node, sizeof(int32_t) * (size_t)n_el, st));
+            SG_TRY(upload(s, s.los_t, d->los_t, sizeof(double) * (size_t)n_el, st));
+        }
+    }
     SG_TRY(upload(s, s.albedo, d->surf_albedo, sizeof(float) * s.npx, st));
     SG_TRY(upload(s, s.pos, pos.data(), sizeof(int32_t) * pos.size(), st));
     SG_TRY(upload(s, s.adj_ptr, d->adj_ptr, sizeof(int64_t) * ((size_t)s.N + 1), st));
@@ -1392,11 +1460,15 @@ uint64_t reservations(const sg_scene_desc *d, const sg_solve_opts *o, bool with_
     const uint64_t nvox = (uint64_t)d->nx * d->ny * d->nz, npx = (uint64_t)d->nx * d->ny;
     const uint64_t nl = (uint64_t)d->n_lambda, nf = (uint64_t)d->n_fib, np = (uint64_t)d->n_phase;
     const uint64_t n = (uint64_t)N, e = (uint64_t)E, z = (uint64_t)nnz;
+    const uint64_t n_vol = d->n_nodes > 0 ? (uint64_t)d->n_nodes : nvox;
+    const uint64_t n_el = d->n_nodes > 0 ? (uint64_t)d->los_ptr[npx] : 0;
     bool table = false;
     for (int k = 0; k < d->n_phase; ++k) table = table || (d->phase_kind && d->phase_kind[k] == SG_PHASE_TABLE);
     uint64_t b = a(nvox, 4) * 2 + (np > 1 ? a(np * nvox, 4) : 0) + a(npx, 4) + a(3 * n, 4) + a(n + 1, 8) +
                  a(e, 4) + a(3 * nf, 8) + a((np + 1) * nf, 8) + (table ? a(np * (uint64_t)d->phase_lut_n, 8) : 0) +
                  (d->sigma_mode == SG_SIGMA_COLOUR ? a(nf * (kHullNb + 1), 4) : 0);
+    if (d->n_nodes > 0)  // general nodes: their medium and the lines of sight's elements
+        b += a(n_vol, 4) * 2 + (np > 1 ? a(np * n_vol, 4) : 0) + a(npx + 1, 8) + a(n_el, 4) + a(n_el, 8);
     b += a(e, 4) + a(n + 1, 8) + a(e + 1, 8) + a(n / 2048 + 2, 8) + a(e, 4);
     uint64_t n_big = 0, n_rows = 0;
     for (int64_t l = 0; l < N; ++l) {

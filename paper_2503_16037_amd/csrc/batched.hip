@@ -19,8 +19,9 @@ namespace sg {
 
 namespace {
 
-// rho_l(lambda) and the solar factor T_sun,l(lambda) (x mu0 on the surface).
-__global__ __launch_bounds__(256) void k_bnode_coef(int N, int nvox, int nl, const float *__restrict__ mu_s,
+// rho_l(lambda) and the solar factor T_sun,l(lambda) (x mu0 on the surface); mu_s, mu_a:
+// the medium at each of the nvol volume nodes.
+__global__ __launch_bounds__(256) void k_bnode_coef(int N, int nvol, int nl, const float *__restrict__ mu_s,
                                                    const float *__restrict__ mu_a, const float *__restrict__ albedo,
                                                    const float *__restrict__ tsun_s, const float *__restrict__ tsun_a,
                                                    const float *__restrict__ abs_scale, float dx, float mu0,
@@ -30,17 +31,17 @@ __global__ __launch_bounds__(256) void k_bnode_coef(int N, int nvox, int nl, con
     const int l = (int)(i / nl), lam = (int)(i % nl);
     const float s = abs_scale[lam];
     float r;
-    if (l < nvox) {
+    if (l < nvol) {
         const float ms = mu_s[l];
         const float me = ms + s * mu_a[l];
         if (mode == 1) r = ms * dx;
         else r = me > 0.f ? (ms / me) * (-expm1f(-me * dx)) : 0.f;
     } else {
-        r = albedo[l - nvox];
+        r = albedo[l - nvol];
     }
     const float ts = expf(-(tsun_s[l] + s * tsun_a[l]));
     brho[i] = r;
-    bsrc[i] = l < nvox ? ts : mu0 * ts;
+    bsrc[i] = l < nvol ? ts : mu0 * ts;
 }
 
 // One node per wavefront, lanes = wavelengths (tiles of 64).  The node's phase-cell
@@ -378,11 +379,11 @@ __global__ void k_fill_f32(float *__restrict__ a, long long n) {
         a[i] = 0.f;
 }
 
-__device__ __forceinline__ double theta_mix_b(const PhaseSet &pm, const float *__restrict__ frac, int nvox, int v,
+__device__ __forceinline__ double theta_mix_b(const PhaseSet &pm, const float *__restrict__ frac, int stride, int v,
                                               double mu) {
     double th = 0.0;
     for (int c = 0; c < pm.n; ++c) {
-        const double f = frac ? (double)frac[(long long)c * nvox + v] : 1.0;
+        const double f = frac ? (double)frac[(long long)c * stride + v] : 1.0;
         th += f * phase_theta(pm, c, mu);
     }
     return th;
@@ -390,7 +391,7 @@ __device__ __forceinline__ double theta_mix_b(const PhaseSet &pm, const float *_
 
 // J[l][lambda]: one wavefront per node; lane m evaluates in-edge m's phase function
 // once, then the lanes (wavelengths) accumulate in FP64.
-__global__ __launch_bounds__(64) void k_bnode_J(int N, int nvox, int nl, const long long *__restrict__ adj_ptr,
+__global__ __launch_bounds__(64) void k_bnode_J(int N, int nvol, int nl, const long long *__restrict__ adj_ptr,
                                                const int *__restrict__ adj_idx, const int *__restrict__ rev,
                                                const int *__restrict__ pos, const float *__restrict__ tau_s,
                                                const float *__restrict__ tau_a, const float *__restrict__ abs_scale,
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(64) void k_bnode_J(int N, int nvox, int nl, const l
     const int lane = threadIdx.x;
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
-    const bool vol = l < nvox;
+    const bool vol = l < nvol;
     if (lane < d) {
         double t = 1.0;
         if (vol) {
@@ -413,11 +414,11 @@ __global__ __launch_bounds__(64) void k_bnode_J(int N, int nvox, int nl, const l
             const long long Dz = (long long)pos[3 * l + 2] - pos[3 * j + 2];
             const double nrm = sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
             const double mu = ((double)Dx / nrm) * vx + ((double)Dy / nrm) * vy + ((double)Dz / nrm) * vz;
-            t = theta_mix_b(pm, frac, nvox, l, mu);
+            t = theta_mix_b(pm, frac, nvol, l, mu);
         }
         th[lane] = t;
     }
-    const double th_sun = vol ? theta_mix_b(pm, frac, nvox, l, sx * vx + sy * vy + sz * vz) : 1.0;
+    const double th_sun = vol ? theta_mix_b(pm, frac, nvol, l, sx * vx + sy * vy + sz * vz) : 1.0;
     __syncthreads();
     for (int l0 = 0; l0 < nl; l0 += 64) {
         const int lam = l0 + lane;
@@ -442,12 +443,13 @@ __global__ __launch_bounds__(64) void k_bpixels(int nx, int ny, int nz, int per,
                                                double len_view, long long vdx, long long vdy, long long vdz,
                                                long long sdx, long long sdy, long long sdz, double len_sun,
                                                const float *__restrict__ albedo, const double *__restrict__ J,
-                                               int surface, double mu0, double *__restrict__ out) {
+                                               int surface, double mu0, int nvol,
+                                               const long long *__restrict__ los_ptr, const int *__restrict__ los_node,
+                                               const double *__restrict__ los_t, double *__restrict__ out) {
     const int p = blockIdx.x;
     const int lane = threadIdx.x;
     const long long ix = p % nx, iy = p / nx;
     const long long px = ix * kFx + kFx / 2, py = iy * kFx + kFx / 2;
-    const long long nvox = (long long)nx * ny * nz;
     const double a_pi = (double)albedo[p] / 3.14159265358979323846;
     for (int l0 = 0; l0 < nl; l0 += 64) {
         const int lam = min(l0 + lane, nl - 1);
@@ -459,18 +461,48 @@ __global__ __launch_bounds__(64) void k_bpixels(int nx, int ny, int nz, int per,
             return true;
         });
         double I = 0.0, cum = 0.0;
-        voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
-            const long long v = x + (long long)nx * (y + (long long)ny * z);
-            const double ms = (double)mu_s[v];
-            const double me = ms + s * (double)mu_a[v];
-            const double tk = me * ((double)num / (double)den * len_view);
-            const double om = me > 0.0 ? ms / me : 0.0;
-            I += exp(-(tau_tot - (cum + tk))) * (om * (-expm1(-tk))) * J[v * nl + lam];
-            cum += tk;
-            return true;
-        });
+        if (!los_ptr) {
+            voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
+                const long long v = x + (long long)nx * (y + (long long)ny * z);
+                const double ms = (double)mu_s[v];
+                const double me = ms + s * (double)mu_a[v];
+                const double tk = me * ((double)num / (double)den * len_view);
+                const double om = me > 0.0 ? ms / me : 0.0;
+                I += exp(-(tau_tot - (cum + tk))) * (om * (-expm1(-tk))) * J[v * nl + lam];
+                cum += tk;
+                return true;
+            });
+        } else {
+            // general nodes: chords cut at the ends of the line's elements (see k_pixels)
+            const long long e1 = los_ptr[p + 1];
+            long long e = los_ptr[p];
+            double t = 0.0;
+            voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
+                const long long v = x + (long long)nx * (y + (long long)ny * z);
+                const double ms = (double)mu_s[v];
+                const double me = ms + s * (double)mu_a[v];
+                const double om = me > 0.0 ? ms / me : 0.0;
+                const double t1 = t + (double)num / (double)den;
+                double a = t;
+                while (a < t1) {
+                    while (e < e1 && los_t[e] <= a) ++e;
+                    double b = t1;
+                    int node = -1;
+                    if (e < e1) {
+                        b = fmin(t1, los_t[e]);
+                        node = los_node[e];
+                    }
+                    const double tk = me * ((b - a) * len_view);
+                    if (node >= 0) I += exp(-(tau_tot - (cum + tk))) * (om * (-expm1(-tk))) * J[(long long)node * nl + lam];
+                    cum += tk;
+                    a = b;
+                }
+                t = t1;
+                return true;
+            });
+        }
         if (surface) {
-            I += exp(-tau_tot) * a_pi * J[(nvox + p) * nl + lam];
+            I += exp(-tau_tot) * a_pi * J[((long long)nvol + p) * nl + lam];
         } else {
             double ts = 0.0;
             voxel_walk(nx, ny, nz, per, px, py, 0, sdx, sdy, sdz, true, [&](int x, int y, int z, long long num, long long den) {
@@ -493,8 +525,8 @@ inline int grid_for(long long n) {
 
 void launch_bnode_coef(Scene &s, hipStream_t st) {
     const long long n = (long long)s.N * s.n_lambda;
-    hipLaunchKernelGGL(k_bnode_coef, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.N, s.nvox, s.n_lambda, s.mu_s,
-                       s.mu_a, s.albedo, (const float *)s.tsun_s, (const float *)s.tsun_a, s.abs_scale_d,
+    hipLaunchKernelGGL(k_bnode_coef, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.N, s.n_vol, s.n_lambda,
+                       node_mu_s(s), node_mu_a(s), s.albedo, (const float *)s.tsun_s, (const float *)s.tsun_a, s.abs_scale_d,
                        (float)s.voxel_m, (float)s.mu0, s.weight_mode, s.brho, s.bsrc);
 }
 
@@ -595,8 +627,8 @@ void launch_fill_f32(float *a, long long n, hipStream_t st) {
 
 void launch_batched_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance) {
     const PhaseSet pm = phase_set(s);
-    hipLaunchKernelGGL(k_bnode_J, dim3(s.N), dim3(64), 0, st, s.N, s.nvox, s.n_lambda, s.adj_ptr, s.adj_idx, s.rev,
-                       s.pos, (const float *)s.tau_s, (const float *)s.tau_a, s.abs_scale_d, s.bsrc, phi, pm, s.frac,
+    hipLaunchKernelGGL(k_bnode_J, dim3(s.N), dim3(64), 0, st, s.N, s.n_vol, s.n_lambda, s.adj_ptr, s.adj_idx, s.rev,
+                       s.pos, (const float *)s.tau_s, (const float *)s.tau_a, s.abs_scale_d, s.bsrc, phi, pm, node_frac(s),
                        s.sun_in[0], s.sun_in[1], s.sun_in[2], s.view_u[0], s.view_u[1], s.view_u[2],
                        scatter_order == 1 ? 0 : 1, s.periodic, (long long)s.nx * kFx, (long long)s.ny * kFx, s.J);
     const double fx = s.voxel_m / 65536.0;
@@ -605,7 +637,8 @@ void launch_batched_gather(Scene &s, hipStream_t st, const double *phi, int scat
     hipLaunchKernelGGL(k_bpixels, dim3(s.npx), dim3(64), 0, st, s.nx, s.ny, s.nz, s.periodic, s.n_lambda, s.mu_s,
                        s.mu_a, s.abs_scale_d, lv, (long long)s.view[0], (long long)s.view[1], (long long)s.view[2],
                        (long long)s.sun[0], (long long)s.sun[1], (long long)s.sun[2], ls, s.albedo, s.J, s.surface,
-                       s.mu0, radiance);
+                       s.mu0, s.n_vol, s.general ? s.los_ptr : (const long long *)nullptr, s.los_node, s.los_t,
+                       radiance);
 }
 
 }  // namespace sg

@@ -7,8 +7,11 @@
 //   I_p = sum_k T_entry(k) w_k (1 - exp(-mu_e,k s_k)) J_{v_k} + T_view (A_p / pi) J_{s_p}
 // with s_a the propagation direction of in-edge a, v the unit vector toward the
 // sensor, s_k the chord of the line of sight in voxel v_k and T_entry(k) the
-// transmittance from the chord's far end to the sensor.  Everything here is
-// accumulated in FP64 (one thread per node, then one thread per pixel).
+// transmittance from the chord's far end to the sensor.  With general nodes (the path
+// points of the lines of sight, Sec. 2) the chords are cut at the ends of the line's
+// elements and each piece takes J of its element's node instead of the voxel's.
+// Everything here is accumulated in FP64 (one thread per node, then one thread per
+// pixel).
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -16,19 +19,20 @@ namespace sg {
 
 namespace {
 
-__device__ __forceinline__ double theta_mix(const PhaseSet &pm, const float *__restrict__ frac, int nvox, int v,
+__device__ __forceinline__ double theta_mix(const PhaseSet &pm, const float *__restrict__ frac, int stride, int v,
                                             double mu) {
     double th = 0.0;
     for (int c = 0; c < pm.n; ++c) {
-        const double f = frac ? (double)frac[(long long)c * nvox + v] : 1.0;
+        const double f = frac ? (double)frac[(long long)c * stride + v] : 1.0;
         th += f * phase_theta(pm, c, mu);
     }
     return th;
 }
 
 // One wavefront per node: lane m takes in-edge m's term, then a fixed-order butterfly sum.
+// frac: the phase fractions at each volume node ([component][node]), nvol volume nodes
 template <class Real, bool kPer>
-__global__ __launch_bounds__(256) void k_node_J(int N, int nvox, const long long *__restrict__ adj_ptr,
+__global__ __launch_bounds__(256) void k_node_J(int N, int nvol, const long long *__restrict__ adj_ptr,
                                                const int *__restrict__ adj_idx, const int *__restrict__ rev,
                                                const int *__restrict__ pos, const Real *__restrict__ T,
                                                const Real *__restrict__ Tsun, const double *__restrict__ phi,
@@ -42,7 +46,7 @@ __global__ __launch_bounds__(256) void k_node_J(int N, int nvox, const long long
     if (l >= N) return;
     const long long off = adj_ptr[l], end = adj_ptr[l + 1];
     const int d = (int)(end - off);
-    const bool vol = l < nvox;
+    const bool vol = l < nvol;
     double acc = 0.0;
     if (multiple) {
         for (int m = lane; m < d; m += 64) {
@@ -54,14 +58,14 @@ __global__ __launch_bounds__(256) void k_node_J(int N, int nvox, const long long
                 const long long Dy = min_image((long long)pos[3 * l + 1] - pos[3 * j + 1], wy, per & 2);
                 const long long Dz = (long long)pos[3 * l + 2] - pos[3 * j + 2];
                 const double inv = 1.0 / sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
-                th = theta_mix(pm, frac, nvox, l, ((double)Dx * vx + (double)Dy * vy + (double)Dz * vz) * inv);
+                th = theta_mix(pm, frac, nvol, l, ((double)Dx * vx + (double)Dy * vy + (double)Dz * vz) * inv);
             }
             acc += th * (double)T[e] * phi[rev[e]];
         }
     }
     acc = wave_sum(acc);
     if (lane == 0) {
-        const double src = vol ? theta_mix(pm, frac, nvox, l, sx * vx + sy * vy + sz * vz) * (double)Tsun[l]
+        const double src = vol ? theta_mix(pm, frac, nvol, l, sx * vx + sy * vy + sz * vz) * (double)Tsun[l]
                                : mu0 * (double)Tsun[l];
         J[l] = src + acc;
     }
@@ -72,12 +76,13 @@ __global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, int per, 
                                               long long vdx, long long vdy, long long vdz, long long sdx,
                                               long long sdy, long long sdz, double len_sun,
                                               const float *__restrict__ albedo, const double *__restrict__ J,
-                                              int surface, double mu0, double *__restrict__ out) {
+                                              int surface, double mu0, int nvol, const long long *__restrict__ los_ptr,
+                                              const int *__restrict__ los_node, const double *__restrict__ los_t,
+                                              double *__restrict__ out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nx * ny) return;
     const long long ix = p % nx, iy = p / nx;
     const long long px = ix * kFx + kFx / 2, py = iy * kFx + kFx / 2;
-    const long long nvox = (long long)nx * ny * nz;
     // pass 1: optical depth of the whole line of sight
     double tau_tot = 0.0;
     voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
@@ -88,21 +93,52 @@ __global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, int per, 
     });
     // pass 2: chords, each attenuated from its far end to the sensor
     double I = 0.0, cum = 0.0;
-    voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
-        const long long v = x + (long long)nx * (y + (long long)ny * z);
-        const double ms = (double)mu_s[v];
-        const double me = ms + scale * (double)mu_a[v];
-        const double sk = (double)num / (double)den * len_view;
-        const double tk = me * sk;
-        const double t_entry = exp(-(tau_tot - (cum + tk)));
-        const double om = me > 0.0 ? ms / me : 0.0;
-        I += t_entry * (om * (-expm1(-tk))) * J[v];
-        cum += tk;
-        return true;
-    });
+    if (!los_ptr) {
+        voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
+            const long long v = x + (long long)nx * (y + (long long)ny * z);
+            const double ms = (double)mu_s[v];
+            const double me = ms + scale * (double)mu_a[v];
+            const double sk = (double)num / (double)den * len_view;
+            const double tk = me * sk;
+            const double t_entry = exp(-(tau_tot - (cum + tk)));
+            const double om = me > 0.0 ? ms / me : 0.0;
+            I += t_entry * (om * (-expm1(-tk))) * J[v];  // the voxel's own node
+            cum += tk;
+            return true;
+        });
+    } else {
+        // general nodes: the chord [t, t + dt] cut at the ends of the line's elements; element
+        // e covers (los_t[e - 1], los_t[e]], the part above the last end has no node
+        const long long e1 = los_ptr[p + 1];
+        long long e = los_ptr[p];
+        double t = 0.0;
+        voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
+            const long long v = x + (long long)nx * (y + (long long)ny * z);
+            const double ms = (double)mu_s[v];
+            const double me = ms + scale * (double)mu_a[v];
+            const double om = me > 0.0 ? ms / me : 0.0;
+            const double t1 = t + (double)num / (double)den;
+            double a = t;
+            while (a < t1) {
+                while (e < e1 && los_t[e] <= a) ++e;
+                double b = t1;
+                int node = -1;
+                if (e < e1) {
+                    b = fmin(t1, los_t[e]);
+                    node = los_node[e];
+                }
+                const double tk = me * ((b - a) * len_view);
+                if (node >= 0) I += exp(-(tau_tot - (cum + tk))) * (om * (-expm1(-tk))) * J[node];
+                cum += tk;
+                a = b;
+            }
+            t = t1;
+            return true;
+        });
+    }
     const double a_pi = (double)albedo[p] / 3.14159265358979323846;
     if (surface) {
-        I += exp(-tau_tot) * a_pi * J[nvox + p];
+        I += exp(-tau_tot) * a_pi * J[nvol + p];
     } else {
         double ts = 0.0;
         voxel_walk(nx, ny, nz, per, px, py, 0, sdx, sdy, sdz, true, [&](int x, int y, int z, long long num, long long den) {
@@ -121,8 +157,8 @@ template <class Real>
 void launch_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance) {
     const PhaseSet pm = phase_set(s);
     const auto node_J = s.periodic ? k_node_J<Real, true> : k_node_J<Real, false>;
-    hipLaunchKernelGGL(node_J, dim3((s.N + 3) / 4), dim3(256), 0, st, s.N, s.nvox, s.adj_ptr, s.adj_idx, s.rev, s.pos,
-                       (const Real *)s.T, (const Real *)s.Tsun, phi, pm, s.frac, s.sun_in[0], s.sun_in[1], s.sun_in[2],
+    hipLaunchKernelGGL(node_J, dim3((s.N + 3) / 4), dim3(256), 0, st, s.N, s.n_vol, s.adj_ptr, s.adj_idx, s.rev, s.pos,
+                       (const Real *)s.T, (const Real *)s.Tsun, phi, pm, node_frac(s), s.sun_in[0], s.sun_in[1], s.sun_in[2],
                        s.view_u[0], s.view_u[1], s.view_u[2], s.mu0, scatter_order == 1 ? 0 : 1, s.periodic,
                        (long long)s.nx * kFx, (long long)s.ny * kFx, s.J);
     const double fx = s.voxel_m / 65536.0;
@@ -132,7 +168,8 @@ void launch_gather(Scene &s, hipStream_t st, const double *phi, int scatter_orde
     hipLaunchKernelGGL(k_pixels, dim3((s.npx + 63) / 64), dim3(64), 0, st, s.nx, s.ny, s.nz, s.periodic, s.mu_s, s.mu_a, scale,
                        lv,
                        (long long)s.view[0], (long long)s.view[1], (long long)s.view[2], (long long)s.sun[0],
-                       (long long)s.sun[1], (long long)s.sun[2], ls, s.albedo, s.J, s.surface, s.mu0, radiance);
+                       (long long)s.sun[1], (long long)s.sun[2], ls, s.albedo, s.J, s.surface, s.mu0, s.n_vol,
+                       s.general ? s.los_ptr : (const long long *)nullptr, s.los_node, s.los_t, radiance);
 }
 
 template void launch_gather<float>(Scene &, hipStream_t, const double *, int, double *);

@@ -27,6 +27,9 @@
 //   of cells (bisection on the box volumes); if at least n pairs have k >= t, the
 //   n best of them are the answer; otherwise every pair is streamed in node chunks
 //   through a running best-n list.
+// General nodes (the path points of the lines of sight, Sec. 2) are not tied to voxels:
+// a volume node's partners are all nodes of higher id, and top-n requests go straight
+// to the streamed ranking of every pair.
 // The adjacency is assembled from the sorted directed pair codes (tail N + head).
 #include <hipcub/hipcub.hpp>
 
@@ -58,7 +61,8 @@ std::vector<unsigned long long> cell_budgets() {
 
 struct Geo {
     int nx, ny, nz, surface;
-    long long nvox, N;
+    int general;               // 1: general volume nodes (every pair ranked), 0: one per voxel
+    long long nvox, nvol, N;   // voxels, volume nodes, all nodes
     double mean[3], sd[3];  // per-axis centre and scale (sd = 0: the axis is ignored)
     double mu_max;
 };
@@ -110,7 +114,8 @@ struct Dev {
 
 // ---- kernels ---------------------------------------------------------------------------
 
-// fixed-point position, coupling coefficient and scaled coordinates of every node
+// fixed-point position, coupling coefficient and scaled coordinates of every node; a
+// general node couples with the mu_s of the voxel holding it
 __global__ void k_graph_nodes(Geo g, const int *__restrict__ pos, const float *__restrict__ mu_s,
                               const float *__restrict__ albedo, long long *__restrict__ P, double *__restrict__ q,
                               double *__restrict__ mu) {
@@ -118,13 +123,15 @@ __global__ void k_graph_nodes(Geo g, const int *__restrict__ pos, const float *_
     const long long l = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (l >= g.N) return;
     long long p[3];
-    if (l < g.nvox) {
+    if (l < g.nvol) {
         p[0] = pos[3 * l];
         p[1] = pos[3 * l + 1];
         p[2] = pos[3 * l + 2];
-        mu[l] = (double)mu_s[l];
+        const long long v =
+            g.general ? p[0] / kFx + (long long)g.nx * (p[1] / kFx + (long long)g.ny * (p[2] / kFx)) : l;
+        mu[l] = (double)mu_s[v];
     } else {
-        const long long c = l - g.nvox;
+        const long long c = l - g.nvol;
         p[0] = (c % g.nx) * kFx + kFx / 2;
         p[1] = (c / g.nx) * kFx + kFx / 2;
         p[2] = 0;
@@ -159,7 +166,7 @@ __device__ __forceinline__ Box node_box(const Geo &g, const long long *__restric
     const long long n[3] = {g.nx, g.ny, g.nz};
     // k = 0 for every pair of this node, or a surface node (its pairs with volume
     // nodes are found from the volume side; two surface nodes never couple)
-    if (!(mi > 0.0) || i >= g.nvox) {
+    if (!(mi > 0.0) || i >= g.nvol) {
         for (int a = 0; a < 3; ++a) { b.lo[a] = 1; b.hi[a] = 0; }
         b.surf = false;
         return b;
@@ -210,6 +217,13 @@ __global__ void k_graph_boxes(Geo g, const long long *__restrict__ P, const doub
     if (r > n) return;
     if (r == n) {
         cells[n] = 0;
+        return;
+    }
+    if (g.general) {  // every partner of higher id: the range n0 + r + 1 .. N - 1
+        const long long i = n0 + r;
+        int *o = box + 8 * r;
+        for (int a = 0; a < 8; ++a) o[a] = 0;
+        cells[r] = i < g.nvol && mu[i] > 0.0 ? (unsigned long long)(g.N - 1 - i) : 0ull;
         return;
     }
     const Box b = node_box(g, P, mu, n0 + r, t);
@@ -298,12 +312,14 @@ __global__ __launch_bounds__(256) void k_graph_eval(Geo g, const double *__restr
                 const unsigned nv = bx * by * bz;
                 const unsigned lc = (unsigned)(c - (staged ? scoff[r - fb] : coff[r]));
                 i = n0 + r;
-                if (lc < nv) {
+                if (g.general) {
+                    j = i + 1 + lc;
+                } else if (lc < nv) {
                     const unsigned yz = lc / bx, cx = lc - yz * bx, cz = yz / by, cy = yz - cz * by;
                     j = ((long long)o[0] + cx) + (long long)g.nx * (((long long)o[1] + cy) + (long long)g.ny * ((long long)o[2] + cz));
                 } else {
                     const unsigned sl = lc - nv, sy = sl / bx, sx = sl - sy * bx;
-                    j = g.nvox + ((long long)o[0] + sx) + (long long)g.nx * ((long long)o[1] + sy);
+                    j = g.nvol + ((long long)o[0] + sx) + (long long)g.nx * ((long long)o[1] + sy);
                 }
                 eval = j > i;
                 if (eval) {
@@ -535,13 +551,16 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
     if (!n_edges) return gfail(SG_E_INVALID, "n_edges is NULL");
     if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nx > 1024 || d->ny > 1024 || d->nz > 1024)
         return gfail(SG_E_INVALID, "grid dimensions must be in 1..1024");
-    if (!d->mu_s || !d->vol_pos_fx || (d->surface_nodes && !d->surf_albedo))
+    const bool general = d->n_nodes > 0;
+    if (d->n_nodes < 0) return gfail(SG_E_INVALID, "n_nodes must be >= 0");
+    if (!d->mu_s || !(general ? d->node_pos_fx : d->vol_pos_fx) || (d->surface_nodes && !d->surf_albedo))
         return gfail(SG_E_INVALID, "a required array is NULL");
     if (d->n_pairs < 0) return gfail(SG_E_INVALID, "n_pairs must be >= 0");
     if (d->n_pairs == 0 && !(d->c_min >= 0.0 && std::isfinite(d->c_min)))
         return gfail(SG_E_INVALID, "c_min must be finite and >= 0");
     const long long nvox = (long long)d->nx * d->ny * d->nz;
-    const long long N = nvox + (d->surface_nodes ? (long long)d->nx * d->ny : 0);
+    const long long nvol = general ? (long long)d->n_nodes : nvox;
+    const long long N = nvol + (d->surface_nodes ? (long long)d->nx * d->ny : 0);
     if (N >= (1LL << 31)) return gfail(SG_E_INVALID, "too many nodes");
     float mmax = 0.0f;
     for (long long v = 0; v < nvox; ++v) {
@@ -555,12 +574,19 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
                 return gfail(SG_E_INVALID, "surf_albedo must be in [0, 1]");
     // exact integer moments of the positions, per axis
     __int128 s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0};
-    for (long long v = 0; v < nvox; ++v) {
+    const long long W[3] = {(long long)d->nx * kFx, (long long)d->ny * kFx, (long long)d->nz * kFx};
+    for (long long v = 0; v < nvol; ++v) {
         const long long c[3] = {v % d->nx, (v / d->nx) % d->ny, v / ((long long)d->nx * d->ny)};
         for (int a = 0; a < 3; ++a) {
-            const long long p = d->vol_pos_fx[3 * v + a];
-            if (!(p > c[a] * kFx && p < (c[a] + 1) * kFx))
-                return gfail(SG_E_INVALID, "node position not strictly inside its voxel (node " + std::to_string(v) + ")");
+            const long long p = general ? d->node_pos_fx[3 * v + a] : d->vol_pos_fx[3 * v + a];
+            // a general node lies in the box (x = 0 and y = 0 allowed: a periodic wrap puts
+            // nodes there), off the ground; a per-voxel node strictly inside its voxel
+            const bool in = general ? (a < 2 ? p >= 0 && p < W[a] : p > 0 && p < W[a])
+                                    : p > c[a] * kFx && p < (c[a] + 1) * kFx;
+            if (!in)
+                return gfail(SG_E_INVALID, std::string(general ? "node position outside the box"
+                                                               : "node position not strictly inside its voxel") +
+                                               " (node " + std::to_string(v) + ")");
             s1[a] += p;
             s2[a] += (__int128)p * p;
         }
@@ -579,7 +605,9 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
     g.ny = d->ny;
     g.nz = d->nz;
     g.surface = d->surface_nodes ? 1 : 0;
+    g.general = general ? 1 : 0;
     g.nvox = nvox;
+    g.nvol = nvol;
     g.N = N;
     g.mu_max = (double)mmax;
     for (int a = 0; a < 3; ++a) {
@@ -591,7 +619,7 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
     // node arrays
     int *pos = nullptr;
     float *mus = nullptr, *alb = nullptr;
-    GTRY(B.dev.get(&pos, 3 * nvox));
+    GTRY(B.dev.get(&pos, 3 * nvol));
     GTRY(B.dev.get(&mus, nvox));
     GTRY(B.dev.get(&alb, (long long)d->nx * d->ny));
     GTRY(B.dev.get(&B.P, 3 * N));
@@ -599,7 +627,8 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
     GTRY(B.dev.get(&B.mu, N));
     GTRY(B.dev.get(&B.scal, 4));
     GHIP(hipMemsetAsync(B.scal, 0, 4 * sizeof(unsigned long long), st));
-    GHIP(hipMemcpyAsync(pos, d->vol_pos_fx, sizeof(int) * 3 * nvox, hipMemcpyHostToDevice, st));
+    GHIP(hipMemcpyAsync(pos, general ? d->node_pos_fx : d->vol_pos_fx, sizeof(int) * 3 * nvol, hipMemcpyHostToDevice,
+                        st));
     GHIP(hipMemcpyAsync(mus, d->mu_s, sizeof(float) * nvox, hipMemcpyHostToDevice, st));
     if (d->surface_nodes)
         GHIP(hipMemcpyAsync(alb, d->surf_albedo, sizeof(float) * d->nx * d->ny, hipMemcpyHostToDevice, st));
@@ -622,9 +651,10 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
         const unsigned long long budget = budgets.back();
         double t_fit = 0.0;
         unsigned long long cells = 0;
-        GTRY(B.cells(0.0, cells));
+        if (!general) GTRY(B.cells(0.0, cells));
         const unsigned long long all_cells = cells;
-        for (size_t k = 0; k < budgets.size(); ++k) {
+        // general nodes have no voxel boxes: straight to the streamed ranking of every pair
+        for (size_t k = 0; k < budgets.size() && !general; ++k) {
             const unsigned long long bk = budgets[k];
             t_fit = 0.0;
             if (all_cells > bk) {
@@ -648,7 +678,7 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
         }
         t_used = t_fit;
         ranked = have;
-        if (have >= (unsigned long long)d->n_pairs || t_fit == 0.0) {
+        if (!general && (have >= (unsigned long long)d->n_pairs || t_fit == 0.0)) {
             GTRY(B.sort_desc(keys, codes, have));
             n_sel = std::min<unsigned long long>(have, (unsigned long long)d->n_pairs);
         } else {

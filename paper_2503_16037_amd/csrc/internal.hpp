@@ -69,6 +69,10 @@ struct Scene {
     int nx = 0, ny = 0, nz = 0;
     double voxel_m = 0.0;
     int nvox = 0, N = 0, npx = 0;
+    // volume nodes: nvox (one per voxel, node id = voxel id) or a general node set (the path
+    // points of the lines of sight), each node with the medium of its voxel
+    int n_vol = 0;
+    bool general = false;
     int64_t E = 0, nnz = 0;
     int dmax = 0;
     // nodes of degree above 64 (handled by their own kernels: one workgroup per node in the
@@ -102,6 +106,12 @@ struct Scene {
 
     // inputs
     float *mu_s = nullptr, *mu_a = nullptr, *frac = nullptr, *albedo = nullptr, *abs_scale_d = nullptr;
+    // general nodes: the medium of each node's voxel ([n_vol], fractions [n_phase][n_vol]) and
+    // the lines of sight's elements (pixel p's at los_ptr[p] ...: node and upper end)
+    float *gmu_s = nullptr, *gmu_a = nullptr, *gfrac = nullptr;
+    long long *los_ptr = nullptr;
+    int *los_node = nullptr;
+    double *los_t = nullptr;
     int *pos = nullptr;  // [N][3]
     long long *adj_ptr = nullptr;
     int *adj_idx = nullptr;
@@ -155,6 +165,12 @@ struct Scene {
     int last_scatter_order = 0;
     std::mutex mu;
 };
+
+// The medium at each volume node (indexed by node id; stride n_vol for the fractions): the
+// voxel arrays themselves when nodes and voxels coincide.
+inline const float *node_mu_s(const Scene &s) { return s.general ? s.gmu_s : s.mu_s; }
+inline const float *node_mu_a(const Scene &s) { return s.general ? s.gmu_a : s.mu_a; }
+inline const float *node_frac(const Scene &s) { return s.general ? s.gfrac : s.frac; }
 
 // The phase-function components of a scene (Sec. 3): kind 0 Henyey-Greenstein (g),
 // 1 Rayleigh, 2 a table in cos(theta) (row c of lut, lut_n samples at -1 + 2 m /

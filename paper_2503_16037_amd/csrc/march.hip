@@ -163,21 +163,22 @@ __global__ __launch_bounds__(256) void k_march_sun(int N, int nx, int ny, int nz
 
 // Node weight (reading of Eq. 7's mu_s factor): volume rho = w (1 - exp(-mu_e dx))
 // computed with expm1, or mu_s dx (mode 1); surface rho = albedo.
+// mu_s, mu_a: the medium at each volume node (indexed by node id)
 template <class Real>
-__global__ __launch_bounds__(256) void k_node_weights(int N, int nvox, const float *__restrict__ mu_s,
+__global__ __launch_bounds__(256) void k_node_weights(int N, int nvol, const float *__restrict__ mu_s,
                                                      const float *__restrict__ mu_a,
                                                      const float *__restrict__ albedo, Real dx, Real scale,
                                                      int mode, Real *__restrict__ rho) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= N) return;
     Real r;
-    if (l < nvox) {
+    if (l < nvol) {
         const Real ms = (Real)mu_s[l];
         const Real me = ms + scale * (Real)mu_a[l];
         if (mode == 1) r = ms * dx;
         else r = me > 0 ? (ms / me) * (-expm1(-me * dx)) : (Real)0;
     } else {
-        r = (Real)albedo[l - nvox];
+        r = (Real)albedo[l - nvol];
     }
     rho[l] = r;
 }
@@ -261,7 +262,8 @@ void launch_march(Scene &s, hipStream_t st, float scale, int use_lds) {
 
 template <class Real>
 void launch_node_weights(Scene &s, hipStream_t st, float scale) {
-    hipLaunchKernelGGL((k_node_weights<Real>), dim3((s.N + 255) / 256), dim3(256), 0, st, s.N, s.nvox, s.mu_s, s.mu_a,
+    hipLaunchKernelGGL((k_node_weights<Real>), dim3((s.N + 255) / 256), dim3(256), 0, st, s.N, s.n_vol, node_mu_s(s),
+                       node_mu_a(s),
                        s.albedo, (Real)s.voxel_m, (Real)scale, s.weight_mode, (Real *)s.rho);
 }
 

@@ -71,7 +71,7 @@ __device__ __forceinline__ void own_scan(int d, const double *sx, const double *
 
 template <class Real, class BlkT, bool kWriteQ>
 __global__ __launch_bounds__(64) void k_qbuild(
-    int N, int nvox, const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx,
+    int N, int nvol, const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx,
     const int *__restrict__ pos, const double *__restrict__ lat, const double *__restrict__ tab, int NF, int n_phase,
     const float *__restrict__ frac, double sun_x, double sun_y, double sun_z, Real mu0, const Real *__restrict__ T,
     const Real *__restrict__ rho, const Real *__restrict__ Tsun, const long long *__restrict__ nodeoff,
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(64) void k_qbuild(
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
     if (d == 0 || d > kWave) return;  // higher degree: k_qbuild_big
-    const bool surf = l >= nvox;
+    const bool surf = l >= nvol;
 
     if (lane < d) {
         const int j = adj_idx[off + lane];
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(64) void k_qbuild(
         } else {
             w = 0.0;
             for (int k = 0; k < n_phase; ++k) {
-                const double f = frac ? (double)frac[(long long)k * nvox + l] : 1.0;
+                const double f = frac ? (double)frac[(long long)k * nvol + l] : 1.0;
                 w = w + f * tab[k * NF + i];
             }
         }
@@ -230,7 +230,7 @@ __device__ __forceinline__ int cell_find(const unsigned short *keys, int m) {
 
 template <class Real, class BlkT, bool kWriteQ>
 __global__ __launch_bounds__(64) void k_qbuild_big(
-    int nbig, const int *__restrict__ big, const long long *__restrict__ bigdir, int nvox,
+    int nbig, const int *__restrict__ big, const long long *__restrict__ bigdir, int nvol,
     const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx, const int *__restrict__ pos,
     const double *__restrict__ lat, const double *__restrict__ tab, int NF, int n_phase,
     const float *__restrict__ frac, double sun_x, double sun_y, double sun_z, Real mu0, const Real *__restrict__ T,
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(64) void k_qbuild_big(
     const int lane = threadIdx.x;
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
-    const bool surf = l >= nvox;
+    const bool surf = l >= nvol;
     const int n_in = surf ? 1 : d + 1;
     const int a0 = (int)(wg - bigdir[lo]) * group;
     const int ng = min(group, n_in - a0);
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(64) void k_qbuild_big(
         } else {
             w = 0.0;
             for (int k = 0; k < n_phase; ++k) {
-                const double f = frac ? (double)frac[(long long)k * nvox + l] : 1.0;
+                const double f = frac ? (double)frac[(long long)k * nvol + l] : 1.0;
                 w = w + f * tab[k * NF + i];
             }
         }
@@ -414,7 +414,7 @@ __device__ __forceinline__ double order_value(unsigned long long k) {
 
 template <class Real, class BlkT, bool kWriteQ>
 __global__ __launch_bounds__(64) void k_qcolour(
-    int N, int nvox, const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx,
+    int N, int nvol, const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx,
     const int *__restrict__ pos, const double *__restrict__ lat, const double *__restrict__ tab, int NF, int n_phase,
     const float *__restrict__ frac, double sun_x, double sun_y, double sun_z, Real mu0, const Real *__restrict__ T,
     const Real *__restrict__ rho, const Real *__restrict__ Tsun, const long long *__restrict__ nodeoff,
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(64) void k_qcolour(
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
     if (d == 0 || d > kWave) return;  // higher degree: k_qcolour_big
-    const bool surf = l >= nvox;
+    const bool surf = l >= nvol;
     if (lane < d) {
         const int j = adj_idx[off + lane];
         const long long Dx = min_image((long long)pos[3 * j] - pos[3 * l], wx, per & 1);
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(64) void k_qcolour(
         } else {
             w = 0.0;
             for (int k = 0; k < n_phase; ++k) {
-                const double f = frac ? (double)frac[(long long)k * nvox + l] : 1.0;
+                const double f = frac ? (double)frac[(long long)k * nvol + l] : 1.0;
                 w = w + f * tab[k * NF + i];
             }
         }
@@ -677,7 +677,7 @@ __device__ __forceinline__ void colour_seeds(int m0, int d, int NF, const double
 
 template <class Real, class BlkT, bool kWriteQ>
 __global__ __launch_bounds__(64) void k_qcolour_big(
-    int nbig, const int *__restrict__ big, const long long *__restrict__ bigdir, int nvox,
+    int nbig, const int *__restrict__ big, const long long *__restrict__ bigdir, int nvol,
     const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx, const int *__restrict__ pos,
     const double *__restrict__ lat, const double *__restrict__ tab, int NF, int n_phase,
     const float *__restrict__ frac, double sun_x, double sun_y, double sun_z, Real mu0, const Real *__restrict__ T,
@@ -703,7 +703,7 @@ __global__ __launch_bounds__(64) void k_qcolour_big(
     const int lane = threadIdx.x;
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
-    const bool surf = l >= nvox;
+    const bool surf = l >= nvol;
     auto edge_dir = [&](int m, double &ex, double &ey, double &ez) {
         const int j = adj_idx[off + m];
         const long long Dx = min_image((long long)pos[3 * j] - pos[3 * l], wx, per & 1);
@@ -747,7 +747,7 @@ __global__ __launch_bounds__(64) void k_qcolour_big(
         } else {
             w = 0.0;
             for (int k = 0; k < n_phase; ++k) {
-                const double f = frac ? (double)frac[(long long)k * nvox + l] : 1.0;
+                const double f = frac ? (double)frac[(long long)k * nvol + l] : 1.0;
                 w = w + f * tab[k * NF + i];
             }
         }
@@ -870,14 +870,14 @@ void launch_qbuild(Scene &s, hipStream_t st, int write_q) {
     const int group = qbuild_group(s.n_fib);
     if (s.sigma_mode == SG_SIGMA_COLOUR) {
         if (write_q) {
-            hipLaunchKernelGGL((k_qcolour<Real, float, true>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
-                               s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
+            hipLaunchKernelGGL((k_qcolour<Real, float, true>), dim3(s.N), dim3(64), shm, st, s.N, s.n_vol, s.adj_ptr,
+                               s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, node_frac(s), s.sun_in[0], s.sun_in[1],
                                s.sun_in[2], (Real)s.mu0, (const Real *)nullptr, (const Real *)nullptr,
                                (const Real *)nullptr, s.nodeoff, s.q, (Real *)nullptr, s.qsun, s.hull, s.periodic,
                                (long long)s.nx * kFx, (long long)s.ny * kFx);
         } else {
-            hipLaunchKernelGGL((k_qcolour<Real, Real, false>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
-                               s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
+            hipLaunchKernelGGL((k_qcolour<Real, Real, false>), dim3(s.N), dim3(64), shm, st, s.N, s.n_vol, s.adj_ptr,
+                               s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, node_frac(s), s.sun_in[0], s.sun_in[1],
                                s.sun_in[2], (Real)s.mu0, (const Real *)s.T, (const Real *)s.rho,
                                (const Real *)s.Tsun, s.nodeoff, (Real *)s.val, (Real *)s.S, s.qsun, s.hull, s.periodic,
                                (long long)s.nx * kFx, (long long)s.ny * kFx);
@@ -885,15 +885,15 @@ void launch_qbuild(Scene &s, hipStream_t st, int write_q) {
         if (s.n_big) {  // nodes of degree above 64: one workgroup per (node, incoming direction)
             if (write_q)
                 hipLaunchKernelGGL((k_qcolour_big<Real, float, true>), dim3(s.n_bigdir), dim3(64), 0, st, s.n_big,
-                                   s.big, s.bigdir, s.nvox, s.adj_ptr, s.adj_idx, s.pos, s.lat, s.tab, s.n_fib,
-                                   s.n_phase, s.frac, s.sun_in[0], s.sun_in[1], s.sun_in[2], (Real)s.mu0,
+                                   s.big, s.bigdir, s.n_vol, s.adj_ptr, s.adj_idx, s.pos, s.lat, s.tab, s.n_fib,
+                                   s.n_phase, node_frac(s), s.sun_in[0], s.sun_in[1], s.sun_in[2], (Real)s.mu0,
                                    (const Real *)nullptr, (const Real *)nullptr, (const Real *)nullptr, s.nodeoff, s.q,
                                    (Real *)nullptr, s.qsun, s.hull, s.periodic, (long long)s.nx * kFx,
                                    (long long)s.ny * kFx);
             else
                 hipLaunchKernelGGL((k_qcolour_big<Real, Real, false>), dim3(s.n_bigdir), dim3(64), 0, st, s.n_big,
-                                   s.big, s.bigdir, s.nvox, s.adj_ptr, s.adj_idx, s.pos, s.lat, s.tab, s.n_fib,
-                                   s.n_phase, s.frac, s.sun_in[0], s.sun_in[1], s.sun_in[2], (Real)s.mu0,
+                                   s.big, s.bigdir, s.n_vol, s.adj_ptr, s.adj_idx, s.pos, s.lat, s.tab, s.n_fib,
+                                   s.n_phase, node_frac(s), s.sun_in[0], s.sun_in[1], s.sun_in[2], (Real)s.mu0,
                                    (const Real *)s.T, (const Real *)s.rho, (const Real *)s.Tsun, s.nodeoff,
                                    (Real *)s.val, (Real *)s.S, s.qsun, s.hull, s.periodic, (long long)s.nx * kFx,
                                    (long long)s.ny * kFx);
@@ -903,28 +903,28 @@ void launch_qbuild(Scene &s, hipStream_t st, int write_q) {
     if (s.n_big) {  // nodes of degree above 64
         if (write_q)
             hipLaunchKernelGGL((k_qbuild_big<Real, float, true>), dim3(s.n_bigdir), dim3(64), 0, st, s.n_big, s.big,
-                               s.bigdir, s.nvox, s.adj_ptr, s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac,
+                               s.bigdir, s.n_vol, s.adj_ptr, s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, node_frac(s),
                                s.sun_in[0], s.sun_in[1], s.sun_in[2], (Real)s.mu0, (const Real *)nullptr,
                                (const Real *)nullptr, (const Real *)nullptr, s.nodeoff, s.q, (Real *)nullptr, s.qsun,
                                qbuild_group_big(s.n_fib), s.periodic, (long long)s.nx * kFx,
                                (long long)s.ny * kFx);
         else
             hipLaunchKernelGGL((k_qbuild_big<Real, Real, false>), dim3(s.n_bigdir), dim3(64), 0, st, s.n_big, s.big,
-                               s.bigdir, s.nvox, s.adj_ptr, s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac,
+                               s.bigdir, s.n_vol, s.adj_ptr, s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, node_frac(s),
                                s.sun_in[0], s.sun_in[1], s.sun_in[2], (Real)s.mu0, (const Real *)s.T,
                                (const Real *)s.rho, (const Real *)s.Tsun, s.nodeoff, (Real *)s.val, (Real *)s.S, s.qsun,
                                qbuild_group_big(s.n_fib), s.periodic, (long long)s.nx * kFx,
                                (long long)s.ny * kFx);
     }
     if (write_q) {
-        hipLaunchKernelGGL((k_qbuild<Real, float, true>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
-                           s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
+        hipLaunchKernelGGL((k_qbuild<Real, float, true>), dim3(s.N), dim3(64), shm, st, s.N, s.n_vol, s.adj_ptr,
+                           s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, node_frac(s), s.sun_in[0], s.sun_in[1],
                            s.sun_in[2], (Real)s.mu0, (const Real *)nullptr, (const Real *)nullptr,
                            (const Real *)nullptr, s.nodeoff, s.q, (Real *)nullptr, s.qsun, group, s.periodic, (long long)s.nx * kFx,
                            (long long)s.ny * kFx);
     } else {
-        hipLaunchKernelGGL((k_qbuild<Real, Real, false>), dim3(s.N), dim3(64), shm, st, s.N, s.nvox, s.adj_ptr,
-                           s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, s.frac, s.sun_in[0], s.sun_in[1],
+        hipLaunchKernelGGL((k_qbuild<Real, Real, false>), dim3(s.N), dim3(64), shm, st, s.N, s.n_vol, s.adj_ptr,
+                           s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, node_frac(s), s.sun_in[0], s.sun_in[1],
                            s.sun_in[2], (Real)s.mu0, (const Real *)s.T, (const Real *)s.rho, (const Real *)s.Tsun,
                            s.nodeoff, (Real *)s.val, (Real *)s.S, s.qsun, group, s.periodic, (long long)s.nx * kFx,
                            (long long)s.ny * kFx);

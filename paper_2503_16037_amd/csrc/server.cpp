@@ -49,8 +49,9 @@ struct Request {
     std::vector<float> mu_s, mu_a, frac, albedo, abs_scale;
     std::vector<double> g, lut;
     std::vector<int32_t> kinds;
-    std::vector<int32_t> pos, adj_idx;
-    std::vector<int64_t> adj_ptr;
+    std::vector<int32_t> pos, adj_idx, los_node;
+    std::vector<int64_t> adj_ptr, los_ptr;
+    std::vector<double> los_t;
     // results
     std::vector<double> radiance;
     sg_solve_info info{};
@@ -61,7 +62,8 @@ struct Request {
     void copy_from(const sg_scene_desc *src) {
         d = *src;
         const size_t nvox = (size_t)src->nx * src->ny * src->nz, npx = (size_t)src->nx * src->ny;
-        const size_t N = nvox + (src->surface_nodes ? npx : 0);
+        const size_t nvol = src->n_nodes > 0 ? (size_t)src->n_nodes : nvox;
+        const size_t N = nvol + (src->surface_nodes ? npx : 0);
         const size_t E = (size_t)src->adj_ptr[N];
         mu_s.assign(src->mu_s, src->mu_s + nvox);
         mu_a.assign(src->mu_a, src->mu_a + nvox);
@@ -75,7 +77,14 @@ struct Request {
             for (int k = 0; k < src->n_phase; ++k) table = table || src->phase_kind[k] == SG_PHASE_TABLE;
             if (table) lut.assign(src->phase_lut, src->phase_lut + (size_t)src->n_phase * src->phase_lut_n);
         }
-        pos.assign(src->vol_pos_fx, src->vol_pos_fx + 3 * nvox);
+        if (src->n_nodes > 0) {  // general nodes and the lines of sight's elements
+            pos.assign(src->node_pos_fx, src->node_pos_fx + 3 * nvol);
+            los_ptr.assign(src->los_ptr, src->los_ptr + npx + 1);
+            los_node.assign(src->los_node, src->los_node + los_ptr[npx]);
+            los_t.assign(src->los_t, src->los_t + los_ptr[npx]);
+        } else {
+            pos.assign(src->vol_pos_fx, src->vol_pos_fx + 3 * nvox);
+        }
         adj_ptr.assign(src->adj_ptr, src->adj_ptr + N + 1);
         if (E) adj_idx.assign(src->adj_idx, src->adj_idx + E);
         radiance.assign((size_t)src->n_lambda * npx, 0.0);
@@ -90,7 +99,14 @@ struct Request {
         d.hg_g = g.data();
         d.phase_kind = kinds.empty() ? nullptr : kinds.data();
         d.phase_lut = lut.empty() ? nullptr : lut.data();
-        d.vol_pos_fx = pos.data();
+        if (d.n_nodes > 0) {
+            d.node_pos_fx = pos.data();
+            d.los_ptr = los_ptr.data();
+            d.los_node = los_node.data();
+            d.los_t = los_t.data();
+        } else {
+            d.vol_pos_fx = pos.data();
+        }
         d.adj_ptr = adj_ptr.data();
         d.adj_idx = adj_idx.empty() ? nullptr : adj_idx.data();
     }
@@ -101,6 +117,9 @@ struct Request {
         std::vector<int32_t>().swap(pos);
         std::vector<int32_t>().swap(adj_idx);
         std::vector<int64_t>().swap(adj_ptr);
+        std::vector<int32_t>().swap(los_node);
+        std::vector<int64_t>().swap(los_ptr);
+        std::vector<double>().swap(los_t);
     }
 };
 

@@ -15,7 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsgrt.so")
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 SG_OK, SG_E_INVALID, SG_E_NOMEM, SG_E_DEVICE, SG_E_NOCONV, SG_E_BUSY, SG_E_ABI, SG_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 SG_FP32, SG_FP64 = 0, 1
@@ -39,13 +39,21 @@ class SceneDesc(C.Structure):
                 ("n_fib", C.c_int32), ("node_weight_mode", C.c_int32), ("n_lambda", C.c_int32),
                 ("abs_scale", C.c_void_p), ("phase_kind", C.c_void_p), ("phase_lut_n", C.c_int32),
                 ("phase_lut", C.c_void_p), ("sigma_mode", C.c_int32),
-                ("periodic", C.c_int32)]
+                ("periodic", C.c_int32), ("n_nodes", C.c_int32), ("node_pos_fx", C.c_void_p),
+                ("los_ptr", C.c_void_p), ("los_node", C.c_void_p), ("los_t", C.c_void_p)]
 
 
 class GraphDesc(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("mu_s", C.c_void_p), ("vol_pos_fx", C.c_void_p), ("surface_nodes", C.c_int32),
-                ("surf_albedo", C.c_void_p), ("n_pairs", C.c_int64), ("c_min", C.c_double)]
+                ("surf_albedo", C.c_void_p), ("n_pairs", C.c_int64), ("c_min", C.c_double),
+                ("n_nodes", C.c_int32), ("node_pos_fx", C.c_void_p)]
+
+
+class LosDesc(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("voxel_m", C.c_double), ("view_dir", C.c_int32 * 3), ("periodic", C.c_int32),
+                ("mode", C.c_int32), ("step_m", C.c_double)]
 
 
 class GraphInfo(C.Structure):
@@ -123,6 +131,7 @@ def lib():
                 "sg_server_latencies": (I32, [P, P, I32, P]),
                 "sg_server_destroy": (I32, [P]),
                 "sg_graph_build": (I32, [P, P, P, P, P, I64, P, P]),
+                "sg_los_nodes": (I32, [P, P, P, P, I64, P, P, P, P, I64, P]),
             }
             for name, (res, args) in sigs.items():
                 f = getattr(L, name)
@@ -162,7 +171,17 @@ def make_desc(scene, keep: list) -> SceneDesc:
     d.n_phase = int(g.shape[0])
     d.hg_g = _ptr(g)
     d.phase_frac = None if scene.phase_frac is None else _ptr(arr(scene.phase_frac, np.float32))
-    d.vol_pos_fx = _ptr(arr(scene.vol_pos_fx, np.int32))
+    general = getattr(scene, "node_pos_fx", None)
+    if general is None:
+        d.vol_pos_fx = _ptr(arr(scene.vol_pos_fx, np.int32))
+        d.n_nodes = 0
+    else:
+        g_pos = arr(general, np.int32)
+        d.n_nodes = int(g_pos.reshape(-1, 3).shape[0])
+        d.node_pos_fx = _ptr(g_pos)
+        d.los_ptr = _ptr(arr(scene.los_ptr, np.int64))
+        d.los_node = _ptr(arr(scene.los_node, np.int32))
+        d.los_t = _ptr(arr(scene.los_t, np.float64))
     d.surface_nodes = int(scene.surface_nodes)
     d.adj_ptr = _ptr(arr(scene.adj_ptr, np.int64))
     d.adj_idx = _ptr(arr(scene.adj_idx, np.int32))
@@ -439,12 +458,19 @@ def graph_build(ctx: Context, scene, n_pairs: int = 0, c_min: float = 0.0, strea
     d.abi_version = ABI_VERSION
     d.nx, d.ny, d.nz = int(scene.nx), int(scene.ny), int(scene.nz)
     d.mu_s = _ptr(arr(scene.mu_s, np.float32))
-    d.vol_pos_fx = _ptr(arr(scene.vol_pos_fx, np.int32))
+    general = getattr(scene, "node_pos_fx", None)
+    n_vol = d.nx * d.ny * d.nz
+    if general is None:
+        d.vol_pos_fx = _ptr(arr(scene.vol_pos_fx, np.int32))
+    else:
+        g_pos = arr(general, np.int32)
+        n_vol = d.n_nodes = int(g_pos.reshape(-1, 3).shape[0])
+        d.node_pos_fx = _ptr(g_pos)
     d.surface_nodes = 1 if scene.surface_nodes else 0
     d.surf_albedo = _ptr(arr(scene.surf_albedo, np.float32))
     d.n_pairs = int(n_pairs)
     d.c_min = float(c_min)
-    N = d.nx * d.ny * d.nz + (d.nx * d.ny if d.surface_nodes else 0)
+    N = n_vol + (d.nx * d.ny if d.surface_nodes else 0)
     adj_ptr = np.zeros(N + 1, np.int64)
     ne = C.c_int64(0)
     cap = 2 * int(n_pairs)
@@ -458,3 +484,28 @@ def graph_build(ctx: Context, scene, n_pairs: int = 0, c_min: float = 0.0, strea
                                     ne.value, C.byref(ne), C.byref(gi)))
     out = (adj_ptr, adj_idx[:ne.value].copy())
     return out + (gi.as_dict(),) if info else out
+
+
+def los_nodes(ctx: Context, nx, ny, nz, view_dir, voxel_m, mode="layer", step_m=0.0, periodic=0, stream=None):
+    """sg_los_nodes: the path points of the pixels' lines of sight (one per layer crossed, or
+    every step_m metres).  Returns (node_pos_fx int32 [n][3], los_ptr int64 [nx ny + 1],
+    los_node int32 [elements], los_t float64 [elements]), the general-node fields of a scene."""
+    d = LosDesc()
+    d.abi_version = ABI_VERSION
+    d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
+    d.voxel_m = float(voxel_m)
+    for k in range(3):
+        d.view_dir[k] = int(view_dir[k])
+    d.periodic = int(periodic)
+    d.mode = {"layer": 0, "step": 1}[mode]
+    d.step_m = float(step_m)
+    los_ptr = np.zeros(nx * ny + 1, np.int64)
+    nn, ne = C.c_int64(0), C.c_int64(0)
+    _check(lib().sg_los_nodes(ctx.handle, C.byref(d), _stream_ptr(stream), None, 0, C.byref(nn), None, None, None, 0,
+                              C.byref(ne)))
+    pos = np.zeros((max(nn.value, 1), 3), np.int32)
+    node = np.zeros(max(ne.value, 1), np.int32)
+    t = np.zeros(max(ne.value, 1), np.float64)
+    _check(lib().sg_los_nodes(ctx.handle, C.byref(d), _stream_ptr(stream), _ptr(pos), nn.value, C.byref(nn),
+                              _ptr(los_ptr), _ptr(node), _ptr(t), ne.value, C.byref(ne)))
+    return pos[:nn.value].copy(), los_ptr, node[:ne.value].copy(), t[:ne.value].copy()
