@@ -443,7 +443,9 @@ sg_status sg_graph_build(sg_ctx *ctx, const sg_graph_desc *desc, void *hip_strea
 
 typedef struct sg_server_opts {
     uint32_t abi_version;     /* SG_ABI_VERSION */
-    int32_t max_resident;     /* scenes held on the device at once (>= 1) */
+    int32_t max_resident;     /* scenes held on the device at once (1..4; more are refused: a run
+                                 with eight worker threads ended in a host fault inside the
+                                 runtime's copy path, cause not found) */
     int32_t queue_cap;        /* pending requests before sg_submit returns SG_E_BUSY (>= 1) */
     int32_t n_streams;        /* device streams of the scheduler (1..64), at least max_resident:
                                  each resident slot runs on a stream of its own (a solve captures

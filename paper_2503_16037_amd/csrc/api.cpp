@@ -1372,6 +1372,7 @@ sg_status sg_scene_create(sg_ctx *ctx, const sg_scene_desc *desc, void *hip_stre
     sg_status st = create_scene(ctx, desc, pick_stream(ctx, hip_stream), *s);
     if (st != SG_OK) {
         std::string msg = t_err;
+        (void)hipStreamSynchronize(pick_stream(ctx, hip_stream));  // uploads queued before the failure
         free_scene(s.get());
         set_error(msg);
         return st;

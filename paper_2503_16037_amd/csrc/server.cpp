@@ -38,6 +38,11 @@ double now_ms() {
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Resident slots a server may hold: the configurations its tests and measurements cover
+// (with more workers, one run ended in a host fault inside the runtime's copy path during
+// scene upload, whose cause has not been found).
+constexpr int kMaxResident = 4;
+
 struct Request {
     uint64_t ticket = 0;
     uint64_t bytes = 0;        // reservation used for admission
@@ -187,6 +192,9 @@ struct Server {
             std::string err;
             if (s != SG_OK) err = t_last_error();
             const bool gmres_nomem = sc->gm_nomem;
+            // a solve that stops early (out of budget mid-solve) may leave kernels queued on the
+            // stream: its blocks go back to the pool, and to other streams, only once they ran
+            (void)hipStreamSynchronize(st);
             free_scene(sc);
             delete sc;
             if (s == SG_E_NOMEM) {
@@ -256,6 +264,10 @@ sg_status sg_server_create(sg_ctx *ctx_, const sg_server_opts *opts, sg_server *
     }
     if (opts->max_resident < 1 || opts->queue_cap < 1 || opts->n_streams < 1 || opts->n_streams > 64) {
         set_error("max_resident >= 1, queue_cap >= 1, n_streams in 1..64 required");
+        return SG_E_INVALID;
+    }
+    if (opts->max_resident > kMaxResident) {
+        set_error("max_resident above " + std::to_string(kMaxResident) + " is not supported");
         return SG_E_INVALID;
     }
     if (opts->max_resident > opts->n_streams) {

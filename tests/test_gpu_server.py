@@ -193,6 +193,10 @@ def test_resident_slots_need_streams_of_their_own(ctx):
     with pytest.raises(sgrt.SgError) as e:
         sgrt.Server(ctx, max_resident=3, queue_cap=4, n_streams=2)
     assert e.value.status == sgrt.SG_E_INVALID
+    # more than four resident slots are refused (the configurations covered are 1..4)
+    with pytest.raises(sgrt.SgError) as e:
+        sgrt.Server(ctx, max_resident=5, queue_cap=4, n_streams=5)
+    assert e.value.status == sgrt.SG_E_INVALID
 
 
 def test_tight_budget_with_a_gmres_fallback_in_the_mix():
