@@ -210,7 +210,10 @@ typedef struct sg_solve_opts {
     uint32_t abi_version;  /* SG_ABI_VERSION */
     int32_t precision;     /* SG_FP32: march, matrix and sweeps in FP32, residual and pixel
                               accumulation in FP64; SG_FP64: everything in FP64 */
-    int32_t solver;        /* SG_SOLVER_AUTO: Neumann sweeps, GMRES if they stall */
+    int32_t solver;        /* SG_SOLVER_AUTO: Neumann sweeps, GMRES if they stall, overflow or do
+                              not reach rtol (in a batched scene each wavelength still above
+                              rtol gets its own FP64 GMRES with the sweeps left of max_sweeps);
+                              SG_SOLVER_GMRES: GMRES from zero (per wavelength when batched) */
     double rtol;           /* target of the per-edge relative residual max_e |r_e| / (|phi_e| + 1e-30),
                               r = S - (I - K) phi in FP64; it bounds the error of every edge,
                               including edges many orders of magnitude darker than the mean

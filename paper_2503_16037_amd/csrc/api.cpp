@@ -573,40 +573,49 @@ sg_status neumann(Scene &s, hipStream_t st, Exec &tm, const Real *rhs, Real *&xa
     return SG_OK;
 }
 
-template <class Real>
-sg_status gmres64(Scene &s, hipStream_t st, Exec &tm, const Real *S, double rtol, int m, int max_sweeps,
-                  SolveStats &ss) {
+// GMRES basis of a scene: m + 1 Krylov vectors of E doubles; a batched scene also holds one
+// wavelength's iterate and residual there (two more)
+size_t gmres_len(const Scene &s, int m) { return (size_t)(m + 1 + (s.n_lambda > 1 ? 2 : 0)) * (size_t)s.E; }
+
+sg_status gmres_basis(Scene &s, int m) {
     Ctx *ctx = s.ctx;
-    const int64_t E = s.E;
-    if (!s.gm_V || s.gm_m < m) {
-        if (s.gm_V) {
-            pool_free(ctx, s.gm_V);
-            s.bytes -= pool_round((size_t)(s.gm_m + 1) * E * sizeof(double));
-            s.gm_V = nullptr;
-        }
-        const sg_status st_v = dalloc(s, &s.gm_V, (size_t)(m + 1) * E);
-        s.gm_nomem = st_v == SG_E_NOMEM;
-        if (st_v != SG_OK) return st_v;
-        s.gm_m = m;
+    if (s.gm_V && s.gm_m >= m) return SG_OK;
+    if (s.gm_V) {
+        pool_free(ctx, s.gm_V);
+        s.bytes -= pool_round(gmres_len(s, s.gm_m) * sizeof(double));
+        s.gm_V = nullptr;
     }
+    const sg_status st_v = dalloc(s, &s.gm_V, gmres_len(s, m));
+    s.gm_nomem = st_v == SG_E_NOMEM;
+    if (st_v != SG_OK) return st_v;
+    s.gm_m = m;
+    return SG_OK;
+}
+
+// Restarted GMRES(m) in FP64 on (I - K) x = S for one right-hand side of length E: x is the
+// iterate (updated in place), r its residual, V the m + 1 basis vectors.  residual(m2)
+// computes r = S - (I - K) x and reads its measures (sum |r|, max |r| / (|x| + floor));
+// apply(v, w) computes w = (I - K) v.  Stops at max |r| / |x| <= rtol or after max_sweeps.
+template <class Residual, class Apply>
+sg_status gmres_core(Scene &s, hipStream_t st, double rtol, int m, int max_sweeps, int64_t E, double *x, double *r,
+                     double *V, Residual residual, Apply apply, SolveStats &ss) {
+    Ctx *ctx = s.ctx;
     ss.gmres_used = 1;
     const int nbv = 1024;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), yv(m), h(m + 1), h2(m + 1);
-    double *V = s.gm_V;
     while (true) {
-        launch_residual64<Real>(s, st, S, s.x64, s.r64, s.scal);
+        double m2[2];
+        SG_TRY(residual(m2));
         ++ss.sweeps;
         ++ss.refinements;
-        double m2[2];
-        SG_TRY(read_scalars(s, st, s.scal, m2, 2));
         ss.rel = std::isfinite(m2[0]) ? m2[1] : HUGE_VAL;  // max over edges of |r| / |x|
         if (ss.rel <= rtol || ss.sweeps >= max_sweeps) break;
-        launch_dot_multi(s.r64, E, 1, s.r64, E, s.partial, nbv, s.scal, st);
+        launch_dot_multi(r, E, 1, r, E, s.partial, nbv, s.scal, st);
         double beta2;
         SG_TRY(read_scalars(s, st, s.scal, &beta2, 1));
         const double beta = std::sqrt(beta2);
         if (!std::isfinite(beta)) break;  // a non-finite iterate: reported as not converged
-        SG_HIP(hipMemcpyAsync(V, s.r64, sizeof(double) * E, hipMemcpyDeviceToDevice, st));
+        SG_HIP(hipMemcpyAsync(V, r, sizeof(double) * E, hipMemcpyDeviceToDevice, st));
         launch_scale64(V, 1.0 / beta, E, st);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
@@ -614,7 +623,7 @@ sg_status gmres64(Scene &s, hipStream_t st, Exec &tm, const Real *S, double rtol
         bool bad = false;  // a non-finite Krylov vector (e.g. K holds infinities): stop after this cycle
         for (; k < m && ss.sweeps < max_sweeps; ++k) {
             double *vk = V + (size_t)k * E, *w = V + (size_t)(k + 1) * E;
-            launch_apply_imk64<Real>(s, st, vk, w);
+            apply(vk, w);
             ++ss.sweeps;
             // classical Gram-Schmidt, twice
             launch_dot_multi(V, E, k + 1, w, E, s.partial, nbv, s.scal, st);
@@ -654,15 +663,66 @@ sg_status gmres64(Scene &s, hipStream_t st, Exec &tm, const Real *S, double rtol
             for (int q = j + 1; q < k; ++q) acc -= H[(size_t)j * m + q] * yv[q];
             yv[j] = acc / H[(size_t)j * m + j];
         }
-        // x64 += V y  (axpy_multi subtracts, so pass -y)
+        // x += V y  (axpy_multi subtracts, so pass -y)
         std::vector<double> ny(k);
         for (int j = 0; j < k; ++j) ny[j] = -yv[j];
         SG_HIP(hipMemcpyAsync(s.scal + 64, ny.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
-        launch_axpy_multi(s.x64, V, E, k, s.scal + 64, E, st);
+        launch_axpy_multi(x, V, E, k, s.scal + 64, E, st);
         SG_HIP(hipStreamSynchronize(st));
         if (bad) break;
     }
     ss.converged = ss.rel <= rtol;
+    return SG_OK;
+}
+
+template <class Real>
+sg_status gmres64(Scene &s, hipStream_t st, Exec &tm, const Real *S, double rtol, int m, int max_sweeps,
+                  SolveStats &ss) {
+    (void)tm;
+    SG_TRY(gmres_basis(s, m));
+    return gmres_core(
+        s, st, rtol, m, max_sweeps, s.E, s.x64, s.r64, s.gm_V,
+        [&](double *m2) {
+            launch_residual64<Real>(s, st, S, s.x64, s.r64, s.scal);
+            return read_scalars(s, st, s.scal, m2, 2);
+        },
+        [&](const double *v, double *w) { launch_apply_imk64<Real>(s, st, v, w); }, ss);
+}
+
+// GMRES fallback of a batched scene: each wavelength whose relative residual rel[k] is above
+// rtol is solved on its own, in FP64 with the batched matrix at that wavelength, from its
+// current iterate (from zero when that iterate is not finite); rel[k] is updated.  Each
+// wavelength gets its own budget of max_sweeps.
+sg_status gmres_batched(Scene &s, hipStream_t st, double rtol, int m, int max_sweeps, std::vector<double> &rel,
+                        SolveStats &ss) {
+    const int nl = s.n_lambda;
+    const int64_t E = s.E;
+    SG_TRY(gmres_basis(s, m));
+    double *V = s.gm_V, *xl = s.gm_V + (size_t)(m + 1) * E, *rl = xl + E;
+    bool all = true;
+    for (int k = 0; k < nl; ++k) {
+        if (rel[k] <= rtol) continue;
+        if (std::isfinite(rel[k])) launch_lam_take64(s.x64, nl, k, E, xl, st);
+        else launch_fill<double>(xl, 0.0, E, st);
+        SolveStats ls;
+        SG_TRY(gmres_core(
+            s, st, rtol, m, max_sweeps, E, xl, rl, V,
+            [&](double *m2) {
+                launch_blam_residual64(s, st, k, xl, rl);
+                return read_scalars(s, st, s.scal, m2, 2);
+            },
+            [&](const double *v, double *w) { launch_blam_apply64(s, st, k, v, w); }, ls));
+        launch_lam_put64(xl, nl, k, E, s.x64, st);
+        rel[k] = ls.rel;
+        ss.sweeps += ls.sweeps;
+        ss.refinements += ls.refinements;
+        all = all && ls.converged;
+        if (sg_log())
+            fprintf(stderr, "[sgrt] batched GMRES, wavelength %d: relative residual %.3e after %d sweeps\n", k, ls.rel,
+                    ls.sweeps);
+    }
+    ss.gmres_used = 1;
+    ss.converged = all;
     return SG_OK;
 }
 
@@ -934,7 +994,7 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
     const long long n = (long long)s.E * nl;
     const double rtol = o.rtol > 0 ? o.rtol : 1e-6;
     const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 2000;
-    if (o.solver == SG_SOLVER_GMRES) return fail(SG_E_INVALID, "GMRES is available for single-wavelength scenes");
+    const int m = o.gmres_restart > 0 ? std::min(std::max(o.gmres_restart, 2), 64) : 32;
     if (o.lambda_tile > 0 && o.lambda_tile < 64 && o.lambda_tile < smallest_tile(nl))
         return fail(SG_E_INVALID, "lambda_tile " + std::to_string(o.lambda_tile) + " is narrower than the " +
                                       std::to_string(nl) + " wavelengths");
@@ -960,6 +1020,14 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
         }
         return SG_OK;
     };
+    if (o.solver == SG_SOLVER_GMRES) {  // every wavelength by GMRES from zero
+        launch_fill<double>(s.x64, 0.0, n, st);
+        std::vector<double> rel(nl, HUGE_VAL);
+        SG_TRY(gmres_batched(s, st, rtol, m, max_sweeps, rel, ss));
+        ss.rel = *std::max_element(rel.begin(), rel.end());
+        SG_HIP(hipGetLastError());
+        return SG_OK;
+    }
     bool warm = false, have_r = false;
     double worst = 0.0;
     if (o.warm_start) {  // kept if better than zero for every wavelength
@@ -988,6 +1056,21 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
                                ss, st2));
         launch_lam_axpy(s.x64, ca, d_sc, nl, n, st);
         if (st2) stalled = 1;
+    }
+    // a stall, an overflow or refinements that did not get there: the wavelengths still above
+    // rtol go to GMRES (each with the sweeps left of the budget)
+    const int left = max_sweeps - ss.sweeps;
+    if (!ss.converged && o.solver == SG_SOLVER_AUTO && left > 1) {
+        SG_TRY(residual(worst));
+        std::vector<double> rel(nl);
+        for (int k = 0; k < nl; ++k)
+            rel[k] = std::isfinite(m2[2 * k]) && std::isfinite(m2[2 * k + 1]) ? m2[2 * k + 1] : HUGE_VAL;
+        if (worst <= rtol) {
+            ss.converged = 1;
+        } else {
+            SG_TRY(gmres_batched(s, st, rtol, m, left, rel, ss));
+        }
+        ss.rel = *std::max_element(rel.begin(), rel.end());
     }
     SG_HIP(hipGetLastError());
     return SG_OK;
@@ -1041,6 +1124,7 @@ sg_status solve_batched(Scene &s, const sg_solve_opts &o, hipStream_t st, double
         info->converged = ss.converged;
         info->sweeps = ss.sweeps;
         info->refinements = ss.refinements;
+        info->gmres_used = ss.gmres_used;
         info->rel_residual = ss.rel;
         info->n_nodes = s.N;
         info->n_edges = s.E;
@@ -1491,13 +1575,12 @@ uint64_t reservations(const sg_scene_desc *d, const sg_solve_opts *o, bool with_
     }
     if (o) {  // what a solve with these options allocates beyond the scene's arrays
         if (o->build_col_idx) b += a(z, 4);
-        if (nl == 1) {
-            // FP64 solves trade the FP32 working arrays (released first) for FP64 ones
-            if (o->precision == SG_FP64) b += (a(e, 8) * 9 + a(n, 8) * 4 + a(z, 8)) - (a(e, 4) * 9 + a(n, 4) * 4 + a(z, 4));
-            if (with_gmres) {
-                const uint64_t m = o->gmres_restart > 0 ? (uint64_t)std::min(std::max(o->gmres_restart, 2), 64) : 32;
-                b += a((m + 1) * e, 8);
-            }
+        // FP64 solves trade the FP32 working arrays (released first) for FP64 ones
+        if (nl == 1 && o->precision == SG_FP64)
+            b += (a(e, 8) * 9 + a(n, 8) * 4 + a(z, 8)) - (a(e, 4) * 9 + a(n, 4) * 4 + a(z, 4));
+        if (with_gmres) {  // the basis; a batched scene adds one wavelength's iterate and residual
+            const uint64_t m = o->gmres_restart > 0 ? (uint64_t)std::min(std::max(o->gmres_restart, 2), 64) : 32;
+            b += a((m + 1 + (nl > 1 ? 2 : 0)) * e, 8);
         }
     }
     return b;

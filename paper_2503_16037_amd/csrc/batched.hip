@@ -348,6 +348,69 @@ __global__ __launch_bounds__(256) void k_spmm_pack(
     }
 }
 
+// One wavelength of a batched scene in FP64, for its GMRES fallback: one wavefront per node,
+// lane n = the node's row n (degree <= 64), columns summed in increasing order.  The matrix
+// is the batched sweep's at wavelength lam, K[b, a] = rho_l Q[b, a] T_a with T_a from the
+// same exp2 (so the fallback solves the system the batched residual measures).
+//   kResidual: r = S - v + K v with the node's measures (sum |r|, max |r| / (|v| + floor));
+//   otherwise: w = v - K v.
+template <bool kResidual>
+__global__ __launch_bounds__(256) void k_blam64(int N, int nl, int lam, float s, const long long *__restrict__ adj_ptr,
+                                               const long long *__restrict__ nodeoff, const int *__restrict__ rev,
+                                               const float *__restrict__ q, const float *__restrict__ qsun,
+                                               const float *__restrict__ tau_s, const float *__restrict__ tau_a,
+                                               const float *__restrict__ brho, const float *__restrict__ bsrc,
+                                               const double *__restrict__ v, double *__restrict__ w,
+                                               float2 *__restrict__ meas) {
+    const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (l >= N) return;
+    const long long off = adj_ptr[l];
+    const int d = (int)(adj_ptr[l + 1] - off);
+    if (d == 0) {
+        if (kResidual && lane == 0) meas[l] = make_float2(0.f, 0.f);
+        return;
+    }
+    const long long base = nodeoff[l];
+    const long long em = off + min(lane, d - 1);  // lane m: in-edge m's input
+    const double xin = (double)edge_T(tau_s[em], tau_a[em], s) * v[rev[em]];
+    const bool act = lane < d;
+    double acc = 0.0;
+    for (int m = 0; m < d; ++m) {
+        const double xm = __shfl(xin, m, 64);
+        if (act) acc += (double)q[base + (long long)m * d + lane] * xm;
+    }
+    double a = 0.0, u = 0.0;
+    if (act) {
+        const long long b = off + lane;
+        const float rlf = brho[(long long)l * nl + lam];
+        if (kResidual) {
+            const double Sb = (double)(rlf * bsrc[(long long)l * nl + lam] * qsun[b]);
+            const double rb = (Sb - v[b]) + (double)rlf * acc;
+            w[b] = rb;
+            a = fabs(rb);
+            u = keep_nan(a / (fabs(v[b]) + kRelFloor));
+        } else {
+            w[b] = v[b] - (double)rlf * acc;
+        }
+    }
+    if (kResidual) {
+        a = wave_sum(a);
+        u = wave_max(u);
+        if (lane == 0) meas[l] = make_float2((float)a, (float)u);
+    }
+}
+
+// one wavelength's slice of an edge-major [E][nl] vector, and back
+__global__ void k_lam_take64(const double *__restrict__ x, int nl, int lam, long long E, double *__restrict__ out) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e < E) out[e] = x[e * nl + lam];
+}
+__global__ void k_lam_put64(const double *__restrict__ in, int nl, int lam, long long E, double *__restrict__ x) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e < E) x[e * nl + lam] = in[e];
+}
+
 __global__ void k_lam_scale_f32(float *__restrict__ b, const double *__restrict__ sc, int nl, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         b[i] = (float)((double)b[i] * sc[i % nl]);
@@ -603,6 +666,27 @@ void launch_bfirst(Scene &s, hipStream_t st, const float *rhs, float *x) {
     dim3 gr((s.N + 3) / 4, (s.n_lambda + 63) / 64);
     hipLaunchKernelGGL(k_bfirst, gr, dim3(256), 0, st, s.N, s.n_lambda, s.adj_ptr, s.qsun, s.brho, s.bsrc, rhs, x,
                        s.meas);
+}
+
+void launch_blam_residual64(Scene &s, hipStream_t st, int lam, const double *x, double *r) {
+    hipLaunchKernelGGL(k_blam64<true>, dim3((s.N + 3) / 4), dim3(256), 0, st, s.N, s.n_lambda, lam, s.abs_scale[lam],
+                       s.adj_ptr, s.nodeoff, s.rev, s.q, s.qsun, (const float *)s.tau_s, (const float *)s.tau_a, s.brho,
+                       s.bsrc, x, r, s.meas);
+    launch_measures(s, 1, s.scal, st);
+}
+
+void launch_blam_apply64(Scene &s, hipStream_t st, int lam, const double *v, double *w) {
+    hipLaunchKernelGGL(k_blam64<false>, dim3((s.N + 3) / 4), dim3(256), 0, st, s.N, s.n_lambda, lam, s.abs_scale[lam],
+                       s.adj_ptr, s.nodeoff, s.rev, s.q, s.qsun, (const float *)s.tau_s, (const float *)s.tau_a, s.brho,
+                       s.bsrc, v, w, (float2 *)nullptr);
+}
+
+void launch_lam_take64(const double *x, int nl, int lam, long long E, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_lam_take64, dim3(grid_for(E)), dim3(256), 0, st, x, nl, lam, E, out);
+}
+
+void launch_lam_put64(const double *in, int nl, int lam, long long E, double *x, hipStream_t st) {
+    hipLaunchKernelGGL(k_lam_put64, dim3(grid_for(E)), dim3(256), 0, st, in, nl, lam, E, x);
 }
 
 void launch_lam_scale_f32(float *b, const double *sc, int nl, long long n, hipStream_t st) {

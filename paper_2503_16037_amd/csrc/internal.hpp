@@ -142,7 +142,7 @@ struct Scene {
 
     // FP64 solve state
     double *x64 = nullptr, *r64 = nullptr;  // [E * n_lambda]
-    double *gm_V = nullptr;                 // GMRES basis [(m+1) * E]
+    double *gm_V = nullptr;                 // GMRES basis [(m+1) * E] (+ [2 * E] in a batched scene)
     int gm_m = 0;
     bool gm_nomem = false;                  // the last solve ran out of budget allocating the basis
     double *partial = nullptr;  // block partial sums (GMRES dot products)
@@ -310,6 +310,12 @@ void launch_spmm(Scene &s, hipStream_t st, int grid, const float *rhs, const flo
 void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, float *r32);
 // b[e][lambda] *= sc[lambda] (FP32 values, FP64 scales)
 void launch_lam_scale_f32(float *b, const double *sc, int nl, long long n, hipStream_t st);
+// one wavelength of a batched scene in FP64 (its GMRES fallback): the residual r = S - (I - K) x
+// with its two measures in scal[0..1], w = (I - K) v, and one wavelength's slice of [E][nl]
+void launch_blam_residual64(Scene &s, hipStream_t st, int lam, const double *x, double *r);
+void launch_blam_apply64(Scene &s, hipStream_t st, int lam, const double *v, double *w);
+void launch_lam_take64(const double *x, int nl, int lam, long long E, double *out, hipStream_t st);
+void launch_lam_put64(const double *in, int nl, int lam, long long E, double *x, hipStream_t st);
 void launch_lam_axpy(double *x, const float *d, const double *sc, int nl, long long n, hipStream_t st);
 void launch_f32_to_64(const float *a, double *b, long long n, hipStream_t st);
 void launch_lam_to_edge_major(const double *src, double *dst, int nl, long long E, hipStream_t st);

@@ -146,3 +146,40 @@ def test_lambda_tile_rejected_when_invalid(ctx):
             assert e.value.status == sgrt.SG_E_INVALID
         rad, info = g.solve(lambda_tile=16)
         assert info["converged"] == 1
+
+
+def test_batched_gmres_forced(ctx):
+    """solver = GMRES on a batched scene: every wavelength by its own FP64 GMRES with the
+    batched matrix at that wavelength, from zero; each against the oracle and against the
+    batched Neumann solve."""
+    from paper_2503_16037_amd import sgrt
+    sc = scenes.make_batched(nx=10, ny=9, nz=6, n_lambda=5)
+    say("batched forced GMRES", sc.name)
+    with sgrt.Scene(ctx, sc) as g:
+        rad_n, _ = g.solve()
+        rad, info = g.solve(solver="gmres", gmres_restart=16)
+    assert info["converged"] == 1 and info["gmres_used"] == 1
+    assert info["rel_residual"] <= 1e-6
+    assert rel_err(rad, rad_n).max() < 2e-5
+    for k in range(sc.n_lambda):
+        ora = oracle.run(sc, abs_scale=float(sc.abs_scale[k]))
+        assert rel_err(rad[k], ora["radiance"]).max() < 1e-4, k
+
+
+def test_batched_gmres_fallback_on_divergent_series(ctx):
+    """The literal node weight on a tight cluster makes the batched Neumann series diverge at
+    every wavelength; the solve falls back to GMRES per wavelength and matches the oracle
+    (which solves the same systems by GMRES)."""
+    from paper_2503_16037_amd import sgrt
+    from test_oracle_matrix_solve import clustered_scene
+    sc = clustered_scene()
+    sc = sc.with_(abs_scale=np.array([0.3, 1.0, 3.0, 10.0], np.float32))
+    say("batched GMRES fallback", sc.name)
+    with sgrt.Scene(ctx, sc) as g:
+        rad, info = g.solve()
+    assert info["converged"] == 1 and info["gmres_used"] == 1
+    for k in range(sc.n_lambda):
+        ora = oracle.run(sc, abs_scale=float(sc.abs_scale[k]))
+        assert ora["solve"]["gmres"]
+        scale = np.abs(ora["radiance"]).max()
+        assert np.abs(rad[k] - ora["radiance"]).max() <= 1e-4 * scale, k
