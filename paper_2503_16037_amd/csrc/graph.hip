@@ -31,8 +31,10 @@
 // a volume node's partners are all nodes of higher id, and top-n requests go straight
 // to the streamed ranking of every pair.
 // The adjacency is assembled from the sorted directed pair codes (tail N + head).
-#include <hipcub/hipcub.hpp>
-
+// Scans, the evaluated-pair sum and the sorts are this file's own: a three-phase
+// exclusive scan, and a stable least-significant-digit radix sort (8-bit digits, one
+// wavefront per tile of 4096 keys, a key's rank among equal digits of its 64-key round
+// from eight ballots).
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -387,6 +389,144 @@ __global__ void k_graph_rowptr(long long N, long long E, const unsigned long lon
     ptr[l] = a;
 }
 
+// ---- scans, sums and sorts of the builder -----------------------------------------------
+
+constexpr int kScanItems = 8;                 // consecutive items per thread
+constexpr int kScanBlock = 256 * kScanItems;  // items per workgroup
+
+// exclusive prefix of v over the workgroup's 256 threads; total = the workgroup's sum
+template <class T>
+__device__ __forceinline__ T block_exclusive(T v, T *lds, T &total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const T y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[w] = x;
+    __syncthreads();
+    T before = 0;
+    total = 0;
+    for (int k = 0; k < 4; ++k) {
+        if (k < w) before += lds[k];
+        total += lds[k];
+    }
+    return before + x - v;
+}
+
+// pass 1: each workgroup's items scanned (exclusive, plus init), its total to tsum
+template <class T>
+__global__ __launch_bounds__(256) void k_scan_local(const T *__restrict__ in, T *__restrict__ out, long long n, T init,
+                                                    T *__restrict__ tsum) {
+    __shared__ T lds[4];
+    const long long i0 = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanItems;
+    T v[kScanItems];
+    T sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        v[j] = i0 + j < n ? in[i0 + j] : (T)0;
+        sum += v[j];
+    }
+    T total;
+    T ex = block_exclusive(sum, lds, total) + init;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        if (i0 + j < n) out[i0 + j] = ex;
+        ex += v[j];
+    }
+    if (tsum && threadIdx.x == 0) tsum[blockIdx.x] = total;
+}
+
+// pass 3: the workgroups' offsets added
+template <class T>
+__global__ void k_scan_add(T *__restrict__ out, long long n, const T *__restrict__ off) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) out[i] += off[i / kScanBlock];
+}
+
+// sum of n values, one atomic per workgroup (integer: the order does not matter)
+__global__ __launch_bounds__(256) void k_sum_u64(const unsigned long long *__restrict__ in, long long n,
+                                                 unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long lds[4];
+    unsigned long long v = 0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        v += in[i];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(out, lds[0] + lds[1] + lds[2] + lds[3]);
+}
+
+constexpr int kRsItems = 64;             // keys per lane in a tile
+constexpr int kRsTile = 64 * kRsItems;  // keys per tile (one wavefront)
+
+// digit counts of each tile, digit-major: hist[digit * ntiles + tile]
+__global__ __launch_bounds__(256) void k_rs_hist(const unsigned long long *__restrict__ keys, long long n, int bit,
+                                                 long long ntiles, unsigned *__restrict__ hist) {
+    __shared__ unsigned cnt[4][256];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long tile = (long long)blockIdx.x * 4 + w;
+    for (int d = lane; d < 256; d += 64) cnt[w][d] = 0u;
+    __syncthreads();
+    if (tile < ntiles) {
+        const long long base = tile * kRsTile;
+        for (int r = 0; r < kRsItems; ++r) {
+            const long long i = base + (long long)r * 64 + lane;
+            if (i < n) atomicAdd(&cnt[w][(unsigned)(keys[i] >> bit) & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    if (tile < ntiles)
+        for (int d = lane; d < 256; d += 64) hist[(long long)d * ntiles + tile] = cnt[w][d];
+}
+
+// Stable scatter by one digit: tile t's keys with digit d go to off[d * ntiles + t] onward,
+// in their order.  Round r of a tile holds keys base + 64 r + lane; a key's rank among the
+// round's keys with its digit comes from the ballots of the digit's eight bits, the running
+// count of each digit lives in the wavefront's LDS row.
+__global__ __launch_bounds__(256) void k_rs_scatter(const unsigned long long *__restrict__ kin,
+                                                    const unsigned long long *__restrict__ vin,
+                                                    unsigned long long *__restrict__ kout,
+                                                    unsigned long long *__restrict__ vout, long long n, int bit,
+                                                    long long ntiles, const unsigned *__restrict__ off) {
+    __shared__ unsigned run[4][256];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long tile = (long long)blockIdx.x * 4 + w;
+    const bool tv = tile < ntiles;
+    for (int d = lane; d < 256; d += 64) run[w][d] = tv ? off[(long long)d * ntiles + tile] : 0u;
+    __syncthreads();
+    if (!tv) return;  // no barrier below: each wavefront works on its own LDS row
+    const long long base = tile * kRsTile;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int r = 0; r < kRsItems; ++r) {
+        const long long i = base + (long long)r * 64 + lane;
+        const bool ok = i < n;
+        const unsigned long long k = ok ? kin[i] : 0ull;
+        const unsigned dg = (unsigned)(k >> bit) & 255u;
+        unsigned long long peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const unsigned long long m = __ballot(ok && ((dg >> b) & 1u));
+            peers &= ((dg >> b) & 1u) ? m : ~m;
+        }
+        const unsigned before = (unsigned)__popcll(peers & below);
+        const unsigned p = ok ? run[w][dg] + before : 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (ok && before == 0u) run[w][dg] = p + (unsigned)__popcll(peers);  // the digit's first lane
+        __builtin_amdgcn_wave_barrier();
+        if (ok) {
+            kout[p] = k;
+            if (vin) vout[p] = vin[i];
+        }
+    }
+}
+
+// descending doubles (all positive) as ascending integers, and back
+__global__ void k_desc_bits(unsigned long long *__restrict__ a, long long n) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) a[i] = ~a[i];
+}
+
 unsigned blocks_for(long long n, int threads) { return (unsigned)std::max<long long>(1, (n + threads - 1) / threads); }
 
 // ---- host driver ---------------------------------------------------------------------
@@ -450,11 +590,7 @@ struct Builder {
         hipLaunchKernelGGL(k_graph_boxes, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st, g, P, mu, t, n0, n, box,
                            cells);
         GHIP(hipGetLastError());
-        size_t tb = 0;
-        GHIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cells, coff, (int)n + 1, st));
-        unsigned char *tsp = nullptr;
-        GTRY(tmp.get(&tsp, tb));
-        GHIP(hipcub::DeviceScan::ExclusiveSum(tsp, tb, cells, coff, (int)n + 1, st));
+        GTRY(scan<unsigned long long>(cells, coff, n + 1, 0ull));
         unsigned long long T = 0;
         GHIP(hipMemcpyAsync(&T, coff + n, sizeof(T), hipMemcpyDeviceToHost, st));
         GHIP(hipStreamSynchronize(st));
@@ -475,18 +611,11 @@ struct Builder {
         if (e0) (void)hipEventRecord(e0->second, st);
         GHIP(hipGetLastError());
         // boff = have + exclusive sum of the workgroup counts; boff[nb] = the new total
-        size_t tb2 = 0;
-        GHIP(hipcub::DeviceScan::ExclusiveScan(nullptr, tb2, bcount, boff, hipcub::Sum(), (unsigned long long)have,
-                                               (int)nb + 1, st));
-        unsigned char *tsp2 = nullptr;
-        GTRY(tmp.get(&tsp2, tb2));
-        GHIP(hipcub::DeviceScan::ExclusiveScan(tsp2, tb2, bcount, boff, hipcub::Sum(), (unsigned long long)have,
-                                               (int)nb + 1, st));
-        size_t tb3 = 0;
-        GHIP(hipcub::DeviceReduce::Sum(nullptr, tb3, bev, evsum, (int)nb, st));
-        unsigned char *tsp3 = nullptr;
-        GTRY(tmp.get(&tsp3, tb3));
-        GHIP(hipcub::DeviceReduce::Sum(tsp3, tb3, bev, evsum, (int)nb, st));
+        GTRY(scan<unsigned long long>(bcount, boff, (long long)nb + 1, (unsigned long long)have));
+        GHIP(hipMemsetAsync(evsum, 0, sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(k_sum_u64, dim3((unsigned)std::min<unsigned long long>((nb + 255) / 256, 1024)), dim3(256), 0,
+                           st, bev, (long long)nb, evsum);
+        GHIP(hipGetLastError());
         unsigned long long total = 0, ev = 0;
         GHIP(hipMemcpyAsync(&total, boff + nb, sizeof(total), hipMemcpyDeviceToHost, st));
         GHIP(hipMemcpyAsync(&ev, evsum, sizeof(ev), hipMemcpyDeviceToHost, st));
@@ -517,26 +646,69 @@ struct Builder {
         return SG_OK;
     }
 
-    // stable sort by key, descending (equal keys keep their order), in place
-    sg_status sort_desc(double *&keys, unsigned long long *&codes, unsigned long long n) {
+    // out[i] = init + in[0] + ... + in[i - 1] for i < n (in and out distinct)
+    template <class T>
+    sg_status scan(const T *in, T *out, long long n, T init) {
+        if (n <= 0) return SG_OK;
+        const long long nb = (n + kScanBlock - 1) / kScanBlock;
+        if (nb == 1) {
+            hipLaunchKernelGGL((k_scan_local<T>), dim3(1), dim3(256), 0, st, in, out, n, init, (T *)nullptr);
+            GHIP(hipGetLastError());
+            return SG_OK;
+        }
+        Dev tmp(ctx);
+        T *tsum = nullptr, *toff = nullptr;
+        GTRY(tmp.get(&tsum, nb));
+        GTRY(tmp.get(&toff, nb));
+        hipLaunchKernelGGL((k_scan_local<T>), dim3((unsigned)nb), dim3(256), 0, st, in, out, n, (T)0, tsum);
+        GHIP(hipGetLastError());
+        GTRY(scan<T>(tsum, toff, nb, init));
+        hipLaunchKernelGGL((k_scan_add<T>), dim3(blocks_for(n, 256)), dim3(256), 0, st, out, n, (const T *)toff);
+        GHIP(hipGetLastError());
+        GHIP(hipStreamSynchronize(st));  // the scratch above is released at return
+        return SG_OK;
+    }
+
+    // stable ascending sort of n 64-bit keys, with their values when vals is given, in place
+    // (eight passes of 8-bit digits through a second buffer)
+    sg_status sort_u64(unsigned long long *keys, unsigned long long *vals, long long n) {
         if (n < 2) return SG_OK;
         Dev tmp(ctx);
-        double *k2 = nullptr;
-        unsigned long long *c2 = nullptr;
-        GTRY(dev.get(&k2, n));
-        GTRY(dev.get(&c2, n));
-        size_t tb = 0;
-        GHIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, keys, k2, codes, c2, (int)n, 0, 64, st));
-        unsigned char *tsp = nullptr;
-        GTRY(tmp.get(&tsp, tb));
+        const long long ntiles = (n + kRsTile - 1) / kRsTile;
+        unsigned long long *k2 = nullptr, *v2 = nullptr;
+        unsigned *hist = nullptr, *off = nullptr;
+        GTRY(tmp.get(&k2, n));
+        if (vals) GTRY(tmp.get(&v2, n));
+        GTRY(tmp.get(&hist, 256 * ntiles));
+        GTRY(tmp.get(&off, 256 * ntiles));
+        const unsigned nblk = (unsigned)((ntiles + 3) / 4);
+        unsigned long long *ka = keys, *va = vals, *kb = k2, *vb = v2;
+        for (int bit = 0; bit < 64; bit += 8) {
+            hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(256), 0, st, ka, n, bit, ntiles, hist);
+            GHIP(hipGetLastError());
+            GTRY(scan<unsigned>(hist, off, 256 * ntiles, 0u));
+            hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(256), 0, st, ka, va, kb, vb, n, bit, ntiles,
+                               (const unsigned *)off);
+            GHIP(hipGetLastError());
+            std::swap(ka, kb);
+            std::swap(va, vb);
+        }
+        GHIP(hipStreamSynchronize(st));  // eight passes: the result is back in keys / vals
+        return SG_OK;
+    }
+
+    // stable sort by key, descending (equal keys keep their order), in place; the keys are
+    // positive, so their bit patterns complemented sort ascending in the same order
+    sg_status sort_desc(double *&keys, unsigned long long *&codes, unsigned long long n) {
+        if (n < 2) return SG_OK;
+        auto *k = reinterpret_cast<unsigned long long *>(keys);
         auto *e = mark(ev_sort);
-        GHIP(hipcub::DeviceRadixSort::SortPairsDescending(tsp, tb, keys, k2, codes, c2, (int)n, 0, 64, st));
+        hipLaunchKernelGGL(k_desc_bits, dim3(blocks_for((long long)n, 256)), dim3(256), 0, st, k, (long long)n);
+        GTRY(sort_u64(k, codes, (long long)n));
+        hipLaunchKernelGGL(k_desc_bits, dim3(blocks_for((long long)n, 256)), dim3(256), 0, st, k, (long long)n);
         if (e) (void)hipEventRecord(e->second, st);
+        GHIP(hipGetLastError());
         GHIP(hipStreamSynchronize(st));
-        dev.release(keys);
-        dev.release(codes);
-        keys = k2;
-        codes = c2;
         return SG_OK;
     }
 };
@@ -703,29 +875,24 @@ sg_status graph_build(Ctx *ctx, const sg_graph_desc *d, hipStream_t st, int64_t 
     *n_edges = E;
     if (E >= (1LL << 31) - 1) return gfail(SG_E_INVALID, "too many edges");
     Dev tmp(ctx);
-    unsigned long long *dir = nullptr, *dir2 = nullptr;
+    unsigned long long *dir = nullptr;
     int *head = nullptr;
     long long *ptr = nullptr;
     GTRY(tmp.get(&dir, E));
-    GTRY(tmp.get(&dir2, E));
     GTRY(tmp.get(&head, E));
     GTRY(tmp.get(&ptr, N + 1));
     if (n_sel) {
         hipLaunchKernelGGL(k_graph_directed, dim3(blocks_for((long long)n_sel, 256)), dim3(256), 0, st,
                            (long long)n_sel, N, codes, dir);
         GHIP(hipGetLastError());
-        size_t tb = 0;
-        GHIP(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, dir, dir2, (int)E, 0, 64, st));
-        unsigned char *tsp = nullptr;
-        GTRY(tmp.get(&tsp, tb));
         auto *e = B.mark(B.ev_sort);
-        GHIP(hipcub::DeviceRadixSort::SortKeys(tsp, tb, dir, dir2, (int)E, 0, 64, st));
+        GTRY(B.sort_u64(dir, nullptr, E));
         if (e) (void)hipEventRecord(e->second, st);
-        hipLaunchKernelGGL(k_graph_heads, dim3(blocks_for(E, 256)), dim3(256), 0, st, E, N, dir2, head);
+        hipLaunchKernelGGL(k_graph_heads, dim3(blocks_for(E, 256)), dim3(256), 0, st, E, N, dir, head);
         GHIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_graph_rowptr, dim3(blocks_for(N + 1, 256)), dim3(256), 0, st, N, E,
-                       (const unsigned long long *)dir2, ptr);
+                       (const unsigned long long *)dir, ptr);
     GHIP(hipGetLastError());
     if (adj_ptr) GHIP(hipMemcpyAsync(adj_ptr, ptr, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToHost, st));
     if (adj_idx && cap >= E && E > 0)
