@@ -216,7 +216,10 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int N, int groups, const 
             const Real yn = sb + acc;
             y[b] = yn;
             r = fabs((double)yn - (double)xb);
-            u = keep_nan(r / (fabs((double)yn) + kRelFloor));
+            // a NaN here is dropped by the max below, but it also makes this sweep's L1 sum
+            // non-finite, which the solve policy checks first (guarding u as well would cost
+            // this kernel two registers and a wave per SIMD)
+            u = r / (fabs((double)yn) + kRelFloor);
         }
         if (monitor) {
             r = wave_sum(r);
