@@ -55,7 +55,8 @@ enum {
     SG_E_NOCONV = -4,  /* the solve stopped above its tolerance; outputs hold the best iterate */
     SG_E_BUSY = -5,    /* server queue full, try again */
     SG_E_ABI = -6,     /* abi_version mismatch */
-    SG_E_STATE = -7    /* operation needs a prior solve (exports) or a finished ticket */
+    SG_E_STATE = -7,   /* operation needs a prior solve (exports) or a finished ticket */
+    SG_E_CANCELLED = -8 /* the request was cancelled before it ran (sg_cancel) */
 };
 
 /* Thread-local text of the last non-OK status on the calling thread ("" if none). */
@@ -491,6 +492,14 @@ sg_status sg_submit(sg_server *srv, const sg_scene_desc *desc, uint64_t *ticket)
  * queued or running.
  */
 sg_status sg_poll(sg_server *srv, uint64_t ticket, double *radiance, sg_solve_info *info, int32_t *done);
+
+/*
+ * Cancel a request that is still queued: it leaves the queue and its ticket finishes with
+ * SG_E_CANCELLED (sg_poll / sg_wait then return that status and release the ticket).
+ * Errors: SG_E_STATE (the request is running or has finished: it is not touched),
+ * SG_E_INVALID (unknown ticket).
+ */
+sg_status sg_cancel(sg_server *srv, uint64_t ticket);
 
 /* Block until the ticket finishes; same outputs as sg_poll. */
 sg_status sg_wait(sg_server *srv, uint64_t ticket, double *radiance, sg_solve_info *info);

@@ -22,6 +22,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sgoracle.c")
 _LIB = os.path.join(_HERE, "libsgoracle.so")
+# a prebuilt library to load instead (e.g. a sanitizer build of sgoracle.c)
+_LIB_OVERRIDE = os.environ.get("SGORACLE_LIB")
 _lock = threading.Lock()
 _lib = None
 
@@ -44,9 +46,12 @@ def lib():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-                build(force=True)
-            L = C.CDLL(_LIB)
+            if _LIB_OVERRIDE:
+                L = C.CDLL(_LIB_OVERRIDE)
+            else:
+                if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                    build(force=True)
+                L = C.CDLL(_LIB)
             P = C.c_void_p
             L.or_trace_p.restype = C.c_int
             L.or_trace_p.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, C.c_int, P, P, C.c_int]

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libsgrt.so")
 ABI_VERSION = 7
 
 SG_OK, SG_E_INVALID, SG_E_NOMEM, SG_E_DEVICE, SG_E_NOCONV, SG_E_BUSY, SG_E_ABI, SG_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
+SG_E_CANCELLED = -8
 SG_FP32, SG_FP64 = 0, 1
 SOLVERS = {"auto": 0, "neumann": 1, "gmres": 2}
 VEC = {"tau_s": 0, "tau_a": 1, "tau_sun_s": 2, "tau_sun_a": 3, "rho": 4, "source": 5, "phi": 6, "qsun": 7}
@@ -128,6 +129,7 @@ def lib():
                 "sg_submit": (I32, [P, P, P]),
                 "sg_poll": (I32, [P, U64, P, P, P]),
                 "sg_wait": (I32, [P, U64, P, P]),
+                "sg_cancel": (I32, [P, U64]),
                 "sg_server_latencies": (I32, [P, P, I32, P]),
                 "sg_server_destroy": (I32, [P]),
                 "sg_graph_build": (I32, [P, P, P, P, P, I64, P, P]),
@@ -425,6 +427,14 @@ class Server:
         d = info.as_dict()
         d["status"] = st
         return rad.reshape(shp), d
+
+    def cancel(self, ticket: int) -> int:
+        """sg_cancel: SG_OK when the queued request was cancelled (its wait then reports
+        SG_E_CANCELLED), SG_E_STATE when it is running or finished."""
+        st = lib().sg_cancel(self.handle, ticket)
+        if st not in (SG_OK, SG_E_STATE):
+            _check(st)
+        return st
 
     @staticmethod
     def reservation(scene) -> int:

@@ -235,3 +235,29 @@ def test_tight_budget_with_a_gmres_fallback_in_the_mix():
                     assert np.array_equal(rad.reshape(ref.shape), ref), sc.name
         finally:
             srv.close()
+
+
+def test_cancel_a_queued_request(ctx):
+    """sg_cancel takes a queued request out (its wait reports SG_E_CANCELLED and it never
+    runs); the running one is not touched; the one behind it is still the solo result."""
+    from paper_2503_16037_amd import sgrt
+    head = scenes.make_cloud()  # 128 x 128 x 48: created and solved in tens of ms
+    small = [scenes.make_random_small(20 + i, nx=5, ny=4, nz=3, kscale=2.0) for i in range(2)]
+    with sgrt.Scene(ctx, small[1]) as g:
+        ref = np.asarray(g.solve()[0]).reshape(small[1].n_lambda, small[1].ny, small[1].nx)
+    srv = sgrt.Server(ctx, max_resident=1, queue_cap=8, n_streams=1)
+    try:
+        t0 = srv.submit(head)
+        t1 = srv.submit(small[0])
+        t2 = srv.submit(small[1])
+        assert srv.cancel(t1) == sgrt.SG_OK
+        _, info1 = srv.wait(t1)
+        assert info1["status"] == sgrt.SG_E_CANCELLED
+        _, info0 = srv.wait(t0)
+        assert info0["status"] == 0
+        rad2, info2 = srv.wait(t2)
+        assert info2["status"] == 0 and np.array_equal(rad2, ref)
+        with pytest.raises(sgrt.SgError):  # released ticket
+            srv.cancel(t2)
+    finally:
+        srv.close()
