@@ -377,6 +377,20 @@ sg_status sg_los_nodes(sg_ctx *ctx, const sg_los_desc *desc, void *hip_stream, i
                        int64_t node_cap, int64_t *n_nodes, int64_t *los_ptr, int32_t *los_node, double *los_t,
                        int64_t el_cap, int64_t *n_elements);
 
+/*
+ * Bounds-checked builds.  libsgrt_debug.so is the same library compiled with
+ * SG_DEBUG_BOUNDS: the kernels check their indexed global and LDS accesses against the
+ * arrays' extents; a failed check skips the access (no fault) and records the first failing
+ * site of its code module, and the entry point that ran the kernel (scene creation, solve,
+ * export, trace, graph build, placement) returns SG_E_DEVICE naming the site.  A debugging
+ * aid for callers that suspect their inputs or the library; results of a build without the
+ * checks are identical when no check fails.
+ * *enabled: 1 in a checked build, 0 otherwise.  selftest = 1 (checked builds): one check that
+ * fails by construction runs first (its index is never used), so *site returns 0xffff -- the
+ * checker's own test.  *site: the first failed check since the last report, or 0.
+ */
+sg_status sg_debug_bounds(sg_ctx *ctx, int32_t selftest, int32_t *enabled, uint32_t *site);
+
 /* ------------------------------------------------------------------------------------ */
 /* The scattering graph itself (Sec. 2, Eq. 4; Sec. 3)                                   */
 /* ------------------------------------------------------------------------------------ */

@@ -1,7 +1,8 @@
 """Build libsgrt.so (the HIP library behind include/sgrt.h) for gfx950 with hipcc.
 
 Every source is compiled in-tree into ``_build/`` and linked into
-``paper_2503_16037_amd/libsgrt.so``.  Packed FP32 instructions are disabled
+``paper_2503_16037_amd/libsgrt.so``; ``build(debug=True)`` makes the bounds-checked
+``libsgrt_debug.so`` (SG_DEBUG_BOUNDS, objects in ``_build/debug/``).  Packed FP32 instructions are disabled
 for all device code; the phase-cell kernel, the graph builder and the host
 runtime are compiled without floating-point contraction (their operation order
 is part of the definition of lattice ownership and of the coupling ranking).
@@ -17,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsgrt.so")
+OUT_DEBUG = os.path.join(HERE, "libsgrt_debug.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("SGRT_ARCH", "gfx950")
 
@@ -32,9 +34,11 @@ def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, src + ".o")
+def _compile(src: str, debug: bool = False) -> str:
+    obj = os.path.join(BUILD, "debug" if debug else "", src + ".o")
     cmd = ["hipcc", *COMMON]
+    if debug:
+        cmd.append("-DSG_DEBUG_BOUNDS")
     if src in NO_CONTRACT:
         cmd.append("-ffp-contract=off")
     cmd += EXTRA.get(src, [])
@@ -50,21 +54,22 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = True, debug: bool = False) -> str:
+    os.makedirs(os.path.join(BUILD, "debug") if debug else BUILD, exist_ok=True)
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = OUT + ".tmp%d" % os.getpid()
+        objs = list(ex.map(lambda f: _compile(f, debug), srcs))
+    out = OUT_DEBUG if debug else OUT
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print(f"built {OUT}")
-    return OUT
+        print(f"built {out}")
+    return out
 
 
 if __name__ == "__main__":
-    build()
+    build(debug="--debug" in sys.argv)

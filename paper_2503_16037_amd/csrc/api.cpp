@@ -29,6 +29,32 @@ void set_error(const std::string &msg) { t_err = msg; }
 std::string t_last_error() { return t_err; }
 
 namespace {
+std::vector<unsigned (*)()> &bounds_readers() {
+    static std::vector<unsigned (*)()> v;  // filled while the library loads
+    return v;
+}
+}  // namespace
+
+void register_bounds_reader(unsigned (*reader)()) { bounds_readers().push_back(reader); }
+
+sg_status bounds_report() {
+#ifdef SG_DEBUG_BOUNDS
+    unsigned site = 0u;
+    for (auto r : bounds_readers()) {
+        const unsigned v = r();
+        if (v && !site) site = v;
+    }
+    if (site) {
+        char buf[96];
+        std::snprintf(buf, sizeof(buf), "bounds check failed at site 0x%04x (the access was skipped)", site);
+        set_error(buf);
+        return SG_E_DEVICE;
+    }
+#endif
+    return SG_OK;
+}
+
+namespace {
 
 bool sg_log() {
     static const bool on = [] {
@@ -1199,7 +1225,8 @@ void free_scene_impl(Scene *s);
 
 void free_scene(Scene *s) { free_scene_impl(s); }
 sg_status create_scene(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Scene &s) {
-    return create_scene_impl(ctx, d, st, s);
+    const sg_status r = create_scene_impl(ctx, d, st, s);
+    return r == SG_OK ? bounds_report() : r;
 }
 
 namespace {
@@ -1498,12 +1525,17 @@ sg_status solve_scene(Scene &s, const sg_solve_opts &o, hipStream_t st, double *
     std::lock_guard<std::mutex> lk(s.mu);
     SG_HIP(hipSetDevice(ctx->device));
     ++s.solves;
+    sg_status r;
     if (s.n_lambda > 1) {
         if (o.precision != SG_FP32) return fail(SG_E_INVALID, "several wavelengths are solved in FP32 only");
-        return solve_batched(s, o, st, radiance, on_dev, info);
+        r = solve_batched(s, o, st, radiance, on_dev, info);
+    } else if (o.precision == SG_FP64) {
+        r = solve_single<double>(s, o, st, radiance, on_dev, info);
+    } else {
+        r = solve_single<float>(s, o, st, radiance, on_dev, info);
     }
-    if (o.precision == SG_FP64) return solve_single<double>(s, o, st, radiance, on_dev, info);
-    return solve_single<float>(s, o, st, radiance, on_dev, info);
+    const sg_status b = bounds_report();
+    return b != SG_OK ? b : r;
 }
 
 sg_status check_opts(const sg_solve_opts *opts, sg_solve_opts &o) {
@@ -1671,7 +1703,7 @@ sg_status sg_export_csr(sg_scene *scene, int32_t lambda, int64_t *row_ptr, int32
         }
     }
     SG_HIP(hipStreamSynchronize(st));
-    return SG_OK;
+    return bounds_report();
 }
 
 sg_status sg_export_vector(sg_scene *scene, int32_t which, double *out) {
@@ -1730,7 +1762,7 @@ sg_status sg_export_vector(sg_scene *scene, int32_t which, double *out) {
         for (size_t r = 0; r < rows; ++r)
             for (int k = 0; k < s.n_lambda; ++k) out[(size_t)k * rows + r] = t[r * s.n_lambda + k];
     }
-    return SG_OK;
+    return bounds_report();
 }
 
 sg_status sg_trace(sg_scene *scene, int32_t kind, const int64_t *ids, int32_t n_ids, int32_t cap, int32_t *voxels,
@@ -1764,6 +1796,31 @@ sg_status sg_trace(sg_scene *scene, int32_t kind, const int64_t *ids, int32_t n_
     (void)hipFree(d_vox);
     (void)hipFree(d_dt);
     (void)hipFree(d_cnt);
+    return bounds_report();
+}
+
+
+sg_status sg_debug_bounds(sg_ctx *ctx_, int32_t selftest, int32_t *enabled, uint32_t *site) {
+    Ctx *ctx = reinterpret_cast<Ctx *>(ctx_);
+    if (!ctx || !enabled || !site) return fail(SG_E_INVALID, "NULL argument");
+    *site = 0u;
+#ifdef SG_DEBUG_BOUNDS
+    *enabled = 1;
+    SG_HIP(hipSetDevice(ctx->device));
+    if (selftest) {
+        launch_bounds_selftest(ctx->stream);
+        SG_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    const sg_status r = bounds_report();
+    if (r != SG_OK) {
+        const std::string m = t_last_error();
+        *site = (uint32_t)std::strtoul(m.substr(m.find("0x")).c_str(), nullptr, 16);
+        return SG_OK;
+    }
+#else
+    (void)selftest;
+    *enabled = 0;
+#endif
     return SG_OK;
 }
 

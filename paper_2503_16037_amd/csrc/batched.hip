@@ -173,6 +173,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(wide_waves_
             if (monitor && lv) meas[(long long)l * nl + lam] = make_float2(0.f, 0.f);
             continue;
         }
+#ifdef SG_DEBUG_BOUNDS
+        {  // the node's Q block and its in-edges' reverse ids
+            bool ok = SG_IN(nodeoff[l] + (long long)d * d - 1, nodeoff[N], 0x401);
+            if (lane < d) ok = SG_IN(rev[adj_ptr[l] + lane], adj_ptr[N], 0x402) && ok;
+            if (!__all(ok)) continue;
+        }
+#endif
         const int bucket = (d + 7) >> 3;
         float2 part = make_float2(0.f, 0.f);
 #define SG_NODE(DB)                                                                                              \
@@ -317,7 +324,7 @@ __global__ __launch_bounds__(256) void k_spmm_pack(
         }
         for (int m = lam; m < d; m += W) {
             const long long e = off + m;
-            srv[m] = rev[e];
+            srv[m] = SG_IN(rev[e], adj_ptr[N], 0x403) ? rev[e] : (int)e;
             sts[m] = tau_s[e];
             sta[m] = tau_a[e];
         }
@@ -373,7 +380,8 @@ __global__ __launch_bounds__(256) void k_blam64(int N, int nl, int lam, float s,
     }
     const long long base = nodeoff[l];
     const long long em = off + min(lane, d - 1);  // lane m: in-edge m's input
-    const double xin = (double)edge_T(tau_s[em], tau_a[em], s) * v[rev[em]];
+    const int rv0 = rev[em];
+    const double xin = (double)edge_T(tau_s[em], tau_a[em], s) * v[SG_IN(rv0, adj_ptr[N], 0x405) ? rv0 : (int)em];
     const bool act = lane < d;
     double acc = 0.0;
     for (int m = 0; m < d; ++m) {
@@ -471,7 +479,8 @@ __global__ __launch_bounds__(64) void k_bnode_J(int N, int nvol, int nl, const l
     if (lane < d) {
         double t = 1.0;
         if (vol) {
-            const int j = adj_idx[off + lane];
+            const int j0 = adj_idx[off + lane];
+            const int j = SG_IN(j0, N, 0x404) ? j0 : l;
             const long long Dx = min_image((long long)pos[3 * l] - pos[3 * j], wx, per & 1);
             const long long Dy = min_image((long long)pos[3 * l + 1] - pos[3 * j + 1], wy, per & 2);
             const long long Dz = (long long)pos[3 * l + 2] - pos[3 * j + 2];
@@ -520,13 +529,15 @@ __global__ __launch_bounds__(64) void k_bpixels(int nx, int ny, int nz, int per,
         double tau_tot = 0.0;
         voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
             const long long v = x + (long long)nx * (y + (long long)ny * z);
-            tau_tot += ((double)mu_s[v] + s * (double)mu_a[v]) * ((double)num / (double)den * len_view);
+            if (SG_IN(v, (long long)nx * ny * nz, 0x406))
+                tau_tot += ((double)mu_s[v] + s * (double)mu_a[v]) * ((double)num / (double)den * len_view);
             return true;
         });
         double I = 0.0, cum = 0.0;
         if (!los_ptr) {
             voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
                 const long long v = x + (long long)nx * (y + (long long)ny * z);
+                if (!SG_IN(v, (long long)nx * ny * nz, 0x407)) return true;
                 const double ms = (double)mu_s[v];
                 const double me = ms + s * (double)mu_a[v];
                 const double tk = me * ((double)num / (double)den * len_view);
@@ -542,6 +553,7 @@ __global__ __launch_bounds__(64) void k_bpixels(int nx, int ny, int nz, int per,
             double t = 0.0;
             voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
                 const long long v = x + (long long)nx * (y + (long long)ny * z);
+                if (!SG_IN(v, (long long)nx * ny * nz, 0x408)) return true;
                 const double ms = (double)mu_s[v];
                 const double me = ms + s * (double)mu_a[v];
                 const double om = me > 0.0 ? ms / me : 0.0;
@@ -556,7 +568,8 @@ __global__ __launch_bounds__(64) void k_bpixels(int nx, int ny, int nz, int per,
                         node = los_node[e];
                     }
                     const double tk = me * ((b - a) * len_view);
-                    if (node >= 0) I += exp(-(tau_tot - (cum + tk))) * (om * (-expm1(-tk))) * J[(long long)node * nl + lam];
+                    if (node >= 0 && SG_IN(node, nvol, 0x409))
+                        I += exp(-(tau_tot - (cum + tk))) * (om * (-expm1(-tk))) * J[(long long)node * nl + lam];
                     cum += tk;
                     a = b;
                 }
@@ -570,7 +583,8 @@ __global__ __launch_bounds__(64) void k_bpixels(int nx, int ny, int nz, int per,
             double ts = 0.0;
             voxel_walk(nx, ny, nz, per, px, py, 0, sdx, sdy, sdz, true, [&](int x, int y, int z, long long num, long long den) {
                 const long long v = x + (long long)nx * (y + (long long)ny * z);
-                ts += ((double)mu_s[v] + s * (double)mu_a[v]) * ((double)num / (double)den * len_sun);
+                if (SG_IN(v, (long long)nx * ny * nz, 0x40a))
+                    ts += ((double)mu_s[v] + s * (double)mu_a[v]) * ((double)num / (double)den * len_sun);
                 return true;
             });
             I += exp(-tau_tot) * a_pi * mu0 * exp(-ts);

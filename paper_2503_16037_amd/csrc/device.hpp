@@ -15,6 +15,34 @@ namespace sg {
 constexpr long long kFx = 65536;  // fixed-point units per voxel edge
 constexpr int kWave = 64;
 
+// Bounds-checked builds (SG_DEBUG_BOUNDS, libsgrt_debug.so): SG_IN(i, n, site) is true when
+// 0 <= i < n; otherwise the first failing site of this code module is recorded and the
+// caller skips the access.  Each module registers a reader of its record, which the entry
+// points consult after their kernels (bounds_report).  In release builds it is the constant
+// true and costs nothing.
+#ifdef SG_DEBUG_BOUNDS
+namespace {
+__device__ unsigned g_oob_site = 0u;
+__device__ __forceinline__ bool in_bounds(long long i, long long n, unsigned site) {
+    if (i >= 0 && i < n) return true;
+    atomicCAS(&g_oob_site, 0u, site);
+    return false;
+}
+unsigned oob_read_and_clear() {
+    unsigned v = 0u, z = 0u;
+    if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_oob_site), sizeof(v)) != hipSuccess) return 0u;
+    if (v) (void)hipMemcpyToSymbol(HIP_SYMBOL(g_oob_site), &z, sizeof(z));
+    return v;
+}
+struct OobRegistrar {
+    OobRegistrar() { register_bounds_reader(&oob_read_and_clear); }
+} g_oob_registrar;
+}  // namespace
+#define SG_IN(i, n, site) (::sg::in_bounds((long long)(i), (long long)(n), (unsigned)(site)))
+#else
+#define SG_IN(i, n, site) true
+#endif
+
 __device__ __forceinline__ long long floor_div_fx(long long a) {
     // floor(a / kFx) for any sign (kFx is a power of two: arithmetic shift)
     return a >> 16;

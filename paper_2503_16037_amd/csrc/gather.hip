@@ -52,8 +52,10 @@ __global__ __launch_bounds__(256) void k_node_J(int N, int nvol, const long long
         for (int m = lane; m < d; m += 64) {
             const long long e = off + m;
             double th = 1.0;
+            if (!SG_IN(rev[e], adj_ptr[N], 0x501)) continue;
             if (vol) {
                 const int j = adj_idx[e];
+                if (!SG_IN(j, N, 0x502)) continue;
                 const long long Dx = min_image((long long)pos[3 * l] - pos[3 * j], wx, per & 1);
                 const long long Dy = min_image((long long)pos[3 * l + 1] - pos[3 * j + 1], wy, per & 2);
                 const long long Dz = (long long)pos[3 * l + 2] - pos[3 * j + 2];
@@ -87,6 +89,7 @@ __global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, int per, 
     double tau_tot = 0.0;
     voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
         const long long v = x + (long long)nx * (y + (long long)ny * z);
+        if (!SG_IN(v, (long long)nx * ny * nz, 0x503)) return true;
         const double me = (double)mu_s[v] + scale * (double)mu_a[v];
         tau_tot += me * ((double)num / (double)den * len_view);
         return true;
@@ -96,6 +99,7 @@ __global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, int per, 
     if (!los_ptr) {
         voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
             const long long v = x + (long long)nx * (y + (long long)ny * z);
+            if (!SG_IN(v, (long long)nx * ny * nz, 0x504)) return true;
             const double ms = (double)mu_s[v];
             const double me = ms + scale * (double)mu_a[v];
             const double sk = (double)num / (double)den * len_view;
@@ -114,6 +118,7 @@ __global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, int per, 
         double t = 0.0;
         voxel_walk(nx, ny, nz, per, px, py, 0, vdx, vdy, vdz, true, [&](int x, int y, int z, long long num, long long den) {
             const long long v = x + (long long)nx * (y + (long long)ny * z);
+            if (!SG_IN(v, (long long)nx * ny * nz, 0x505)) return true;
             const double ms = (double)mu_s[v];
             const double me = ms + scale * (double)mu_a[v];
             const double om = me > 0.0 ? ms / me : 0.0;
@@ -128,7 +133,8 @@ __global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, int per, 
                     node = los_node[e];
                 }
                 const double tk = me * ((b - a) * len_view);
-                if (node >= 0) I += exp(-(tau_tot - (cum + tk))) * (om * (-expm1(-tk))) * J[node];
+                if (node >= 0 && SG_IN(node, nvol, 0x506))
+                    I += exp(-(tau_tot - (cum + tk))) * (om * (-expm1(-tk))) * J[node];
                 cum += tk;
                 a = b;
             }
@@ -143,7 +149,8 @@ __global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, int per, 
         double ts = 0.0;
         voxel_walk(nx, ny, nz, per, px, py, 0, sdx, sdy, sdz, true, [&](int x, int y, int z, long long num, long long den) {
             const long long v = x + (long long)nx * (y + (long long)ny * z);
-            ts += ((double)mu_s[v] + scale * (double)mu_a[v]) * ((double)num / (double)den * len_sun);
+            if (SG_IN(v, (long long)nx * ny * nz, 0x507))
+                ts += ((double)mu_s[v] + scale * (double)mu_a[v]) * ((double)num / (double)den * len_sun);
             return true;
         });
         I += exp(-tau_tot) * a_pi * mu0 * exp(-ts);

@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) void k_graph_eval(Geo g, const double *__restr
                     const unsigned sl = lc - nv, sy = sl / bx, sx = sl - sy * bx;
                     j = g.nvol + ((long long)o[0] + sx) + (long long)g.nx * ((long long)o[1] + sy);
                 }
-                eval = j > i;
+                eval = j > i && SG_IN(j, g.N, 0x701);
                 if (eval) {
                     k = pair_key(q, mu, i, j);
                     ok = k > 0.0 && (strict ? k > t : k >= t);
@@ -341,8 +341,10 @@ __global__ __launch_bounds__(256) void k_graph_eval(Geo g, const double *__restr
         }
         if (kFill && ok) {
             const unsigned long long at = run + before + __popcll(m & ((1ull << lane) - 1ull));
-            keys[at] = k;
-            codes[at] = (unsigned long long)i * (unsigned long long)g.N + (unsigned long long)j;
+            if (SG_IN(at, boff[gridDim.x], 0x702)) {
+                keys[at] = k;
+                codes[at] = (unsigned long long)i * (unsigned long long)g.N + (unsigned long long)j;
+            }
         }
         run += total;
         __syncthreads();  // wcnt is rewritten by the next round
@@ -514,7 +516,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const unsigned long long *__
         __builtin_amdgcn_wave_barrier();
         if (ok && before == 0u) run[w][dg] = p + (unsigned)__popcll(peers);  // the digit's first lane
         __builtin_amdgcn_wave_barrier();
-        if (ok) {
+        if (ok && SG_IN(p, n, 0x703)) {
             kout[p] = k;
             if (vin) vout[p] = vin[i];
         }
@@ -919,6 +921,8 @@ extern "C" sg_status sg_graph_build(sg_ctx *ctx, const sg_graph_desc *desc, void
     if (!ctx) return sg::gfail(SG_E_INVALID, "ctx is NULL");
     if (ctx->sticky.load()) return sg::gfail(SG_E_DEVICE, "context is in a failed state");
     if (hipSetDevice(ctx->device) != hipSuccess) return sg::gfail(SG_E_DEVICE, "hipSetDevice failed");
-    return sg::graph_build(ctx, desc, hip_stream ? (hipStream_t)hip_stream : ctx->stream, adj_ptr, adj_idx, cap,
-                           n_edges, info);
+    const sg_status r = sg::graph_build(ctx, desc, hip_stream ? (hipStream_t)hip_stream : ctx->stream, adj_ptr,
+                                        adj_idx, cap, n_edges, info);
+    const sg_status b = sg::bounds_report();
+    return b != SG_OK ? b : r;
 }

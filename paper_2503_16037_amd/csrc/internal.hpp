@@ -26,6 +26,11 @@ constexpr int kMaxDegree = 4096;
 constexpr int kMaxWaveDegree = 64;
 
 void set_error(const std::string &msg);
+// Bounds-checked builds: each code module registers a reader of its first failed check
+// (0: none), and bounds_report returns SG_E_DEVICE naming it (SG_OK in release builds).
+void register_bounds_reader(unsigned (*reader)());
+sg_status bounds_report();
+void launch_bounds_selftest(hipStream_t st);  // one failing check on purpose (never dereferenced)
 std::string t_last_error();
 
 // a captured chunk of sweeps: key = (kind, chunk length, buffers and flags it was recorded with)

@@ -21,7 +21,8 @@ namespace {
 struct LosGeo {
     int nx, ny, nz, per, mode;
     long long dx, dy, dz;
-    double h;  // SG_LOS_STEP: the step in line-parameter units
+    double h;                       // SG_LOS_STEP: the step in line-parameter units
+    long long n_nodes = 0, n_el = 0;  // fill pass: the outputs' sizes (bounds-checked builds)
 };
 
 // The node of element [a, b] of the line from (px, py, 0): the rounded middle point (m =
@@ -60,14 +61,14 @@ __global__ __launch_bounds__(64) void k_los_place(LosGeo g, int fill, const long
         int id = -1;
         if (element_node(g, px, py, a, b, q)) {
             id = (int)(n0 + nn);
-            if (fill) {
+            if (fill && SG_IN(n0 + nn, g.n_nodes, 0x801)) {
                 pos[3 * (n0 + nn)] = q[0];
                 pos[3 * (n0 + nn) + 1] = q[1];
                 pos[3 * (n0 + nn) + 2] = q[2];
             }
             ++nn;
         }
-        if (fill) {
+        if (fill && SG_IN(e0 + ne, g.n_el, 0x802)) {
             el_node[e0 + ne] = id;
             el_t[e0 + ne] = b;
         }
@@ -210,6 +211,8 @@ extern "C" sg_status sg_los_nodes(sg_ctx *ctx_, const sg_los_desc *d, void *hip_
     if ((e = hipMemcpyAsync(off_n, on.data(), sizeof(long long) * npx, hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(off_e, oe.data(), sizeof(long long) * npx, hipMemcpyHostToDevice, st)) != hipSuccess)
         return dev("hipMemcpyAsync", e);
+    g.n_nodes = on[npx];
+    g.n_el = oe[npx];
     hipLaunchKernelGGL(k_los_place, dim3(blocks), dim3(64), 0, st, g, 1, off_n, off_e, (long long *)nullptr,
                        (long long *)nullptr, pos, el_node, el_t);
     if ((e = hipGetLastError()) != hipSuccess) return dev("k_los_place", e);
@@ -218,5 +221,5 @@ extern "C" sg_status sg_los_nodes(sg_ctx *ctx_, const sg_los_desc *d, void *hip_
         (oe[npx] && (e = hipMemcpyAsync(los_t, el_t, sizeof(double) * oe[npx], hipMemcpyDeviceToHost, st)) != hipSuccess) ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
         return dev("hipMemcpyAsync", e);
-    return SG_OK;
+    return bounds_report();
 }

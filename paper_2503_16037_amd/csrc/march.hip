@@ -81,8 +81,10 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
             const int x = t % bw, yz = t / bw;
             const int y = yz % bh, z = yz / bh;
             const long long g = (bx0 + x) + (long long)nx * ((by0 + y) + (long long)ny * (bz0 + z));
-            bs[t] = mu_s[g];
-            ba[t] = mu_a[g];
+            if (SG_IN(t, kBrickCap, 0x101) && SG_IN(g, (long long)nx * ny * nz, 0x102)) {
+                bs[t] = mu_s[g];
+                ba[t] = mu_a[g];
+            }
         }
     }
     __syncthreads();
@@ -91,6 +93,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
         while (k + 1 < nl && sptr[k + 1] <= e) ++k;
         const int l = l0 + k;
         const int j = adj_idx[e];
+        if (!SG_IN(j, N, 0x103)) continue;
         const int a = min(l, j), b = max(l, j);
         const long long px = pos[3 * a], py = pos[3 * a + 1], pz = pos[3 * a + 2];
         const long long dx = min_image(pos[3 * b] - px, nx * kFx, per & 1);
@@ -103,12 +106,16 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
                 const Real dt = ratio<Real>(num, den);
                 if ((unsigned)xo < (unsigned)bw && (unsigned)yo < (unsigned)bh && (unsigned)zo < (unsigned)bd) {
                     const int t = xo + bw * (yo + bh * zo);
-                    ss += (Real)bs[t] * dt;
-                    sa += (Real)ba[t] * dt;
+                    if (SG_IN(t, kBrickCap, 0x104)) {
+                        ss += (Real)bs[t] * dt;
+                        sa += (Real)ba[t] * dt;
+                    }
                 } else {  // outside the staged brick (only a periodic segment, wrapped round the grid)
                     const long long g = x + (long long)nx * (y + (long long)ny * z);
-                    ss += (Real)mu_s[g] * dt;
-                    sa += (Real)mu_a[g] * dt;
+                    if (SG_IN(g, (long long)nx * ny * nz, 0x105)) {
+                        ss += (Real)mu_s[g] * dt;
+                        sa += (Real)mu_a[g] * dt;
+                    }
                 }
                 return true;
             });
@@ -116,8 +123,10 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
             voxel_walk(nx, ny, nz, per, px, py, pz, dx, dy, dz, false, [&](int x, int y, int z, long long num, long long den) {
                 const long long vox = x + (long long)nx * (y + (long long)ny * z);
                 const Real dt = ratio<Real>(num, den);
-                ss += (Real)mu_s[vox] * dt;
-                sa += (Real)mu_a[vox] * dt;
+                if (SG_IN(vox, (long long)nx * ny * nz, 0x106)) {
+                    ss += (Real)mu_s[vox] * dt;
+                    sa += (Real)mu_a[vox] * dt;
+                }
                 return true;
             });
         }
@@ -150,8 +159,10 @@ __global__ __launch_bounds__(256) void k_march_sun(int N, int nx, int ny, int nz
                [&](int x, int y, int z, long long num, long long den) {
                    const long long vox = x + (long long)nx * (y + (long long)ny * z);
                    const Real dt = ratio<Real>(num, den);
-                   ss += (Real)mu_s[vox] * dt;
-                   sa += (Real)mu_a[vox] * dt;
+                   if (SG_IN(vox, (long long)nx * ny * nz, 0x107)) {
+                       ss += (Real)mu_s[vox] * dt;
+                       sa += (Real)mu_a[vox] * dt;
+                   }
                    return ss + smin * sa < lim;
                });
     ss *= L;
@@ -207,6 +218,7 @@ __global__ __launch_bounds__(64) void k_trace(int kind, int N, int nx, int ny, i
     if (kind == 0) {
         const int l = edge_tail(adj_ptr, N, id);
         const int j = adj_idx[id];
+        if (!SG_IN(j, N, 0x108)) return;
         const int a = min(l, j), b = max(l, j);
         px = pos[3 * a]; py = pos[3 * a + 1]; pz = pos[3 * a + 2];
         dx = min_image(pos[3 * b] - px, nx * kFx, per & 1);

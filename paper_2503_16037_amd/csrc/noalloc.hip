@@ -130,7 +130,7 @@ sg_status sg_trace_noalloc(sg_scene *scene, int32_t kind, const int64_t *ids, in
         (e = hipMemcpyAsync(count, d_cnt, sizeof(int) * n, hipMemcpyDeviceToHost, st)) != hipSuccess)
         return dev_fail("hipMemcpyAsync", e);
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return dev_fail("hipStreamSynchronize", e);
-    return SG_OK;
+    return bounds_report();
 }
 
 }  // extern "C"

@@ -91,9 +91,11 @@ __global__ __launch_bounds__(64) void k_qbuild(
     const int d = (int)(adj_ptr[l + 1] - off);
     if (d == 0 || d > kWave) return;  // higher degree: k_qbuild_big
     const bool surf = l >= nvol;
+    if (!SG_IN(nodeoff[l] + (long long)d * d - 1, nodeoff[N], 0x201)) return;
 
     if (lane < d) {
-        const int j = adj_idx[off + lane];
+        const int j0 = adj_idx[off + lane];
+        const int j = SG_IN(j0, N, 0x202) ? j0 : l;
         const long long Dx = min_image((long long)pos[3 * j] - pos[3 * l], wx, per & 1);
         const long long Dy = min_image((long long)pos[3 * j + 1] - pos[3 * l + 1], wy, per & 2);
         const long long Dz = (long long)pos[3 * j + 2] - pos[3 * l + 2];
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(64) void k_qbuild(
             const int p = j * 64 + lane;
             if (p < np) {
                 const int al = small_div(p, inv_nf);
-                atomicAdd(&bins[al * 64 + own[j]], wq[p - al * NF]);
+                if (SG_IN(al * 64 + own[j], kQMaxGroup * 64, 0x203)) atomicAdd(&bins[al * 64 + own[j]], wq[p - al * NF]);
             }
         }
         __syncthreads();
@@ -431,8 +433,10 @@ __global__ __launch_bounds__(64) void k_qcolour(
     const int d = (int)(adj_ptr[l + 1] - off);
     if (d == 0 || d > kWave) return;  // higher degree: k_qcolour_big
     const bool surf = l >= nvol;
+    if (!SG_IN(nodeoff[l] + (long long)d * d - 1, nodeoff[N], 0x204)) return;
     if (lane < d) {
-        const int j = adj_idx[off + lane];
+        const int j0 = adj_idx[off + lane];
+        const int j = SG_IN(j0, N, 0x205) ? j0 : l;
         const long long Dx = min_image((long long)pos[3 * j] - pos[3 * l], wx, per & 1);
         const long long Dy = min_image((long long)pos[3 * j + 1] - pos[3 * l + 1], wy, per & 2);
         const long long Dz = (long long)pos[3 * j + 2] - pos[3 * l + 2];
@@ -587,8 +591,8 @@ __global__ __launch_bounds__(64) void k_qcolour(
         // cells: fixed-point sums per colour, then this direction's column
         if (lane < d) bins[lane] = 0ull;
         __syncthreads();
-        if (ok0 && col[i0] >= 0) atomicAdd(&bins[col[i0]], wq[i0]);
-        if (ok1 && col[i1] >= 0) atomicAdd(&bins[col[i1]], wq[i1]);
+        if (ok0 && col[i0] >= 0 && SG_IN(col[i0], d, 0x206)) atomicAdd(&bins[col[i0]], wq[i0]);
+        if (ok1 && col[i1] >= 0 && SG_IN(col[i1], d, 0x207)) atomicAdd(&bins[col[i1]], wq[i1]);
         __syncthreads();
         if (lane < d) {
             const int m = lane;

@@ -203,10 +203,12 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int N, int groups, const 
             if (monitor && lane == 0) meas[l] = make_float2(0.f, 0.f);
             continue;
         }
+        if (!SG_IN(base + (long long)d * d - 1, nodeoff[N], 0x301)) continue;
         const bool act = lane < d;
         const long long b = off + min(lane, d - 1);  // lanes past d repeat the last row
         // the index load first, so that the gather waits for it alone
-        const int rv = rev[b];
+        const int rv0 = rev[b];
+        const int rv = SG_IN(rv0, adj_ptr[N], 0x302) ? rv0 : (int)b;
         const Real sb = S[b];
         const Real xb = monitor ? x[b] : (Real)0;  // the previous value only for the measures
         const Real xl = x[rv];
@@ -278,9 +280,11 @@ __global__ __launch_bounds__(kSpmvThreads) void k_residual64(int N, int groups, 
             if (lane == 0) meas[l] = make_float2(0.f, 0.f);
             continue;
         }
+        if (!SG_IN(base + (long long)d * d - 1, nodeoff[N], 0x303)) continue;
         const bool act = lane < d;
         const long long b = off + min(lane, d - 1);
-        const int rv = rev[b];
+        const int rv0 = rev[b];
+        const int rv = SG_IN(rv0, adj_ptr[N], 0x304) ? rv0 : (int)b;
         const double sb = (double)S[b], xb = x[b];
         const double xl = x[rv];
         const double acc = node_row<double>(val + base, blk, d, lane, xl);
@@ -313,9 +317,11 @@ __global__ __launch_bounds__(kSpmvThreads) void k_apply_imk64(int N, const long 
     const int d = (int)(adj_ptr[l + 1] - off);
     if (d == 0 || d > kWave) return;  // higher degree: k_apply_imk64_big
     const long long base = nodeoff[l];
+    if (!SG_IN(base + (long long)d * d - 1, nodeoff[N], 0x305)) return;
     const bool act = lane < d;
     const long long b = off + min(lane, d - 1);
-    const double xl = v[rev[b]];
+    const int rv0 = rev[b];
+    const double xl = v[SG_IN(rv0, adj_ptr[N], 0x306) ? rv0 : (int)b];
     const double acc = node_row<double>(val + base, blk, d, lane, xl);
     if (act) wv[b] = v[b] - acc;
 }

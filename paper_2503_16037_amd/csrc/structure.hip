@@ -100,6 +100,7 @@ __global__ __launch_bounds__(256) void k_rev(int N, const long long *__restrict_
     const int d = (int)(adj_ptr[l + 1] - off);
     for (int m = lane; m < d; m += 64) {
         const int j = adj_idx[off + m];
+        if (!SG_IN(j, N, 0x601)) continue;
         long long lo = adj_ptr[j], hi = adj_ptr[j + 1];
         while (lo < hi) {
             const long long mid = (lo + hi) >> 1;
@@ -120,6 +121,7 @@ __global__ __launch_bounds__(256) void k_check_symmetric(int N, const long long 
     const int d = (int)(adj_ptr[l + 1] - off);
     for (int m = lane; m < d; m += 64) {
         const int j = adj_idx[off + m];
+        if (!SG_IN(j, N, 0x602)) continue;
         const long long end = adj_ptr[j + 1];
         long long lo = adj_ptr[j], hi = end;
         while (lo < hi) {
@@ -152,6 +154,7 @@ __global__ __launch_bounds__(256) void k_col_idx(int N, const long long *__restr
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
     const long long b0 = nodeoff[l];
+    if (!SG_IN(b0 + (long long)d * d - 1, nodeoff[N], 0x603)) return;
     for (int t = lane; t < d * d; t += 64) col[b0 + t] = rev[off + (t % d)];
 }
 
@@ -173,6 +176,14 @@ void launch_check_symmetric(Scene &s, unsigned *bad, hipStream_t st) {
     const int nb = (s.N + 3) / 4;
     hipLaunchKernelGGL(k_check_symmetric, dim3(nb), dim3(256), 0, st, s.N, s.adj_ptr, s.adj_idx, bad);
 }
+
+// The bounds checker's self-test: one check that fails by construction (the index equals
+// the extent); the array behind it is never read.
+__global__ void k_bounds_selftest(int n) {
+    if (threadIdx.x == 0 && !SG_IN(n, n, 0xffffu)) return;
+}
+
+void launch_bounds_selftest(hipStream_t st) { hipLaunchKernelGGL(k_bounds_selftest, dim3(1), dim3(64), 0, st, 7); }
 
 void launch_col_idx(Scene &s, hipStream_t st) {
     const int nb = (s.N + 3) / 4;

@@ -14,7 +14,9 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsgrt.so")
+# SGRT_LIB=debug selects the bounds-checked build (libsgrt_debug.so); another value is a path
+LIB_PATH = {"": os.path.join(HERE, "libsgrt.so"), "debug": os.path.join(HERE, "libsgrt_debug.so")}.get(
+    os.environ.get("SGRT_LIB", ""), os.environ.get("SGRT_LIB", ""))
 ABI_VERSION = 7
 
 SG_OK, SG_E_INVALID, SG_E_NOMEM, SG_E_DEVICE, SG_E_NOCONV, SG_E_BUSY, SG_E_ABI, SG_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
@@ -130,6 +132,7 @@ def lib():
                 "sg_poll": (I32, [P, U64, P, P, P]),
                 "sg_wait": (I32, [P, U64, P, P]),
                 "sg_cancel": (I32, [P, U64]),
+                "sg_debug_bounds": (I32, [P, I32, P, P]),
                 "sg_server_latencies": (I32, [P, P, I32, P]),
                 "sg_server_destroy": (I32, [P]),
                 "sg_graph_build": (I32, [P, P, P, P, P, I64, P, P]),
@@ -494,6 +497,15 @@ def graph_build(ctx: Context, scene, n_pairs: int = 0, c_min: float = 0.0, strea
                                     ne.value, C.byref(ne), C.byref(gi)))
     out = (adj_ptr, adj_idx[:ne.value].copy())
     return out + (gi.as_dict(),) if info else out
+
+
+def debug_bounds(ctx: Context, selftest: bool = False):
+    """sg_debug_bounds: (enabled, site) -- whether this library checks its kernels' indexed
+    accesses, and the first failed check since the last report (0: none); selftest runs one
+    check that fails by construction first (site 0xffff)."""
+    en, site = C.c_int32(), C.c_uint32()
+    _check(lib().sg_debug_bounds(ctx.handle, 1 if selftest else 0, C.byref(en), C.byref(site)))
+    return bool(en.value), int(site.value)
 
 
 def los_nodes(ctx: Context, nx, ny, nz, view_dir, voxel_m, mode="layer", step_m=0.0, periodic=0, stream=None):
