@@ -8,8 +8,10 @@
 // kernels).  From a scene's second solve on, the tuner times a short list of
 // launch shapes with HIP events on the scene's own data and keeps the fastest, per
 // problem shape, for the life of the process (a scene solved once, as in serving,
-// never pays for tuning); SG_AUTOTUNE_CACHE names an optional text file that keeps
-// the choices across processes.
+// never pays for tuning); SG_AUTOTUNE_CACHE names an optional file that keeps the
+// choices across processes, one JSON object per line (appended as choices are made):
+//   {"kind": k, "N": n, "E": e, "nnz": z, "dmax": d, "n_lambda": l, "bytes": b, "grid": g, "tile": t}
+// Lines of any other shape are ignored.
 //
 // Graphs.  A chunk of sweeps is a fixed sequence of kernel launches on fixed
 // buffers.  The second time a scene runs the same chunk it is captured on the
@@ -41,6 +43,11 @@ std::mutex g_tune_mu;
 std::map<TuneKey, Shape> g_tuned;
 bool g_cache_loaded = false;
 
+// one cache entry (printf and scanf format alike: the keys in this order)
+constexpr const char *kCacheLine =
+    "{\"kind\": %lld, \"N\": %lld, \"E\": %lld, \"nnz\": %lld, \"dmax\": %lld, \"n_lambda\": %lld, "
+    "\"bytes\": %lld, \"grid\": %d, \"tile\": %d}";
+
 const char *cache_path() {
     const char *p = std::getenv("SG_AUTOTUNE_CACHE");
     return (p && p[0]) ? p : nullptr;
@@ -53,11 +60,14 @@ void load_cache_locked() {
     if (!p) return;
     FILE *f = std::fopen(p, "r");
     if (!f) return;
-    TuneKey k;
-    Shape v;
-    while (std::fscanf(f, "%lld %lld %lld %lld %lld %lld %lld %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6],
-                       &v.grid, &v.tile) == 9)
-        if (v.grid > 0) g_tuned[k] = v;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        TuneKey k;
+        Shape v;
+        if (std::sscanf(line, kCacheLine, &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6], &v.grid, &v.tile) == 9 &&
+            v.grid > 0)
+            g_tuned[k] = v;
+    }
     std::fclose(f);
 }
 
@@ -67,8 +77,8 @@ void store_cache_locked(const TuneKey &k, Shape v) {
     if (!p) return;
     FILE *f = std::fopen(p, "a");
     if (!f) return;
-    std::fprintf(f, "%lld %lld %lld %lld %lld %lld %lld %d %d\n", k[0], k[1], k[2], k[3], k[4], k[5], k[6], v.grid,
-                 v.tile);
+    std::fprintf(f, kCacheLine, k[0], k[1], k[2], k[3], k[4], k[5], k[6], v.grid, v.tile);
+    std::fputc('\n', f);
     std::fclose(f);
 }
 

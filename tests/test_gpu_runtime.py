@@ -74,3 +74,44 @@ def test_timing_reports_sweep_kernels(ctx):
         _, info = g.solve(timing=True)
     assert info["spmv_launches"] >= info["sweeps"] - info["refinements"] > 0
     assert 0 < info["ms_spmv_sum"] <= info["ms_solve"] <= info["ms_total"]
+
+
+_CACHE_CHILD = r'''
+import sys
+import numpy as np
+sys.path.insert(0, ROOT)
+from paper_2503_16037_amd import scenes, sgrt
+sc = scenes.make_random_small(7, nx=10, ny=9, nz=6, kscale=2.0)
+ctx = sgrt.Context(0)
+with sgrt.Scene(ctx, sc) as g:
+    for _ in range(SOLVES):
+        rad, _ = g.solve()
+ctx.close()
+np.save(OUT, np.asarray(rad))
+'''
+
+
+def test_autotune_cache_is_json_lines_and_reused(tmp_path):
+    """SG_AUTOTUNE_CACHE: the tuner's choices are appended as JSON lines with the problem key
+    and the shape, a later process reads them back, and results do not depend on them."""
+    import json
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.jsonl"
+    env = dict(os.environ, SG_AUTOTUNE_CACHE=str(cache))
+    outs = []
+    for solves in (3, 1):  # the first process tunes (from its second solve), the next one reads
+        out = tmp_path / ("rad%d.npy" % solves)
+        script = "ROOT = %r\nSOLVES = %d\nOUT = %r\n" % (root, solves, str(out)) + _CACHE_CHILD
+        r = subprocess.run([sys.executable, "-c", script], env=env, capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-3000:]
+        outs.append(np.load(out))
+        if solves == 3:
+            lines = cache.read_text().splitlines()
+            assert lines, "no tuning choice written"
+            for line in lines:
+                rec = json.loads(line)
+                assert set(rec) == {"kind", "N", "E", "nnz", "dmax", "n_lambda", "bytes", "grid", "tile"}
+                assert rec["grid"] > 0
+    assert np.array_equal(outs[0], outs[1])
