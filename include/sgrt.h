@@ -351,7 +351,8 @@ typedef struct sg_los_desc {
     int32_t view_dir[3];    /* toward the sensor (z > 0), |components| <= 2^22 */
     int32_t periodic;       /* as in sg_scene_desc */
     int32_t mode;           /* SG_LOS_LAYER or SG_LOS_STEP */
-    double step_m;          /* SG_LOS_STEP: the distance between nodes along a line, metres (> 0) */
+    double step_m;          /* SG_LOS_STEP: the distance between nodes along a line, metres (> 0;
+                               fewer than 1e8 steps per line, else SG_E_INVALID) */
 } sg_los_desc;
 enum { SG_LOS_LAYER = 0, SG_LOS_STEP = 1 };
 

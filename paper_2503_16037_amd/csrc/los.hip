@@ -168,10 +168,10 @@ extern "C" sg_status sg_los_nodes(sg_ctx *ctx_, const sg_los_desc *d, void *hip_
                             (d->voxel_m / 65536.0);
         if (!(d->step_m > 0.0) || !std::isfinite(d->step_m)) return lfail(SG_E_INVALID, "step_m must be > 0");
         g.h = d->step_m / plen;
-        // elements per line: at most its length over the step
-        const double t_max = (double)(d->nx + d->ny + d->nz + 3) * 65536.0 / (double)d->view_dir[2] *
-                             (d->periodic ? 65536.0 : 1.0);
-        if (!(t_max / g.h < 1e9)) return lfail(SG_E_INVALID, "step_m too small for the lines' length");
+        // elements per line: at most its length over the step; a line from the ground leaves
+        // through the top at t = nz 2^16 / D_z at the latest (bounded or periodic)
+        const double t_max = (double)d->nz * 65536.0 / (double)d->view_dir[2];
+        if (!(t_max / g.h < 1e8)) return lfail(SG_E_INVALID, "step_m too small for the lines' length");
     }
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return lfail(SG_E_DEVICE, "hipSetDevice failed");

@@ -248,3 +248,23 @@ def test_invalid_los_scenes_are_rejected(ctx):
         with pytest.raises(sgrt.SgError):
             with sgrt.Scene(ctx, b):
                 pass
+
+
+@pytest.mark.parametrize("sigma_mode", [0, 1])
+def test_high_degree_los_nodes_fp64(ctx, sigma_mode):
+    """Line-of-sight nodes on their ranked graph (Eq. 4, 12 couplings per node: degrees up to
+    250, above 64 on 25 nodes): the high-degree kernels on general nodes, both phase-cell
+    rules, every pixel within 1e-10 of the oracle in FP64."""
+    from paper_2503_16037_amd import sgrt
+    sc0 = scenes.make_random_small(2, nx=10, ny=9, nz=6, vza=30.0, vaa=200.0, kscale=2.0)
+    pos, lp, ln, lt = oracle.los_nodes(sc0.nx, sc0.ny, sc0.nz, sc0.view_dir, sc0.voxel_m, "layer")
+    sc = scenes.with_los_nodes(sc0, pos, lp, ln, lt, name="los-ranked")
+    ap, ai = oracle.coupling_graph(sc, n_pairs=12 * len(pos))
+    sc = dataclasses.replace(sc, adj_ptr=ap, adj_idx=ai, sigma_mode=sigma_mode)
+    assert np.diff(ap).max() > 64
+    say("high-degree los", sc.n_vol, "nodes, max degree", int(np.diff(ap).max()), "sigma", sigma_mode)
+    ora = oracle.run(sc)
+    with sgrt.Scene(ctx, sc) as g:
+        rad, info = g.solve(precision="fp64")
+    assert info["converged"] == 1
+    assert rel_err(rad, ora["radiance"]).max() < 1e-10
