@@ -225,7 +225,10 @@ typedef struct sg_solve_opts {
     int32_t build_col_idx; /* 1: also materialise the CSR column index array */
     int32_t timing;        /* 1: per-stage HIP-event timings into sg_solve_info */
     int32_t flags;         /* SG_NO_GRAPHS: launch sweep chunks one by one instead of replaying
-                              captured HIP graphs; SG_NO_AUTOTUNE: default launch shapes */
+                              captured HIP graphs; SG_NO_AUTOTUNE: default launch shapes;
+                              SG_EXACT_CELLS: every phase-cell ownership decision (Eq. 7) by the
+                              FP64 scan alone, without the FP32 screen that certifies most of
+                              them first (the same owners and result bits, slower) */
     int32_t lambda_tile;   /* scenes of several wavelengths: wavelength lanes per node in the
                               sweep kernels, 8, 16, 32 or 64 (a wavefront then holds 64 /
                               lambda_tile nodes); at least n_lambda unless 64 (more than 64
@@ -245,7 +248,7 @@ typedef struct sg_solve_opts {
     const double *warm_start;
     int32_t warm_start_on_device;
 } sg_solve_opts;
-enum { SG_NO_GRAPHS = 1, SG_NO_AUTOTUNE = 2 };
+enum { SG_NO_GRAPHS = 1, SG_NO_AUTOTUNE = 2, SG_EXACT_CELLS = 4 };
 
 typedef struct sg_solve_info {
     int32_t converged;      /* 1 if every wavelength reached rtol */

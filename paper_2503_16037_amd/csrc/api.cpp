@@ -836,6 +836,7 @@ sg_status solve_single(Scene &s, const sg_solve_opts &o, hipStream_t st, double 
     tm.on = o.timing != 0;
     tm.graphs = !(o.flags & SG_NO_GRAPHS) && !tm.on;
     tm.autotune = !(o.flags & SG_NO_AUTOTUNE);
+    s.qscreen = (o.flags & SG_EXACT_CELLS) ? 0 : 1;
     tm.st = st;
     const float scale = s.abs_scale.empty() ? 1.0f : s.abs_scale[0];
     hipEvent_t e0 = tm.mark();
@@ -1109,6 +1110,7 @@ sg_status solve_batched(Scene &s, const sg_solve_opts &o, hipStream_t st, double
     tm.on = o.timing != 0;
     tm.graphs = !(o.flags & SG_NO_GRAPHS) && !tm.on;
     tm.autotune = !(o.flags & SG_NO_AUTOTUNE);
+    s.qscreen = (o.flags & SG_EXACT_CELLS) ? 0 : 1;
     tm.st = st;
     hipEvent_t e0 = tm.mark();
     launch_structure(s, st);

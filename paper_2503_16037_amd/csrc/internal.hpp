@@ -96,6 +96,7 @@ struct Scene {
     double lut_scale[4] = {1, 1, 1, 1};  // 1 / integral over the sphere of each table row
     double *lut = nullptr;             // [n_phase][lut_n] phase tables (device)
     int sigma_mode = 0;                // SG_SIGMA_VORONOI or SG_SIGMA_COLOUR
+    int qscreen = 1;                   // phase-cell owners through the FP32 screen (0: FP64 scan only)
     int periodic = 0;                  // bit 0: x, bit 1: y repeat with the grid's period
     int *hull = nullptr;               // colouring: [n_fib][kHullNb] hull neighbours, then [n_fib] counts
     int n_fib = 100;

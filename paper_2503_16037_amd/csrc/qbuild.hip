@@ -24,6 +24,11 @@
 //   q_ik = fma(R_2k, p_i2, fma(R_1k, p_i1, R_0k p_i0))      (q_i = R^T p_i)
 //   v_im = fma(q_i2, s_m2, fma(q_i1, s_m1, q_i0 s_m0))      (= p_i . R s_m)
 // with no other contraction, hence the pragma below and -ffp-contract=off.
+//
+// The regular kernel finds that argmax through an FP32 screen with a proven error bound
+// (FP64 compares and maxima issue at about half the rate of FP32 and 32-bit integer
+// operations): every decision the screen cannot certify is taken by the FP64 sequence above,
+// so each owner is the one the FP64 sequence gives (see screen_owners).
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -38,34 +43,110 @@ constexpr double kUnfix = 1.0 / 4503599627370496.0;
 constexpr int kQSlots = 8;     // (direction, lattice point) pairs per lane in a group
 constexpr int kQMaxGroup = 8;  // incoming directions per group
 
-// LDS layout of a node (doubles): sites [3][64], rotations [kQMaxGroup][9], lattice
-// weights [128] (fixed point), bins [kQMaxGroup][64] (fixed point), lattice [3][128]
-constexpr int kQLds = 192 + kQMaxGroup * 9 + 128 + kQMaxGroup * 64 + 384;
+// Dynamic LDS layout of a node in k_qbuild (doubles), sized by the lattice and the group so
+// that four workgroups fit per SIMD: sites [3][64], the sites in FP32 as float4 [64] (128
+// doubles' worth), lattice [3][N_fib] (one array per axis), lattice weights [N_fib] (fixed
+// point), rotations [group][9], bins [group][64] (fixed point)
+__host__ __device__ constexpr int qbuild_lds_doubles(int NF, int group) { return 320 + 4 * NF + 73 * group; }
 
 // p / n for 0 <= p < 1024 and 1 <= n <= 128 with one FP32 multiply: (p + 1/2) / n is at
 // least 1/(2n) >= 2^-8 away from an integer, far above the rounding error of the
 // product (below 2^-12 here, also with a reciprocal a few ulp off)
 __device__ __forceinline__ int small_div(int p, float inv_n) { return (int)(((float)p + 0.5f) * inv_n); }
 
-// Running argmax over the node's out-edge directions for the lane's slots of
-// (direction, lattice point) pairs.  Ties go to the lowest index: the index moves only
-// on a strict increase, and the running maximum (fmax) equals the kept value on ties.
-// Only the first S slots are scanned (S covers the group's pairs; slots past its last pair
-// within them hold repeats and are scanned too).
-template <int S>
-__device__ __forceinline__ void own_scan(int d, const double *sx, const double *sy, const double *sz,
-                                         const double (&q0)[kQSlots], const double (&q1)[kQSlots],
-                                         const double (&q2)[kQSlots], double (&best)[kQSlots], int (&own)[kQSlots]) {
+// q = R^T p for lattice point (x, y, z) (R row-major, 9 doubles)
+__device__ __forceinline__ void rotate_point(const double *R, double x, double y, double z, double &q0, double &q1,
+                                             double &q2) {
 #pragma clang fp contract(off)
-#pragma unroll 2
-    for (int m = 0; m < d; ++m) {
-        const double tx = sx[m], ty = sy[m], tz = sz[m];
+    q0 = fma(R[6], z, fma(R[3], y, R[0] * x));
+    q1 = fma(R[7], z, fma(R[4], y, R[1] * x));
+    q2 = fma(R[8], z, fma(R[5], y, R[2] * x));
+}
+
+// The FP32 screen.  For a slot with FP64 rotated point q and every out-edge m it forms
+//   t_m = fma(q2, s_m2, fma(q1, s_m1, fma(q0, s_m0, c))),  c = 1 + 2^-10,
+// from the FP32 roundings of q and s_m, replaces the low six bits of t_m's bit pattern by
+// 63 - m (t_m is positive, so the patterns order like the values and the packed maximum
+// names its index), and keeps the largest packed value P_b and the second largest P_2.
+// Error bound: with |q|, |s_m| <= 1 + 2^-49, rounding q and s to FP32 moves q.s by at most
+// 2^-23 (1 + 2^-24), each of the three FMAs (results in [2^-11, 2.01]) rounds by at most
+// 2^-23, and the packing moves a value by less than 64 ulp <= 2^-17 P, so every packed P_m
+// lies within E_m = 2^-17 P_m + 2^-20 of c + q.s_m, while the FP64 sequence lies within
+// 2^-51 of q.s_m.  If P_b - P_2 > 2^-16 P_b + 2^-18 (>= E_b + E_2 + 2^-50) then for every
+// m != b the FP64 value of m is strictly below that of b: b is the FP64 argmax, with no tie.
+// Other slots (near-ties: about one pair in 4000 on jittered grids) rerun the FP64 scan.
+constexpr float kScreenOff = 1.0f + 0x1p-10f;
+
+// one bitfield insert, (63 & k) | (~63 & t), under the inline constant 63 (written out: the
+// compiler splits the plain expression into an AND with a literal and an OR)
+__device__ __forceinline__ float screen_pack(float t, int k) {
+    float r;
+    asm("v_bfi_b32 %0, 63, %1, %2" : "=v"(r) : "s"(k), "v"(t));
+    return r;
+}
+
+// Owners of the lane's first S slots of (direction, lattice point) pairs (S covers the
+// group's pairs; slots past its last pair within them hold repeats and are scanned too).
+template <int S>
+__device__ __forceinline__ void screen_owners(int d, const float4 *s4, const double *sx, const double *sy,
+                                              const double *sz, const double *Rg, const double *lt, int lane, int np,
+                                              int NF, float inv_nf, const float (&f0)[kQSlots],
+                                              const float (&f1)[kQSlots], const float (&f2)[kQSlots], bool screen,
+                                              int (&own)[kQSlots]) {
+#pragma clang fp contract(off)
+    float best[S], second[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        best[j] = 0.0f;
+        second[j] = 0.0f;
+    }
+    // two out-edges per step: the top two of (best, second, p, w) are max3(best, p, w) and
+    // max(second, med3(best, p, w)) since second <= best
+    int m = 0;
+    for (; m + 1 < d; m += 2) {
+        const float4 t = s4[m], u = s4[m + 1];
 #pragma unroll
         for (int j = 0; j < S; ++j) {
-            const double v = fma(q2[j], tz, fma(q1[j], ty, q0[j] * tx));
-            own[j] = v > best[j] ? m : own[j];
-            best[j] = fmax(best[j], v);
+            const float pv = screen_pack(fmaf(f2[j], t.z, fmaf(f1[j], t.y, fmaf(f0[j], t.x, kScreenOff))), 63 - m);
+            const float pw = screen_pack(fmaf(f2[j], u.z, fmaf(f1[j], u.y, fmaf(f0[j], u.x, kScreenOff))), 62 - m);
+            second[j] = fmaxf(second[j], __builtin_amdgcn_fmed3f(best[j], pv, pw));
+            best[j] = fmaxf(fmaxf(best[j], pv), pw);
         }
+    }
+    if (m < d) {
+        const float4 t = s4[m];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const float pv = screen_pack(fmaf(f2[j], t.z, fmaf(f1[j], t.y, fmaf(f0[j], t.x, kScreenOff))), 63 - m);
+            second[j] = __builtin_amdgcn_fmed3f(best[j], second[j], pv);
+            best[j] = fmaxf(best[j], pv);
+        }
+    }
+    unsigned pending = 0;  // slots the screen does not certify
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        own[j] = 63 - (int)(__float_as_uint(best[j]) & 63u);
+        if (!(screen && best[j] - second[j] > fmaf(best[j], 0x1p-16f, 0x1p-18f))) pending |= 1u << j;
+    }
+    // each lane decides its pending slots with the FP64 sequence (one slot per pass: lanes
+    // with different pending slots share the passes); ties go to the lowest index, the index
+    // moving only on a strict increase
+    while (pending) {
+        const int j = __builtin_ctz(pending);
+        pending &= pending - 1;
+        const int p = min(j * 64 + lane, np - 1);
+        const int al = small_div(p, inv_nf), i = p - al * NF;
+        double q0, q1, q2;
+        rotate_point(Rg + 9 * al, lt[i], lt[NF + i], lt[2 * NF + i], q0, q1, q2);
+        double bb = -__builtin_inf();
+        int o = 0;
+        for (int k = 0; k < d; ++k) {
+            const double v = fma(q2, sz[k], fma(q1, sy[k], q0 * sx[k]));
+            o = v > bb ? k : o;
+            bb = fmax(bb, v);
+        }
+#pragma unroll
+        for (int jj = 0; jj < S; ++jj) own[jj] = jj == j ? o : own[jj];
     }
 }
 
@@ -76,14 +157,15 @@ __global__ __launch_bounds__(64) void k_qbuild(
     const float *__restrict__ frac, double sun_x, double sun_y, double sun_z, Real mu0, const Real *__restrict__ T,
     const Real *__restrict__ rho, const Real *__restrict__ Tsun, const long long *__restrict__ nodeoff,
     BlkT *__restrict__ val, Real *__restrict__ S, float *__restrict__ qsun, int group, int per, long long wx,
-    long long wy) {
+    long long wy, int screen) {
 #pragma clang fp contract(off)
-    __shared__ double smem[kQLds];
-    double *sx = smem, *sy = smem + 64, *sz = smem + 128;
-    double *Rg = smem + 192;
-    unsigned long long *wq = reinterpret_cast<unsigned long long *>(smem + 192 + kQMaxGroup * 9);
-    unsigned long long *bins = wq + 128;
-    double *lt = smem + 192 + kQMaxGroup * 9 + 128 + kQMaxGroup * 64;  // lattice, one array per axis
+    extern __shared__ double qb_lds[];
+    double *sx = qb_lds, *sy = qb_lds + 64, *sz = qb_lds + 128;
+    float4 *s4 = reinterpret_cast<float4 *>(qb_lds + 192);
+    double *lt = qb_lds + 320;  // lattice, one array per axis
+    unsigned long long *wq = reinterpret_cast<unsigned long long *>(qb_lds + 320 + 3 * NF);
+    double *Rg = qb_lds + 320 + 4 * NF;
+    unsigned long long *bins = reinterpret_cast<unsigned long long *>(Rg + 9 * group);
 
     const int l = blockIdx.x;
     const int lane = threadIdx.x;
@@ -100,14 +182,16 @@ __global__ __launch_bounds__(64) void k_qbuild(
         const long long Dy = min_image((long long)pos[3 * j + 1] - pos[3 * l + 1], wy, per & 2);
         const long long Dz = (long long)pos[3 * j + 2] - pos[3 * l + 2];
         const double nrm = sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
-        sx[lane] = (double)Dx / nrm;
-        sy[lane] = (double)Dy / nrm;
-        sz[lane] = (double)Dz / nrm;
+        const double ex = (double)Dx / nrm, ey = (double)Dy / nrm, ez = (double)Dz / nrm;
+        sx[lane] = ex;
+        sy[lane] = ey;
+        sz[lane] = ez;
+        s4[lane] = make_float4((float)ex, (float)ey, (float)ez, 0.0f);
     }
     for (int i = lane; i < NF; i += 64) {
         lt[i] = lat[3 * i];
-        lt[128 + i] = lat[3 * i + 1];
-        lt[256 + i] = lat[3 * i + 2];
+        lt[NF + i] = lat[3 * i + 1];
+        lt[2 * NF + i] = lat[3 * i + 2];
     }
     const float inv_nf = 1.0f / (float)NF, inv_d = 1.0f / (float)d;
     // phase weights of the lattice points in fixed point
@@ -156,33 +240,34 @@ __global__ __launch_bounds__(64) void k_qbuild(
         }
         for (int t = lane; t < ng * 64; t += 64) bins[t] = 0ull;
         __syncthreads();
-        // this lane's pairs: q = R^T p for each, then the running argmax over the sites
+        // this lane's pairs: q = R^T p for each (FP64, rounded to FP32 for the screen), then
+        // the owners
         const int np = ng * NF;  // pairs of this group
-        double q0[kQSlots], q1[kQSlots], q2[kQSlots], best[kQSlots];
+        float f0[kQSlots], f1[kQSlots], f2[kQSlots];
         int own[kQSlots];
 #pragma unroll
         for (int j = 0; j < kQSlots; ++j) {
             const int p = min(j * 64 + lane, np - 1);  // past the last pair: a repeat, not counted
             const int al = small_div(p, inv_nf), i = p - al * NF;
-            const double *R = Rg + 9 * al;
-            const double x = lt[i], y = lt[128 + i], z = lt[256 + i];
-            q0[j] = fma(R[6], z, fma(R[3], y, R[0] * x));
-            q1[j] = fma(R[7], z, fma(R[4], y, R[1] * x));
-            q2[j] = fma(R[8], z, fma(R[5], y, R[2] * x));
-            best[j] = -__builtin_inf();
+            double q0, q1, q2;
+            rotate_point(Rg + 9 * al, lt[i], lt[NF + i], lt[2 * NF + i], q0, q1, q2);
+            f0[j] = (float)q0;
+            f1[j] = (float)q1;
+            f2[j] = (float)q2;
             own[j] = 0;
         }
         // slots per lane that this group's pairs need (a node's last group is often short)
-        if (np <= 2 * 64) own_scan<2>(d, sx, sy, sz, q0, q1, q2, best, own);
-        else if (np <= 4 * 64) own_scan<4>(d, sx, sy, sz, q0, q1, q2, best, own);
-        else if (np <= 6 * 64) own_scan<6>(d, sx, sy, sz, q0, q1, q2, best, own);
-        else own_scan<kQSlots>(d, sx, sy, sz, q0, q1, q2, best, own);
+        const bool scr = screen != 0;
+        if (np <= 2 * 64) screen_owners<2>(d, s4, sx, sy, sz, Rg, lt, lane, np, NF, inv_nf, f0, f1, f2, scr, own);
+        else if (np <= 4 * 64) screen_owners<4>(d, s4, sx, sy, sz, Rg, lt, lane, np, NF, inv_nf, f0, f1, f2, scr, own);
+        else if (np <= 6 * 64) screen_owners<6>(d, s4, sx, sy, sz, Rg, lt, lane, np, NF, inv_nf, f0, f1, f2, scr, own);
+        else screen_owners<kQSlots>(d, s4, sx, sy, sz, Rg, lt, lane, np, NF, inv_nf, f0, f1, f2, scr, own);
 #pragma unroll
         for (int j = 0; j < kQSlots; ++j) {
             const int p = j * 64 + lane;
             if (p < np) {
                 const int al = small_div(p, inv_nf);
-                if (SG_IN(al * 64 + own[j], kQMaxGroup * 64, 0x203)) atomicAdd(&bins[al * 64 + own[j]], wq[p - al * NF]);
+                if (SG_IN(al * 64 + own[j], group * 64, 0x203)) atomicAdd(&bins[al * 64 + own[j]], wq[p - al * NF]);
             }
         }
         __syncthreads();
@@ -872,6 +957,7 @@ template <class Real>
 void launch_qbuild(Scene &s, hipStream_t st, int write_q) {
     const size_t shm = 0;
     const int group = qbuild_group(s.n_fib);
+    const size_t qshm = sizeof(double) * (size_t)qbuild_lds_doubles(s.n_fib, group);
     if (s.sigma_mode == SG_SIGMA_COLOUR) {
         if (write_q) {
             hipLaunchKernelGGL((k_qcolour<Real, float, true>), dim3(s.N), dim3(64), shm, st, s.N, s.n_vol, s.adj_ptr,
@@ -921,17 +1007,17 @@ void launch_qbuild(Scene &s, hipStream_t st, int write_q) {
                                (long long)s.ny * kFx);
     }
     if (write_q) {
-        hipLaunchKernelGGL((k_qbuild<Real, float, true>), dim3(s.N), dim3(64), shm, st, s.N, s.n_vol, s.adj_ptr,
+        hipLaunchKernelGGL((k_qbuild<Real, float, true>), dim3(s.N), dim3(64), qshm, st, s.N, s.n_vol, s.adj_ptr,
                            s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, node_frac(s), s.sun_in[0], s.sun_in[1],
                            s.sun_in[2], (Real)s.mu0, (const Real *)nullptr, (const Real *)nullptr,
                            (const Real *)nullptr, s.nodeoff, s.q, (Real *)nullptr, s.qsun, group, s.periodic, (long long)s.nx * kFx,
-                           (long long)s.ny * kFx);
+                           (long long)s.ny * kFx, s.qscreen);
     } else {
-        hipLaunchKernelGGL((k_qbuild<Real, Real, false>), dim3(s.N), dim3(64), shm, st, s.N, s.n_vol, s.adj_ptr,
+        hipLaunchKernelGGL((k_qbuild<Real, Real, false>), dim3(s.N), dim3(64), qshm, st, s.N, s.n_vol, s.adj_ptr,
                            s.adj_idx, s.pos, s.lat, s.tab, s.n_fib, s.n_phase, node_frac(s), s.sun_in[0], s.sun_in[1],
                            s.sun_in[2], (Real)s.mu0, (const Real *)s.T, (const Real *)s.rho, (const Real *)s.Tsun,
                            s.nodeoff, (Real *)s.val, (Real *)s.S, s.qsun, group, s.periodic, (long long)s.nx * kFx,
-                           (long long)s.ny * kFx);
+                           (long long)s.ny * kFx, s.qscreen);
     }
 }
 

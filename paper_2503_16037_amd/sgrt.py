@@ -214,11 +214,12 @@ def make_desc(scene, keep: list) -> SceneDesc:
     return d
 
 
-SG_NO_GRAPHS, SG_NO_AUTOTUNE = 1, 2
+SG_NO_GRAPHS, SG_NO_AUTOTUNE, SG_EXACT_CELLS = 1, 2, 4
 
 
 def make_opts(precision="fp32", solver="auto", rtol=0.0, max_sweeps=0, gmres_restart=0, scatter_order=0,
-              build_col_idx=False, timing=False, graphs=True, autotune=True, lambda_tile=0) -> SolveOpts:
+              build_col_idx=False, timing=False, graphs=True, autotune=True, lambda_tile=0,
+              screen=True) -> SolveOpts:
     o = SolveOpts()
     o.abi_version = ABI_VERSION
     o.precision = SG_FP64 if precision in ("fp64", SG_FP64) else SG_FP32
@@ -229,7 +230,8 @@ def make_opts(precision="fp32", solver="auto", rtol=0.0, max_sweeps=0, gmres_res
     o.scatter_order = int(scatter_order)
     o.build_col_idx = 1 if build_col_idx else 0
     o.timing = 1 if timing else 0
-    o.flags = (0 if graphs else SG_NO_GRAPHS) | (0 if autotune else SG_NO_AUTOTUNE)
+    o.flags = ((0 if graphs else SG_NO_GRAPHS) | (0 if autotune else SG_NO_AUTOTUNE)
+               | (0 if screen else SG_EXACT_CELLS))
     o.lambda_tile = int(lambda_tile)
     return o
 
