@@ -43,11 +43,11 @@ constexpr double kUnfix = 1.0 / 4503599627370496.0;
 constexpr int kQSlots = 8;     // (direction, lattice point) pairs per lane in a group
 constexpr int kQMaxGroup = 8;  // incoming directions per group
 
-// Dynamic LDS layout of a node in k_qbuild (doubles), sized by the lattice and the group so
-// that four workgroups fit per SIMD: sites [3][64], the sites in FP32 as float4 [64] (128
-// doubles' worth), lattice [3][N_fib] (one array per axis), lattice weights [N_fib] (fixed
-// point), rotations [group][9], bins [group][64] (fixed point)
-__host__ __device__ constexpr int qbuild_lds_doubles(int NF, int group) { return 320 + 4 * NF + 73 * group; }
+// Dynamic LDS layout of a node in k_qbuild (in doubles), sized by the lattice and the group so
+// that four workgroups fit per SIMD: sites [3][64]; in FP32 as float4 (16-byte aligned): the
+// sites [64], the lattice [N_fib], the rotations' columns [group][3]; then lattice weights
+// [N_fib] (fixed point), rotations [group][9] (FP64), bins [group][64] (fixed point)
+__host__ __device__ constexpr int qbuild_lds_doubles(int NF, int group) { return 320 + 3 * NF + 79 * group; }
 
 // p / n for 0 <= p < 1024 and 1 <= n <= 128 with one FP32 multiply: (p + 1/2) / n is at
 // least 1/(2n) >= 2^-8 away from an integer, far above the rounding error of the
@@ -63,18 +63,21 @@ __device__ __forceinline__ void rotate_point(const double *R, double x, double y
     q2 = fma(R[8], z, fma(R[5], y, R[2] * x));
 }
 
-// The FP32 screen.  For a slot with FP64 rotated point q and every out-edge m it forms
-//   t_m = fma(q2, s_m2, fma(q1, s_m1, fma(q0, s_m0, c))),  c = 1 + 2^-10,
-// from the FP32 roundings of q and s_m, replaces the low six bits of t_m's bit pattern by
-// 63 - m (t_m is positive, so the patterns order like the values and the packed maximum
-// names its index), and keeps the largest packed value P_b and the second largest P_2.
-// Error bound: with |q|, |s_m| <= 1 + 2^-49, rounding q and s to FP32 moves q.s by at most
-// 2^-23 (1 + 2^-24), each of the three FMAs (results in [2^-11, 2.01]) rounds by at most
-// 2^-23, and the packing moves a value by less than 64 ulp <= 2^-17 P, so every packed P_m
-// lies within E_m = 2^-17 P_m + 2^-20 of c + q.s_m, while the FP64 sequence lies within
-// 2^-51 of q.s_m.  If P_b - P_2 > 2^-16 P_b + 2^-18 (>= E_b + E_2 + 2^-50) then for every
-// m != b the FP64 value of m is strictly below that of b: b is the FP64 argmax, with no tie.
-// Other slots (near-ties: about one pair in 4000 on jittered grids) rerun the FP64 scan.
+// The FP32 screen.  For a slot with rotated point q and every out-edge m it forms
+//   t_m = fma(q2', s_m2', fma(q1', s_m1', fma(q0', s_m0', c))),  c = 1 + 2^-10,
+// where s' is s_m rounded to FP32 and q' = R'^T p' is the rotation done in FP32 (one multiply,
+// two FMAs per component) from the FP32 roundings R' and p'; it replaces the low six bits of
+// t_m's bit pattern by 63 - m (t_m is positive, so the patterns order like the values and the
+// packed maximum names its index) and keeps the largest packed value P_b and the second
+// largest P_2.  Error bound: with |p|, |s_m| and R's columns of norm <= 1 + 2^-49, every
+// component of q' is within 5 * 2^-24 of q (two input roundings and three operation roundings,
+// each at most 2^-24 times a magnitude <= 1), so q'.s' is within 5 sqrt(3) 2^-24 + 2^-23 <
+// 2^-20.5 of q.s; the three FMAs (results in [2^-11, 2.01]) round by at most 2^-23 each; and the
+// packing moves a value by less than 64 ulp <= 2^-17 P.  So every packed P_m lies within E_m =
+// 2^-17 P_m + 2^-19 of c + q.s_m, while the FP64 sequence lies within 2^-51 of q.s_m.  If
+// P_b - P_2 > 2^-16 P_b + 2^-17 (>= E_b + E_2 + 2^-50) then for every m != b the FP64 value of
+// m is strictly below that of b: b is the FP64 argmax, with no tie.  Other slots (near-ties:
+// a few pairs in 10,000 on jittered grids) rerun the FP64 sequence.
 constexpr float kScreenOff = 1.0f + 0x1p-10f;
 
 // one bitfield insert, (63 & k) | (~63 & t), under the inline constant 63 (written out: the
@@ -89,8 +92,8 @@ __device__ __forceinline__ float screen_pack(float t, int k) {
 // group's pairs; slots past its last pair within them hold repeats and are scanned too).
 template <int S>
 __device__ __forceinline__ void screen_owners(int d, const float4 *s4, const double *sx, const double *sy,
-                                              const double *sz, const double *Rg, const double *lt, int lane, int np,
-                                              int NF, float inv_nf, const float (&f0)[kQSlots],
+                                              const double *sz, const double *Rg, const double *__restrict__ lat,
+                                              int lane, int ng, int NF, float inv_nf, const float (&f0)[kQSlots],
                                               const float (&f1)[kQSlots], const float (&f2)[kQSlots], bool screen,
                                               int (&own)[kQSlots]) {
 #pragma clang fp contract(off)
@@ -126,18 +129,19 @@ __device__ __forceinline__ void screen_owners(int d, const float4 *s4, const dou
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         own[j] = 63 - (int)(__float_as_uint(best[j]) & 63u);
-        if (!(screen && best[j] - second[j] > fmaf(best[j], 0x1p-16f, 0x1p-18f))) pending |= 1u << j;
+        if (!(screen && best[j] - second[j] > fmaf(best[j], 0x1p-16f, 0x1p-17f))) pending |= 1u << j;
     }
     // each lane decides its pending slots with the FP64 sequence (one slot per pass: lanes
     // with different pending slots share the passes); ties go to the lowest index, the index
-    // moving only on a strict increase
+    // moving only on a strict increase.  A slot past the group's last pair takes any valid
+    // direction (its owner is not used).
     while (pending) {
         const int j = __builtin_ctz(pending);
         pending &= pending - 1;
-        const int p = min(j * 64 + lane, np - 1);
-        const int al = small_div(p, inv_nf), i = p - al * NF;
+        const int p = j * 64 + lane;
+        const int al0 = small_div(p, inv_nf), i = p - al0 * NF, al = min(al0, ng - 1);
         double q0, q1, q2;
-        rotate_point(Rg + 9 * al, lt[i], lt[NF + i], lt[2 * NF + i], q0, q1, q2);
+        rotate_point(Rg + 9 * al, lat[3 * i], lat[3 * i + 1], lat[3 * i + 2], q0, q1, q2);
         double bb = -__builtin_inf();
         int o = 0;
         for (int k = 0; k < d; ++k) {
@@ -162,9 +166,10 @@ __global__ __launch_bounds__(64) void k_qbuild(
     extern __shared__ double qb_lds[];
     double *sx = qb_lds, *sy = qb_lds + 64, *sz = qb_lds + 128;
     float4 *s4 = reinterpret_cast<float4 *>(qb_lds + 192);
-    double *lt = qb_lds + 320;  // lattice, one array per axis
-    unsigned long long *wq = reinterpret_cast<unsigned long long *>(qb_lds + 320 + 3 * NF);
-    double *Rg = qb_lds + 320 + 4 * NF;
+    float4 *lt4 = reinterpret_cast<float4 *>(qb_lds + 320);
+    float4 *Rc4 = reinterpret_cast<float4 *>(qb_lds + 320 + 2 * NF);
+    unsigned long long *wq = reinterpret_cast<unsigned long long *>(qb_lds + 320 + 2 * NF + 6 * group);
+    double *Rg = qb_lds + 320 + 3 * NF + 6 * group;
     unsigned long long *bins = reinterpret_cast<unsigned long long *>(Rg + 9 * group);
 
     const int l = blockIdx.x;
@@ -188,12 +193,18 @@ __global__ __launch_bounds__(64) void k_qbuild(
         sz[lane] = ez;
         s4[lane] = make_float4((float)ex, (float)ey, (float)ez, 0.0f);
     }
-    for (int i = lane; i < NF; i += 64) {
-        lt[i] = lat[3 * i];
-        lt[NF + i] = lat[3 * i + 1];
-        lt[2 * NF + i] = lat[3 * i + 2];
-    }
+    for (int i = lane; i < NF; i += 64)
+        lt4[i] = make_float4((float)lat[3 * i], (float)lat[3 * i + 1], (float)lat[3 * i + 2], 0.0f);
     const float inv_nf = 1.0f / (float)NF, inv_d = 1.0f / (float)d;
+    // the lane's slots: slot j holds pair p = 64 j + lane of a group, direction p / N_fib of
+    // the group and lattice point p mod N_fib, kept as direction * 128 + point
+    int sai[kQSlots];
+#pragma unroll
+    for (int j = 0; j < kQSlots; ++j) {
+        const int p = j * 64 + lane;
+        const int al = small_div(p, inv_nf);
+        sai[j] = al * 128 + (p - al * NF);
+    }
     // phase weights of the lattice points in fixed point
     for (int i = lane; i < NF; i += 64) {
         double w;
@@ -215,7 +226,8 @@ __global__ __launch_bounds__(64) void k_qbuild(
     const int n_in = surf ? 1 : d + 1;
     for (int a0 = 0; a0 < n_in; a0 += group) {
         const int ng = min(group, n_in - a0);
-        // rotations of this group's incoming directions, and empty bins
+        // rotations of this group's incoming directions (FP64, and their columns in FP32), and
+        // empty bins
         if (lane < ng) {
             const int a = a0 + lane;
             double *R = Rg + 9 * lane;
@@ -237,38 +249,37 @@ __global__ __launch_bounds__(64) void k_qbuild(
                     R[6] = ux; R[7] = uy; R[8] = uz;
                 }
             }
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                Rc4[3 * lane + k] = make_float4((float)R[k], (float)R[3 + k], (float)R[6 + k], 0.0f);
         }
         for (int t = lane; t < ng * 64; t += 64) bins[t] = 0ull;
         __syncthreads();
-        // this lane's pairs: q = R^T p for each (FP64, rounded to FP32 for the screen), then
-        // the owners
+        // this lane's pairs: q' = R'^T p' in FP32 for each (a slot past the group's last pair
+        // takes the group's last direction: scanned, not counted), then the owners
         const int np = ng * NF;  // pairs of this group
         float f0[kQSlots], f1[kQSlots], f2[kQSlots];
         int own[kQSlots];
 #pragma unroll
         for (int j = 0; j < kQSlots; ++j) {
-            const int p = min(j * 64 + lane, np - 1);  // past the last pair: a repeat, not counted
-            const int al = small_div(p, inv_nf), i = p - al * NF;
-            double q0, q1, q2;
-            rotate_point(Rg + 9 * al, lt[i], lt[NF + i], lt[2 * NF + i], q0, q1, q2);
-            f0[j] = (float)q0;
-            f1[j] = (float)q1;
-            f2[j] = (float)q2;
+            const int al = min(sai[j] >> 7, ng - 1);
+            const float4 pt = lt4[sai[j] & 127], c0 = Rc4[3 * al], c1 = Rc4[3 * al + 1], c2 = Rc4[3 * al + 2];
+            f0[j] = fmaf(c0.z, pt.z, fmaf(c0.y, pt.y, c0.x * pt.x));
+            f1[j] = fmaf(c1.z, pt.z, fmaf(c1.y, pt.y, c1.x * pt.x));
+            f2[j] = fmaf(c2.z, pt.z, fmaf(c2.y, pt.y, c2.x * pt.x));
             own[j] = 0;
         }
         // slots per lane that this group's pairs need (a node's last group is often short)
         const bool scr = screen != 0;
-        if (np <= 2 * 64) screen_owners<2>(d, s4, sx, sy, sz, Rg, lt, lane, np, NF, inv_nf, f0, f1, f2, scr, own);
-        else if (np <= 4 * 64) screen_owners<4>(d, s4, sx, sy, sz, Rg, lt, lane, np, NF, inv_nf, f0, f1, f2, scr, own);
-        else if (np <= 6 * 64) screen_owners<6>(d, s4, sx, sy, sz, Rg, lt, lane, np, NF, inv_nf, f0, f1, f2, scr, own);
-        else screen_owners<kQSlots>(d, s4, sx, sy, sz, Rg, lt, lane, np, NF, inv_nf, f0, f1, f2, scr, own);
+        if (np <= 2 * 64) screen_owners<2>(d, s4, sx, sy, sz, Rg, lat, lane, ng, NF, inv_nf, f0, f1, f2, scr, own);
+        else if (np <= 4 * 64) screen_owners<4>(d, s4, sx, sy, sz, Rg, lat, lane, ng, NF, inv_nf, f0, f1, f2, scr, own);
+        else if (np <= 6 * 64) screen_owners<6>(d, s4, sx, sy, sz, Rg, lat, lane, ng, NF, inv_nf, f0, f1, f2, scr, own);
+        else screen_owners<kQSlots>(d, s4, sx, sy, sz, Rg, lat, lane, ng, NF, inv_nf, f0, f1, f2, scr, own);
 #pragma unroll
         for (int j = 0; j < kQSlots; ++j) {
-            const int p = j * 64 + lane;
-            if (p < np) {
-                const int al = small_div(p, inv_nf);
-                if (SG_IN(al * 64 + own[j], group * 64, 0x203)) atomicAdd(&bins[al * 64 + own[j]], wq[p - al * NF]);
-            }
+            const int al = sai[j] >> 7;  // below ng exactly for the group's pairs
+            if (al < ng && SG_IN(al * 64 + own[j], group * 64, 0x203))
+                atomicAdd(&bins[al * 64 + own[j]], wq[sai[j] & 127]);
         }
         __syncthreads();
         // this group's columns: pair t = (a - a0) d + m is column a, row m
