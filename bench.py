@@ -388,7 +388,7 @@ def bench_graph(args):
            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                           "p99": round(float(np.percentile(lat, 99)), 4)},
            "roofline": {"kernel": "k_graph_pairs (count + fill passes)", "bound": "alu",
-                        "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "T FP64 lane-op/s",
+                        "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "T lane-op/s",
                         "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
                         "algorithmic_per_launch": ops / 2, "avg_launch_ms": round(ms_pairs / 2, 5)},
            "graph": {"pairs_in_all": N * (N - 1) // 2, "pairs_evaluated": inf["pairs_evaluated"],
@@ -506,7 +506,7 @@ def main():
         issued = QBUILD_OPS_ISSUED_PER_PAIR * qpairs / (stages["ms_qbuild"] * 1e-3) / 1e12
         roof = {"kernel": ("k_qcolour" if args.sigma == "colour" else "k_qbuild") + " (phase cells + K values + source)",
                 "bound": "alu",
-                "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "T FP64 lane-op/s",
+                "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "T lane-op/s",
                 "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": measured_traffic("k_qbuild", args.workload),
                 "algorithmic_per_launch": qops, "ops_per_pair": QBUILD_OPS_PER_PAIR,
                 "avg_launch_ms": round(stages["ms_qbuild"], 4),
@@ -521,7 +521,7 @@ def main():
     # the phase cells against the ALU peak whichever kernel dominates the step
     cell_roof = {"kernel": "k_qcolour" if args.sigma == "colour" else "k_qbuild", "bound": "alu",
                  "avg_launch_ms": round(stages["ms_qbuild"], 4), "ops_per_pair": QBUILD_OPS_PER_PAIR,
-                 "achieved": round(qops / (stages["ms_qbuild"] * 1e-3) / 1e12, 3), "unit": "T FP64 lane-op/s",
+                 "achieved": round(qops / (stages["ms_qbuild"] * 1e-3) / 1e12, 3), "unit": "T lane-op/s",
                  "frac": round(qops / (stages["ms_qbuild"] * 1e-3) / 1e12 / ALU_PEAK_TOPS, 4),
                  "owners": "FP64 scan only" if args.exact_cells else "FP32 screen, FP64 scan where uncertified"}
     sweep_roof = {"kernel": "k_spmv", "avg_launch_ms": round(spmv_avg_ms, 5), "bytes_per_launch": round(sbytes),
