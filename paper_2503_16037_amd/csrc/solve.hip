@@ -133,6 +133,19 @@ __device__ __forceinline__ double bcast(double v, int m) {
 // (consecutive lanes, consecutive addresses).  The caller issues its other loads around
 // this call; xl holds the input of in-edge `lane` (lane m's value is broadcast).
 // blk == NULL: no LDS slice, every lane reads its row from memory.
+constexpr int kStage = 16;  // block loads in flight per lane
+
+// n passes of 64 consecutive block elements from t0 into the wavefront's LDS slice
+template <int n, class Real>
+__device__ __forceinline__ void stage_passes(const Real *__restrict__ blk_g, Real *__restrict__ blk, int t0, int nq,
+                                             int lane) {
+    Real v[n];
+#pragma unroll
+    for (int j = 0; j < n; ++j) v[j] = blk_g[min(t0 + j * 64 + lane, nq - 1)];
+#pragma unroll
+    for (int j = 0; j < n; ++j) blk[min(t0 + j * 64 + lane, nq - 1)] = v[j];
+}
+
 template <class Acc, class Real, class XT>
 __device__ __forceinline__ Acc node_row(const Real *__restrict__ blk_g, Real *__restrict__ blk, int d, int lane,
                                         XT xl) {
@@ -142,16 +155,19 @@ __device__ __forceinline__ Acc node_row(const Real *__restrict__ blk_g, Real *__
             for (int m = 0; m < d; ++m) acc += (Acc)blk_g[(long long)m * d + lane] * (Acc)bcast(xl, m);
         return acc;
     }
-    // branch-free: out-of-range lanes reload and rewrite the last element, so the loads
-    // are issued back to back and waited for once
-    constexpr int kStage = 16;
+    // as many 64-element passes as the block needs, at most kStage at a time (a wave-uniform
+    // switch into straight-line copies, so the loads are issued back to back and waited for
+    // once); lanes past the block's end reload and rewrite its last element
     const int nq = d * d;
     for (int t0 = 0; t0 < nq; t0 += 64 * kStage) {
-        Real v[kStage];
-#pragma unroll
-        for (int j = 0; j < kStage; ++j) v[j] = blk_g[min(t0 + j * 64 + lane, nq - 1)];
-#pragma unroll
-        for (int j = 0; j < kStage; ++j) blk[min(t0 + j * 64 + lane, nq - 1)] = v[j];
+        switch (min(kStage, (nq - t0 + 63) >> 6)) {
+#define SG_STAGE_CASE(n) \
+    case n: stage_passes<n>(blk_g, blk, t0, nq, lane); break;
+            SG_STAGE_CASE(1) SG_STAGE_CASE(2) SG_STAGE_CASE(3) SG_STAGE_CASE(4) SG_STAGE_CASE(5) SG_STAGE_CASE(6)
+            SG_STAGE_CASE(7) SG_STAGE_CASE(8) SG_STAGE_CASE(9) SG_STAGE_CASE(10) SG_STAGE_CASE(11) SG_STAGE_CASE(12)
+            SG_STAGE_CASE(13) SG_STAGE_CASE(14) SG_STAGE_CASE(15) default: stage_passes<kStage>(blk_g, blk, t0, nq, lane);
+#undef SG_STAGE_CASE
+        }
     }
     __builtin_amdgcn_wave_barrier();
     Acc acc = (Acc)0;
