@@ -108,7 +108,7 @@ Shape time_candidates(hipStream_t st, const std::vector<Shape> &cands, F &&launc
 
 std::vector<Shape> grid_candidates(int groups, int tile = 0) {
     std::vector<Shape> c;
-    for (int g : {256, 512, 768, 1024, 1536, 2048, 3072, 4096})
+    for (int g : {256, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192, 12288, 16384})
         if (g < groups) c.push_back({g, tile});
     c.push_back({groups, tile});  // one node group per workgroup
     return c;

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int N, int groups, const 
         const Real sb = S[b];
         const Real xb = monitor ? x[b] : (Real)0;  // the previous value only for the measures
         const Real xl = x[rv];
-        const Real acc = node_row<Real>(val + base, blk, d, lane, xl);
+        const Real acc = node_row<Real>(val + base, d <= dmax ? blk : nullptr, d, lane, xl);
         double r = 0.0, u = 0.0;
         if (act) {
             const Real yn = sb + acc;
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_residual64(int N, int groups, 
         const int rv = SG_IN(rv0, adj_ptr[N], 0x304) ? rv0 : (int)b;
         const double sb = (double)S[b], xb = x[b];
         const double xl = x[rv];
-        const double acc = node_row<double>(val + base, blk, d, lane, xl);
+        const double acc = node_row<double>(val + base, d <= dmax ? blk : nullptr, d, lane, xl);
         double a = 0.0, u = 0.0;
         if (act) {
             const double rb = (sb - xb) + acc;
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_apply_imk64(int N, const long 
     const long long b = off + min(lane, d - 1);
     const int rv0 = rev[b];
     const double xl = v[SG_IN(rv0, adj_ptr[N], 0x306) ? rv0 : (int)b];
-    const double acc = node_row<double>(val + base, blk, d, lane, xl);
+    const double acc = node_row<double>(val + base, d <= dmax ? blk : nullptr, d, lane, xl);
     if (act) wv[b] = v[b] - acc;
 }
 
@@ -563,16 +563,19 @@ inline int grid_for(long long n) {
 
 int spmv_blocks(const Scene &s) { return (s.N + kNodesPerSpmvBlock - 1) / kNodesPerSpmvBlock; }
 
-// LDS of a sweep workgroup: one node block per wavefront, at most 64 KiB (FP32 always
-// fits, dmax <= 64); beyond it (FP64, dmax > 45) the kernels read rows from memory
+// LDS of a sweep workgroup: one node block per wavefront, sized for degree up to 32 (a
+// 4 KB FP32 slice, so eight wavefronts per SIMD fit; a radius graph's nodes above it are a
+// few in a million) and at most 64 KiB; the rows of larger nodes are read from memory (the
+// same products in the same order)
+constexpr int kLdsDegree = 32;
 template <class Real>
 static size_t block_lds(const Scene &s) {
-    const int dm = std::min(s.dmax, kWave);  // nodes of higher degree have their own kernels
+    const int dm = std::min(s.dmax, kLdsDegree);
     const size_t b = (size_t)kNodesPerSpmvBlock * dm * dm * sizeof(Real);
     return b <= 64 * 1024 ? b : 0;
 }
 template <class Real>
-static int lds_dmax(const Scene &s) { return block_lds<Real>(s) ? std::min(s.dmax, kWave) : 0; }
+static int lds_dmax(const Scene &s) { return block_lds<Real>(s) ? std::min(s.dmax, kLdsDegree) : 0; }
 
 // default launch shape of the sweeps: one group of four nodes per workgroup (the kernels
 // also run persistent over fewer workgroups; the tuner measures both)
