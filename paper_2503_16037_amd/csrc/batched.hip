@@ -60,6 +60,17 @@ __device__ __forceinline__ float edge_T(float ts, float ta, float s) {
     return __builtin_amdgcn_exp2f(-(ts + s * ta) * 1.4426950408889634f);
 }
 
+// n passes of 64 consecutive block elements from t0 into the wavefront's LDS slice
+template <int n>
+__device__ __forceinline__ void stage_q(const float *__restrict__ qg, float *__restrict__ qs, int t0, int nq,
+                                        int lane) {
+    float v[n];
+#pragma unroll
+    for (int j = 0; j < n; ++j) v[j] = qg[min(t0 + j * 64 + lane, nq - 1)];
+#pragma unroll
+    for (int j = 0; j < n; ++j) qs[min(t0 + j * 64 + lane, nq - 1)] = v[j];
+}
+
 template <int DB, class XT, class YT, class AccT, bool kResidual>
 __device__ __forceinline__ float2 wide_node(int l, int lane, int lam, bool lv, float s, int nl, int monitor,
                                             float *__restrict__ qs, const long long *__restrict__ adj_ptr,
@@ -74,19 +85,25 @@ __device__ __forceinline__ float2 wide_node(int l, int lane, int lam, bool lv, f
     const int d = (int)(adj_ptr[l + 1] - off);
     const long long base = nodeoff[l];
     // per in-edge data in lane m (lanes past d repeat the last in-edge), then the node's
-    // phase-cell block into this wavefront's LDS slice; all loads branch-free, so they
-    // are issued back to back (out-of-range lanes reload and rewrite the last element)
+    // phase-cell block into this wavefront's LDS slice: as many 64-element passes as the
+    // block needs, at most 16 at a time (a wave-uniform switch into straight-line copies,
+    // so the loads are issued back to back; out-of-range lanes reload and rewrite the last
+    // element)
     const long long em = off + min(lane, d - 1);
     const int rv = rev[em];
     const float ts = tau_s[em], ta = tau_a[em];
     {
         const int nq = d * d;
-        for (int t0 = lane; t0 < nq; t0 += 64 * kU) {
-            float v[kU];
-#pragma unroll
-            for (int j = 0; j < kU; ++j) v[j] = q[base + min(t0 + j * 64, nq - 1)];
-#pragma unroll
-            for (int j = 0; j < kU; ++j) qs[min(t0 + j * 64, nq - 1)] = v[j];
+        for (int t0 = 0; t0 < nq; t0 += 64 * 16) {
+            switch (min(16, (nq - t0 + 63) >> 6)) {
+#define SG_STAGE_CASE(n) \
+    case n: stage_q<n>(q + base, qs, t0, nq, lane); break;
+                SG_STAGE_CASE(1) SG_STAGE_CASE(2) SG_STAGE_CASE(3) SG_STAGE_CASE(4) SG_STAGE_CASE(5)
+                SG_STAGE_CASE(6) SG_STAGE_CASE(7) SG_STAGE_CASE(8) SG_STAGE_CASE(9) SG_STAGE_CASE(10)
+                SG_STAGE_CASE(11) SG_STAGE_CASE(12) SG_STAGE_CASE(13) SG_STAGE_CASE(14) SG_STAGE_CASE(15)
+                default: stage_q<16>(q + base, qs, t0, nq, lane);
+#undef SG_STAGE_CASE
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
