@@ -1,12 +1,14 @@
 // Beer-Lambert-Bouguer transmittances by exact voxel marches (Sec. 2, Eq. 3;
 // the exp(-integral mu_e) factor of Eq. 6, Eq. 9 and Eq. 11).
 //
-// Edge march: every directed edge is walked from the lower to the higher node
-// id, so both directions of a pair carry bit-identical values.  A workgroup
-// takes a run of consecutive tail nodes, reduces the bounding box of all its
-// edges' end voxels, stages that brick of the two extinction channels (mu_s,
-// mu_a) in LDS, and marches its edges from LDS; a brick larger than the LDS
-// budget falls back to global (L2-resident) reads.
+// Edge march: each coupling is walked once, from the lower to the higher node id,
+// and its values are written to both directed edges (the reverse edge's index from
+// the structure pass), so both directions carry bit-identical values.  A workgroup
+// takes a run of consecutive tail nodes and their forward edges (head id above the
+// tail's: a suffix of each sorted row), spread evenly over its threads; it reduces
+// the bounding box of those edges' end voxels, stages that brick of the two
+// extinction channels (mu_s, mu_a) in LDS, and marches the edges from LDS; a brick
+// larger than the LDS budget falls back to global (L2-resident) reads.
 // Two channels are kept per path (tau_s, tau_a), so any wavelength's optical
 // depth is tau_s + s * tau_a (the per-basis path arrays of Sec. 3).
 #include "device.hpp"
@@ -31,26 +33,45 @@ template <class Real, bool kPer>
 __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
     int N, int nx, int ny, int nz, int per_arg, const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx,
     const int *__restrict__ pos, const float *__restrict__ mu_s, const float *__restrict__ mu_a, Real len_scale,
-    Real scale, Real *__restrict__ tau_s, Real *__restrict__ tau_a, Real *__restrict__ T, int use_lds) {
+    Real scale, const int *__restrict__ rev, Real *__restrict__ tau_s, Real *__restrict__ tau_a,
+    Real *__restrict__ T, int use_lds) {
     const int per = kPer ? per_arg : 0;
     __shared__ float bs[kBrickCap];
     __shared__ float ba[kBrickCap];
-    __shared__ long long sptr[kNodesPerBlock + 1];
+    __shared__ long long fbeg[kNodesPerBlock];  // first forward edge of each node
+    __shared__ int fptr[kNodesPerBlock + 1];    // exclusive prefix of forward edge counts
     __shared__ int bb[6];
     const int l0 = blockIdx.x * kNodesPerBlock;
     const int l1 = min(N, l0 + kNodesPerBlock);
     const int nl = l1 - l0;
-    if (threadIdx.x <= nl) sptr[threadIdx.x] = adj_ptr[l0 + threadIdx.x];
+    if (threadIdx.x < nl) {  // a row is sorted by head id: its forward edges are a suffix
+        const int l = l0 + threadIdx.x;
+        long long lo = adj_ptr[l], hi = adj_ptr[l + 1];
+        const long long end = hi;
+        while (lo < hi) {
+            const long long mid = (lo + hi) >> 1;
+            if (adj_idx[mid] <= l) lo = mid + 1; else hi = mid;
+        }
+        fbeg[threadIdx.x] = lo;
+        fptr[threadIdx.x + 1] = (int)(end - lo);
+    }
     if (threadIdx.x < 3) bb[threadIdx.x] = 1 << 30;
     else if (threadIdx.x < 6) bb[threadIdx.x] = -(1 << 30);
     __syncthreads();
-    const long long e0 = sptr[0], e1 = sptr[nl];
-    // bounding box of all end voxels of the block's edges: per-thread, then per wave
-    // (butterfly), then one LDS atomic per wave and coordinate
+    if (threadIdx.x == 0) {
+        fptr[0] = 0;
+        for (int k = 0; k < nl; ++k) fptr[k + 1] += fptr[k];
+    }
+    __syncthreads();
+    const int nf = fptr[nl];
+    // bounding box of the end voxels of the block's forward edges: per-thread, then per
+    // wave (butterfly), then one LDS atomic per wave and coordinate
     int mnx = 1 << 30, mny = 1 << 30, mnz = 1 << 30, mxx = -(1 << 30), mxy = -(1 << 30), mxz = -(1 << 30);
-    for (long long e = e0 + threadIdx.x; e < e1; e += kMarchThreads) {
+    for (int f = threadIdx.x; f < nf; f += kMarchThreads) {
+        int k = 0;
+        while (k + 1 < nl && fptr[k + 1] <= f) ++k;
         int vx, vy, vz;
-        node_voxel(pos, adj_idx[e], vx, vy, vz);
+        node_voxel(pos, adj_idx[fbeg[k] + (f - fptr[k])], vx, vy, vz);
         mnx = min(mnx, vx); mny = min(mny, vy); mnz = min(mnz, vz);
         mxx = max(mxx, vx); mxy = max(mxy, vy); mxz = max(mxz, vz);
     }
@@ -71,7 +92,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
         atomicMax(&bb[3], mxx); atomicMax(&bb[4], mxy); atomicMax(&bb[5], mxz);
     }
     __syncthreads();
-    if (e0 == e1) return;
+    if (nf == 0) return;
     const int bx0 = bb[0], by0 = bb[1], bz0 = bb[2];
     const int bw = bb[3] - bx0 + 1, bh = bb[4] - by0 + 1, bd = bb[5] - bz0 + 1;
     const bool lds = use_lds && (long long)bw * bh * bd <= kBrickCap;
@@ -88,13 +109,16 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
         }
     }
     __syncthreads();
-    for (long long e = e0 + threadIdx.x; e < e1; e += kMarchThreads) {
+    for (int f = threadIdx.x; f < nf; f += kMarchThreads) {
         int k = 0;
-        while (k + 1 < nl && sptr[k + 1] <= e) ++k;
+        while (k + 1 < nl && fptr[k + 1] <= f) ++k;
+        const long long e = fbeg[k] + (f - fptr[k]);
         const int l = l0 + k;
         const int j = adj_idx[e];
         if (!SG_IN(j, N, 0x103)) continue;
-        const int a = min(l, j), b = max(l, j);
+        const int er = rev[e];  // the edge j -> l
+        if (!SG_IN(er, adj_ptr[N], 0x107)) continue;
+        const int a = l, b = j;  // a < b
         const long long px = pos[3 * a], py = pos[3 * a + 1], pz = pos[3 * a + 2];
         const long long dx = min_image(pos[3 * b] - px, nx * kFx, per & 1);
         const long long dy = min_image(pos[3 * b + 1] - py, ny * kFx, per & 2);
@@ -135,7 +159,13 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
         sa *= L;
         tau_s[e] = ss;
         tau_a[e] = sa;
-        if (T) T[e] = exp(-(ss + scale * sa));
+        tau_s[er] = ss;
+        tau_a[er] = sa;
+        if (T) {
+            const Real t = exp(-(ss + scale * sa));
+            T[e] = t;
+            T[er] = t;
+        }
     }
 }
 
@@ -258,8 +288,8 @@ void launch_march(Scene &s, hipStream_t st, float scale, int use_lds) {
     // the bounded-grid instantiations carry no periodic branches
     const auto edges = s.periodic ? k_march_edges<Real, true> : k_march_edges<Real, false>;
     hipLaunchKernelGGL(edges, dim3(nb), dim3(kMarchThreads), 0, st, s.N, s.nx, s.ny, s.nz, s.periodic, s.adj_ptr,
-                       s.adj_idx, s.pos, s.mu_s, s.mu_a, len_scale, (Real)scale, (Real *)s.tau_s, (Real *)s.tau_a,
-                       (Real *)s.T, use_lds);
+                       s.adj_idx, s.pos, s.mu_s, s.mu_a, len_scale, (Real)scale, s.rev, (Real *)s.tau_s,
+                       (Real *)s.tau_a, (Real *)s.T, use_lds);
     float smin = scale;
     if (s.n_lambda > 1) {
         smin = s.abs_scale[0];
