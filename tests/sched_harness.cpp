@@ -1,9 +1,13 @@
 // The server's scheduler (paper_2503_16037_amd/csrc/sched.hpp) driven by a scripted backend
 // on the CPU: no device, each "run" takes a request's scripted bytes from a budget, holds
-// them for a few milliseconds and gives them back, or fails as scripted.  One scenario per
-// run (argument), printing "ok <name>" or "FAIL <name>: <why>"; exit status 0 when it holds.
+// them for a few milliseconds (or, gated, until the scenario releases it) and gives them
+// back, or fails as scripted.  A scenario that needs a request to be still running at some
+// step gates it, so no outcome depends on timing.  One scenario per run (argument),
+// printing "ok <name>" or "FAIL <name>: <why>"; exit status 0 when it holds.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <condition_variable>
 #include <cstdio>
 #include <map>
 #include <memory>
@@ -23,6 +27,7 @@ struct Script {
     int ms = 5;                // how long a run holds them
     int fail_runs = 0;         // injected allocation failures: the first runs fail
     bool gmres_nomem = false;  // the first run fails for a GMRES basis
+    bool gated = false;        // hold the bytes until the scenario opens the gate
 };
 
 struct FakeBackend : public Backend {
@@ -35,6 +40,16 @@ struct FakeBackend : public Backend {
     std::vector<uint64_t> started;              // tickets in the order their runs began
     std::map<uint64_t, std::vector<uint64_t>> bytes_seen;  // reservation at each run
     int released = 0;
+    std::condition_variable gate_cv;
+    std::map<uint64_t, bool> gate_open;  // by ticket
+
+    void open(uint64_t ticket) {
+        {
+            std::lock_guard<std::mutex> lk(m);
+            gate_open[ticket] = true;
+        }
+        gate_cv.notify_all();
+    }
 
     uint64_t budget() const override { return budget_; }
     uint64_t used() const override { return used_.load(); }
@@ -81,7 +96,12 @@ struct FakeBackend : public Backend {
         int mr = max_running.load();
         while (rn > mr && !max_running.compare_exchange_weak(mr, rn)) {
         }
-        std::this_thread::sleep_for(std::chrono::milliseconds(sc.ms));
+        if (sc.gated) {
+            std::unique_lock<std::mutex> lk(m);
+            gate_cv.wait(lk, [&] { return gate_open[r.ticket]; });
+        } else {
+            std::this_thread::sleep_for(std::chrono::milliseconds(sc.ms));
+        }
         --running;
         used_ -= sc.need;
         r.radiance.assign(1, (double)r.ticket);
@@ -126,7 +146,27 @@ struct Run {
     void wait_running(int n) {
         while (be.running.load() < n) std::this_thread::sleep_for(std::chrono::microseconds(200));
     }
+    // polls cond (under the scheduler's lock) for up to 60 s
+    template <class F>
+    bool wait_until(F &&cond) {
+        const auto t0 = std::chrono::steady_clock::now();
+        while (std::chrono::steady_clock::now() - t0 < std::chrono::seconds(60)) {
+            {
+                std::lock_guard<std::mutex> lk(s.mu);
+                if (cond()) return true;
+            }
+            std::this_thread::sleep_for(std::chrono::microseconds(200));
+        }
+        return false;
+    }
 };
+
+Script held(uint64_t need) {
+    Script sc;
+    sc.need = need;
+    sc.gated = true;
+    return sc;
+}
 
 bool fail(const char *name, const std::string &why) {
     std::printf("FAIL %s: %s\n", name, why.c_str());
@@ -149,10 +189,16 @@ bool admission() {
 // waits for it (no overtaking).
 bool fifo() {
     Run r(3, 64, 100);
-    r.submit(60, Script{60, 60});
+    r.submit(60, held(60));
     r.wait_running(1);
     r.submit(60, Script{60, 5});  // does not fit next to the first
     r.submit(10, Script{10, 5});  // would fit, but is behind it
+    std::this_thread::sleep_for(std::chrono::milliseconds(30));  // room to overtake, if it would
+    {
+        std::lock_guard<std::mutex> lk(r.be.m);
+        if (r.be.started.size() != 1) return fail("fifo", "a queued request started next to the held one");
+    }
+    r.be.open(r.tickets[0]);
     for (auto t : r.tickets)
         if (r.wait(t) != SG_OK) return fail("fifo", "a request failed");
     const auto &o = r.be.started;
@@ -163,11 +209,12 @@ bool fifo() {
 // A full queue refuses with SG_E_BUSY, and takes requests again once it has room.
 bool backpressure() {
     Run r(1, 2, 100);
-    r.submit(10, Script{10, 150});
+    r.submit(10, held(10));
     r.wait_running(1);
     if (r.submit(10, Script{10, 1}) != SG_OK || r.submit(10, Script{10, 1}) != SG_OK)
         return fail("backpressure", "queue refused below its capacity");
     if (r.submit(10, Script{10, 1}) != SG_E_BUSY) return fail("backpressure", "full queue accepted a request");
+    r.be.open(r.tickets[0]);
     for (auto t : r.tickets)
         if (r.wait(t) != SG_OK) return fail("backpressure", "a request failed");
     if (r.submit(10, Script{10, 1}) != SG_OK) return fail("backpressure", "drained queue refused");
@@ -184,9 +231,11 @@ bool over_budget() {
 // A request that runs out of budget in the mix goes back to the queue and succeeds later.
 bool requeue_in_mix() {
     Run r(2, 8, 100);
-    r.submit(50, Script{50, 80});  // holds its bytes while the next one starts
+    r.submit(50, held(50));       // holds its bytes while the next one starts
     r.wait_running(1);
-    r.submit(50, Script{60, 5});   // needs more than reserved: 50 + 60 > 100
+    r.submit(50, Script{60, 5});  // needs more than reserved: 50 + 60 > 100
+    if (!r.wait_until([&] { return r.s.n_requeued >= 1; })) return fail("requeue_in_mix", "nothing was requeued");
+    r.be.open(r.tickets[0]);
     for (auto t : r.tickets)
         if (r.wait(t) != SG_OK) return fail("requeue_in_mix", "a request failed");
     if (r.s.n_requeued < 1) return fail("requeue_in_mix", "nothing was requeued");
@@ -256,13 +305,14 @@ bool injected() {
 // finished one is not touched.
 bool cancel() {
     Run r(1, 8, 100);
-    r.submit(10, Script{10, 100});
+    r.submit(10, held(10));
     r.wait_running(1);
     r.submit(10, Script{10, 1});
     r.submit(10, Script{10, 1});
     std::string err;
     if (r.s.cancel(r.tickets[1], err) != SG_OK) return fail("cancel", "queued request not cancelled");
     if (r.s.cancel(r.tickets[0], err) != SG_E_STATE) return fail("cancel", "running request cancelled");
+    r.be.open(r.tickets[0]);
     if (r.wait(r.tickets[1]) != SG_E_CANCELLED) return fail("cancel", "cancelled ticket did not say so");
     if (r.wait(r.tickets[0]) != SG_OK) return fail("cancel", "running request failed");
     for (;;) {  // the third finishes; cancelling it then changes nothing
