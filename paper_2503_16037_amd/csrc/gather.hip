@@ -29,8 +29,10 @@ __device__ __forceinline__ double theta_mix(const PhaseSet &pm, const float *__r
     return th;
 }
 
-// One wavefront per node: lane m takes in-edge m's term, then a fixed-order butterfly sum.
-// frac: the phase fractions at each volume node ([component][node]), nvol volume nodes
+// Two nodes per wavefront, one per 32-lane half: lane m of a half takes in-edges m, m + 32,
+// ..., then a fixed-order butterfly sum within the half (degree ~24 would leave most of a
+// 64-lane wavefront idle).  frac: the phase fractions at each volume node
+// ([component][node]), nvol volume nodes
 template <class Real, bool kPer>
 __global__ __launch_bounds__(256) void k_node_J(int N, int nvol, const long long *__restrict__ adj_ptr,
                                                const int *__restrict__ adj_idx, const int *__restrict__ rev,
@@ -41,15 +43,15 @@ __global__ __launch_bounds__(256) void k_node_J(int N, int nvol, const long long
                                                int multiple, int per_arg, long long wx, long long wy,
                                                double *__restrict__ J) {
     const int per = kPer ? per_arg : 0;
-    const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (l >= N) return;
+    const int l = blockIdx.x * 8 + (threadIdx.x >> 5);
+    const int lane = threadIdx.x & 31;
+    if (l >= N) return;  // a half past the last node exits; the shuffles below stay within a half
     const long long off = adj_ptr[l], end = adj_ptr[l + 1];
     const int d = (int)(end - off);
     const bool vol = l < nvol;
     double acc = 0.0;
     if (multiple) {
-        for (int m = lane; m < d; m += 64) {
+        for (int m = lane; m < d; m += 32) {
             const long long e = off + m;
             double th = 1.0;
             if (!SG_IN(rev[e], adj_ptr[N], 0x501)) continue;
@@ -59,13 +61,15 @@ __global__ __launch_bounds__(256) void k_node_J(int N, int nvol, const long long
                 const long long Dx = min_image((long long)pos[3 * l] - pos[3 * j], wx, per & 1);
                 const long long Dy = min_image((long long)pos[3 * l + 1] - pos[3 * j + 1], wy, per & 2);
                 const long long Dz = (long long)pos[3 * l + 2] - pos[3 * j + 2];
-                const double inv = 1.0 / sqrt((double)(Dx * Dx + Dy * Dy + Dz * Dz));
-                th = theta_mix(pm, frac, nvol, l, ((double)Dx * vx + (double)Dy * vy + (double)Dz * vz) * inv);
+                const double dx = (double)Dx, dy = (double)Dy, dz = (double)Dz;
+                const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+                th = theta_mix(pm, frac, nvol, l, (dx * vx + dy * vy + dz * vz) * inv);
             }
             acc += th * (double)T[e] * phi[rev[e]];
         }
     }
-    acc = wave_sum(acc);
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
     if (lane == 0) {
         const double src = vol ? theta_mix(pm, frac, nvol, l, sx * vx + sy * vy + sz * vz) * (double)Tsun[l]
                                : mu0 * (double)Tsun[l];
@@ -164,7 +168,7 @@ template <class Real>
 void launch_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance) {
     const PhaseSet pm = phase_set(s);
     const auto node_J = s.periodic ? k_node_J<Real, true> : k_node_J<Real, false>;
-    hipLaunchKernelGGL(node_J, dim3((s.N + 3) / 4), dim3(256), 0, st, s.N, s.n_vol, s.adj_ptr, s.adj_idx, s.rev, s.pos,
+    hipLaunchKernelGGL(node_J, dim3((s.N + 7) / 8), dim3(256), 0, st, s.N, s.n_vol, s.adj_ptr, s.adj_idx, s.rev, s.pos,
                        (const Real *)s.T, (const Real *)s.Tsun, phi, pm, node_frac(s), s.sun_in[0], s.sun_in[1], s.sun_in[2],
                        s.view_u[0], s.view_u[1], s.view_u[2], s.mu0, scatter_order == 1 ? 0 : 1, s.periodic,
                        (long long)s.nx * kFx, (long long)s.ny * kFx, s.J);
