@@ -11,6 +11,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -219,6 +220,35 @@ void unit3(const int v[3], double u[3], double sign) {
     u[2] = (double)(long long)(sign * z) / n;
 }
 
+// Host validation of large arrays: check(i) over [0, n) on up to 16 host threads, contiguous
+// ranges; returns the smallest failing index and its message (nullptr: all hold), so the
+// reported failure does not depend on the thread count.
+struct FirstFailure {
+    int64_t index;
+    const char *why;
+};
+template <class F>
+FirstFailure first_failure(int64_t n, F &&check) {
+    const int64_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const int T = (int)std::max<int64_t>(1, std::min<int64_t>({16, hw, n / 65536}));
+    std::vector<FirstFailure> first(T, FirstFailure{n, nullptr});
+    auto run = [&](int t) {
+        const int64_t a = n * t / T, b = n * (t + 1) / T;
+        for (int64_t i = a; i < b; ++i)
+            if (const char *why = check(i)) {
+                first[t] = FirstFailure{i, why};
+                return;
+            }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < T; ++t) th.emplace_back(run, t);
+    run(0);
+    for (auto &x : th) x.join();
+    for (const auto &f : first)
+        if (f.why) return f;  // ranges are in index order
+    return FirstFailure{n, nullptr};
+}
+
 sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz, int &dmax) {
     if (!d) return fail(SG_E_INVALID, "desc is NULL");
     if (d->abi_version != SG_ABI_VERSION) return fail(SG_E_ABI, "scene desc abi_version mismatch");
@@ -274,36 +304,46 @@ sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz,
     const int64_t nvox = (int64_t)d->nx * d->ny * d->nz;
     const int64_t nvol = general ? (int64_t)d->n_nodes : nvox;
     N = nvol + (d->surface_nodes ? (int64_t)d->nx * d->ny : 0);
-    for (int64_t v = 0; v < nvox; ++v) {
-        const float a = d->mu_s[v], b = d->mu_a[v];
-        if (!(a >= 0.0f) || !(b >= 0.0f) || !std::isfinite(a) || !std::isfinite(b))
-            return fail(SG_E_INVALID, "mu_s and mu_a must be finite and >= 0");
+    {
+        const FirstFailure f = first_failure(nvox, [&](int64_t v) -> const char * {
+            const float a = d->mu_s[v], b = d->mu_a[v];
+            return (!(a >= 0.0f) || !(b >= 0.0f) || !std::isfinite(a) || !std::isfinite(b))
+                       ? "mu_s and mu_a must be finite and >= 0"
+                       : nullptr;
+        });
+        if (f.why) return fail(SG_E_INVALID, f.why);
     }
-    if (d->phase_frac)
-        for (int64_t v = 0; v < nvox * d->n_phase; ++v)
-            if (!(d->phase_frac[v] >= 0.0f) || !(d->phase_frac[v] <= 1.0f))
-                return fail(SG_E_INVALID, "phase_frac must be in [0, 1]");
+    if (d->phase_frac) {
+        const FirstFailure f = first_failure(nvox * d->n_phase, [&](int64_t v) -> const char * {
+            return (!(d->phase_frac[v] >= 0.0f) || !(d->phase_frac[v] <= 1.0f)) ? "phase_frac must be in [0, 1]"
+                                                                                  : nullptr;
+        });
+        if (f.why) return fail(SG_E_INVALID, f.why);
+    }
     for (int64_t v = 0; v < (int64_t)d->nx * d->ny; ++v)
         if (!(d->surf_albedo[v] >= 0.0f) || !(d->surf_albedo[v] <= 1.0f))
             return fail(SG_E_INVALID, "surf_albedo must be in [0, 1]");
     if (!general) {
-        for (int64_t v = 0; v < nvox; ++v) {
+        const FirstFailure f = first_failure(nvox, [&](int64_t v) -> const char * {
             const int64_t ix = v % d->nx, iy = (v / d->nx) % d->ny, iz = v / ((int64_t)d->nx * d->ny);
             const int64_t p[3] = {d->vol_pos_fx[3 * v], d->vol_pos_fx[3 * v + 1], d->vol_pos_fx[3 * v + 2]};
             const int64_t c[3] = {ix, iy, iz};
             for (int k = 0; k < 3; ++k)
-                if (!(p[k] > c[k] * 65536 && p[k] < (c[k] + 1) * 65536))
-                    return fail(SG_E_INVALID, "node position not strictly inside its voxel (node " + std::to_string(v) + ")");
-        }
+                if (!(p[k] > c[k] * 65536 && p[k] < (c[k] + 1) * 65536)) return "node position not strictly inside its voxel";
+            return nullptr;
+        });
+        if (f.why) return fail(SG_E_INVALID, std::string(f.why) + " (node " + std::to_string(f.index) + ")");
     } else {
         const int64_t W[3] = {(int64_t)d->nx * 65536, (int64_t)d->ny * 65536, (int64_t)d->nz * 65536};
-        for (int64_t l = 0; l < nvol; ++l)
+        const FirstFailure f = first_failure(nvol, [&](int64_t l) -> const char * {
             for (int k = 0; k < 3; ++k) {
                 const int64_t c = d->node_pos_fx[3 * l + k];
                 const bool per = k < 2 && (d->periodic >> k & 1);
-                if (per ? !(c >= 0 && c < W[k]) : !(c > 0 && c < W[k]))
-                    return fail(SG_E_INVALID, "general node outside the box (node " + std::to_string(l) + ")");
+                if (per ? !(c >= 0 && c < W[k]) : !(c > 0 && c < W[k])) return "general node outside the box";
             }
+            return nullptr;
+        });
+        if (f.why) return fail(SG_E_INVALID, std::string(f.why) + " (node " + std::to_string(f.index) + ")");
         const int64_t npx = (int64_t)d->nx * d->ny;
         if (d->los_ptr[0] != 0) return fail(SG_E_INVALID, "los_ptr[0] must be 0");
         for (int64_t p = 0; p < npx; ++p) {
@@ -337,13 +377,19 @@ sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz,
                                           (wave_only ? "; several wavelengths allow 64)" : ")"));
         dmax = std::max<int>(dmax, (int)deg);
         nnz += deg * deg;
-        for (int64_t e = ap[l]; e < ap[l + 1]; ++e) {
-            const int64_t j = d->adj_idx[e];
-            if (j < 0 || j >= N) return fail(SG_E_INVALID, "adjacency head out of range");
-            if (j == l) return fail(SG_E_INVALID, "self loop");
-            if (e > ap[l] && d->adj_idx[e - 1] >= j) return fail(SG_E_INVALID, "adjacency rows must be strictly ascending");
-            if (l >= nvol && j >= nvol) return fail(SG_E_INVALID, "surface-surface pair");
-        }  // symmetry is checked on the device once the adjacency is uploaded
+    }
+    {  // symmetry is checked on the device once the adjacency is uploaded
+        const FirstFailure f = first_failure(N, [&](int64_t l) -> const char * {
+            for (int64_t e = ap[l]; e < ap[l + 1]; ++e) {
+                const int64_t j = d->adj_idx[e];
+                if (j < 0 || j >= N) return "adjacency head out of range";
+                if (j == l) return "self loop";
+                if (e > ap[l] && d->adj_idx[e - 1] >= j) return "adjacency rows must be strictly ascending";
+                if (l >= nvol && j >= nvol) return "surface-surface pair";
+            }
+            return nullptr;
+        });
+        if (f.why) return fail(SG_E_INVALID, f.why);
     }
     if (d->periodic & ~(SG_PERIODIC_X | SG_PERIODIC_Y))
         return fail(SG_E_INVALID, "periodic must combine SG_PERIODIC_X and SG_PERIODIC_Y");
@@ -361,12 +407,14 @@ sg_status validate(const sg_scene_desc *d, int64_t &N, int64_t &E, int64_t &nnz,
             return (k == 0 ? c % d->nx : c / d->nx) * 65536LL + 32768;
         };
         const long long W[2] = {(long long)d->nx * 65536, (long long)d->ny * 65536};
-        for (int64_t l = 0; l < N; ++l)
+        const FirstFailure f = first_failure(N, [&](int64_t l) -> const char * {
             for (int64_t e = ap[l]; e < ap[l + 1]; ++e)
                 for (int k = 0; k < 2; ++k)
                     if ((d->periodic >> k & 1) && 2 * std::llabs(coord(d->adj_idx[e], k) - coord(l, k)) == W[k])
-                        return fail(SG_E_INVALID, "a coupled pair is exactly half a period apart (node " +
-                                                      std::to_string(l) + ")");
+                        return "a coupled pair is exactly half a period apart";
+            return nullptr;
+        });
+        if (f.why) return fail(SG_E_INVALID, std::string(f.why) + " (node " + std::to_string(f.index) + ")");
     }
     return SG_OK;
 }
