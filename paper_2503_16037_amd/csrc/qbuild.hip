@@ -311,7 +311,9 @@ __global__ __launch_bounds__(64) void k_qbuild(
 // g.  The (direction, lattice point) pairs fill the lanes' eight slots as in k_qbuild, and
 // the node's out-edge directions are formed in LDS 64 at a time and scanned in ascending
 // order with k_qbuild's operation sequence and tie rule, so each direction read from LDS
-// serves eight dot products.  A direction's lattice points have at most N_fib distinct
+// serves eight dot products.  No FP32 screen here: with hundreds to thousands of out-edges
+// the top two of a pair are within the screen's bound far more often (percents of the
+// pairs), and deciding those again cost more than the screen saved.  A direction's lattice points have at most N_fib distinct
 // owners among the d out-edges, so its cell sums go to a 256-slot open-addressing table in
 // LDS (owner -> fixed-point sum, exact integer atomics) rather than d words; the column is
 // then written by looking every row up (absent: 0).

@@ -5,8 +5,9 @@ is proven in its source, and takes every other decision with the FP64 operation 
 SG_EXACT_CELLS takes all of them with the FP64 sequence.  Both must give the same owners,
 hence the same matrix values, sources and radiances bit for bit.  The scenes cover jittered
 grids (few near-ties), nodes at the voxel centres (exact ties everywhere: the fallback
-decides them), two phase components, surfaces, a periodic slab, line-of-sight nodes, both
-precisions and a batch of wavelengths (the Q-only build).
+decides them), two phase components, surfaces, a periodic slab, line-of-sight nodes, nodes of
+degree above 64 (the chunked screen of the high-degree kernel), both precisions and a batch of
+wavelengths (the Q-only build).
 """
 import dataclasses
 import sys
@@ -47,6 +48,29 @@ def los():
     return scenes.with_los_nodes(sc, pos, lp, ln, lt, radius_vox=1.8, name="los-step")
 
 
+def coupled():
+    """Strongest couplings (Eq. 4), 20 per voxel: nodes of degree above 64 (the high-degree
+    kernel, with its chunked screen and second pass)."""
+    sc = scenes.make_random_small(4, nx=8, ny=8, nz=6, kscale=2.0)
+    ap, ai = oracle.coupling_graph(sc, n_pairs=20 * sc.nvox)
+    assert np.diff(ap).max() > 64
+    return dataclasses.replace(sc, adj_ptr=ap, adj_idx=ai, name="coupled-20")
+
+
+def star():
+    """One node coupled to 2000 others on a 17x16x16 grid: 32 chunks of out-edge directions."""
+    sc = scenes.make_random_small(8, nx=17, ny=16, nz=16, kscale=0.5)
+    c = sc.nvox // 2
+    leaves = [v for v in range(sc.nvox) if v != c][:2000]
+    rows = [[] for _ in range(sc.n_nodes)]
+    rows[c] = leaves
+    for v in leaves:
+        rows[v] = [c]
+    ap = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    ai = np.concatenate([np.asarray(r, np.int32) for r in rows if r]).astype(np.int32)
+    return dataclasses.replace(sc, adj_ptr=ap, adj_idx=ai, name="star-2000")
+
+
 SCENES = {
     "plume": lambda: scenes.make_plume(nx=32, ny=32, nz=16),
     "cloud": lambda: scenes.make_cloud(nx=32, ny=32, nz=12),
@@ -54,6 +78,8 @@ SCENES = {
     "slab-centred": lambda: scenes.make_slab(),
     "random-two-phase": lambda: scenes.make_random_small(5, nx=5, ny=4, nz=4, two_phase=True),
     "los": los,
+    "coupled-20": coupled,
+    "star-2000": star,
 }
 
 
