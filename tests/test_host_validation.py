@@ -120,3 +120,18 @@ def test_degree_limits():
     with pytest.raises(sgrt.SgError) as e:
         sgrt.scene_reservation(dataclasses.replace(sc, abs_scale=np.array([1.0, 2.0], np.float32)))
     assert "degree above 64" in str(e.value)
+
+
+def test_first_failure_is_reported_whatever_the_thread_split():
+    """Large arrays are checked on several host threads, each over a contiguous range of
+    nodes; the failure reported is still the one at the lowest index (here positions
+    outside their voxels at nodes 10 and 150,000, in different ranges)."""
+    sc = scenes.make_random_small(3, nx=64, ny=64, nz=40, kscale=2.0)
+    assert sc.nvox > 2 * 65536  # at least two ranges
+    for bad, want in (((10, 150000), 10), ((150000,), 150000)):
+        def plant(p):
+            for v in bad:
+                p[v, 0] = (v % sc.nx + 2) * 65536  # beyond the voxel's x range
+        with pytest.raises(sgrt.SgError) as e:
+            sgrt.scene_reservation(with_array(sc, "vol_pos_fx", plant))
+        assert f"(node {want})" in str(e.value), str(e.value)
