@@ -19,8 +19,8 @@ namespace sg {
 namespace {
 
 constexpr int kMarchThreads = 256;
-constexpr int kNodesPerBlock = 12;
-constexpr int kBrickCap = 4096;  // voxels staged per workgroup (2 channels x 16 KB)
+constexpr int kNodesPerBlock = 32;
+constexpr int kBrickCap = 1024;  // voxels staged per workgroup (2 channels x 4 KB)
 
 __device__ __forceinline__ void node_voxel(const int *__restrict__ pos, int l, int &vx, int &vy, int &vz) {
     vx = pos[3 * l] >> 16;
