@@ -80,33 +80,40 @@ __device__ __forceinline__ long long min_image(long long d, long long w, bool on
     return d;
 }
 
-template <class Visit>
-__device__ __forceinline__ int voxel_walk(int nx, int ny, int nz, int per, long long px, long long py, long long pz,
-                                          long long dx, long long dy, long long dz, bool ray, Visit &&visit) {
+// The walk with its crossing times held in T: long long, or double where every product
+// stays below 2^53 and FP64 therefore represents it exactly (a bounded grid: crossing
+// numerators below 1025 * 2^16, |D| below 2^26, so the products stay below 2^53), which
+// trades the multi-instruction 64-bit integer products for one FP64 multiply each; both
+// give the same voxels and the same num / den.
+template <class T, class Visit>
+__device__ __forceinline__ int voxel_walk_t(int nx, int ny, int nz, int per, long long px, long long py, long long pz,
+                                            long long dx, long long dy, long long dz, bool ray, Visit &&visit) {
     long long ix, iy, iz;
     int sx, sy, sz;
-    long long nxn, nyn, nzn, dxd, dyd, dzd;
-    if (dx > 0) { ix = floor_div_fx(px); sx = 1; nxn = (ix + 1) * kFx - px; dxd = dx; }
-    else if (dx < 0) { ix = floor_div_fx(px + kFx - 1) - 1; sx = -1; nxn = px - ix * kFx; dxd = -dx; }
-    else { ix = floor_div_fx(px); sx = 0; nxn = 1; dxd = 0; }
-    if (dy > 0) { iy = floor_div_fx(py); sy = 1; nyn = (iy + 1) * kFx - py; dyd = dy; }
-    else if (dy < 0) { iy = floor_div_fx(py + kFx - 1) - 1; sy = -1; nyn = py - iy * kFx; dyd = -dy; }
-    else { iy = floor_div_fx(py); sy = 0; nyn = 1; dyd = 0; }
-    if (dz > 0) { iz = floor_div_fx(pz); sz = 1; nzn = (iz + 1) * kFx - pz; dzd = dz; }
-    else if (dz < 0) { iz = floor_div_fx(pz + kFx - 1) - 1; sz = -1; nzn = pz - iz * kFx; dzd = -dz; }
-    else { iz = floor_div_fx(pz); sz = 0; nzn = 1; dzd = 0; }
+    long long nxn0, nyn0, nzn0, dxd0, dyd0, dzd0;
+    if (dx > 0) { ix = floor_div_fx(px); sx = 1; nxn0 = (ix + 1) * kFx - px; dxd0 = dx; }
+    else if (dx < 0) { ix = floor_div_fx(px + kFx - 1) - 1; sx = -1; nxn0 = px - ix * kFx; dxd0 = -dx; }
+    else { ix = floor_div_fx(px); sx = 0; nxn0 = 1; dxd0 = 0; }
+    if (dy > 0) { iy = floor_div_fx(py); sy = 1; nyn0 = (iy + 1) * kFx - py; dyd0 = dy; }
+    else if (dy < 0) { iy = floor_div_fx(py + kFx - 1) - 1; sy = -1; nyn0 = py - iy * kFx; dyd0 = -dy; }
+    else { iy = floor_div_fx(py); sy = 0; nyn0 = 1; dyd0 = 0; }
+    if (dz > 0) { iz = floor_div_fx(pz); sz = 1; nzn0 = (iz + 1) * kFx - pz; dzd0 = dz; }
+    else if (dz < 0) { iz = floor_div_fx(pz + kFx - 1) - 1; sz = -1; nzn0 = pz - iz * kFx; dzd0 = -dz; }
+    else { iz = floor_div_fx(pz); sz = 0; nzn0 = 1; dzd0 = 0; }
+    T nxn = (T)nxn0, nyn = (T)nyn0, nzn = (T)nzn0;
+    const T dxd = (T)dxd0, dyd = (T)dyd0, dzd = (T)dzd0, step = (T)kFx;
 
     const bool wx_on = per & 1, wy_on = per & 2;
     // wrapped indices (the start is at most one voxel outside on a periodic axis)
     int wx = (int)ix, wy = (int)iy;
     if (wx_on) wx = wx < 0 ? wx + nx : (wx >= nx ? wx - nx : wx);
     if (wy_on) wy = wy < 0 ? wy + ny : (wy >= ny ? wy - ny : wy);
-    long long cn = 0, cd = 1;  // current time
+    T cn = 0, cd = 1;  // current time
     int count = 0;
     const int max_steps = per ? kMaxWalk : nx + ny + nz + 2;
     for (int it = 0; it < max_steps; ++it) {
         if ((!wx_on && (ix < 0 || ix >= nx)) || (!wy_on && (iy < 0 || iy >= ny)) || iz < 0 || iz >= nz) break;
-        long long mn = nxn, md = dxd;
+        T mn = nxn, md = dxd;
         if (nyn * md < mn * dyd) { mn = nyn; md = dyd; }
         if (nzn * md < mn * dzd) { mn = nzn; md = dzd; }
         bool last = false;
@@ -118,23 +125,29 @@ __device__ __forceinline__ int voxel_walk(int nx, int ny, int nz, int per, long 
         const bool ey = nyn * md == mn * dyd;
         const bool ez = nzn * md == mn * dzd;
         if (ex) {
-            ix += sx; nxn += kFx; wx += sx;
+            ix += sx; nxn += step; wx += sx;
             wx = wx == nx ? 0 : (wx < 0 ? nx - 1 : wx);  // non-periodic: the loop ends first
         }
         if (ey) {
-            iy += sy; nyn += kFx; wy += sy;
+            iy += sy; nyn += step; wy += sy;
             wy = wy == ny ? 0 : (wy < 0 ? ny - 1 : wy);
         }
-        if (ez) { iz += sz; nzn += kFx; }
+        if (ez) { iz += sz; nzn += step; }
         cn = mn;
         cd = md;
     }
     return count;
 }
 
-template <class Real>
-__device__ __forceinline__ Real ratio(long long num, long long den) {
-    return (Real)num / (Real)den;
+template <class Visit>
+__device__ __forceinline__ int voxel_walk(int nx, int ny, int nz, int per, long long px, long long py, long long pz,
+                                          long long dx, long long dy, long long dz, bool ray, Visit &&visit) {
+    return voxel_walk_t<long long>(nx, ny, nz, per, px, py, pz, dx, dy, dz, ray, visit);
+}
+
+template <class Real, class T>
+__device__ __forceinline__ Real ratio(T num, T den) {
+    return (Real)num / (Real)den;  // num, den exact integers (long long, or double below 2^53)
 }
 
 // Henyey-Greenstein phase function, normalised over the sphere.

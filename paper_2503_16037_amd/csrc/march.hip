@@ -14,6 +14,8 @@
 #include "device.hpp"
 #include "internal.hpp"
 
+#include <type_traits>
+
 namespace sg {
 
 namespace {
@@ -21,6 +23,11 @@ namespace {
 constexpr int kMarchThreads = 256;
 constexpr int kNodesPerBlock = 32;
 constexpr int kBrickCap = 1024;  // voxels staged per workgroup (2 channels x 4 KB)
+
+// Crossing-time arithmetic of the marches: FP64 on a bounded grid (exact there, and one
+// multiply per product), 64-bit integers on periodic axes (walks long enough to pass 2^53)
+template <bool kPer>
+using WalkT = typename std::conditional<kPer, long long, double>::type;
 
 __device__ __forceinline__ void node_voxel(const int *__restrict__ pos, int l, int &vx, int &vy, int &vz) {
     vx = pos[3 * l] >> 16;
@@ -117,7 +124,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
         const int j = adj_idx[e];
         if (!SG_IN(j, N, 0x103)) continue;
         const int er = rev[e];  // the edge j -> l
-        if (!SG_IN(er, adj_ptr[N], 0x107)) continue;
+        if (!SG_IN(er, adj_ptr[N], 0x109)) continue;
         const int a = l, b = j;  // a < b
         const long long px = pos[3 * a], py = pos[3 * a + 1], pz = pos[3 * a + 2];
         const long long dx = min_image(pos[3 * b] - px, nx * kFx, per & 1);
@@ -125,7 +132,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
         const long long dz = pos[3 * b + 2] - pz;
         Real ss = 0, sa = 0;
         if (lds) {
-            voxel_walk(nx, ny, nz, per, px, py, pz, dx, dy, dz, false, [&](int x, int y, int z, long long num, long long den) {
+            voxel_walk_t<WalkT<kPer>>(nx, ny, nz, per, px, py, pz, dx, dy, dz, false, [&](int x, int y, int z, auto num, auto den) {
                 const int xo = x - bx0, yo = y - by0, zo = z - bz0;
                 const Real dt = ratio<Real>(num, den);
                 if ((unsigned)xo < (unsigned)bw && (unsigned)yo < (unsigned)bh && (unsigned)zo < (unsigned)bd) {
@@ -144,7 +151,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_march_edges(
                 return true;
             });
         } else {
-            voxel_walk(nx, ny, nz, per, px, py, pz, dx, dy, dz, false, [&](int x, int y, int z, long long num, long long den) {
+            voxel_walk_t<WalkT<kPer>>(nx, ny, nz, per, px, py, pz, dx, dy, dz, false, [&](int x, int y, int z, auto num, auto den) {
                 const long long vox = x + (long long)nx * (y + (long long)ny * z);
                 const Real dt = ratio<Real>(num, den);
                 if (SG_IN(vox, (long long)nx * ny * nz, 0x106)) {
@@ -185,8 +192,8 @@ __global__ __launch_bounds__(256) void k_march_sun(int N, int nx, int ny, int nz
     const Real L = sqrt((Real)(sdx * sdx + sdy * sdy + sdz * sdz)) * len_scale;
     const Real lim = cutoff / L;
     Real ss = 0, sa = 0;
-    voxel_walk(nx, ny, nz, per, pos[3 * l], pos[3 * l + 1], pos[3 * l + 2], sdx, sdy, sdz, true,
-               [&](int x, int y, int z, long long num, long long den) {
+    voxel_walk_t<WalkT<kPer>>(nx, ny, nz, per, pos[3 * l], pos[3 * l + 1], pos[3 * l + 2], sdx, sdy, sdz, true,
+               [&](int x, int y, int z, auto num, auto den) {
                    const long long vox = x + (long long)nx * (y + (long long)ny * z);
                    const Real dt = ratio<Real>(num, den);
                    if (SG_IN(vox, (long long)nx * ny * nz, 0x107)) {
