@@ -253,21 +253,24 @@ template <class Real>
 __global__ __launch_bounds__(kSpmvThreads) void k_first(int N, const long long *__restrict__ adj_ptr,
                                                        const Real *__restrict__ rhs, Real *__restrict__ x,
                                                        float2 *__restrict__ meas) {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int l = __builtin_amdgcn_readfirstlane(blockIdx.x * kNodesPerSpmvBlock + w);
-    if (l >= N) return;
+    // two nodes per wavefront, one per 32-lane half (a node has ~24 rows)
+    const int l = blockIdx.x * (2 * kNodesPerSpmvBlock) + (threadIdx.x >> 5), lane = threadIdx.x & 31;
+    if (l >= N) return;  // a half past the last node exits; the shuffles below stay within a half
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
     double r = 0.0, u = 0.0;
-    for (int n = lane; n < d; n += kWave) {
+    for (int n = lane; n < d; n += 32) {
         const Real v = rhs[off + n];
         x[off + n] = v;
         const double a = fabs((double)v);
         r += a;
         u = fmax(u, keep_nan(a / (a + kRelFloor)));
     }
-    r = wave_sum(r);
-    u = wave_max(u);
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) {
+        r += __shfl_xor(r, o, 32);
+        u = fmax(u, __shfl_xor(u, o, 32));
+    }
     if (lane == 0) meas[l] = make_float2((float)r, (float)u);
 }
 
@@ -602,8 +605,8 @@ void launch_spmv(Scene &s, hipStream_t st, const Real *S, const Real *x, Real *y
 
 template <class Real>
 void launch_first(Scene &s, hipStream_t st, const Real *rhs, Real *x, double *out) {
-    hipLaunchKernelGGL((k_first<Real>), dim3(spmv_blocks(s)), dim3(kSpmvThreads), 0, st, s.N, s.adj_ptr, rhs, x,
-                       s.meas);
+    hipLaunchKernelGGL((k_first<Real>), dim3((s.N + 2 * kNodesPerSpmvBlock - 1) / (2 * kNodesPerSpmvBlock)),
+                       dim3(kSpmvThreads), 0, st, s.N, s.adj_ptr, rhs, x, s.meas);
     launch_measures(s, 1, out, st);
 }
 
