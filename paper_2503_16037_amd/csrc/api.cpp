@@ -885,6 +885,7 @@ sg_status solve_single(Scene &s, const sg_solve_opts &o, hipStream_t st, double 
     tm.graphs = !(o.flags & SG_NO_GRAPHS) && !tm.on;
     tm.autotune = !(o.flags & SG_NO_AUTOTUNE);
     s.qscreen = (o.flags & SG_EXACT_CELLS) ? 0 : 1;
+    s.phi32 = nullptr;
     tm.st = st;
     const float scale = s.abs_scale.empty() ? 1.0f : s.abs_scale[0];
     hipEvent_t e0 = tm.mark();
@@ -1079,10 +1080,18 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
     int stalled = 0;
     std::vector<double> m2((size_t)2 * nl), sc(nl);
     double *d_sc = s.lam_buf;  // [nl]
-    // FP64 residual of x64 for every wavelength: the worst per-edge relative residual, and
-    // the scales r / rel (at most |x| per edge: well inside the FP32 range)
+    // the solution as an FP64 copy (made only when a correction, GMRES or an export needs it;
+    // until then it is the FP32 iterate, whose promoted values the residual reads)
+    auto materialize = [&]() {
+        if (s.phi32) launch_f32_to_64(s.phi32, s.x64, n, st);
+        s.phi32 = nullptr;
+    };
+    // FP64 residual of the solution for every wavelength: the worst per-edge relative
+    // residual, and the scales r / rel (at most |x| per edge: well inside the FP32 range)
     auto residual = [&](double &worst) -> sg_status {
-        launch_bresidual64(s, st, rgrid, s.x64, s.bS);  // r in FP32: the correction's right-hand side
+        // r in FP32: the correction's right-hand side
+        if (s.phi32) launch_bresidual32(s, st, rgrid, s.phi32, s.bS);
+        else launch_bresidual64(s, st, rgrid, s.x64, s.bS);
         launch_measures(s, nl, s.lam_buf + nl, st);  // [nl][2]
         ++ss.sweeps;
         ++ss.refinements;
@@ -1114,7 +1123,7 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
         // per-edge relative updates settle at a few FP32 rounding units: never ask for less
         SG_TRY(neumann_batched(s, st, tm, grid, nullptr, xa, xb, 1, std::max(0.3 * rtol, 4e-6), max_sweeps, ss,
                                stalled));
-        launch_f32_to_64(xa, s.x64, n, st);
+        s.phi32 = xa;  // the solution, until a step below needs it in FP64
     }
     for (int it = 0; it < 10; ++it) {
         if (!have_r) SG_TRY(residual(worst));
@@ -1123,6 +1132,7 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
         if (sg_log()) fprintf(stderr, "[sgrt] FP64 residual after %d sweeps: worst relative %.3e\n", ss.sweeps, worst);
         if (worst <= rtol) { ss.converged = 1; break; }
         if (stalled || ss.sweeps >= max_sweeps || !std::isfinite(worst)) break;
+        materialize();  // the correction's sweeps reuse the FP32 iterate's buffers
         SG_HIP(hipMemcpyAsync(d_sc, sc.data(), sizeof(double) * nl, hipMemcpyHostToDevice, st));
         launch_lam_scale_f32(s.bS, d_sc, nl, n, st);  // r / rel per wavelength
         float *ca = s.bx, *cb = s.by;
@@ -1136,6 +1146,7 @@ sg_status solve_batched_linear(Scene &s, const sg_solve_opts &o, hipStream_t st,
     // rtol go to GMRES (each with the sweeps left of the budget)
     const int left = max_sweeps - ss.sweeps;
     if (!ss.converged && o.solver == SG_SOLVER_AUTO && left > 1) {
+        materialize();
         SG_TRY(residual(worst));
         std::vector<double> rel(nl);
         for (int k = 0; k < nl; ++k)
@@ -1159,6 +1170,7 @@ sg_status solve_batched(Scene &s, const sg_solve_opts &o, hipStream_t st, double
     tm.graphs = !(o.flags & SG_NO_GRAPHS) && !tm.on;
     tm.autotune = !(o.flags & SG_NO_AUTOTUNE);
     s.qscreen = (o.flags & SG_EXACT_CELLS) ? 0 : 1;
+    s.phi32 = nullptr;
     tm.st = st;
     hipEvent_t e0 = tm.mark();
     launch_structure(s, st);
@@ -1186,7 +1198,8 @@ sg_status solve_batched(Scene &s, const sg_solve_opts &o, hipStream_t st, double
     }
     hipEvent_t e4 = tm.mark();
     double *dst = on_dev ? radiance : s.pix;
-    launch_batched_gather(s, st, s.x64, o.scatter_order, dst);
+    if (s.phi32) launch_batched_gather(s, st, (const float *)s.phi32, o.scatter_order, dst);
+    else launch_batched_gather(s, st, (const double *)s.x64, o.scatter_order, dst);
     hipEvent_t e5 = tm.mark();
     SG_HIP(hipGetLastError());
     if (!on_dev)
@@ -1792,7 +1805,11 @@ sg_status sg_export_vector(sg_scene *scene, int32_t which, double *out) {
                 return SG_OK;
             }
             src = s.S; n = (size_t)s.E; break;
-        case SG_VEC_PHI: src = s.x64; n = (size_t)s.E * s.n_lambda; esz = 8; break;
+        case SG_VEC_PHI:  // a batched solution may still be the FP32 iterate (promoted here)
+            src = s.phi32 ? (const void *)s.phi32 : (const void *)s.x64;
+            n = (size_t)s.E * s.n_lambda;
+            esz = s.phi32 ? 4 : 8;
+            break;
         case SG_VEC_QSUN: src = s.qsun; n = s.E; esz = 4; break;
         default: return fail(SG_E_INVALID, "unknown vector");
     }

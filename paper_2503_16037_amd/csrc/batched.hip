@@ -479,11 +479,12 @@ __device__ __forceinline__ double theta_mix_b(const PhaseSet &pm, const float *_
 
 // J[l][lambda]: one wavefront per node; lane m evaluates in-edge m's phase function
 // once, then the lanes (wavelengths) accumulate in FP64.
+template <class PhiT>
 __global__ __launch_bounds__(64) void k_bnode_J(int N, int nvol, int nl, const long long *__restrict__ adj_ptr,
                                                const int *__restrict__ adj_idx, const int *__restrict__ rev,
                                                const int *__restrict__ pos, const float *__restrict__ tau_s,
                                                const float *__restrict__ tau_a, const float *__restrict__ abs_scale,
-                                               const float *__restrict__ bsrc, const double *__restrict__ phi,
+                                               const float *__restrict__ bsrc, const PhiT *__restrict__ phi,
                                                PhaseSet pm, const float *__restrict__ frac, double sx, double sy,
                                                double sz, double vx, double vy, double vz, int multiple,
                                                int per, long long wx, long long wy, double *__restrict__ J) {
@@ -518,7 +519,7 @@ __global__ __launch_bounds__(64) void k_bnode_J(int N, int nvol, int nl, const l
             for (int m = 0; m < d; ++m) {
                 const long long e = off + m;
                 const double T = (double)edge_T(tau_s[e], tau_a[e], s);
-                acc += th[m] * T * phi[(long long)rev[e] * nl + lam];
+                acc += th[m] * T * (double)phi[(long long)rev[e] * nl + lam];
             }
         }
         J[(long long)l * nl + lam] = acc;
@@ -693,6 +694,10 @@ void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, f
     launch_wide<double, float, double, true>(s, st, grid, nullptr, x64, r32, 1);
 }
 
+void launch_bresidual32(Scene &s, hipStream_t st, int grid, const float *x, float *r32) {
+    launch_wide<float, float, double, true>(s, st, grid, nullptr, x, r32, 1);
+}
+
 void launch_bfirst(Scene &s, hipStream_t st, const float *rhs, float *x) {
     dim3 gr((s.N + 3) / 4, (s.n_lambda + 63) / 64);
     hipLaunchKernelGGL(k_bfirst, gr, dim3(256), 0, st, s.N, s.n_lambda, s.adj_ptr, s.qsun, s.brho, s.bsrc, rhs, x,
@@ -740,9 +745,10 @@ void launch_fill_f32(float *a, long long n, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n)), dim3(256), 0, st, a, n);
 }
 
-void launch_batched_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance) {
+template <class PhiT>
+static void batched_gather(Scene &s, hipStream_t st, const PhiT *phi, int scatter_order, double *radiance) {
     const PhaseSet pm = phase_set(s);
-    hipLaunchKernelGGL(k_bnode_J, dim3(s.N), dim3(64), 0, st, s.N, s.n_vol, s.n_lambda, s.adj_ptr, s.adj_idx, s.rev,
+    hipLaunchKernelGGL(k_bnode_J<PhiT>, dim3(s.N), dim3(64), 0, st, s.N, s.n_vol, s.n_lambda, s.adj_ptr, s.adj_idx, s.rev,
                        s.pos, (const float *)s.tau_s, (const float *)s.tau_a, s.abs_scale_d, s.bsrc, phi, pm, node_frac(s),
                        s.sun_in[0], s.sun_in[1], s.sun_in[2], s.view_u[0], s.view_u[1], s.view_u[2],
                        scatter_order == 1 ? 0 : 1, s.periodic, (long long)s.nx * kFx, (long long)s.ny * kFx, s.J);
@@ -754,6 +760,13 @@ void launch_batched_gather(Scene &s, hipStream_t st, const double *phi, int scat
                        (long long)s.sun[0], (long long)s.sun[1], (long long)s.sun[2], ls, s.albedo, s.J, s.surface,
                        s.mu0, s.n_vol, s.general ? s.los_ptr : (const long long *)nullptr, s.los_node, s.los_t,
                        radiance);
+}
+
+void launch_batched_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance) {
+    batched_gather(s, st, phi, scatter_order, radiance);
+}
+void launch_batched_gather(Scene &s, hipStream_t st, const float *phi, int scatter_order, double *radiance) {
+    batched_gather(s, st, phi, scatter_order, radiance);
 }
 
 }  // namespace sg

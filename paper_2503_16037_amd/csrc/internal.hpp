@@ -96,6 +96,8 @@ struct Scene {
     double lut_scale[4] = {1, 1, 1, 1};  // 1 / integral over the sphere of each table row
     double *lut = nullptr;             // [n_phase][lut_n] phase tables (device)
     int sigma_mode = 0;                // SG_SIGMA_VORONOI or SG_SIGMA_COLOUR
+    float *phi32 = nullptr;  // a batched solve's solution while it is the FP32 iterate itself (bx or by),
+                             // before any FP64 copy was needed
     int qscreen = 1;                   // phase-cell owners through the FP32 screen (0: FP64 scan only)
     int periodic = 0;                  // bit 0: x, bit 1: y repeat with the grid's period
     int *hull = nullptr;               // colouring: [n_fib][kHullNb] hull neighbours, then [n_fib] counts
@@ -314,6 +316,8 @@ void launch_spmm(Scene &s, hipStream_t st, int grid, const float *rhs, const flo
 // r = S + K x64 - x64 evaluated in FP64 for all wavelengths and stored in FP32 (the correction
 // solve takes it in FP32); per-node measures of r relative to x (from the FP64 values) to s.meas
 void launch_bresidual64(Scene &s, hipStream_t st, int grid, const double *x64, float *r32);
+// the same residual of the FP32 iterate itself (its values promoted: the bits of x64 = x)
+void launch_bresidual32(Scene &s, hipStream_t st, int grid, const float *x, float *r32);
 // b[e][lambda] *= sc[lambda] (FP32 values, FP64 scales)
 void launch_lam_scale_f32(float *b, const double *sc, int nl, long long n, hipStream_t st);
 // one wavelength of a batched scene in FP64 (its GMRES fallback): the residual r = S - (I - K) x
@@ -327,6 +331,7 @@ void launch_f32_to_64(const float *a, double *b, long long n, hipStream_t st);
 void launch_lam_to_edge_major(const double *src, double *dst, int nl, long long E, hipStream_t st);
 void launch_fill_f32(float *a, long long n, hipStream_t st);
 void launch_batched_gather(Scene &s, hipStream_t st, const double *phi, int scatter_order, double *radiance);
+void launch_batched_gather(Scene &s, hipStream_t st, const float *phi, int scatter_order, double *radiance);
 
 }  // namespace sg
 
