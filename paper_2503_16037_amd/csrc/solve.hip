@@ -126,13 +126,6 @@ __device__ __forceinline__ double bcast(double v, int m) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Row lane of node block K_l times the gathered inputs: sum over m < d of K[lane][m] xg_m,
-// in increasing m.  The block (d^2 values at blk_g, column-major: element (row n,
-// column m) at m d + n) is copied to this wavefront's LDS slice with flat coalesced
-// loads, kStage per lane in flight; rows are then read from LDS without bank conflicts
-// (consecutive lanes, consecutive addresses).  The caller issues its other loads around
-// this call; xl holds the input of in-edge `lane` (lane m's value is broadcast).
-// blk == NULL: no LDS slice, every lane reads its row from memory.
 constexpr int kStage = 16;  // block loads in flight per lane
 
 // n passes of 64 consecutive block elements from t0 into the wavefront's LDS slice
@@ -146,6 +139,13 @@ __device__ __forceinline__ void stage_passes(const Real *__restrict__ blk_g, Rea
     for (int j = 0; j < n; ++j) blk[min(t0 + j * 64 + lane, nq - 1)] = v[j];
 }
 
+// Row lane of node block K_l times the gathered inputs: sum over m < d of K[lane][m] xg_m,
+// in increasing m.  The block (d^2 values at blk_g, column-major: element (row n,
+// column m) at m d + n) is copied to this wavefront's LDS slice with flat coalesced
+// loads, kStage per lane in flight; rows are then read from LDS without bank conflicts
+// (consecutive lanes, consecutive addresses).  The caller issues its other loads around
+// this call; xl holds the input of in-edge `lane` (lane m's value is broadcast).
+// blk == NULL: no LDS slice, every lane reads its row from memory.
 template <class Acc, class Real, class XT>
 __device__ __forceinline__ Acc node_row(const Real *__restrict__ blk_g, Real *__restrict__ blk, int d, int lane,
                                         XT xl) {
