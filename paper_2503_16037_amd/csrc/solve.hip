@@ -172,7 +172,16 @@ __device__ __forceinline__ Acc node_row(const Real *__restrict__ blk_g, Real *__
     __builtin_amdgcn_wave_barrier();
     Acc acc = (Acc)0;
     const int n = min(lane, d - 1);
-    for (int m = 0; m < d; ++m) acc += (Acc)blk[m * d + n] * (Acc)bcast(xl, m);
+    // eight LDS reads in flight at a time (the products still accumulate in increasing m)
+    int m = 0;
+    for (; m + 8 <= d; m += 8) {
+        Real k[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) k[j] = blk[(m + j) * d + n];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc += (Acc)k[j] * (Acc)bcast(xl, m + j);
+    }
+    for (; m < d; ++m) acc += (Acc)blk[m * d + n] * (Acc)bcast(xl, m);
     __builtin_amdgcn_wave_barrier();  // the slice is rewritten by the next node
     return acc;
 }
