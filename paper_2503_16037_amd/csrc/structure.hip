@@ -90,15 +90,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(long long *__restrict
         if (base + i < n) a[base + i] += off;
 }
 
-// rev(e) for every edge: position of (head, tail) in the head's row (one wave per node).
+// rev(e) for every edge: position of (head, tail) in the head's row.  Two nodes per
+// wavefront, one per 32-lane half (a node has ~24 edges, each a chain of dependent loads
+// through the binary search, so a resident wavefront advances two chains per node slot).
 __global__ __launch_bounds__(256) void k_rev(int N, const long long *__restrict__ adj_ptr,
                                             const int *__restrict__ adj_idx, int *__restrict__ rev) {
-    const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+    const int l = blockIdx.x * 8 + (threadIdx.x >> 5);
+    const int lane = threadIdx.x & 31;
     if (l >= N) return;
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
-    for (int m = lane; m < d; m += 64) {
+    for (int m = lane; m < d; m += 32) {
         const int j = adj_idx[off + m];
         if (!SG_IN(j, N, 0x601)) continue;
         long long lo = adj_ptr[j], hi = adj_ptr[j + 1];
@@ -135,13 +137,13 @@ __global__ __launch_bounds__(256) void k_check_symmetric(int N, const long long 
 __global__ __launch_bounds__(256) void k_row_ptr(int N, long long E, const long long *__restrict__ adj_ptr,
                                                 const long long *__restrict__ nodeoff,
                                                 long long *__restrict__ row_ptr) {
-    const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+    const int l = blockIdx.x * 8 + (threadIdx.x >> 5);  // two nodes per wavefront
+    const int lane = threadIdx.x & 31;
     if (l >= N) return;
     const long long off = adj_ptr[l];
     const int d = (int)(adj_ptr[l + 1] - off);
     const long long b0 = nodeoff[l];
-    for (int m = lane; m < d; m += 64) row_ptr[off + m] = b0 + (long long)m * d;
+    for (int m = lane; m < d; m += 32) row_ptr[off + m] = b0 + (long long)m * d;
     if (l == N - 1 && lane == 0) row_ptr[E] = nodeoff[N];
 }
 
@@ -167,7 +169,7 @@ void launch_structure(Scene &s, hipStream_t st) {
     hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kScanThreads), 0, st, s.nodeoff, N, s.scan_tmp);
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanThreads), 0, st, s.scan_tmp, nt, s.nodeoff + N);
     hipLaunchKernelGGL(k_scan_add, dim3(nt), dim3(kScanThreads), 0, st, s.nodeoff, N, s.scan_tmp);
-    const int nb = (N + 3) / 4;
+    const int nb = (N + 7) / 8;  // two nodes per wavefront, eight per workgroup
     hipLaunchKernelGGL(k_rev, dim3(nb), dim3(256), 0, st, N, s.adj_ptr, s.adj_idx, s.rev);
     hipLaunchKernelGGL(k_row_ptr, dim3(nb), dim3(256), 0, st, N, (long long)s.E, s.adj_ptr, s.nodeoff, s.row_ptr);
 }
