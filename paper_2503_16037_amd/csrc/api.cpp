@@ -875,6 +875,21 @@ sg_status solve_linear(Scene &s, const sg_solve_opts &o, hipStream_t st, Exec &t
     return SG_OK;
 }
 
+// The sun march (scale: the absorption multiplier) on the scene's second stream, ordered
+// after everything already queued on st (the previous solve's readers of the sun's optical
+// depths included); st waits for ev_join before this solve's first reader.  It needs only
+// the positions and the extinction grids, so it runs beside the structure pass and the edge
+// march.
+template <class Real>
+sg_status fork_sun_march(Scene &s, hipStream_t st, float scale) {
+    Ctx *ctx = s.ctx;
+    SG_HIP(hipEventRecord(s.ev_fork, st));
+    SG_HIP(hipStreamWaitEvent(s.aux, s.ev_fork, 0));
+    launch_march_sun<Real>(s, s.aux, scale);
+    SG_HIP(hipEventRecord(s.ev_join, s.aux));
+    return SG_OK;
+}
+
 template <class Real>
 sg_status solve_single(Scene &s, const sg_solve_opts &o, hipStream_t st, double *radiance, int on_dev,
                        sg_solve_info *info) {
@@ -888,19 +903,21 @@ sg_status solve_single(Scene &s, const sg_solve_opts &o, hipStream_t st, double 
     s.phi32 = nullptr;
     tm.st = st;
     const float scale = s.abs_scale.empty() ? 1.0f : s.abs_scale[0];
+    if (o.build_col_idx && !s.col_idx) SG_TRY(dalloc(s, &s.col_idx, (size_t)s.nnz));
+    SG_TRY(fork_sun_march<Real>(s, st, scale));
     hipEvent_t e0 = tm.mark();
     launch_structure(s, st);
     if (o.build_col_idx) {
-        if (!s.col_idx) SG_TRY(dalloc(s, &s.col_idx, (size_t)s.nnz));
         launch_col_idx(s, st);
         s.col_built = true;
     } else {
         s.col_built = false;
     }
     hipEvent_t e1 = tm.mark();
-    launch_march<Real>(s, st, scale, 1);
+    launch_march_edges<Real>(s, st, scale, 1);
     launch_node_weights<Real>(s, st, scale);
     hipEvent_t e2 = tm.mark();
+    SG_HIP(hipStreamWaitEvent(st, s.ev_join, 0));  // the sun march
     launch_qbuild<Real>(s, st, 0);
     hipEvent_t e3 = tm.mark();
     SG_HIP(hipGetLastError());
@@ -1172,17 +1189,19 @@ sg_status solve_batched(Scene &s, const sg_solve_opts &o, hipStream_t st, double
     s.qscreen = (o.flags & SG_EXACT_CELLS) ? 0 : 1;
     s.phi32 = nullptr;
     tm.st = st;
+    if (o.build_col_idx && !s.col_idx) SG_TRY(dalloc(s, &s.col_idx, (size_t)s.nnz));
+    SG_TRY(fork_sun_march<float>(s, st, 1.0f));
     hipEvent_t e0 = tm.mark();
     launch_structure(s, st);
     if (o.build_col_idx) {
-        if (!s.col_idx) SG_TRY(dalloc(s, &s.col_idx, (size_t)s.nnz));
         launch_col_idx(s, st);
         s.col_built = true;
     } else {
         s.col_built = false;
     }
     hipEvent_t e1 = tm.mark();
-    launch_march<float>(s, st, 1.0f, 1);
+    launch_march_edges<float>(s, st, 1.0f, 1);
+    SG_HIP(hipStreamWaitEvent(st, s.ev_join, 0));  // the sun march, read by the node coefficients
     launch_bnode_coef(s, st);
     hipEvent_t e2 = tm.mark();
     launch_qbuild<float>(s, st, 1);
@@ -1296,6 +1315,16 @@ namespace {
 
 void free_scene_impl(Scene *s) {
     clear_graphs(*s);
+    // the sun march of a solve that stopped before joining may still run on the second
+    // stream: it ends before any block goes back to the pool
+    if (s->aux) {
+        (void)hipStreamSynchronize(s->aux);
+        (void)hipStreamDestroy(s->aux);
+        s->aux = nullptr;
+    }
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+    s->ev_fork = s->ev_join = nullptr;
     void *ptrs[] = {s->big, s->bigdir, s->bigrow, s->big_part, s->mu_s, s->mu_a, s->frac, s->albedo, s->abs_scale_d, s->pos, s->adj_ptr, s->adj_idx, s->lat,
                     s->tab, s->lut, s->hull, s->rev, s->nodeoff, s->row_ptr, s->col_idx, s->scan_tmp, s->tau_s, s->tau_a, s->tsun_s,
                     s->tsun_a, s->T, s->Tsun, s->rho, s->val, s->S, s->x, s->y, s->c_rhs, s->c_a, s->c_b, s->qsun,
@@ -1523,6 +1552,9 @@ sg_status create_scene_impl(Ctx *ctx, const sg_scene_desc *d, hipStream_t st, Sc
         SG_HIP(hipStreamSynchronize(st));
         if (nbad) return fail(SG_E_INVALID, "adjacency is not symmetric (" + std::to_string(nbad) + " edges)");
     }
+    SG_HIP(hipStreamCreateWithFlags(&s.aux, hipStreamNonBlocking));
+    SG_HIP(hipEventCreateWithFlags(&s.ev_fork, hipEventDisableTiming));
+    SG_HIP(hipEventCreateWithFlags(&s.ev_join, hipEventDisableTiming));
     SG_HIP(hipStreamSynchronize(st));
     if (sg_log())
         fprintf(stderr, "[sgrt] scene create: validate %.2f ms, allocate %.2f ms, upload %.2f ms (%zu MB reserved)\n",

@@ -162,6 +162,11 @@ struct Scene {
     double *pix = nullptr;   // [n_lambda * npx] radiance staging for host outputs
 
     std::map<GraphKey, SceneGraph> graphs;  // captured sweep chunks
+    // a second stream for the sun march, which runs beside the structure pass and the edge
+    // march (fork from the solve's stream at its start, join before the first reader of the
+    // sun's optical depths); created with the scene, default priority
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int spmv_grid = 0, spmm_grid = 0;       // tuned launch shapes (0 = not tuned yet)
     int spmm_tile = 0;                      // tuned wavelength tile of the batched sweeps
     int tile = 64;                          // wavelength tile of the current batched solve
@@ -245,7 +250,9 @@ void launch_col_idx(Scene &s, hipStream_t st);
 void launch_check_symmetric(Scene &s, unsigned *bad, hipStream_t st);
 
 template <class Real>
-void launch_march(Scene &s, hipStream_t st, float scale, int use_lds);
+void launch_march_edges(Scene &s, hipStream_t st, float scale, int use_lds);
+template <class Real>
+void launch_march_sun(Scene &s, hipStream_t st, float scale);
 template <class Real>
 void launch_node_weights(Scene &s, hipStream_t st, float scale);
 template <class Real>

@@ -289,7 +289,7 @@ __global__ __launch_bounds__(64) void k_trace(int kind, int N, int nx, int ny, i
 }  // namespace
 
 template <class Real>
-void launch_march(Scene &s, hipStream_t st, float scale, int use_lds) {
+void launch_march_edges(Scene &s, hipStream_t st, float scale, int use_lds) {
     const Real len_scale = (Real)(s.voxel_m / 65536.0);
     const int nb = (s.N + kNodesPerBlock - 1) / kNodesPerBlock;
     // the bounded-grid instantiations carry no periodic branches
@@ -297,6 +297,11 @@ void launch_march(Scene &s, hipStream_t st, float scale, int use_lds) {
     hipLaunchKernelGGL(edges, dim3(nb), dim3(kMarchThreads), 0, st, s.N, s.nx, s.ny, s.nz, s.periodic, s.adj_ptr,
                        s.adj_idx, s.pos, s.mu_s, s.mu_a, len_scale, (Real)scale, s.rev, (Real *)s.tau_s,
                        (Real *)s.tau_a, (Real *)s.T, use_lds);
+}
+
+template <class Real>
+void launch_march_sun(Scene &s, hipStream_t st, float scale) {
+    const Real len_scale = (Real)(s.voxel_m / 65536.0);
     float smin = scale;
     if (s.n_lambda > 1) {
         smin = s.abs_scale[0];
@@ -323,8 +328,10 @@ void launch_trace(Scene &s, hipStream_t st, int kind, const long long *ids, int 
                        (long long)s.view[1], (long long)s.view[2], ids, n, cap, vox, dt, count);
 }
 
-template void launch_march<float>(Scene &, hipStream_t, float, int);
-template void launch_march<double>(Scene &, hipStream_t, float, int);
+template void launch_march_edges<float>(Scene &, hipStream_t, float, int);
+template void launch_march_edges<double>(Scene &, hipStream_t, float, int);
+template void launch_march_sun<float>(Scene &, hipStream_t, float);
+template void launch_march_sun<double>(Scene &, hipStream_t, float);
 template void launch_node_weights<float>(Scene &, hipStream_t, float);
 template void launch_node_weights<double>(Scene &, hipStream_t, float);
 
