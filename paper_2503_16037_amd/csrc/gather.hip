@@ -49,12 +49,19 @@ __global__ __launch_bounds__(256) void k_node_J(int N, int nvol, const long long
     const long long off = adj_ptr[l], end = adj_ptr[l + 1];
     const int d = (int)(end - off);
     const bool vol = l < nvol;
+    // the direct-sun term is taken by the lane after the last in-edge (m == d), through the
+    // same phase evaluation as the edges, so no lane finishes alone after the sum
     double acc = 0.0;
-    if (multiple) {
-        for (int m = lane; m < d; m += 32) {
-            const long long e = off + m;
-            double th = 1.0;
+    for (int m = lane; m <= d; m += 32) {
+        const bool sun = m == d;
+        if (!sun && !multiple) continue;
+        const long long e = off + min(m, d - 1);
+        double mu = sx * vx + sy * vy + sz * vz, w;
+        if (sun) {
+            w = (double)Tsun[l];
+        } else {
             if (!SG_IN(rev[e], adj_ptr[N], 0x501)) continue;
+            w = (double)T[e] * phi[rev[e]];
             if (vol) {
                 const int j = adj_idx[e];
                 if (!SG_IN(j, N, 0x502)) continue;
@@ -63,18 +70,15 @@ __global__ __launch_bounds__(256) void k_node_J(int N, int nvol, const long long
                 const long long Dz = (long long)pos[3 * l + 2] - pos[3 * j + 2];
                 const double dx = (double)Dx, dy = (double)Dy, dz = (double)Dz;
                 const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-                th = theta_mix(pm, frac, nvol, l, (dx * vx + dy * vy + dz * vz) * inv);
+                mu = (dx * vx + dy * vy + dz * vz) * inv;
             }
-            acc += th * (double)T[e] * phi[rev[e]];
         }
+        const double th = vol ? theta_mix(pm, frac, nvol, l, mu) : (sun ? mu0 : 1.0);
+        acc += th * w;
     }
 #pragma unroll
     for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
-    if (lane == 0) {
-        const double src = vol ? theta_mix(pm, frac, nvol, l, sx * vx + sy * vy + sz * vz) * (double)Tsun[l]
-                               : mu0 * (double)Tsun[l];
-        J[l] = src + acc;
-    }
+    if (lane == 0) J[l] = acc;
 }
 
 __global__ __launch_bounds__(64) void k_pixels(int nx, int ny, int nz, int per, const float *__restrict__ mu_s,
