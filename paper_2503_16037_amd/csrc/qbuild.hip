@@ -154,8 +154,11 @@ __device__ __forceinline__ void screen_owners(int d, const float4 *s4, const dou
     }
 }
 
+// Five wavefronts per SIMD (96 VGPRs; its LDS allows about 4.75): the per-node setup
+// spills a few values that each group reloads, which costs less than the fifth wavefront
+// gains in hiding the loads and atomics around the screen
 template <class Real, class BlkT, bool kWriteQ>
-__global__ __launch_bounds__(64) void k_qbuild(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_qbuild(
     int N, int nvol, const long long *__restrict__ adj_ptr, const int *__restrict__ adj_idx,
     const int *__restrict__ pos, const double *__restrict__ lat, const double *__restrict__ tab, int NF, int n_phase,
     const float *__restrict__ frac, double sun_x, double sun_y, double sun_z, Real mu0, const Real *__restrict__ T,
