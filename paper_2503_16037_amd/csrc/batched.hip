@@ -162,11 +162,13 @@ __device__ __forceinline__ float2 wide_node(int l, int lane, int lam, bool lv, f
     return make_float2((float)sum, (float)mrel);
 }
 
-// Occupancy hint for the FP32 sweep: at the requested waves per SIMD the compiler fits
-// every instantiation without spilling (72 VGPRs at D = 40 instead of 98).  The FP64
-// residual (run once per refinement) keeps its natural allocation.
+// Occupancy hints: at the requested waves per SIMD the compiler fits each instantiation
+// without spilling (the FP32 sweep: 72 VGPRs at D = 40 instead of 98; the FP64 residual up
+// to D = 40: 122 instead of 144, four waves per SIMD instead of three, where five would
+// spill its accumulators; the larger FP64 residuals keep their natural allocation, since
+// their accumulators alone fill four waves' registers).
 template <int D, bool kResidual>
-constexpr int wide_waves_per_eu() { return kResidual ? 1 : (D <= 40 ? 7 : 5); }
+constexpr int wide_waves_per_eu() { return kResidual ? (D <= 40 ? 4 : 1) : (D <= 40 ? 7 : 5); }
 
 template <int D, class XT, class YT, class AccT, bool kResidual>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(wide_waves_per_eu<D, kResidual>()))) void k_spmm_wide(
