@@ -420,13 +420,90 @@ def bench_graph(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_los(args):
+    """Scattering nodes on the pixels' lines of sight (Sec. 2 path points; Sec. 3 step 1) for
+    the 64x64x32 plume: the placement (sg_los_nodes, one node per layer crossed or one per
+    50 m step) timed on its own, then the layer nodes coupled by their 11.5 x n strongest
+    couplings (Eq. 4, sg_graph_build) and whole solves of that scene timed like the main
+    workloads; the pixels are checked against the FP64 oracle on the same nodes and graph."""
+    import torch
+
+    from paper_2503_16037_amd import scenes, sgrt
+
+    base = scenes.make_plume()
+    ctx = sgrt.Context(0)
+    place = {}
+    for mode, step_m in (("layer", 0.0), ("step", 50.0)):
+        for _ in range(max(1, args.warmup)):
+            out = sgrt.los_nodes(ctx, base.nx, base.ny, base.nz, base.view_dir, base.voxel_m, mode, step_m=step_m)
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(args.steps):
+            t = time.perf_counter()
+            out = sgrt.los_nodes(ctx, base.nx, base.ny, base.nz, base.view_dir, base.voxel_m, mode, step_m=step_m)
+            lat.append((time.perf_counter() - t) * 1e3)
+        place[mode] = {"nodes": int(len(out[0])), "elements": int(len(out[2])),
+                       "ms_p50": round(float(np.percentile(lat, 50)), 4),
+                       "ms_p99": round(float(np.percentile(lat, 99)), 4), "out": out}
+    pos, lp, ln, lt = place["layer"].pop("out")
+    place["step"].pop("out")
+    sc = scenes.with_los_nodes(base, pos, lp, ln, lt, name="plume-64x64x32-los-layer")
+    n = len(pos) + (sc.nx * sc.ny if sc.surface_nodes else 0)
+    t = time.perf_counter()
+    ap_, ai_ = sgrt.graph_build(ctx, sc, n_pairs=int(11.5 * n))
+    ms_graph = (time.perf_counter() - t) * 1e3
+    sc = sc.with_(adj_ptr=ap_, adj_idx=ai_)
+    with sgrt.Scene(ctx, sc) as g:
+        for _ in range(max(2, args.warmup)):  # the second solve tunes the sweep's launch shape
+            g.solve()
+        torch.cuda.synchronize()
+        infos, lat = [], []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            rad, info = g.solve(timing=True)
+            lat.append((time.perf_counter() - ts) * 1e3)
+            infos.append(info)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        nnz = g.sizes["nnz"]
+    stages = {k: round(float(np.mean([i[k] for i in infos])), 4)
+              for k in ("ms_structure", "ms_march", "ms_qbuild", "ms_solve", "ms_gather", "ms_total")}
+    out = {"metric": "scenes/s on line-of-sight nodes (placement, coupling graph, whole solves)",
+           "value": round(args.steps / elapsed, 3), "unit": "scenes/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"plume-64x64x32 (seed 2) on its pixels' line-of-sight nodes (one per layer), "
+                                  f"{n} nodes incl. surface, {int(ap_[-1])} couplings (the 11.5 x n strongest)",
+                      "parallelism": "single GPU"},
+           "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                          "p99": round(float(np.percentile(lat, 99)), 4)},
+           "stages_ms": stages, "sweeps_per_step": float(np.mean([i["sweeps"] for i in infos])),
+           "nnz": int(nnz), "placement": place, "ms_graph_build": round(ms_graph, 3)}
+    if not args.no_check or not args.no_cpu_baseline:
+        import oracle  # test infrastructure: the check and the CPU baseline only
+        t = time.perf_counter()
+        ora = oracle.run(sc)
+        t_cpu = time.perf_counter() - t
+        if not args.no_check:
+            err = np.abs(np.asarray(rad, np.float64) - ora["radiance"]) / np.maximum(np.abs(ora["radiance"]), 1e-300)
+            out["max_rel_err_vs_oracle"] = float(err.max())
+            out["p99_rel_err_vs_oracle"] = float(np.percentile(err, 99))
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = {"value": round(1.0 / t_cpu, 6), "unit": "scenes/s",
+                                   "cores": oracle.num_threads(), "kind": "oracle", "host": host_cpu(),
+                                   "sample": f"one solve of the same scene, FP64, all stages, {t_cpu:.2f} s"}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cloud",
-                    help="plume | cloud | batched | plain | slab (periodic plume) | served | graph | nfib | coupling | copy")
+                    help="plume | cloud | batched | plain | slab (periodic plume) | served | graph | los | nfib | coupling | copy")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--served", type=int, default=40, help="requests of the served stream (workload served)")
@@ -456,6 +533,9 @@ def main():
         return
     if args.workload == "coupling":
         bench_coupling(args)
+        return
+    if args.workload == "los":
+        bench_los(args)
         return
 
     import torch
