@@ -459,8 +459,8 @@ __global__ __launch_bounds__(256) void k_sum_u64(const unsigned long long *__res
     if (threadIdx.x == 0) atomicAdd(out, lds[0] + lds[1] + lds[2] + lds[3]);
 }
 
-constexpr int kRsItems = 64;             // keys per lane in a tile
-constexpr int kRsTile = 64 * kRsItems;  // keys per tile (one wavefront)
+constexpr int kRsItems = 16;             // keys per lane in a tile
+constexpr int kRsTile = 64 * kRsItems;  // keys per tile (one wavefront; staged in LDS by the scatter)
 
 // digit counts of each tile, digit-major: hist[digit * ntiles + tile]
 __global__ __launch_bounds__(256) void k_rs_hist(const unsigned long long *__restrict__ keys, long long n, int bit,
@@ -483,21 +483,47 @@ __global__ __launch_bounds__(256) void k_rs_hist(const unsigned long long *__res
 }
 
 // Stable scatter by one digit: tile t's keys with digit d go to off[d * ntiles + t] onward,
-// in their order.  Round r of a tile holds keys base + 64 r + lane; a key's rank among the
-// round's keys with its digit comes from the ballots of the digit's eight bits, the running
-// count of each digit lives in the wavefront's LDS row.
+// in their order.  The tile is first sorted by digit in the wavefront's LDS (a stable
+// counting sort: local digit starts from the tile's counts, then round r of the tile, keys
+// base + 64 r + lane, ranked among the round's keys of its digit by the ballots of the
+// digit's eight bits, after the digit's running count), then written out in that order, so
+// the lanes holding one digit store to consecutive addresses.  Same order as placing every
+// key straight at its global position.
 __global__ __launch_bounds__(256) void k_rs_scatter(const unsigned long long *__restrict__ kin,
                                                     const unsigned long long *__restrict__ vin,
                                                     unsigned long long *__restrict__ kout,
                                                     unsigned long long *__restrict__ vout, long long n, int bit,
-                                                    long long ntiles, const unsigned *__restrict__ off) {
-    __shared__ unsigned run[4][256];
+                                                    long long ntiles, const unsigned *__restrict__ off,
+                                                    const unsigned *__restrict__ hist) {
+    __shared__ unsigned gbase[4][256], lbase[4][256], run[4][256];
+    __shared__ unsigned long long sk[4][kRsTile], sv[4][kRsTile];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long tile = (long long)blockIdx.x * 4 + w;
-    const bool tv = tile < ntiles;
-    for (int d = lane; d < 256; d += 64) run[w][d] = tv ? off[(long long)d * ntiles + tile] : 0u;
-    __syncthreads();
-    if (!tv) return;  // no barrier below: each wavefront works on its own LDS row
+    if (tile >= ntiles) return;  // no barrier below: each wavefront works on its own LDS rows
+    // the tile's digit counts, four consecutive digits per lane, and their exclusive scan
+    unsigned c[4], sum = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int d = 4 * lane + j;
+        c[j] = hist[(long long)d * ntiles + tile];
+        gbase[w][d] = off[(long long)d * ntiles + tile];
+        sum += c[j];
+    }
+    unsigned incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    unsigned start = incl - sum;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int d = 4 * lane + j;
+        lbase[w][d] = start;
+        run[w][d] = start;
+        start += c[j];
+    }
+    __builtin_amdgcn_wave_barrier();
     const long long base = tile * kRsTile;
     const unsigned long long below = (1ull << lane) - 1ull;
     for (int r = 0; r < kRsItems; ++r) {
@@ -515,10 +541,22 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const unsigned long long *__
         const unsigned p = ok ? run[w][dg] + before : 0u;
         __builtin_amdgcn_wave_barrier();
         if (ok && before == 0u) run[w][dg] = p + (unsigned)__popcll(peers);  // the digit's first lane
+        if (ok && SG_IN(p, kRsTile, 0x703)) {
+            sk[w][p] = k;
+            if (vin) sv[w][p] = vin[i];
+        }
         __builtin_amdgcn_wave_barrier();
-        if (ok && SG_IN(p, n, 0x703)) {
-            kout[p] = k;
-            if (vin) vout[p] = vin[i];
+    }
+    // write-out in digit order: local position j holds the (j - lbase[digit])-th key of its
+    // digit in this tile
+    const int nk = (int)min((long long)kRsTile, n - base);
+    for (int j = lane; j < nk; j += 64) {
+        const unsigned long long k = sk[w][j];
+        const unsigned dg = (unsigned)(k >> bit) & 255u;
+        const unsigned g = gbase[w][dg] + ((unsigned)j - lbase[w][dg]);
+        if (SG_IN(g, n, 0x704)) {
+            kout[g] = k;
+            if (vin) vout[g] = sv[w][j];
         }
     }
 }
@@ -690,7 +728,7 @@ struct Builder {
             GHIP(hipGetLastError());
             GTRY(scan<unsigned>(hist, off, 256 * ntiles, 0u));
             hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(256), 0, st, ka, va, kb, vb, n, bit, ntiles,
-                               (const unsigned *)off);
+                               (const unsigned *)off, (const unsigned *)hist);
             GHIP(hipGetLastError());
             std::swap(ka, kb);
             std::swap(va, vb);
